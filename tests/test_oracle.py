@@ -1,0 +1,414 @@
+"""Pins of the CPU oracle against facts fixed outside it (no GPU needed).
+
+* Eq. 1 evaluator: closed forms (ring of cliques, one community, singletons, a directed
+  bipartite graph) and brute-force optima of tiny graphs.
+* Exact one-step gain: the oracle's checking mode recounts Eq. 1 from scratch around every
+  committed move (single-move mode compares each predicted gain with the recount), and the
+  printed Eq. 2 differs from the recounted change by the target-independent terms only.
+* Decouple: the emitter/acceptor filter satisfies the characterising properties of the
+  greedy filter in gain order.
+* Hierarchy: subtract-add repair equals a from-scratch Eq. 3 grouping after every batch;
+  totals, degrees, label nesting, refined roots and refined connectivity recounted in numpy.
+* Batch semantics: the maintained Q equals Eq. 1 evaluated on the generator's own edge set.
+"""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.statecheck import check_state, oracle_state
+
+
+def ring_of_cliques(r, s, wc=1, wr=1):
+    """r cliques K_s; clique i's last vertex joins clique i+1's first vertex (weight wr)."""
+    e = []
+    for c in range(r):
+        base = c * s
+        for i in range(s):
+            for j in range(i + 1, s):
+                e.append((base + i, base + j, wc))
+        e.append((base + s - 1, ((c + 1) % r) * s, wr))
+    return np.array(e, dtype=np.uint32)
+
+
+def ring_q(r, s, k, wc=1, wr=1, gamma=Fraction(1)):
+    """Closed form for k consecutive cliques per community: the community's internal weight is
+    k E wc + (k-1) wr and its volume is 2k(E wc + wr) with E = s(s-1)/2, so
+    Q = (k E wc + (k-1) wr) / (k (E wc + wr)) - gamma k / r."""
+    E = s * (s - 1) // 2
+    return Fraction(k * E * wc + (k - 1) * wr, k * (E * wc + wr)) - gamma * Fraction(k, r)
+
+
+def q_exact(n, edges, labels, directed=False, gamma=(1, 1)):
+    num, m, _ = oracle.eval_modularity(n, edges, labels, directed, gamma)
+    return Fraction(0) if m == 0 else Fraction(num, gamma[1] * m * m)
+
+
+# ---------------------------------------------------------------------------- Eq. 1 pins
+
+@pytest.mark.parametrize("r,s,k", [(10, 6, 1), (10, 6, 2), (30, 5, 1), (30, 5, 2), (30, 5, 3), (30, 3, 1),
+                                   (30, 3, 2), (30, 3, 3), (3, 3, 1)])
+def test_eq1_ring_of_cliques_closed_form(r, s, k):
+    e = ring_of_cliques(r, s)
+    lab = np.array([(u // s) // k for u in range(r * s)], dtype=np.uint32)
+    assert q_exact(r * s, e, lab) == ring_q(r, s, k)
+
+
+def test_eq1_ring_values_printed():
+    # r=10, s=6 gives 0.8375 for single cliques; r=3, s=3 gives 5/12
+    assert ring_q(10, 6, 1) == Fraction(67, 80)
+    assert ring_q(3, 3, 1) == Fraction(5, 12)
+    # resolution limit: for r=30, s=3 three cliques per community beat single cliques
+    assert ring_q(30, 3, 3) > ring_q(30, 3, 1)
+
+
+@pytest.mark.parametrize("wc,wr,k,gamma", [(3, 1, 1, (1, 1)), (2, 5, 2, (1, 1)), (7, 2, 1, (3, 2)),
+                                           (1, 1, 2, (1, 2))])
+def test_eq1_weighted_ring_with_resolution(wc, wr, k, gamma):
+    r, s = 12, 4
+    e = ring_of_cliques(r, s, wc, wr)
+    lab = np.array([(u // s) // k for u in range(r * s)], dtype=np.uint32)
+    assert q_exact(r * s, e, lab, gamma=gamma) == ring_q(r, s, k, wc, wr, Fraction(*gamma))
+
+
+def test_eq1_one_community_and_singletons():
+    rng = np.random.default_rng(1)
+    n = 40
+    for directed in (False, True):
+        pairs = set()
+        while len(pairs) < 120:
+            u, v = rng.integers(0, n, 2)
+            if u != v:
+                pairs.add((int(u), int(v)) if directed else (int(min(u, v)), int(max(u, v))))
+        e = np.array([(u, v, rng.integers(1, 9)) for u, v in sorted(pairs)], dtype=np.uint32)
+        for gamma in ((1, 1), (3, 2), (1, 3)):
+            g = Fraction(*gamma)
+            assert q_exact(n, e, np.zeros(n, np.uint32), directed, gamma) == 1 - g
+            # singletons: Q = -gamma * sum kout_i kin_i / m^2
+            ko = np.zeros(n, dtype=np.int64)
+            ki = np.zeros(n, dtype=np.int64)
+            for u, v, w in e.tolist():
+                ko[u] += w
+                ki[v] += w
+                if not directed:
+                    ko[v] += w
+                    ki[u] += w
+            m = int(ko.sum())
+            expect = -g * Fraction(int((ko * ki).sum()), m * m)
+            assert q_exact(n, e, np.arange(n, dtype=np.uint32), directed, gamma) == expect
+
+
+def test_eq1_directed_bipartite_closed_form():
+    # all edges A -> B: the split {A},{B} has no internal weight and Kout(A)Kin(A) =
+    # Kout(B)Kin(B) = 0, so Q = 0 exactly, while the same edges read undirected give -1/2.
+    A, B = range(0, 5), range(5, 11)
+    e = np.array([(a, b, 1 + (a + b) % 4) for a in A for b in B], dtype=np.uint32)
+    lab = np.array([0] * 5 + [1] * 6, dtype=np.uint32)
+    assert q_exact(11, e, lab, directed=True) == 0
+    assert q_exact(11, e, lab, directed=False) == Fraction(-1, 2)
+    assert q_exact(11, e, np.arange(11, dtype=np.uint32), directed=True) == 0
+
+
+# ------------------------------------------------------------------- brute-force optima
+
+def set_partitions(n):
+    """All set partitions of range(n) as restricted growth strings."""
+    a = [0] * n
+
+    def rec(i, mx):
+        if i == n:
+            yield list(a)
+            return
+        for c in range(mx + 2):
+            a[i] = c
+            yield from rec(i + 1, max(mx, c))
+
+    yield from rec(1, 0) if n > 0 else iter([[]])
+
+
+def brute_force_best(n, e, directed=False):
+    best = None
+    for p in set_partitions(n):
+        q = q_exact(n, e, np.array(p, dtype=np.uint32), directed)
+        if best is None or q > best:
+            best = q
+    return best
+
+
+def test_bruteforce_ring_of_three_triangles():
+    e = ring_of_cliques(3, 3)
+    best = brute_force_best(9, e)
+    assert best == Fraction(5, 12)
+    o = oracle.Oracle(9, e)
+    lab = o.partition()
+    assert q_exact(9, e, lab) == best
+    assert o.qnum() == Fraction(5, 12) * (2 * 12) ** 2
+
+
+def test_bruteforce_two_cliques():
+    e = [(i, j, 1) for i in range(4) for j in range(i + 1, 4)] + \
+        [(4 + i, 4 + j, 1) for i in range(4) for j in range(i + 1, 4)]
+    e = np.array(e, dtype=np.uint32)
+    best = brute_force_best(8, e)
+    o = oracle.Oracle(8, e)
+    assert q_exact(8, e, o.partition()) == best == Fraction(1, 2)
+
+
+@pytest.mark.parametrize("seed,directed", [(0, False), (1, False), (2, True), (3, True), (4, False)])
+def test_bruteforce_upper_bound(seed, directed):
+    rng = np.random.default_rng(seed)
+    n = 8
+    pairs = set()
+    while len(pairs) < 12:
+        u, v = rng.integers(0, n, 2)
+        if u != v:
+            pairs.add((int(u), int(v)) if directed else (int(min(u, v)), int(max(u, v))))
+    e = np.array([(u, v, rng.integers(1, 6)) for u, v in sorted(pairs)], dtype=np.uint32)
+    best = brute_force_best(n, e, directed)
+    o = oracle.Oracle(n, e, directed=directed, flags=oracle.FLAG_CHECK_MOVES)
+    assert o.last_rc == 0
+    got = q_exact(n, e, o.partition(), directed)
+    assert got <= best
+    assert Fraction(o.qnum(), 1) == got * (2 * int(e[:, 2].sum()) if not directed else int(e[:, 2].sum())) ** 2
+
+
+# ------------------------------------------------------------ exact gain (check (a))
+
+def random_graph(rng, n, m_edges, directed, wmax=8, loops=0):
+    pairs = set()
+    while len(pairs) < m_edges:
+        u, v = rng.integers(0, n, 2)
+        if u != v:
+            pairs.add((int(u), int(v)) if directed else (int(min(u, v)), int(max(u, v))))
+    e = [(u, v, int(rng.integers(1, wmax + 1))) for u, v in sorted(pairs)]
+    for x in rng.choice(n, loops, replace=False):
+        e.append((int(x), int(x), int(rng.integers(1, wmax + 1))))
+    return np.array(e, dtype=np.uint32)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("gamma", [(1, 1), (3, 2), (2, 5)])
+@pytest.mark.parametrize("single", [True, False])
+def test_every_move_matches_recount(directed, gamma, single):
+    rng = np.random.default_rng(7 + directed + 3 * gamma[0] + 11 * single)
+    e = random_graph(rng, 60, 200, directed, loops=5)
+    flags = oracle.FLAG_CHECK_MOVES | (oracle.FLAG_SINGLE_MOVE if single else 0)
+    o = oracle.Oracle(60, e, directed=directed, flags=flags, gamma=gamma)
+    assert o.last_rc == 0, o.check()
+    assert o.check() == ""
+
+
+def test_eq2_differs_by_target_independent_terms():
+    """Eq. 2 as printed (K_a and w(v,a) include v) equals the recounted change of Q minus
+    2 w_vv / m plus 2 gamma kout_v kin_v / m^2, for arbitrary moves."""
+    rng = np.random.default_rng(3)
+    for directed in (False, True):
+        for gamma in ((1, 1), (3, 2)):
+            g = Fraction(*gamma)
+            n = 30
+            e = random_graph(rng, n, 90, directed, loops=4)
+            W = {}
+            for u, v, w in e.tolist():
+                W[(u, v)] = W.get((u, v), 0) + w
+                if not directed and u != v:
+                    W[(v, u)] = W.get((v, u), 0) + w
+            m = sum(W.values())
+            kout = [sum(w for (a, b), w in W.items() if a == x) for x in range(n)]
+            kin = [sum(w for (a, b), w in W.items() if b == x) for x in range(n)]
+            for _ in range(25):
+                lab = rng.integers(0, 6, n).astype(np.uint32)
+                v = int(rng.integers(0, n))
+                a = int(lab[v])
+                b = int((a + 1 + rng.integers(0, 5)) % 6)
+                before = q_exact(n, e, lab, directed, gamma)
+                lab2 = lab.copy()
+                lab2[v] = b
+                dq = q_exact(n, e, lab2, directed, gamma) - before
+
+                def w_to(c):
+                    return sum(W.get((v, u), 0) for u in range(n) if lab[u] == c)
+
+                def w_from(c):
+                    return sum(W.get((u, v), 0) for u in range(n) if lab[u] == c)
+
+                Kin = lambda c: sum(kin[u] for u in range(n) if lab[u] == c)  # noqa: E731
+                Kout = lambda c: sum(kout[u] for u in range(n) if lab[u] == c)  # noqa: E731
+                dw = w_to(b) + w_from(b) - w_to(a) - w_from(a)
+                dd = kout[v] * (Kin(b) - Kin(a)) + kin[v] * (Kout(b) - Kout(a))
+                eq2 = Fraction(dw, m) - g * Fraction(dd, m * m)
+                wvv = W.get((v, v), 0)
+                assert dq == eq2 + Fraction(2 * wvv, m) - g * Fraction(2 * kout[v] * kin[v], m * m)
+
+
+# ---------------------------------------------------------------------------- decouple
+
+def _conflict(x, y):
+    return x[1] == y[2] or x[2] == y[1]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_decouple_is_greedy_filter(seed):
+    rng = np.random.default_rng(seed)
+    k = 300
+    ncomm = 12 if seed % 2 else 40
+    vab = []
+    for v in rng.permutation(1000)[:k]:
+        a = int(rng.integers(0, ncomm))
+        b = int((a + 1 + rng.integers(0, ncomm - 1)) % ncomm)
+        if seed >= 4 and rng.random() < 0.3:
+            b = 0 if a != 0 else 1     # a hub acceptor
+        vab.append((int(v), a, b))
+    gains = [int(rng.integers(1, 50)) * (1 << int(rng.integers(0, 90))) for _ in range(k)]
+    acc = oracle.decouple(vab, gains)
+    order = sorted(range(k), key=lambda i: (-gains[i], vab[i][0]))
+    accepted = [i for i in order if acc[i]]
+    emit = {vab[i][1] for i in accepted}
+    accp = {vab[i][2] for i in accepted}
+    assert not (emit & accp)                     # no community has both roles
+    for pos, i in enumerate(order):
+        earlier_acc = [j for j in order[:pos] if acc[j]]
+        hit = any(_conflict(vab[i], vab[j]) for j in earlier_acc)
+        assert acc[i] == (not hit)               # accepted iff no earlier accepted conflict
+
+
+# -------------------------------------------------------------- hierarchy invariants
+
+def _stream_cases():
+    return [("planted-und", False), ("planted-dir", True)]
+
+
+@pytest.mark.parametrize("name,directed", _stream_cases())
+def test_invariants_after_every_batch(name, directed):
+    s = synth.Stream(600, directed, synth.BASE_SEED + 50 + directed)
+    s.planted(60, 0.15 if not directed else 0.08, 0.004, 1, 8)
+    o = oracle.Oracle(s.n, s.edges(), directed=directed, flags=oracle.FLAG_CHECK_MOVES)
+    assert o.last_rc == 0
+    for b in range(8):
+        bt = s.batch(40)
+        assert o.apply_batch(bt.ins, bt.dels, bt.chg) == 0, o.check()
+        st = oracle_state(o)
+        errs = check_state(st, directed)
+        assert not errs, (b, errs)
+        # maintained Q equals Eq. 1 on the generator's own edge set
+        num, m, _ = oracle.eval_modularity(s.n, s.edges(), o.partition(), directed)
+        assert num == o.qnum() and m == st["m"]
+
+
+def test_directed_symmetric_equals_undirected():
+    s = synth.planted_small(seed_offset=60, n=400, blocks=8, p_in=0.1, p_out=0.01)
+    e = s.edges()
+    sym = np.concatenate([e, e[:, [1, 0, 2]]])
+    ou = oracle.Oracle(s.n, e, directed=False)
+    od = oracle.Oracle(s.n, sym, directed=True)
+    assert np.array_equal(ou.partition(), od.partition())
+    assert ou.qnum() == od.qnum()
+    for _ in range(5):
+        bt = s.batch(30)
+        ou.apply_batch(bt.ins, bt.dels, bt.chg)
+        od.apply_batch(np.concatenate([bt.ins, bt.ins[:, [1, 0, 2]]]),
+                       np.concatenate([bt.dels, bt.dels[:, [1, 0]]]),
+                       np.concatenate([bt.chg, bt.chg[:, [1, 0, 2]]]))
+        assert np.array_equal(ou.partition(), od.partition())
+        assert ou.qnum() == od.qnum()
+
+
+def test_ring_of_cliques_recovered():
+    e = ring_of_cliques(10, 6)
+    o = oracle.Oracle(60, e)
+    lab = o.partition()
+    # every clique is one community and distinct cliques are apart: Q = 0.8375 exactly
+    for c in range(10):
+        assert len(set(lab[c * 6:(c + 1) * 6].tolist())) == 1
+    assert len(set(lab.tolist())) == 10
+    assert q_exact(60, e, lab) == Fraction(67, 80)
+
+
+# --------------------------------------------------------------------- batch semantics
+
+def _snapshot(o):
+    st = oracle_state(o)
+    return st, o.partition()
+
+
+def _same(a, b):
+    from tests.statecheck import diff_states
+    return not diff_states(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_errors_leave_state_unchanged():
+    s = synth.planted_small(seed_offset=70, n=200, blocks=4, p_in=0.2, p_out=0.02)
+    e = s.edges()
+    o = oracle.Oracle(s.n, e)
+    snap = _snapshot(o)
+    u, v, w = (int(x) for x in e[0])
+    absent = (0, 0)
+    have = {(int(a), int(b)) for a, b, _ in e}
+    for a in range(s.n):
+        for b in range(a + 1, s.n):
+            if (a, b) not in have:
+                absent = (a, b)
+                break
+        if absent != (0, 0):
+            break
+    cases = [
+        (oracle.OracleError, dict(ins=[(s.n, 1, 1)]), -1),
+        (None, dict(ins=[(absent[0], absent[1], 0)]), -1),
+        (None, dict(ins=[(absent[0], absent[1], 2)], chg=[(absent[1], absent[0], 3)]), -2),
+        (None, dict(dels=[(u, v)], chg=[(v, u, 5)]), -2),
+        (None, dict(dels=[absent]), -3),
+        (None, dict(chg=[(absent[0], absent[1], 4)]), -3),
+        (None, dict(ins=[(u, v, 0xFFFFFFFF)]), -4),
+        (None, dict(ins=[(absent[0], absent[1], 5)], dels=[(s.n + 5, 0)]), -1),
+    ]
+    for _, kw, code in cases:
+        assert o.apply_batch(**kw) == code, kw
+        assert _same(snap, _snapshot(o)), kw
+
+
+def test_empty_graph_and_zero_m():
+    o = oracle.Oracle(10, np.zeros((0, 3), np.uint32))
+    assert o.modularity() == 0.0 and o.qnum() == 0
+    assert np.array_equal(o.partition(), np.arange(10))
+    assert o.apply_batch(ins=[(0, 1, 3), (1, 2, 3), (5, 6, 1)]) == 0
+    assert o.check() == ""
+    assert o.apply_batch(dels=[(0, 1), (1, 2), (5, 6)]) == 0
+    assert o.qnum() == 0 and o.check() == ""
+
+
+def test_insert_onto_existing_edge_increments():
+    e = ring_of_cliques(4, 4)
+    o = oracle.Oracle(16, e)
+    u, v, w = (int(x) for x in e[0])
+    assert o.apply_batch(ins=[(v, u, 3)]) == 0          # unordered pair, undirected
+    lv = o.level(0)
+    k = (lv["rows"] == u) & (lv["cols"] == v)
+    assert int(lv["w"][k][0]) == w + 3
+    assert o.check() == ""
+
+
+def test_create_rejects_duplicates():
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(5, [(0, 1, 1), (1, 0, 2)])
+    # directed graphs keep both orientations as distinct pairs
+    o = oracle.Oracle(5, [(0, 1, 1), (1, 0, 2)], directed=True)
+    assert o.check() == ""
+
+
+def test_self_loops_counted_once():
+    e = np.array([(0, 0, 5), (0, 1, 2), (1, 2, 2)], dtype=np.uint32)
+    o = oracle.Oracle(3, e, flags=oracle.FLAG_CHECK_MOVES)
+    assert o.last_rc == 0
+    assert o.scalars()["m"] == 5 + 2 * 2 + 2 * 2
+
+
+def test_planted_partition_recovery_sanity():
+    # well-separated blocks (p_in=0.2, p_out=0.002) are recovered exactly (sanity, not parity)
+    s = synth.planted_small(p_in=0.2, p_out=0.002)
+    o = oracle.Oracle(s.n, s.edges())
+    lab = o.partition()
+    truth = np.arange(s.n) // 100
+    purity = sum(np.bincount(lab[truth == b]).max() for b in range(20)) / s.n
+    assert purity == 1.0 and len(set(lab.tolist())) == 20
