@@ -1,0 +1,173 @@
+/*
+ * ldl.h -- C ABI of the MI355X (gfx950) LD-Leiden library.
+ *
+ * LD-Leiden maintains a modularity partition of a weighted directed or undirected graph
+ * under batches of edge insertions, deletions and weight changes (paper Sec. II, problem
+ * statement).  Each batch runs the paper's Algorithm 1 (Sec. III-C) on the GPU: batch
+ * apply and statistic repair, frontier-restricted local moves with the decoupling filter
+ * (Sec. III-D, III-E), restricted refinement, and subtract-add repair of the aggregate
+ * hierarchy (Sec. III-F, Eq. 3).
+ *
+ * Arithmetic is exact: weights are integers, gains are compared as integers (the modularity
+ * change scaled by q*m^2 for resolution gamma = p/q; half of that for undirected graphs), ties
+ * go to the lowest community id and every stage is round-synchronous, so results are
+ * deterministic and independent of launch shapes.
+ *
+ * Conventions for every call:
+ *   - Return value: LDL_OK (0) or a negative LDL_E* code.  Batches are atomic: on any error
+ *     except LDL_EDEVICE the graph and partition are unchanged.  After LDL_EDEVICE the handle
+ *     is poisoned and every later call returns LDL_EBROKEN.
+ *   - Vertices are 0..n-1 (n fixed at creation).  Undirected pairs are unordered.
+ *   - Input arrays are owned by the caller and only read during the call; the handle owns
+ *     all device memory it allocates.  A handle is not thread-safe; distinct handles may be
+ *     used from different threads.
+ *   - All calls are synchronous with respect to the handle's stream.
+ */
+#ifndef LDL_H
+#define LDL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDL_OK 0
+#define LDL_EINVAL (-1)    /* null pointer, n == 0, id >= n, zero weight, bad config       */
+#define LDL_EDUP (-2)      /* a vertex pair appears twice in one batch                      */
+#define LDL_ENOEDGE (-3)   /* deletion or change of an absent edge                          */
+#define LDL_EOVERFLOW (-4) /* an edge weight would exceed 2^32-1, or m would reach 2^40    */
+#define LDL_ENOMEM (-5)    /* device allocation failed                                      */
+#define LDL_EDEVICE (-6)   /* a HIP runtime error; the handle is poisoned                   */
+#define LDL_EBROKEN (-7)   /* the handle was poisoned by an earlier device error            */
+
+typedef struct ldl_handle ldl_handle;
+
+/* An edge (u, v) with integer weight w >= 1. */
+typedef struct ldl_edge {
+  uint32_t u, v, w;
+} ldl_edge;
+
+/* A vertex pair (u, v). */
+typedef struct ldl_pair {
+  uint32_t u, v;
+} ldl_pair;
+
+/*
+ * Parameters (paper Table I; defaults from the parameter study, Sec. IV-D):
+ *   directed            0: undirected (W symmetric), 1: directed
+ *   gamma_num/den       resolution gamma = num/den of Eq. 1, both in [1, 65535]; default 1/1
+ *   N                   outer passes (>= 1); default 2
+ *   L                   top hierarchy level index, levels 0..L (0..16); default 4
+ *   M                   move / refinement iterations per level (>= 1); default 5
+ *   alpha_num/den       gain threshold alpha (Alg. 1 l.13, l.27); default 1/1000
+ *   beta_num/den        moved-frontier threshold beta (l.14, l.20); default 1/100
+ *   device              HIP device ordinal
+ *   stream              hipStream_t to run on, or NULL for the handle's own stream
+ *   profile             nonzero: time the local-move kernels with HIP events (see stats)
+ */
+typedef struct ldl_config {
+  int32_t directed;
+  int32_t gamma_num, gamma_den;
+  int32_t N, L, M;
+  int32_t alpha_num, alpha_den;
+  int32_t beta_num, beta_den;
+  int32_t device;
+  void* stream;
+  int32_t profile;
+} ldl_config;
+
+/* Per-call statistics (all counts summed over the call). */
+typedef struct ldl_batch_stats {
+  uint64_t updates;           /* input updates that changed a weight                      */
+  uint64_t levels_processed;  /* process-level invocations over all passes                */
+  uint64_t move_iters;        /* move iterations                                          */
+  uint64_t refine_iters;      /* refinement iterations                                    */
+  uint64_t scanned_vertices;  /* vertices evaluated by the local-move kernels             */
+  uint64_t scanned_entries;   /* adjacency entries read by the local-move kernels         */
+  uint64_t distinct_comms;    /* (vertex, neighbour community) pairs evaluated            */
+  uint64_t candidates;        /* candidates with positive gain                            */
+  uint64_t accepted;          /* moves accepted by the decoupling filter                  */
+  uint64_t rollbacks;         /* move mini-batches rolled back (Alg. 1 l.11)              */
+  uint64_t refine_moves;      /* accepted refinement moves                                */
+  uint64_t agg_tuples;        /* aggregate-repair tuples emitted                          */
+  uint64_t bm_launches;       /* local-move kernel launches (profile != 0)                */
+  double bm_ms;               /* summed local-move kernel time in ms (profile != 0)       */
+  double bm_bytes;            /* algorithmic bytes of those kernels (profile != 0)        */
+  double total_ms;            /* wall time of the call measured with HIP events           */
+} ldl_batch_stats;
+
+/* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */
+void ldl_default_config(ldl_config* cfg);
+
+/*
+ * Create a handle for n vertices and the initial edge set (host array, n_edges entries,
+ * insertion semantics; a repeated pair is LDL_EDUP).  Runs static Leiden, i.e. the batch
+ * update applied to the all-singleton state (Sec. IV-E: batch 0 initialises the full snapshot).
+ * cfg may be NULL for the defaults.  On success *out receives the handle.
+ */
+int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_t n_edges,
+               ldl_handle** out);
+
+/*
+ * Apply one batch (host arrays; any count may be 0) and run Algorithm 1:
+ *   ins[i]: w_new = w_old + w (creates the edge when absent)
+ *   del[i]: removes the edge (absent edge: LDL_ENOEDGE)
+ *   chg[i]: sets the weight to w >= 1 (absent edge: LDL_ENOEDGE)
+ * A pair may appear at most once across the three lists.  stats may be NULL.
+ */
+int ldl_apply_batch(ldl_handle* h, const ldl_edge* ins, uint64_t n_ins, const ldl_pair* del,
+                    uint64_t n_del, const ldl_edge* chg, uint64_t n_chg, ldl_batch_stats* stats);
+
+/* As ldl_apply_batch, with the three arrays in device memory of the handle's device. */
+int ldl_apply_batch_device(ldl_handle* h, const ldl_edge* d_ins, uint64_t n_ins, const ldl_pair* d_del,
+                           uint64_t n_del, const ldl_edge* d_chg, uint64_t n_chg, ldl_batch_stats* stats);
+
+/* Copy the level-0 partition (community id of each vertex, ids in [0, n)) into the caller's
+ * host array of length n (n must equal the handle's vertex count). */
+int ldl_get_partition(const ldl_handle* h, uint32_t* labels, uint64_t n);
+
+/* Eq. 1 for the current partition in FP64: Qnum / (q m^2), with Qnum exact (0 when m == 0). */
+int ldl_modularity(const ldl_handle* h, double* q);
+
+/* Exact numerator q*m*Ein - p*sum_c Kout_c Kin_c as a signed 128-bit value (hi, lo) and the
+ * denominator q*m^2 likewise; Q = num / den. */
+int ldl_modularity_exact(const ldl_handle* h, int64_t* num_hi, uint64_t* num_lo, int64_t* den_hi,
+                         uint64_t* den_lo);
+
+/* Release every device resource of the handle.  NULL is ignored. */
+void ldl_destroy(ldl_handle* h);
+
+/*
+ * State export for checking (host arrays sized by the caller):
+ *   ldl_export_scalars: top level index, m, Ein, sum Kout*Kin (hi, lo)
+ *   ldl_export_totals:  community totals Kout, Kin (length n each)
+ *   ldl_export_level:   node arrays of level r (alive u8, label u32, parent u32, kout, kin i64)
+ *   ldl_level_nnz:      number of stored matrix entries of level r (returns 0 on error)
+ *   ldl_export_entries: those entries as (row, col, weight) arrays of length nnz, row-major
+ */
+int ldl_export_scalars(const ldl_handle* h, int32_t* top, int64_t* m, int64_t* ein, int64_t* skk_hi,
+                       uint64_t* skk_lo);
+int ldl_export_totals(const ldl_handle* h, int64_t* kout, int64_t* kin);
+int ldl_export_level(const ldl_handle* h, int32_t r, uint8_t* alive, uint32_t* lab, uint32_t* par,
+                     int64_t* kout, int64_t* kin);
+uint64_t ldl_level_nnz(const ldl_handle* h, int32_t r);
+int ldl_export_entries(const ldl_handle* h, int32_t r, uint32_t* rows, uint32_t* cols, int64_t* w);
+
+/* Per-iteration trace (8 int64 per record: pass, level, phase 0 move / 1 refine, iteration,
+ * scanned vertices, candidates, accepted, low 64 bits of the exact batch gain). */
+int ldl_set_trace(ldl_handle* h, int32_t on);
+uint64_t ldl_trace_len(const ldl_handle* h);
+int ldl_trace(const ldl_handle* h, int64_t* out);
+
+/* Human-readable name of an LDL_* code. */
+const char* ldl_strerror(int code);
+
+/* Library version string. */
+const char* ldl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDL_H */

@@ -1,0 +1,262 @@
+"""Python binding of the gfx950 LD-Leiden library (``libldl.so``, C ABI in ``include/ldl.h``).
+
+Argument marshalling only: every step of the batch update runs in the HIP kernels behind the
+C ABI.  PyTorch is used for device-resident inputs and streams.  There is no fallback: if
+``libldl.so`` has not been built, importing the library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldl.so")
+
+LDL_OK = 0
+ERRORS = {0: "LDL_OK", -1: "LDL_EINVAL", -2: "LDL_EDUP", -3: "LDL_ENOEDGE", -4: "LDL_EOVERFLOW",
+          -5: "LDL_ENOMEM", -6: "LDL_EDEVICE", -7: "LDL_EBROKEN"}
+
+
+class LdlError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        super().__init__(f"{what}: {ERRORS.get(code, code)}" if what else ERRORS.get(code, str(code)))
+        self.code = code
+
+
+class ldl_config(ctypes.Structure):
+    _fields_ = [("directed", ctypes.c_int32), ("gamma_num", ctypes.c_int32), ("gamma_den", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("alpha_num", ctypes.c_int32), ("alpha_den", ctypes.c_int32), ("beta_num", ctypes.c_int32),
+                ("beta_den", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("profile", ctypes.c_int32)]
+
+
+class ldl_batch_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "updates", "levels_processed", "move_iters", "refine_iters", "scanned_vertices", "scanned_entries",
+        "distinct_comms", "candidates", "accepted", "rollbacks", "refine_moves", "agg_tuples", "bm_launches")] + \
+        [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# every entry point declared in include/ldl.h
+ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply_batch_device", "ldl_get_partition",
+               "ldl_modularity", "ldl_modularity_exact", "ldl_destroy", "ldl_export_scalars", "ldl_export_totals",
+               "ldl_export_level", "ldl_level_nnz", "ldl_export_entries", "ldl_set_trace", "ldl_trace_len",
+               "ldl_trace", "ldl_strerror", "ldl_version")
+
+_lib = None
+
+
+def load_library():
+    """Load libldl.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+    P = ctypes.POINTER
+    lib.ldl_default_config.argtypes = [P(ldl_config)]
+    lib.ldl_create.argtypes = [P(ldl_config), u32, vp, u64, P(vp)]
+    lib.ldl_create.restype = i32
+    for name in ("ldl_apply_batch", "ldl_apply_batch_device"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, vp, u64, vp, u64, vp, u64, P(ldl_batch_stats)]
+        f.restype = i32
+    lib.ldl_get_partition.argtypes = [vp, vp, u64]
+    lib.ldl_get_partition.restype = i32
+    lib.ldl_modularity.argtypes = [vp, P(ctypes.c_double)]
+    lib.ldl_modularity.restype = i32
+    lib.ldl_modularity_exact.argtypes = [vp, vp, vp, vp, vp]
+    lib.ldl_modularity_exact.restype = i32
+    lib.ldl_destroy.argtypes = [vp]
+    lib.ldl_destroy.restype = None
+    lib.ldl_export_scalars.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.ldl_export_scalars.restype = i32
+    lib.ldl_export_totals.argtypes = [vp, vp, vp]
+    lib.ldl_export_totals.restype = i32
+    lib.ldl_export_level.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.ldl_export_level.restype = i32
+    lib.ldl_level_nnz.argtypes = [vp, i32]
+    lib.ldl_level_nnz.restype = u64
+    lib.ldl_export_entries.argtypes = [vp, i32, vp, vp, vp]
+    lib.ldl_export_entries.restype = i32
+    lib.ldl_set_trace.argtypes = [vp, i32]
+    lib.ldl_set_trace.restype = i32
+    lib.ldl_trace_len.argtypes = [vp]
+    lib.ldl_trace_len.restype = u64
+    lib.ldl_trace.argtypes = [vp, vp]
+    lib.ldl_trace.restype = i32
+    lib.ldl_strerror.argtypes = [i32]
+    lib.ldl_strerror.restype = ctypes.c_char_p
+    lib.ldl_version.argtypes = []
+    lib.ldl_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _u32(a, cols):
+    if a is None:
+        return np.zeros((0, cols), dtype=np.uint32)
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32).reshape(-1, cols))
+
+
+def _i128(hi, lo) -> int:
+    return (int(hi) << 64) | int(lo)
+
+
+def ldl_default_config() -> ldl_config:
+    c = ldl_config()
+    load_library().ldl_default_config(ctypes.byref(c))
+    return c
+
+
+class Graph:
+    """A resident LD-Leiden state on one GPU: ``ldl_create`` runs static Leiden on the initial
+    edges; ``apply_batch`` runs one batch update (Algorithm 1)."""
+
+    def __init__(self, n, edges, directed=False, gamma=(1, 1), N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100),
+                 device=0, stream=None, profile=False):
+        self.lib = load_library()
+        c = ldl_default_config()
+        c.directed, c.gamma_num, c.gamma_den = int(directed), gamma[0], gamma[1]
+        c.N, c.L, c.M = N, L, M
+        c.alpha_num, c.alpha_den, c.beta_num, c.beta_den = alpha[0], alpha[1], beta[0], beta[1]
+        c.device = device
+        c.stream = stream
+        c.profile = int(bool(profile))
+        self.n = int(n)
+        self.directed = bool(directed)
+        self.L = L
+        e = _u32(edges, 3)
+        h = ctypes.c_void_p()
+        rc = self.lib.ldl_create(ctypes.byref(c), self.n, e.ctypes.data, len(e), ctypes.byref(h))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_create")
+        self.h = h.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ldl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_batch(self, ins=None, dels=None, chg=None, raise_on_error=True):
+        i, d, c = _u32(ins, 3), _u32(dels, 2), _u32(chg, 3)
+        st = ldl_batch_stats()
+        rc = self.lib.ldl_apply_batch(self.h, i.ctypes.data, len(i), d.ctypes.data, len(d), c.ctypes.data, len(c),
+                                      ctypes.byref(st))
+        if rc != LDL_OK and raise_on_error:
+            raise LdlError(rc, "ldl_apply_batch")
+        return (st.as_dict() if rc == LDL_OK else rc)
+
+    def apply_batch_device(self, ins_t, dels_t, chg_t, raise_on_error=True):
+        """Device-resident batch: uint32/int32 torch tensors of shape (k,3), (k,2), (k,3)."""
+        st = ldl_batch_stats()
+
+        def ptr(t):
+            return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+        def cnt(t):
+            return 0 if t is None else int(t.shape[0])
+
+        rc = self.lib.ldl_apply_batch_device(self.h, ptr(ins_t), cnt(ins_t), ptr(dels_t), cnt(dels_t), ptr(chg_t),
+                                             cnt(chg_t), ctypes.byref(st))
+        if rc != LDL_OK and raise_on_error:
+            raise LdlError(rc, "ldl_apply_batch_device")
+        return (st.as_dict() if rc == LDL_OK else rc)
+
+    def partition(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.uint32)
+        rc = self.lib.ldl_get_partition(self.h, out.ctypes.data, self.n)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_get_partition")
+        return out
+
+    def modularity(self) -> float:
+        q = ctypes.c_double()
+        rc = self.lib.ldl_modularity(self.h, ctypes.byref(q))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_modularity")
+        return q.value
+
+    def modularity_exact(self):
+        nh, nl, dh, dl = ctypes.c_int64(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_uint64()
+        rc = self.lib.ldl_modularity_exact(self.h, ctypes.byref(nh), ctypes.byref(nl), ctypes.byref(dh),
+                                           ctypes.byref(dl))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_modularity_exact")
+        return _i128(nh.value, nl.value), _i128(dh.value, dl.value)
+
+    def qnum(self) -> int:
+        return self.modularity_exact()[0]
+
+    def scalars(self) -> dict:
+        top, m, ein, sh, sl = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(),
+                               ctypes.c_uint64())
+        rc = self.lib.ldl_export_scalars(self.h, ctypes.byref(top), ctypes.byref(m), ctypes.byref(ein),
+                                         ctypes.byref(sh), ctypes.byref(sl))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_scalars")
+        return {"top": top.value, "m": m.value, "Ein": ein.value, "SKK": _i128(sh.value, sl.value)}
+
+    def totals(self):
+        ko = np.empty(self.n, dtype=np.int64)
+        ki = np.empty(self.n, dtype=np.int64)
+        rc = self.lib.ldl_export_totals(self.h, ko.ctypes.data, ki.ctypes.data)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_totals")
+        return ko, ki
+
+    def level(self, r) -> dict:
+        n = self.n
+        alive = np.empty(n, dtype=np.uint8)
+        lab = np.empty(n, dtype=np.uint32)
+        par = np.empty(n, dtype=np.uint32)
+        kout = np.empty(n, dtype=np.int64)
+        kin = np.empty(n, dtype=np.int64)
+        rc = self.lib.ldl_export_level(self.h, r, alive.ctypes.data, lab.ctypes.data, par.ctypes.data,
+                                       kout.ctypes.data, kin.ctypes.data)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_level")
+        nnz = int(self.lib.ldl_level_nnz(self.h, r))
+        rows = np.empty(nnz, dtype=np.uint32)
+        cols = np.empty(nnz, dtype=np.uint32)
+        w = np.empty(nnz, dtype=np.int64)
+        rc = self.lib.ldl_export_entries(self.h, r, rows.ctypes.data, cols.ctypes.data, w.ctypes.data)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_entries")
+        return {"alive": alive, "lab": lab, "par": par, "kout": kout, "kin": kin, "rows": rows, "cols": cols,
+                "w": w}
+
+    def state(self) -> dict:
+        sc = self.scalars()
+        ko, ki = self.totals()
+        return {"top": sc["top"], "m": sc["m"], "Ein": sc["Ein"], "SKK": sc["SKK"], "Kout": ko, "Kin": ki,
+                "levels": [self.level(r) for r in range(sc["top"] + 1)]}
+
+    def set_trace(self, on=True):
+        self.lib.ldl_set_trace(self.h, int(on))
+
+    def trace(self) -> np.ndarray:
+        k = int(self.lib.ldl_trace_len(self.h))
+        out = np.empty((k, 8), dtype=np.int64)
+        if k:
+            self.lib.ldl_trace(self.h, out.ctypes.data)
+        return out
+
+
+def version() -> str:
+    return load_library().ldl_version().decode()

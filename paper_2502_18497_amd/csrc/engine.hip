@@ -1,0 +1,1255 @@
+// Host engine of the LD-Leiden batch update (Algorithm 1) and the C ABI of include/ldl.h.
+//
+// Device state per level r = 0..L (node ids share [0, n) at every level, Sec. III-A):
+//   dynamic CSR (out; in as well for directed graphs), alive flags, degrees kout/kin, labels
+//   P^r, parents pi_r and refined-community sizes (r < L).  Community totals Kout/Kin are one
+//   level-invariant table.  The host keeps m, Ein and sum Kout*Kin exactly and reads back the
+//   small counters that decide Algorithm 1's data-dependent control flow.
+//
+// Readings of the paper's open points (also stated in the oracle):
+//   * gains are compared exactly as integers; candidates need gain > 0; ties go to the
+//     lowest community id; candidates are ordered by gain, then vertex id (Sec. III-E)
+//   * every iteration is round-synchronous: candidates see the state at its start
+//   * seeds of level r: changed entry endpoints and their ancestors; the frontier is the
+//     seeds plus all members of their communities; Expand adds movers, their neighbours and
+//     all members of the source and target communities
+//   * TouchedRefined: refined communities of the level's seeds and movers, reset to
+//     singletons; only singletons move during refinement, to adjacent refined communities
+//     carrying the same move label
+//   * a level is materialised from scratch (Eq. 3) the first time it is reached; afterwards
+//     it is repaired by subtract-add tuples and the tuple deltas cascade to every level above
+//   * moves at level r >= 1 are pushed down by relabelling P^s(u) = P^{s+1}(pi_s(u)); the
+//     relabelled nodes seed the next outer pass
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ldl.h"
+#include "ldl_kernels.h"
+
+namespace ldl {
+
+typedef __int128 i128;
+
+struct DeviceError {
+  hipError_t e;
+};
+struct NoMem {};
+
+static void hcheck(hipError_t e) {
+  if (e != hipSuccess) throw DeviceError{e};
+}
+
+template <typename T>
+static T* dalloc(uint64_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    throw NoMem{};
+  }
+  hcheck(e);
+  return (T*)p;
+}
+
+// Device-side counters and accumulators, mirrored into pinned host memory on demand.
+struct Scal {
+  uint32_t counts[64];
+  uint32_t bins[8];
+  uint32_t ncand, nacc, nlive2, err, first_bad, overflow, hub_over, pad0;
+  u64a pool_top[2 * 17];
+  u64a hub_top;
+  i64a dm, dein;
+  u64a dskk_lo;
+  i64a dskk_hi;
+  u64a tcount, tneed, nruns, ecount;
+  u64a st_entries, st_distinct, st_vertices;
+  u64a maxv;
+};
+
+enum SetId {
+  S_D0 = 0,  // 0..16 seed sets per level
+  S_U = 17, S_U2, S_S, S_MOVED, S_RSET, S_RCUR, S_C, S_TOUCH, S_COMM, S_REFM, S_MOV, S_DIRTY, S_LVC, S_DIED,
+  S_REV, S_DIED2, S_REV2, S_TMP, S_NSETS
+};
+
+struct HSet {
+  uint32_t* stamp = nullptr;
+  uint32_t* list = nullptr;
+  uint32_t epoch = 0;
+  int ci = 0;
+};
+
+struct Csr {
+  CsrRef ref{};
+  uint64_t pool_cap = 0;
+  int slot = 0;  // index of its pool-top counter
+};
+
+struct Level {
+  Csr out, in;
+  uint8_t* alive = nullptr;
+  int64_t* kout = nullptr;
+  int64_t* kin = nullptr;  // == kout for undirected graphs
+  uint32_t* lab = nullptr;
+  uint32_t* par = nullptr;
+  uint32_t* rsize = nullptr;
+};
+
+struct TraceRec {
+  int64_t v[8];
+};
+
+struct Engine {
+  // configuration
+  int directed = 0;
+  int64_t gp = 1, gq = 1;
+  int N = 2, L = 4, M = 5;
+  int64_t an = 1, ad = 1000, bn = 1, bd = 100;
+  int device = 0;
+  int profile = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  uint32_t n = 0;
+  bool broken = false;
+
+  // exact scalars (host)
+  int64_t m = 0, Ein = 0;
+  i128 SKK = 0;
+  int top = 0;
+  int pass_idx = 0;
+
+  std::vector<Level> lv;
+  int64_t* Kout = nullptr;
+  int64_t* Kin = nullptr;
+
+  Scal* ds = nullptr;
+  Scal* hs = nullptr;
+  HSet sets[S_NSETS];
+  bool set_has_list[S_NSETS];
+
+  // scratch (size n unless noted)
+  uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
+  uint64_t* plan_off = nullptr;
+  uint32_t* plan_cap = nullptr;
+  uint32_t *minE = nullptr, *minA = nullptr, *accE = nullptr, *accA = nullptr;
+  uint32_t acc_epoch = 0;
+  uint8_t* lfflag = nullptr;
+  uint32_t *rank = nullptr, *liveA = nullptr, *liveB = nullptr, *acc = nullptr, *entry = nullptr;
+  int64_t *tko = nullptr, *tki = nullptr;
+  uint32_t* bins[kNumBins] = {};
+  uint32_t* hub_over_alt = nullptr;
+  CandBuf cand{};
+  uint64_t *skey0 = nullptr, *skey1 = nullptr;
+  uint32_t *sidx0 = nullptr, *sidx1 = nullptr;
+  HubPool hub{};
+  // growable record buffers
+  uint64_t rec_cap = 0;
+  uint64_t *rkey0 = nullptr, *rkey1 = nullptr;
+  uint32_t *ridx0 = nullptr, *ridx1 = nullptr;
+  int64_t* rdelta = nullptr;
+  uint64_t ent_cap = 0;
+  uint64_t *ekey0 = nullptr, *ekey1 = nullptr;
+  int64_t *edel0 = nullptr, *edel1 = nullptr;
+  uint32_t *ex = nullptr, *ey = nullptr;
+  uint8_t* insflag = nullptr;
+  uint64_t ins_cap = 0;
+  uint64_t tup_cap = 0;
+  uint64_t *tk0 = nullptr, *tk1 = nullptr, *tk2 = nullptr;
+  int64_t *tv0 = nullptr, *tv1 = nullptr, *tv2 = nullptr;
+  uint32_t *tx = nullptr, *ty = nullptr;
+  void* cub_tmp = nullptr;
+  size_t cub_bytes = 0;
+  std::vector<void*> owned;
+
+  // statistics / trace
+  ldl_batch_stats stats{};
+  bool tracing = false;
+  std::vector<TraceRec> trace;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+  size_t ev_used = 0;
+  std::vector<double> bm_bytes_pending;
+
+  // ------------------------------------------------------------------ memory helpers
+  template <typename T>
+  T* alloc(uint64_t count) {
+    T* p = dalloc<T>(count);
+    owned.push_back((void*)p);
+    return p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it != owned.end()) owned.erase(it);
+    (void)hipFree(p);
+  }
+  template <typename T>
+  void regrow(T*& p, uint64_t count) {
+    release((void*)p);
+    p = alloc<T>(count);
+  }
+
+  ~Engine() {
+    for (void* p : owned) (void)hipFree(p);
+    if (hs) (void)hipHostFree(hs);
+    if (cub_tmp) (void)hipFree(cub_tmp);
+    for (auto& e : ev_pool) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    if (own_stream && st) (void)hipStreamDestroy(st);
+  }
+
+  // ------------------------------------------------------------------ sets
+  SetRef ref(int id) {
+    HSet& s = sets[id];
+    return SetRef{s.stamp, set_has_list[id] ? s.list : nullptr, &ds->counts[s.ci], s.epoch};
+  }
+  void begin(int id) {
+    HSet& s = sets[id];
+    if (++s.epoch == 0) {
+      hcheck(hipMemsetAsync(s.stamp, 0, sizeof(uint32_t) * (uint64_t)n, st));
+      s.epoch = 1;
+    }
+    hcheck(hipMemsetAsync(&ds->counts[s.ci], 0, sizeof(uint32_t), st));
+  }
+  uint32_t count(int id) const { return hs->counts[sets[id].ci]; }
+  void sync_read() {
+    hcheck(hipMemcpyAsync(hs, ds, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+  }
+  template <typename T>
+  void zero(T* field) {
+    hcheck(hipMemsetAsync(field, 0, sizeof(T), st));
+  }
+
+  i128 qnum() const { return (i128)gq * m * Ein - (i128)gp * SKK; }
+
+  // ------------------------------------------------------------------ setup
+  void init(const ldl_config& c, uint32_t n_) {
+    directed = c.directed != 0;
+    gp = c.gamma_num; gq = c.gamma_den;
+    N = c.N; L = c.L; M = c.M;
+    an = c.alpha_num; ad = c.alpha_den; bn = c.beta_num; bd = c.beta_den;
+    device = c.device;
+    profile = c.profile;
+    n = n_;
+    hcheck(hipSetDevice(device));
+    if (c.stream) {
+      st = (hipStream_t)c.stream;
+    } else {
+      hcheck(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    ds = alloc<Scal>(1);
+    hcheck(hipMemsetAsync(ds, 0, sizeof(Scal), st));
+    void* hp = nullptr;
+    hcheck(hipHostMalloc(&hp, sizeof(Scal), hipHostMallocDefault));
+    hs = (Scal*)hp;
+    std::memset(hs, 0, sizeof(Scal));
+    for (int i = 0; i < S_NSETS; ++i) {
+      set_has_list[i] = !(i == S_COMM || i == S_REFM || i == S_MOV);
+      if (i <= 16 && i > L) continue;
+      sets[i].stamp = alloc<uint32_t>(n);
+      hcheck(hipMemsetAsync(sets[i].stamp, 0, sizeof(uint32_t) * (uint64_t)n, st));
+      if (set_has_list[i]) sets[i].list = alloc<uint32_t>(n);
+      sets[i].ci = i;
+      sets[i].epoch = 0;
+    }
+    for (int i = 0; i < S_NSETS; ++i)
+      if (sets[i].stamp) begin(i);   // epoch 1: stamps start at 0, so every set starts empty
+    lv.resize(L + 1);
+    for (int r = 0; r <= L; ++r) {
+      Level& V = lv[r];
+      V.alive = alloc<uint8_t>(n);
+      V.kout = alloc<int64_t>(n);
+      V.kin = directed ? alloc<int64_t>(n) : V.kout;
+      V.lab = alloc<uint32_t>(n);
+      launch_fill_u8(V.alive, r == 0 ? 1 : 0, n, st);
+      launch_fill_i64(V.kout, 0, n, st);
+      if (directed) launch_fill_i64(V.kin, 0, n, st);
+      launch_iota(V.lab, n, st);
+      if (r < L) {
+        V.par = alloc<uint32_t>(n);
+        V.rsize = alloc<uint32_t>(n);
+        launch_iota(V.par, n, st);
+        launch_fill_u32(V.rsize, 0, n, st);
+      }
+      V.out.slot = 2 * r;
+      V.in.slot = 2 * r + 1;
+      csr_init(V.out, r > 0);
+      if (directed) csr_init(V.in, r > 0);
+    }
+    Kout = alloc<int64_t>(n);
+    Kin = directed ? alloc<int64_t>(n) : Kout;
+    launch_fill_i64(Kout, 0, n, st);
+    if (directed) launch_fill_i64(Kin, 0, n, st);
+    oldlab = alloc<uint32_t>(n);
+    oldpar = alloc<uint32_t>(n);
+    rowdel = alloc<uint32_t>(n);
+    rowins = alloc<uint32_t>(n);
+    launch_fill_u32(rowdel, 0, n, st);
+    launch_fill_u32(rowins, 0, n, st);
+    plan_off = alloc<uint64_t>(n);
+    plan_cap = alloc<uint32_t>(n);
+    minE = alloc<uint32_t>(n);
+    minA = alloc<uint32_t>(n);
+    accE = alloc<uint32_t>(n);
+    accA = alloc<uint32_t>(n);
+    launch_fill_u32(accE, 0, n, st);
+    launch_fill_u32(accA, 0, n, st);
+    lfflag = alloc<uint8_t>(n);
+    rank = alloc<uint32_t>(n);
+    liveA = alloc<uint32_t>(n);
+    liveB = alloc<uint32_t>(n);
+    acc = alloc<uint32_t>(n);
+    entry = alloc<uint32_t>(n);
+    tko = alloc<int64_t>(n);
+    tki = alloc<int64_t>(n);
+    for (int b = 0; b < kNumBins; ++b) bins[b] = alloc<uint32_t>(n);
+    hub_over_alt = alloc<uint32_t>(n);
+    cand.v = alloc<uint32_t>(n);
+    cand.a = alloc<uint32_t>(n);
+    cand.b = alloc<uint32_t>(n);
+    cand.glo = alloc<uint64_t>(n);
+    cand.ghi = alloc<int64_t>(n);
+    cand.count = &ds->ncand;
+    skey0 = alloc<uint64_t>(n);
+    skey1 = alloc<uint64_t>(n);
+    sidx0 = alloc<uint32_t>(n);
+    sidx1 = alloc<uint32_t>(n);
+    uint64_t hc = 1;
+    while (hc < 4ull * n) hc <<= 1;
+    if (hc < (1ull << 16)) hc = 1ull << 16;
+    hub.keys = alloc<uint32_t>(hc);
+    hub.vals = alloc<u64a>(hc);
+    hub.cap = hc;
+    hub.top = &ds->hub_top;
+    hub.over_count = &ds->hub_over;
+    hcheck(hipStreamSynchronize(st));
+  }
+
+  void csr_init(Csr& c, bool wide) {
+    c.ref.off = alloc<uint64_t>(n);
+    c.ref.deg = alloc<uint32_t>(n);
+    c.ref.cap = alloc<uint32_t>(n);
+    hcheck(hipMemsetAsync(c.ref.off, 0, 8ull * n, st));
+    hcheck(hipMemsetAsync(c.ref.deg, 0, 4ull * n, st));
+    hcheck(hipMemsetAsync(c.ref.cap, 0, 4ull * n, st));
+    c.ref.wide = wide ? 1 : 0;
+    c.ref.nbr = nullptr;
+    c.ref.w = nullptr;
+    c.pool_cap = 0;
+  }
+
+  // ------------------------------------------------------------------ growable buffers
+  void ensure_records(uint64_t k) {
+    if (k <= rec_cap) return;
+    uint64_t c = std::max<uint64_t>(k, rec_cap * 2);
+    regrow(rkey0, c); regrow(rkey1, c); regrow(ridx0, c); regrow(ridx1, c); regrow(rdelta, c);
+    rec_cap = c;
+  }
+  void ensure_entries(uint64_t k) {
+    if (k <= ent_cap) return;
+    uint64_t c = std::max<uint64_t>(k, ent_cap * 2);
+    regrow(ekey0, c); regrow(ekey1, c); regrow(edel0, c); regrow(edel1, c); regrow(ex, c); regrow(ey, c);
+    ent_cap = c;
+  }
+  void ensure_insflag(uint64_t k) {
+    if (k <= ins_cap) return;
+    uint64_t c = std::max<uint64_t>(k, ins_cap * 2);
+    regrow(insflag, c);
+    ins_cap = c;
+  }
+  void ensure_tuples(uint64_t k) {
+    if (k <= tup_cap) return;
+    uint64_t c = std::max<uint64_t>(k, tup_cap + tup_cap / 2);
+    regrow(tk0, c); regrow(tk1, c); regrow(tk2, c); regrow(tv0, c); regrow(tv1, c); regrow(tv2, c);
+    regrow(tx, c); regrow(ty, c);
+    tup_cap = c;
+  }
+  void cub(int rc) {
+    if (rc == -2) throw NoMem{};
+    if (rc != 0) throw DeviceError{hipErrorUnknown};
+  }
+
+  // ------------------------------------------------------------------ dynamic CSR
+  // Rebuild the pool of c with per-row slack and room for `extra` more slots.
+  void csr_grow(Csr& c, uint64_t extra) {
+    uint32_t* newcap = alloc<uint32_t>(n);
+    uint64_t* newcap64 = alloc<uint64_t>(n);
+    uint64_t* newoff = alloc<uint64_t>(n);
+    launch_csr_newcap(c.ref.deg, newcap, newcap64, n, st);
+    cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, newcap64, newoff, n, st));
+    uint64_t last_off = 0, last_cap = 0;
+    hcheck(hipMemcpyAsync(&last_off, newoff + (n - 1), 8, hipMemcpyDeviceToHost, st));
+    hcheck(hipMemcpyAsync(&last_cap, newcap64 + (n - 1), 8, hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+    const uint64_t used = last_off + last_cap;
+    uint64_t cap = used + extra + (used + extra) / 2 + 1024;
+    CsrRef to = c.ref;
+    to.nbr = alloc<uint32_t>(cap);
+    to.w = c.ref.wide ? (void*)alloc<int64_t>(cap) : (void*)alloc<uint32_t>(cap);
+    if (c.ref.nbr) launch_csr_move_rows(c.ref, to, newoff, newcap, n, st);
+    else {
+      hcheck(hipMemcpyAsync(c.ref.off, newoff, 8ull * n, hipMemcpyDeviceToDevice, st));
+      hcheck(hipMemcpyAsync(c.ref.cap, newcap, 4ull * n, hipMemcpyDeviceToDevice, st));
+    }
+    hcheck(hipStreamSynchronize(st));
+    release(c.ref.nbr);
+    release(c.ref.w);
+    c.ref.nbr = to.nbr;
+    c.ref.w = to.w;
+    c.pool_cap = cap;
+    hcheck(hipMemcpyAsync(&ds->pool_top[c.slot], &used, 8, hipMemcpyHostToDevice, st));
+    hcheck(hipStreamSynchronize(st));
+    release(newcap);
+    release(newcap64);
+    release(newoff);
+  }
+
+  // Apply sorted records (key = row << 32 | col, distinct keys) to one orientation.
+  void csr_apply(Csr& c, const uint64_t* keys, const int64_t* delta, uint64_t k) {
+    if (k == 0) return;
+    if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
+    ensure_insflag(k);
+    begin(S_DIRTY);
+    launch_csr_find(c.ref, keys, delta, k, insflag, rowdel, rowins, ref(S_DIRTY), st);
+    sync_read();
+    const uint32_t nd = count(S_DIRTY);
+    if (nd == 0) return;
+    for (int attempt = 0;; ++attempt) {
+      const u64a saved = hs->pool_top[c.slot];
+      zero(&ds->overflow);
+      launch_csr_plan(c.ref, sets[S_DIRTY].list, nd, rowdel, rowins, plan_off, plan_cap, &ds->pool_top[c.slot],
+                      c.pool_cap, &ds->overflow, st);
+      sync_read();
+      if (!hs->overflow) break;
+      if (attempt > 3) throw NoMem{};
+      hcheck(hipMemcpyAsync(&ds->pool_top[c.slot], &saved, 8, hipMemcpyHostToDevice, st));
+      csr_grow(c, 2 * k + c.pool_cap / 4);
+      sync_read();
+    }
+    launch_csr_rewrite(c.ref, sets[S_DIRTY].list, nd, rowdel, rowins, plan_off, plan_cap, keys, delta, insflag, k,
+                       st);
+  }
+
+  // Apply reduced records to level s (out, and in via a transposed sort when directed).
+  void apply_records(int s, const uint64_t* keys, const int64_t* vals, uint64_t k, bool degrees) {
+    if (k == 0) return;
+    Level& V = lv[s];
+    csr_apply(V.out, keys, vals, k);
+    if (directed) {
+      // scratch tk1/tk2/tv2 must not alias the caller's keys/vals
+      if (k > tup_cap || keys == tk1 || keys == tk2 || vals == tv2) throw DeviceError{hipErrorInvalidValue};
+      launch_transpose_keys(keys, tk2, k, st);
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, vals, tv2, k, 0, 64, st));
+      // tk1 and tv2 now hold the transposed records in (col, row) order
+      csr_apply(V.in, tk1, tv2, k);
+    }
+    if (degrees) launch_csr_degrees(V.kout, directed ? V.kin : nullptr, keys, vals, k, st);
+  }
+
+  // sort (keys, vals) of length k and reduce equal keys; result in (tk2, tv2) with *runs
+  uint64_t sort_reduce(uint64_t* keys, int64_t* vals, uint64_t k, uint64_t* okeys, int64_t* ovals) {
+    if (k == 0) return 0;
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, keys, tk1, vals, tv1, k, 0, 64, st));
+    cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, okeys, tv1, ovals, &ds->nruns, k, st));
+    sync_read();
+    return hs->nruns;
+  }
+
+  // ------------------------------------------------------------------ batch ingest
+  // Returns LDL_OK or a validation error (state untouched).
+  int ingest(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg,
+             uint64_t nc) {
+    const uint64_t K = ni + nd + nc;
+    if (K == 0) return LDL_OK;
+    ensure_records(K);
+    ensure_entries(2 * K);
+    ensure_tuples(2 * K);
+    zero(&ds->err);
+    hcheck(hipMemsetAsync(&ds->first_bad, 0xFF, 4, st));
+    zero(&ds->dm);
+    launch_ingest_records(dins, ni, ddel, nd, dchg, nc, n, directed, rkey0, ridx0, &ds->err, st);
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, rkey0, rkey1, ridx0, ridx1, K, 0, 64, st));
+    sync_read();
+    if (hs->err & 1u) return LDL_EINVAL;
+    Level& V0 = lv[0];
+    if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
+    launch_ingest_check(V0.out.ref, rkey1, ridx1, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
+                        &ds->first_bad, &ds->dm, st);
+    sync_read();
+    if (hs->err & 2u) return LDL_EDUP;
+    if (hs->err & 12u) return hs->first_bad < ni ? LDL_EOVERFLOW : LDL_ENOEDGE;
+    if (m + hs->dm >= ((int64_t)1 << 40)) return LDL_EOVERFLOW;
+    const int64_t dm = hs->dm;
+    // matrix entries of the net changes
+    zero(&ds->ecount);
+    launch_ingest_entries(rkey1, rdelta, K, directed, ekey0, edel0, &ds->ecount, st);
+    sync_read();
+    const uint64_t E = hs->ecount;
+    if (E == 0) return LDL_OK;
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 64, st));
+    stats.updates = K;
+    // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
+    begin(S_TOUCH);
+    launch_ingest_mark(ekey1, E, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), st);
+    zero(&ds->dein);
+    zero(&ds->dskk_lo);
+    zero(&ds->dskk_hi);
+    launch_ingest_totals(ekey1, edel1, E, V0.lab, Kout, directed ? Kin : nullptr, &ds->dein, st);
+    sync_read();
+    launch_dskk(sets[S_TOUCH].list, count(S_TOUCH), Kout, Kin, tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
+    apply_records(0, ekey1, edel1, E, true);
+    sync_read();
+    m += dm;
+    Ein += hs->dein;
+    SKK += ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
+    // cascade the entry deltas through pi to every existing level; ancestors are seeds
+    if (top >= 1) {
+      launch_split_keys(ekey1, E, ex, ey, st);
+      for (int s = 1; s <= top; ++s) {
+        launch_cascade_map(ex, ey, edel1, E, lv[s - 1].par, tk0, tv0, ref(S_D0 + s), st);
+        const uint64_t R = sort_reduce(tk0, tv0, E, tk2, tv2);
+        // tk2/tv2 are reused inside apply_records for directed graphs: keep a copy
+        hcheck(hipMemcpyAsync(ekey0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
+        hcheck(hipMemcpyAsync(edel0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
+        apply_records(s, ekey0, edel0, R, true);
+      }
+    }
+    return LDL_OK;
+  }
+
+  // ------------------------------------------------------------------ candidates
+  MoveView view(int r, int refine) {
+    Level& V = lv[r];
+    MoveView mv{};
+    mv.out = V.out.ref;
+    mv.in = directed ? V.in.ref : CsrRef{};
+    mv.lab = V.lab;
+    mv.par = V.par;
+    mv.alive = V.alive;
+    mv.kout = V.kout;
+    mv.kin = V.kin;
+    if (refine) {
+      mv.Kout = lv[r + 1].kout;
+      mv.Kin = lv[r + 1].kin;
+    } else {
+      mv.Kout = Kout;
+      mv.Kin = Kin;
+    }
+    mv.rsize = V.rsize;
+    mv.qm = gq * m;
+    mv.p = gp;
+    mv.directed = directed;
+    return mv;
+  }
+
+  std::pair<hipEvent_t, hipEvent_t> next_events() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t a, b;
+      hcheck(hipEventCreate(&a));
+      hcheck(hipEventCreate(&b));
+      ev_pool.push_back(std::make_pair(a, b));
+    }
+    return ev_pool[ev_used++];
+  }
+
+  // BestMove_r / BestRef_r over list[0..cnt): candidates in `cand`, returns their number
+  uint32_t best(int r, const uint32_t* list, uint32_t cnt, int refine) {
+    if (cnt == 0) return 0;
+    MoveView mv = view(r, refine);
+    zero(&ds->ncand);
+    hcheck(hipMemsetAsync(ds->bins, 0, sizeof(ds->bins), st));
+    zero(&ds->st_entries);
+    zero(&ds->st_distinct);
+    zero(&ds->st_vertices);
+    launch_bin(mv, list, cnt, refine, bins, ds->bins, st);
+    sync_read();
+    uint32_t bc[kNumBins];
+    for (int b = 0; b < kNumBins; ++b) bc[b] = hs->bins[b];
+    MoveStats ms{&ds->st_entries, &ds->st_distinct, &ds->st_vertices};
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    if (profile) {
+      ev = next_events();
+      hcheck(hipEventRecord(ev.first, st));
+    }
+    for (int b = 0; b < kNumBins - 1; ++b) launch_best(mv, b, bins[b], bc[b], refine, cand, hub, ms, st);
+    uint32_t* hl = bins[kNumBins - 1];
+    uint32_t hcnt = bc[kNumBins - 1];
+    uint32_t* other = hub_over_alt;
+    while (hcnt) {
+      zero(&ds->hub_top);
+      zero(&ds->hub_over);
+      HubPool hp = hub;
+      hp.over = other;
+      launch_best(mv, kNumBins - 1, hl, hcnt, refine, cand, hp, ms, st);
+      sync_read();
+      const uint32_t left = hs->hub_over;
+      if (left >= hcnt) throw DeviceError{hipErrorUnknown};
+      std::swap(hl, other);
+      hcnt = left;
+    }
+    if (profile) hcheck(hipEventRecord(ev.second, st));
+    sync_read();
+    stats.scanned_vertices += hs->st_vertices;
+    stats.scanned_entries += hs->st_entries;
+    stats.distinct_comms += hs->st_distinct;
+    stats.candidates += hs->ncand;
+    if (profile) {
+      // algorithmic bytes: per vertex list id, offsets/degrees, label, degrees, own totals;
+      // per entry neighbour id, weight, neighbour label (+ parent in refinement); per
+      // distinct community its totals; per candidate the 28-byte record
+      const double wb = lv[r].out.ref.wide ? 8.0 : 4.0;
+      const double dirf = directed ? 2.0 : 1.0;
+      const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 8 : 8 * dirf);
+      const double per_e = 4 + wb + 4 + (refine ? 4 : 0);
+      const double per_d = 8 * dirf;
+      const double bytes = per_v * hs->st_vertices + per_e * hs->st_entries + per_d * hs->st_distinct +
+                           28.0 * hs->ncand;
+      bm_bytes_pending.push_back(bytes);
+      stats.bm_launches += 1;
+    }
+    return hs->ncand;
+  }
+
+  // exact greedy filter over cand[0..K): accepted candidate indices in `acc`; returns count
+  uint32_t decouple(uint32_t K) {
+    if (K == 0) return 0;
+    // order by (gain descending, vertex ascending) with stable radix passes
+    launch_iota(sidx0, K, st);
+    launch_gather_u32_as_u64(cand.v, nullptr, K, skey0, st);
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, 32, st));
+    launch_gather_u64(cand.glo, sidx1, K, skey0, 1, st);
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx1, sidx0, K, 0, 64, st));
+    zero(&ds->maxv);
+    cub(prim_max_u64(&cub_tmp, &cub_bytes, (const uint64_t*)cand.ghi, &ds->maxv, K, st));
+    sync_read();
+    uint32_t* order = sidx0;
+    if (hs->maxv != 0) {
+      launch_gather_u64((const uint64_t*)cand.ghi, sidx0, K, skey0, 1, st);
+      cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, 64, st));
+      order = sidx1;
+    }
+    launch_rank_from_order(order, K, rank, st);
+    // rounds
+    if (++acc_epoch == 0) {
+      launch_fill_u32(accE, 0, n, st);
+      launch_fill_u32(accA, 0, n, st);
+      acc_epoch = 1;
+    }
+    hcheck(hipMemsetAsync(lfflag, 0, K, st));
+    launch_iota(liveA, K, st);
+    zero(&ds->nacc);
+    uint32_t nl = K;
+    uint32_t *la = liveA, *lb = liveB;
+    while (nl) {
+      launch_lf_reset(la, nl, cand.a, cand.b, minE, minA, st);
+      launch_lf_min(la, nl, cand.a, cand.b, rank, minE, minA, st);
+      launch_lf_accept(la, nl, cand.a, cand.b, rank, minE, minA, accE, accA, acc_epoch, lfflag, acc, &ds->nacc, st);
+      zero(&ds->nlive2);
+      launch_lf_reject(la, nl, cand.a, cand.b, accE, accA, acc_epoch, lfflag, lb, &ds->nlive2, st);
+      sync_read();
+      if (hs->nlive2 >= nl) throw DeviceError{hipErrorUnknown};
+      nl = hs->nlive2;
+      std::swap(la, lb);
+    }
+    return hs->nacc;
+  }
+
+  void record(int r, int phase, int iter, uint64_t nscan, uint64_t ncand, uint64_t nacc, i128 dq) {
+    if (!tracing) return;
+    TraceRec t;
+    t.v[0] = pass_idx; t.v[1] = r; t.v[2] = phase; t.v[3] = iter;
+    t.v[4] = (int64_t)nscan; t.v[5] = (int64_t)ncand; t.v[6] = (int64_t)nacc; t.v[7] = (int64_t)(uint64_t)dq;
+    trace.push_back(t);
+  }
+
+  // ------------------------------------------------------------------ move commit
+  i128 commit_moves(int r, uint32_t na, int64_t& dein, i128& dskk) {
+    Level& V = lv[r];
+    begin(S_TOUCH);
+    begin(S_MOV);
+    launch_commit_mark(acc, na, cand, sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, Kout, Kin, ref(S_TOUCH), tko,
+                       tki, st);
+    launch_commit_apply(acc, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
+    zero(&ds->dein);
+    zero(&ds->dskk_lo);
+    zero(&ds->dskk_hi);
+    launch_commit_dein(acc, na, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
+                       sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, &ds->dein, st);
+    sync_read();
+    launch_dskk(sets[S_TOUCH].list, count(S_TOUCH), Kout, Kin, tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
+    sync_read();
+    dein = hs->dein;
+    dskk = ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
+    return (i128)gq * m * dein - (i128)gp * dskk;
+  }
+
+  // ------------------------------------------------------------------ one level
+  void process_level(int r) {
+    Level& V = lv[r];
+    stats.levels_processed++;
+    sync_read();
+    const uint32_t E0 = count(S_D0 + r);
+    hcheck(hipMemcpyAsync(entry, sets[S_D0 + r].list, 4ull * E0, hipMemcpyDeviceToDevice, st));
+    begin(S_D0 + r);
+    // frontier: alive seeds and all members of their communities
+    begin(S_COMM);
+    launch_set_add_mapped(ref(S_COMM), entry, E0, V.lab, V.alive, st);
+    begin(S_U);
+    launch_members(ref(S_U), n, V.alive, V.lab, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
+    const i128 Q0 = qnum();
+    begin(S_MOVED);
+    CsrRef in = directed ? V.in.ref : V.out.ref;
+    for (int j = 1; j <= M; ++j) {
+      stats.move_iters++;
+      sync_read();
+      const uint32_t nU = count(S_U);
+      begin(S_S);
+      launch_neighbours(ref(S_S), sets[S_U].list, nU, V.out.ref, in, directed, st);
+      sync_read();
+      const uint32_t nS = count(S_S);
+      const uint32_t K = best(r, sets[S_S].list, nS, 0);
+      const uint32_t na = decouple(K);
+      int64_t dein = 0;
+      i128 dskk = 0;
+      const i128 dq = commit_moves(r, na, dein, dskk);
+      record(r, 0, j, nS, K, na, dq);
+      if (dq < 0) {  // Alg. 1 l.11
+        launch_commit_apply(acc, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
+        stats.rollbacks++;
+        break;
+      }
+      Ein += dein;
+      SKK += dskk;
+      stats.accepted += na;
+      launch_set_add_acc_v(ref(S_MOVED), acc, na, cand, st);
+      // Expand_r: movers, their neighbours, members of the touched communities
+      begin(S_U2);
+      if (na) {
+        begin(S_COMM);
+        launch_mark_acc_comms(acc, na, cand, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
+        launch_members(ref(S_U2), n, V.alive, V.lab, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
+        launch_neighbours_acc(ref(S_U2), acc, na, cand, V.out.ref, in, directed, st);
+      }
+      std::swap(sets[S_U], sets[S_U2]);
+      if ((i128)ad * dq < (i128)an * Q0) break;            // Alg. 1 l.13
+      if ((i128)bd * na < (i128)bn * nS) break;           // Alg. 1 l.14
+    }
+    if (r < L) refine(r, E0);
+    sync_read();
+    if (r >= 1 && count(S_MOVED) > 0) label_refresh(r);
+  }
+
+  // ------------------------------------------------------------------ refinement
+  void refine(int r, uint32_t E0) {
+    Level& V = lv[r];
+    Level& H = lv[r + 1];
+    int64_t* Krin = directed ? H.kin : nullptr;
+    if (r == top) launch_ref_init_top(n, V.alive, V.kout, V.kin, H.kout, Krin, V.rsize, st);
+    sync_read();
+    const uint32_t nMoved = count(S_MOVED);
+    begin(S_REFM);
+    launch_set_add_mapped(ref(S_REFM), entry, E0, V.par, nullptr, st);
+    launch_set_add_mapped(ref(S_REFM), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
+    begin(S_RSET);
+    launch_members(ref(S_RSET), n, V.alive, V.par, sets[S_REFM].stamp, sets[S_REFM].epoch, st);
+    sync_read();
+    const uint32_t nR0 = count(S_RSET);
+    launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st);
+    launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 1, st);
+    const uint32_t* Rl = sets[S_RSET].list;
+    uint32_t Rc = nR0;
+    CsrRef in = directed ? V.in.ref : V.out.ref;
+    for (int j = 1; j <= M; ++j) {
+      stats.refine_iters++;
+      const uint32_t K = best(r, Rl, Rc, 1);
+      const uint32_t na = decouple(K);
+      launch_ref_commit(acc, na, cand, V.par, V.kout, V.kin, H.kout, Krin, V.rsize, st);
+      stats.refine_moves += na;
+      record(r, 1, j, Rc, K, na, 0);
+      if ((i128)bd * na < (i128)bn * Rc) break;            // Alg. 1 l.20
+      begin(S_RCUR);
+      launch_spexpand(acc, na, cand, V.out.ref, in, directed, V.lab, V.par, V.rsize, ref(S_RCUR), ref(S_RSET),
+                      oldpar, st);
+      sync_read();
+      Rl = sets[S_RCUR].list;
+      Rc = count(S_RCUR);
+    }
+    if (r == top) materialise(r);
+    else aggregate(r, E0);
+  }
+
+  // ------------------------------------------------------------------ aggregate repair
+  void aggregate(int r, uint32_t E0) {
+    Level& V = lv[r];
+    Level& H = lv[r + 1];
+    sync_read();
+    const uint32_t nRset = count(S_RSET), nMoved = count(S_MOVED);
+    begin(S_C);
+    launch_changed(sets[S_RSET].list, nRset, V.par, oldpar, ref(S_C), st);
+    sync_read();
+    const uint32_t nC = count(S_C);
+    CsrRef in = directed ? V.in.ref : V.out.ref;
+    zero(&ds->tneed);
+    launch_tuple_count(sets[S_C].list, nC, V.out.ref, in, directed, &ds->tneed, st);
+    sync_read();
+    ensure_tuples(hs->tneed + 16);
+    zero(&ds->tcount);
+    const int Dn = S_D0 + r + 1;
+    launch_tuples(sets[S_C].list, nC, V.out.ref, in, directed, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, 1,
+                  tk0, tv0, &ds->tcount, tup_cap, ref(Dn), st);
+    // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
+    launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
+    launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
+    launch_set_add_mapped(ref(Dn), sets[S_RSET].list, nRset, V.par, nullptr, st);
+    launch_set_add_mapped(ref(Dn), sets[S_C].list, nC, oldpar, nullptr, st);
+    // liveness of level r+1 and revival / death chains above it
+    begin(S_LVC);
+    launch_set_add_mapped(ref(S_LVC), sets[S_RSET].list, nRset, oldpar, nullptr, st);
+    launch_set_add_mapped(ref(S_LVC), sets[S_RSET].list, nRset, V.par, nullptr, st);
+    sync_read();
+    begin(S_DIED);
+    begin(S_REV);
+    launch_live_update(sets[S_LVC].list, count(S_LVC), V.rsize, H.alive, r + 1 < L ? H.par : nullptr, H.lab, V.lab,
+                       ref(S_DIED), ref(S_REV), st);
+    launch_label_up(sets[S_RSET].list, nRset, V.par, H.alive, V.lab, H.lab, st);
+    int died = S_DIED, rev = S_REV, died2 = S_DIED2, rev2 = S_REV2;
+    for (int s = r + 2; s <= top; ++s) {
+      sync_read();
+      const uint32_t nd = count(died), nrv = count(rev);
+      if (nd + nrv == 0) break;
+      begin(S_LVC);
+      launch_live_prop(sets[died].list, nd, sets[rev].list, nrv, lv[s - 1].par, lv[s - 1].rsize, ref(S_LVC), st);
+      sync_read();
+      begin(died2);
+      begin(rev2);
+      launch_live_update(sets[S_LVC].list, count(S_LVC), lv[s - 1].rsize, lv[s].alive, s < L ? lv[s].par : nullptr,
+                         lv[s].lab, lv[s - 1].lab, ref(died2), ref(rev2), st);
+      std::swap(died, died2);
+      std::swap(rev, rev2);
+    }
+    // subtract-add tuples: reduce, apply at r+1 (degrees already exact), cascade upwards
+    sync_read();
+    const uint64_t T = hs->tcount;
+    if (T > tup_cap) throw DeviceError{hipErrorUnknown};
+    stats.agg_tuples += T;
+    uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
+    if (R == 0) return;
+    hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
+    hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
+    apply_records(r + 1, tk0, tv0, R, false);
+    for (int s = r + 2; s <= top; ++s) {
+      launch_split_keys(tk0, R, tx, ty, st);
+      SetRef none{};
+      launch_cascade_map(tx, ty, tv0, R, lv[s - 1].par, tk2, tv2, none, st);
+      // tk2/tv2 hold the mapped records; reduce them into tk0/tv0
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 64, st));
+      cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, tk0, tv1, tv0, &ds->nruns, R, st));
+      sync_read();
+      R = hs->nruns;
+      if (R == 0) return;
+      apply_records(s, tk0, tv0, R, true);
+    }
+  }
+
+  // first visit of level r+1: Eq. 3 from scratch
+  void materialise(int r) {
+    Level& V = lv[r];
+    Level& H = lv[r + 1];
+    launch_materialise_nodes(n, V.rsize, H.alive, V.lab, H.lab, r + 1 < L ? H.par : nullptr, st);
+    begin(S_TMP);
+    launch_alive_list(n, V.alive, ref(S_TMP), st);
+    sync_read();
+    const uint32_t na = count(S_TMP);
+    CsrRef in = directed ? V.in.ref : V.out.ref;
+    zero(&ds->tneed);
+    launch_tuple_count(sets[S_TMP].list, na, V.out.ref, in, directed, &ds->tneed, st);
+    sync_read();
+    ensure_tuples(hs->tneed / 2 + 16);
+    zero(&ds->tcount);
+    SetRef none{};
+    launch_tuples(sets[S_TMP].list, na, V.out.ref, in, directed, V.par, nullptr, nullptr, 0, 0, tk0, tv0,
+                  &ds->tcount, tup_cap, none, st);
+    sync_read();
+    const uint64_t T = hs->tcount;
+    if (T > tup_cap) throw DeviceError{hipErrorUnknown};
+    const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
+    hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
+    hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
+    apply_records(r + 1, tk0, tv0, R, false);
+    top = r + 1;
+    launch_alive_list(n, H.alive, ref(S_D0 + r + 1), st);
+  }
+
+  void label_refresh(int r) {
+    for (int s = r - 1; s >= 0; --s)
+      launch_label_refresh(n, lv[s].alive, lv[s].par, lv[s + 1].lab, lv[s].lab, ref(S_D0 + s), st);
+  }
+
+  // ------------------------------------------------------------------ Algorithm 1
+  int apply(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg, uint64_t nc) {
+    const int rc = ingest(dins, ni, ddel, nd, dchg, nc);
+    if (rc != LDL_OK) return rc;
+    for (int i = 1; i <= N; ++i) {
+      pass_idx = i;
+      const i128 Qp = qnum();
+      bool any = false;
+      for (int r = 0; r <= top && r <= L; ++r) {
+        sync_read();
+        if (count(S_D0 + r) == 0) continue;
+        any = true;
+        process_level(r);
+      }
+      sync_read();
+      bool all_empty = true;
+      for (int r = 0; r <= L; ++r)
+        if (count(S_D0 + r)) all_empty = false;
+      if (!any || all_empty) break;
+      if ((i128)ad * (qnum() - Qp) < (i128)an * Qp) break;  // Alg. 1 l.27
+    }
+    for (int r = 0; r <= L; ++r) begin(S_D0 + r);
+    hcheck(hipStreamSynchronize(st));
+    return LDL_OK;
+  }
+
+  void finish_profile() {
+    if (!profile) return;
+    hcheck(hipStreamSynchronize(st));
+    for (size_t i = 0; i < ev_used; ++i) {
+      float ms = 0;
+      hcheck(hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second));
+      stats.bm_ms += ms;
+    }
+    for (double b : bm_bytes_pending) stats.bm_bytes += b;
+    ev_used = 0;
+    bm_bytes_pending.clear();
+  }
+
+  // ------------------------------------------------------------------ export
+  void export_entries(int r, std::vector<uint64_t>& keys, std::vector<int64_t>& w) {
+    Level& V = lv[r];
+    zero(&ds->ecount);
+    sync_read();
+    uint64_t nnz = nnz_of(r);
+    keys.assign(nnz, 0);
+    w.assign(nnz, 0);
+    if (nnz == 0 || !V.out.ref.nbr) return;
+    ensure_tuples(nnz);
+    zero(&ds->ecount);
+    launch_csr_entries(V.out.ref, n, tk0, tv0, &ds->ecount, st);
+    hcheck(hipMemcpyAsync(keys.data(), tk0, 8 * nnz, hipMemcpyDeviceToHost, st));
+    hcheck(hipMemcpyAsync(w.data(), tv0, 8 * nnz, hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+    std::vector<std::pair<uint64_t, int64_t>> kv(nnz);
+    for (uint64_t i = 0; i < nnz; ++i) kv[i] = std::make_pair(keys[i], w[i]);
+    std::sort(kv.begin(), kv.end());
+    for (uint64_t i = 0; i < nnz; ++i) { keys[i] = kv[i].first; w[i] = kv[i].second; }
+  }
+  uint64_t nnz_of(int r) {
+    std::vector<uint32_t> deg(n);
+    hcheck(hipMemcpyAsync(deg.data(), lv[r].out.ref.deg, 4ull * n, hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+    uint64_t s = 0;
+    for (uint32_t d : deg) s += d;
+    return s;
+  }
+};
+
+}  // namespace ldl
+
+// ====================================================================== C ABI
+
+struct ldl_handle {
+  ldl::Engine* e;
+};
+
+namespace {
+
+int guard_err(ldl_handle* h, int code) {
+  if (code == LDL_EDEVICE && h) h->e->broken = true;
+  return code;
+}
+
+template <typename F>
+int run_guarded(ldl_handle* h, F&& f) {
+  try {
+    return f();
+  } catch (const ldl::NoMem&) {
+    return LDL_ENOMEM;
+  } catch (const ldl::DeviceError&) {
+    return guard_err(h, LDL_EDEVICE);
+  } catch (const std::bad_alloc&) {
+    return LDL_ENOMEM;
+  }
+}
+
+bool cfg_ok(const ldl_config& c) {
+  auto in16 = [](int32_t x, int32_t lo) { return x >= lo && x < 65536; };
+  return in16(c.gamma_num, 1) && in16(c.gamma_den, 1) && c.N >= 1 && c.M >= 1 && c.L >= 0 && c.L <= 16 &&
+         in16(c.alpha_num, 0) && in16(c.alpha_den, 1) && in16(c.beta_num, 0) && in16(c.beta_den, 1) &&
+         (c.directed == 0 || c.directed == 1);
+}
+
+int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair* del, uint64_t nd,
+                 const ldl_edge* chg, uint64_t nc, ldl_batch_stats* stats, bool on_device) {
+  if (!h) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  if ((ni && !ins) || (nd && !del) || (nc && !chg)) return LDL_EINVAL;
+  if (ni + nd + nc >= (1ull << 31)) return LDL_EINVAL;
+  return run_guarded(h, [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    e.stats = ldl_batch_stats{};
+    hipEvent_t t0, t1;
+    ldl::hcheck(hipEventCreate(&t0));
+    ldl::hcheck(hipEventCreate(&t1));
+    ldl::hcheck(hipEventRecord(t0, e.st));
+    const uint32_t *di = (const uint32_t*)ins, *dd = (const uint32_t*)del, *dc = (const uint32_t*)chg;
+    uint32_t* tmp = nullptr;
+    if (!on_device) {
+      const uint64_t words = 3 * ni + 2 * nd + 3 * nc;
+      tmp = ldl::dalloc<uint32_t>(words ? words : 1);
+      if (ni) ldl::hcheck(hipMemcpyAsync(tmp, ins, 12 * ni, hipMemcpyHostToDevice, e.st));
+      if (nd) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni, del, 8 * nd, hipMemcpyHostToDevice, e.st));
+      if (nc) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni + 2 * nd, chg, 12 * nc, hipMemcpyHostToDevice, e.st));
+      di = tmp;
+      dd = tmp + 3 * ni;
+      dc = tmp + 3 * ni + 2 * nd;
+    }
+    int rc;
+    try {
+      rc = e.apply(di, ni, dd, nd, dc, nc);
+    } catch (...) {
+      if (tmp) (void)hipFree(tmp);
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      throw;
+    }
+    ldl::hcheck(hipEventRecord(t1, e.st));
+    ldl::hcheck(hipEventSynchronize(t1));
+    float ms = 0;
+    ldl::hcheck(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (tmp) (void)hipFree(tmp);
+    e.finish_profile();
+    e.stats.total_ms = ms;
+    if (stats) *stats = e.stats;
+    return rc;
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+void ldl_default_config(ldl_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->directed = 0;
+  c->gamma_num = 1; c->gamma_den = 1;
+  c->N = 2; c->L = 4; c->M = 5;
+  c->alpha_num = 1; c->alpha_den = 1000;
+  c->beta_num = 1; c->beta_den = 100;
+  c->device = 0;
+  c->stream = nullptr;
+  c->profile = 0;
+}
+
+int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_t n_edges, ldl_handle** out) {
+  if (!out) return LDL_EINVAL;
+  *out = nullptr;
+  ldl_config c;
+  ldl_default_config(&c);
+  if (cfg) c = *cfg;
+  if (n == 0 || !cfg_ok(c) || (n_edges && !edges)) return LDL_EINVAL;
+  ldl_handle* h = new (std::nothrow) ldl_handle;
+  if (!h) return LDL_ENOMEM;
+  h->e = new (std::nothrow) ldl::Engine();
+  if (!h->e) {
+    delete h;
+    return LDL_ENOMEM;
+  }
+  int rc = run_guarded(h, [&]() -> int {
+    h->e->init(c, n);
+    return LDL_OK;
+  });
+  if (rc == LDL_OK) rc = apply_common(h, edges, n_edges, nullptr, 0, nullptr, 0, nullptr, false);
+  if (rc != LDL_OK) {
+    delete h->e;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LDL_OK;
+}
+
+int ldl_apply_batch(ldl_handle* h, const ldl_edge* ins, uint64_t n_ins, const ldl_pair* del, uint64_t n_del,
+                    const ldl_edge* chg, uint64_t n_chg, ldl_batch_stats* stats) {
+  return apply_common(h, ins, n_ins, del, n_del, chg, n_chg, stats, false);
+}
+
+int ldl_apply_batch_device(ldl_handle* h, const ldl_edge* d_ins, uint64_t n_ins, const ldl_pair* d_del,
+                           uint64_t n_del, const ldl_edge* d_chg, uint64_t n_chg, ldl_batch_stats* stats) {
+  return apply_common(h, d_ins, n_ins, d_del, n_del, d_chg, n_chg, stats, true);
+}
+
+int ldl_get_partition(const ldl_handle* h, uint32_t* labels, uint64_t n) {
+  if (!h || !labels || n != h->e->n) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    ldl::hcheck(hipMemcpyAsync(labels, e.lv[0].lab, 4ull * e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipStreamSynchronize(e.st));
+    return LDL_OK;
+  });
+}
+
+int ldl_modularity_exact(const ldl_handle* h, int64_t* num_hi, uint64_t* num_lo, int64_t* den_hi,
+                         uint64_t* den_lo) {
+  if (!h || !num_hi || !num_lo || !den_hi || !den_lo) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  const ldl::Engine& e = *h->e;
+  const ldl::i128 num = e.qnum();
+  const ldl::i128 den = (ldl::i128)e.gq * e.m * e.m;
+  *num_hi = (int64_t)(num >> 64);
+  *num_lo = (uint64_t)num;
+  *den_hi = (int64_t)(den >> 64);
+  *den_lo = (uint64_t)den;
+  return LDL_OK;
+}
+
+int ldl_modularity(const ldl_handle* h, double* q) {
+  if (!h || !q) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  const ldl::Engine& e = *h->e;
+  if (e.m == 0) {
+    *q = 0.0;
+    return LDL_OK;
+  }
+  *q = (double)e.qnum() / ((double)e.gq * (double)e.m * (double)e.m);
+  return LDL_OK;
+}
+
+void ldl_destroy(ldl_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->e->device);
+  delete h->e;
+  delete h;
+}
+
+int ldl_export_scalars(const ldl_handle* h, int32_t* top, int64_t* m, int64_t* ein, int64_t* skk_hi,
+                       uint64_t* skk_lo) {
+  if (!h || !top || !m || !ein || !skk_hi || !skk_lo) return LDL_EINVAL;
+  const ldl::Engine& e = *h->e;
+  *top = e.top;
+  *m = e.m;
+  *ein = e.Ein;
+  *skk_hi = (int64_t)(e.SKK >> 64);
+  *skk_lo = (uint64_t)e.SKK;
+  return LDL_OK;
+}
+
+int ldl_export_totals(const ldl_handle* h, int64_t* kout, int64_t* kin) {
+  if (!h || !kout || !kin) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    ldl::hcheck(hipMemcpyAsync(kout, e.Kout, 8ull * e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipMemcpyAsync(kin, e.Kin, 8ull * e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipStreamSynchronize(e.st));
+    return LDL_OK;
+  });
+}
+
+int ldl_export_level(const ldl_handle* h, int32_t r, uint8_t* alive, uint32_t* lab, uint32_t* par, int64_t* kout,
+                     int64_t* kin) {
+  if (!h || !alive || !lab || !par || !kout || !kin) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  if (r < 0 || r > h->e->top) return LDL_EINVAL;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    ldl::Level& V = e.lv[r];
+    ldl::hcheck(hipMemcpyAsync(alive, V.alive, e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipMemcpyAsync(lab, V.lab, 4ull * e.n, hipMemcpyDeviceToHost, e.st));
+    if (V.par) ldl::hcheck(hipMemcpyAsync(par, V.par, 4ull * e.n, hipMemcpyDeviceToHost, e.st));
+    else std::memset(par, 0, 4ull * e.n);
+    ldl::hcheck(hipMemcpyAsync(kout, V.kout, 8ull * e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipMemcpyAsync(kin, V.kin, 8ull * e.n, hipMemcpyDeviceToHost, e.st));
+    ldl::hcheck(hipStreamSynchronize(e.st));
+    return LDL_OK;
+  });
+}
+
+uint64_t ldl_level_nnz(const ldl_handle* h, int32_t r) {
+  if (!h || h->e->broken || r < 0 || r > h->e->top) return 0;
+  uint64_t v = 0;
+  int rc = run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    v = h->e->nnz_of(r);
+    return LDL_OK;
+  });
+  return rc == LDL_OK ? v : 0;
+}
+
+int ldl_export_entries(const ldl_handle* h, int32_t r, uint32_t* rows, uint32_t* cols, int64_t* w) {
+  if (!h || !rows || !cols || !w) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  if (r < 0 || r > h->e->top) return LDL_EINVAL;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    std::vector<uint64_t> keys;
+    std::vector<int64_t> ws;
+    h->e->export_entries(r, keys, ws);
+    for (size_t i = 0; i < keys.size(); ++i) {
+      rows[i] = (uint32_t)(keys[i] >> 32);
+      cols[i] = (uint32_t)keys[i];
+      w[i] = ws[i];
+    }
+    return LDL_OK;
+  });
+}
+
+int ldl_set_trace(ldl_handle* h, int32_t on) {
+  if (!h) return LDL_EINVAL;
+  h->e->tracing = on != 0;
+  h->e->trace.clear();
+  return LDL_OK;
+}
+
+uint64_t ldl_trace_len(const ldl_handle* h) { return h ? h->e->trace.size() : 0; }
+
+int ldl_trace(const ldl_handle* h, int64_t* out) {
+  if (!h || !out) return LDL_EINVAL;
+  for (size_t i = 0; i < h->e->trace.size(); ++i) std::memcpy(out + 8 * i, h->e->trace[i].v, 64);
+  return LDL_OK;
+}
+
+const char* ldl_strerror(int code) {
+  switch (code) {
+    case LDL_OK: return "LDL_OK";
+    case LDL_EINVAL: return "LDL_EINVAL";
+    case LDL_EDUP: return "LDL_EDUP";
+    case LDL_ENOEDGE: return "LDL_ENOEDGE";
+    case LDL_EOVERFLOW: return "LDL_EOVERFLOW";
+    case LDL_ENOMEM: return "LDL_ENOMEM";
+    case LDL_EDEVICE: return "LDL_EDEVICE";
+    case LDL_EBROKEN: return "LDL_EBROKEN";
+    default: return "LDL_UNKNOWN";
+  }
+}
+
+const char* ldl_version(void) { return "ldl 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Device-side helpers shared by the LD-Leiden HIP kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ldl {
+
+typedef __int128 i128;
+typedef unsigned long long u64a;   // type taken by the 64-bit atomics
+typedef long long i64a;
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------------ stamped sets
+// A set over ids [0, n) is a stamp array plus an append list: x is in the set iff
+// stamp[x] == epoch.  The first inserter of x appends it to the list.
+__device__ __forceinline__ bool set_claim(uint32_t* stamp, uint32_t epoch, uint32_t x) {
+  if (__hip_atomic_load(&stamp[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return false;
+  return atomicExch(&stamp[x], epoch) != epoch;
+}
+__device__ __forceinline__ void set_add(uint32_t* stamp, uint32_t epoch, uint32_t* list, uint32_t* count,
+                                        uint32_t x) {
+  if (set_claim(stamp, epoch, x)) list[atomicAdd(count, 1u)] = x;
+}
+
+// ------------------------------------------------------------------ exact accumulation
+// Signed 128-bit accumulation into (lo, hi) words with two 64-bit atomics: the carry out of
+// the low word is detected from the value returned by the low-word atomic.
+__device__ __forceinline__ void atomic_add_i128(u64a* lo, i64a* hi, i128 v) {
+  const u64a vlo = (u64a)v;
+  const i64a vhi = (i64a)(v >> 64);
+  const u64a old = atomicAdd(lo, vlo);
+  const i64a carry = (old + vlo < old) ? 1 : 0;
+  if (vhi + carry != 0) atomicAdd((u64a*)hi, (u64a)(vhi + carry));
+}
+__device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) { atomicAdd((u64a*)p, (u64a)v); }
+
+// ------------------------------------------------------------------ wave reductions
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Best (gain, id): larger gain wins, equal gains go to the lower id.  valid == false is
+// worse than anything.
+struct Best {
+  int64_t hi;
+  uint64_t lo;
+  uint32_t id;
+  int valid;
+};
+__device__ __forceinline__ i128 best_gain(const Best& b) { return ((i128)b.hi << 64) | (i128)b.lo; }
+__device__ __forceinline__ bool better(const Best& x, const Best& y) {
+  if (!x.valid) return false;
+  if (!y.valid) return true;
+  if (x.hi != y.hi) return x.hi > y.hi;
+  if (x.lo != y.lo) return x.lo > y.lo;
+  return x.id < y.id;
+}
+__device__ __forceinline__ Best shfl_xor_best(const Best& b, int mask, int width) {
+  Best r;
+  r.hi = __shfl_xor(b.hi, mask, width);
+  r.lo = (uint64_t)__shfl_xor((long long)b.lo, mask, width);
+  r.id = (uint32_t)__shfl_xor((int)b.id, mask, width);
+  r.valid = __shfl_xor(b.valid, mask, width);
+  return r;
+}
+// reduce over aligned groups of `width` lanes (width a power of two <= 64)
+__device__ __forceinline__ Best group_best(Best b, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) {
+    Best t = shfl_xor_best(b, o, width);
+    if (better(t, b)) b = t;
+  }
+  return b;
+}
+__device__ __forceinline__ Best make_best(i128 g, uint32_t id) {
+  Best b;
+  b.hi = (int64_t)(g >> 64);
+  b.lo = (uint64_t)g;
+  b.id = id;
+  b.valid = 1;
+  return b;
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+}  // namespace ldl

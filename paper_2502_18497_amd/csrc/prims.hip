@@ -1,0 +1,95 @@
+// Library primitives (radix sort, reduce-by-key, scan, max) from hipCUB, with temporary
+// storage grown on demand.
+#include <hipcub/hipcub.hpp>
+
+#include "ldl_kernels.h"
+
+namespace ldl {
+
+namespace {
+
+int ensure(void** tmp, size_t* bytes, size_t need) {
+  if (need <= *bytes && *tmp) return 0;
+  if (*tmp) (void)hipFree(*tmp);
+  *tmp = nullptr;
+  size_t n = need + (need >> 2) + 256;
+  if (hipMalloc(tmp, n) != hipSuccess) {
+    *tmp = nullptr;
+    *bytes = 0;
+    return -1;
+  }
+  *bytes = n;
+  return 0;
+}
+
+struct SumI64 {
+  __host__ __device__ __forceinline__ int64_t operator()(const int64_t& a, const int64_t& b) const { return a + b; }
+};
+
+}  // namespace
+
+int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+                            uint32_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) !=
+      hipSuccess)
+    return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceRadixSort::SortPairs(*tmp, have, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) ==
+                 hipSuccess
+             ? 0
+             : -1;
+}
+
+int prim_sort_pairs_u64_i64(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,
+                            int64_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) !=
+      hipSuccess)
+    return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceRadixSort::SortPairs(*tmp, have, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) ==
+                 hipSuccess
+             ? 0
+             : -1;
+}
+
+int prim_reduce_by_key(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,
+                       int64_t* vout, u64a* nruns, uint64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceReduce::ReduceByKey(nullptr, need, kin, kout, vin, vout, nruns, SumI64(), (int)n, s) !=
+      hipSuccess)
+    return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceReduce::ReduceByKey(*tmp, have, kin, kout, vin, vout, nruns, SumI64(), (int)n, s) ==
+                 hipSuccess
+             ? 0
+             : -1;
+}
+
+int prim_exclusive_sum_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, uint64_t* out, uint64_t n,
+                           hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceScan::ExclusiveSum(*tmp, have, in, out, (int)n, s) == hipSuccess ? 0 : -1;
+}
+
+int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, uint64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceReduce::Max(nullptr, need, in, (uint64_t*)out, (int)n, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceReduce::Max(*tmp, have, in, (uint64_t*)out, (int)n, s) == hipSuccess ? 0 : -1;
+}
+
+}  // namespace ldl

@@ -1,0 +1,60 @@
+"""Shared drivers for GPU-versus-oracle parity runs."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from tests.statecheck import check_state, diff_states, oracle_state
+
+
+def first_trace_divergence(tg: np.ndarray, to: np.ndarray):
+    k = min(len(tg), len(to))
+    for i in range(k):
+        if not np.array_equal(tg[i], to[i]):
+            return i, tg[i].tolist(), to[i].tolist()
+    if len(tg) != len(to):
+        return k, (tg[k].tolist() if k < len(tg) else None), (to[k].tolist() if k < len(to) else None)
+    return None
+
+
+def run_parity(n, edges, batches, directed=False, full_state=True, check_invariants=True, **cfg):
+    """Create both sides, apply the same batches and compare after every step.  Returns the
+    GPU graph and the oracle for further checks."""
+    import paper_2502_18497_amd as ldl
+
+    og = oracle.Oracle(n, edges, directed=directed, flags=oracle.FLAG_TRACE, **cfg)
+    g = ldl.Graph(n, edges, directed=directed, **cfg)
+    g.set_trace(True)
+    # the trace is enabled after creation on the GPU side: compare creation by state only
+    step = "create"
+
+    def compare():
+        pg, po = g.partition(), og.partition()
+        msgs = []
+        if not np.array_equal(pg, po):
+            msgs.append(f"partition differs at {int(np.count_nonzero(pg != po))} vertices")
+        if g.qnum() != og.qnum():
+            msgs.append(f"Q numerator {g.qnum()} != {og.qnum()}")
+        if full_state:
+            sg, so = g.state(), oracle_state(og)
+            msgs += diff_states(sg, so)
+            if check_invariants:
+                msgs += [f"gpu invariant: {m}" for m in check_state(sg, directed)]
+        return msgs
+
+    msgs = compare()
+    assert not msgs, (step, msgs)
+    og.trace_clear()
+    for bi, b in enumerate(batches):
+        step = f"batch {bi}"
+        rcg = g.apply_batch(b.ins, b.dels, b.chg, raise_on_error=False)
+        rco = og.apply_batch(b.ins, b.dels, b.chg)
+        assert rco == 0, (step, rco)
+        assert isinstance(rcg, dict), (step, rcg)
+        msgs = compare()
+        if msgs:
+            div = first_trace_divergence(g.trace(), og.trace())
+            raise AssertionError((step, msgs, "first trace divergence (gpu, oracle):", div))
+        g.set_trace(True)
+        og.trace_clear()
+    return g, og
