@@ -1,0 +1,326 @@
+#!/usr/bin/env python3
+"""Batch-update throughput of the gfx950 LD-Leiden library on one GPU.
+
+Workload: undirected R-MAT, scale 20 (1,048,576 vertices, 8,388,608 unique edges,
+a/b/c/d = 0.57/0.19/0.19/0.05, weights uniform 1..16, gamma = 1), static Leiden at creation
+(untimed set-up), then a stream of update batches of 10^4 updates (70% inserts of random
+non-edges, 20% deletions, 10% reweights).  One step = one ldl_apply_batch_device call (the
+whole batch update of Algorithm 1) on a batch already resident in HBM.  A second timed phase
+runs batches of 10^3 updates for the batch-size comparison.
+
+The JSON line carries the roofline of the dominant local-move kernel (HIP events around each
+of its launches during the timed steps, algorithmic bytes counted by the kernels) and the CPU
+oracle's throughput on a bounded sample of the same stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline_worker(scale, batch, nbatches, out):
+    """Oracle on the same stream: creation (untimed) then `nbatches` timed batches."""
+    import oracle
+    import synth
+
+    s = synth.rmat_undirected(scale=scale)
+    e = s.edges()
+    t0 = time.perf_counter()
+    o = oracle.Oracle(s.n, e)
+    out["create_s"] = time.perf_counter() - t0
+    out["batches"] = [s.batch(batch) for _ in range(nbatches)]
+    out["oracle"] = o
+
+
+def run_mix(args):
+    """Uneven multi-graph mix: graphs of log-uniform size with their own batch streams of
+    log-uniform batch size; plain = each graph's batches applied one call at a time, graph
+    after graph; batched = one ldl_apply_batches call per step holding every graph's next
+    batch.  Both start from the same created states; results are checked to be identical."""
+    import numpy as np
+    import torch  # noqa: F401
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    rng = np.random.default_rng(synth.BASE_SEED + 4)
+    streams, sizes = [], []
+    for g in range(args.graphs):
+        s, bs = synth.planted_mix_graph(g, nmin_exp=3.0, nmax_exp=args.mix_max_exp)
+        streams.append(s)
+        sizes.append([min(b, max(1, s.num_edges() // 2), args.mix_max_batch) for b in bs[:args.steps]])
+    edges = [s.edges() for s in streams]
+    batches = [[st.batch(b) for b in sz] for st, sz in zip(streams, sizes)]
+    t0 = time.perf_counter()
+    plain = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+    batched = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+    log(f"created {2 * len(streams)} graphs (sum n = {sum(s.n for s in streams)}) in {time.perf_counter() - t0:.1f}s")
+    updates = sum(b.size for bl in batches for b in bl)
+    lat_plain = []
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        for g in range(len(streams)):
+            b = batches[g][j]
+            t = time.perf_counter()
+            plain[g].apply_batch(b.ins, b.dels, b.chg)
+            lat_plain.append(time.perf_counter() - t)
+    t_plain = time.perf_counter() - t0
+    lat_step = []
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        t = time.perf_counter()
+        status, _ = ldl.apply_batches(batched, [(batches[g][j].ins, batches[g][j].dels, batches[g][j].chg)
+                                                for g in range(len(streams))], workers=args.workers)
+        lat_step.append(time.perf_counter() - t)
+        assert all(x == 0 for x in status)
+    t_batched = time.perf_counter() - t0
+    same = all(np.array_equal(a.partition(), b.partition()) and a.qnum() == b.qnum() for a, b in zip(plain, batched))
+    out = {"metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
+           "value": updates / t_batched, "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": 1e3 * t_batched / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"mix-{len(streams)}-planted-graphs", "graphs": len(streams),
+                      "n_range": [min(s.n for s in streams), max(s.n for s in streams)],
+                      "sum_n": sum(s.n for s in streams), "batches_per_graph": args.steps,
+                      "workers": args.workers, "updates": updates},
+           "plain_edges_per_s": updates / t_plain, "batched_vs_plain": t_plain / t_batched,
+           "identical_to_plain": bool(same),
+           "latency_ms": {"plain_batch_p50": float(1e3 * np.percentile(lat_plain, 50)),
+                          "plain_batch_p99": float(1e3 * np.percentile(lat_plain, 99)),
+                          "batched_step_p50": float(1e3 * np.percentile(lat_step, 50)),
+                          "batched_step_p99": float(1e3 * np.percentile(lat_step, 99))}}
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Serving loop: resident graphs receive update batches as a Poisson stream at several rates;
+    latency = arrival to completion.  Compared with the plain FIFO path (one thread applying
+    the same requests in arrival order)."""
+    import numpy as np
+    import torch  # noqa: F401
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    rng = np.random.default_rng(synth.BASE_SEED + 5)
+    streams = []
+    for g in range(args.graphs):
+        s, _ = synth.planted_mix_graph(g, seed_offset=5, nmin_exp=3.5, nmax_exp=args.mix_max_exp)
+        streams.append(s)
+    edges = [s.edges() for s in streams]
+    nreq = args.requests
+    reqs = []
+    for _ in range(nreq):
+        g = int(rng.integers(0, len(streams)))
+        size = synth.lognormal_int(rng, 1000.0, 1.5, 1, args.mix_max_batch)
+        size = min(size, max(1, streams[g].num_edges() // 4))
+        reqs.append((g, streams[g].batch(size)))
+    updates = sum(b.size for _, b in reqs)
+    # plain FIFO reference (also the saturation throughput)
+    plain = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+    t0 = time.perf_counter()
+    for g, b in reqs:
+        plain[g].apply_batch(b.ins, b.dels, b.chg)
+    t_plain = time.perf_counter() - t0
+    sat = nreq / t_plain
+    results = []
+    final_same = True
+    for frac in args.rates:
+        lam = frac * sat
+        served = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+        srv = ldl.Server(workers=args.workers, mem_budget_bytes=args.mem_budget)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, nreq))
+        t0 = time.perf_counter()
+        tickets = []
+        for (g, b), at in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(served[g], b.ins, b.dels, b.chg))
+        lat = []
+        for t in tickets:
+            rc, _, ms = srv.wait(t)
+            assert rc == 0
+            lat.append(ms)
+        t_all = time.perf_counter() - t0
+        srv.close()
+        final_same &= all(np.array_equal(a.partition(), b.partition()) and a.qnum() == b.qnum()
+                          for a, b in zip(plain, served))
+        results.append({"offered_x_plain_saturation": frac, "requests_per_s": nreq / t_all,
+                        "edges_per_s": updates / t_all, "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99))})
+        log(f"rate {frac:.2f}x: {results[-1]}")
+    best = max(results, key=lambda r: r["edges_per_s"])
+    out = {"metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
+           "value": best["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+           "ms_per_step": 1e3 / best["requests_per_s"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"serve-{len(streams)}-resident-graphs", "graphs": len(streams),
+                      "sum_n": sum(s.n for s in streams), "requests": nreq, "workers": args.workers,
+                      "batch": "lognormal median 1e3 sigma 1.5", "updates": updates},
+           "plain_fifo_edges_per_s": updates / t_plain, "served_vs_plain": best["edges_per_s"] / (updates / t_plain),
+           "identical_to_plain": bool(final_same), "sweep": results}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=10000)
+    ap.add_argument("--small-batch", type=int, default=1000)
+    ap.add_argument("--small-steps", type=int, default=20)
+    ap.add_argument("--cpu-batches", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve"], default="rmat")
+    ap.add_argument("--graphs", type=int, default=64)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--mix-max-exp", type=float, default=5.0)
+    ap.add_argument("--mix-max-batch", type=int, default=10000)
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0])
+    ap.add_argument("--mem-budget", type=int, default=16 << 30)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the batch update of one graph runs on one device", file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "mix":
+        return run_mix(args)
+    if args.workload == "serve":
+        return run_serve(args)
+
+    import numpy as np
+    import torch
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    torch.cuda.set_device(0)
+    cpu = {}
+    th = None
+    if not args.no_cpu_baseline:
+        th = threading.Thread(target=cpu_baseline_worker, args=(args.scale, args.batch, args.cpu_batches, cpu),
+                              daemon=True)
+        th.start()
+
+    t0 = time.perf_counter()
+    s = synth.rmat_undirected(scale=args.scale)
+    e = s.edges()
+    log(f"generated n={s.n} edges={len(e)} in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    g = ldl.Graph(s.n, e, profile=True)
+    create_s = time.perf_counter() - t0
+    log(f"create (static Leiden) {create_s:.2f}s Q={g.modularity():.6f}")
+
+    def to_dev(b):
+        return [torch.from_numpy(x.astype(np.int32)).cuda() if len(x) else None for x in (b.ins, b.dels, b.chg)]
+
+    big = [to_dev(s.batch(args.batch)) for _ in range(args.warmup + args.steps)]
+    small = [to_dev(s.batch(args.small_batch)) for _ in range(args.small_steps)]
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        g.apply_batch_device(*big[i])
+    torch.cuda.synchronize()
+
+    def timed(batches):
+        per, stats = [], []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for b in batches:
+            t = time.perf_counter()
+            stats.append(g.apply_batch_device(*b))
+            per.append(time.perf_counter() - t)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t_start, per, stats
+
+    T, per, stats = timed(big[args.warmup:])
+    log(f"timed {args.steps} batches of {args.batch}: {T:.3f}s")
+    Ts, per_s, _ = timed(small)
+    log(f"timed {args.small_steps} batches of {args.small_batch}: {Ts:.3f}s")
+
+    updates = sum(int(x.shape[0]) for b in big[args.warmup:] for x in b if x is not None)
+    value = updates / T
+    bin_ms = np.sum([st["bin_ms"] for st in stats], axis=0)
+    bin_bytes = np.sum([st["bin_bytes"] for st in stats], axis=0)
+    bin_launch = np.sum([st["bin_launches"] for st in stats], axis=0)
+    dom = int(np.argmax(bin_ms))
+    achieved = float(bin_bytes[dom] / (bin_ms[dom] * 1e-3) / 1e9) if bin_ms[dom] > 0 else 0.0
+    entries = sum(st["scanned_entries"] for st in stats)
+    bm_ms = sum(st["bm_ms"] for st in stats)
+    bm_bytes = sum(st["bm_bytes"] for st in stats)
+    small_updates = sum(int(x.shape[0]) for b in small for x in b if x is not None)
+
+    cpu_obj = None
+    if th is not None:
+        th.join()
+        o = cpu["oracle"]
+        n_cpu = 0
+        t0 = time.perf_counter()
+        for b in cpu["batches"]:
+            assert o.apply_batch(b.ins, b.dels, b.chg) == 0
+            n_cpu += b.size
+        tc = time.perf_counter() - t0
+        cpu_obj = {"value": n_cpu / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                   "sample": f"{len(cpu['batches'])} batch(es) of {args.batch} updates on the same scale-"
+                             f"{args.scale} R-MAT stream after an untimed static Leiden "
+                             f"({cpu['create_s']:.1f}s); single-threaded C++ oracle, {tc:.1f}s"}
+
+    out = {
+        "metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"rmat{args.scale}-undirected-batch{args.batch}", "n": s.n, "edges": int(len(e)),
+                   "rmat": [0.57, 0.19, 0.19, 0.05], "weights": "uniform 1..16", "batch": args.batch,
+                   "mix": "70/20/10 insert/delete/reweight", "gamma": 1, "N": 2, "L": 4, "M": 5,
+                   "alpha": 0.001, "beta": 0.01},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": ldl.candidate_kernel_name(dom), "launches": int(bin_launch[dom]),
+                     "avg_launch_us": float(1e3 * bin_ms[dom] / max(1, bin_launch[dom])),
+                     "bytes_per_launch": float(bin_bytes[dom] / max(1, bin_launch[dom]))},
+        "cpu_baseline": cpu_obj,
+        "latency_ms": {"p50": float(1e3 * np.percentile(per, 50)), "p99": float(1e3 * np.percentile(per, 99))},
+        "frontier_entries_per_s": entries / T,
+        "local_move_GBps_all_bins": (bm_bytes / (bm_ms * 1e-3) / 1e9) if bm_ms > 0 else 0.0,
+        "candidate_kernels": {ldl.candidate_kernel_name(k): {"ms": float(bin_ms[k]), "GBps": float(
+            bin_bytes[k] / (bin_ms[k] * 1e-3) / 1e9) if bin_ms[k] > 0 else 0.0, "launches": int(bin_launch[k])}
+            for k in range(20) if bin_launch[k]},
+        "small_batch": {"batch": args.small_batch, "edges_per_s": small_updates / Ts,
+                        "p50_ms": float(1e3 * np.percentile(per_s, 50)),
+                        "p99_ms": float(1e3 * np.percentile(per_s, 99))},
+        "create_s": create_s,
+        "modularity": g.modularity(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

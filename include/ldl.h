@@ -95,6 +95,15 @@ typedef struct ldl_batch_stats {
   double bm_ms;               /* summed local-move kernel time in ms (profile != 0)       */
   double bm_bytes;            /* algorithmic bytes of those kernels (profile != 0)        */
   double total_ms;            /* wall time of the call measured with HIP events           */
+  /* per candidate kernel k = 10*refine + 5*wide + bin, where bin is the degree bin of the
+   * scanned vertices (entries per vertex in (0,8], (8,32], (32,128], (128,2048], above),
+   * wide = 1 for the int64 weights of aggregate levels and refine = 1 for BestRef:
+   * launches, kernel time (HIP events around each launch, profile != 0), algorithmic bytes
+   * (profile != 0) and adjacency entries read */
+  uint64_t bin_launches[20];
+  double bin_ms[20];
+  double bin_bytes[20];
+  uint64_t bin_entries[20];
 } ldl_batch_stats;
 
 /* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */
@@ -159,6 +168,48 @@ int ldl_export_entries(const ldl_handle* h, int32_t r, uint32_t* rows, uint32_t*
 int ldl_set_trace(ldl_handle* h, int32_t on);
 uint64_t ldl_trace_len(const ldl_handle* h);
 int ldl_trace(const ldl_handle* h, int64_t* out);
+
+/*
+ * Multi-graph batched mode.  bs[i] is applied to hs[i]; entries that name the same handle are
+ * applied in index order, one at a time, and entries of different handles run concurrently on
+ * up to `workers` host threads, each handle on its own HIP stream (workers == 0: one per
+ * distinct handle, at most 64).  The result of every handle is identical to applying its
+ * batches alone with ldl_apply_batch.  Arrays are host memory owned by the caller.  status[i]
+ * (nullable) receives each entry's return code, stats[i] (nullable) its statistics; the call
+ * returns LDL_OK if every entry succeeded, else the first failing code in index order.
+ */
+typedef struct ldl_batch {
+  const ldl_edge* ins;
+  uint64_t n_ins;
+  const ldl_pair* del;
+  uint64_t n_del;
+  const ldl_edge* chg;
+  uint64_t n_chg;
+} ldl_batch;
+
+int ldl_apply_batches(ldl_handle* const* hs, const ldl_batch* bs, uint32_t count, uint32_t workers, int* status,
+                      ldl_batch_stats* stats);
+
+/*
+ * Serving loop over resident graphs.  A server owns `workers` host threads.  ldl_server_submit
+ * copies a batch for handle h into a request and returns its ticket; requests of one handle
+ * run in submission order, back to back on the worker that holds the handle; requests of
+ * different handles overlap on the device.  A request is admitted only while the estimated
+ * device-memory footprint of all running requests stays within `mem_budget_bytes` (a request
+ * larger than the budget runs alone).  ldl_server_wait blocks until the ticket completes and
+ * returns its code, statistics and latency (submission to completion, milliseconds).  A handle
+ * must not be used outside the server while it has queued requests.
+ */
+typedef struct ldl_server ldl_server;
+
+int ldl_server_create(uint32_t workers, uint64_t mem_budget_bytes, ldl_server** out);
+int ldl_server_submit(ldl_server* s, ldl_handle* h, const ldl_edge* ins, uint64_t n_ins, const ldl_pair* del,
+                      uint64_t n_del, const ldl_edge* chg, uint64_t n_chg, uint64_t* ticket);
+int ldl_server_wait(ldl_server* s, uint64_t ticket, int* status, ldl_batch_stats* stats, double* latency_ms);
+/* Block until every submitted request has completed. */
+int ldl_server_drain(ldl_server* s);
+/* Drain, stop the workers and free the server (handles stay valid). NULL is ignored. */
+void ldl_server_destroy(ldl_server* s);
 
 /* Human-readable name of an LDL_* code. */
 const char* ldl_strerror(int code);

@@ -37,17 +37,29 @@ class ldl_batch_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "updates", "levels_processed", "move_iters", "refine_iters", "scanned_vertices", "scanned_entries",
         "distinct_comms", "candidates", "accepted", "rollbacks", "refine_moves", "agg_tuples", "bm_launches")] + \
-        [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")]
+        [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")] + \
+        [("bin_launches", ctypes.c_uint64 * 20), ("bin_ms", ctypes.c_double * 20),
+         ("bin_bytes", ctypes.c_double * 20), ("bin_entries", ctypes.c_uint64 * 20)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k.startswith("bin_") else v
+        return d
 
 
 # every entry point declared in include/ldl.h
 ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply_batch_device", "ldl_get_partition",
                "ldl_modularity", "ldl_modularity_exact", "ldl_destroy", "ldl_export_scalars", "ldl_export_totals",
                "ldl_export_level", "ldl_level_nnz", "ldl_export_entries", "ldl_set_trace", "ldl_trace_len",
-               "ldl_trace", "ldl_strerror", "ldl_version")
+               "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
+               "ldl_server_drain", "ldl_server_destroy", "ldl_strerror", "ldl_version")
+
+
+class ldl_batch(ctypes.Structure):
+    _fields_ = [("ins", ctypes.c_void_p), ("n_ins", ctypes.c_uint64), ("del_", ctypes.c_void_p),
+                ("n_del", ctypes.c_uint64), ("chg", ctypes.c_void_p), ("n_chg", ctypes.c_uint64)]
 
 _lib = None
 
@@ -60,6 +72,11 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950); there is no fallback path")
+    # PyTorch provides the device memory and streams this library works with, so both must use
+    # one HIP runtime: importing torch first loads its runtime, and the library's libamdhip64
+    # dependency then resolves to that already-loaded runtime instead of a second copy.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
     P = ctypes.POINTER
@@ -98,6 +115,18 @@ def load_library():
     lib.ldl_strerror.restype = ctypes.c_char_p
     lib.ldl_version.argtypes = []
     lib.ldl_version.restype = ctypes.c_char_p
+    lib.ldl_apply_batches.argtypes = [vp, P(ldl_batch), u32, u32, vp, P(ldl_batch_stats)]
+    lib.ldl_apply_batches.restype = i32
+    lib.ldl_server_create.argtypes = [u32, u64, P(vp)]
+    lib.ldl_server_create.restype = i32
+    lib.ldl_server_submit.argtypes = [vp, vp, vp, u64, vp, u64, vp, u64, P(u64)]
+    lib.ldl_server_submit.restype = i32
+    lib.ldl_server_wait.argtypes = [vp, u64, P(ctypes.c_int), P(ldl_batch_stats), P(ctypes.c_double)]
+    lib.ldl_server_wait.restype = i32
+    lib.ldl_server_drain.argtypes = [vp]
+    lib.ldl_server_drain.restype = i32
+    lib.ldl_server_destroy.argtypes = [vp]
+    lib.ldl_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -256,6 +285,82 @@ class Graph:
         if k:
             self.lib.ldl_trace(self.h, out.ctypes.data)
         return out
+
+
+def apply_batches(graphs, batches, workers=0):
+    """Multi-graph batched mode: batches[i] = (ins, dels, chg) is applied to graphs[i]; entries of
+    one graph run in order, different graphs overlap.  Returns (status list, stats list)."""
+    lib = load_library()
+    k = len(graphs)
+    hs = (ctypes.c_void_p * k)(*[g.h for g in graphs])
+    keep = []
+    arr = (ldl_batch * k)()
+    for i, (ins, dels, chg) in enumerate(batches):
+        a, b, c = _u32(ins, 3), _u32(dels, 2), _u32(chg, 3)
+        keep += [a, b, c]
+        arr[i] = ldl_batch(a.ctypes.data, len(a), b.ctypes.data, len(b), c.ctypes.data, len(c))
+    status = np.zeros(k, dtype=np.int32)
+    stats = (ldl_batch_stats * k)()
+    lib.ldl_apply_batches(hs, arr, k, workers, status.ctypes.data, stats)
+    return status.tolist(), [st.as_dict() for st in stats]
+
+
+class Server:
+    """Serving loop over resident graphs (native worker threads, admission by footprint)."""
+
+    def __init__(self, workers=8, mem_budget_bytes=8 << 30):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self.lib.ldl_server_create(workers, mem_budget_bytes, ctypes.byref(h))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_server_create")
+        self.h = h.value
+
+    def submit(self, graph, ins=None, dels=None, chg=None) -> int:
+        a, b, c = _u32(ins, 3), _u32(dels, 2), _u32(chg, 3)
+        t = ctypes.c_uint64()
+        rc = self.lib.ldl_server_submit(self.h, graph.h, a.ctypes.data, len(a), b.ctypes.data, len(b), c.ctypes.data,
+                                        len(c), ctypes.byref(t))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_server_submit")
+        return t.value
+
+    def wait(self, ticket):
+        rc, st, ms = ctypes.c_int(), ldl_batch_stats(), ctypes.c_double()
+        r = self.lib.ldl_server_wait(self.h, ticket, ctypes.byref(rc), ctypes.byref(st), ctypes.byref(ms))
+        if r != LDL_OK:
+            raise LdlError(r, "ldl_server_wait")
+        return rc.value, st.as_dict(), ms.value
+
+    def drain(self):
+        self.lib.ldl_server_drain(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ldl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def candidate_kernel_name(k: int, directed: bool = False) -> str:
+    """rocprofv3 name of candidate kernel k = 10*refine + 5*wide + bin (see ldl_batch_stats)."""
+    refine, wide, b = k // 10, (k // 5) % 2, k % 5
+    wt = "long" if wide else "unsigned int"
+    d, r = ("true" if directed else "false"), ("true" if refine else "false")
+    if b == 0:
+        return f"k_best_group<{wt}, 8, {d}, {r}>"
+    if b == 1:
+        return f"k_best_group<{wt}, 32, {d}, {r}>"
+    if b == 2:
+        return f"k_best_hash<{wt}, 64, 256, {d}, {r}>"
+    if b == 3:
+        return f"k_best_hash<{wt}, 256, 4096, {d}, {r}>"
+    return f"k_hub_insert<{wt}, {d}, {r}>"
 
 
 def version() -> str:

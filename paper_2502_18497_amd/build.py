@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libldl.so")
-SOURCES = ["kernels_graph.hip", "kernels_move.hip", "prims.hip", "engine.hip"]
+SOURCES = ["kernels_graph.hip", "kernels_move.hip", "prims.hip", "engine.hip", "server.cpp"]
 ARCH = os.environ.get("LDL_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
@@ -19,7 +19,9 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-ta
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    flags = FLAGS if src.endswith(".hip") else ["-O3", "-std=c++17", "-fPIC", "-pthread", "-I",
+                                                 os.path.join(ROOT, "include"), "-I", CSRC]
+    cmd = ["hipcc", *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -32,7 +34,7 @@ def build(jobs: int = 4) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     subprocess.run(cmd, check=True, capture_output=True)
     os.replace(tmp, LIB)
     return LIB

@@ -63,14 +63,15 @@ static T* dalloc(uint64_t count) {
 struct Scal {
   uint32_t counts[64];
   uint32_t bins[8];
-  uint32_t ncand, nacc, nlive2, err, first_bad, overflow, hub_over, pad0;
+  uint32_t bin_start[8];
+  uint32_t ncand, nacc, nlive2, err, first_bad, overflow, hub_over, nseg;
   u64a pool_top[2 * 17];
   u64a hub_top;
   i64a dm, dein;
   u64a dskk_lo;
   i64a dskk_hi;
   u64a tcount, tneed, nruns, ecount;
-  u64a st_entries, st_distinct, st_vertices;
+  u64a st_entries[kNumBins], st_distinct[kNumBins], st_vertices[kNumBins], st_cands[kNumBins];
   u64a maxv;
 };
 
@@ -118,6 +119,7 @@ struct Engine {
   hipStream_t st = nullptr;
   bool own_stream = false;
   uint32_t n = 0;
+  int id_bits = 32;     // bits of a vertex id: keys row << 32 | col need 32 + id_bits bits
   bool broken = false;
 
   // exact scalars (host)
@@ -145,7 +147,17 @@ struct Engine {
   uint32_t *rank = nullptr, *liveA = nullptr, *liveB = nullptr, *acc = nullptr, *entry = nullptr;
   int64_t *tko = nullptr, *tki = nullptr;
   uint32_t* bins[kNumBins] = {};
+  uint32_t* binbuf = nullptr;
+  uint32_t *bhist = nullptr, *boffs = nullptr;
+  uint64_t *tcounts = nullptr, *toffs = nullptr;
   uint32_t* hub_over_alt = nullptr;
+  uint64_t *hsize = nullptr, *hoff = nullptr;
+  int64_t* hown = nullptr;
+  uint64_t part_cap = 0;
+  int64_t* phi = nullptr;
+  uint64_t* plo = nullptr;
+  uint32_t* pid = nullptr;
+  int* pvalid = nullptr;
   CandBuf cand{};
   uint64_t *skey0 = nullptr, *skey1 = nullptr;
   uint32_t *sidx0 = nullptr, *sidx1 = nullptr;
@@ -160,6 +172,10 @@ struct Engine {
   int64_t *edel0 = nullptr, *edel1 = nullptr;
   uint32_t *ex = nullptr, *ey = nullptr;
   uint8_t* insflag = nullptr;
+  uint64_t* seg_lo = nullptr;
+  uint64_t *seg_hi = nullptr, *items = nullptr, *item_off = nullptr;
+  int64_t* slotbuf = nullptr;
+  int64_t* rslot = nullptr;
   uint64_t ins_cap = 0;
   uint64_t tup_cap = 0;
   uint64_t *tk0 = nullptr, *tk1 = nullptr, *tk2 = nullptr;
@@ -175,7 +191,12 @@ struct Engine {
   std::vector<TraceRec> trace;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
   size_t ev_used = 0;
-  std::vector<double> bm_bytes_pending;
+  struct Pending {
+    int bin;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Pending> pending;
 
   // ------------------------------------------------------------------ memory helpers
   template <typename T>
@@ -232,6 +253,26 @@ struct Engine {
 
   i128 qnum() const { return (i128)gq * m * Ein - (i128)gp * SKK; }
 
+  // list of a marked set: ids with stamp == epoch, ascending, count into the set's counter
+  void select_set(int id) {
+    HSet& s = sets[id];
+    cub(prim_select_stamp(&cub_tmp, &cub_bytes, s.stamp, s.epoch, n, s.list, &ds->counts[s.ci], st));
+  }
+
+  // per-node tuple counts and their exclusive prefix (toffs); grows the tuple buffers
+  uint64_t tuple_offsets(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, const uint32_t* cstamp,
+                         uint32_t cep, int repair) {
+    if (k == 0) return 0;
+    launch_tuple_counts(list, k, out, in, directed, cstamp, cep, repair, tcounts, st);
+    hcheck(hipMemsetAsync(tcounts + k, 0, 8, st));
+    cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
+    uint64_t T = 0;
+    hcheck(hipMemcpyAsync(&T, toffs + k, 8, hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+    ensure_tuples(T + 16);
+    return T;
+  }
+
   // ------------------------------------------------------------------ setup
   void init(const ldl_config& c, uint32_t n_) {
     directed = c.directed != 0;
@@ -241,6 +282,8 @@ struct Engine {
     device = c.device;
     profile = c.profile;
     n = n_;
+    id_bits = 1;
+    while (id_bits < 32 && (1ull << id_bits) < (uint64_t)n) ++id_bits;
     hcheck(hipSetDevice(device));
     if (c.stream) {
       st = (hipStream_t)c.stream;
@@ -313,8 +356,18 @@ struct Engine {
     entry = alloc<uint32_t>(n);
     tko = alloc<int64_t>(n);
     tki = alloc<int64_t>(n);
-    for (int b = 0; b < kNumBins; ++b) bins[b] = alloc<uint32_t>(n);
+    for (int b = 0; b < kNumBins; ++b) bins[b] = nullptr;
+    binbuf = alloc<uint32_t>(n);
+    bhist = alloc<uint32_t>(kNumBins * kBinBlocks + 1);
+    boffs = alloc<uint32_t>(kNumBins * kBinBlocks + 1);
+    hcheck(hipMemsetAsync(bhist, 0, 4ull * (kNumBins * kBinBlocks + 1), st));
+    tcounts = alloc<uint64_t>((uint64_t)n + 1);
+    toffs = alloc<uint64_t>((uint64_t)n + 1);
+    hcheck(hipMemsetAsync(tcounts, 0, 8ull * ((uint64_t)n + 1), st));
     hub_over_alt = alloc<uint32_t>(n);
+    hsize = alloc<uint64_t>((uint64_t)n + 1);
+    hoff = alloc<uint64_t>((uint64_t)n + 1);
+    hown = alloc<int64_t>(n);
     cand.v = alloc<uint32_t>(n);
     cand.a = alloc<uint32_t>(n);
     cand.b = alloc<uint32_t>(n);
@@ -353,7 +406,7 @@ struct Engine {
   void ensure_records(uint64_t k) {
     if (k <= rec_cap) return;
     uint64_t c = std::max<uint64_t>(k, rec_cap * 2);
-    regrow(rkey0, c); regrow(rkey1, c); regrow(ridx0, c); regrow(ridx1, c); regrow(rdelta, c);
+    regrow(rkey0, c); regrow(rkey1, c); regrow(ridx0, c); regrow(ridx1, c); regrow(rdelta, c); regrow(rslot, c);
     rec_cap = c;
   }
   void ensure_entries(uint64_t k) {
@@ -366,6 +419,11 @@ struct Engine {
     if (k <= ins_cap) return;
     uint64_t c = std::max<uint64_t>(k, ins_cap * 2);
     regrow(insflag, c);
+    regrow(seg_lo, c);
+    regrow(seg_hi, c);
+    regrow(items, c + 1);
+    regrow(item_off, c + 1);
+    regrow(slotbuf, c);
     ins_cap = c;
   }
   void ensure_tuples(uint64_t k) {
@@ -415,13 +473,18 @@ struct Engine {
     release(newoff);
   }
 
-  // Apply sorted records (key = row << 32 | col, distinct keys) to one orientation.
-  void csr_apply(Csr& c, const uint64_t* keys, const int64_t* delta, uint64_t k) {
+  // Apply sorted records (key = row << 32 | col, distinct keys) to one orientation; when
+  // deg_arr is given, each row's delta sum is added to it.
+  void csr_apply(Csr& c, const uint64_t* keys, const int64_t* delta, uint64_t k, int64_t* deg_arr) {
     if (k == 0) return;
     if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
     ensure_insflag(k);
+    zero(&ds->nseg);
+    launch_segments(keys, k, seg_lo, &ds->nseg, st);
+    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, slotbuf, &cub_tmp, &cub_bytes, st);
     begin(S_DIRTY);
-    launch_csr_find(c.ref, keys, delta, k, insflag, rowdel, rowins, ref(S_DIRTY), st);
+    launch_seg_apply(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, rowdel, rowins, deg_arr,
+                     sets[S_DIRTY].list, &ds->counts[sets[S_DIRTY].ci], st);
     sync_read();
     const uint32_t nd = count(S_DIRTY);
     if (nd == 0) return;
@@ -445,22 +508,21 @@ struct Engine {
   void apply_records(int s, const uint64_t* keys, const int64_t* vals, uint64_t k, bool degrees) {
     if (k == 0) return;
     Level& V = lv[s];
-    csr_apply(V.out, keys, vals, k);
+    csr_apply(V.out, keys, vals, k, degrees ? V.kout : nullptr);
     if (directed) {
       // scratch tk1/tk2/tv2 must not alias the caller's keys/vals
       if (k > tup_cap || keys == tk1 || keys == tk2 || vals == tv2) throw DeviceError{hipErrorInvalidValue};
       launch_transpose_keys(keys, tk2, k, st);
-      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, vals, tv2, k, 0, 64, st));
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, vals, tv2, k, 0, 32 + id_bits, st));
       // tk1 and tv2 now hold the transposed records in (col, row) order
-      csr_apply(V.in, tk1, tv2, k);
+      csr_apply(V.in, tk1, tv2, k, degrees ? V.kin : nullptr);
     }
-    if (degrees) launch_csr_degrees(V.kout, directed ? V.kin : nullptr, keys, vals, k, st);
   }
 
   // sort (keys, vals) of length k and reduce equal keys; result in (tk2, tv2) with *runs
   uint64_t sort_reduce(uint64_t* keys, int64_t* vals, uint64_t k, uint64_t* okeys, int64_t* ovals) {
     if (k == 0) return 0;
-    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, keys, tk1, vals, tv1, k, 0, 64, st));
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, keys, tk1, vals, tv1, k, 0, 32 + id_bits, st));
     cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, okeys, tv1, ovals, &ds->nruns, k, st));
     sync_read();
     return hs->nruns;
@@ -479,13 +541,18 @@ struct Engine {
     hcheck(hipMemsetAsync(&ds->first_bad, 0xFF, 4, st));
     zero(&ds->dm);
     launch_ingest_records(dins, ni, ddel, nd, dchg, nc, n, directed, rkey0, ridx0, &ds->err, st);
-    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, rkey0, rkey1, ridx0, ridx1, K, 0, 64, st));
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, rkey0, rkey1, ridx0, ridx1, K, 0, 32 + id_bits, st));
     sync_read();
     if (hs->err & 1u) return LDL_EINVAL;
     Level& V0 = lv[0];
     if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
-    launch_ingest_check(V0.out.ref, rkey1, ridx1, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
-                        &ds->first_bad, &ds->dm, st);
+    ensure_insflag(K);
+    zero(&ds->nseg);
+    launch_segments(rkey1, K, seg_lo, &ds->nseg, st);
+    launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, rslot, &cub_tmp, &cub_bytes,
+                      st);
+    launch_ingest_validate(V0.out.ref, rkey1, ridx1, rslot, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
+                           &ds->first_bad, &ds->dm, st);
     sync_read();
     if (hs->err & 2u) return LDL_EDUP;
     if (hs->err & 12u) return hs->first_bad < ni ? LDL_EOVERFLOW : LDL_ENOEDGE;
@@ -497,7 +564,7 @@ struct Engine {
     sync_read();
     const uint64_t E = hs->ecount;
     if (E == 0) return LDL_OK;
-    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 64, st));
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 32 + id_bits, st));
     stats.updates = K;
     // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
     begin(S_TOUCH);
@@ -563,61 +630,116 @@ struct Engine {
     return ev_pool[ev_used++];
   }
 
-  // BestMove_r / BestRef_r over list[0..cnt): candidates in `cand`, returns their number
+  // BestMove_r / BestRef_r over list[0..cnt): candidates in `cand`, returns their number.
+  // With profiling, every kernel launch is bracketed by HIP events on its stream and its
+  // algorithmic bytes are computed from the counters the kernel itself accumulates.
   uint32_t best(int r, const uint32_t* list, uint32_t cnt, int refine) {
     if (cnt == 0) return 0;
     MoveView mv = view(r, refine);
     zero(&ds->ncand);
-    hcheck(hipMemsetAsync(ds->bins, 0, sizeof(ds->bins), st));
-    zero(&ds->st_entries);
-    zero(&ds->st_distinct);
-    zero(&ds->st_vertices);
-    launch_bin(mv, list, cnt, refine, bins, ds->bins, st);
+    hcheck(hipMemsetAsync(ds->st_entries, 0, sizeof(ds->st_entries) * 4, st));
+    launch_bin_count(mv, list, cnt, refine, bhist, st);
+    cub(prim_exclusive_sum_u32(&cub_tmp, &cub_bytes, bhist, boffs, kNumBins * kBinBlocks + 1, st));
+    launch_bin_fill(mv, list, cnt, refine, boffs, binbuf, ds->bin_start, ds->bins, st);
     sync_read();
     uint32_t bc[kNumBins];
-    for (int b = 0; b < kNumBins; ++b) bc[b] = hs->bins[b];
-    MoveStats ms{&ds->st_entries, &ds->st_distinct, &ds->st_vertices};
-    std::pair<hipEvent_t, hipEvent_t> ev{};
-    if (profile) {
-      ev = next_events();
-      hcheck(hipEventRecord(ev.first, st));
+    for (int b = 0; b < kNumBins; ++b) {
+      bc[b] = hs->bins[b];
+      bins[b] = binbuf + hs->bin_start[b];
     }
-    for (int b = 0; b < kNumBins - 1; ++b) launch_best(mv, b, bins[b], bc[b], refine, cand, hub, ms, st);
-    uint32_t* hl = bins[kNumBins - 1];
-    uint32_t hcnt = bc[kNumBins - 1];
-    uint32_t* other = hub_over_alt;
-    while (hcnt) {
-      zero(&ds->hub_top);
-      zero(&ds->hub_over);
-      HubPool hp = hub;
-      hp.over = other;
-      launch_best(mv, kNumBins - 1, hl, hcnt, refine, cand, hp, ms, st);
-      sync_read();
-      const uint32_t left = hs->hub_over;
-      if (left >= hcnt) throw DeviceError{hipErrorUnknown};
-      std::swap(hl, other);
-      hcnt = left;
+    const int wide = lv[r].out.ref.wide;
+    const int cat0 = 10 * refine + 5 * wide;
+    // algorithmic bytes: per vertex its list id, offsets and degrees, label, degrees and the
+    // totals of its own community; per entry neighbour id, weight and neighbour label (plus
+    // the parent in refinement); per distinct community its totals; per candidate 28 bytes
+    const double wb = wide ? 8.0 : 4.0;
+    const double dirf = directed ? 2.0 : 1.0;
+    const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 0 : 8 * dirf);
+    const double per_e = 4 + wb + 4 + (refine ? 4 : 0);
+    const double per_d = 8 * dirf;
+    auto bytes_of = [&](int b) {
+      return per_v * hs->st_vertices[b] + per_e * hs->st_entries[b] + per_d * hs->st_distinct[b] +
+             28.0 * hs->st_cands[b];
+    };
+    size_t first_pending = pending.size();
+    for (int b = 0; b < kNumBins - 1; ++b) {
+      if (!bc[b]) continue;
+      MoveStats ms{&ds->st_entries[b], &ds->st_distinct[b], &ds->st_vertices[b], &ds->st_cands[b]};
+      std::pair<hipEvent_t, hipEvent_t> ev{};
+      if (profile) {
+        ev = next_events();
+        hcheck(hipEventRecord(ev.first, st));
+      }
+      launch_best(mv, b, bins[b], bc[b], refine, cand, hub, ms, st);
+      if (profile) {
+        hcheck(hipEventRecord(ev.second, st));
+        pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
+      }
     }
-    if (profile) hcheck(hipEventRecord(ev.second, st));
     sync_read();
-    stats.scanned_vertices += hs->st_vertices;
-    stats.scanned_entries += hs->st_entries;
-    stats.distinct_comms += hs->st_distinct;
-    stats.candidates += hs->ncand;
-    if (profile) {
-      // algorithmic bytes: per vertex list id, offsets/degrees, label, degrees, own totals;
-      // per entry neighbour id, weight, neighbour label (+ parent in refinement); per
-      // distinct community its totals; per candidate the 28-byte record
-      const double wb = lv[r].out.ref.wide ? 8.0 : 4.0;
-      const double dirf = directed ? 2.0 : 1.0;
-      const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 8 : 8 * dirf);
-      const double per_e = 4 + wb + 4 + (refine ? 4 : 0);
-      const double per_d = 8 * dirf;
-      const double bytes = per_v * hs->st_vertices + per_e * hs->st_entries + per_d * hs->st_distinct +
-                           28.0 * hs->ncand;
-      bm_bytes_pending.push_back(bytes);
-      stats.bm_launches += 1;
+    for (int b = 0; b < kNumBins - 1; ++b) {
+      if (!bc[b]) continue;
+      stats.scanned_vertices += hs->st_vertices[b];
+      stats.scanned_entries += hs->st_entries[b];
+      stats.distinct_comms += hs->st_distinct[b];
+      stats.bin_entries[cat0 + b] += hs->st_entries[b];
+      if (profile)
+        for (size_t i = first_pending; i < pending.size(); ++i)
+          if (pending[i].bin == cat0 + b) pending[i].bytes = bytes_of(b);
     }
+    // hubs: tables of pow2 >= 2T slots, processed in groups whose tables fit the pool
+    const int hb = kNumBins - 1;
+    const uint32_t h = bc[hb];
+    if (h) {
+      const uint32_t* hl = bins[hb];
+      launch_hub_prep(mv, hl, h, hsize, &ds->maxv, st);
+      cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, hsize, hoff, (uint64_t)h + 1, st));
+      std::vector<uint64_t> ho((size_t)h + 1);
+      hcheck(hipMemcpyAsync(ho.data(), hoff, 8ull * ((uint64_t)h + 1), hipMemcpyDeviceToHost, st));
+      hcheck(hipMemsetAsync(&ds->st_entries[hb], 0, 8, st));
+      hcheck(hipMemsetAsync(&ds->st_distinct[hb], 0, 8, st));
+      hcheck(hipMemsetAsync(&ds->st_vertices[hb], 0, 8, st));
+      hcheck(hipMemsetAsync(&ds->st_cands[hb], 0, 8, st));
+      hcheck(hipStreamSynchronize(st));
+      MoveStats ms{&ds->st_entries[hb], &ds->st_distinct[hb], &ds->st_vertices[hb], &ds->st_cands[hb]};
+      const size_t hub_first = pending.size();
+      uint32_t i0 = 0;
+      while (i0 < h) {
+        uint32_t i1 = i0 + 1;
+        uint64_t maxsize = ho[i0 + 1] - ho[i0];
+        if (maxsize > hub.cap) throw DeviceError{hipErrorUnknown};
+        while (i1 < h && ho[i1 + 1] - ho[i0] <= hub.cap) {
+          maxsize = std::max<uint64_t>(maxsize, ho[i1 + 1] - ho[i1]);
+          ++i1;
+        }
+        const uint32_t ng = i1 - i0;
+        const uint32_t max_parts = (uint32_t)((maxsize + kHubScanSlots - 1) / kHubScanSlots);
+        const uint64_t need = (uint64_t)ng * max_parts;
+        if (need > part_cap) {
+          const uint64_t c = std::max<uint64_t>(need, 2 * part_cap);
+          regrow(phi, c); regrow(plo, c); regrow(pid, c); regrow(pvalid, c);
+          part_cap = c;
+        }
+        hcheck(hipMemsetAsync(hown, 0, 8ull * ng, st));
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (profile) ev = next_events();
+        launch_hub_group(mv, hl, i0, ng, hoff, ho[i0], ho[i1] - ho[i0], maxsize / 2, refine, hub, hown, max_parts,
+                         phi, plo, pid, pvalid, cand, ms, st, profile ? ev.first : nullptr,
+                         profile ? ev.second : nullptr);
+        if (profile) pending.push_back(Pending{cat0 + hb, ev.first, ev.second, 0.0});
+        i0 = i1;
+      }
+      sync_read();
+      stats.scanned_vertices += hs->st_vertices[hb];
+      stats.scanned_entries += hs->st_entries[hb];
+      stats.distinct_comms += hs->st_distinct[hb];
+      stats.bin_entries[cat0 + hb] += hs->st_entries[hb];
+      // bytes of the insert kernels: per vertex its list id, offsets/degrees and label; per entry
+      if (profile && pending.size() > hub_first)
+        pending[hub_first].bytes = (4 + 12 * dirf + 4) * hs->st_vertices[hb] + per_e * hs->st_entries[hb];
+    }
+    sync_read();
+    stats.candidates += hs->ncand;
     return hs->ncand;
   }
 
@@ -627,7 +749,7 @@ struct Engine {
     // order by (gain descending, vertex ascending) with stable radix passes
     launch_iota(sidx0, K, st);
     launch_gather_u32_as_u64(cand.v, nullptr, K, skey0, st);
-    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, 32, st));
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, id_bits, st));
     launch_gather_u64(cand.glo, sidx1, K, skey0, 1, st);
     cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx1, sidx0, K, 0, 64, st));
     zero(&ds->maxv);
@@ -706,7 +828,9 @@ struct Engine {
     begin(S_COMM);
     launch_set_add_mapped(ref(S_COMM), entry, E0, V.lab, V.alive, st);
     begin(S_U);
-    launch_members(ref(S_U), n, V.alive, V.lab, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
+    launch_mark_members(sets[S_U].stamp, sets[S_U].epoch, n, V.alive, V.lab, sets[S_COMM].stamp, sets[S_COMM].epoch,
+                        st);
+    select_set(S_U);
     const i128 Q0 = qnum();
     begin(S_MOVED);
     CsrRef in = directed ? V.in.ref : V.out.ref;
@@ -715,7 +839,8 @@ struct Engine {
       sync_read();
       const uint32_t nU = count(S_U);
       begin(S_S);
-      launch_neighbours(ref(S_S), sets[S_U].list, nU, V.out.ref, in, directed, st);
+      launch_mark_neighbours(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, nU, V.out.ref, in, directed, st);
+      select_set(S_S);
       sync_read();
       const uint32_t nS = count(S_S);
       const uint32_t K = best(r, sets[S_S].list, nS, 0);
@@ -738,8 +863,10 @@ struct Engine {
       if (na) {
         begin(S_COMM);
         launch_mark_acc_comms(acc, na, cand, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
-        launch_members(ref(S_U2), n, V.alive, V.lab, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
-        launch_neighbours_acc(ref(S_U2), acc, na, cand, V.out.ref, in, directed, st);
+        launch_mark_members(sets[S_U2].stamp, sets[S_U2].epoch, n, V.alive, V.lab, sets[S_COMM].stamp,
+                            sets[S_COMM].epoch, st);
+        launch_mark_neighbours_acc(sets[S_U2].stamp, sets[S_U2].epoch, acc, na, cand, V.out.ref, in, directed, st);
+        select_set(S_U2);
       }
       std::swap(sets[S_U], sets[S_U2]);
       if ((i128)ad * dq < (i128)an * Q0) break;            // Alg. 1 l.13
@@ -762,7 +889,9 @@ struct Engine {
     launch_set_add_mapped(ref(S_REFM), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(S_REFM), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
     begin(S_RSET);
-    launch_members(ref(S_RSET), n, V.alive, V.par, sets[S_REFM].stamp, sets[S_REFM].epoch, st);
+    launch_mark_members(sets[S_RSET].stamp, sets[S_RSET].epoch, n, V.alive, V.par, sets[S_REFM].stamp,
+                        sets[S_REFM].epoch, st);
+    select_set(S_RSET);
     sync_read();
     const uint32_t nR0 = count(S_RSET);
     launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st);
@@ -796,18 +925,15 @@ struct Engine {
     sync_read();
     const uint32_t nRset = count(S_RSET), nMoved = count(S_MOVED);
     begin(S_C);
-    launch_changed(sets[S_RSET].list, nRset, V.par, oldpar, ref(S_C), st);
+    launch_mark_changed(sets[S_C].stamp, sets[S_C].epoch, sets[S_RSET].list, nRset, V.par, oldpar, st);
+    select_set(S_C);
     sync_read();
     const uint32_t nC = count(S_C);
     CsrRef in = directed ? V.in.ref : V.out.ref;
-    zero(&ds->tneed);
-    launch_tuple_count(sets[S_C].list, nC, V.out.ref, in, directed, &ds->tneed, st);
-    sync_read();
-    ensure_tuples(hs->tneed + 16);
-    zero(&ds->tcount);
     const int Dn = S_D0 + r + 1;
-    launch_tuples(sets[S_C].list, nC, V.out.ref, in, directed, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, 1,
-                  tk0, tv0, &ds->tcount, tup_cap, ref(Dn), st);
+    const uint64_t T = tuple_offsets(sets[S_C].list, nC, V.out.ref, in, sets[S_C].stamp, sets[S_C].epoch, 1);
+    launch_tuples_at(sets[S_C].list, nC, V.out.ref, in, directed, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, 1,
+                     toffs, tk0, tv0, ref(Dn), st);
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
@@ -839,9 +965,6 @@ struct Engine {
       std::swap(rev, rev2);
     }
     // subtract-add tuples: reduce, apply at r+1 (degrees already exact), cascade upwards
-    sync_read();
-    const uint64_t T = hs->tcount;
-    if (T > tup_cap) throw DeviceError{hipErrorUnknown};
     stats.agg_tuples += T;
     uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
     if (R == 0) return;
@@ -853,7 +976,7 @@ struct Engine {
       SetRef none{};
       launch_cascade_map(tx, ty, tv0, R, lv[s - 1].par, tk2, tv2, none, st);
       // tk2/tv2 hold the mapped records; reduce them into tk0/tv0
-      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 64, st));
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 32 + id_bits, st));
       cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, tk0, tv1, tv0, &ds->nruns, R, st));
       sync_read();
       R = hs->nruns;
@@ -872,17 +995,10 @@ struct Engine {
     sync_read();
     const uint32_t na = count(S_TMP);
     CsrRef in = directed ? V.in.ref : V.out.ref;
-    zero(&ds->tneed);
-    launch_tuple_count(sets[S_TMP].list, na, V.out.ref, in, directed, &ds->tneed, st);
-    sync_read();
-    ensure_tuples(hs->tneed / 2 + 16);
-    zero(&ds->tcount);
+    const uint64_t T = tuple_offsets(sets[S_TMP].list, na, V.out.ref, in, nullptr, 0, 0);
     SetRef none{};
-    launch_tuples(sets[S_TMP].list, na, V.out.ref, in, directed, V.par, nullptr, nullptr, 0, 0, tk0, tv0,
-                  &ds->tcount, tup_cap, none, st);
-    sync_read();
-    const uint64_t T = hs->tcount;
-    if (T > tup_cap) throw DeviceError{hipErrorUnknown};
+    launch_tuples_at(sets[S_TMP].list, na, V.out.ref, in, directed, V.par, nullptr, nullptr, 0, 0, toffs, tk0, tv0,
+                     none, st);
     const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
     hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
@@ -925,14 +1041,18 @@ struct Engine {
   void finish_profile() {
     if (!profile) return;
     hcheck(hipStreamSynchronize(st));
-    for (size_t i = 0; i < ev_used; ++i) {
+    for (const Pending& p : pending) {
       float ms = 0;
-      hcheck(hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second));
+      hcheck(hipEventElapsedTime(&ms, p.a, p.b));
+      stats.bin_ms[p.bin] += ms;
+      stats.bin_bytes[p.bin] += p.bytes;
+      stats.bin_launches[p.bin] += 1;
       stats.bm_ms += ms;
+      stats.bm_bytes += p.bytes;
+      stats.bm_launches += 1;
     }
-    for (double b : bm_bytes_pending) stats.bm_bytes += b;
     ev_used = 0;
-    bm_bytes_pending.clear();
+    pending.clear();
   }
 
   // ------------------------------------------------------------------ export

@@ -139,6 +139,304 @@ __global__ void k_csr_find(CsrRef c, const uint64_t* keys, const int64_t* delta,
   }
 }
 
+// Row segments of sorted record keys: one entry (first record index) per distinct row.
+__global__ void k_segments(const uint64_t* keys, uint64_t k, uint64_t* seg_lo, uint32_t* nseg) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const bool head = i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32);
+    const uint32_t at = wave_reserve(nseg, head);
+    if (head) seg_lo[at] = i;
+  }
+}
+
+__device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key);
+
+// Workgroup per row segment: the segment's records (up to 2048 at a time) go into an LDS
+// hash table keyed by column, then the row is streamed once and every entry probes the
+// table, so the cost is O(degree + records) per row.
+// MODE 0: write the slot (or -1) of every record.  MODE 1: apply the deltas in place
+// (a zero result leaves a w = 0 tombstone), flag insertions, count per-row deletions and
+// insertions and collect the rows that change shape in `dirty`.
+constexpr int kSegChunk = 2048;
+template <int MODE>
+__global__ __launch_bounds__(256) void k_seg_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k,
+                                                  const uint64_t* seg_lo, const uint32_t* nseg_ptr, int64_t* slot_out,
+                                                  uint8_t* insflag, uint32_t* rowdel, uint32_t* rowins,
+                                                  SetRef dirty) {
+  __shared__ uint32_t tkey[2 * kSegChunk];
+  __shared__ uint32_t tval[2 * kSegChunk];
+  __shared__ int64_t sslot[kSegChunk];
+  __shared__ uint64_t s_hi;
+  __shared__ uint32_t s_cnt[2];
+  const uint32_t nseg = *nseg_ptr;
+  for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
+    const uint64_t lo = seg_lo[seg];
+    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    if (threadIdx.x == 0) {
+      s_hi = lower_bound_u64(keys, k, ((uint64_t)row + 1) << 32);
+      s_cnt[0] = 0;
+      s_cnt[1] = 0;
+    }
+    __syncthreads();
+    const uint64_t hi = s_hi;
+    const uint64_t off = c.off[row];
+    const uint32_t deg = c.deg[row];
+    uint32_t ndel = 0, nins = 0;
+    for (uint64_t clo = lo; clo < hi; clo += kSegChunk) {
+      const uint32_t kk = (uint32_t)((hi - clo) < (uint64_t)kSegChunk ? (hi - clo) : (uint64_t)kSegChunk);
+      uint32_t size = 64;
+      while (size < 2 * kk) size <<= 1;
+      const uint32_t mask = size - 1;
+      for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
+      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) sslot[i] = -1;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
+        const uint32_t col = (uint32_t)keys[clo + i];
+        uint32_t h = hash32(col) & mask;
+        for (;;) {
+          const uint32_t prev = atomicCAS(&tkey[h], kEmpty, col);
+          if (prev == kEmpty) {
+            tval[h] = i;
+            break;
+          }
+          h = (h + 1) & mask;
+        }
+      }
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < deg; j += blockDim.x) {
+        const uint32_t x = c.nbr[off + j];
+        uint32_t h = hash32(x) & mask;
+        for (;;) {
+          const uint32_t kx = tkey[h];
+          if (kx == kEmpty) break;
+          if (kx == x) {
+            sslot[tval[h]] = (int64_t)(off + j);
+            break;
+          }
+          h = (h + 1) & mask;
+        }
+      }
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
+        const int64_t sl = sslot[i];
+        if (MODE == 0) {
+          slot_out[clo + i] = sl;
+        } else {
+          const int64_t d = delta[clo + i];
+          if (d == 0) {
+            insflag[clo + i] = 0;
+          } else if (sl >= 0) {
+            const int64_t nw = wget(c, (uint64_t)sl) + d;
+            wset(c, (uint64_t)sl, nw);
+            insflag[clo + i] = 0;
+            if (nw == 0) ++ndel;
+          } else {
+            insflag[clo + i] = 1;
+            ++nins;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (MODE == 1) {
+      if (ndel) atomicAdd(&s_cnt[0], ndel);
+      if (nins) atomicAdd(&s_cnt[1], nins);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        rowdel[row] = s_cnt[0];
+        rowins[row] = s_cnt[1];
+        if (s_cnt[0] + s_cnt[1]) dirty.list[atomicAdd(dirty.count, 1u)] = row;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- row-segment lookup split into (segment, record chunk, row slice) work items, so a
+// huge row is streamed by many workgroups and a row with many records by several tables.
+constexpr uint32_t kSlice = 16384;
+
+__global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo,
+                            const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items) {
+  const uint32_t nseg = *nseg_ptr;
+  for (uint64_t s = gtid(); s <= k; s += gstride()) {
+    if (s >= nseg) {
+      items[s] = 0;
+      continue;
+    }
+    const uint64_t lo = seg_lo[s];
+    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint64_t hi = lower_bound_u64(keys, k, ((uint64_t)row + 1) << 32);
+    seg_hi[s] = hi;
+    const uint64_t deg = c.deg[row];
+    const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
+    const uint64_t nrc = (hi - lo + kSegChunk - 1) / kSegChunk;
+    items[s] = nsl * nrc;
+  }
+}
+
+__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t n, uint64_t key) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// workgroup per work item: LDS table of the item's record chunk, stream the item's row slice,
+// write the slot of every record found (each record matches at most one entry)
+__global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k,
+                                                    const uint64_t* seg_lo, const uint64_t* seg_hi,
+                                                    const uint32_t* nseg_ptr, const uint64_t* item_off,
+                                                    int64_t* slot_out) {
+  __shared__ uint32_t tkey[2 * kSegChunk];
+  __shared__ uint32_t tval[2 * kSegChunk];
+  const uint32_t nseg = *nseg_ptr;
+  const uint64_t total = item_off[nseg];
+  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t sg = upper_bound_u64(item_off, nseg + 1, it) - 1;
+    const uint64_t sub = it - item_off[sg];
+    const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint64_t deg = c.deg[row];
+    const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
+    const uint64_t rc = sub / nsl, sl = sub % nsl;
+    const uint64_t clo = lo + rc * kSegChunk;
+    const uint32_t kk = (uint32_t)((hi - clo) < (uint64_t)kSegChunk ? (hi - clo) : (uint64_t)kSegChunk);
+    uint32_t size = 64;
+    while (size < 2 * kk) size <<= 1;
+    const uint32_t mask = size - 1;
+    for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
+      const uint32_t col = (uint32_t)keys[clo + i];
+      uint32_t h = hash32(col) & mask;
+      for (;;) {
+        const uint32_t prev = atomicCAS(&tkey[h], kEmpty, col);
+        if (prev == kEmpty) {
+          tval[h] = i;
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+    }
+    __syncthreads();
+    const uint64_t off = c.off[row];
+    const uint64_t e0 = sl * kSlice;
+    const uint64_t e1 = e0 + kSlice < deg ? e0 + kSlice : deg;
+    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
+      const uint32_t x = c.nbr[off + j];
+      uint32_t h = hash32(x) & mask;
+      for (;;) {
+        const uint32_t kx = tkey[h];
+        if (kx == kEmpty) break;
+        if (kx == x) {
+          slot_out[clo + tval[h]] = (int64_t)(off + j);
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// workgroup per segment: apply the row's deltas at the looked-up slots (a zero result leaves a
+// w = 0 tombstone), flag insertions, count deletions / insertions, add the row's delta sum to
+// its degree (when deg != null) and collect rows that change shape in `dirty`
+__global__ __launch_bounds__(256) void k_seg_apply(CsrRef c, const uint64_t* keys, const int64_t* delta,
+                                                   const uint64_t* seg_lo, const uint64_t* seg_hi,
+                                                   const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* insflag,
+                                                   uint32_t* rowdel, uint32_t* rowins, int64_t* deg_arr,
+                                                   uint32_t* dirty_list, uint32_t* dirty_count) {
+  __shared__ int64_t red[3 * 4];
+  const uint32_t nseg = *nseg_ptr;
+  for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    int64_t ndel = 0, nins = 0, dsum = 0;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const int64_t d = delta[i];
+      const int64_t sl = slot[i];
+      dsum += d;
+      if (d == 0) {
+        insflag[i] = 0;
+      } else if (sl >= 0) {
+        const int64_t nw = wget(c, (uint64_t)sl) + d;
+        wset(c, (uint64_t)sl, nw);
+        insflag[i] = 0;
+        if (nw == 0) ++ndel;
+      } else {
+        insflag[i] = 1;
+        ++nins;
+      }
+    }
+    ndel = wave_sum_i64(ndel);
+    nins = wave_sum_i64(nins);
+    dsum = wave_sum_i64(dsum);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & 63) == 0) {
+      red[3 * w] = ndel;
+      red[3 * w + 1] = nins;
+      red[3 * w + 2] = dsum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t a = 0, b = 0, d = 0;
+      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+        a += red[3 * i];
+        b += red[3 * i + 1];
+        d += red[3 * i + 2];
+      }
+      rowdel[row] = (uint32_t)a;
+      rowins[row] = (uint32_t)b;
+      if (deg_arr) deg_arr[row] += d;
+      if (a + b) dirty_list[atomicAdd(dirty_count, 1u)] = row;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_i64_dev(int64_t* p, int64_t v, uint64_t n) {
+  for (uint64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+// Per sorted ingest record: duplicate check, validation and delta from the looked-up slot.
+__global__ void k_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot,
+                                  uint64_t k, const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd,
+                                  const uint32_t* chg, int directed, int64_t* delta, uint32_t* err,
+                                  uint32_t* first_bad, i64a* dm) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint64_t key = keys[i];
+    if (i > 0 && keys[i - 1] == key) atomicOr(err, 2u);
+    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
+    const int64_t sl = slot[i];
+    const uint32_t src = idx[i];
+    const int64_t old = sl >= 0 ? (int64_t)((const uint32_t*)out0.w)[sl] : 0;
+    int64_t d = 0;
+    bool bad = false;
+    if (src < ni) {
+      const int64_t w = ins[3 * (uint64_t)src + 2];
+      if (old + w > 0xFFFFFFFFll) { bad = true; atomicOr(err, 8u); }
+      d = w;
+    } else if (src < ni + nd) {
+      if (sl < 0) { bad = true; atomicOr(err, 4u); }
+      d = -old;
+    } else {
+      const int64_t w = chg[3 * ((uint64_t)src - ni - nd) + 2];
+      if (sl < 0) { bad = true; atomicOr(err, 4u); }
+      d = w - old;
+    }
+    if (bad) {
+      atomicMin(first_bad, src);
+      d = 0;
+    }
+    delta[i] = d;
+    if (d != 0) atomicAdd((u64a*)dm, (u64a)((!directed && u != v) ? 2 * d : d));
+  }
+}
+
 __global__ void k_csr_plan(CsrRef c, const uint32_t* dirty, uint32_t nd, const uint32_t* rowdel,
                            const uint32_t* rowins, uint64_t* plan_off, uint32_t* plan_cap, u64a* pool_top,
                            uint64_t pool_cap, uint32_t* overflow) {
@@ -386,8 +684,9 @@ __global__ void k_ingest_mark(const uint64_t* ekeys, uint64_t k, const uint32_t*
     const uint32_t cs[2] = {lab0[x], lab0[y]};
     for (int t = 0; t < 2; ++t) {
       const uint32_t c = cs[t];
-      if (set_claim(touched.stamp, touched.epoch, c)) {
-        const uint32_t at = atomicAdd(touched.count, 1u);
+      const bool claimed = set_claim(touched.stamp, touched.epoch, c);
+      const uint32_t at = wave_reserve(touched.count, claimed);
+      if (claimed) {
         touched.list[at] = c;
         tko[at] = Kout[c];
         tki[at] = Kin[c];
@@ -669,10 +968,153 @@ __global__ void k_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out) {
   }
 }
 
+__global__ void k_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t* alive, const uint32_t* key,
+                               const uint32_t* mark, uint32_t mark_ep) {
+  for (uint64_t u = gtid(); u < n; u += gstride())
+    if (alive[u] && mark[key[u]] == mark_ep) stamp[u] = ep;
+}
+
+// wave per listed vertex; plain stores (every writer stores the same epoch)
+__global__ void k_mark_neighbours(uint32_t* stamp, uint32_t ep, const uint32_t* list, uint32_t count, CsrRef out,
+                                  CsrRef in, int directed) {
+  const int lane = lane_id();
+  for (uint64_t i = gwave(); i < count; i += gwstride()) {
+    const uint32_t v = list[i];
+    if (lane == 0) stamp[v] = ep;
+    const uint64_t o = out.off[v];
+    const uint32_t d = out.deg[v];
+    for (uint32_t j = lane; j < d; j += kWave) stamp[out.nbr[o + j]] = ep;
+    if (directed) {
+      const uint64_t oi = in.off[v];
+      const uint32_t di = in.deg[v];
+      for (uint32_t j = lane; j < di; j += kWave) stamp[in.nbr[oi + j]] = ep;
+    }
+  }
+}
+
+__global__ void k_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
+                               const uint32_t* oldpar) {
+  for (uint64_t i = gtid(); i < nr; i += gstride()) {
+    const uint32_t u = rset[i];
+    if (par[u] != oldpar[u]) stamp[u] = ep;
+  }
+}
+
+// number of tuples node u emits (materialise: its out-entries; repair: twice its out-entries
+// plus twice its in-side entries whose other end is outside C)
+__global__ void k_tuple_counts(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed,
+                               const uint32_t* cstamp, uint32_t cep, int repair, uint64_t* counts) {
+  const int lane = lane_id();
+  for (uint64_t i = gwave(); i < k; i += gwstride()) {
+    const uint32_t u = list[i];
+    const uint32_t dout = out.deg[u];
+    if (!repair) {
+      if (lane == 0) counts[i] = dout;
+      continue;
+    }
+    const CsrRef& c = directed ? in : out;
+    const uint64_t o = c.off[u];
+    const uint32_t d = c.deg[u];
+    int64_t outside = 0;
+    for (uint32_t j = lane; j < d; j += kWave) outside += cstamp[c.nbr[o + j]] != cep ? 1 : 0;
+    outside = wave_sum_i64(outside);
+    if (lane == 0) counts[i] = 2ull * dout + 2ull * (uint64_t)outside;
+  }
+}
+
+// tuples of node list[i] written from offs[i] on, in entry order (see k_tuples)
+__global__ void k_tuples_at(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed,
+                            const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
+                            int repair, const uint64_t* offs, uint64_t* tkeys, int64_t* tvals, SetRef seeds) {
+  const int lane = lane_id();
+  for (uint64_t i = gwave(); i < k; i += gwstride()) {
+    const uint32_t u = list[i];
+    const uint32_t pu = par[u];
+    const uint32_t ou = repair ? oldpar[u] : pu;
+    uint64_t pos = offs[i];
+    {
+      const uint64_t o = out.off[u];
+      const uint32_t d = out.deg[u];
+      for (uint32_t j = lane; j < d; j += kWave) {
+        const uint32_t v = out.nbr[o + j];
+        const int64_t w = wget(out, o + j);
+        const uint32_t pv = par[v];
+        if (!repair) {
+          tkeys[pos + j] = ((uint64_t)pu << 32) | pv;
+          tvals[pos + j] = w;
+        } else {
+          const uint32_t ov = cstamp[v] == cep ? oldpar[v] : pv;
+          tkeys[pos + 2 * j] = ((uint64_t)ou << 32) | ov;
+          tvals[pos + 2 * j] = -w;
+          tkeys[pos + 2 * j + 1] = ((uint64_t)pu << 32) | pv;
+          tvals[pos + 2 * j + 1] = w;
+          set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ov);
+          set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pv);
+        }
+      }
+      pos += repair ? 2ull * d : (uint64_t)d;
+    }
+    if (!repair) continue;
+    if (lane == 0) {
+      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ou);
+      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pu);
+    }
+    const CsrRef& c = directed ? in : out;
+    const uint64_t o = c.off[u];
+    const uint32_t d = c.deg[u];
+    for (uint32_t base = 0; base < d; base += kWave) {
+      const uint32_t j = base + lane;
+      bool act = j < d;
+      uint32_t v = 0;
+      int64_t w = 0;
+      if (act) {
+        v = c.nbr[o + j];
+        w = wget(c, o + j);
+        if (cstamp[v] == cep) act = false;
+      }
+      const uint32_t r = rank_in_wave(act);
+      const uint32_t tot = (uint32_t)__popcll(__ballot(act));
+      if (act) {
+        const uint32_t pv = par[v];
+        const uint64_t p2 = pos + 2ull * r;
+        tkeys[p2] = ((uint64_t)pv << 32) | ou;
+        tvals[p2] = -w;
+        tkeys[p2 + 1] = ((uint64_t)pv << 32) | pu;
+        tvals[p2 + 1] = w;
+      }
+      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, act ? par[v] : 0u, act);
+      pos += 2ull * tot;
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
 
+void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t* alive, const uint32_t* key,
+                         const uint32_t* mark, uint32_t mark_ep, hipStream_t s) {
+  if (n) k_mark_members<<<grid_for(n), kTpb, 0, s>>>(stamp, ep, n, alive, key, mark, mark_ep);
+}
+void launch_mark_neighbours(uint32_t* stamp, uint32_t ep, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in,
+                            int directed, hipStream_t s) {
+  if (count) k_mark_neighbours<<<grid_waves(count), kTpb, 0, s>>>(stamp, ep, list, count, out, in, directed);
+}
+void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
+                         const uint32_t* oldpar, hipStream_t s) {
+  if (nr) k_mark_changed<<<grid_for(nr), kTpb, 0, s>>>(stamp, ep, rset, nr, par, oldpar);
+}
+void launch_tuple_counts(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* cstamp,
+                         uint32_t cep, int repair, uint64_t* counts, hipStream_t s) {
+  if (k) k_tuple_counts<<<grid_waves(k), kTpb, 0, s>>>(list, k, out, in, directed, cstamp, cep, repair, counts);
+}
+void launch_tuples_at(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* par,
+                      const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep, int repair, const uint64_t* offs,
+                      uint64_t* tkeys, int64_t* tvals, SetRef seeds_or_null, hipStream_t s) {
+  if (k)
+    k_tuples_at<<<grid_waves(k), kTpb, 0, s>>>(list, k, out, in, directed, par, oldpar, cstamp, cep, repair, offs,
+                                               tkeys, tvals, seeds_or_null);
+}
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n) k_fill_u32<<<grid_for(n), kTpb, 0, s>>>(p, v, n);
 }
@@ -706,6 +1148,46 @@ void launch_neighbours(SetRef set, const uint32_t* list, uint32_t count, CsrRef 
 void launch_csr_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, uint8_t* insflag,
                      uint32_t* rowdel, uint32_t* rowins, SetRef dirty, hipStream_t s) {
   if (k) k_csr_find<<<grid_waves(k), kTpb, 0, s>>>(c, keys, delta, k, insflag, rowdel, rowins, dirty);
+}
+void launch_segments(const uint64_t* keys, uint64_t k, uint64_t* seg_lo, uint32_t* nseg, hipStream_t s) {
+  if (k) k_segments<<<grid_for(k), kTpb, 0, s>>>(keys, k, seg_lo, nseg);
+}
+void launch_seg_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                     const uint32_t* nseg_ptr, uint32_t nseg_max, int64_t* slot_out, uint8_t* insflag,
+                     uint32_t* rowdel, uint32_t* rowins, SetRef dirty, int apply, hipStream_t s) {
+  if (!k) return;
+  unsigned g = nseg_max < 8192 ? (nseg_max ? nseg_max : 1) : 8192;
+  if (apply)
+    k_seg_find<1><<<g, 256, 0, s>>>(c, keys, delta, k, seg_lo, nseg_ptr, slot_out, insflag, rowdel, rowins, dirty);
+  else
+    k_seg_find<0><<<g, 256, 0, s>>>(c, keys, delta, k, seg_lo, nseg_ptr, slot_out, insflag, rowdel, rowins, dirty);
+}
+void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
+                            const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
+                            int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
+                            hipStream_t s) {
+  if (k)
+    k_ingest_validate<<<grid_for(k), kTpb, 0, s>>>(out0, keys, idx, slot, k, ins, ni, del, nd, chg, directed, delta,
+                                                   err, first_bad, dm);
+}
+void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
+                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
+                       size_t* tmp_bytes, hipStream_t s) {
+  if (!k) return;
+  k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items);
+  prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
+  k_fill_i64_dev<<<grid_for(k), kTpb, 0, s>>>(slot_out, -1, k);
+  const unsigned g = k < 8192 ? (unsigned)k : 8192u;
+  k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out);
+}
+void launch_seg_apply(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                      const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* insflag,
+                      uint32_t* rowdel, uint32_t* rowins, int64_t* deg_arr, uint32_t* dirty_list, uint32_t* dirty_count,
+                      hipStream_t s) {
+  if (!k) return;
+  const unsigned g = k < 8192 ? (unsigned)k : 8192u;
+  k_seg_apply<<<g, 256, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, insflag, rowdel, rowins, deg_arr,
+                                dirty_list, dirty_count);
 }
 void launch_csr_plan(CsrRef c, const uint32_t* dirty, uint32_t nd, const uint32_t* rowdel, const uint32_t* rowins,
                      uint64_t* plan_off, uint32_t* plan_cap, u64a* pool_top, uint64_t pool_cap, uint32_t* overflow,

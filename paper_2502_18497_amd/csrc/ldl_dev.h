@@ -20,11 +20,38 @@ __device__ __forceinline__ bool set_claim(uint32_t* stamp, uint32_t epoch, uint3
   if (__hip_atomic_load(&stamp[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) return false;
   return atomicExch(&stamp[x], epoch) != epoch;
 }
-__device__ __forceinline__ void set_add(uint32_t* stamp, uint32_t epoch, uint32_t* list, uint32_t* count,
-                                        uint32_t x) {
-  if (set_claim(stamp, epoch, x)) list[atomicAdd(count, 1u)] = x;
+// Reserve slots in an append list for the active lanes with `pred`: one atomic per wave.
+// Call from every active lane of the wave (any subset of lanes may be active).
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t* count, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+  return base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
 }
-
+__device__ __forceinline__ unsigned long long wave_reserve64(unsigned long long* count, bool pred,
+                                                             unsigned long long per) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const int lane = (int)__lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m) * per);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)base, leader);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(base >> 32), leader);
+  base = ((unsigned long long)hi << 32) | lo;
+  return base + per * (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+}
+// Insert x (when `valid`) into a stamped set; called from every active lane.
+__device__ __forceinline__ void set_add(uint32_t* stamp, uint32_t epoch, uint32_t* list, uint32_t* count,
+                                        uint32_t x, bool valid = true) {
+  const bool claimed = valid && set_claim(stamp, epoch, x);
+  const uint32_t at = wave_reserve(count, claimed);
+  if (claimed) list[at] = x;
+}
 // ------------------------------------------------------------------ exact accumulation
 // Signed 128-bit accumulation into (lo, hi) words with two 64-bit atomics: the carry out of
 // the low word is detected from the value returned by the low-word atomic.

@@ -63,13 +63,15 @@ struct HubPool {
   uint32_t* over_count;
 };
 
-struct MoveStats {
+struct MoveStats {  // per-launch counters (null: not counted)
   u64a* entries;
   u64a* distinct;
   u64a* vertices;
+  u64a* cands;
 };
 
 constexpr int kNumBins = 5;
+constexpr uint32_t kHubScanSlots = 8192;   // table slots evaluated per hub scan workgroup
 // degree bins: total entries T in (0,8], (8,32], (32,128], (128,2048], (2048, inf)
 constexpr uint32_t kBinLimit[kNumBins - 1] = {8, 32, 128, 2048};
 
@@ -87,6 +89,28 @@ void launch_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, con
 // set.add(u) for every alive u < n with mark[key[u]] == mark_epoch
 void launch_members(SetRef set, uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* mark,
                     uint32_t mark_epoch, hipStream_t s);
+// plain-store marking (stamp[x] = ep, no list): members of marked keys, listed vertices and
+// their neighbours, accepted movers and their neighbours; a later select builds the list
+void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t* alive, const uint32_t* key,
+                         const uint32_t* mark, uint32_t mark_ep, hipStream_t s);
+void launch_mark_neighbours(uint32_t* stamp, uint32_t ep, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in,
+                            int directed, hipStream_t s);
+void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, uint32_t na, CandBuf cand,
+                                CsrRef out, CsrRef in, int directed, hipStream_t s);
+void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
+                         const uint32_t* oldpar, hipStream_t s);
+// degree binning without global atomics: per-block histograms, scan, fill
+constexpr unsigned kBinBlocks = 1024;
+void launch_bin_count(const MoveView& mv, const uint32_t* list, uint32_t count, int refine, uint32_t* hist,
+                      hipStream_t s);
+void launch_bin_fill(const MoveView& mv, const uint32_t* list, uint32_t count, int refine, const uint32_t* offs,
+                     uint32_t* out, uint32_t* bin_start, uint32_t* bin_count, hipStream_t s);
+// aggregation tuples at precomputed per-node offsets (no global atomics)
+void launch_tuple_counts(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* cstamp,
+                         uint32_t cep, int repair, uint64_t* counts, hipStream_t s);
+void launch_tuples_at(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* par,
+                      const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep, int repair, const uint64_t* offs,
+                      uint64_t* tkeys, int64_t* tvals, SetRef seeds_or_null, hipStream_t s);
 // set.add(u) for u in list and every neighbour of u
 void launch_neighbours(SetRef set, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in, int directed,
                        hipStream_t s);
@@ -95,6 +119,24 @@ void launch_neighbours(SetRef set, const uint32_t* list, uint32_t count, CsrRef 
 // Records sorted by key = row << 32 | col with deltas; zero deltas are ignored.
 void launch_csr_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, uint8_t* insflag,
                      uint32_t* rowdel, uint32_t* rowins, SetRef dirty, hipStream_t s);
+// row segments of sorted keys (first record index per row) and the segment-wise row lookup
+void launch_segments(const uint64_t* keys, uint64_t k, uint64_t* seg_lo, uint32_t* nseg, hipStream_t s);
+void launch_seg_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                     const uint32_t* nseg_ptr, uint32_t nseg_max, int64_t* slot_out, uint8_t* insflag,
+                     uint32_t* rowdel, uint32_t* rowins, SetRef dirty, int apply, hipStream_t s);
+// row lookup of sorted records split over (segment, record chunk, row slice) items: slot of
+// every record (or -1); then the per-segment apply (optionally adding row delta sums to deg)
+void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
+                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
+                       size_t* tmp_bytes, hipStream_t s);
+void launch_seg_apply(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                      const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* insflag,
+                      uint32_t* rowdel, uint32_t* rowins, int64_t* deg_arr, uint32_t* dirty_list, uint32_t* dirty_count,
+                      hipStream_t s);
+void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
+                            const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
+                            int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
+                            hipStream_t s);
 void launch_csr_plan(CsrRef c, const uint32_t* dirty, uint32_t nd, const uint32_t* rowdel, const uint32_t* rowins,
                      uint64_t* plan_off, uint32_t* plan_cap, u64a* pool_top, uint64_t pool_cap, uint32_t* overflow,
                      hipStream_t s);
@@ -138,6 +180,15 @@ void launch_bin(const MoveView& mv, const uint32_t* list, uint32_t count, int re
 // one launch per bin; bin index b in [0, kNumBins); hub bin may need re-launches on overflow
 void launch_best(const MoveView& mv, int bin, const uint32_t* list, uint32_t count, int refine, CandBuf cand,
                  HubPool hub, MoveStats st, hipStream_t s);
+
+// hubs split over workgroups: table sizes, then per group of hubs [i0, i0+ng) whose tables
+// span [base0, base0+span) of the pool: clear, insert, scan into partial bests, final reduce
+void launch_hub_prep(const MoveView& mv, const uint32_t* list, uint32_t h, uint64_t* hsize, u64a* maxT,
+                     hipStream_t s);
+void launch_hub_group(const MoveView& mv, const uint32_t* list, uint32_t i0, uint32_t ng, const uint64_t* hoff,
+                      uint64_t base0, uint64_t span, uint64_t maxT, int refine, HubPool hub, int64_t* own,
+                      uint32_t max_parts, int64_t* phi, uint64_t* plo, uint32_t* pid, int* pvalid, CandBuf cand,
+                      MoveStats st, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 
 // ---------------------------------------------------------------- decouple (exact greedy filter)
 void launch_rank_from_order(const uint32_t* order, uint32_t k, uint32_t* rank, hipStream_t s);
@@ -214,6 +265,11 @@ int prim_sort_pairs_u64_i64(void** tmp, size_t* tmp_bytes, const uint64_t* kin, 
 int prim_reduce_by_key(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,
                        int64_t* vout, u64a* nruns, uint64_t n, hipStream_t s);
 int prim_exclusive_sum_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, uint64_t* out, uint64_t n,
+                           hipStream_t s);
+// ids i < n with stamp[i] == ep, in increasing order, count written to *d_count
+int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* out,
+                      uint32_t* d_count, hipStream_t s);
+int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
                            hipStream_t s);
 int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, uint64_t n, hipStream_t s);
 

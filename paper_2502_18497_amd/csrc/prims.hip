@@ -22,6 +22,12 @@ int ensure(void** tmp, size_t* bytes, size_t need) {
   return 0;
 }
 
+struct StampIs {
+  const uint32_t* stamp;
+  uint32_t ep;
+  __host__ __device__ __forceinline__ bool operator()(const uint32_t& i) const { return stamp[i] == ep; }
+};
+
 struct SumI64 {
   __host__ __device__ __forceinline__ int64_t operator()(const int64_t& a, const int64_t& b) const { return a + b; }
 };
@@ -90,6 +96,28 @@ int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, u
   if (ensure(tmp, tmp_bytes, need)) return -2;
   size_t have = *tmp_bytes;
   return hipcub::DeviceReduce::Max(*tmp, have, in, (uint64_t*)out, (int)n, s) == hipSuccess ? 0 : -1;
+}
+
+int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* out,
+                      uint32_t* d_count, hipStream_t s) {
+  if (n == 0) return 0;
+  hipcub::CountingInputIterator<uint32_t> ids(0);
+  StampIs pred{stamp, ep};
+  size_t need = 0;
+  if (hipcub::DeviceSelect::If(nullptr, need, ids, out, d_count, (int)n, pred, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceSelect::If(*tmp, have, ids, out, d_count, (int)n, pred, s) == hipSuccess ? 0 : -1;
+}
+
+int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
+                           hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceScan::ExclusiveSum(*tmp, have, in, out, (int)n, s) == hipSuccess ? 0 : -1;
 }
 
 }  // namespace ldl

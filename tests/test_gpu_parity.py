@@ -223,3 +223,19 @@ def test_full_size_rmat20_properties():
     assert num == g.qnum()
     errs = check_state(g.state(), False, check_connectivity=True)
     assert not errs, errs
+
+
+def test_single_hip_runtime_in_process():
+    import torch
+
+    import paper_2502_18497_amd as ldl
+
+    ldl.load_library()
+    assert torch.cuda.is_available()
+    x = torch.ones(4, device="cuda")
+    assert float(x.sum()) == 4.0
+    paths = set()
+    for line in open("/proc/self/maps"):
+        if "libamdhip64" in line:
+            paths.add(line.split()[-1])
+    assert len(paths) == 1, paths
