@@ -60,24 +60,30 @@ static T* dalloc(uint64_t count) {
 }
 
 // Device-side counters and accumulators, mirrored into pinned host memory on demand.
+// Counters written by one candidate pass (cleared together before it).
+struct PassScal {
+  u64a st_entries[kNumBins], st_distinct[kNumBins], st_vertices[kNumBins], st_cands[kNumBins];
+  u64a maxhi;       // max high word of the candidates' gains
+  u64a hub_need;    // pool slots the hub tables needed
+  uint32_t ncand;
+  uint32_t hub_over;
+};
 struct Scal {
   uint32_t counts[64];
   uint32_t bins[8];
   uint32_t bin_start[8];
-  uint32_t ncand, nacc, nlive2, err, first_bad, overflow, hub_over, nseg;
+  uint32_t nacc, nlive[2], err, first_bad, nseg, nmove, overflow;   // nmove, overflow adjacent
   u64a pool_top[2 * 17];
-  u64a hub_top;
   i64a dm, dein;
   u64a dskk_lo;
   i64a dskk_hi;
   u64a tcount, tneed, nruns, ecount;
-  u64a st_entries[kNumBins], st_distinct[kNumBins], st_vertices[kNumBins], st_cands[kNumBins];
-  u64a maxv;
+  PassScal ps;
 };
 
 enum SetId {
   S_D0 = 0,  // 0..16 seed sets per level
-  S_U = 17, S_U2, S_S, S_MOVED, S_RSET, S_RCUR, S_C, S_TOUCH, S_COMM, S_REFM, S_MOV, S_DIRTY, S_LVC, S_DIED,
+  S_U = 17, S_U2, S_S, S_MOVED, S_RSET, S_RCUR, S_C, S_TOUCH, S_COMM, S_REFM, S_MOV, S_LVC, S_DIED,
   S_REV, S_DIED2, S_REV2, S_TMP, S_NSETS
 };
 
@@ -139,8 +145,6 @@ struct Engine {
 
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
-  uint64_t* plan_off = nullptr;
-  uint32_t* plan_cap = nullptr;
   uint32_t *minE = nullptr, *minA = nullptr, *accE = nullptr, *accA = nullptr;
   uint32_t acc_epoch = 0;
   uint8_t* lfflag = nullptr;
@@ -149,15 +153,9 @@ struct Engine {
   uint32_t* bins[kNumBins] = {};
   uint32_t* binbuf = nullptr;
   uint32_t *bhist = nullptr, *boffs = nullptr;
-  uint64_t *tcounts = nullptr, *toffs = nullptr;
-  uint32_t* hub_over_alt = nullptr;
-  uint64_t *hsize = nullptr, *hoff = nullptr;
-  int64_t* hown = nullptr;
+  uint64_t *tcounts = nullptr, *toffs = nullptr, *tcur = nullptr, *it_cnt = nullptr, *it_off = nullptr;
+  HubWork hw{};
   uint64_t part_cap = 0;
-  int64_t* phi = nullptr;
-  uint64_t* plo = nullptr;
-  uint32_t* pid = nullptr;
-  int* pvalid = nullptr;
   CandBuf cand{};
   uint64_t *skey0 = nullptr, *skey1 = nullptr;
   uint32_t *sidx0 = nullptr, *sidx1 = nullptr;
@@ -171,7 +169,9 @@ struct Engine {
   uint64_t *ekey0 = nullptr, *ekey1 = nullptr;
   int64_t *edel0 = nullptr, *edel1 = nullptr;
   uint32_t *ex = nullptr, *ey = nullptr;
-  uint8_t* insflag = nullptr;
+  uint8_t* insflag = nullptr;     // record types of the row update
+  uint64_t* holebuf = nullptr;
+  uint32_t* movelist = nullptr;
   uint64_t* seg_lo = nullptr;
   uint64_t *seg_hi = nullptr, *items = nullptr, *item_off = nullptr;
   int64_t* slotbuf = nullptr;
@@ -259,12 +259,15 @@ struct Engine {
     cub(prim_select_stamp(&cub_tmp, &cub_bytes, s.stamp, s.epoch, n, s.list, &ds->counts[s.ci], st));
   }
 
-  // per-node tuple counts and their exclusive prefix (toffs); grows the tuple buffers
-  uint64_t tuple_offsets(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, const uint32_t* cstamp,
-                         uint32_t cep, int repair) {
+  // per-node tuple counts over the list of set `sid` (k nodes) and their exclusive prefix
+  // (toffs); returns the tuple total and grows the tuple buffers
+  uint64_t tuple_offsets(int sid, uint32_t k, CsrRef out, CsrRef in, const uint32_t* cstamp, uint32_t cep,
+                         int repair) {
     if (k == 0) return 0;
-    launch_tuple_counts(list, k, out, in, directed, cstamp, cep, repair, tcounts, st);
-    hcheck(hipMemsetAsync(tcounts + k, 0, 8, st));
+    const uint32_t* list = sets[sid].list;
+    const uint32_t* cnt = &ds->counts[sets[sid].ci];
+    cub(launch_items(list, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
+    launch_tuples_count(list, cnt, k, it_off, out, in, cstamp, cep, repair, (u64a*)tcounts, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
     uint64_t T = 0;
     hcheck(hipMemcpyAsync(&T, toffs + k, 8, hipMemcpyDeviceToHost, st));
@@ -338,10 +341,6 @@ struct Engine {
     oldpar = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
-    launch_fill_u32(rowdel, 0, n, st);
-    launch_fill_u32(rowins, 0, n, st);
-    plan_off = alloc<uint64_t>(n);
-    plan_cap = alloc<uint32_t>(n);
     minE = alloc<uint32_t>(n);
     minA = alloc<uint32_t>(n);
     accE = alloc<uint32_t>(n);
@@ -364,29 +363,58 @@ struct Engine {
     tcounts = alloc<uint64_t>((uint64_t)n + 1);
     toffs = alloc<uint64_t>((uint64_t)n + 1);
     hcheck(hipMemsetAsync(tcounts, 0, 8ull * ((uint64_t)n + 1), st));
-    hub_over_alt = alloc<uint32_t>(n);
-    hsize = alloc<uint64_t>((uint64_t)n + 1);
-    hoff = alloc<uint64_t>((uint64_t)n + 1);
-    hown = alloc<int64_t>(n);
+    tcur = alloc<uint64_t>((uint64_t)n + 1);
+    it_cnt = alloc<uint64_t>((uint64_t)n + 1);
+    it_off = alloc<uint64_t>((uint64_t)n + 1);
+    hw.hsize = alloc<uint64_t>((uint64_t)n + 1);
+    hw.hoff = alloc<uint64_t>((uint64_t)n + 1);
+    hw.icnt = alloc<uint64_t>((uint64_t)n + 1);
+    hw.ioff = alloc<uint64_t>((uint64_t)n + 1);
+    hw.scnt = alloc<uint64_t>((uint64_t)n + 1);
+    hw.soff = alloc<uint64_t>((uint64_t)n + 1);
+    hw.own = alloc<int64_t>((uint64_t)n + 1);
     cand.v = alloc<uint32_t>(n);
     cand.a = alloc<uint32_t>(n);
     cand.b = alloc<uint32_t>(n);
     cand.glo = alloc<uint64_t>(n);
     cand.ghi = alloc<int64_t>(n);
-    cand.count = &ds->ncand;
+    cand.count = &ds->ps.ncand;
     skey0 = alloc<uint64_t>(n);
     skey1 = alloc<uint64_t>(n);
     sidx0 = alloc<uint32_t>(n);
     sidx1 = alloc<uint32_t>(n);
-    uint64_t hc = 1;
-    while (hc < 4ull * n) hc <<= 1;
-    if (hc < (1ull << 16)) hc = 1ull << 16;
+    hub.top = &ds->ps.hub_need;
+    hub.over_count = &ds->ps.hub_over;
+    hub_pool(4ull * n);
+    hcheck(hipStreamSynchronize(st));
+  }
+
+  // (re)allocate the hub table pool with at least `slots` slots, empty, and its partials
+  void hub_pool(uint64_t slots) {
+    uint64_t hc = 1ull << 16;
+    while (hc < slots) hc <<= 1;
+    release(hub.keys);
+    release(hub.vals);
+    hub.keys = nullptr;
+    hub.vals = nullptr;
     hub.keys = alloc<uint32_t>(hc);
     hub.vals = alloc<u64a>(hc);
     hub.cap = hc;
-    hub.top = &ds->hub_top;
-    hub.over_count = &ds->hub_over;
-    hcheck(hipStreamSynchronize(st));
+    hcheck(hipMemsetAsync(hub.keys, 0xFF, 4ull * hc, st));
+    hcheck(hipMemsetAsync(hub.vals, 0, 8ull * hc, st));
+    const uint64_t parts = hc / kHubScanSlots + (uint64_t)n + 2;
+    if (parts > part_cap) {
+      regrow(hw.phi, parts); regrow(hw.plo, parts); regrow(hw.pid, parts); regrow(hw.pvalid, parts);
+      part_cap = parts;
+    }
+  }
+
+  // upper bound on the number of hub vertices (more than kBinLimit[3] entries) of level r
+  uint32_t hub_bound(int r) const {
+    const Level& V = lv[r];
+    const uint64_t ent = V.out.pool_cap + (directed ? V.in.pool_cap : 0);
+    const uint64_t b = ent / (kBinLimit[kNumBins - 2] + 1) + 1;
+    return (uint32_t)std::min<uint64_t>(b, n);
   }
 
   void csr_init(Csr& c, bool wide) {
@@ -419,6 +447,8 @@ struct Engine {
     if (k <= ins_cap) return;
     uint64_t c = std::max<uint64_t>(k, ins_cap * 2);
     regrow(insflag, c);
+    regrow(holebuf, c);
+    regrow(movelist, c);
     regrow(seg_lo, c);
     regrow(seg_hi, c);
     regrow(items, c + 1);
@@ -474,34 +504,28 @@ struct Engine {
   }
 
   // Apply sorted records (key = row << 32 | col, distinct keys) to one orientation; when
-  // deg_arr is given, each row's delta sum is added to it.
+  // deg_arr is given, each row's delta sum is added to it.  Rows are updated in place; rows
+  // that outgrow their capacity move to new pool regions (the pool grows when full).
   void csr_apply(Csr& c, const uint64_t* keys, const int64_t* delta, uint64_t k, int64_t* deg_arr) {
     if (k == 0) return;
     if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
     ensure_insflag(k);
-    zero(&ds->nseg);
-    launch_segments(keys, k, seg_lo, &ds->nseg, st);
+    cub(prim_select_heads(&cub_tmp, &cub_bytes, keys, k, seg_lo, &ds->nseg, st));
     launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, slotbuf, &cub_tmp, &cub_bytes, st);
-    begin(S_DIRTY);
-    launch_seg_apply(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, rowdel, rowins, deg_arr,
-                     sets[S_DIRTY].list, &ds->counts[sets[S_DIRTY].ci], st);
+    hcheck(hipMemsetAsync(&ds->nmove, 0, 2 * sizeof(uint32_t), st));   // nmove, overflow
+    launch_seg_update(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, holebuf, deg_arr, rowdel,
+                      rowins, movelist, &ds->nmove, st);
+    launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
+                    &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, st);
     sync_read();
-    const uint32_t nd = count(S_DIRTY);
-    if (nd == 0) return;
-    for (int attempt = 0;; ++attempt) {
-      const u64a saved = hs->pool_top[c.slot];
-      zero(&ds->overflow);
-      launch_csr_plan(c.ref, sets[S_DIRTY].list, nd, rowdel, rowins, plan_off, plan_cap, &ds->pool_top[c.slot],
-                      c.pool_cap, &ds->overflow, st);
-      sync_read();
-      if (!hs->overflow) break;
+    for (int attempt = 0; hs->overflow; ++attempt) {
       if (attempt > 3) throw NoMem{};
-      hcheck(hipMemcpyAsync(&ds->pool_top[c.slot], &saved, 8, hipMemcpyHostToDevice, st));
       csr_grow(c, 2 * k + c.pool_cap / 4);
+      zero(&ds->overflow);
+      launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
+                      &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, st);
       sync_read();
     }
-    launch_csr_rewrite(c.ref, sets[S_DIRTY].list, nd, rowdel, rowins, plan_off, plan_cap, keys, delta, insflag, k,
-                       st);
   }
 
   // Apply reduced records to level s (out, and in via a transposed sort when directed).
@@ -547,8 +571,7 @@ struct Engine {
     Level& V0 = lv[0];
     if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
     ensure_insflag(K);
-    zero(&ds->nseg);
-    launch_segments(rkey1, K, seg_lo, &ds->nseg, st);
+    cub(prim_select_heads(&cub_tmp, &cub_bytes, rkey1, K, seg_lo, &ds->nseg, st));
     launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, rslot, &cub_tmp, &cub_bytes,
                       st);
     launch_ingest_validate(V0.out.ref, rkey1, ridx1, rslot, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
@@ -573,8 +596,8 @@ struct Engine {
     zero(&ds->dskk_lo);
     zero(&ds->dskk_hi);
     launch_ingest_totals(ekey1, edel1, E, V0.lab, Kout, directed ? Kin : nullptr, &ds->dein, st);
-    sync_read();
-    launch_dskk(sets[S_TOUCH].list, count(S_TOUCH), Kout, Kin, tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
+    launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], (uint32_t)std::min<uint64_t>(2 * E, n), Kout, Kin,
+                tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
     apply_records(0, ekey1, edel1, E, true);
     sync_read();
     m += dm;
@@ -630,121 +653,83 @@ struct Engine {
     return ev_pool[ev_used++];
   }
 
-  // BestMove_r / BestRef_r over list[0..cnt): candidates in `cand`, returns their number.
-  // With profiling, every kernel launch is bracketed by HIP events on its stream and its
-  // algorithmic bytes are computed from the counters the kernel itself accumulates.
-  uint32_t best(int r, const uint32_t* list, uint32_t cnt, int refine) {
-    if (cnt == 0) return 0;
+  // BestMove_r / BestRef_r over the list of set `sid` (its count stays on the device):
+  // candidates in `cand`.  One synchronisation reads back the scanned count, the candidate
+  // count and the pass counters.  With profiling, every candidate kernel is bracketed by HIP
+  // events on its stream and its algorithmic bytes follow from the counters it accumulates.
+  uint32_t best(int r, int sid, int refine, uint32_t& scanned) {
     MoveView mv = view(r, refine);
-    zero(&ds->ncand);
-    hcheck(hipMemsetAsync(ds->st_entries, 0, sizeof(ds->st_entries) * 4, st));
-    launch_bin_count(mv, list, cnt, refine, bhist, st);
-    cub(prim_exclusive_sum_u32(&cub_tmp, &cub_bytes, bhist, boffs, kNumBins * kBinBlocks + 1, st));
-    launch_bin_fill(mv, list, cnt, refine, boffs, binbuf, ds->bin_start, ds->bins, st);
-    sync_read();
-    uint32_t bc[kNumBins];
-    for (int b = 0; b < kNumBins; ++b) {
-      bc[b] = hs->bins[b];
-      bins[b] = binbuf + hs->bin_start[b];
-    }
+    const uint32_t* list = sets[sid].list;
+    const uint32_t* cnt = &ds->counts[sets[sid].ci];
     const int wide = lv[r].out.ref.wide;
     const int cat0 = 10 * refine + 5 * wide;
+    const size_t first_pending = pending.size();
+    for (int attempt = 0;; ++attempt) {
+      hcheck(hipMemsetAsync(&ds->ps, 0, sizeof(PassScal), st));
+      launch_bin_count(mv, list, cnt, refine, bhist, st);
+      cub(prim_exclusive_sum_u32(&cub_tmp, &cub_bytes, bhist, boffs, kNumBins * kBinBlocks + 1, st));
+      launch_bin_fill(mv, list, cnt, refine, boffs, binbuf, ds->bin_start, ds->bins, st);
+      const uint32_t hb = hub_bound(r);
+      for (int b = 0; b < kNumBins; ++b) {
+        if (b == kNumBins - 1 && hb == 0) break;
+        MoveStats ms{&ds->ps.st_entries[b], &ds->ps.st_distinct[b], &ds->ps.st_vertices[b], &ds->ps.st_cands[b],
+                     &ds->ps.maxhi};
+        BinRef br{binbuf, &ds->bin_start[b], &ds->bins[b]};
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (profile) ev = next_events();
+        if (b < kNumBins - 1) {
+          if (profile) hcheck(hipEventRecord(ev.first, st));
+          launch_best(mv, b, br, n, refine, cand, ms, st);
+          if (profile) hcheck(hipEventRecord(ev.second, st));
+        } else {
+          // hubs: the events bracket the table-insert kernel, which reads the entries
+          cub(launch_hub(mv, br, hb, refine, hub, hw, cand, ms, &cub_tmp, &cub_bytes, st,
+                         profile ? ev.first : nullptr, profile ? ev.second : nullptr));
+        }
+        if (profile) pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
+      }
+      sync_read();
+      if (hs->ps.hub_over & 2u) throw DeviceError{hipErrorUnknown};
+      if (hs->ps.hub_over & 1u) {
+        if (attempt > 2) throw NoMem{};
+        hub_pool(hs->ps.hub_need);   // grow and redo the pass: its state is unchanged
+        pending.resize(first_pending);
+        continue;
+      }
+      break;
+    }
+    scanned = hs->counts[sets[sid].ci];
     // algorithmic bytes: per vertex its list id, offsets and degrees, label, degrees and the
     // totals of its own community; per entry neighbour id, weight and neighbour label (plus
-    // the parent in refinement); per distinct community its totals; per candidate 28 bytes
+    // the parent in refinement); per distinct community its totals; per candidate 28 bytes.
+    // The hub insert kernel reads per vertex its id, offsets, degrees and label, and the entries.
     const double wb = wide ? 8.0 : 4.0;
     const double dirf = directed ? 2.0 : 1.0;
     const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 0 : 8 * dirf);
     const double per_e = 4 + wb + 4 + (refine ? 4 : 0);
     const double per_d = 8 * dirf;
-    auto bytes_of = [&](int b) {
-      return per_v * hs->st_vertices[b] + per_e * hs->st_entries[b] + per_d * hs->st_distinct[b] +
-             28.0 * hs->st_cands[b];
-    };
-    size_t first_pending = pending.size();
-    for (int b = 0; b < kNumBins - 1; ++b) {
-      if (!bc[b]) continue;
-      MoveStats ms{&ds->st_entries[b], &ds->st_distinct[b], &ds->st_vertices[b], &ds->st_cands[b]};
-      std::pair<hipEvent_t, hipEvent_t> ev{};
+    const PassScal& ps = hs->ps;
+    for (int b = 0; b < kNumBins; ++b) {
+      stats.scanned_vertices += ps.st_vertices[b];
+      stats.scanned_entries += ps.st_entries[b];
+      stats.distinct_comms += ps.st_distinct[b];
+      stats.bin_entries[cat0 + b] += ps.st_entries[b];
       if (profile) {
-        ev = next_events();
-        hcheck(hipEventRecord(ev.first, st));
-      }
-      launch_best(mv, b, bins[b], bc[b], refine, cand, hub, ms, st);
-      if (profile) {
-        hcheck(hipEventRecord(ev.second, st));
-        pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
-      }
-    }
-    sync_read();
-    for (int b = 0; b < kNumBins - 1; ++b) {
-      if (!bc[b]) continue;
-      stats.scanned_vertices += hs->st_vertices[b];
-      stats.scanned_entries += hs->st_entries[b];
-      stats.distinct_comms += hs->st_distinct[b];
-      stats.bin_entries[cat0 + b] += hs->st_entries[b];
-      if (profile)
+        const double bytes = b < kNumBins - 1
+                                 ? per_v * ps.st_vertices[b] + per_e * ps.st_entries[b] +
+                                       per_d * ps.st_distinct[b] + 28.0 * ps.st_cands[b]
+                                 : (4 + 12 * dirf + 4) * ps.st_vertices[b] + per_e * ps.st_entries[b];
         for (size_t i = first_pending; i < pending.size(); ++i)
-          if (pending[i].bin == cat0 + b) pending[i].bytes = bytes_of(b);
-    }
-    // hubs: tables of pow2 >= 2T slots, processed in groups whose tables fit the pool
-    const int hb = kNumBins - 1;
-    const uint32_t h = bc[hb];
-    if (h) {
-      const uint32_t* hl = bins[hb];
-      launch_hub_prep(mv, hl, h, hsize, &ds->maxv, st);
-      cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, hsize, hoff, (uint64_t)h + 1, st));
-      std::vector<uint64_t> ho((size_t)h + 1);
-      hcheck(hipMemcpyAsync(ho.data(), hoff, 8ull * ((uint64_t)h + 1), hipMemcpyDeviceToHost, st));
-      hcheck(hipMemsetAsync(&ds->st_entries[hb], 0, 8, st));
-      hcheck(hipMemsetAsync(&ds->st_distinct[hb], 0, 8, st));
-      hcheck(hipMemsetAsync(&ds->st_vertices[hb], 0, 8, st));
-      hcheck(hipMemsetAsync(&ds->st_cands[hb], 0, 8, st));
-      hcheck(hipStreamSynchronize(st));
-      MoveStats ms{&ds->st_entries[hb], &ds->st_distinct[hb], &ds->st_vertices[hb], &ds->st_cands[hb]};
-      const size_t hub_first = pending.size();
-      uint32_t i0 = 0;
-      while (i0 < h) {
-        uint32_t i1 = i0 + 1;
-        uint64_t maxsize = ho[i0 + 1] - ho[i0];
-        if (maxsize > hub.cap) throw DeviceError{hipErrorUnknown};
-        while (i1 < h && ho[i1 + 1] - ho[i0] <= hub.cap) {
-          maxsize = std::max<uint64_t>(maxsize, ho[i1 + 1] - ho[i1]);
-          ++i1;
-        }
-        const uint32_t ng = i1 - i0;
-        const uint32_t max_parts = (uint32_t)((maxsize + kHubScanSlots - 1) / kHubScanSlots);
-        const uint64_t need = (uint64_t)ng * max_parts;
-        if (need > part_cap) {
-          const uint64_t c = std::max<uint64_t>(need, 2 * part_cap);
-          regrow(phi, c); regrow(plo, c); regrow(pid, c); regrow(pvalid, c);
-          part_cap = c;
-        }
-        hcheck(hipMemsetAsync(hown, 0, 8ull * ng, st));
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (profile) ev = next_events();
-        launch_hub_group(mv, hl, i0, ng, hoff, ho[i0], ho[i1] - ho[i0], maxsize / 2, refine, hub, hown, max_parts,
-                         phi, plo, pid, pvalid, cand, ms, st, profile ? ev.first : nullptr,
-                         profile ? ev.second : nullptr);
-        if (profile) pending.push_back(Pending{cat0 + hb, ev.first, ev.second, 0.0});
-        i0 = i1;
+          if (pending[i].bin == cat0 + b) pending[i].bytes = bytes;
       }
-      sync_read();
-      stats.scanned_vertices += hs->st_vertices[hb];
-      stats.scanned_entries += hs->st_entries[hb];
-      stats.distinct_comms += hs->st_distinct[hb];
-      stats.bin_entries[cat0 + hb] += hs->st_entries[hb];
-      // bytes of the insert kernels: per vertex its list id, offsets/degrees and label; per entry
-      if (profile && pending.size() > hub_first)
-        pending[hub_first].bytes = (4 + 12 * dirf + 4) * hs->st_vertices[hb] + per_e * hs->st_entries[hb];
     }
-    sync_read();
-    stats.candidates += hs->ncand;
-    return hs->ncand;
+    stats.candidates += ps.ncand;
+    return ps.ncand;
   }
 
-  // exact greedy filter over cand[0..K): accepted candidate indices in `acc`; returns count
-  uint32_t decouple(uint32_t K) {
+  // exact greedy filter over cand[0..K): accepted candidate indices in `acc`; returns count.
+  // The rounds read their live counts on the device; the host checks them every few rounds.
+  uint32_t decouple(uint32_t K, uint64_t maxhi) {
     if (K == 0) return 0;
     // order by (gain descending, vertex ascending) with stable radix passes
     launch_iota(sidx0, K, st);
@@ -752,17 +737,13 @@ struct Engine {
     cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, id_bits, st));
     launch_gather_u64(cand.glo, sidx1, K, skey0, 1, st);
     cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx1, sidx0, K, 0, 64, st));
-    zero(&ds->maxv);
-    cub(prim_max_u64(&cub_tmp, &cub_bytes, (const uint64_t*)cand.ghi, &ds->maxv, K, st));
-    sync_read();
     uint32_t* order = sidx0;
-    if (hs->maxv != 0) {
+    if (maxhi != 0) {
       launch_gather_u64((const uint64_t*)cand.ghi, sidx0, K, skey0, 1, st);
       cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, 64, st));
       order = sidx1;
     }
     launch_rank_from_order(order, K, rank, st);
-    // rounds
     if (++acc_epoch == 0) {
       launch_fill_u32(accE, 0, n, st);
       launch_fill_u32(accA, 0, n, st);
@@ -771,18 +752,28 @@ struct Engine {
     hcheck(hipMemsetAsync(lfflag, 0, K, st));
     launch_iota(liveA, K, st);
     zero(&ds->nacc);
-    uint32_t nl = K;
+    hcheck(hipMemsetD32Async((hipDeviceptr_t)&ds->nlive[0], K, 1, st));
+    constexpr int kRoundsPerCheck = 4;
     uint32_t *la = liveA, *lb = liveB;
-    while (nl) {
-      launch_lf_reset(la, nl, cand.a, cand.b, minE, minA, st);
-      launch_lf_min(la, nl, cand.a, cand.b, rank, minE, minA, st);
-      launch_lf_accept(la, nl, cand.a, cand.b, rank, minE, minA, accE, accA, acc_epoch, lfflag, acc, &ds->nacc, st);
-      zero(&ds->nlive2);
-      launch_lf_reject(la, nl, cand.a, cand.b, accE, accA, acc_epoch, lfflag, lb, &ds->nlive2, st);
+    int ca = 0;   // index of la's count in nlive
+    uint32_t known = K;
+    for (;;) {
+      for (int k = 0; k < kRoundsPerCheck; ++k) {
+        uint32_t* na_ = &ds->nlive[ca];
+        uint32_t* nb_ = &ds->nlive[1 - ca];
+        launch_lf_reset(la, na_, K, cand.a, cand.b, minE, minA, nb_, st);
+        launch_lf_min(la, na_, K, cand.a, cand.b, rank, minE, minA, st);
+        launch_lf_accept(la, na_, K, cand.a, cand.b, rank, minE, minA, accE, accA, acc_epoch, lfflag, acc, &ds->nacc,
+                         st);
+        launch_lf_reject(la, na_, K, cand.a, cand.b, accE, accA, acc_epoch, lfflag, lb, nb_, st);
+        std::swap(la, lb);
+        ca = 1 - ca;
+      }
       sync_read();
-      if (hs->nlive2 >= nl) throw DeviceError{hipErrorUnknown};
-      nl = hs->nlive2;
-      std::swap(la, lb);
+      const uint32_t nl = hs->nlive[ca];
+      if (nl == 0) break;
+      if (nl >= known) throw DeviceError{hipErrorUnknown};   // every round accepts a candidate
+      known = nl;
     }
     return hs->nacc;
   }
@@ -796,20 +787,23 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ move commit
+  // commit the na accepted moves (count on the device at ds->nacc); one synchronisation reads
+  // the exact change of Ein and of sum Kout*Kin
   i128 commit_moves(int r, uint32_t na, int64_t& dein, i128& dskk) {
     Level& V = lv[r];
+    const uint32_t* nap = &ds->nacc;
     begin(S_TOUCH);
     begin(S_MOV);
-    launch_commit_mark(acc, na, cand, sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, Kout, Kin, ref(S_TOUCH), tko,
-                       tki, st);
-    launch_commit_apply(acc, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
+    launch_commit_mark(acc, nap, na, cand, sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, Kout, Kin, ref(S_TOUCH),
+                       tko, tki, st);
+    launch_commit_apply(acc, nap, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
     zero(&ds->dein);
     zero(&ds->dskk_lo);
     zero(&ds->dskk_hi);
-    launch_commit_dein(acc, na, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
+    launch_commit_dein(acc, nap, na, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
                        sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, &ds->dein, st);
-    sync_read();
-    launch_dskk(sets[S_TOUCH].list, count(S_TOUCH), Kout, Kin, tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
+    launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], 2 * na, Kout, Kin, tko, tki, &ds->dskk_lo,
+                &ds->dskk_hi, st);
     sync_read();
     dein = hs->dein;
     dskk = ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
@@ -836,36 +830,40 @@ struct Engine {
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.move_iters++;
-      sync_read();
-      const uint32_t nU = count(S_U);
+      // scan set: the frontier and its neighbours (counts stay on the device)
       begin(S_S);
-      launch_mark_neighbours(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, nU, V.out.ref, in, directed, st);
+      const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
+      cub(launch_items(sets[S_U].list, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off, nullptr,
+                       nullptr, &cub_tmp, &cub_bytes, st));
+      launch_mark_items(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, &ds->counts[sets[S_U].ci], n, it_off,
+                        V.out.ref, in_or_none, st);
       select_set(S_S);
-      sync_read();
-      const uint32_t nS = count(S_S);
-      const uint32_t K = best(r, sets[S_S].list, nS, 0);
-      const uint32_t na = decouple(K);
+      uint32_t nS = 0;
+      const uint32_t K = best(r, S_S, 0, nS);
+      const uint32_t na = decouple(K, hs->ps.maxhi);
       int64_t dein = 0;
       i128 dskk = 0;
       const i128 dq = commit_moves(r, na, dein, dskk);
       record(r, 0, j, nS, K, na, dq);
+      const uint32_t* nap = &ds->nacc;
       if (dq < 0) {  // Alg. 1 l.11
-        launch_commit_apply(acc, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
+        launch_commit_apply(acc, nap, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
         stats.rollbacks++;
         break;
       }
       Ein += dein;
       SKK += dskk;
       stats.accepted += na;
-      launch_set_add_acc_v(ref(S_MOVED), acc, na, cand, st);
+      launch_set_add_acc_v(ref(S_MOVED), acc, nap, na, cand, st);
       // Expand_r: movers, their neighbours, members of the touched communities
       begin(S_U2);
       if (na) {
         begin(S_COMM);
-        launch_mark_acc_comms(acc, na, cand, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
+        launch_mark_acc_comms(acc, nap, na, cand, sets[S_COMM].stamp, sets[S_COMM].epoch, st);
         launch_mark_members(sets[S_U2].stamp, sets[S_U2].epoch, n, V.alive, V.lab, sets[S_COMM].stamp,
                             sets[S_COMM].epoch, st);
-        launch_mark_neighbours_acc(sets[S_U2].stamp, sets[S_U2].epoch, acc, na, cand, V.out.ref, in, directed, st);
+        launch_mark_neighbours_acc(sets[S_U2].stamp, sets[S_U2].epoch, acc, nap, na, cand, V.out.ref, in, directed,
+                                   st);
         select_set(S_U2);
       }
       std::swap(sets[S_U], sets[S_U2]);
@@ -896,24 +894,27 @@ struct Engine {
     const uint32_t nR0 = count(S_RSET);
     launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st);
     launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 1, st);
-    const uint32_t* Rl = sets[S_RSET].list;
-    uint32_t Rc = nR0;
+    int cur = S_RSET;          // the set whose list this iteration scans
+    bool rset_grew = false;    // SPExpand marked new members: rebuild the Rset list at the end
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.refine_iters++;
-      const uint32_t K = best(r, Rl, Rc, 1);
-      const uint32_t na = decouple(K);
-      launch_ref_commit(acc, na, cand, V.par, V.kout, V.kin, H.kout, Krin, V.rsize, st);
+      uint32_t Rc = 0;
+      const uint32_t K = best(r, cur, 1, Rc);
+      const uint32_t na = decouple(K, hs->ps.maxhi);
+      const uint32_t* nap = &ds->nacc;
+      launch_ref_commit(acc, nap, na, cand, V.par, V.kout, V.kin, H.kout, Krin, V.rsize, st);
       stats.refine_moves += na;
       record(r, 1, j, Rc, K, na, 0);
       if ((i128)bd * na < (i128)bn * Rc) break;            // Alg. 1 l.20
       begin(S_RCUR);
-      launch_spexpand(acc, na, cand, V.out.ref, in, directed, V.lab, V.par, V.rsize, ref(S_RCUR), ref(S_RSET),
-                      oldpar, st);
-      sync_read();
-      Rl = sets[S_RCUR].list;
-      Rc = count(S_RCUR);
+      launch_spexpand(acc, nap, na, cand, V.out.ref, in, directed, V.lab, V.par, V.rsize, sets[S_RCUR].stamp,
+                      sets[S_RCUR].epoch, sets[S_RSET].stamp, sets[S_RSET].epoch, oldpar, st);
+      select_set(S_RCUR);
+      rset_grew = rset_grew || na > 0;
+      cur = S_RCUR;
     }
+    if (rset_grew) select_set(S_RSET);
     if (r == top) materialise(r);
     else aggregate(r, E0);
   }
@@ -931,14 +932,17 @@ struct Engine {
     const uint32_t nC = count(S_C);
     CsrRef in = directed ? V.in.ref : V.out.ref;
     const int Dn = S_D0 + r + 1;
-    const uint64_t T = tuple_offsets(sets[S_C].list, nC, V.out.ref, in, sets[S_C].stamp, sets[S_C].epoch, 1);
-    launch_tuples_at(sets[S_C].list, nC, V.out.ref, in, directed, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, 1,
-                     toffs, tk0, tv0, ref(Dn), st);
+    const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, sets[S_C].stamp, sets[S_C].epoch, 1);
+    if (nC)
+      launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, oldpar,
+                        sets[S_C].stamp, sets[S_C].epoch, 1, toffs, (u64a*)tcur, tk0, tv0, sets[Dn].stamp,
+                        sets[Dn].epoch, st);
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_RSET].list, nRset, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_C].list, nC, oldpar, nullptr, st);
+    select_set(Dn);   // the tuple kernel marked seeds without listing them
     // liveness of level r+1 and revival / death chains above it
     begin(S_LVC);
     launch_set_add_mapped(ref(S_LVC), sets[S_RSET].list, nRset, oldpar, nullptr, st);
@@ -994,11 +998,10 @@ struct Engine {
     launch_alive_list(n, V.alive, ref(S_TMP), st);
     sync_read();
     const uint32_t na = count(S_TMP);
-    CsrRef in = directed ? V.in.ref : V.out.ref;
-    const uint64_t T = tuple_offsets(sets[S_TMP].list, na, V.out.ref, in, nullptr, 0, 0);
-    SetRef none{};
-    launch_tuples_at(sets[S_TMP].list, na, V.out.ref, in, directed, V.par, nullptr, nullptr, 0, 0, toffs, tk0, tv0,
-                     none, st);
+    const uint64_t T = tuple_offsets(S_TMP, na, V.out.ref, CsrRef{}, nullptr, 0, 0);
+    if (na)
+      launch_tuples_gen(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], na, it_off, V.out.ref, CsrRef{}, V.par,
+                        nullptr, nullptr, 0, 0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, st);
     const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
     hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));

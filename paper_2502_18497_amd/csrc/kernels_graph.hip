@@ -39,6 +39,25 @@ __device__ __forceinline__ uint32_t rank_in_wave(bool pred) {
   return (uint32_t)__popcll(below);
 }
 
+// rank of the calling thread among the block's threads with `pred` (thread order) and their
+// total; every thread of the block calls it (lds: one word per wavefront)
+__device__ __forceinline__ uint32_t block_rank(bool pred, uint32_t* lds, uint32_t& total) {
+  const uint64_t m = __ballot(pred);
+  const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) lds[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+    const uint32_t c = lds[i];
+    if (i < w) before += c;
+    tot += c;
+  }
+  total = tot;
+  return before + r;
+}
+
 // ------------------------------------------------------------------ generic helpers
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n) {
@@ -70,189 +89,14 @@ __global__ void k_set_add_mapped(SetRef set, const uint32_t* list, uint32_t coun
     else set_claim(set.stamp, set.epoch, k);
   }
 }
-__global__ void k_members(SetRef set, uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* mark,
-                          uint32_t ep) {
-  for (uint64_t u = gtid(); u < n; u += gstride()) {
-    if (!alive[u]) continue;
-    if (mark[key[u]] == ep) set_add(set.stamp, set.epoch, set.list, set.count, (uint32_t)u);
-  }
-}
-
-// wave per listed vertex: the vertex and every out/in neighbour join the set
-__global__ void k_neighbours(SetRef set, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in, int directed) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < count; i += gwstride()) {
-    const uint32_t v = list[i];
-    if (lane == 0) set_add(set.stamp, set.epoch, set.list, set.count, v);
-    const uint64_t o = out.off[v];
-    const uint32_t d = out.deg[v];
-    for (uint32_t j = lane; j < d; j += kWave) set_add(set.stamp, set.epoch, set.list, set.count, out.nbr[o + j]);
-    if (directed) {
-      const uint64_t oi = in.off[v];
-      const uint32_t di = in.deg[v];
-      for (uint32_t j = lane; j < di; j += kWave) set_add(set.stamp, set.epoch, set.list, set.count, in.nbr[oi + j]);
-    }
-  }
-}
-
-// ------------------------------------------------------------------ dynamic CSR
-
-// wave per record: locate col in row; update in place, tombstone (w = 0) on a zero result,
-// or flag an insertion.  Rows that lose or gain entries join `dirty`.
-__global__ void k_csr_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, uint8_t* insflag,
-                           uint32_t* rowdel, uint32_t* rowins, SetRef dirty) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < k; i += gwstride()) {
-    const int64_t d = delta[i];
-    if (d == 0) {
-      if (lane == 0) insflag[i] = 0;
-      continue;
-    }
-    const uint32_t row = (uint32_t)(keys[i] >> 32), col = (uint32_t)keys[i];
-    const uint64_t o = c.off[row];
-    const uint32_t deg = c.deg[row];
-    int64_t slot = -1;
-    for (uint32_t base = 0; base < deg; base += kWave) {
-      const uint32_t j = base + lane;
-      const bool hit = j < deg && c.nbr[o + j] == col;
-      const uint64_t m = __ballot(hit);
-      if (m) {
-        slot = (int64_t)(o + base + (uint32_t)__ffsll((long long)m) - 1);
-        break;
-      }
-    }
-    if (lane == 0) {
-      if (slot >= 0) {
-        const int64_t nw = wget(c, (uint64_t)slot) + d;
-        wset(c, (uint64_t)slot, nw);
-        insflag[i] = 0;
-        if (nw == 0) {
-          atomicAdd(&rowdel[row], 1u);
-          set_add(dirty.stamp, dirty.epoch, dirty.list, dirty.count, row);
-        }
-      } else {
-        insflag[i] = 1;
-        atomicAdd(&rowins[row], 1u);
-        set_add(dirty.stamp, dirty.epoch, dirty.list, dirty.count, row);
-      }
-    }
-  }
-}
-
 // Row segments of sorted record keys: one entry (first record index) per distinct row.
-__global__ void k_segments(const uint64_t* keys, uint64_t k, uint64_t* seg_lo, uint32_t* nseg) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const bool head = i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32);
-    const uint32_t at = wave_reserve(nseg, head);
-    if (head) seg_lo[at] = i;
-  }
-}
-
 __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key);
 
-// Workgroup per row segment: the segment's records (up to 2048 at a time) go into an LDS
-// hash table keyed by column, then the row is streamed once and every entry probes the
-// table, so the cost is O(degree + records) per row.
-// MODE 0: write the slot (or -1) of every record.  MODE 1: apply the deltas in place
-// (a zero result leaves a w = 0 tombstone), flag insertions, count per-row deletions and
-// insertions and collect the rows that change shape in `dirty`.
+// ---- row lookup of sorted records.  The records of one row (a segment, up to 2048 at a
+// time) go into an LDS hash table keyed by column and the row is streamed once, each entry
+// probing the table: O(degree + records) per row.  Work items are (segment, record chunk,
+// row slice) so a huge row is streamed by many workgroups.
 constexpr int kSegChunk = 2048;
-template <int MODE>
-__global__ __launch_bounds__(256) void k_seg_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k,
-                                                  const uint64_t* seg_lo, const uint32_t* nseg_ptr, int64_t* slot_out,
-                                                  uint8_t* insflag, uint32_t* rowdel, uint32_t* rowins,
-                                                  SetRef dirty) {
-  __shared__ uint32_t tkey[2 * kSegChunk];
-  __shared__ uint32_t tval[2 * kSegChunk];
-  __shared__ int64_t sslot[kSegChunk];
-  __shared__ uint64_t s_hi;
-  __shared__ uint32_t s_cnt[2];
-  const uint32_t nseg = *nseg_ptr;
-  for (uint32_t seg = blockIdx.x; seg < nseg; seg += gridDim.x) {
-    const uint64_t lo = seg_lo[seg];
-    const uint32_t row = (uint32_t)(keys[lo] >> 32);
-    if (threadIdx.x == 0) {
-      s_hi = lower_bound_u64(keys, k, ((uint64_t)row + 1) << 32);
-      s_cnt[0] = 0;
-      s_cnt[1] = 0;
-    }
-    __syncthreads();
-    const uint64_t hi = s_hi;
-    const uint64_t off = c.off[row];
-    const uint32_t deg = c.deg[row];
-    uint32_t ndel = 0, nins = 0;
-    for (uint64_t clo = lo; clo < hi; clo += kSegChunk) {
-      const uint32_t kk = (uint32_t)((hi - clo) < (uint64_t)kSegChunk ? (hi - clo) : (uint64_t)kSegChunk);
-      uint32_t size = 64;
-      while (size < 2 * kk) size <<= 1;
-      const uint32_t mask = size - 1;
-      for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
-      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) sslot[i] = -1;
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
-        const uint32_t col = (uint32_t)keys[clo + i];
-        uint32_t h = hash32(col) & mask;
-        for (;;) {
-          const uint32_t prev = atomicCAS(&tkey[h], kEmpty, col);
-          if (prev == kEmpty) {
-            tval[h] = i;
-            break;
-          }
-          h = (h + 1) & mask;
-        }
-      }
-      __syncthreads();
-      for (uint32_t j = threadIdx.x; j < deg; j += blockDim.x) {
-        const uint32_t x = c.nbr[off + j];
-        uint32_t h = hash32(x) & mask;
-        for (;;) {
-          const uint32_t kx = tkey[h];
-          if (kx == kEmpty) break;
-          if (kx == x) {
-            sslot[tval[h]] = (int64_t)(off + j);
-            break;
-          }
-          h = (h + 1) & mask;
-        }
-      }
-      __syncthreads();
-      for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
-        const int64_t sl = sslot[i];
-        if (MODE == 0) {
-          slot_out[clo + i] = sl;
-        } else {
-          const int64_t d = delta[clo + i];
-          if (d == 0) {
-            insflag[clo + i] = 0;
-          } else if (sl >= 0) {
-            const int64_t nw = wget(c, (uint64_t)sl) + d;
-            wset(c, (uint64_t)sl, nw);
-            insflag[clo + i] = 0;
-            if (nw == 0) ++ndel;
-          } else {
-            insflag[clo + i] = 1;
-            ++nins;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    if (MODE == 1) {
-      if (ndel) atomicAdd(&s_cnt[0], ndel);
-      if (nins) atomicAdd(&s_cnt[1], nins);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        rowdel[row] = s_cnt[0];
-        rowins[row] = s_cnt[1];
-        if (s_cnt[0] + s_cnt[1]) dirty.list[atomicAdd(dirty.count, 1u)] = row;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ---- row-segment lookup split into (segment, record chunk, row slice) work items, so a
-// huge row is streamed by many workgroups and a row with many records by several tables.
 constexpr uint32_t kSlice = 16384;
 
 __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo,
@@ -265,7 +109,7 @@ __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const ui
     }
     const uint64_t lo = seg_lo[s];
     const uint32_t row = (uint32_t)(keys[lo] >> 32);
-    const uint64_t hi = lower_bound_u64(keys, k, ((uint64_t)row + 1) << 32);
+    const uint64_t hi = s + 1 < nseg ? seg_lo[s + 1] : k;   // heads are selected in key order
     seg_hi[s] = hi;
     const uint64_t deg = c.deg[row];
     const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
@@ -342,59 +186,205 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
   }
 }
 
-// workgroup per segment: apply the row's deltas at the looked-up slots (a zero result leaves a
-// w = 0 tombstone), flag insertions, count deletions / insertions, add the row's delta sum to
-// its degree (when deg != null) and collect rows that change shape in `dirty`
-__global__ __launch_bounds__(256) void k_seg_apply(CsrRef c, const uint64_t* keys, const int64_t* delta,
-                                                   const uint64_t* seg_lo, const uint64_t* seg_hi,
-                                                   const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* insflag,
-                                                   uint32_t* rowdel, uint32_t* rowins, int64_t* deg_arr,
-                                                   uint32_t* dirty_list, uint32_t* dirty_count) {
-  __shared__ int64_t red[3 * 4];
+// ---- in-place row update, O(records + deletions) per row.  Workgroup per segment (one row's
+// records): apply every delta at its looked-up slot; a weight that reaches 0 is a deletion, a
+// record without a slot an insertion.  When the new degree fits the row's capacity the row is
+// repaired in place: with t0 = deg - ndel, the surviving entries among the last ndel slots
+// move into the deletion holes below t0 (the two counts are equal), and insertions are
+// written from t0 on.  Entry order within a row carries no meaning.  Rows that outgrow their
+// capacity are listed for k_seg_move.
+constexpr uint8_t kRecNone = 0, kRecUpd = 1, kRecDel = 2, kRecIns = 3;
+
+__global__ __launch_bounds__(kTpb) void k_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta,
+                                                     const uint64_t* seg_lo, const uint64_t* seg_hi,
+                                                     const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
+                                                     uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel,
+                                                     uint32_t* rowins, uint32_t* move_list, uint32_t* move_count) {
+  __shared__ int64_t red[3 * (kTpb / kWave)];
+  __shared__ uint32_t lds[kTpb / kWave];
   const uint32_t nseg = *nseg_ptr;
   for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
     const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint64_t off = c.off[row];
+    const uint32_t deg = c.deg[row];
+    const uint32_t cap = c.cap[row];
     int64_t ndel = 0, nins = 0, dsum = 0;
     for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
       const int64_t d = delta[i];
       const int64_t sl = slot[i];
       dsum += d;
-      if (d == 0) {
-        insflag[i] = 0;
-      } else if (sl >= 0) {
-        const int64_t nw = wget(c, (uint64_t)sl) + d;
-        wset(c, (uint64_t)sl, nw);
-        insflag[i] = 0;
-        if (nw == 0) ++ndel;
-      } else {
-        insflag[i] = 1;
-        ++nins;
+      uint8_t t = kRecNone;
+      if (d != 0) {
+        if (sl >= 0) {
+          const int64_t nw = wget(c, (uint64_t)sl) + d;
+          wset(c, (uint64_t)sl, nw);
+          t = nw == 0 ? kRecDel : kRecUpd;
+          if (nw == 0) ++ndel;
+        } else {
+          t = kRecIns;
+          ++nins;
+        }
       }
+      rtype[i] = t;
     }
     ndel = wave_sum_i64(ndel);
     nins = wave_sum_i64(nins);
     dsum = wave_sum_i64(dsum);
     const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & 63) == 0) {
+    __syncthreads();
+    if (lane_id() == 0) {
       red[3 * w] = ndel;
       red[3 * w + 1] = nins;
       red[3 * w + 2] = dsum;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t a = 0, b = 0, d = 0;
-      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-        a += red[3 * i];
-        b += red[3 * i + 1];
-        d += red[3 * i + 2];
+    ndel = nins = dsum = 0;
+    for (int q = 0; q < (int)(blockDim.x / kWave); ++q) {
+      ndel += red[3 * q];
+      nins += red[3 * q + 1];
+      dsum += red[3 * q + 2];
+    }
+    if (threadIdx.x == 0 && deg_arr && dsum) deg_arr[row] += dsum;
+    if (ndel + nins == 0) continue;                       // uniform over the workgroup
+    const uint64_t ndeg = (uint64_t)deg - (uint64_t)ndel + (uint64_t)nins;
+    if (ndeg > cap) {
+      if (threadIdx.x == 0) {
+        rowdel[row] = (uint32_t)ndel;
+        rowins[row] = (uint32_t)nins;
+        move_list[atomicAdd(move_count, 1u)] = sg;
       }
-      rowdel[row] = (uint32_t)a;
-      rowins[row] = (uint32_t)b;
-      if (deg_arr) deg_arr[row] += d;
-      if (a + b) dirty_list[atomicAdd(dirty_count, 1u)] = row;
+      continue;
+    }
+    const uint32_t t0 = deg - (uint32_t)ndel;
+    // holes below t0, in record order (at most ndel <= hi - lo of them)
+    uint32_t nh = 0;
+    for (uint64_t b = lo; b < hi; b += blockDim.x) {
+      const uint64_t i = b + threadIdx.x;
+      bool f = false;
+      uint64_t sl = 0;
+      if (i < hi && rtype[i] == kRecDel) {
+        sl = (uint64_t)slot[i];
+        f = sl - off < t0;
+      }
+      uint32_t tot;
+      const uint32_t r = block_rank(f, lds, tot);
+      if (f) hole[lo + nh + r] = sl;
+      nh += tot;
     }
     __syncthreads();
+    // survivors among the last ndel slots fill the holes
+    uint32_t ns = 0;
+    for (uint32_t b = t0; b < deg; b += blockDim.x) {
+      const uint32_t p = b + threadIdx.x;
+      bool f = false;
+      uint32_t x = 0;
+      int64_t wv = 0;
+      if (p < deg) {
+        wv = wget(c, off + p);
+        f = wv != 0;
+        if (f) x = c.nbr[off + p];
+      }
+      uint32_t tot;
+      const uint32_t r = block_rank(f, lds, tot);
+      if (f && ns + r < nh) {
+        const uint64_t dst = hole[lo + ns + r];
+        c.nbr[dst] = x;
+        wset(c, dst, wv);
+      }
+      ns += tot;
+    }
+    __syncthreads();
+    // insertions from t0 on
+    uint32_t ni = 0;
+    for (uint64_t b = lo; b < hi; b += blockDim.x) {
+      const uint64_t i = b + threadIdx.x;
+      const bool f = i < hi && rtype[i] == kRecIns;
+      uint32_t tot;
+      const uint32_t r = block_rank(f, lds, tot);
+      if (f) {
+        const uint64_t dst = off + t0 + ni + r;
+        c.nbr[dst] = (uint32_t)keys[i];
+        wset(c, dst, delta[i]);
+      }
+      ni += tot;
+    }
+    if (threadIdx.x == 0) c.deg[row] = (uint32_t)ndeg;
+    __syncthreads();
+  }
+}
+
+// workgroup per listed row: a region of 1.25x its new degree is taken from the pool, the
+// surviving entries and the insertions are copied there.  A row that finds the pool full
+// stays listed (the caller grows the pool and launches again); done entries become kEmpty.
+__global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta,
+                                                   const uint64_t* seg_lo, const uint64_t* seg_hi, const uint8_t* rtype,
+                                                   const uint32_t* rowdel, const uint32_t* rowins, uint32_t* move_list,
+                                                   const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
+                                                   uint32_t* overflow) {
+  __shared__ uint32_t lds[kTpb / kWave];
+  __shared__ uint64_t s_dst;
+  const uint32_t nm = *move_count;
+  for (uint32_t j = blockIdx.x; j < nm; j += gridDim.x) {
+    const uint32_t sg = move_list[j];
+    if (sg == kEmpty) continue;
+    const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint64_t src = c.off[row];
+    const uint32_t deg = c.deg[row];
+    const uint64_t ndeg = (uint64_t)deg - rowdel[row] + rowins[row];
+    uint64_t nc = ndeg + (ndeg >> 2);
+    if (nc < ndeg + 4) nc = ndeg + 4;
+    if (nc > 0xFFFFFFFFull) nc = 0xFFFFFFFFull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const u64a o = atomicAdd(pool_top, (u64a)nc);
+      if (o + nc > pool_cap) {
+        atomicOr(overflow, 1u);
+        s_dst = ~0ull;
+      } else {
+        s_dst = o;
+      }
+    }
+    __syncthreads();
+    const uint64_t dst = s_dst;
+    if (dst == ~0ull) continue;
+    uint32_t written = 0;
+    for (uint32_t b = 0; b < deg; b += blockDim.x) {
+      const uint32_t p = b + threadIdx.x;
+      bool f = false;
+      uint32_t x = 0;
+      int64_t wv = 0;
+      if (p < deg) {
+        wv = wget(c, src + p);
+        f = wv != 0;
+        if (f) x = c.nbr[src + p];
+      }
+      uint32_t tot;
+      const uint32_t r = block_rank(f, lds, tot);
+      if (f) {
+        c.nbr[dst + written + r] = x;
+        wset(c, dst + written + r, wv);
+      }
+      written += tot;
+    }
+    for (uint64_t b = lo; b < hi; b += blockDim.x) {
+      const uint64_t i = b + threadIdx.x;
+      const bool f = i < hi && rtype[i] == kRecIns;
+      uint32_t tot;
+      const uint32_t r = block_rank(f, lds, tot);
+      if (f) {
+        c.nbr[dst + written + r] = (uint32_t)keys[i];
+        wset(c, dst + written + r, delta[i]);
+      }
+      written += tot;
+    }
+    if (threadIdx.x == 0) {
+      c.off[row] = dst;
+      c.cap[row] = (uint32_t)nc;
+      c.deg[row] = written;
+      move_list[j] = kEmpty;
+    }
   }
 }
 
@@ -437,32 +427,6 @@ __global__ void k_ingest_validate(CsrRef out0, const uint64_t* keys, const uint3
   }
 }
 
-__global__ void k_csr_plan(CsrRef c, const uint32_t* dirty, uint32_t nd, const uint32_t* rowdel,
-                           const uint32_t* rowins, uint64_t* plan_off, uint32_t* plan_cap, u64a* pool_top,
-                           uint64_t pool_cap, uint32_t* overflow) {
-  for (uint64_t j = gtid(); j < nd; j += gstride()) {
-    const uint32_t row = dirty[j];
-    const uint64_t need = (uint64_t)c.deg[row] - rowdel[row] + rowins[row];
-    if (need <= c.cap[row]) {
-      plan_off[j] = c.off[row];
-      plan_cap[j] = c.cap[row];
-      continue;
-    }
-    uint64_t nc = need + (need >> 2);
-    if (nc < need + 4) nc = need + 4;
-    if (nc > 0xFFFFFFFFull) nc = 0xFFFFFFFFull;
-    const u64a o = atomicAdd(pool_top, (u64a)nc);
-    if (o + nc > pool_cap) {
-      atomicOr(overflow, 1u);
-      plan_off[j] = ~0ull;
-      plan_cap[j] = 0;
-    } else {
-      plan_off[j] = o;
-      plan_cap[j] = (uint32_t)nc;
-    }
-  }
-}
-
 __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key) {
   uint64_t lo = 0, hi = n;
   while (lo < hi) {
@@ -471,70 +435,6 @@ __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key)
     else hi = mid;
   }
   return lo;
-}
-
-// wave per dirty row: compact survivors (w != 0) to the planned location, then append the
-// row's flagged insertions (records of the row are contiguous in the sorted keys)
-__global__ void k_csr_rewrite(CsrRef c, const uint32_t* dirty, uint32_t nd, uint32_t* rowdel, uint32_t* rowins,
-                              const uint64_t* plan_off, const uint32_t* plan_cap, const uint64_t* keys,
-                              const int64_t* delta, const uint8_t* insflag, uint64_t k) {
-  const int lane = lane_id();
-  for (uint64_t j = gwave(); j < nd; j += gwstride()) {
-    const uint32_t row = dirty[j];
-    const uint64_t src = c.off[row];
-    const uint32_t deg = c.deg[row];
-    const uint64_t dst = plan_off[j];
-    uint32_t written = 0;
-    for (uint32_t base = 0; base < deg; base += kWave) {
-      const uint32_t i = base + lane;
-      uint32_t nb = 0;
-      int64_t w = 0;
-      if (i < deg) {
-        nb = c.nbr[src + i];
-        w = wget(c, src + i);
-      }
-      const bool keep = i < deg && w != 0;
-      const uint32_t r = rank_in_wave(keep);
-      const uint32_t tot = (uint32_t)__popcll(__ballot(keep));
-      // every lane has read its element before any lane writes (writes land at or below reads)
-      __builtin_amdgcn_wave_barrier();
-      if (keep) {
-        c.nbr[dst + written + r] = nb;
-        wset(c, dst + written + r, w);
-      }
-      __builtin_amdgcn_wave_barrier();
-      written += tot;
-    }
-    const uint64_t lo = lower_bound_u64(keys, k, (uint64_t)row << 32);
-    const uint64_t hi = lower_bound_u64(keys, k, ((uint64_t)row + 1) << 32);
-    for (uint64_t base = lo; base < hi; base += kWave) {
-      const uint64_t i = base + lane;
-      const bool ins = i < hi && insflag[i];
-      const uint32_t r = rank_in_wave(ins);
-      const uint32_t tot = (uint32_t)__popcll(__ballot(ins));
-      if (ins) {
-        c.nbr[dst + written + r] = (uint32_t)keys[i];
-        wset(c, dst + written + r, delta[i]);
-      }
-      written += tot;
-    }
-    if (lane == 0) {
-      c.off[row] = dst;
-      c.cap[row] = plan_cap[j];
-      c.deg[row] = written;
-      rowdel[row] = 0;
-      rowins[row] = 0;
-    }
-  }
-}
-
-__global__ void k_csr_degrees(int64_t* kout, int64_t* kin, const uint64_t* keys, const int64_t* delta, uint64_t k) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const int64_t d = delta[i];
-    if (d == 0) continue;
-    atomic_add_i64(&kout[keys[i] >> 32], d);
-    if (kin) atomic_add_i64(&kin[(uint32_t)keys[i]], d);
-  }
 }
 
 __global__ void k_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n) {
@@ -609,54 +509,6 @@ __global__ void k_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_
   }
 }
 
-// wave per sorted record: duplicate check, existing weight, delta and validation
-__global__ void k_ingest_check(CsrRef out0, const uint64_t* keys, const uint32_t* idx, uint64_t k,
-                               const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd,
-                               const uint32_t* chg, int directed, int64_t* delta, uint32_t* err,
-                               uint32_t* first_bad, i64a* dm) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < k; i += gwstride()) {
-    const uint64_t key = keys[i];
-    if (lane == 0 && i > 0 && keys[i - 1] == key) atomicOr(err, 2u);
-    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
-    const uint64_t o = out0.off[u];
-    const uint32_t deg = out0.deg[u];
-    int64_t slot = -1;
-    for (uint32_t base = 0; base < deg; base += kWave) {
-      const uint32_t j = base + lane;
-      const bool hit = j < deg && out0.nbr[o + j] == v;
-      const uint64_t m = __ballot(hit);
-      if (m) {
-        slot = (int64_t)(o + base + (uint32_t)__ffsll((long long)m) - 1);
-        break;
-      }
-    }
-    if (lane != 0) continue;
-    const uint32_t src = idx[i];
-    const int64_t old = slot >= 0 ? (int64_t)((const uint32_t*)out0.w)[slot] : 0;
-    int64_t d = 0;
-    bool bad = false;
-    if (src < ni) {
-      const int64_t w = ins[3 * (uint64_t)src + 2];
-      if (old + w > 0xFFFFFFFFll) { bad = true; atomicOr(err, 8u); }
-      d = w;
-    } else if (src < ni + nd) {
-      if (slot < 0) { bad = true; atomicOr(err, 4u); }
-      d = -old;
-    } else {
-      const int64_t w = chg[3 * ((uint64_t)src - ni - nd) + 2];
-      if (slot < 0) { bad = true; atomicOr(err, 4u); }
-      d = w - old;
-    }
-    if (bad) {
-      atomicMin(first_bad, src);
-      d = 0;
-    }
-    delta[i] = d;
-    if (d != 0) atomicAdd((u64a*)dm, (u64a)((!directed && u != v) ? 2 * d : d));
-  }
-}
-
 __global__ void k_ingest_entries(const uint64_t* keys, const int64_t* delta, uint64_t k, int directed,
                                  uint64_t* ekeys, int64_t* edelta, u64a* count) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
@@ -707,13 +559,16 @@ __global__ void k_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, ui
   }
 }
 
-__global__ void k_dskk(const uint32_t* touched, uint32_t nt, const int64_t* Kout, const int64_t* Kin,
+__global__ void k_dskk(const uint32_t* touched, const uint32_t* nt_ptr, const int64_t* Kout, const int64_t* Kin,
                        const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi) {
+  const uint32_t nt = *nt_ptr;
+  i128 d = 0;
   for (uint64_t t = gtid(); t < nt; t += gstride()) {
     const uint32_t c = touched[t];
-    const i128 d = (i128)Kout[c] * Kin[c] - (i128)tko[t] * tki[t];
-    if (d != 0) atomic_add_i128(lo, hi, d);
+    d += (i128)Kout[c] * Kin[c] - (i128)tko[t] * tki[t];
   }
+  d = wave_sum_i128(d);   // every lane of the wave is active here
+  if ((threadIdx.x & (kWave - 1)) == 0 && d != 0) atomic_add_i128(lo, hi, d);
 }
 
 __global__ void k_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
@@ -770,118 +625,6 @@ __global__ void k_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint3
       atomic_add_i64(&Krout[u], kout[u]);
       if (Krin) atomic_add_i64(&Krin[u], kin[u]);
       atomicAdd(&rsize[u], 1u);
-    }
-  }
-}
-
-// ------------------------------------------------------------------ aggregate repair
-
-__global__ void k_changed(const uint32_t* rset, uint32_t nr, const uint32_t* par, const uint32_t* oldpar,
-                          SetRef C) {
-  for (uint64_t i = gtid(); i < nr; i += gstride()) {
-    const uint32_t u = rset[i];
-    if (par[u] != oldpar[u]) set_add(C.stamp, C.epoch, C.list, C.count, u);
-  }
-}
-
-__global__ void k_tuple_count(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, u64a* total) {
-  u64a local = 0;
-  for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const uint32_t u = list[i];
-    local += 2ull * ((u64a)out.deg[u] + (directed ? (u64a)in.deg[u] : (u64a)out.deg[u]));
-  }
-  if (local) atomicAdd(total, local);
-}
-
-// wave per node.  repair == 0 (materialise): one tuple (par(u), par(v), w) per out-entry.
-// repair == 1: for u in C, each matrix entry incident to u once: (oldpar, oldpar, -w) and
-// (par, par, +w); entries whose other end is also in C are taken from the out side only.
-__global__ void k_tuples(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* par,
-                         const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep, int repair, uint64_t* tkeys,
-                         int64_t* tvals, u64a* tcount, uint64_t tcap, SetRef seeds) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < k; i += gwstride()) {
-    const uint32_t u = list[i];
-    const uint32_t pu = par[u];
-    const uint32_t ou = repair ? oldpar[u] : pu;
-    // out side
-    {
-      const uint64_t o = out.off[u];
-      const uint32_t d = out.deg[u];
-      for (uint32_t base = 0; base < d; base += kWave) {
-        const uint32_t j = base + lane;
-        const bool act = j < d;
-        uint32_t v = 0;
-        int64_t w = 0;
-        if (act) {
-          v = out.nbr[o + j];
-          w = wget(out, o + j);
-        }
-        const uint32_t per = repair ? 2u : 1u;
-        const uint32_t r = rank_in_wave(act);
-        const uint32_t tot = (uint32_t)__popcll(__ballot(act));
-        u64a at = 0;
-        if (lane == 0 && tot) at = atomicAdd(tcount, (u64a)tot * per);
-        at = __shfl(at, 0, kWave);
-        if (act) {
-          const uint32_t pv = par[v];
-          const uint64_t pos = at + (u64a)r * per;
-          if (!repair) {
-            if (pos < tcap) {
-              tkeys[pos] = ((uint64_t)pu << 32) | pv;
-              tvals[pos] = w;
-            }
-          } else {
-            const uint32_t ov = cstamp[v] == cep ? oldpar[v] : pv;
-            if (pos + 1 < tcap) {
-              tkeys[pos] = ((uint64_t)ou << 32) | ov;
-              tvals[pos] = -w;
-              tkeys[pos + 1] = ((uint64_t)pu << 32) | pv;
-              tvals[pos + 1] = w;
-            }
-            set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ov);
-            set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pv);
-          }
-        }
-      }
-    }
-    if (!repair) continue;
-    if (lane == 0) {
-      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ou);
-      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pu);
-    }
-    // in side: entries (v, u) with v outside C
-    {
-      const CsrRef& c = directed ? in : out;
-      const uint64_t o = c.off[u];
-      const uint32_t d = c.deg[u];
-      for (uint32_t base = 0; base < d; base += kWave) {
-        const uint32_t j = base + lane;
-        bool act = j < d;
-        uint32_t v = 0;
-        int64_t w = 0;
-        if (act) {
-          v = c.nbr[o + j];
-          w = wget(c, o + j);
-          if (cstamp[v] == cep) act = false;
-        }
-        const uint32_t r = rank_in_wave(act);
-        const uint32_t tot = (uint32_t)__popcll(__ballot(act));
-        u64a at = 0;
-        if (lane == 0 && tot) at = atomicAdd(tcount, (u64a)tot * 2);
-        at = __shfl(at, 0, kWave);
-        if (act) {
-          const uint32_t pv = par[v];
-          const uint64_t pos = at + (u64a)r * 2;
-          if (pos + 1 < tcap) {
-            tkeys[pos] = ((uint64_t)pv << 32) | ou;
-            tvals[pos] = -w;
-            tkeys[pos + 1] = ((uint64_t)pv << 32) | pu;
-            tvals[pos + 1] = w;
-          }
-          set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pv);
-        }
-      }
     }
   }
 }
@@ -975,23 +718,6 @@ __global__ void k_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const u
 }
 
 // wave per listed vertex; plain stores (every writer stores the same epoch)
-__global__ void k_mark_neighbours(uint32_t* stamp, uint32_t ep, const uint32_t* list, uint32_t count, CsrRef out,
-                                  CsrRef in, int directed) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < count; i += gwstride()) {
-    const uint32_t v = list[i];
-    if (lane == 0) stamp[v] = ep;
-    const uint64_t o = out.off[v];
-    const uint32_t d = out.deg[v];
-    for (uint32_t j = lane; j < d; j += kWave) stamp[out.nbr[o + j]] = ep;
-    if (directed) {
-      const uint64_t oi = in.off[v];
-      const uint32_t di = in.deg[v];
-      for (uint32_t j = lane; j < di; j += kWave) stamp[in.nbr[oi + j]] = ep;
-    }
-  }
-}
-
 __global__ void k_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
                                const uint32_t* oldpar) {
   for (uint64_t i = gtid(); i < nr; i += gstride()) {
@@ -1002,90 +728,177 @@ __global__ void k_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rse
 
 // number of tuples node u emits (materialise: its out-entries; repair: twice its out-entries
 // plus twice its in-side entries whose other end is outside C)
-__global__ void k_tuple_counts(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed,
-                               const uint32_t* cstamp, uint32_t cep, int repair, uint64_t* counts) {
-  const int lane = lane_id();
-  for (uint64_t i = gwave(); i < k; i += gwstride()) {
-    const uint32_t u = list[i];
-    const uint32_t dout = out.deg[u];
-    if (!repair) {
-      if (lane == 0) counts[i] = dout;
-      continue;
-    }
-    const CsrRef& c = directed ? in : out;
-    const uint64_t o = c.off[u];
-    const uint32_t d = c.deg[u];
-    int64_t outside = 0;
-    for (uint32_t j = lane; j < d; j += kWave) outside += cstamp[c.nbr[o + j]] != cep ? 1 : 0;
-    outside = wave_sum_i64(outside);
-    if (lane == 0) counts[i] = 2ull * dout + 2ull * (uint64_t)outside;
+// ---- node lists split into wavefront items.  Node i of a list has s_i entries, its out
+// entries followed by its in entries (when in.off is set); it is split into ceil(s_i / kItem)
+// items and ioff is the exclusive prefix of the item counts.  Every wavefront takes a
+// contiguous range of items (one binary search, then a linear walk), so a hub node is spread
+// over many wavefronts and a run of small nodes over few.
+__device__ __forceinline__ uint64_t node_slots(const CsrRef& out, const CsrRef& in, uint32_t u) {
+  return (uint64_t)out.deg[u] + (in.off ? (uint64_t)in.deg[u] : 0ull);
+}
+
+// entry j of node u (out entries first)
+__device__ __forceinline__ void node_entry(const CsrRef& out, const CsrRef& in, uint32_t u, uint32_t dout, uint64_t j,
+                                           uint32_t& x, int64_t& w) {
+  if (j < dout) {
+    const uint64_t e = out.off[u] + j;
+    x = out.nbr[e];
+    w = wget(out, e);
+  } else {
+    const uint64_t e = in.off[u] + (j - dout);
+    x = in.nbr[e];
+    w = wget(in, e);
   }
 }
 
-// tuples of node list[i] written from offs[i] on, in entry order (see k_tuples)
-__global__ void k_tuples_at(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed,
-                            const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
-                            int repair, const uint64_t* offs, uint64_t* tkeys, int64_t* tvals, SetRef seeds) {
+__global__ void k_item_counts(const uint32_t* list, const uint32_t* countp, uint32_t bound, CsrRef out, CsrRef in,
+                              uint64_t* icnt, uint64_t* zero_a, uint64_t* zero_b) {
+  const uint32_t c0 = *countp;
+  const uint32_t cnt = c0 < bound ? c0 : bound;
+  for (uint64_t i = gtid(); i <= bound; i += gstride()) {
+    uint64_t c = 0;
+    if (i < cnt) c = (node_slots(out, in, list[i]) + kItem - 1) / kItem;
+    icnt[i] = c;
+    if (zero_a) zero_a[i] = 0;
+    if (zero_b) zero_b[i] = 0;
+  }
+}
+
+// f(i, q): item q of list node i; called with the whole wavefront
+template <class F>
+__device__ __forceinline__ void wave_items(const uint64_t* ioff, uint32_t cnt, F&& f) {
+  const uint64_t total = ioff[cnt];
+  const uint64_t W = gwstride();
+  const uint64_t per = (total + W - 1) / W;
+  uint64_t it = gwave() * per;
+  const uint64_t end = it + per < total ? it + per : total;
+  if (it >= end) return;
+  uint32_t lo = 0, hi = cnt;   // ioff[lo] <= it < ioff[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (ioff[mid] <= it) lo = mid;
+    else hi = mid;
+  }
+  uint32_t i = lo;
+  for (; it < end; ++it) {
+    while (ioff[i + 1] <= it) ++i;
+    f(i, it - ioff[i]);
+  }
+}
+
+// stamp[x] = ep for every listed node and each of its entries' neighbours
+__global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* countp, uint32_t bound,
+                             const uint64_t* ioff, CsrRef out, CsrRef in) {
   const int lane = lane_id();
-  for (uint64_t i = gwave(); i < k; i += gwstride()) {
+  const uint32_t c0 = *countp;
+  const uint32_t cnt = c0 < bound ? c0 : bound;
+  wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
+    const uint32_t u = list[i];
+    const uint32_t dout = out.deg[u];
+    const uint64_t s = node_slots(out, in, u);
+    const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
+    if (q == 0 && lane == 0) stamp[u] = ep;
+    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+      uint32_t x;
+      int64_t w;
+      node_entry(out, in, u, dout, j, x, w);
+      stamp[x] = ep;
+    }
+  });
+}
+
+// Subtract-add tuples of Eq. 3.  Materialise (REPAIR false): (P(u), P(x), w) for every out entry.
+// Repair over the changed nodes C (cstamp == cep): for an out entry (u, x) of u in C, the
+// old pair (oldpar u, oldpar x) loses w and the new pair (par u, par x) gains it (x outside C
+// keeps its parent); for an in entry (v, u) with v outside C, (par v, oldpar u) loses w and
+// (par v, par u) gains it (entries between two C nodes come from the out side).  Node i's
+// tuples start at toffs[i]: out tuples in entry order, then in tuples at a per-node cursor.
+template <bool REPAIR>
+__global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
+                               CsrRef out, CsrRef in, const uint32_t* cstamp, uint32_t cep, u64a* counts) {
+  const int lane = lane_id();
+  const uint32_t c0 = *countp;
+  const uint32_t cnt = c0 < bound ? c0 : bound;
+  wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
+    const uint32_t u = list[i];
+    const uint32_t dout = out.deg[u];
+    const uint64_t s = node_slots(out, in, u);
+    const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
+    int64_t c = 0;
+    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+      if (j < dout) c += REPAIR ? 2 : 1;
+      else if (cstamp[in.nbr[in.off[u] + (j - dout)]] != cep) c += 2;
+    }
+    c = wave_sum_i64(c);
+    if (lane == 0 && c) atomicAdd(&counts[i], (u64a)c);
+  });
+}
+
+template <bool REPAIR>
+__global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
+                             CsrRef out, CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp,
+                             uint32_t cep, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
+                             uint32_t* seed_stamp, uint32_t seed_ep) {
+  const int lane = lane_id();
+  const uint32_t c0 = *countp;
+  const uint32_t cnt = c0 < bound ? c0 : bound;
+  wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
     const uint32_t u = list[i];
     const uint32_t pu = par[u];
-    const uint32_t ou = repair ? oldpar[u] : pu;
-    uint64_t pos = offs[i];
-    {
-      const uint64_t o = out.off[u];
-      const uint32_t d = out.deg[u];
-      for (uint32_t j = lane; j < d; j += kWave) {
-        const uint32_t v = out.nbr[o + j];
-        const int64_t w = wget(out, o + j);
-        const uint32_t pv = par[v];
-        if (!repair) {
-          tkeys[pos + j] = ((uint64_t)pu << 32) | pv;
-          tvals[pos + j] = w;
+    const uint32_t ou = REPAIR ? oldpar[u] : pu;
+    const uint32_t dout = out.deg[u];
+    const uint64_t s = node_slots(out, in, u);
+    const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
+    const uint64_t base = toffs[i];
+    if (REPAIR && q == 0 && lane == 0) {
+      seed_stamp[ou] = seed_ep;
+      seed_stamp[pu] = seed_ep;
+    }
+    for (uint64_t jb = j0; jb < j1; jb += kWave) {   // wavefront-uniform steps
+      const uint64_t j = jb + lane;
+      const bool valid = j < j1;
+      uint32_t x = 0;
+      int64_t w = 0;
+      if (valid) node_entry(out, in, u, dout, j, x, w);
+      if (valid && j < dout) {
+        const uint32_t px = par[x];
+        if (!REPAIR) {
+          tkeys[base + j] = ((uint64_t)pu << 32) | px;
+          tvals[base + j] = w;
         } else {
-          const uint32_t ov = cstamp[v] == cep ? oldpar[v] : pv;
-          tkeys[pos + 2 * j] = ((uint64_t)ou << 32) | ov;
-          tvals[pos + 2 * j] = -w;
-          tkeys[pos + 2 * j + 1] = ((uint64_t)pu << 32) | pv;
-          tvals[pos + 2 * j + 1] = w;
-          set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ov);
-          set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pv);
+          const uint32_t ox = cstamp[x] == cep ? oldpar[x] : px;
+          tkeys[base + 2 * j] = ((uint64_t)ou << 32) | ox;
+          tvals[base + 2 * j] = -w;
+          tkeys[base + 2 * j + 1] = ((uint64_t)pu << 32) | px;
+          tvals[base + 2 * j + 1] = w;
+          seed_stamp[ox] = seed_ep;
+          seed_stamp[px] = seed_ep;
         }
       }
-      pos += repair ? 2ull * d : (uint64_t)d;
-    }
-    if (!repair) continue;
-    if (lane == 0) {
-      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, ou);
-      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, pu);
-    }
-    const CsrRef& c = directed ? in : out;
-    const uint64_t o = c.off[u];
-    const uint32_t d = c.deg[u];
-    for (uint32_t base = 0; base < d; base += kWave) {
-      const uint32_t j = base + lane;
-      bool act = j < d;
-      uint32_t v = 0;
-      int64_t w = 0;
-      if (act) {
-        v = c.nbr[o + j];
-        w = wget(c, o + j);
-        if (cstamp[v] == cep) act = false;
+      if (REPAIR && jb + kWave > dout) {
+        const bool act = valid && j >= dout && cstamp[x] != cep;
+        const uint64_t m = __ballot(act);
+        if (m) {
+          const uint32_t tot = (uint32_t)__popcll(m);
+          const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          u64a b = 0;
+          if (lane == 0) b = atomicAdd(&cur[i], 2ull * tot);
+          const uint32_t blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+          const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+          b = ((u64a)bhi << 32) | blo;
+          if (act) {
+            const uint32_t pv = par[x];
+            const uint64_t p2 = base + 2ull * dout + b + 2ull * r;
+            tkeys[p2] = ((uint64_t)pv << 32) | ou;
+            tvals[p2] = -w;
+            tkeys[p2 + 1] = ((uint64_t)pv << 32) | pu;
+            tvals[p2 + 1] = w;
+            seed_stamp[pv] = seed_ep;
+          }
+        }
       }
-      const uint32_t r = rank_in_wave(act);
-      const uint32_t tot = (uint32_t)__popcll(__ballot(act));
-      if (act) {
-        const uint32_t pv = par[v];
-        const uint64_t p2 = pos + 2ull * r;
-        tkeys[p2] = ((uint64_t)pv << 32) | ou;
-        tvals[p2] = -w;
-        tkeys[p2 + 1] = ((uint64_t)pv << 32) | pu;
-        tvals[p2 + 1] = w;
-      }
-      set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, act ? par[v] : 0u, act);
-      pos += 2ull * tot;
     }
-  }
+  });
 }
 
 }  // namespace
@@ -1096,24 +909,34 @@ void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t
                          const uint32_t* mark, uint32_t mark_ep, hipStream_t s) {
   if (n) k_mark_members<<<grid_for(n), kTpb, 0, s>>>(stamp, ep, n, alive, key, mark, mark_ep);
 }
-void launch_mark_neighbours(uint32_t* stamp, uint32_t ep, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in,
-                            int directed, hipStream_t s) {
-  if (count) k_mark_neighbours<<<grid_waves(count), kTpb, 0, s>>>(stamp, ep, list, count, out, in, directed);
-}
 void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
                          const uint32_t* oldpar, hipStream_t s) {
   if (nr) k_mark_changed<<<grid_for(nr), kTpb, 0, s>>>(stamp, ep, rset, nr, par, oldpar);
 }
-void launch_tuple_counts(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* cstamp,
-                         uint32_t cep, int repair, uint64_t* counts, hipStream_t s) {
-  if (k) k_tuple_counts<<<grid_waves(k), kTpb, 0, s>>>(list, k, out, in, directed, cstamp, cep, repair, counts);
+int launch_items(const uint32_t* list, const uint32_t* count, uint32_t bound, CsrRef out, CsrRef in, uint64_t* icnt,
+                 uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp, size_t* tmp_bytes, hipStream_t s) {
+  k_item_counts<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(list, count, bound, out, in, icnt, zero_a, zero_b);
+  return prim_exclusive_sum_u64(tmp, tmp_bytes, icnt, ioff, (uint64_t)bound + 1, s);
 }
-void launch_tuples_at(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* par,
-                      const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep, int repair, const uint64_t* offs,
-                      uint64_t* tkeys, int64_t* tvals, SetRef seeds_or_null, hipStream_t s) {
-  if (k)
-    k_tuples_at<<<grid_waves(k), kTpb, 0, s>>>(list, k, out, in, directed, par, oldpar, cstamp, cep, repair, offs,
-                                               tkeys, tvals, seeds_or_null);
+void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
+                       const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s) {
+  k_mark_items<<<kItemBlocks, kTpb, 0, s>>>(stamp, ep, list, count, bound, ioff, out, in);
+}
+void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
+                         CsrRef in, const uint32_t* cstamp, uint32_t cep, int repair, u64a* counts, hipStream_t s) {
+  if (repair) k_tuples_count<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, cstamp, cep, counts);
+  else k_tuples_count<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, cstamp, cep, counts);
+}
+void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
+                       CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
+                       int repair, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
+                       uint32_t* seed_stamp, uint32_t seed_ep, hipStream_t s) {
+  if (repair)
+    k_tuples_gen<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
+                                                    cur, tkeys, tvals, seed_stamp, seed_ep);
+  else
+    k_tuples_gen<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
+                                                     cur, tkeys, tvals, seed_stamp, seed_ep);
 }
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n) k_fill_u32<<<grid_for(n), kTpb, 0, s>>>(p, v, n);
@@ -1137,31 +960,6 @@ void launch_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, con
                            const uint8_t* alive_or_null, hipStream_t s) {
   if (count) k_set_add_mapped<<<grid_for(count), kTpb, 0, s>>>(set, list, count, key, alive_or_null);
 }
-void launch_members(SetRef set, uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* mark,
-                    uint32_t mark_epoch, hipStream_t s) {
-  if (n) k_members<<<grid_for(n), kTpb, 0, s>>>(set, n, alive, key, mark, mark_epoch);
-}
-void launch_neighbours(SetRef set, const uint32_t* list, uint32_t count, CsrRef out, CsrRef in, int directed,
-                       hipStream_t s) {
-  if (count) k_neighbours<<<grid_waves(count), kTpb, 0, s>>>(set, list, count, out, in, directed);
-}
-void launch_csr_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, uint8_t* insflag,
-                     uint32_t* rowdel, uint32_t* rowins, SetRef dirty, hipStream_t s) {
-  if (k) k_csr_find<<<grid_waves(k), kTpb, 0, s>>>(c, keys, delta, k, insflag, rowdel, rowins, dirty);
-}
-void launch_segments(const uint64_t* keys, uint64_t k, uint64_t* seg_lo, uint32_t* nseg, hipStream_t s) {
-  if (k) k_segments<<<grid_for(k), kTpb, 0, s>>>(keys, k, seg_lo, nseg);
-}
-void launch_seg_find(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
-                     const uint32_t* nseg_ptr, uint32_t nseg_max, int64_t* slot_out, uint8_t* insflag,
-                     uint32_t* rowdel, uint32_t* rowins, SetRef dirty, int apply, hipStream_t s) {
-  if (!k) return;
-  unsigned g = nseg_max < 8192 ? (nseg_max ? nseg_max : 1) : 8192;
-  if (apply)
-    k_seg_find<1><<<g, 256, 0, s>>>(c, keys, delta, k, seg_lo, nseg_ptr, slot_out, insflag, rowdel, rowins, dirty);
-  else
-    k_seg_find<0><<<g, 256, 0, s>>>(c, keys, delta, k, seg_lo, nseg_ptr, slot_out, insflag, rowdel, rowins, dirty);
-}
 void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
                             const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                             int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
@@ -1180,32 +978,23 @@ void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_
   const unsigned g = k < 8192 ? (unsigned)k : 8192u;
   k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out);
 }
-void launch_seg_apply(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
-                      const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* insflag,
-                      uint32_t* rowdel, uint32_t* rowins, int64_t* deg_arr, uint32_t* dirty_list, uint32_t* dirty_count,
-                      hipStream_t s) {
+void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                       const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
+                       uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel, uint32_t* rowins, uint32_t* move_list,
+                       uint32_t* move_count, hipStream_t s) {
   if (!k) return;
   const unsigned g = k < 8192 ? (unsigned)k : 8192u;
-  k_seg_apply<<<g, 256, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, insflag, rowdel, rowins, deg_arr,
-                                dirty_list, dirty_count);
+  k_seg_update<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel, rowins,
+                                  move_list, move_count);
 }
-void launch_csr_plan(CsrRef c, const uint32_t* dirty, uint32_t nd, const uint32_t* rowdel, const uint32_t* rowins,
-                     uint64_t* plan_off, uint32_t* plan_cap, u64a* pool_top, uint64_t pool_cap, uint32_t* overflow,
-                     hipStream_t s) {
-  if (nd)
-    k_csr_plan<<<grid_for(nd), kTpb, 0, s>>>(c, dirty, nd, rowdel, rowins, plan_off, plan_cap, pool_top, pool_cap,
-                                             overflow);
-}
-void launch_csr_rewrite(CsrRef c, const uint32_t* dirty, uint32_t nd, uint32_t* rowdel, uint32_t* rowins,
-                        const uint64_t* plan_off, const uint32_t* plan_cap, const uint64_t* keys, const int64_t* delta,
-                        const uint8_t* insflag, uint64_t k, hipStream_t s) {
-  if (nd)
-    k_csr_rewrite<<<grid_waves(nd), kTpb, 0, s>>>(c, dirty, nd, rowdel, rowins, plan_off, plan_cap, keys, delta,
-                                                  insflag, k);
-}
-void launch_csr_degrees(int64_t* kout, int64_t* kin_or_null, const uint64_t* keys, const int64_t* delta, uint64_t k,
-                        hipStream_t s) {
-  if (k) k_csr_degrees<<<grid_for(k), kTpb, 0, s>>>(kout, kin_or_null, keys, delta, k);
+void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
+                     const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,
+                     uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
+                     uint32_t* overflow, hipStream_t s) {
+  if (!k) return;
+  const unsigned g = k < 1024 ? (unsigned)k : 1024u;
+  k_seg_move<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, rtype, rowdel, rowins, move_list, move_count, pool_top,
+                                pool_cap, overflow);
 }
 void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, hipStream_t s) {
   if (n) k_csr_newcap<<<grid_for(n), kTpb, 0, s>>>(deg, newcap, newcap64, n);
@@ -1223,13 +1012,6 @@ void launch_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_t* del
   const uint64_t t = ni + nd + nc;
   if (t) k_ingest_records<<<grid_for(t), kTpb, 0, s>>>(ins, ni, del, nd, chg, nc, n, directed, keys, idx, err);
 }
-void launch_ingest_check(CsrRef out0, const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins,
-                         uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg, int directed,
-                         int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm, hipStream_t s) {
-  if (k)
-    k_ingest_check<<<grid_waves(k), kTpb, 0, s>>>(out0, keys, idx, k, ins, ni, del, nd, chg, directed, delta, err,
-                                                  first_bad, dm);
-}
 void launch_ingest_entries(const uint64_t* keys, const int64_t* delta, uint64_t k, int directed, uint64_t* ekeys,
                            int64_t* edelta, u64a* count, hipStream_t s) {
   if (k) k_ingest_entries<<<grid_for(k), kTpb, 0, s>>>(keys, delta, k, directed, ekeys, edelta, count);
@@ -1242,9 +1024,11 @@ void launch_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t
                           int64_t* Kout, int64_t* Kin_or_null, i64a* dein, hipStream_t s) {
   if (k) k_ingest_totals<<<grid_for(k), kTpb, 0, s>>>(ekeys, edelta, k, lab0, Kout, Kin_or_null, dein);
 }
-void launch_dskk(const uint32_t* touched, uint32_t nt, const int64_t* Kout, const int64_t* Kin, const int64_t* tko,
-                 const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s) {
-  if (nt) k_dskk<<<grid_for(nt), kTpb, 0, s>>>(touched, nt, Kout, Kin, tko, tki, lo, hi);
+void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, const int64_t* Kout, const int64_t* Kin,
+                 const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s) {
+  if (!nt_max) return;
+  const unsigned g = grid_for(nt_max) < 1024u ? grid_for(nt_max) : 1024u;
+  k_dskk<<<g, kTpb, 0, s>>>(touched, nt, Kout, Kin, tko, tki, lo, hi);
 }
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
                         uint64_t* keys, int64_t* vals, SetRef seeds, hipStream_t s) {
@@ -1264,21 +1048,6 @@ void launch_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* o
                       const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize, int phase,
                       hipStream_t s) {
   if (nr) k_ref_reset<<<grid_for(nr), kTpb, 0, s>>>(R, nr, par, oldpar, kout, kin, Krout, Krin_or_null, rsize, phase);
-}
-void launch_changed(const uint32_t* rset, uint32_t nr, const uint32_t* par, const uint32_t* oldpar, SetRef C,
-                    hipStream_t s) {
-  if (nr) k_changed<<<grid_for(nr), kTpb, 0, s>>>(rset, nr, par, oldpar, C);
-}
-void launch_tuple_count(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, u64a* total,
-                        hipStream_t s) {
-  if (k) k_tuple_count<<<grid_for(k), kTpb, 0, s>>>(list, k, out, in, directed, total);
-}
-void launch_tuples(const uint32_t* list, uint32_t k, CsrRef out, CsrRef in, int directed, const uint32_t* par,
-                   const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep, int repair, uint64_t* tkeys,
-                   int64_t* tvals, u64a* tcount, uint64_t tcap, SetRef seeds_or_null, hipStream_t s) {
-  if (k)
-    k_tuples<<<grid_waves(k), kTpb, 0, s>>>(list, k, out, in, directed, par, oldpar, cstamp, cep, repair, tkeys, tvals,
-                                            tcount, tcap, seeds_or_null);
 }
 void launch_live_update(const uint32_t* cand, uint32_t k, const uint32_t* rsize_below, uint8_t* alive,
                         uint32_t* par_or_null, uint32_t* lab, const uint32_t* lab_below, SetRef died,

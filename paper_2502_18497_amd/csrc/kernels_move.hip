@@ -116,28 +116,6 @@ __device__ __forceinline__ void emit_cand_at(const CandBuf& cb, uint32_t at, uin
   cb.ghi[at] = b.hi;
 }
 
-// ------------------------------------------------------------------ binning
-__global__ void k_bin(MoveView mv, const uint32_t* list, uint32_t count, int refine, uint32_t* b0, uint32_t* b1,
-                      uint32_t* b2, uint32_t* b3, uint32_t* b4, uint32_t* bc) {
-  for (uint64_t i = gtid(); i < count; i += gstride()) {
-    const uint32_t v = list[i];
-    if (refine && !(mv.par[v] == v && mv.rsize[v] == 1)) continue;   // only singletons move
-    const uint64_t T = (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
-    if (T == 0) continue;
-    int b = 4;
-    if (T <= kBinLimit[0]) b = 0;
-    else if (T <= kBinLimit[1]) b = 1;
-    else if (T <= kBinLimit[2]) b = 2;
-    else if (T <= kBinLimit[3]) b = 3;
-    uint32_t* dsts[kNumBins] = {b0, b1, b2, b3, b4};
-#pragma unroll
-    for (int t = 0; t < kNumBins; ++t) {
-      const uint32_t at = wave_reserve(&bc[t], b == t);
-      if (b == t) dsts[t][at] = v;
-    }
-  }
-}
-
 // ------------------------------------------------------------------ binning without atomics
 __device__ __forceinline__ int bin_of(const MoveView& mv, uint32_t v, int refine) {
   if (refine && !(mv.par[v] == v && mv.rsize[v] == 1)) return -1;   // only singletons move
@@ -151,10 +129,11 @@ __device__ __forceinline__ int bin_of(const MoveView& mv, uint32_t v, int refine
 }
 
 // block b owns list[b*chunk, (b+1)*chunk); hist[bin * gridDim + b] = its count per bin
-__global__ void k_bin_count(MoveView mv, const uint32_t* list, uint32_t count, int refine, uint32_t* hist) {
+__global__ void k_bin_count(MoveView mv, const uint32_t* list, const uint32_t* countp, int refine, uint32_t* hist) {
   __shared__ uint32_t h[kNumBins];
   if (threadIdx.x < kNumBins) h[threadIdx.x] = 0;
   __syncthreads();
+  const uint32_t count = *countp;
   const uint64_t chunk = ((uint64_t)count + gridDim.x - 1) / gridDim.x;
   const uint64_t lo = (uint64_t)blockIdx.x * chunk;
   const uint64_t hi = lo + chunk < count ? lo + chunk : count;
@@ -166,9 +145,10 @@ __global__ void k_bin_count(MoveView mv, const uint32_t* list, uint32_t count, i
   if (threadIdx.x < kNumBins) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_bin_fill(MoveView mv, const uint32_t* list, uint32_t count, int refine, const uint32_t* offs,
+__global__ void k_bin_fill(MoveView mv, const uint32_t* list, const uint32_t* countp, int refine, const uint32_t* offs,
                            uint32_t* out, uint32_t* bin_start, uint32_t* bin_count) {
   __shared__ uint32_t pos[kNumBins];
+  const uint32_t count = *countp;
   const unsigned nb = gridDim.x;
   if (threadIdx.x < kNumBins) pos[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
   if (blockIdx.x == 0 && threadIdx.x < kNumBins) {
@@ -189,9 +169,10 @@ __global__ void k_bin_fill(MoveView mv, const uint32_t* list, uint32_t count, in
 }
 
 // movers and their neighbours marked with plain stores
-__global__ void k_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, uint32_t na, CandBuf cand,
-                                      CsrRef out, CsrRef in, int directed) {
+__global__ void k_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, const uint32_t* nap,
+                                      CandBuf cand, CsrRef out, CsrRef in, int directed) {
   const int lane = lane_id();
+  const uint32_t na = *nap;
   for (uint64_t t = gwave(); t < na; t += gwstride()) {
     const uint32_t v = cand.v[acc[t]];
     if (lane == 0) stamp[v] = ep;
@@ -255,37 +236,61 @@ __device__ __forceinline__ void stage_flush(Stage<CAP>& s, const CandBuf& cand) 
 
 struct LocalStats {
   unsigned long long entries = 0, distinct = 0, vertices = 0, cands = 0;
+  unsigned long long maxhi = 0;   // gains of candidates are positive, so their high words are >= 0
 };
 
-// every thread of the block calls this once, at exit
+__device__ __forceinline__ void note_cand(LocalStats& ls, const Best& b) {
+  ls.cands += 1;
+  if ((unsigned long long)b.hi > ls.maxhi) ls.maxhi = (unsigned long long)b.hi;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = (unsigned long long)__shfl_xor((long long)v, o, 64);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// every thread of the block calls this once, at exit; red holds 5 words per wavefront
 __device__ __forceinline__ void stats_flush(LocalStats ls, const MoveStats& st, unsigned long long* red) {
-  if (!st.entries) return;
-  unsigned long long v[4] = {ls.entries, ls.distinct, ls.vertices, ls.cands};
+  unsigned long long v[5] = {ls.entries, ls.distinct, ls.vertices, ls.cands, ls.maxhi};
 #pragma unroll
   for (int k = 0; k < 4; ++k) v[k] = (unsigned long long)wave_sum_i64((int64_t)v[k]);
+  v[4] = wave_max_u64(v[4]);
   const int w = threadIdx.x / kWave;
   __syncthreads();
   if ((threadIdx.x & 63) == 0)
-    for (int k = 0; k < 4; ++k) red[4 * w + k] = v[k];
+    for (int k = 0; k < 5; ++k) red[5 * w + k] = v[k];
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     unsigned long long t = 0;
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += red[4 * i + threadIdx.x];
-    u64a* dst = threadIdx.x == 0 ? st.entries : threadIdx.x == 1 ? st.distinct : threadIdx.x == 2 ? st.vertices
-                                                                                                 : st.cands;
-    if (t) atomicAdd(dst, t);
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+      const unsigned long long x = red[5 * i + threadIdx.x];
+      if (threadIdx.x < 4) t += x;
+      else t = x > t ? x : t;
+    }
+    if (threadIdx.x == 4) {
+      if (t) atomicMax(st.maxhi, t);
+    } else if (st.entries && t) {
+      u64a* dst = threadIdx.x == 0 ? st.entries : threadIdx.x == 1 ? st.distinct : threadIdx.x == 2 ? st.vertices
+                                                                                                   : st.cands;
+      atomicAdd(dst, t);
+    }
   }
 }
 
 // ------------------------------------------------------------------ small degrees: lane groups
 template <typename WT, int G, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, const uint32_t* list, uint32_t count,
-                                                     CandBuf cand, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int VPB = kTpb / G;            // vertices per block iteration
   __shared__ Stage<256> stage;
-  __shared__ unsigned long long red[4 * (kTpb / kWave)];
+  __shared__ unsigned long long red[5 * (kTpb / kWave)];
   if (threadIdx.x == 0) stage.n = 0;
   __syncthreads();
+  const uint32_t count = *br.count;
+  const uint32_t* list = br.base + *br.start;
   LocalStats ls;
   const int li = threadIdx.x & (G - 1);
   for (uint64_t base = (uint64_t)blockIdx.x * VPB; base < count; base += (uint64_t)gridDim.x * VPB) {
@@ -333,7 +338,7 @@ __global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, const uint32_t
       ls.vertices += 1;
       if (b.valid && best_gain(b) > 0) {
         stage_push(stage, v, REF ? v : vi.lab, b);
-        ls.cands += 1;
+        note_cand(ls, b);
       }
     }
     __syncthreads();
@@ -385,16 +390,17 @@ __device__ __forceinline__ void table_insert(uint32_t* keys, u64a* vals, uint32_
 
 // TEAM lanes per vertex with a private LDS table of SLOTS (>= 2 T) entries
 template <typename WT, int TEAM, int SLOTS, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, const uint32_t* list, uint32_t count, CandBuf cand,
-                                                    MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int TEAMS = kTpb / TEAM;
   __shared__ uint32_t skey[TEAMS][SLOTS];
   __shared__ u64a sval[TEAMS][SLOTS];
   __shared__ int64_t red_i[kTpb / kWave];
   __shared__ Best red_b[kTpb / kWave];
   __shared__ Stage<64> stage;
-  __shared__ unsigned long long red_s[4 * (kTpb / kWave)];
+  __shared__ unsigned long long red_s[5 * (kTpb / kWave)];
   if (threadIdx.x == 0) stage.n = 0;
+  const uint32_t count = *br.count;
+  const uint32_t* list = br.base + *br.start;
   const int t = threadIdx.x / TEAM;
   const int li = threadIdx.x % TEAM;
   LocalStats ls;
@@ -448,7 +454,7 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, const uint32_t*
       ls.vertices += 1;
       if (b.valid && best_gain(b) > 0) {
         stage_push(stage, v, REF ? v : vi.lab, b);
-        ls.cands += 1;
+        note_cand(ls, b);
       }
     }
     __syncthreads();
@@ -458,208 +464,192 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, const uint32_t*
   stats_flush(ls, st, red_s);
 }
 
-// hubs: one workgroup per vertex, table of pow2 >= 2T slots carved from a global pool; a
-// vertex that finds the pool full is deferred to the overflow list for a later launch
+// ---- hubs split over many workgroups, driven from device counts.  Hub i (of the bin's h
+// vertices) owns a table of hsize[i] = pow2 >= max(64, 2 T_i) slots at hoff[i] in the pool.
+// Insert items (icnt[i] chunks of kHubChunk entries, pre-aggregated in LDS) fill the tables;
+// scan items (scnt[i] slices of kHubScan slots) evaluate the gains into partial bests at
+// soff[i] + slice and return their slots to empty; one wavefront per hub reduces the partials.
+// Hubs whose table ends beyond the pool are skipped and reported (bit 0 of *over, with the
+// required size in *need); more than `bound` hubs is reported as bit 1.
+constexpr uint32_t kHubChunk = 2048;
+constexpr uint32_t kHubScan = kHubScanSlots;
+
+__device__ __forceinline__ uint32_t hub_count(const BinRef& br, uint32_t bound) {
+  const uint32_t c = *br.count;
+  return c < bound ? c : bound;
+}
+
+// largest i in [0, h) with off[i] <= it, for non-decreasing off with off[h] > it
+__device__ __forceinline__ uint32_t item_owner(const uint64_t* off, uint32_t h, uint64_t it) {
+  uint32_t lo = 0, hi = h;   // off[lo] <= it < off[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= it) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t entries_of(const MoveView& mv, uint32_t v) {
+  return (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
+}
+
+__global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, uint64_t* hsize) {
+  const uint32_t h = hub_count(br, bound);
+  const uint32_t* list = br.base + *br.start;
+  for (uint64_t i = gtid(); i <= bound; i += gstride()) {
+    uint64_t size = 0;
+    if (i < h) {
+      const uint64_t T = entries_of(mv, list[i]);
+      size = 64;
+      while (size < 2 * T) size <<= 1;
+    }
+    hsize[i] = size;
+  }
+}
+
+__global__ void k_hub_plan(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff, uint64_t cap, uint64_t* icnt,
+                           uint64_t* scnt, int64_t* own, u64a* need, uint32_t* over) {
+  const uint32_t c = *br.count;
+  const uint32_t h = c < bound ? c : bound;
+  const uint32_t* list = br.base + *br.start;
+  for (uint64_t i = gtid(); i <= bound; i += gstride()) {
+    uint64_t ic = 0, sc = 0;
+    if (i < h && hoff[i + 1] <= cap) {
+      const uint64_t T = entries_of(mv, list[i]);
+      ic = (T + kHubChunk - 1) / kHubChunk;
+      sc = (hoff[i + 1] - hoff[i] + kHubScan - 1) / kHubScan;
+      own[i] = 0;
+    }
+    icnt[i] = ic;
+    scnt[i] = sc;
+  }
+  if (gtid() == 0) {
+    const uint64_t total = hoff[h];
+    *need = total;
+    uint32_t f = 0;
+    if (total > cap) f |= 1u;
+    if (c > bound) f |= 2u;
+    if (f) atomicOr(over, f);
+  }
+}
+
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_best_hub(MoveView mv, const uint32_t* list, uint32_t count, CandBuf cand,
-                                                   HubPool hub, MoveStats st) {
-  __shared__ int64_t red_i[kTpb / kWave];
-  __shared__ Best red_b[kTpb / kWave];
-  __shared__ uint64_t s_base;
-  __shared__ int s_ok;
-  __shared__ Stage<32> stage;
-  __shared__ unsigned long long red_s[4 * (kTpb / kWave)];
-  if (threadIdx.x == 0) stage.n = 0;
-  LocalStats ls;
-  for (uint64_t slot = blockIdx.x; slot < count; slot += gridDim.x) {
-    const uint32_t v = list[slot];
+__global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff,
+                                                     const uint64_t* ioff, HubPool hub, int64_t* own, MoveStats st) {
+  __shared__ int64_t red[kTpb / kWave];
+  __shared__ uint32_t lkey[2 * kHubChunk];
+  __shared__ u64a lval[2 * kHubChunk];
+  const uint32_t h = hub_count(br, bound);
+  const uint32_t* list = br.base + *br.start;
+  const uint64_t total = ioff[h];
+  uint64_t nent = 0;
+  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t i = item_owner(ioff, h, it);
+    const uint32_t v = list[i];
     const uint32_t dout = mv.out.deg[v];
     const uint32_t din = DIR ? mv.in.deg[v] : 0;
     const uint32_t T = dout + din;
-    uint64_t size = 1;
-    while (size < 2ull * T) size <<= 1;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const u64a o = atomicAdd(hub.top, (u64a)size);
-      s_ok = (o + size <= hub.cap) ? 1 : 0;
-      s_base = o;
-      if (!s_ok) hub.over[atomicAdd(hub.over_count, 1u)] = v;
-    }
-    __syncthreads();
-    if (!s_ok) continue;
-    uint32_t* keys = hub.keys + s_base;
-    u64a* vals = hub.vals + s_base;
-    const uint32_t mask = (uint32_t)(size - 1);
-    for (uint64_t s = threadIdx.x; s < size; s += kTpb) {
-      keys[s] = kEmpty;
-      vals[s] = 0;
-    }
-    __threadfence();
-    __syncthreads();
-    const VInfo vi = vinfo<DIR, REF>(mv, v);
+    const uint64_t e0 = (it - ioff[i]) * kHubChunk;
+    const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
+    const uint64_t base = hoff[i];
+    const uint32_t mask = (uint32_t)(hoff[i + 1] - base - 1);
+    uint32_t* keys = hub.keys + base;
+    u64a* vals = hub.vals + base;
+    const uint32_t labv = mv.lab[v];
     const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-    int64_t own = 0;
-    for (uint32_t j = threadIdx.x; j < T; j += kTpb) {
+    // aggregate the chunk in LDS first so hot communities cost one global update per chunk
+    for (uint32_t t = threadIdx.x; t < 2 * kHubChunk; t += blockDim.x) {
+      lkey[t] = kEmpty;
+      lval[t] = 0;
+    }
+    __syncthreads();
+    int64_t ow = 0;
+    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
       uint32_t x;
       int64_t w;
-      entry_at<WT, DIR>(mv, oo, dout, oi, j, x, w);
-      const uint32_t key = entry_key<REF>(mv, v, vi.lab, x);
+      entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
+      const uint32_t key = entry_key<REF>(mv, v, labv, x);
       if (key == kEmpty) continue;
-      if (!REF && key == vi.lab) {
-        own += w;
+      if (!REF && key == labv) {
+        ow += w;
         continue;
       }
-      table_insert(keys, vals, mask, key, w);
-    }
-    __threadfence();
-    __syncthreads();
-    own = team_sum<kTpb>(own, red_i);
-    Best b;
-    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    for (uint64_t s = threadIdx.x; s < size; s += kTpb) {
-      const uint32_t key = __hip_atomic_load(&keys[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (key == kEmpty) continue;
-      ls.distinct += 1;
-      const int64_t a = (int64_t)__hip_atomic_load(&vals[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const Best c = make_best(gain<DIR, REF>(mv, vi, key, a, own), key);
-      if (better(c, b)) b = c;
-    }
-    b = team_best<kTpb>(b, red_b);
-    if (threadIdx.x == 0) {
-      ls.entries += T;
-      ls.vertices += 1;
-      if (b.valid && best_gain(b) > 0) {
-        stage_push(stage, v, REF ? v : vi.lab, b);
-        ls.cands += 1;
-      }
+      table_insert(lkey, lval, 2 * kHubChunk - 1, key, w);
     }
     __syncthreads();
-    if (stage.n + 1 > 32) stage_flush(stage, cand);
-  }
-  stage_flush(stage, cand);
-  stats_flush(ls, st, red_s);
-}
-
-// ---- hubs split over many workgroups.  Each hub vertex i owns a table of hsize[i] =
-// pow2 >= 2 T_i slots at hoff[i] in the pool; entry chunks insert in parallel, slot chunks
-// evaluate gains into partial bests, and one wavefront per hub reduces the partials.
-constexpr uint32_t kHubChunk = 4096;   // entries per insert workgroup
-constexpr uint32_t kHubScan = kHubScanSlots;
-
-__global__ void k_hub_prep(MoveView mv, const uint32_t* list, uint32_t h, uint64_t* hsize, u64a* maxT) {
-  u64a mt = 0;
-  for (uint64_t i = gtid(); i <= h; i += gstride()) {
-    if (i == h) {
-      hsize[h] = 0;
-      continue;
+    for (uint32_t t = threadIdx.x; t < 2 * kHubChunk; t += blockDim.x) {
+      const uint32_t key = lkey[t];
+      if (key != kEmpty) table_insert(keys, vals, mask, key, (int64_t)lval[t]);
     }
-    const uint32_t v = list[i];
-    const uint64_t T = (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
-    uint64_t size = 64;
-    while (size < 2 * T) size <<= 1;
-    hsize[i] = size;
-    if (T > mt) mt = T;
+    ow = team_sum<kTpb>(ow, red);
+    if (threadIdx.x == 0 && ow) atomic_add_i64(&own[i], ow);
+    nent += e1 - e0;
+    __syncthreads();
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    const u64a t = (u64a)__shfl_xor((long long)mt, o, 64);
-    if (t > mt) mt = t;
-  }
-  if ((threadIdx.x & 63) == 0 && mt) atomicMax(maxT, mt);
+  if (threadIdx.x == 0 && st.entries && nent) atomicAdd(st.entries, (u64a)nent);
 }
 
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(256) void k_hub_insert(MoveView mv, const uint32_t* list, uint32_t i0,
-                                                    const uint64_t* hoff, uint64_t base0, HubPool hub, int64_t* own,
-                                                    MoveStats st) {
-  __shared__ int64_t red[kTpb / kWave];
-  const uint32_t i = i0 + blockIdx.y;
-  const uint32_t v = list[i];
-  const uint32_t dout = mv.out.deg[v];
-  const uint32_t din = DIR ? mv.in.deg[v] : 0;
-  const uint32_t T = dout + din;
-  const uint64_t e0 = (uint64_t)blockIdx.x * kHubChunk;
-  if (e0 >= T) return;                      // whole workgroup leaves together
-  const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
-  const uint64_t base = hoff[i] - base0;
-  const uint32_t mask = (uint32_t)(hoff[i + 1] - hoff[i] - 1);
-  uint32_t* keys = hub.keys + base;
-  u64a* vals = hub.vals + base;
-  const uint32_t labv = mv.lab[v];
-  const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-  int64_t ow = 0;
-  for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
-    uint32_t x;
-    int64_t w;
-    entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
-    const uint32_t key = entry_key<REF>(mv, v, labv, x);
-    if (key == kEmpty) continue;
-    if (!REF && key == labv) {
-      ow += w;
-      continue;
-    }
-    table_insert(keys, vals, mask, key, w);
-  }
-  ow = team_sum<kTpb>(ow, red);
-  if (threadIdx.x == 0) {
-    if (ow) atomic_add_i64(&own[blockIdx.y], ow);
-    if (st.entries) atomicAdd(st.entries, (u64a)(e1 - e0));
-  }
-}
-
-template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(256) void k_hub_scan(MoveView mv, const uint32_t* list, uint32_t i0,
-                                                  const uint64_t* hoff, uint64_t base0, HubPool hub,
-                                                  const int64_t* own, uint32_t max_parts, int64_t* phi, uint64_t* plo,
-                                                  uint32_t* pid, int* pvalid, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_hub_scan(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff,
+                                                   const uint64_t* soff, HubPool hub, const int64_t* own, int64_t* phi,
+                                                   uint64_t* plo, uint32_t* pid, int* pvalid, MoveStats st) {
   __shared__ Best red_b[kTpb / kWave];
   __shared__ int64_t red_i[kTpb / kWave];
-  const uint32_t i = i0 + blockIdx.y;
-  const uint64_t size = hoff[i + 1] - hoff[i];
-  const uint64_t s0 = (uint64_t)blockIdx.x * kHubScan;
-  if (s0 >= size) return;
-  const uint64_t s1 = s0 + kHubScan < size ? s0 + kHubScan : size;
-  const uint64_t base = hoff[i] - base0;
-  const uint32_t v = list[i];
-  const VInfo vi = vinfo<DIR, REF>(mv, v);
-  const int64_t ow = own[blockIdx.y];
-  Best b;
-  b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-  int64_t nd = 0;
-  for (uint64_t sl = s0 + threadIdx.x; sl < s1; sl += blockDim.x) {
-    const uint32_t key = __hip_atomic_load(&hub.keys[base + sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (key == kEmpty) continue;
-    ++nd;
-    const int64_t a = (int64_t)__hip_atomic_load(&hub.vals[base + sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const Best c = make_best(gain<DIR, REF>(mv, vi, key, a, ow), key);
-    if (better(c, b)) b = c;
+  const uint32_t h = hub_count(br, bound);
+  const uint32_t* list = br.base + *br.start;
+  const uint64_t total = soff[h];
+  uint64_t ndist = 0;
+  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t i = item_owner(soff, h, it);
+    const uint64_t base = hoff[i];
+    const uint64_t size = hoff[i + 1] - base;
+    const uint64_t s0 = (it - soff[i]) * kHubScan;
+    const uint64_t s1 = s0 + kHubScan < size ? s0 + kHubScan : size;
+    const uint32_t v = list[i];
+    const VInfo vi = vinfo<DIR, REF>(mv, v);
+    const int64_t ow = own[i];
+    Best b;
+    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
+    int64_t nd = 0;
+    for (uint64_t sl = s0 + threadIdx.x; sl < s1; sl += blockDim.x) {
+      const uint32_t key = hub.keys[base + sl];
+      if (key == kEmpty) continue;
+      ++nd;
+      const int64_t a = (int64_t)hub.vals[base + sl];
+      hub.keys[base + sl] = kEmpty;    // the pool is left empty for the next launch
+      hub.vals[base + sl] = 0;
+      const Best c = make_best(gain<DIR, REF>(mv, vi, key, a, ow), key);
+      if (better(c, b)) b = c;
+    }
+    nd = team_sum<kTpb>(nd, red_i);
+    b = team_best<kTpb>(b, red_b);
+    if (threadIdx.x == 0) {
+      phi[it] = b.hi;
+      plo[it] = b.lo;
+      pid[it] = b.id;
+      pvalid[it] = b.valid;
+      ndist += (uint64_t)nd;
+    }
+    __syncthreads();
   }
-  nd = team_sum<kTpb>(nd, red_i);
-  b = team_best<kTpb>(b, red_b);
-  if (threadIdx.x == 0) {
-    const uint64_t at = (uint64_t)blockIdx.y * max_parts + blockIdx.x;
-    phi[at] = b.hi;
-    plo[at] = b.lo;
-    pid[at] = b.id;
-    pvalid[at] = b.valid;
-    if (st.entries && nd) atomicAdd(st.distinct, (u64a)nd);
-  }
+  if (threadIdx.x == 0 && st.entries && ndist) atomicAdd(st.distinct, (u64a)ndist);
 }
 
 template <bool REF>
-__global__ void k_hub_final(const uint32_t* list, uint32_t i0, uint32_t ng, const uint64_t* hoff,
-                            const uint32_t* lab, uint32_t max_parts, const int64_t* phi, const uint64_t* plo,
-                            const uint32_t* pid, const int* pvalid, CandBuf cand, MoveStats st) {
+__global__ void k_hub_final(BinRef br, uint32_t bound, const uint64_t* soff, const uint32_t* lab, const int64_t* phi,
+                            const uint64_t* plo, const uint32_t* pid, const int* pvalid, CandBuf cand, MoveStats st) {
   const int lane = lane_id();
-  for (uint64_t g = gwave(); g < ng; g += gwstride()) {
-    const uint32_t i = i0 + (uint32_t)g;
-    const uint64_t size = hoff[i + 1] - hoff[i];
-    const uint32_t np = (uint32_t)((size + kHubScan - 1) / kHubScan);
+  const uint32_t h = hub_count(br, bound);
+  const uint32_t* list = br.base + *br.start;
+  for (uint64_t i = gwave(); i < h; i += gwstride()) {
+    const uint64_t p0 = soff[i], p1 = soff[i + 1];
+    if (p0 == p1) continue;                  // skipped: table beyond the pool
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    for (uint32_t p = lane; p < np; p += kWave) {
-      const uint64_t at = g * max_parts + p;
+    for (uint64_t p = p0 + lane; p < p1; p += kWave) {
       Best c;
-      c.hi = phi[at]; c.lo = plo[at]; c.id = pid[at]; c.valid = pvalid[at];
+      c.hi = phi[p]; c.lo = plo[p]; c.id = pid[p]; c.valid = pvalid[p];
       if (better(c, b)) b = c;
     }
     b = group_best(b, kWave);
@@ -668,34 +658,31 @@ __global__ void k_hub_final(const uint32_t* list, uint32_t i0, uint32_t ng, cons
       if (st.entries) atomicAdd(st.vertices, 1ull);
       if (b.valid && best_gain(b) > 0) {
         emit_cand_at(cand, atomicAdd(cand.count, 1u), v, REF ? v : lab[v], b);
-        if (st.cands) atomicAdd(st.cands, 1ull);
+        if (st.entries) atomicAdd(st.cands, 1ull);
+        atomicMax(st.maxhi, (u64a)b.hi);
       }
     }
   }
 }
 
-__global__ void k_hub_clear(uint32_t* keys, u64a* vals, uint64_t n) {
-  for (uint64_t i = gtid(); i < n; i += gstride()) {
-    keys[i] = kEmpty;
-    vals[i] = 0;
-  }
-}
-
 template <typename WT, bool DIR, bool REF>
-void hub_group_dispatch(const MoveView& mv, const uint32_t* list, uint32_t i0, uint32_t ng, const uint64_t* hoff,
-                        uint64_t base0, uint64_t span, uint64_t maxT, HubPool hub, int64_t* own, uint32_t max_parts,
-                        int64_t* phi, uint64_t* plo, uint32_t* pid, int* pvalid, CandBuf cand, MoveStats st,
-                        hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-  k_hub_clear<<<grid_for(span), kTpb, 0, s>>>(hub.keys, hub.vals, span);
+int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, HubWork hw, CandBuf cand, MoveStats st,
+                 void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
+  const unsigned gb = grid_for((uint64_t)bound + 1);
+  k_hub_size<<<gb, kTpb, 0, s>>>(mv, br, bound, hw.hsize);
+  int rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.hsize, hw.hoff, (uint64_t)bound + 1, s);
+  if (rc) return rc;
+  k_hub_plan<<<gb, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hub.cap, hw.icnt, hw.scnt, hw.own, hub.top, hub.over_count);
+  if ((rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.icnt, hw.ioff, (uint64_t)bound + 1, s))) return rc;
+  if ((rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.scnt, hw.soff, (uint64_t)bound + 1, s))) return rc;
   if (ev_a) (void)hipEventRecord(ev_a, s);
-  dim3 gi((unsigned)((maxT + kHubChunk - 1) / kHubChunk), ng);
-  k_hub_insert<WT, DIR, REF><<<gi, kTpb, 0, s>>>(mv, list, i0, hoff, base0, hub, own, st);
+  k_hub_insert<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hw.ioff, hub, hw.own, st);
   if (ev_b) (void)hipEventRecord(ev_b, s);
-  dim3 gs(max_parts, ng);
-  k_hub_scan<WT, DIR, REF><<<gs, kTpb, 0, s>>>(mv, list, i0, hoff, base0, hub, own, max_parts, phi, plo, pid, pvalid,
-                                              st);
-  k_hub_final<REF><<<grid_waves(ng), kTpb, 0, s>>>(list, i0, ng, hoff, mv.lab, max_parts, phi, plo, pid, pvalid,
-                                                   cand, st);
+  k_hub_scan<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hw.soff, hub, hw.own, hw.phi,
+                                                           hw.plo, hw.pid, hw.pvalid, st);
+  k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.soff, mv.lab, hw.phi, hw.plo, hw.pid, hw.pvalid,
+                                                      cand, st);
+  return 0;
 }
 
 inline unsigned persist_grid(uint64_t items_per_block_units) {
@@ -706,23 +693,21 @@ inline unsigned persist_grid(uint64_t items_per_block_units) {
 }
 
 template <typename WT, bool DIR, bool REF>
-void best_dispatch(const MoveView& mv, int bin, const uint32_t* list, uint32_t count, CandBuf cand, HubPool hub,
-                   MoveStats st, hipStream_t s) {
+void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, CandBuf cand, MoveStats st,
+                   hipStream_t s) {
+  const uint64_t c = max_count;
   switch (bin) {
     case 0:
-      k_best_group<WT, 8, DIR, REF><<<persist_grid((count + 31) / 32), kTpb, 0, s>>>(mv, list, count, cand, st);
+      k_best_group<WT, 8, DIR, REF><<<persist_grid((c + 31) / 32), kTpb, 0, s>>>(mv, br, cand, st);
       break;
     case 1:
-      k_best_group<WT, 32, DIR, REF><<<persist_grid((count + 7) / 8), kTpb, 0, s>>>(mv, list, count, cand, st);
+      k_best_group<WT, 32, DIR, REF><<<persist_grid((c + 7) / 8), kTpb, 0, s>>>(mv, br, cand, st);
       break;
     case 2:
-      k_best_hash<WT, 64, 256, DIR, REF><<<persist_grid((count + 3) / 4), kTpb, 0, s>>>(mv, list, count, cand, st);
-      break;
-    case 3:
-      k_best_hash<WT, 256, 4096, DIR, REF><<<persist_grid(count), kTpb, 0, s>>>(mv, list, count, cand, st);
+      k_best_hash<WT, 64, 256, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
       break;
     default:
-      k_best_hub<WT, DIR, REF><<<persist_grid(count), kTpb, 0, s>>>(mv, list, count, cand, hub, st);
+      k_best_hash<WT, 256, 4096, DIR, REF><<<persist_grid(c), kTpb, 0, s>>>(mv, br, cand, st);
   }
 }
 
@@ -745,25 +730,29 @@ __global__ void k_gather_u64(const uint64_t* src, const uint32_t* idx, uint32_t 
 __global__ void k_gather_u32_as_u64(const uint32_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst) {
   for (uint64_t i = gtid(); i < k; i += gstride()) dst[i] = idx ? src[idx[i]] : src[i];
 }
-__global__ void k_lf_reset(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b, uint32_t* minE,
-                           uint32_t* minA) {
+__global__ void k_lf_reset(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
+                           uint32_t* minE, uint32_t* minA, uint32_t* out_count) {
+  const uint32_t nl = *nlp;
+  if (gtid() == 0) *out_count = 0;
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
     minE[a[i]] = kEmpty; minA[a[i]] = kEmpty;
     minE[b[i]] = kEmpty; minA[b[i]] = kEmpty;
   }
 }
-__global__ void k_lf_min(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b,
+__global__ void k_lf_min(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
                          const uint32_t* rank, uint32_t* minE, uint32_t* minA) {
+  const uint32_t nl = *nlp;
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
     atomicMin(&minE[a[i]], rank[i]);
     atomicMin(&minA[b[i]], rank[i]);
   }
 }
-__global__ void k_lf_accept(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b,
+__global__ void k_lf_accept(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
                             const uint32_t* rank, const uint32_t* minE, const uint32_t* minA, uint32_t* accE,
                             uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count) {
+  const uint32_t nl = *nlp;
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
     const uint32_t r = rank[i];
@@ -778,9 +767,10 @@ __global__ void k_lf_accept(const uint32_t* live, uint32_t nl, const uint32_t* a
     }
   }
 }
-__global__ void k_lf_reject(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b,
+__global__ void k_lf_reject(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
                             const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag,
                             uint32_t* live2, uint32_t* live2_count) {
+  const uint32_t nl = *nlp;
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
     const bool keep = !flag[i] && !(accA[a[i]] == ep || accE[b[i]] == ep);
@@ -790,9 +780,10 @@ __global__ void k_lf_reject(const uint32_t* live, uint32_t nl, const uint32_t* a
 }
 
 // ------------------------------------------------------------------ commit / rollback
-__global__ void k_commit_mark(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* mov_stamp, uint32_t mov_ep,
-                              uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin, SetRef touched,
-                              int64_t* tko, int64_t* tki) {
+__global__ void k_commit_mark(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* mov_stamp,
+                              uint32_t mov_ep, uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin,
+                              SetRef touched, int64_t* tko, int64_t* tki) {
+  const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride()) {
     const uint32_t i = acc[t];
     const uint32_t v = cand.v[i];
@@ -812,8 +803,9 @@ __global__ void k_commit_mark(const uint32_t* acc, uint32_t na, CandBuf cand, ui
   }
 }
 
-__global__ void k_commit_apply(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* lab, const int64_t* kout,
-                               const int64_t* kin, int64_t* Kout, int64_t* Kin, int forward) {
+__global__ void k_commit_apply(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* lab,
+                               const int64_t* kout, const int64_t* kin, int64_t* Kout, int64_t* Kin, int forward) {
+  const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride()) {
     const uint32_t i = acc[t];
     const uint32_t v = cand.v[i];
@@ -831,10 +823,11 @@ __global__ void k_commit_apply(const uint32_t* acc, uint32_t na, CandBuf cand, u
 
 // wave per mover: exact change of the same-label weight over matrix entries incident to
 // movers, each entry once (entries between two movers from the out side)
-__global__ void k_commit_dein(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in, int directed,
-                              const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
+__global__ void k_commit_dein(const uint32_t* acc, const uint32_t* nap, CandBuf cand, CsrRef out, CsrRef in,
+                              int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
                               const uint32_t* oldlab, i64a* dein) {
   const int lane = lane_id();
+  const uint32_t na = *nap;
   for (uint64_t t = gwave(); t < na; t += gwstride()) {
     const uint32_t v = cand.v[acc[t]];
     const uint32_t lv_new = lab[v], lv_old = oldlab[v];
@@ -867,38 +860,25 @@ __global__ void k_commit_dein(const uint32_t* acc, uint32_t na, CandBuf cand, Cs
   }
 }
 
-__global__ void k_mark_acc_comms(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* stamp, uint32_t ep) {
+__global__ void k_mark_acc_comms(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* stamp,
+                                 uint32_t ep) {
+  const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride()) {
     const uint32_t i = acc[t];
-    set_claim(stamp, ep, cand.a[i]);
-    set_claim(stamp, ep, cand.b[i]);
+    stamp[cand.a[i]] = ep;
+    stamp[cand.b[i]] = ep;
   }
 }
 
-__global__ void k_set_add_acc_v(SetRef set, const uint32_t* acc, uint32_t na, CandBuf cand) {
+__global__ void k_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t* nap, CandBuf cand) {
+  const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride())
     set_add(set.stamp, set.epoch, set.list, set.count, cand.v[acc[t]]);
 }
 
-__global__ void k_neighbours_acc(SetRef set, const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in,
-                                 int directed) {
-  const int lane = lane_id();
-  for (uint64_t t = gwave(); t < na; t += gwstride()) {
-    const uint32_t v = cand.v[acc[t]];
-    if (lane == 0) set_add(set.stamp, set.epoch, set.list, set.count, v);
-    const uint64_t o = out.off[v];
-    const uint32_t d = out.deg[v];
-    for (uint32_t j = lane; j < d; j += kWave) set_add(set.stamp, set.epoch, set.list, set.count, out.nbr[o + j]);
-    if (directed) {
-      const uint64_t oi = in.off[v];
-      const uint32_t di = in.deg[v];
-      for (uint32_t j = lane; j < di; j += kWave) set_add(set.stamp, set.epoch, set.list, set.count, in.nbr[oi + j]);
-    }
-  }
-}
-
-__global__ void k_ref_commit(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* par, const int64_t* kout,
-                             const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize) {
+__global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* par,
+                             const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize) {
+  const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride()) {
     const uint32_t i = acc[t];
     const uint32_t u = cand.v[i], y = cand.b[i];
@@ -914,11 +894,15 @@ __global__ void k_ref_commit(const uint32_t* acc, uint32_t na, CandBuf cand, uin
   }
 }
 
-// SPExpand: singleton neighbours of refinement movers that carry the mover's label
-__global__ void k_spexpand(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in, int directed,
-                           const uint32_t* lab, const uint32_t* par, const uint32_t* rsize, SetRef rcur, SetRef rset,
+// SPExpand: singleton neighbours of refinement movers that carry the mover's label join
+// Rcur; the ones new to Rset join it too, with their old parent (themselves) recorded.  Marks
+// are plain stores (every writer of a word stores the same value); lists come from a select.
+__global__ void k_spexpand(const uint32_t* acc, const uint32_t* nap, CandBuf cand, CsrRef out, CsrRef in,
+                           int directed, const uint32_t* lab, const uint32_t* par, const uint32_t* rsize,
+                           uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep,
                            uint32_t* oldpar) {
   const int lane = lane_id();
+  const uint32_t na = *nap;
   for (uint64_t t = gwave(); t < na; t += gwstride()) {
     const uint32_t v = cand.v[acc[t]];
     const uint32_t lv = lab[v];
@@ -928,13 +912,11 @@ __global__ void k_spexpand(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRe
       const uint32_t d = c.deg[v];
       for (uint32_t j = lane; j < d; j += kWave) {
         const uint32_t x = c.nbr[o + j];
-        const bool ok = x != v && lab[x] == lv && par[x] == x && rsize[x] == 1;
-        set_add(rcur.stamp, rcur.epoch, rcur.list, rcur.count, x, ok);
-        const bool claimed = ok && set_claim(rset.stamp, rset.epoch, x);
-        const uint32_t at = wave_reserve(rset.count, claimed);
-        if (claimed) {
-          rset.list[at] = x;
+        if (x == v || lab[x] != lv || par[x] != x || rsize[x] != 1) continue;
+        rcur_stamp[x] = rcur_ep;
+        if (rset_stamp[x] != rset_ep) {
           oldpar[x] = x;
+          rset_stamp[x] = rset_ep;
         }
       }
     }
@@ -944,69 +926,53 @@ __global__ void k_spexpand(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRe
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+// Kernels that read their item count from device memory get a grid sized from a host-side
+// upper bound (the grid-stride loops cover any count up to it).
 
-void launch_bin_count(const MoveView& mv, const uint32_t* list, uint32_t count, int refine, uint32_t* hist,
+void launch_bin_count(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, uint32_t* hist,
                       hipStream_t s) {
   k_bin_count<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, hist);
 }
-void launch_bin_fill(const MoveView& mv, const uint32_t* list, uint32_t count, int refine, const uint32_t* offs,
+void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, const uint32_t* offs,
                      uint32_t* out, uint32_t* bin_start, uint32_t* bin_count, hipStream_t s) {
   k_bin_fill<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, offs, out, bin_start, bin_count);
 }
-void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, uint32_t na, CandBuf cand,
-                                CsrRef out, CsrRef in, int directed, hipStream_t s) {
-  if (na) k_mark_neighbours_acc<<<grid_waves(na), kTpb, 0, s>>>(stamp, ep, acc, na, cand, out, in, directed);
-}
-void launch_hub_prep(const MoveView& mv, const uint32_t* list, uint32_t h, uint64_t* hsize, u64a* maxT,
-                     hipStream_t s) {
-  k_hub_prep<<<grid_for((uint64_t)h + 1), kTpb, 0, s>>>(mv, list, h, hsize, maxT);
-}
-void launch_hub_group(const MoveView& mv, const uint32_t* list, uint32_t i0, uint32_t ng, const uint64_t* hoff,
-                      uint64_t base0, uint64_t span, uint64_t maxT, int refine, HubPool hub, int64_t* own,
-                      uint32_t max_parts, int64_t* phi, uint64_t* plo, uint32_t* pid, int* pvalid, CandBuf cand,
-                      MoveStats st, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-  const bool dir = mv.directed != 0;
-#define LDL_HUB(WT, D, R)                                                                                          \
-  hub_group_dispatch<WT, D, R>(mv, list, i0, ng, hoff, base0, span, maxT, hub, own, max_parts, phi, plo, pid,      \
-                               pvalid, cand, st, s, ev_a, ev_b)
-  if (!mv.out.wide) {
-    if (dir) { if (refine) LDL_HUB(uint32_t, true, true); else LDL_HUB(uint32_t, true, false); }
-    else { if (refine) LDL_HUB(uint32_t, false, true); else LDL_HUB(uint32_t, false, false); }
-  } else {
-    if (dir) { if (refine) LDL_HUB(int64_t, true, true); else LDL_HUB(int64_t, true, false); }
-    else { if (refine) LDL_HUB(int64_t, false, true); else LDL_HUB(int64_t, false, false); }
-  }
-#undef LDL_HUB
-}
-void launch_bin(const MoveView& mv, const uint32_t* list, uint32_t count, int refine, uint32_t* const* bins,
-                uint32_t* bin_counts, hipStream_t s) {
-  if (count)
-    k_bin<<<grid_for(count), kTpb, 0, s>>>(mv, list, count, refine, bins[0], bins[1], bins[2], bins[3], bins[4],
-                                           bin_counts);
+void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, const uint32_t* na,
+                                uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in, int directed, hipStream_t s) {
+  if (na_max)
+    k_mark_neighbours_acc<<<grid_waves(na_max), kTpb, 0, s>>>(stamp, ep, acc, na, cand, out, in, directed);
 }
 
-void launch_best(const MoveView& mv, int bin, const uint32_t* list, uint32_t count, int refine, CandBuf cand,
-                 HubPool hub, MoveStats st, hipStream_t s) {
-  if (!count) return;
-  const bool dir = mv.directed != 0;
-  if (!mv.out.wide) {
-    if (dir) {
-      if (refine) best_dispatch<uint32_t, true, true>(mv, bin, list, count, cand, hub, st, s);
-      else best_dispatch<uint32_t, true, false>(mv, bin, list, count, cand, hub, st, s);
-    } else {
-      if (refine) best_dispatch<uint32_t, false, true>(mv, bin, list, count, cand, hub, st, s);
-      else best_dispatch<uint32_t, false, false>(mv, bin, list, count, cand, hub, st, s);
-    }
-  } else {
-    if (dir) {
-      if (refine) best_dispatch<int64_t, true, true>(mv, bin, list, count, cand, hub, st, s);
-      else best_dispatch<int64_t, true, false>(mv, bin, list, count, cand, hub, st, s);
-    } else {
-      if (refine) best_dispatch<int64_t, false, true>(mv, bin, list, count, cand, hub, st, s);
-      else best_dispatch<int64_t, false, false>(mv, bin, list, count, cand, hub, st, s);
-    }
-  }
+#define LDL_TYPED(CALL)                                                                                             \
+  do {                                                                                                             \
+    const bool dir_ = mv.directed != 0;                                                                            \
+    if (!mv.out.wide) {                                                                                            \
+      if (dir_) { if (refine) CALL(uint32_t, true, true); else CALL(uint32_t, true, false); }                      \
+      else { if (refine) CALL(uint32_t, false, true); else CALL(uint32_t, false, false); }                         \
+    } else {                                                                                                       \
+      if (dir_) { if (refine) CALL(int64_t, true, true); else CALL(int64_t, true, false); }                        \
+      else { if (refine) CALL(int64_t, false, true); else CALL(int64_t, false, false); }                           \
+    }                                                                                                              \
+  } while (0)
+
+void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int refine, CandBuf cand, MoveStats st,
+                 hipStream_t s) {
+  if (!max_count) return;
+#define LDL_BEST(WT, D, R) best_dispatch<WT, D, R>(mv, bin, br, max_count, cand, st, s)
+  LDL_TYPED(LDL_BEST);
+#undef LDL_BEST
 }
+
+int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPool hub, HubWork hw, CandBuf cand,
+               MoveStats st, void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
+  if (!bound) return 0;
+  int rc = 0;
+#define LDL_HUB(WT, D, R) rc = hub_dispatch<WT, D, R>(mv, br, bound, hub, hw, cand, st, tmp, tmp_bytes, s, ev_a, ev_b)
+  LDL_TYPED(LDL_HUB);
+#undef LDL_HUB
+  return rc;
+}
+#undef LDL_TYPED
 
 void launch_rank_from_order(const uint32_t* order, uint32_t k, uint32_t* rank, hipStream_t s) {
   if (k) k_rank_from_order<<<grid_for(k), kTpb, 0, s>>>(order, k, rank);
@@ -1018,65 +984,68 @@ void launch_gather_u64(const uint64_t* src, const uint32_t* idx, uint32_t k, uin
 void launch_gather_u32_as_u64(const uint32_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, hipStream_t s) {
   if (k) k_gather_u32_as_u64<<<grid_for(k), kTpb, 0, s>>>(src, idx, k, dst);
 }
-void launch_lf_reset(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b, uint32_t* minE,
-                     uint32_t* minA, hipStream_t s) {
-  if (nl) k_lf_reset<<<grid_for(nl), kTpb, 0, s>>>(live, nl, a, b, minE, minA);
+void launch_lf_reset(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
+                     uint32_t* minE, uint32_t* minA, uint32_t* out_count, hipStream_t s) {
+  k_lf_reset<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, minE, minA, out_count);
 }
-void launch_lf_min(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b, const uint32_t* rank,
-                   uint32_t* minE, uint32_t* minA, hipStream_t s) {
-  if (nl) k_lf_min<<<grid_for(nl), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA);
+void launch_lf_min(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
+                   const uint32_t* rank, uint32_t* minE, uint32_t* minA, hipStream_t s) {
+  if (nl_max) k_lf_min<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA);
 }
-void launch_lf_accept(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b, const uint32_t* rank,
-                      const uint32_t* minE, const uint32_t* minA, uint32_t* accE, uint32_t* accA, uint32_t ep,
-                      uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count, hipStream_t s) {
-  if (nl)
-    k_lf_accept<<<grid_for(nl), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA, accE, accA, ep, flag, acc_list,
-                                              acc_count);
+void launch_lf_accept(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
+                      const uint32_t* rank, const uint32_t* minE, const uint32_t* minA, uint32_t* accE, uint32_t* accA,
+                      uint32_t ep, uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count, hipStream_t s) {
+  if (nl_max)
+    k_lf_accept<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA, accE, accA, ep, flag, acc_list,
+                                                  acc_count);
 }
-void launch_lf_reject(const uint32_t* live, uint32_t nl, const uint32_t* a, const uint32_t* b, const uint32_t* accE,
-                      const uint32_t* accA, uint32_t ep, const uint8_t* flag, uint32_t* live2, uint32_t* live2_count,
-                      hipStream_t s) {
-  if (nl) k_lf_reject<<<grid_for(nl), kTpb, 0, s>>>(live, nl, a, b, accE, accA, ep, flag, live2, live2_count);
+void launch_lf_reject(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
+                      const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag, uint32_t* live2,
+                      uint32_t* live2_count, hipStream_t s) {
+  if (nl_max)
+    k_lf_reject<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, accE, accA, ep, flag, live2, live2_count);
 }
-void launch_commit_mark(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* mov_stamp, uint32_t mov_ep,
-                        uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin, SetRef touched, int64_t* tko,
-                        int64_t* tki, hipStream_t s) {
-  if (na)
-    k_commit_mark<<<grid_for(na), kTpb, 0, s>>>(acc, na, cand, mov_stamp, mov_ep, oldlab, Kout, Kin, touched, tko,
-                                                tki);
+void launch_commit_mark(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* mov_stamp,
+                        uint32_t mov_ep, uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin, SetRef touched,
+                        int64_t* tko, int64_t* tki, hipStream_t s) {
+  if (na_max)
+    k_commit_mark<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, mov_stamp, mov_ep, oldlab, Kout, Kin, touched, tko,
+                                                    tki);
 }
-void launch_commit_apply(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* lab, const int64_t* kout,
-                         const int64_t* kin, int64_t* Kout, int64_t* Kin_or_null, int forward, hipStream_t s) {
-  if (na) k_commit_apply<<<grid_for(na), kTpb, 0, s>>>(acc, na, cand, lab, kout, kin, Kout, Kin_or_null, forward);
+void launch_commit_apply(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* lab,
+                         const int64_t* kout, const int64_t* kin, int64_t* Kout, int64_t* Kin_or_null, int forward,
+                         hipStream_t s) {
+  if (na_max)
+    k_commit_apply<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, lab, kout, kin, Kout, Kin_or_null, forward);
 }
-void launch_commit_dein(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in, int directed,
-                        const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep, const uint32_t* oldlab,
-                        i64a* dein, hipStream_t s) {
-  if (na)
-    k_commit_dein<<<grid_waves(na), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, mov_stamp, mov_ep, oldlab,
-                                                  dein);
+void launch_commit_dein(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
+                        int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
+                        const uint32_t* oldlab, i64a* dein, hipStream_t s) {
+  if (na_max)
+    k_commit_dein<<<grid_waves(na_max), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, mov_stamp, mov_ep,
+                                                      oldlab, dein);
 }
-void launch_mark_acc_comms(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* stamp, uint32_t ep,
-                           hipStream_t s) {
-  if (na) k_mark_acc_comms<<<grid_for(na), kTpb, 0, s>>>(acc, na, cand, stamp, ep);
+void launch_mark_acc_comms(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* stamp,
+                           uint32_t ep, hipStream_t s) {
+  if (na_max) k_mark_acc_comms<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, stamp, ep);
 }
-void launch_set_add_acc_v(SetRef set, const uint32_t* acc, uint32_t na, CandBuf cand, hipStream_t s) {
-  if (na) k_set_add_acc_v<<<grid_for(na), kTpb, 0, s>>>(set, acc, na, cand);
+void launch_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand,
+                          hipStream_t s) {
+  if (na_max) k_set_add_acc_v<<<grid_for(na_max), kTpb, 0, s>>>(set, acc, na, cand);
 }
-void launch_neighbours_acc(SetRef set, const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in,
-                           int directed, hipStream_t s) {
-  if (na) k_neighbours_acc<<<grid_waves(na), kTpb, 0, s>>>(set, acc, na, cand, out, in, directed);
+void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
+                       const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize,
+                       hipStream_t s) {
+  if (na_max)
+    k_ref_commit<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, par, kout, kin, Krout, Krin_or_null, rsize);
 }
-void launch_ref_commit(const uint32_t* acc, uint32_t na, CandBuf cand, uint32_t* par, const int64_t* kout,
-                       const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize, hipStream_t s) {
-  if (na) k_ref_commit<<<grid_for(na), kTpb, 0, s>>>(acc, na, cand, par, kout, kin, Krout, Krin_or_null, rsize);
-}
-void launch_spexpand(const uint32_t* acc, uint32_t na, CandBuf cand, CsrRef out, CsrRef in, int directed,
-                     const uint32_t* lab, const uint32_t* par, const uint32_t* rsize, SetRef rcur, SetRef rset,
-                     uint32_t* oldpar, hipStream_t s) {
-  if (na)
-    k_spexpand<<<grid_waves(na), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, par, rsize, rcur, rset,
-                                               oldpar);
+void launch_spexpand(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
+                     int directed, const uint32_t* lab, const uint32_t* par, const uint32_t* rsize,
+                     uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep, uint32_t* oldpar,
+                     hipStream_t s) {
+  if (na_max)
+    k_spexpand<<<grid_waves(na_max), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, par, rsize, rcur_stamp,
+                                                   rcur_ep, rset_stamp, rset_ep, oldpar);
 }
 
 }  // namespace ldl

@@ -71,6 +71,16 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
+__device__ __forceinline__ i128 wave_sum_i128(i128 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t lo = (uint64_t)__shfl_xor((long long)(uint64_t)v, o, 64);
+    const int64_t hi = (int64_t)__shfl_xor((long long)(int64_t)(v >> 64), o, 64);
+    v += ((i128)hi << 64) | (i128)lo;
+  }
+  return v;
+}
+
 // Best (gain, id): larger gain wins, equal gains go to the lower id.  valid == false is
 // worse than anything.
 struct Best {

@@ -28,6 +28,13 @@ struct StampIs {
   __host__ __device__ __forceinline__ bool operator()(const uint32_t& i) const { return stamp[i] == ep; }
 };
 
+struct RowHead {
+  const uint64_t* keys;
+  __host__ __device__ __forceinline__ bool operator()(const uint64_t& i) const {
+    return i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32);
+  }
+};
+
 struct SumI64 {
   __host__ __device__ __forceinline__ int64_t operator()(const int64_t& a, const int64_t& b) const { return a + b; }
 };
@@ -108,6 +115,18 @@ int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint
   if (ensure(tmp, tmp_bytes, need)) return -2;
   size_t have = *tmp_bytes;
   return hipcub::DeviceSelect::If(*tmp, have, ids, out, d_count, (int)n, pred, s) == hipSuccess ? 0 : -1;
+}
+
+int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, uint64_t* out,
+                      uint32_t* d_count, hipStream_t s) {
+  if (k == 0) return 0;
+  hipcub::CountingInputIterator<uint64_t> ids(0);
+  RowHead pred{keys};
+  size_t need = 0;
+  if (hipcub::DeviceSelect::If(nullptr, need, ids, out, d_count, (int)k, pred, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceSelect::If(*tmp, have, ids, out, d_count, (int)k, pred, s) == hipSuccess ? 0 : -1;
 }
 
 int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
