@@ -104,6 +104,9 @@ typedef struct ldl_batch_stats {
   double bin_ms[20];
   double bin_bytes[20];
   uint64_t bin_entries[20];
+  uint64_t lf_rounds;         /* decoupling rounds launched                               */
+  uint64_t host_syncs;        /* stream synchronisations (host reads of device counters)  */
+  uint64_t agg_records;       /* reduced records applied to levels above 0                */
 } ldl_batch_stats;
 
 /* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */

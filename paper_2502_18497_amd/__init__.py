@@ -39,7 +39,8 @@ class ldl_batch_stats(ctypes.Structure):
         "distinct_comms", "candidates", "accepted", "rollbacks", "refine_moves", "agg_tuples", "bm_launches")] + \
         [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")] + \
         [("bin_launches", ctypes.c_uint64 * 20), ("bin_ms", ctypes.c_double * 20),
-         ("bin_bytes", ctypes.c_double * 20), ("bin_entries", ctypes.c_uint64 * 20)]
+         ("bin_bytes", ctypes.c_double * 20), ("bin_entries", ctypes.c_uint64 * 20)] + \
+        [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")]
 
     def as_dict(self) -> dict:
         d = {}

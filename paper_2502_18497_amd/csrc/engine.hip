@@ -67,12 +67,19 @@ struct PassScal {
   u64a hub_need;    // pool slots the hub tables needed
   uint32_t ncand;
   uint32_t hub_over;
+  // commit of the iteration: exact changes of Ein and sum Kout*Kin, touched communities
+  i64a cdein;
+  u64a cdskk_lo;
+  i64a cdskk_hi;
+  uint32_t ntouch;
+  uint32_t pad_;
 };
+static_assert(sizeof(PassScal) % 4 == 0, "PassScal is cleared as 32-bit words");
 struct Scal {
   uint32_t counts[64];
   uint32_t bins[8];
   uint32_t bin_start[8];
-  uint32_t nacc, nlive[2], err, first_bad, nseg, nmove, overflow;   // nmove, overflow adjacent
+  uint32_t nacc, nacc2, nlive[2], err, first_bad, nseg, nmove, overflow;   // nmove, overflow adjacent
   u64a pool_top[2 * 17];
   i64a dm, dein;
   u64a dskk_lo;
@@ -142,23 +149,25 @@ struct Engine {
   Scal* hs = nullptr;
   HSet sets[S_NSETS];
   bool set_has_list[S_NSETS];
+  bool set_selected[S_NSETS];   // list and count always rebuilt by a select
 
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
-  uint32_t *minE = nullptr, *minA = nullptr, *accE = nullptr, *accA = nullptr;
+  uint32_t *accE = nullptr, *accA = nullptr;
+  LfFirst lfE{}, lfA{};
+  uint32_t *lf_la = nullptr, *lf_lb = nullptr;
+  int lf_ca = 0;                 // index of lf_la's count in ds->nlive
   uint32_t acc_epoch = 0;
   uint8_t* lfflag = nullptr;
-  uint32_t *rank = nullptr, *liveA = nullptr, *liveB = nullptr, *acc = nullptr, *entry = nullptr;
+  uint32_t *liveA = nullptr, *liveB = nullptr, *acc = nullptr, *entry = nullptr;
   int64_t *tko = nullptr, *tki = nullptr;
   uint32_t* bins[kNumBins] = {};
   uint32_t* binbuf = nullptr;
-  uint32_t *bhist = nullptr, *boffs = nullptr;
+  uint32_t* bhist = nullptr;
   uint64_t *tcounts = nullptr, *toffs = nullptr, *tcur = nullptr, *it_cnt = nullptr, *it_off = nullptr;
   HubWork hw{};
   uint64_t part_cap = 0;
   CandBuf cand{};
-  uint64_t *skey0 = nullptr, *skey1 = nullptr;
-  uint32_t *sidx0 = nullptr, *sidx1 = nullptr;
   HubPool hub{};
   // growable record buffers
   uint64_t rec_cap = 0;
@@ -233,18 +242,28 @@ struct Engine {
     HSet& s = sets[id];
     return SetRef{s.stamp, set_has_list[id] ? s.list : nullptr, &ds->counts[s.ci], s.epoch};
   }
+  // empty a set: a new epoch, and a zero count for sets whose kernels append to the list
   void begin(int id) {
     HSet& s = sets[id];
     if (++s.epoch == 0) {
       hcheck(hipMemsetAsync(s.stamp, 0, sizeof(uint32_t) * (uint64_t)n, st));
       s.epoch = 1;
     }
-    hcheck(hipMemsetAsync(&ds->counts[s.ci], 0, sizeof(uint32_t), st));
+    if (set_has_list[id] && !set_selected[id]) hcheck(hipMemsetAsync(&ds->counts[s.ci], 0, sizeof(uint32_t), st));
+  }
+  // a new epoch only (the caller counts the members elsewhere)
+  void begin_epoch(int id) {
+    HSet& s = sets[id];
+    if (++s.epoch == 0) {
+      hcheck(hipMemsetAsync(s.stamp, 0, sizeof(uint32_t) * (uint64_t)n, st));
+      s.epoch = 1;
+    }
   }
   uint32_t count(int id) const { return hs->counts[sets[id].ci]; }
   void sync_read() {
     hcheck(hipMemcpyAsync(hs, ds, sizeof(Scal), hipMemcpyDeviceToHost, st));
     hcheck(hipStreamSynchronize(st));
+    stats.host_syncs++;
   }
   template <typename T>
   void zero(T* field) {
@@ -266,7 +285,7 @@ struct Engine {
     if (k == 0) return 0;
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
-    cub(launch_items(list, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
+    cub(launch_items(list, nullptr, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
     launch_tuples_count(list, cnt, k, it_off, out, in, cstamp, cep, repair, (u64a*)tcounts, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
     uint64_t T = 0;
@@ -302,6 +321,7 @@ struct Engine {
     std::memset(hs, 0, sizeof(Scal));
     for (int i = 0; i < S_NSETS; ++i) {
       set_has_list[i] = !(i == S_COMM || i == S_REFM || i == S_MOV);
+      set_selected[i] = i == S_U || i == S_U2 || i == S_S || i == S_RCUR || i == S_RSET || i == S_C;
       if (i <= 16 && i > L) continue;
       sets[i].stamp = alloc<uint32_t>(n);
       hcheck(hipMemsetAsync(sets[i].stamp, 0, sizeof(uint32_t) * (uint64_t)n, st));
@@ -311,6 +331,7 @@ struct Engine {
     }
     for (int i = 0; i < S_NSETS; ++i)
       if (sets[i].stamp) begin(i);   // epoch 1: stamps start at 0, so every set starts empty
+    hcheck(hipMemsetAsync(ds->counts, 0, sizeof(ds->counts), st));
     lv.resize(L + 1);
     for (int r = 0; r <= L; ++r) {
       Level& V = lv[r];
@@ -341,14 +362,18 @@ struct Engine {
     oldpar = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
-    minE = alloc<uint32_t>(n);
-    minA = alloc<uint32_t>(n);
+    lfE = LfFirst{alloc<u64a>(n), alloc<u64a>(n), alloc<uint32_t>(n)};
+    lfA = LfFirst{alloc<u64a>(n), alloc<u64a>(n), alloc<uint32_t>(n)};
+    for (LfFirst* f : {&lfE, &lfA}) {   // empty: the decoupling rounds keep them so
+      hcheck(hipMemsetAsync(f->hi, 0, 8ull * n, st));
+      hcheck(hipMemsetAsync(f->lo, 0, 8ull * n, st));
+      hcheck(hipMemsetAsync(f->v, 0xFF, 4ull * n, st));
+    }
     accE = alloc<uint32_t>(n);
     accA = alloc<uint32_t>(n);
     launch_fill_u32(accE, 0, n, st);
     launch_fill_u32(accA, 0, n, st);
     lfflag = alloc<uint8_t>(n);
-    rank = alloc<uint32_t>(n);
     liveA = alloc<uint32_t>(n);
     liveB = alloc<uint32_t>(n);
     acc = alloc<uint32_t>(n);
@@ -358,7 +383,6 @@ struct Engine {
     for (int b = 0; b < kNumBins; ++b) bins[b] = nullptr;
     binbuf = alloc<uint32_t>(n);
     bhist = alloc<uint32_t>(kNumBins * kBinBlocks + 1);
-    boffs = alloc<uint32_t>(kNumBins * kBinBlocks + 1);
     hcheck(hipMemsetAsync(bhist, 0, 4ull * (kNumBins * kBinBlocks + 1), st));
     tcounts = alloc<uint64_t>((uint64_t)n + 1);
     toffs = alloc<uint64_t>((uint64_t)n + 1);
@@ -366,12 +390,8 @@ struct Engine {
     tcur = alloc<uint64_t>((uint64_t)n + 1);
     it_cnt = alloc<uint64_t>((uint64_t)n + 1);
     it_off = alloc<uint64_t>((uint64_t)n + 1);
-    hw.hsize = alloc<uint64_t>((uint64_t)n + 1);
-    hw.hoff = alloc<uint64_t>((uint64_t)n + 1);
-    hw.icnt = alloc<uint64_t>((uint64_t)n + 1);
-    hw.ioff = alloc<uint64_t>((uint64_t)n + 1);
-    hw.scnt = alloc<uint64_t>((uint64_t)n + 1);
-    hw.soff = alloc<uint64_t>((uint64_t)n + 1);
+    hw.cnt = alloc<U64x3>((uint64_t)n + 1);
+    hw.off = alloc<U64x3>((uint64_t)n + 1);
     hw.own = alloc<int64_t>((uint64_t)n + 1);
     cand.v = alloc<uint32_t>(n);
     cand.a = alloc<uint32_t>(n);
@@ -379,10 +399,6 @@ struct Engine {
     cand.glo = alloc<uint64_t>(n);
     cand.ghi = alloc<int64_t>(n);
     cand.count = &ds->ps.ncand;
-    skey0 = alloc<uint64_t>(n);
-    skey1 = alloc<uint64_t>(n);
-    sidx0 = alloc<uint32_t>(n);
-    sidx1 = alloc<uint32_t>(n);
     hub.top = &ds->ps.hub_need;
     hub.over_count = &ds->ps.hub_over;
     hub_pool(4ull * n);
@@ -654,61 +670,61 @@ struct Engine {
   }
 
   // BestMove_r / BestRef_r over the list of set `sid` (its count stays on the device):
-  // candidates in `cand`.  One synchronisation reads back the scanned count, the candidate
-  // count and the pass counters.  With profiling, every candidate kernel is bracketed by HIP
-  // events on its stream and its algorithmic bytes follow from the counters it accumulates.
-  uint32_t best(int r, int sid, int refine, uint32_t& scanned) {
+  // candidates in `cand`, their count in ds->ps.ncand.  With profiling, every candidate
+  // kernel is bracketed by HIP events on its stream; its algorithmic bytes follow from the
+  // counters it accumulates, read back by best_finish.
+  void best_launch(int r, int sid, int refine) {
     MoveView mv = view(r, refine);
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
-    const int wide = lv[r].out.ref.wide;
-    const int cat0 = 10 * refine + 5 * wide;
-    const size_t first_pending = pending.size();
-    for (int attempt = 0;; ++attempt) {
-      hcheck(hipMemsetAsync(&ds->ps, 0, sizeof(PassScal), st));
-      launch_bin_count(mv, list, cnt, refine, bhist, st);
-      cub(prim_exclusive_sum_u32(&cub_tmp, &cub_bytes, bhist, boffs, kNumBins * kBinBlocks + 1, st));
-      launch_bin_fill(mv, list, cnt, refine, boffs, binbuf, ds->bin_start, ds->bins, st);
-      const uint32_t hb = hub_bound(r);
-      for (int b = 0; b < kNumBins; ++b) {
-        if (b == kNumBins - 1 && hb == 0) break;
-        MoveStats ms{&ds->ps.st_entries[b], &ds->ps.st_distinct[b], &ds->ps.st_vertices[b], &ds->ps.st_cands[b],
-                     &ds->ps.maxhi};
-        BinRef br{binbuf, &ds->bin_start[b], &ds->bins[b]};
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (profile) ev = next_events();
-        if (b < kNumBins - 1) {
-          if (profile) hcheck(hipEventRecord(ev.first, st));
-          launch_best(mv, b, br, n, refine, cand, ms, st);
-          if (profile) hcheck(hipEventRecord(ev.second, st));
-        } else {
-          // hubs: the events bracket the table-insert kernel, which reads the entries
-          cub(launch_hub(mv, br, hb, refine, hub, hw, cand, ms, &cub_tmp, &cub_bytes, st,
-                         profile ? ev.first : nullptr, profile ? ev.second : nullptr));
-        }
-        if (profile) pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
+    const int cat0 = 10 * refine + 5 * lv[r].out.ref.wide;
+    launch_bin_count(mv, list, cnt, refine, bhist, (uint32_t*)&ds->ps, sizeof(PassScal) / 4, st);
+    launch_bin_fill(mv, list, cnt, refine, bhist, binbuf, ds->bin_start, ds->bins, st);
+    const uint32_t hb = hub_bound(r);
+    for (int b = 0; b < kNumBins; ++b) {
+      if (b == kNumBins - 1 && hb == 0) break;
+      MoveStats ms{&ds->ps.st_entries[b], &ds->ps.st_distinct[b], &ds->ps.st_vertices[b], &ds->ps.st_cands[b],
+                   &ds->ps.maxhi};
+      BinRef br{binbuf, &ds->bin_start[b], &ds->bins[b]};
+      std::pair<hipEvent_t, hipEvent_t> ev{};
+      if (profile) ev = next_events();
+      if (b < kNumBins - 1) {
+        if (profile) hcheck(hipEventRecord(ev.first, st));
+        launch_best(mv, b, br, n, refine, cand, ms, st);
+        if (profile) hcheck(hipEventRecord(ev.second, st));
+      } else {
+        // hubs: the events bracket the table-insert kernel, which reads the entries
+        cub(launch_hub(mv, br, hb, refine, hub, hw, cand, ms, &cub_tmp, &cub_bytes, st, profile ? ev.first : nullptr,
+                       profile ? ev.second : nullptr));
       }
-      sync_read();
-      if (hs->ps.hub_over & 2u) throw DeviceError{hipErrorUnknown};
-      if (hs->ps.hub_over & 1u) {
-        if (attempt > 2) throw NoMem{};
-        hub_pool(hs->ps.hub_need);   // grow and redo the pass: its state is unchanged
-        pending.resize(first_pending);
-        continue;
-      }
-      break;
+      if (profile) pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
+    }
+  }
+
+  // After a synchronisation: false when the hub pool was too small (it has been grown and the
+  // pass must be redone; profiling records of the pass are dropped).  Otherwise the scanned
+  // count, the candidate count and the pass statistics.
+  bool best_finish(int r, int sid, int refine, size_t first_pending, uint32_t& scanned, uint32_t& K) {
+    const PassScal& ps = hs->ps;
+    if (ps.hub_over & 2u) throw DeviceError{hipErrorUnknown};
+    if (ps.hub_over & 1u) {
+      hub_pool(ps.hub_need);
+      pending.resize(first_pending);
+      return false;
     }
     scanned = hs->counts[sets[sid].ci];
+    K = ps.ncand;
     // algorithmic bytes: per vertex its list id, offsets and degrees, label, degrees and the
     // totals of its own community; per entry neighbour id, weight and neighbour label (plus
     // the parent in refinement); per distinct community its totals; per candidate 28 bytes.
     // The hub insert kernel reads per vertex its id, offsets, degrees and label, and the entries.
+    const int wide = lv[r].out.ref.wide;
+    const int cat0 = 10 * refine + 5 * wide;
     const double wb = wide ? 8.0 : 4.0;
     const double dirf = directed ? 2.0 : 1.0;
     const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 0 : 8 * dirf);
     const double per_e = 4 + wb + 4 + (refine ? 4 : 0);
     const double per_d = 8 * dirf;
-    const PassScal& ps = hs->ps;
     for (int b = 0; b < kNumBins; ++b) {
       stats.scanned_vertices += ps.st_vertices[b];
       stats.scanned_entries += ps.st_entries[b];
@@ -723,59 +739,47 @@ struct Engine {
           if (pending[i].bin == cat0 + b) pending[i].bytes = bytes;
       }
     }
-    stats.candidates += ps.ncand;
-    return ps.ncand;
+    stats.candidates += K;
+    return true;
   }
 
-  // exact greedy filter over cand[0..K): accepted candidate indices in `acc`; returns count.
-  // The rounds read their live counts on the device; the host checks them every few rounds.
-  uint32_t decouple(uint32_t K, uint64_t maxhi) {
-    if (K == 0) return 0;
-    // order by (gain descending, vertex ascending) with stable radix passes
-    launch_iota(sidx0, K, st);
-    launch_gather_u32_as_u64(cand.v, nullptr, K, skey0, st);
-    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, id_bits, st));
-    launch_gather_u64(cand.glo, sidx1, K, skey0, 1, st);
-    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx1, sidx0, K, 0, 64, st));
-    uint32_t* order = sidx0;
-    if (maxhi != 0) {
-      launch_gather_u64((const uint64_t*)cand.ghi, sidx0, K, skey0, 1, st);
-      cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, skey0, skey1, sidx0, sidx1, K, 0, 64, st));
-      order = sidx1;
-    }
-    launch_rank_from_order(order, K, rank, st);
+  // ---- exact greedy filter over the candidates (Sec. III-E), count read on the device:
+  // accepted candidate indices are appended to `acc`, their count in ds->nacc
+  static constexpr int kLfRounds = 4;   // rounds launched before the host looks
+  void decouple_start() {
     if (++acc_epoch == 0) {
       launch_fill_u32(accE, 0, n, st);
       launch_fill_u32(accA, 0, n, st);
       acc_epoch = 1;
     }
-    hcheck(hipMemsetAsync(lfflag, 0, K, st));
-    launch_iota(liveA, K, st);
-    zero(&ds->nacc);
-    hcheck(hipMemsetD32Async((hipDeviceptr_t)&ds->nlive[0], K, 1, st));
-    constexpr int kRoundsPerCheck = 4;
-    uint32_t *la = liveA, *lb = liveB;
-    int ca = 0;   // index of la's count in nlive
-    uint32_t known = K;
-    for (;;) {
-      for (int k = 0; k < kRoundsPerCheck; ++k) {
-        uint32_t* na_ = &ds->nlive[ca];
-        uint32_t* nb_ = &ds->nlive[1 - ca];
-        launch_lf_reset(la, na_, K, cand.a, cand.b, minE, minA, nb_, st);
-        launch_lf_min(la, na_, K, cand.a, cand.b, rank, minE, minA, st);
-        launch_lf_accept(la, na_, K, cand.a, cand.b, rank, minE, minA, accE, accA, acc_epoch, lfflag, acc, &ds->nacc,
-                         st);
-        launch_lf_reject(la, na_, K, cand.a, cand.b, accE, accA, acc_epoch, lfflag, lb, nb_, st);
-        std::swap(la, lb);
-        ca = 1 - ca;
-      }
+    launch_lf_init(&ds->ps.ncand, n, liveA, lfflag, &ds->nlive[0], &ds->nacc, st);
+    lf_la = liveA;
+    lf_lb = liveB;
+    lf_ca = 0;
+    decouple_rounds(kLfRounds);
+  }
+  void decouple_rounds(int rounds) {
+    for (int k = 0; k < rounds; ++k) {
+      launch_lf_round(lf_la, &ds->nlive[lf_ca], n, cand, lfE, lfA, accE, accA, acc_epoch, lfflag, acc, &ds->nacc,
+                      lf_lb, &ds->nlive[1 - lf_ca], st);
+      std::swap(lf_la, lf_lb);
+      lf_ca = 1 - lf_ca;
+      stats.lf_rounds++;
+    }
+  }
+  // after a synchronisation: finish the filter when candidates are still live; returns the
+  // index where the newly accepted candidates start (the total is then in hs->nacc)
+  uint32_t decouple_finish() {
+    const uint32_t na1 = hs->nacc;
+    uint32_t known = hs->nlive[lf_ca];
+    while (known) {
+      decouple_rounds(kLfRounds);
       sync_read();
-      const uint32_t nl = hs->nlive[ca];
-      if (nl == 0) break;
+      const uint32_t nl = hs->nlive[lf_ca];
       if (nl >= known) throw DeviceError{hipErrorUnknown};   // every round accepts a candidate
       known = nl;
     }
-    return hs->nacc;
+    return na1;
   }
 
   void record(int r, int phase, int iter, uint64_t nscan, uint64_t ncand, uint64_t nacc, i128 dq) {
@@ -787,27 +791,60 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ move commit
-  // commit the na accepted moves (count on the device at ds->nacc); one synchronisation reads
-  // the exact change of Ein and of sum Kout*Kin
-  i128 commit_moves(int r, uint32_t na, int64_t& dein, i128& dskk) {
+  // commit the accepted moves acc[0..*nap) (count on the device): labels and totals, and the
+  // exact change of Ein and of sum Kout*Kin into ds->dein / ds->dskk_{lo,hi}
+  void commit_launch(int r, const uint32_t* accp, const uint32_t* nap) {
     Level& V = lv[r];
-    const uint32_t* nap = &ds->nacc;
-    begin(S_TOUCH);
+    begin_epoch(S_TOUCH);   // its count for the commit is ps.ntouch, cleared with the pass counters
     begin(S_MOV);
-    launch_commit_mark(acc, nap, na, cand, sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, Kout, Kin, ref(S_TOUCH),
-                       tko, tki, st);
-    launch_commit_apply(acc, nap, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
-    zero(&ds->dein);
-    zero(&ds->dskk_lo);
-    zero(&ds->dskk_hi);
-    launch_commit_dein(acc, nap, na, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
-                       sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, &ds->dein, st);
-    launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], 2 * na, Kout, Kin, tko, tki, &ds->dskk_lo,
-                &ds->dskk_hi, st);
-    sync_read();
-    dein = hs->dein;
-    dskk = ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
-    return (i128)gq * m * dein - (i128)gp * dskk;
+    SetRef touched{sets[S_TOUCH].stamp, sets[S_TOUCH].list, &ds->ps.ntouch, sets[S_TOUCH].epoch};
+    launch_commit_mark(accp, nap, n, cand, sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, Kout, Kin, touched, tko,
+                       tki, st);
+    launch_commit_apply(accp, nap, n, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
+    launch_commit_dein(accp, nap, n, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
+                       sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, &ds->ps.cdein, st);
+    launch_dskk(sets[S_TOUCH].list, &ds->ps.ntouch, n, Kout, Kin, tko, tki, &ds->ps.cdskk_lo, &ds->ps.cdskk_hi, st);
+  }
+  i128 read_dskk() const { return ((i128)hs->ps.cdskk_hi << 64) | (i128)hs->ps.cdskk_lo; }
+
+  // One speculative local-move (refine = 0) or refinement (refine = 1) iteration over set sid:
+  // candidates, decoupling rounds and the commit are queued together and read back by one
+  // synchronisation.  A hub-pool overflow undoes the commit and redoes the iteration; live
+  // candidates after the first rounds are finished and committed as a second phase (the
+  // changes of Ein and sum Kout*Kin add up over the phases).
+  void iterate(int r, int sid, int refine, uint32_t& scanned, uint32_t& K, uint32_t& na, int64_t& dein, i128& dskk) {
+    Level& V = lv[r];
+    Level* H = refine ? &lv[r + 1] : nullptr;
+    int64_t* Krin = (refine && directed) ? H->kin : nullptr;
+    auto commit = [&](const uint32_t* accp, const uint32_t* nap, int forward) {
+      if (refine) launch_ref_commit(accp, nap, n, cand, V.par, V.kout, V.kin, H->kout, Krin, V.rsize, forward, st);
+      else if (forward) commit_launch(r, accp, nap);
+      else launch_commit_apply(accp, nap, n, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
+    };
+    for (int attempt = 0;; ++attempt) {
+      const size_t fp = pending.size();
+      best_launch(r, sid, refine);
+      decouple_start();
+      commit(acc, &ds->nacc, 1);
+      sync_read();
+      if (best_finish(r, sid, refine, fp, scanned, K)) break;
+      commit(acc, &ds->nacc, 0);   // undo: the candidate set was incomplete
+      if (attempt > 2) throw NoMem{};
+    }
+    dein = refine ? 0 : hs->ps.cdein;
+    dskk = refine ? 0 : read_dskk();
+    const uint32_t na1 = decouple_finish();
+    na = hs->nacc;
+    if (na > na1) {
+      hcheck(hipMemsetD32Async((hipDeviceptr_t)&ds->nacc2, (int)(na - na1), 1, st));
+      hcheck(hipMemsetAsync(&ds->ps.cdein, 0, 32, st));   // cdein, cdskk_lo/hi, ntouch
+      commit(acc + na1, &ds->nacc2, 1);
+      sync_read();
+      if (!refine) {
+        dein += hs->ps.cdein;
+        dskk += read_dskk();
+      }
+    }
   }
 
   // ------------------------------------------------------------------ one level
@@ -833,20 +870,19 @@ struct Engine {
       // scan set: the frontier and its neighbours (counts stay on the device)
       begin(S_S);
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
-      cub(launch_items(sets[S_U].list, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off, nullptr,
+      cub(launch_items(sets[S_U].list, nullptr, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off, nullptr,
                        nullptr, &cub_tmp, &cub_bytes, st));
       launch_mark_items(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, &ds->counts[sets[S_U].ci], n, it_off,
                         V.out.ref, in_or_none, st);
       select_set(S_S);
-      uint32_t nS = 0;
-      const uint32_t K = best(r, S_S, 0, nS);
-      const uint32_t na = decouple(K, hs->ps.maxhi);
+      uint32_t nS = 0, K = 0, na = 0;
       int64_t dein = 0;
       i128 dskk = 0;
-      const i128 dq = commit_moves(r, na, dein, dskk);
+      iterate(r, S_S, 0, nS, K, na, dein, dskk);
+      const i128 dq = (i128)gq * m * dein - (i128)gp * dskk;
       record(r, 0, j, nS, K, na, dq);
       const uint32_t* nap = &ds->nacc;
-      if (dq < 0) {  // Alg. 1 l.11
+      if (dq < 0) {  // Alg. 1 l.11: undo every accepted move of the iteration
         launch_commit_apply(acc, nap, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
         stats.rollbacks++;
         break;
@@ -855,6 +891,9 @@ struct Engine {
       SKK += dskk;
       stats.accepted += na;
       launch_set_add_acc_v(ref(S_MOVED), acc, nap, na, cand, st);
+      if ((i128)ad * dq < (i128)an * Q0) break;            // Alg. 1 l.13
+      if ((i128)bd * na < (i128)bn * nS) break;           // Alg. 1 l.14
+      if (j == M) break;                                  // the next frontier would not be used
       // Expand_r: movers, their neighbours, members of the touched communities
       begin(S_U2);
       if (na) {
@@ -865,10 +904,10 @@ struct Engine {
         launch_mark_neighbours_acc(sets[S_U2].stamp, sets[S_U2].epoch, acc, nap, na, cand, V.out.ref, in, directed,
                                    st);
         select_set(S_U2);
+      } else {
+        zero(&ds->counts[sets[S_U2].ci]);
       }
       std::swap(sets[S_U], sets[S_U2]);
-      if ((i128)ad * dq < (i128)an * Q0) break;            // Alg. 1 l.13
-      if ((i128)bd * na < (i128)bn * nS) break;           // Alg. 1 l.14
     }
     if (r < L) refine(r, E0);
     sync_read();
@@ -899,16 +938,19 @@ struct Engine {
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.refine_iters++;
-      uint32_t Rc = 0;
-      const uint32_t K = best(r, cur, 1, Rc);
-      const uint32_t na = decouple(K, hs->ps.maxhi);
+      uint32_t Rc = 0, K = 0, na = 0;
+      int64_t dein_unused = 0;
+      i128 dskk_unused = 0;
+      iterate(r, cur, 1, Rc, K, na, dein_unused, dskk_unused);
       const uint32_t* nap = &ds->nacc;
-      launch_ref_commit(acc, nap, na, cand, V.par, V.kout, V.kin, H.kout, Krin, V.rsize, st);
       stats.refine_moves += na;
       record(r, 1, j, Rc, K, na, 0);
       if ((i128)bd * na < (i128)bn * Rc) break;            // Alg. 1 l.20
       begin(S_RCUR);
-      launch_spexpand(acc, nap, na, cand, V.out.ref, in, directed, V.lab, V.par, V.rsize, sets[S_RCUR].stamp,
+      const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
+      cub(launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, nullptr, nullptr, &cub_tmp,
+                       &cub_bytes, st));
+      launch_spexpand(cand.v, acc, nap, na, it_off, V.out.ref, in_or_none, V.lab, V.par, V.rsize, sets[S_RCUR].stamp,
                       sets[S_RCUR].epoch, sets[S_RSET].stamp, sets[S_RSET].epoch, oldpar, st);
       select_set(S_RCUR);
       rset_grew = rset_grew || na > 0;
@@ -971,6 +1013,7 @@ struct Engine {
     // subtract-add tuples: reduce, apply at r+1 (degrees already exact), cascade upwards
     stats.agg_tuples += T;
     uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
+    stats.agg_records += R;
     if (R == 0) return;
     hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));

@@ -751,13 +751,18 @@ __device__ __forceinline__ void node_entry(const CsrRef& out, const CsrRef& in, 
   }
 }
 
-__global__ void k_item_counts(const uint32_t* list, const uint32_t* countp, uint32_t bound, CsrRef out, CsrRef in,
-                              uint64_t* icnt, uint64_t* zero_a, uint64_t* zero_b) {
+// node i of a list, through an optional index list
+__device__ __forceinline__ uint32_t list_node(const uint32_t* list, const uint32_t* idx, uint64_t i) {
+  return idx ? list[idx[i]] : list[i];
+}
+
+__global__ void k_item_counts(const uint32_t* list, const uint32_t* idx, const uint32_t* countp, uint32_t bound,
+                              CsrRef out, CsrRef in, uint64_t* icnt, uint64_t* zero_a, uint64_t* zero_b) {
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
   for (uint64_t i = gtid(); i <= bound; i += gstride()) {
     uint64_t c = 0;
-    if (i < cnt) c = (node_slots(out, in, list[i]) + kItem - 1) / kItem;
+    if (i < cnt) c = (node_slots(out, in, list_node(list, idx, i)) + kItem - 1) / kItem;
     icnt[i] = c;
     if (zero_a) zero_a[i] = 0;
     if (zero_b) zero_b[i] = 0;
@@ -901,6 +906,37 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
   });
 }
 
+// SPExpand over wavefront items of the refinement movers: their singleton neighbours with the
+// mover's label join Rcur; those new to Rset join it too, with their old parent (themselves)
+// recorded.  Plain-store marks (every writer of a word stores the same value); the lists
+// come from a select.
+__global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, const uint32_t* countp, uint32_t bound,
+                                 const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
+                                 const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
+                                 uint32_t rset_ep, uint32_t* oldpar) {
+  const int lane = lane_id();
+  const uint32_t c0 = *countp;
+  const uint32_t cnt = c0 < bound ? c0 : bound;
+  wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
+    const uint32_t v = list_node(movers, idx, i);
+    const uint32_t lv = lab[v];
+    const uint32_t dout = out.deg[v];
+    const uint64_t s = node_slots(out, in, v);
+    const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
+    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
+      uint32_t x;
+      int64_t w;
+      node_entry(out, in, v, dout, j, x, w);
+      if (x == v || lab[x] != lv || par[x] != x || rsize[x] != 1) continue;
+      rcur_stamp[x] = rcur_ep;
+      if (rset_stamp[x] != rset_ep) {
+        oldpar[x] = x;
+        rset_stamp[x] = rset_ep;
+      }
+    }
+  });
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -913,10 +949,18 @@ void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uin
                          const uint32_t* oldpar, hipStream_t s) {
   if (nr) k_mark_changed<<<grid_for(nr), kTpb, 0, s>>>(stamp, ep, rset, nr, par, oldpar);
 }
-int launch_items(const uint32_t* list, const uint32_t* count, uint32_t bound, CsrRef out, CsrRef in, uint64_t* icnt,
-                 uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp, size_t* tmp_bytes, hipStream_t s) {
-  k_item_counts<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(list, count, bound, out, in, icnt, zero_a, zero_b);
+int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
+                 CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
+                 size_t* tmp_bytes, hipStream_t s) {
+  k_item_counts<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(list, idx, count, bound, out, in, icnt, zero_a, zero_b);
   return prim_exclusive_sum_u64(tmp, tmp_bytes, icnt, ioff, (uint64_t)bound + 1, s);
+}
+void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t* count, uint32_t bound,
+                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
+                     const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
+                     uint32_t rset_ep, uint32_t* oldpar, hipStream_t s) {
+  k_spexpand_items<<<kItemBlocks, kTpb, 0, s>>>(movers, idx, count, bound, ioff, out, in, lab, par, rsize, rcur_stamp,
+                                                rcur_ep, rset_stamp, rset_ep, oldpar);
 }
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
                        const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s) {

@@ -129,8 +129,11 @@ __device__ __forceinline__ int bin_of(const MoveView& mv, uint32_t v, int refine
 }
 
 // block b owns list[b*chunk, (b+1)*chunk); hist[bin * gridDim + b] = its count per bin
-__global__ void k_bin_count(MoveView mv, const uint32_t* list, const uint32_t* countp, int refine, uint32_t* hist) {
+__global__ void k_bin_count(MoveView mv, const uint32_t* list, const uint32_t* countp, int refine, uint32_t* hist,
+                            uint32_t* zero_words, uint32_t nzero) {
   __shared__ uint32_t h[kNumBins];
+  if (blockIdx.x == 0)
+    for (uint32_t t = threadIdx.x; t < nzero; t += blockDim.x) zero_words[t] = 0;
   if (threadIdx.x < kNumBins) h[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t count = *countp;
@@ -145,17 +148,42 @@ __global__ void k_bin_count(MoveView mv, const uint32_t* list, const uint32_t* c
   if (threadIdx.x < kNumBins) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void k_bin_fill(MoveView mv, const uint32_t* list, const uint32_t* countp, int refine, const uint32_t* offs,
-                           uint32_t* out, uint32_t* bin_start, uint32_t* bin_count) {
+// every block reduces the per-block histograms itself (kBinBlocks words per bin): its start in
+// each bin is the sum of the earlier bins plus the earlier blocks' counts of that bin
+__global__ __launch_bounds__(kTpb) void k_bin_fill(MoveView mv, const uint32_t* list, const uint32_t* countp,
+                                                   int refine, const uint32_t* hist, uint32_t* out,
+                                                   uint32_t* bin_start, uint32_t* bin_count) {
+  __shared__ uint32_t red[2 * kNumBins][kTpb / kWave];
   __shared__ uint32_t pos[kNumBins];
+  const unsigned nb = gridDim.x;   // == kBinBlocks <= kTpb
   const uint32_t count = *countp;
-  const unsigned nb = gridDim.x;
-  if (threadIdx.x < kNumBins) pos[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
-  if (blockIdx.x == 0 && threadIdx.x < kNumBins) {
-    const uint32_t start = offs[threadIdx.x * nb];
-    const uint32_t end = threadIdx.x + 1 < kNumBins ? offs[(threadIdx.x + 1) * nb] : offs[kNumBins * nb];
-    bin_start[threadIdx.x] = start;
-    bin_count[threadIdx.x] = end - start;
+  const int w = threadIdx.x / kWave;
+#pragma unroll
+  for (int t = 0; t < kNumBins; ++t) {
+    const uint32_t x = threadIdx.x < nb ? hist[t * nb + threadIdx.x] : 0u;
+    const uint32_t all = (uint32_t)wave_sum_i64((int64_t)x);
+    const uint32_t before = (uint32_t)wave_sum_i64(threadIdx.x < blockIdx.x ? (int64_t)x : 0);
+    if (lane_id() == 0) {
+      red[2 * t][w] = all;
+      red[2 * t + 1][w] = before;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t base = 0;
+    for (int t = 0; t < kNumBins; ++t) {
+      uint32_t all = 0, before = 0;
+      for (int q = 0; q < (int)(blockDim.x / kWave); ++q) {
+        all += red[2 * t][q];
+        before += red[2 * t + 1][q];
+      }
+      pos[t] = base + before;
+      if (blockIdx.x == 0) {
+        bin_start[t] = base;
+        bin_count[t] = all;
+      }
+      base += all;
+    }
   }
   __syncthreads();
   const uint64_t chunk = ((uint64_t)count + nb - 1) / nb;
@@ -465,12 +493,13 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
 }
 
 // ---- hubs split over many workgroups, driven from device counts.  Hub i (of the bin's h
-// vertices) owns a table of hsize[i] = pow2 >= max(64, 2 T_i) slots at hoff[i] in the pool.
-// Insert items (icnt[i] chunks of kHubChunk entries, pre-aggregated in LDS) fill the tables;
-// scan items (scnt[i] slices of kHubScan slots) evaluate the gains into partial bests at
-// soff[i] + slice and return their slots to empty; one wavefront per hub reduces the partials.
-// Hubs whose table ends beyond the pool are skipped and reported (bit 0 of *over, with the
-// required size in *need); more than `bound` hubs is reported as bit 1.
+// vertices) owns a table of pow2 >= max(64, 2 T_i) slots in the pool, has ceil(T_i / kHubChunk)
+// insert items (entry chunks pre-aggregated in LDS) and one scan item per kHubScan table
+// slots; one exclusive scan of the three counts places tables, items and partial bests.
+// Scan items evaluate the gains into partial bests and return their slots to empty; one
+// wavefront per hub reduces the partials.  Hubs whose table ends beyond the pool are
+// skipped and reported (bit 0 of *over, with the pool size needed in *need); more than
+// `bound` hubs is reported as bit 1.
 constexpr uint32_t kHubChunk = 2048;
 constexpr uint32_t kHubScan = kHubScanSlots;
 
@@ -479,81 +508,65 @@ __device__ __forceinline__ uint32_t hub_count(const BinRef& br, uint32_t bound) 
   return c < bound ? c : bound;
 }
 
-// largest i in [0, h) with off[i] <= it, for non-decreasing off with off[h] > it
-__device__ __forceinline__ uint32_t item_owner(const uint64_t* off, uint32_t h, uint64_t it) {
+__device__ __forceinline__ uint64_t entries_of(const MoveView& mv, uint32_t v) {
+  return (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
+}
+
+// largest i in [0, h) with off[i].F <= it, for off non-decreasing in F with off[h].F > it
+template <int F>
+__device__ __forceinline__ uint32_t item_owner(const U64x3* off, uint32_t h, uint64_t it) {
   uint32_t lo = 0, hi = h;   // off[lo] <= it < off[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= it) lo = mid;
+    const uint64_t x = F == 1 ? off[mid].y : off[mid].z;
+    if (x <= it) lo = mid;
     else hi = mid;
   }
   return lo;
 }
 
-__device__ __forceinline__ uint64_t entries_of(const MoveView& mv, uint32_t v) {
-  return (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
-}
-
-__global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, uint64_t* hsize) {
-  const uint32_t h = hub_count(br, bound);
-  const uint32_t* list = br.base + *br.start;
-  for (uint64_t i = gtid(); i <= bound; i += gstride()) {
-    uint64_t size = 0;
-    if (i < h) {
-      const uint64_t T = entries_of(mv, list[i]);
-      size = 64;
-      while (size < 2 * T) size <<= 1;
-    }
-    hsize[i] = size;
-  }
-}
-
-__global__ void k_hub_plan(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff, uint64_t cap, uint64_t* icnt,
-                           uint64_t* scnt, int64_t* own, u64a* need, uint32_t* over) {
+__global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, U64x3* cnt, int64_t* own, uint32_t* over) {
   const uint32_t c = *br.count;
   const uint32_t h = c < bound ? c : bound;
   const uint32_t* list = br.base + *br.start;
+  if (gtid() == 0 && c > bound) atomicOr(over, 2u);
   for (uint64_t i = gtid(); i <= bound; i += gstride()) {
-    uint64_t ic = 0, sc = 0;
-    if (i < h && hoff[i + 1] <= cap) {
+    U64x3 x{0, 0, 0};
+    if (i < h) {
       const uint64_t T = entries_of(mv, list[i]);
-      ic = (T + kHubChunk - 1) / kHubChunk;
-      sc = (hoff[i + 1] - hoff[i] + kHubScan - 1) / kHubScan;
+      uint64_t size = 64;
+      while (size < 2 * T) size <<= 1;
+      x.x = size;
+      x.y = (T + kHubChunk - 1) / kHubChunk;
+      x.z = (size + kHubScan - 1) / kHubScan;
       own[i] = 0;
     }
-    icnt[i] = ic;
-    scnt[i] = sc;
-  }
-  if (gtid() == 0) {
-    const uint64_t total = hoff[h];
-    *need = total;
-    uint32_t f = 0;
-    if (total > cap) f |= 1u;
-    if (c > bound) f |= 2u;
-    if (f) atomicOr(over, f);
+    cnt[i] = x;
   }
 }
 
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff,
-                                                     const uint64_t* ioff, HubPool hub, int64_t* own, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
+                                                     HubPool hub, int64_t* own, MoveStats st) {
   __shared__ int64_t red[kTpb / kWave];
   __shared__ uint32_t lkey[2 * kHubChunk];
   __shared__ u64a lval[2 * kHubChunk];
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
-  const uint64_t total = ioff[h];
+  const uint64_t total = off[h].y;
   uint64_t nent = 0;
   for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t i = item_owner(ioff, h, it);
+    const uint32_t i = item_owner<1>(off, h, it);
+    const uint64_t base = off[i].x;
+    const uint64_t size = off[i + 1].x - base;
+    if (base + size > hub.cap) continue;       // table beyond the pool: reported by k_hub_final
     const uint32_t v = list[i];
     const uint32_t dout = mv.out.deg[v];
     const uint32_t din = DIR ? mv.in.deg[v] : 0;
     const uint32_t T = dout + din;
-    const uint64_t e0 = (it - ioff[i]) * kHubChunk;
+    const uint64_t e0 = (it - off[i].y) * kHubChunk;
     const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
-    const uint64_t base = hoff[i];
-    const uint32_t mask = (uint32_t)(hoff[i + 1] - base - 1);
+    const uint32_t mask = (uint32_t)(size - 1);
     uint32_t* keys = hub.keys + base;
     u64a* vals = hub.vals + base;
     const uint32_t labv = mv.lab[v];
@@ -591,20 +604,21 @@ __global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uin
 }
 
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_hub_scan(MoveView mv, BinRef br, uint32_t bound, const uint64_t* hoff,
-                                                   const uint64_t* soff, HubPool hub, const int64_t* own, int64_t* phi,
-                                                   uint64_t* plo, uint32_t* pid, int* pvalid, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_hub_scan(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
+                                                   HubPool hub, const int64_t* own, int64_t* phi, uint64_t* plo,
+                                                   uint32_t* pid, int* pvalid, MoveStats st) {
   __shared__ Best red_b[kTpb / kWave];
   __shared__ int64_t red_i[kTpb / kWave];
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
-  const uint64_t total = soff[h];
+  const uint64_t total = off[h].z;
   uint64_t ndist = 0;
   for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t i = item_owner(soff, h, it);
-    const uint64_t base = hoff[i];
-    const uint64_t size = hoff[i + 1] - base;
-    const uint64_t s0 = (it - soff[i]) * kHubScan;
+    const uint32_t i = item_owner<2>(off, h, it);
+    const uint64_t base = off[i].x;
+    const uint64_t size = off[i + 1].x - base;
+    if (base + size > hub.cap) continue;
+    const uint64_t s0 = (it - off[i].z) * kHubScan;
     const uint64_t s1 = s0 + kHubScan < size ? s0 + kHubScan : size;
     const uint32_t v = list[i];
     const VInfo vi = vinfo<DIR, REF>(mv, v);
@@ -637,14 +651,20 @@ __global__ __launch_bounds__(kTpb) void k_hub_scan(MoveView mv, BinRef br, uint3
 }
 
 template <bool REF>
-__global__ void k_hub_final(BinRef br, uint32_t bound, const uint64_t* soff, const uint32_t* lab, const int64_t* phi,
-                            const uint64_t* plo, const uint32_t* pid, const int* pvalid, CandBuf cand, MoveStats st) {
+__global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_t cap, const uint32_t* lab,
+                            const int64_t* phi, const uint64_t* plo, const uint32_t* pid, const int* pvalid,
+                            CandBuf cand, MoveStats st, u64a* need, uint32_t* over) {
   const int lane = lane_id();
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
+  if (gtid() == 0) {
+    const uint64_t total = off[h].x;
+    *need = total;
+    if (total > cap) atomicOr(over, 1u);
+  }
   for (uint64_t i = gwave(); i < h; i += gwstride()) {
-    const uint64_t p0 = soff[i], p1 = soff[i + 1];
-    if (p0 == p1) continue;                  // skipped: table beyond the pool
+    if (off[i + 1].x > cap) continue;          // skipped: table beyond the pool
+    const uint64_t p0 = off[i].z, p1 = off[i + 1].z;
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
     for (uint64_t p = p0 + lane; p < p1; p += kWave) {
@@ -668,20 +688,16 @@ __global__ void k_hub_final(BinRef br, uint32_t bound, const uint64_t* soff, con
 template <typename WT, bool DIR, bool REF>
 int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, HubWork hw, CandBuf cand, MoveStats st,
                  void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-  const unsigned gb = grid_for((uint64_t)bound + 1);
-  k_hub_size<<<gb, kTpb, 0, s>>>(mv, br, bound, hw.hsize);
-  int rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.hsize, hw.hoff, (uint64_t)bound + 1, s);
+  k_hub_size<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(mv, br, bound, hw.cnt, hw.own, hub.over_count);
+  const int rc = prim_exclusive_sum_u64x3(tmp, tmp_bytes, hw.cnt, hw.off, (uint64_t)bound + 1, s);
   if (rc) return rc;
-  k_hub_plan<<<gb, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hub.cap, hw.icnt, hw.scnt, hw.own, hub.top, hub.over_count);
-  if ((rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.icnt, hw.ioff, (uint64_t)bound + 1, s))) return rc;
-  if ((rc = prim_exclusive_sum_u64(tmp, tmp_bytes, hw.scnt, hw.soff, (uint64_t)bound + 1, s))) return rc;
   if (ev_a) (void)hipEventRecord(ev_a, s);
-  k_hub_insert<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hw.ioff, hub, hw.own, st);
+  k_hub_insert<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.off, hub, hw.own, st);
   if (ev_b) (void)hipEventRecord(ev_b, s);
-  k_hub_scan<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.hoff, hw.soff, hub, hw.own, hw.phi,
-                                                           hw.plo, hw.pid, hw.pvalid, st);
-  k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.soff, mv.lab, hw.phi, hw.plo, hw.pid, hw.pvalid,
-                                                      cand, st);
+  k_hub_scan<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.off, hub, hw.own, hw.phi, hw.plo, hw.pid,
+                                                           hw.pvalid, st);
+  k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.off, hub.cap, mv.lab, hw.phi, hw.plo, hw.pid,
+                                                      hw.pvalid, cand, st, hub.top, hub.over_count);
   return 0;
 }
 
@@ -712,70 +728,103 @@ void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, C
 }
 
 // ------------------------------------------------------------------ decouple rounds
-// Candidates in rank order (gain descending, vertex ascending).  Candidate i conflicts with j
-// when a_i == b_j or b_i == a_j.  The sequential filter accepts a candidate iff no earlier
-// accepted candidate conflicts with it, i.e. it returns the lexicographically first maximal
-// independent set of the conflict graph; each round accepts every live candidate without an
-// earlier live conflict and drops the live candidates that conflict with an accepted one.
+// Candidates are ordered by gain (descending), then vertex id (ascending).  Candidate i
+// conflicts with j when a_i == b_j or b_i == a_j.  The sequential filter accepts a candidate
+// iff no earlier accepted candidate conflicts with it, i.e. it returns the lexicographically
+// first maximal independent set of the conflict graph.  Each round accepts every live
+// candidate that precedes all live candidates entering its source and all live candidates
+// leaving its target, then drops the live candidates that conflict with an accepted one.
+// The first live candidate leaving (E) and entering (A) each community is found exactly,
+// without a sort, by three atomic passes: max of the gain's high word, max of the low word
+// among those with that high word, min of the vertex among those with both.  The
+// per-community words are empty between rounds: each round's reject kernel clears the ones
+// its live candidates wrote.
+__device__ __forceinline__ uint32_t dev_count(const uint32_t* p, uint32_t bound) {
+  const uint32_t c = *p;
+  return c < bound ? c : bound;
+}
 
-__global__ void k_rank_from_order(const uint32_t* order, uint32_t k, uint32_t* rank) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) rank[order[i]] = (uint32_t)i;
-}
-__global__ void k_gather_u64(const uint64_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, int invert) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const uint64_t x = src[idx[i]];
-    dst[i] = invert ? ~x : x;
+__global__ void k_lf_init(const uint32_t* kp, uint32_t bound, uint32_t* live, uint8_t* flag, uint32_t* nlive,
+                          uint32_t* nacc) {
+  const uint32_t K = dev_count(kp, bound);
+  if (gtid() == 0) {
+    *nlive = K;
+    *nacc = 0;
+  }
+  for (uint64_t i = gtid(); i < K; i += gstride()) {
+    live[i] = (uint32_t)i;
+    flag[i] = 0;
   }
 }
-__global__ void k_gather_u32_as_u64(const uint32_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) dst[i] = idx ? src[idx[i]] : src[i];
-}
-__global__ void k_lf_reset(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
-                           uint32_t* minE, uint32_t* minA, uint32_t* out_count) {
-  const uint32_t nl = *nlp;
-  if (gtid() == 0) *out_count = 0;
+
+template <int PASS>
+__global__ void k_lf_pass(const uint32_t* live, const uint32_t* nlp, uint32_t bound, CandBuf cand, LfFirst E,
+                          LfFirst A) {
+  const uint32_t nl = dev_count(nlp, bound);
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
-    minE[a[i]] = kEmpty; minA[a[i]] = kEmpty;
-    minE[b[i]] = kEmpty; minA[b[i]] = kEmpty;
+    const uint32_t a = cand.a[i], b = cand.b[i];
+    const u64a hi = (u64a)cand.ghi[i], lo = cand.glo[i];
+    if (PASS == 0) {
+      atomicMax(&E.hi[a], hi);
+      atomicMax(&A.hi[b], hi);
+    } else if (PASS == 1) {
+      if (E.hi[a] == hi) atomicMax(&E.lo[a], lo);
+      if (A.hi[b] == hi) atomicMax(&A.lo[b], lo);
+    } else {
+      const uint32_t v = cand.v[i];
+      if (E.hi[a] == hi && E.lo[a] == lo) atomicMin(&E.v[a], v);
+      if (A.hi[b] == hi && A.lo[b] == lo) atomicMin(&A.v[b], v);
+    }
   }
 }
-__global__ void k_lf_min(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
-                         const uint32_t* rank, uint32_t* minE, uint32_t* minA) {
-  const uint32_t nl = *nlp;
-  for (uint64_t t = gtid(); t < nl; t += gstride()) {
-    const uint32_t i = live[t];
-    atomicMin(&minE[a[i]], rank[i]);
-    atomicMin(&minA[b[i]], rank[i]);
-  }
+
+// candidate (hi, lo, v) precedes the first of a set (empty sets have v == kEmpty)
+__device__ __forceinline__ bool precedes_first(u64a hi, u64a lo, uint32_t v, const LfFirst& F, uint32_t c) {
+  const uint32_t fv = F.v[c];
+  if (fv == kEmpty) return true;
+  const u64a fh = F.hi[c], fl = F.lo[c];
+  if (hi != fh) return hi > fh;
+  if (lo != fl) return lo > fl;
+  return v < fv;
 }
-__global__ void k_lf_accept(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
-                            const uint32_t* rank, const uint32_t* minE, const uint32_t* minA, uint32_t* accE,
-                            uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count) {
-  const uint32_t nl = *nlp;
+
+__global__ void k_lf_accept(const uint32_t* live, const uint32_t* nlp, uint32_t bound, CandBuf cand, LfFirst E,
+                            LfFirst A, uint32_t* accE, uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list,
+                            uint32_t* acc_count, uint32_t* next_count) {
+  const uint32_t nl = dev_count(nlp, bound);
+  if (gtid() == 0) *next_count = 0;   // the reject kernel appends the survivors
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
-    const uint32_t r = rank[i];
-    // no live earlier candidate enters my source or leaves my target
-    const bool ok = minA[a[i]] > r && minE[b[i]] > r;
+    const uint32_t a = cand.a[i], b = cand.b[i];
+    const u64a hi = (u64a)cand.ghi[i], lo = cand.glo[i];
+    const uint32_t v = cand.v[i];
+    // no live candidate entering my source or leaving my target comes first
+    const bool ok = precedes_first(hi, lo, v, A, a) && precedes_first(hi, lo, v, E, b);
     const uint32_t at = wave_reserve(acc_count, ok);
     if (ok) {
       flag[i] = 1;
-      accE[a[i]] = ep;
-      accA[b[i]] = ep;
+      accE[a] = ep;
+      accA[b] = ep;
       acc_list[at] = i;
     }
   }
 }
-__global__ void k_lf_reject(const uint32_t* live, const uint32_t* nlp, const uint32_t* a, const uint32_t* b,
-                            const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag,
+
+// drops the live candidates that conflict with an accepted one and returns the per-community
+// words of this round's communities to their empty state for the next round
+__global__ void k_lf_reject(const uint32_t* live, const uint32_t* nlp, uint32_t bound, CandBuf cand, LfFirst E,
+                            LfFirst A, const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag,
                             uint32_t* live2, uint32_t* live2_count) {
-  const uint32_t nl = *nlp;
+  const uint32_t nl = dev_count(nlp, bound);
   for (uint64_t t = gtid(); t < nl; t += gstride()) {
     const uint32_t i = live[t];
-    const bool keep = !flag[i] && !(accA[a[i]] == ep || accE[b[i]] == ep);
+    const uint32_t a = cand.a[i], b = cand.b[i];
+    const bool keep = !flag[i] && !(accA[a] == ep || accE[b] == ep);
     const uint32_t at = wave_reserve(live2_count, keep);
     if (keep) live2[at] = i;
+    E.hi[a] = 0; E.lo[a] = 0; E.v[a] = kEmpty;
+    A.hi[b] = 0; A.lo[b] = 0; A.v[b] = kEmpty;
   }
 }
 
@@ -876,49 +925,28 @@ __global__ void k_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t*
     set_add(set.stamp, set.epoch, set.list, set.count, cand.v[acc[t]]);
 }
 
+// singleton u joins refined community y (forward) or returns to itself (undo)
 __global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* par,
-                             const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize) {
+                             const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize,
+                             int forward) {
   const uint32_t na = *nap;
   for (uint64_t t = gtid(); t < na; t += gstride()) {
     const uint32_t i = acc[t];
     const uint32_t u = cand.v[i], y = cand.b[i];
-    par[u] = y;
-    atomic_add_i64(&Krout[y], kout[u]);
-    atomic_add_i64(&Krout[u], -kout[u]);
+    const int64_t sg = forward ? 1 : -1;
+    par[u] = forward ? y : u;
+    atomic_add_i64(&Krout[y], sg * kout[u]);
+    atomic_add_i64(&Krout[u], -sg * kout[u]);
     if (Krin) {
-      atomic_add_i64(&Krin[y], kin[u]);
-      atomic_add_i64(&Krin[u], -kin[u]);
+      atomic_add_i64(&Krin[y], sg * kin[u]);
+      atomic_add_i64(&Krin[u], -sg * kin[u]);
     }
-    atomicAdd(&rsize[y], 1u);
-    atomicSub(&rsize[u], 1u);
-  }
-}
-
-// SPExpand: singleton neighbours of refinement movers that carry the mover's label join
-// Rcur; the ones new to Rset join it too, with their old parent (themselves) recorded.  Marks
-// are plain stores (every writer of a word stores the same value); lists come from a select.
-__global__ void k_spexpand(const uint32_t* acc, const uint32_t* nap, CandBuf cand, CsrRef out, CsrRef in,
-                           int directed, const uint32_t* lab, const uint32_t* par, const uint32_t* rsize,
-                           uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep,
-                           uint32_t* oldpar) {
-  const int lane = lane_id();
-  const uint32_t na = *nap;
-  for (uint64_t t = gwave(); t < na; t += gwstride()) {
-    const uint32_t v = cand.v[acc[t]];
-    const uint32_t lv = lab[v];
-    for (int side = 0; side < (directed ? 2 : 1); ++side) {
-      const CsrRef& c = side == 0 ? out : in;
-      const uint64_t o = c.off[v];
-      const uint32_t d = c.deg[v];
-      for (uint32_t j = lane; j < d; j += kWave) {
-        const uint32_t x = c.nbr[o + j];
-        if (x == v || lab[x] != lv || par[x] != x || rsize[x] != 1) continue;
-        rcur_stamp[x] = rcur_ep;
-        if (rset_stamp[x] != rset_ep) {
-          oldpar[x] = x;
-          rset_stamp[x] = rset_ep;
-        }
-      }
+    if (forward) {
+      atomicAdd(&rsize[y], 1u);
+      atomicSub(&rsize[u], 1u);
+    } else {
+      atomicSub(&rsize[y], 1u);
+      atomicAdd(&rsize[u], 1u);
     }
   }
 }
@@ -930,12 +958,13 @@ __global__ void k_spexpand(const uint32_t* acc, const uint32_t* nap, CandBuf can
 // upper bound (the grid-stride loops cover any count up to it).
 
 void launch_bin_count(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, uint32_t* hist,
-                      hipStream_t s) {
-  k_bin_count<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, hist);
+                      uint32_t* zero_words, uint32_t nzero, hipStream_t s) {
+  k_bin_count<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, hist, zero_words, nzero);
 }
-void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, const uint32_t* offs,
+void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, const uint32_t* hist,
                      uint32_t* out, uint32_t* bin_start, uint32_t* bin_count, hipStream_t s) {
-  k_bin_fill<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, offs, out, bin_start, bin_count);
+  static_assert(kBinBlocks <= kTpb, "one histogram word per thread");
+  k_bin_fill<<<kBinBlocks, kTpb, 0, s>>>(mv, list, count, refine, hist, out, bin_start, bin_count);
 }
 void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, const uint32_t* na,
                                 uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in, int directed, hipStream_t s) {
@@ -974,78 +1003,58 @@ int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPoo
 }
 #undef LDL_TYPED
 
-void launch_rank_from_order(const uint32_t* order, uint32_t k, uint32_t* rank, hipStream_t s) {
-  if (k) k_rank_from_order<<<grid_for(k), kTpb, 0, s>>>(order, k, rank);
+void launch_lf_init(const uint32_t* K, uint32_t bound, uint32_t* live, uint8_t* flag, uint32_t* nlive, uint32_t* nacc,
+                    hipStream_t s) {
+  k_lf_init<<<kLfBlocks, kTpb, 0, s>>>(K, bound, live, flag, nlive, nacc);
 }
-void launch_gather_u64(const uint64_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, int invert,
-                       hipStream_t s) {
-  if (k) k_gather_u64<<<grid_for(k), kTpb, 0, s>>>(src, idx, k, dst, invert);
+void launch_lf_round(const uint32_t* live, const uint32_t* nl, uint32_t bound, CandBuf cand, LfFirst E, LfFirst A,
+                     uint32_t* accE, uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list,
+                     uint32_t* acc_count, uint32_t* live2, uint32_t* live2_count, hipStream_t s) {
+  k_lf_pass<0><<<kLfBlocks, kTpb, 0, s>>>(live, nl, bound, cand, E, A);
+  k_lf_pass<1><<<kLfBlocks, kTpb, 0, s>>>(live, nl, bound, cand, E, A);
+  k_lf_pass<2><<<kLfBlocks, kTpb, 0, s>>>(live, nl, bound, cand, E, A);
+  k_lf_accept<<<kLfBlocks, kTpb, 0, s>>>(live, nl, bound, cand, E, A, accE, accA, ep, flag, acc_list, acc_count,
+                                        live2_count);
+  k_lf_reject<<<kLfBlocks, kTpb, 0, s>>>(live, nl, bound, cand, E, A, accE, accA, ep, flag, live2, live2_count);
 }
-void launch_gather_u32_as_u64(const uint32_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, hipStream_t s) {
-  if (k) k_gather_u32_as_u64<<<grid_for(k), kTpb, 0, s>>>(src, idx, k, dst);
-}
-void launch_lf_reset(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                     uint32_t* minE, uint32_t* minA, uint32_t* out_count, hipStream_t s) {
-  k_lf_reset<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, minE, minA, out_count);
-}
-void launch_lf_min(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                   const uint32_t* rank, uint32_t* minE, uint32_t* minA, hipStream_t s) {
-  if (nl_max) k_lf_min<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA);
-}
-void launch_lf_accept(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                      const uint32_t* rank, const uint32_t* minE, const uint32_t* minA, uint32_t* accE, uint32_t* accA,
-                      uint32_t ep, uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count, hipStream_t s) {
-  if (nl_max)
-    k_lf_accept<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, rank, minE, minA, accE, accA, ep, flag, acc_list,
-                                                  acc_count);
-}
-void launch_lf_reject(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                      const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag, uint32_t* live2,
-                      uint32_t* live2_count, hipStream_t s) {
-  if (nl_max)
-    k_lf_reject<<<grid_for(nl_max), kTpb, 0, s>>>(live, nl, a, b, accE, accA, ep, flag, live2, live2_count);
-}
+// grids for counts read on the device: at most kLfBlocks workgroups (grid-stride loops)
+inline unsigned cap_grid(unsigned g) { return g < kLfBlocks ? g : kLfBlocks; }
+
 void launch_commit_mark(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* mov_stamp,
                         uint32_t mov_ep, uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin, SetRef touched,
                         int64_t* tko, int64_t* tki, hipStream_t s) {
   if (na_max)
-    k_commit_mark<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, mov_stamp, mov_ep, oldlab, Kout, Kin, touched, tko,
-                                                    tki);
+    k_commit_mark<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, mov_stamp, mov_ep, oldlab, Kout, Kin,
+                                                              touched, tko, tki);
 }
 void launch_commit_apply(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* lab,
                          const int64_t* kout, const int64_t* kin, int64_t* Kout, int64_t* Kin_or_null, int forward,
                          hipStream_t s) {
   if (na_max)
-    k_commit_apply<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, lab, kout, kin, Kout, Kin_or_null, forward);
+    k_commit_apply<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, lab, kout, kin, Kout, Kin_or_null,
+                                                               forward);
 }
 void launch_commit_dein(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
                         int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
                         const uint32_t* oldlab, i64a* dein, hipStream_t s) {
   if (na_max)
-    k_commit_dein<<<grid_waves(na_max), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, mov_stamp, mov_ep,
-                                                      oldlab, dein);
+    k_commit_dein<<<cap_grid(grid_waves(na_max)), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, mov_stamp,
+                                                                mov_ep, oldlab, dein);
 }
 void launch_mark_acc_comms(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* stamp,
                            uint32_t ep, hipStream_t s) {
-  if (na_max) k_mark_acc_comms<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, stamp, ep);
+  if (na_max) k_mark_acc_comms<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, stamp, ep);
 }
 void launch_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand,
                           hipStream_t s) {
-  if (na_max) k_set_add_acc_v<<<grid_for(na_max), kTpb, 0, s>>>(set, acc, na, cand);
+  if (na_max) k_set_add_acc_v<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(set, acc, na, cand);
 }
 void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
                        const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize,
-                       hipStream_t s) {
+                       int forward, hipStream_t s) {
   if (na_max)
-    k_ref_commit<<<grid_for(na_max), kTpb, 0, s>>>(acc, na, cand, par, kout, kin, Krout, Krin_or_null, rsize);
-}
-void launch_spexpand(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
-                     int directed, const uint32_t* lab, const uint32_t* par, const uint32_t* rsize,
-                     uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep, uint32_t* oldpar,
-                     hipStream_t s) {
-  if (na_max)
-    k_spexpand<<<grid_waves(na_max), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, par, rsize, rcur_stamp,
-                                                   rcur_ep, rset_stamp, rset_ep, oldpar);
+    k_ref_commit<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, par, kout, kin, Krout, Krin_or_null, rsize,
+                                                             forward);
 }
 
 }  // namespace ldl

@@ -104,19 +104,23 @@ void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* ac
                                 uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in, int directed, hipStream_t s);
 void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
                          const uint32_t* oldpar, hipStream_t s);
-// degree binning without global atomics: per-block histograms, scan, fill
-constexpr unsigned kBinBlocks = 1024;
+// degree binning without global atomics: per-block histograms, then a fill whose blocks
+// derive their output positions from the histograms
+constexpr unsigned kBinBlocks = 256;
+// (the count kernel also clears zero_words[0..nzero), the counters of the pass that follows)
 void launch_bin_count(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, uint32_t* hist,
-                      hipStream_t s);
-void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, const uint32_t* offs,
+                      uint32_t* zero_words, uint32_t nzero, hipStream_t s);
+void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* count, int refine, const uint32_t* hist,
                      uint32_t* out, uint32_t* bin_start, uint32_t* bin_count, hipStream_t s);
 // wavefront items over a node list (count on the device, at most `bound` nodes): node i has
 // out.deg + in.deg entries (in only when in.off is set), split into items of kItem entries;
 // icnt/ioff hold bound + 1 words; zero_a / zero_b (optional, bound + 1 words) are cleared
 constexpr uint32_t kItem = 512;
 constexpr unsigned kItemBlocks = 2048;
-int launch_items(const uint32_t* list, const uint32_t* count, uint32_t bound, CsrRef out, CsrRef in, uint64_t* icnt,
-                 uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp, size_t* tmp_bytes, hipStream_t s);
+// (node i = list[idx[i]] when idx is given)
+int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
+                 CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
+                 size_t* tmp_bytes, hipStream_t s);
 // stamp[x] = ep for every listed node and every neighbour over its items
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
                        const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s);
@@ -186,15 +190,14 @@ void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int
 // hub bin, device driven: per-hub table sizes, insert chunks and scan parts are prefix-summed
 // over `bound` + 1 entries (bound >= number of hubs); hubs whose tables do not fit the pool are
 // skipped and flagged.  Work arrays hold bound + 1 entries, partials cap / kHubScanSlots + bound.
+struct U64x3 {
+  uint64_t x, y, z;
+};
 struct HubWork {
-  uint64_t* hsize;
-  uint64_t* hoff;
-  uint64_t* icnt;
-  uint64_t* ioff;
-  uint64_t* scnt;
-  uint64_t* soff;
-  int64_t* own;
-  int64_t* phi;
+  U64x3* cnt;     // per hub: table slots, insert items, scan items (bound + 1 entries)
+  U64x3* off;     // their exclusive prefix
+  int64_t* own;   // weight towards the own community, per hub
+  int64_t* phi;   // partial bests, one per scan item
   uint64_t* plo;
   uint32_t* pid;
   int* pvalid;
@@ -203,21 +206,21 @@ int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPoo
                MoveStats st, void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 
 // ---------------------------------------------------------------- decouple (exact greedy filter)
-void launch_rank_from_order(const uint32_t* order, uint32_t k, uint32_t* rank, hipStream_t s);
-void launch_gather_u64(const uint64_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, int invert,
-                       hipStream_t s);
-void launch_gather_u32_as_u64(const uint32_t* src, const uint32_t* idx, uint32_t k, uint64_t* dst, hipStream_t s);
-// rounds read the live count from device memory; lf_reset also zeroes the round's output count
-void launch_lf_reset(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                     uint32_t* minE, uint32_t* minA, uint32_t* out_count, hipStream_t s);
-void launch_lf_min(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                   const uint32_t* rank, uint32_t* minE, uint32_t* minA, hipStream_t s);
-void launch_lf_accept(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                      const uint32_t* rank, const uint32_t* minE, const uint32_t* minA, uint32_t* accE, uint32_t* accA,
-                      uint32_t ep, uint8_t* flag, uint32_t* acc_list, uint32_t* acc_count, hipStream_t s);
-void launch_lf_reject(const uint32_t* live, const uint32_t* nl, uint32_t nl_max, const uint32_t* a, const uint32_t* b,
-                      const uint32_t* accE, const uint32_t* accA, uint32_t ep, const uint8_t* flag, uint32_t* live2,
-                      uint32_t* live2_count, hipStream_t s);
+// first live candidate leaving / entering each community (per-community words, size n)
+struct LfFirst {
+  u64a* hi;
+  u64a* lo;
+  uint32_t* v;
+};
+constexpr unsigned kLfBlocks = 1024;
+// live = 0..K-1 with K read on the device (at most bound), flags cleared, *nlive = K, *nacc = 0
+void launch_lf_init(const uint32_t* K, uint32_t bound, uint32_t* live, uint8_t* flag, uint32_t* nlive, uint32_t* nacc,
+                    hipStream_t s);
+// one round over the live list (count on the device): accepted candidates are appended to
+// acc_list, survivors to live2 (its count is reset by the round)
+void launch_lf_round(const uint32_t* live, const uint32_t* nl, uint32_t bound, CandBuf cand, LfFirst E, LfFirst A,
+                     uint32_t* accE, uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list,
+                     uint32_t* acc_count, uint32_t* live2, uint32_t* live2_count, hipStream_t s);
 
 // ---------------------------------------------------------------- commit / rollback / expand
 // na: device count of accepted candidates (acc list), na_max an upper bound for the grid
@@ -241,15 +244,17 @@ void launch_ref_init_top(uint32_t n, const uint8_t* alive, const int64_t* kout, 
 void launch_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* oldpar, const int64_t* kout,
                       const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize, int phase,
                       hipStream_t s);
+// forward: singletons join their targets; otherwise the same moves are undone
 void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
                        const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize,
-                       hipStream_t s);
-// SPExpand with plain-store marks: singleton neighbours of movers join rcur (stamp only) and,
-// when new, rset (stamp only, oldpar = self); lists are built later by select
-void launch_spexpand(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
-                     int directed, const uint32_t* lab, const uint32_t* par, const uint32_t* rsize,
-                     uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep, uint32_t* oldpar,
-                     hipStream_t s);
+                       int forward, hipStream_t s);
+// SPExpand over wavefront items of the movers (node i = movers[idx[i]], count on the device;
+// items from launch_items with the same list): plain-store marks into Rcur and Rset, oldpar of
+// new Rset members = themselves; the lists are built later by select
+void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t* count, uint32_t bound,
+                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
+                     const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
+                     uint32_t rset_ep, uint32_t* oldpar, hipStream_t s);
 
 // ---------------------------------------------------------------- aggregate repair
 // materialise: every entry of every alive node (list = alive nodes); repair: entries of C
@@ -283,6 +288,7 @@ int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint
 // first index of every run of equal rows (key >> 32) in sorted keys, ascending; count to *d_count
 int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, uint64_t* out,
                       uint32_t* d_count, hipStream_t s);
+int prim_exclusive_sum_u64x3(void** tmp, size_t* tmp_bytes, const U64x3* in, U64x3* out, uint64_t n, hipStream_t s);
 int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
                            hipStream_t s);
 int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, uint64_t n, hipStream_t s);

@@ -35,6 +35,12 @@ struct RowHead {
   }
 };
 
+struct SumU64x3 {
+  __host__ __device__ __forceinline__ U64x3 operator()(const U64x3& a, const U64x3& b) const {
+    return U64x3{a.x + b.x, a.y + b.y, a.z + b.z};
+  }
+};
+
 struct SumI64 {
   __host__ __device__ __forceinline__ int64_t operator()(const int64_t& a, const int64_t& b) const { return a + b; }
 };
@@ -127,6 +133,16 @@ int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint6
   if (ensure(tmp, tmp_bytes, need)) return -2;
   size_t have = *tmp_bytes;
   return hipcub::DeviceSelect::If(*tmp, have, ids, out, d_count, (int)k, pred, s) == hipSuccess ? 0 : -1;
+}
+
+int prim_exclusive_sum_u64x3(void** tmp, size_t* tmp_bytes, const U64x3* in, U64x3* out, uint64_t n, hipStream_t s) {
+  if (n == 0) return 0;
+  size_t need = 0;
+  const U64x3 zero{0, 0, 0};
+  if (hipcub::DeviceScan::ExclusiveScan(nullptr, need, in, out, SumU64x3(), zero, (int)n, s) != hipSuccess) return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  return hipcub::DeviceScan::ExclusiveScan(*tmp, have, in, out, SumU64x3(), zero, (int)n, s) == hipSuccess ? 0 : -1;
 }
 
 int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
