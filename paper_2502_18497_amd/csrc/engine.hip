@@ -132,7 +132,7 @@ struct Engine {
   hipStream_t st = nullptr;
   bool own_stream = false;
   uint32_t n = 0;
-  int id_bits = 32;     // bits of a vertex id: keys row << 32 | col need 32 + id_bits bits
+  int id_bits = 32;     // bits of a vertex id: keys row << 32 | col need 2 * id_bits bits
   bool broken = false;
 
   // exact scalars (host)
@@ -519,27 +519,27 @@ struct Engine {
     release(newoff);
   }
 
-  // Apply sorted records (key = row << 32 | col, distinct keys) to one orientation; when
+  // Apply sorted records (key = row << id_bits | col, distinct keys) to one orientation; when
   // deg_arr is given, each row's delta sum is added to it.  Rows are updated in place; rows
   // that outgrow their capacity move to new pool regions (the pool grows when full).
   void csr_apply(Csr& c, const uint64_t* keys, const int64_t* delta, uint64_t k, int64_t* deg_arr) {
     if (k == 0) return;
     if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
     ensure_insflag(k);
-    cub(prim_select_heads(&cub_tmp, &cub_bytes, keys, k, seg_lo, &ds->nseg, st));
-    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, slotbuf, &cub_tmp, &cub_bytes, st);
+    cub(prim_select_heads(&cub_tmp, &cub_bytes, keys, k, id_bits, seg_lo, &ds->nseg, st));
+    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, slotbuf, &cub_tmp, &cub_bytes, id_bits, st);
     hcheck(hipMemsetAsync(&ds->nmove, 0, 2 * sizeof(uint32_t), st));   // nmove, overflow
     launch_seg_update(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, holebuf, deg_arr, rowdel,
-                      rowins, movelist, &ds->nmove, st);
+                      rowins, movelist, &ds->nmove, id_bits, st);
     launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
-                    &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, st);
+                    &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, id_bits, st);
     sync_read();
     for (int attempt = 0; hs->overflow; ++attempt) {
       if (attempt > 3) throw NoMem{};
       csr_grow(c, 2 * k + c.pool_cap / 4);
       zero(&ds->overflow);
       launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
-                      &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, st);
+                      &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, id_bits, st);
       sync_read();
     }
   }
@@ -552,8 +552,8 @@ struct Engine {
     if (directed) {
       // scratch tk1/tk2/tv2 must not alias the caller's keys/vals
       if (k > tup_cap || keys == tk1 || keys == tk2 || vals == tv2) throw DeviceError{hipErrorInvalidValue};
-      launch_transpose_keys(keys, tk2, k, st);
-      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, vals, tv2, k, 0, 32 + id_bits, st));
+      launch_transpose_keys(keys, tk2, k, id_bits, st);
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, vals, tv2, k, 0, 2 * id_bits, st));
       // tk1 and tv2 now hold the transposed records in (col, row) order
       csr_apply(V.in, tk1, tv2, k, degrees ? V.kin : nullptr);
     }
@@ -562,7 +562,7 @@ struct Engine {
   // sort (keys, vals) of length k and reduce equal keys; result in (tk2, tv2) with *runs
   uint64_t sort_reduce(uint64_t* keys, int64_t* vals, uint64_t k, uint64_t* okeys, int64_t* ovals) {
     if (k == 0) return 0;
-    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, keys, tk1, vals, tv1, k, 0, 32 + id_bits, st));
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, keys, tk1, vals, tv1, k, 0, 2 * id_bits, st));
     cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, okeys, tv1, ovals, &ds->nruns, k, st));
     sync_read();
     return hs->nruns;
@@ -580,18 +580,18 @@ struct Engine {
     zero(&ds->err);
     hcheck(hipMemsetAsync(&ds->first_bad, 0xFF, 4, st));
     zero(&ds->dm);
-    launch_ingest_records(dins, ni, ddel, nd, dchg, nc, n, directed, rkey0, ridx0, &ds->err, st);
-    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, rkey0, rkey1, ridx0, ridx1, K, 0, 32 + id_bits, st));
+    launch_ingest_records(dins, ni, ddel, nd, dchg, nc, n, directed, rkey0, ridx0, &ds->err, id_bits, st);
+    cub(prim_sort_pairs_u64_u32(&cub_tmp, &cub_bytes, rkey0, rkey1, ridx0, ridx1, K, 0, 2 * id_bits, st));
     sync_read();
     if (hs->err & 1u) return LDL_EINVAL;
     Level& V0 = lv[0];
     if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
     ensure_insflag(K);
-    cub(prim_select_heads(&cub_tmp, &cub_bytes, rkey1, K, seg_lo, &ds->nseg, st));
+    cub(prim_select_heads(&cub_tmp, &cub_bytes, rkey1, K, id_bits, seg_lo, &ds->nseg, st));
     launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, rslot, &cub_tmp, &cub_bytes,
-                      st);
+                      id_bits, st);
     launch_ingest_validate(V0.out.ref, rkey1, ridx1, rslot, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
-                           &ds->first_bad, &ds->dm, st);
+                           &ds->first_bad, &ds->dm, id_bits, st);
     sync_read();
     if (hs->err & 2u) return LDL_EDUP;
     if (hs->err & 12u) return hs->first_bad < ni ? LDL_EOVERFLOW : LDL_ENOEDGE;
@@ -599,19 +599,19 @@ struct Engine {
     const int64_t dm = hs->dm;
     // matrix entries of the net changes
     zero(&ds->ecount);
-    launch_ingest_entries(rkey1, rdelta, K, directed, ekey0, edel0, &ds->ecount, st);
+    launch_ingest_entries(rkey1, rdelta, K, directed, ekey0, edel0, &ds->ecount, id_bits, st);
     sync_read();
     const uint64_t E = hs->ecount;
     if (E == 0) return LDL_OK;
-    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 32 + id_bits, st));
+    cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 2 * id_bits, st));
     stats.updates = K;
     // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
     begin(S_TOUCH);
-    launch_ingest_mark(ekey1, E, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), st);
+    launch_ingest_mark(ekey1, E, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), id_bits, st);
     zero(&ds->dein);
     zero(&ds->dskk_lo);
     zero(&ds->dskk_hi);
-    launch_ingest_totals(ekey1, edel1, E, V0.lab, Kout, directed ? Kin : nullptr, &ds->dein, st);
+    launch_ingest_totals(ekey1, edel1, E, V0.lab, Kout, directed ? Kin : nullptr, &ds->dein, id_bits, st);
     launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], (uint32_t)std::min<uint64_t>(2 * E, n), Kout, Kin,
                 tko, tki, &ds->dskk_lo, &ds->dskk_hi, st);
     apply_records(0, ekey1, edel1, E, true);
@@ -621,9 +621,9 @@ struct Engine {
     SKK += ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
     // cascade the entry deltas through pi to every existing level; ancestors are seeds
     if (top >= 1) {
-      launch_split_keys(ekey1, E, ex, ey, st);
+      launch_split_keys(ekey1, E, ex, ey, id_bits, st);
       for (int s = 1; s <= top; ++s) {
-        launch_cascade_map(ex, ey, edel1, E, lv[s - 1].par, tk0, tv0, ref(S_D0 + s), st);
+        launch_cascade_map(ex, ey, edel1, E, lv[s - 1].par, tk0, tv0, ref(S_D0 + s), id_bits, st);
         const uint64_t R = sort_reduce(tk0, tv0, E, tk2, tv2);
         // tk2/tv2 are reused inside apply_records for directed graphs: keep a copy
         hcheck(hipMemcpyAsync(ekey0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
@@ -978,7 +978,7 @@ struct Engine {
     if (nC)
       launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, oldpar,
                         sets[S_C].stamp, sets[S_C].epoch, 1, toffs, (u64a*)tcur, tk0, tv0, sets[Dn].stamp,
-                        sets[Dn].epoch, st);
+                        sets[Dn].epoch, id_bits, st);
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
@@ -1019,11 +1019,11 @@ struct Engine {
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
     apply_records(r + 1, tk0, tv0, R, false);
     for (int s = r + 2; s <= top; ++s) {
-      launch_split_keys(tk0, R, tx, ty, st);
+      launch_split_keys(tk0, R, tx, ty, id_bits, st);
       SetRef none{};
-      launch_cascade_map(tx, ty, tv0, R, lv[s - 1].par, tk2, tv2, none, st);
+      launch_cascade_map(tx, ty, tv0, R, lv[s - 1].par, tk2, tv2, none, id_bits, st);
       // tk2/tv2 hold the mapped records; reduce them into tk0/tv0
-      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 32 + id_bits, st));
+      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 2 * id_bits, st));
       cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, tk0, tv1, tv0, &ds->nruns, R, st));
       sync_read();
       R = hs->nruns;
@@ -1044,7 +1044,7 @@ struct Engine {
     const uint64_t T = tuple_offsets(S_TMP, na, V.out.ref, CsrRef{}, nullptr, 0, 0);
     if (na)
       launch_tuples_gen(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], na, it_off, V.out.ref, CsrRef{}, V.par,
-                        nullptr, nullptr, 0, 0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, st);
+                        nullptr, nullptr, 0, 0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, id_bits, st);
     const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
     hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));

@@ -100,7 +100,7 @@ constexpr int kSegChunk = 2048;
 constexpr uint32_t kSlice = 16384;
 
 __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo,
-                            const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items) {
+                            const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items, int ks) {
   const uint32_t nseg = *nseg_ptr;
   for (uint64_t s = gtid(); s <= k; s += gstride()) {
     if (s >= nseg) {
@@ -108,7 +108,7 @@ __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const ui
       continue;
     }
     const uint64_t lo = seg_lo[s];
-    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint32_t row = krow(keys[lo], ks);
     const uint64_t hi = s + 1 < nseg ? seg_lo[s + 1] : k;   // heads are selected in key order
     seg_hi[s] = hi;
     const uint64_t deg = c.deg[row];
@@ -133,7 +133,7 @@ __device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t 
 __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k,
                                                     const uint64_t* seg_lo, const uint64_t* seg_hi,
                                                     const uint32_t* nseg_ptr, const uint64_t* item_off,
-                                                    int64_t* slot_out) {
+                                                    int64_t* slot_out, int ks) {
   __shared__ uint32_t tkey[2 * kSegChunk];
   __shared__ uint32_t tval[2 * kSegChunk];
   const uint32_t nseg = *nseg_ptr;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
     const uint32_t sg = upper_bound_u64(item_off, nseg + 1, it) - 1;
     const uint64_t sub = it - item_off[sg];
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
-    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint32_t row = krow(keys[lo], ks);
     const uint64_t deg = c.deg[row];
     const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
     const uint64_t rc = sub / nsl, sl = sub % nsl;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
     for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
-      const uint32_t col = (uint32_t)keys[clo + i];
+      const uint32_t col = kcol(keys[clo + i], ks);
       uint32_t h = hash32(col) & mask;
       for (;;) {
         const uint32_t prev = atomicCAS(&tkey[h], kEmpty, col);
@@ -199,13 +199,13 @@ __global__ __launch_bounds__(kTpb) void k_seg_update(CsrRef c, const uint64_t* k
                                                      const uint64_t* seg_lo, const uint64_t* seg_hi,
                                                      const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
                                                      uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel,
-                                                     uint32_t* rowins, uint32_t* move_list, uint32_t* move_count) {
+                                                     uint32_t* rowins, uint32_t* move_list, uint32_t* move_count, int ks) {
   __shared__ int64_t red[3 * (kTpb / kWave)];
   __shared__ uint32_t lds[kTpb / kWave];
   const uint32_t nseg = *nseg_ptr;
   for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
-    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint32_t row = krow(keys[lo], ks);
     const uint64_t off = c.off[row];
     const uint32_t deg = c.deg[row];
     const uint32_t cap = c.cap[row];
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kTpb) void k_seg_update(CsrRef c, const uint64_t* k
       const uint32_t r = block_rank(f, lds, tot);
       if (f) {
         const uint64_t dst = off + t0 + ni + r;
-        c.nbr[dst] = (uint32_t)keys[i];
+        c.nbr[dst] = kcol(keys[i], ks);
         wset(c, dst, delta[i]);
       }
       ni += tot;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* key
                                                    const uint64_t* seg_lo, const uint64_t* seg_hi, const uint8_t* rtype,
                                                    const uint32_t* rowdel, const uint32_t* rowins, uint32_t* move_list,
                                                    const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                                                   uint32_t* overflow) {
+                                                   uint32_t* overflow, int ks) {
   __shared__ uint32_t lds[kTpb / kWave];
   __shared__ uint64_t s_dst;
   const uint32_t nm = *move_count;
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* key
     const uint32_t sg = move_list[j];
     if (sg == kEmpty) continue;
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
-    const uint32_t row = (uint32_t)(keys[lo] >> 32);
+    const uint32_t row = krow(keys[lo], ks);
     const uint64_t src = c.off[row];
     const uint32_t deg = c.deg[row];
     const uint64_t ndeg = (uint64_t)deg - rowdel[row] + rowins[row];
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* key
       uint32_t tot;
       const uint32_t r = block_rank(f, lds, tot);
       if (f) {
-        c.nbr[dst + written + r] = (uint32_t)keys[i];
+        c.nbr[dst + written + r] = kcol(keys[i], ks);
         wset(c, dst + written + r, delta[i]);
       }
       written += tot;
@@ -396,11 +396,11 @@ __global__ void k_fill_i64_dev(int64_t* p, int64_t v, uint64_t n) {
 __global__ void k_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot,
                                   uint64_t k, const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd,
                                   const uint32_t* chg, int directed, int64_t* delta, uint32_t* err,
-                                  uint32_t* first_bad, i64a* dm) {
+                                  uint32_t* first_bad, i64a* dm, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const uint64_t key = keys[i];
     if (i > 0 && keys[i - 1] == key) atomicOr(err, 2u);
-    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
+    const uint32_t u = krow(key, ks), v = kcol(key, ks);
     const int64_t sl = slot[i];
     const uint32_t src = idx[i];
     const int64_t old = sl >= 0 ? (int64_t)((const uint32_t*)out0.w)[sl] : 0;
@@ -485,7 +485,7 @@ __global__ void k_csr_entries(CsrRef c, uint32_t n, uint64_t* out_keys, int64_t*
 
 __global__ void k_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd,
                                  const uint32_t* chg, uint64_t nc, uint32_t n, int directed, uint64_t* keys,
-                                 uint32_t* idx, uint32_t* err) {
+                                 uint32_t* idx, uint32_t* err, int ks) {
   const uint64_t total = ni + nd + nc;
   for (uint64_t i = gtid(); i < total; i += gstride()) {
     uint32_t u, v, w;
@@ -504,33 +504,33 @@ __global__ void k_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_
       u = 0; v = 0;
     }
     if (!directed && u > v) { uint32_t t = u; u = v; v = t; }
-    keys[i] = ((uint64_t)u << 32) | v;
+    keys[i] = kpack(u, v, ks);
     idx[i] = (uint32_t)i;
   }
 }
 
 __global__ void k_ingest_entries(const uint64_t* keys, const int64_t* delta, uint64_t k, int directed,
-                                 uint64_t* ekeys, int64_t* edelta, u64a* count) {
+                                 uint64_t* ekeys, int64_t* edelta, u64a* count, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const int64_t d = delta[i];
     if (d == 0) continue;
     const uint64_t key = keys[i];
-    const uint32_t u = (uint32_t)(key >> 32), v = (uint32_t)key;
+    const uint32_t u = krow(key, ks), v = kcol(key, ks);
     const bool mirror = !directed && u != v;
     const u64a at = atomicAdd(count, (u64a)(mirror ? 2 : 1));
     ekeys[at] = key;
     edelta[at] = d;
     if (mirror) {
-      ekeys[at + 1] = ((uint64_t)v << 32) | u;
+      ekeys[at + 1] = kpack(v, u, ks);
       edelta[at + 1] = d;
     }
   }
 }
 
 __global__ void k_ingest_mark(const uint64_t* ekeys, uint64_t k, const uint32_t* lab0, const int64_t* Kout,
-                              const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0) {
+                              const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const uint32_t x = (uint32_t)(ekeys[i] >> 32), y = (uint32_t)ekeys[i];
+    const uint32_t x = krow(ekeys[i], ks), y = kcol(ekeys[i], ks);
     set_add(seeds0.stamp, seeds0.epoch, seeds0.list, seeds0.count, x);
     set_add(seeds0.stamp, seeds0.epoch, seeds0.list, seeds0.count, y);
     const uint32_t cs[2] = {lab0[x], lab0[y]};
@@ -548,9 +548,9 @@ __global__ void k_ingest_mark(const uint64_t* ekeys, uint64_t k, const uint32_t*
 }
 
 __global__ void k_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t k, const uint32_t* lab0,
-                                int64_t* Kout, int64_t* Kin, i64a* dein) {
+                                int64_t* Kout, int64_t* Kin, i64a* dein, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const uint32_t x = (uint32_t)(ekeys[i] >> 32), y = (uint32_t)ekeys[i];
+    const uint32_t x = krow(ekeys[i], ks), y = kcol(ekeys[i], ks);
     const int64_t d = edelta[i];
     const uint32_t cx = lab0[x], cy = lab0[y];
     atomic_add_i64(&Kout[cx], d);
@@ -572,7 +572,7 @@ __global__ void k_dskk(const uint32_t* touched, const uint32_t* nt_ptr, const in
 }
 
 __global__ void k_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
-                              uint64_t* keys, int64_t* vals, SetRef seeds) {
+                              uint64_t* keys, int64_t* vals, SetRef seeds, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const uint32_t x = par[ex[i]], y = par[ey[i]];
     ex[i] = x;
@@ -581,20 +581,20 @@ __global__ void k_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uin
       set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, x);
       set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, y);
     }
-    keys[i] = ((uint64_t)x << 32) | y;
+    keys[i] = kpack(x, y, ks);
     vals[i] = ed[i];
   }
 }
 
-__global__ void k_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey) {
+__global__ void k_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
-    ex[i] = (uint32_t)(keys[i] >> 32);
-    ey[i] = (uint32_t)keys[i];
+    ex[i] = krow(keys[i], ks);
+    ey[i] = kcol(keys[i], ks);
   }
 }
 
-__global__ void k_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k) {
-  for (uint64_t i = gtid(); i < k; i += gstride()) tkeys[i] = (keys[i] << 32) | (keys[i] >> 32);
+__global__ void k_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) tkeys[i] = kpack(kcol(keys[i], ks), krow(keys[i], ks), ks);
 }
 
 // ------------------------------------------------------------------ refinement bookkeeping
@@ -843,7 +843,7 @@ template <bool REPAIR>
 __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
                              CsrRef out, CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp,
                              uint32_t cep, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                             uint32_t* seed_stamp, uint32_t seed_ep) {
+                             uint32_t* seed_stamp, uint32_t seed_ep, int ks) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
@@ -868,13 +868,13 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
       if (valid && j < dout) {
         const uint32_t px = par[x];
         if (!REPAIR) {
-          tkeys[base + j] = ((uint64_t)pu << 32) | px;
+          tkeys[base + j] = kpack(pu, px, ks);
           tvals[base + j] = w;
         } else {
           const uint32_t ox = cstamp[x] == cep ? oldpar[x] : px;
-          tkeys[base + 2 * j] = ((uint64_t)ou << 32) | ox;
+          tkeys[base + 2 * j] = kpack(ou, ox, ks);
           tvals[base + 2 * j] = -w;
-          tkeys[base + 2 * j + 1] = ((uint64_t)pu << 32) | px;
+          tkeys[base + 2 * j + 1] = kpack(pu, px, ks);
           tvals[base + 2 * j + 1] = w;
           seed_stamp[ox] = seed_ep;
           seed_stamp[px] = seed_ep;
@@ -894,9 +894,9 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
           if (act) {
             const uint32_t pv = par[x];
             const uint64_t p2 = base + 2ull * dout + b + 2ull * r;
-            tkeys[p2] = ((uint64_t)pv << 32) | ou;
+            tkeys[p2] = kpack(pv, ou, ks);
             tvals[p2] = -w;
-            tkeys[p2 + 1] = ((uint64_t)pv << 32) | pu;
+            tkeys[p2 + 1] = kpack(pv, pu, ks);
             tvals[p2 + 1] = w;
             seed_stamp[pv] = seed_ep;
           }
@@ -974,13 +974,13 @@ void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t b
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
                        CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
                        int repair, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                       uint32_t* seed_stamp, uint32_t seed_ep, hipStream_t s) {
+                       uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s) {
   if (repair)
     k_tuples_gen<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
-                                                    cur, tkeys, tvals, seed_stamp, seed_ep);
+                                                    cur, tkeys, tvals, seed_stamp, seed_ep, ks);
   else
     k_tuples_gen<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
-                                                     cur, tkeys, tvals, seed_stamp, seed_ep);
+                                                     cur, tkeys, tvals, seed_stamp, seed_ep, ks);
 }
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n) k_fill_u32<<<grid_for(n), kTpb, 0, s>>>(p, v, n);
@@ -1007,38 +1007,38 @@ void launch_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, con
 void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
                             const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                             int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
-                            hipStream_t s) {
+                            int ks, hipStream_t s) {
   if (k)
     k_ingest_validate<<<grid_for(k), kTpb, 0, s>>>(out0, keys, idx, slot, k, ins, ni, del, nd, chg, directed, delta,
-                                                   err, first_bad, dm);
+                                                   err, first_bad, dm, ks);
 }
 void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
                        uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
-                       size_t* tmp_bytes, hipStream_t s) {
+                       size_t* tmp_bytes, int ks, hipStream_t s) {
   if (!k) return;
-  k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items);
+  k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items, ks);
   prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
   k_fill_i64_dev<<<grid_for(k), kTpb, 0, s>>>(slot_out, -1, k);
   const unsigned g = k < 8192 ? (unsigned)k : 8192u;
-  k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out);
+  k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out, ks);
 }
 void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                        const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
                        uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel, uint32_t* rowins, uint32_t* move_list,
-                       uint32_t* move_count, hipStream_t s) {
+                       uint32_t* move_count, int ks, hipStream_t s) {
   if (!k) return;
   const unsigned g = k < 8192 ? (unsigned)k : 8192u;
   k_seg_update<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel, rowins,
-                                  move_list, move_count);
+                                  move_list, move_count, ks);
 }
 void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                      const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,
                      uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                     uint32_t* overflow, hipStream_t s) {
+                     uint32_t* overflow, int ks, hipStream_t s) {
   if (!k) return;
   const unsigned g = k < 1024 ? (unsigned)k : 1024u;
   k_seg_move<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, rtype, rowdel, rowins, move_list, move_count, pool_top,
-                                pool_cap, overflow);
+                                pool_cap, overflow, ks);
 }
 void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, hipStream_t s) {
   if (n) k_csr_newcap<<<grid_for(n), kTpb, 0, s>>>(deg, newcap, newcap64, n);
@@ -1052,21 +1052,21 @@ void launch_csr_entries(CsrRef c, uint32_t n, uint64_t* out_keys, int64_t* out_w
 }
 void launch_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                            uint64_t nc, uint32_t n, int directed, uint64_t* keys, uint32_t* idx, uint32_t* err,
-                           hipStream_t s) {
+                           int ks, hipStream_t s) {
   const uint64_t t = ni + nd + nc;
-  if (t) k_ingest_records<<<grid_for(t), kTpb, 0, s>>>(ins, ni, del, nd, chg, nc, n, directed, keys, idx, err);
+  if (t) k_ingest_records<<<grid_for(t), kTpb, 0, s>>>(ins, ni, del, nd, chg, nc, n, directed, keys, idx, err, ks);
 }
 void launch_ingest_entries(const uint64_t* keys, const int64_t* delta, uint64_t k, int directed, uint64_t* ekeys,
-                           int64_t* edelta, u64a* count, hipStream_t s) {
-  if (k) k_ingest_entries<<<grid_for(k), kTpb, 0, s>>>(keys, delta, k, directed, ekeys, edelta, count);
+                           int64_t* edelta, u64a* count, int ks, hipStream_t s) {
+  if (k) k_ingest_entries<<<grid_for(k), kTpb, 0, s>>>(keys, delta, k, directed, ekeys, edelta, count, ks);
 }
 void launch_ingest_mark(const uint64_t* ekeys, uint64_t k, const uint32_t* lab0, const int64_t* Kout,
-                        const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s) {
-  if (k) k_ingest_mark<<<grid_for(k), kTpb, 0, s>>>(ekeys, k, lab0, Kout, Kin, touched, tko, tki, seeds0);
+                        const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, int ks, hipStream_t s) {
+  if (k) k_ingest_mark<<<grid_for(k), kTpb, 0, s>>>(ekeys, k, lab0, Kout, Kin, touched, tko, tki, seeds0, ks);
 }
 void launch_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t k, const uint32_t* lab0,
-                          int64_t* Kout, int64_t* Kin_or_null, i64a* dein, hipStream_t s) {
-  if (k) k_ingest_totals<<<grid_for(k), kTpb, 0, s>>>(ekeys, edelta, k, lab0, Kout, Kin_or_null, dein);
+                          int64_t* Kout, int64_t* Kin_or_null, i64a* dein, int ks, hipStream_t s) {
+  if (k) k_ingest_totals<<<grid_for(k), kTpb, 0, s>>>(ekeys, edelta, k, lab0, Kout, Kin_or_null, dein, ks);
 }
 void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, const int64_t* Kout, const int64_t* Kin,
                  const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s) {
@@ -1075,14 +1075,14 @@ void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, c
   k_dskk<<<g, kTpb, 0, s>>>(touched, nt, Kout, Kin, tko, tki, lo, hi);
 }
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
-                        uint64_t* keys, int64_t* vals, SetRef seeds, hipStream_t s) {
-  if (k) k_cascade_map<<<grid_for(k), kTpb, 0, s>>>(ex, ey, ed, k, par, keys, vals, seeds);
+                        uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s) {
+  if (k) k_cascade_map<<<grid_for(k), kTpb, 0, s>>>(ex, ey, ed, k, par, keys, vals, seeds, ks);
 }
-void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, hipStream_t s) {
-  if (k) k_split_keys<<<grid_for(k), kTpb, 0, s>>>(keys, k, ex, ey);
+void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks, hipStream_t s) {
+  if (k) k_split_keys<<<grid_for(k), kTpb, 0, s>>>(keys, k, ex, ey, ks);
 }
-void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, hipStream_t s) {
-  if (k) k_transpose_keys<<<grid_for(k), kTpb, 0, s>>>(keys, tkeys, k);
+void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, int ks, hipStream_t s) {
+  if (k) k_transpose_keys<<<grid_for(k), kTpb, 0, s>>>(keys, tkeys, k, ks);
 }
 void launch_ref_init_top(uint32_t n, const uint8_t* alive, const int64_t* kout, const int64_t* kin, int64_t* Krout,
                          int64_t* Krin_or_null, uint32_t* rsize, hipStream_t s) {

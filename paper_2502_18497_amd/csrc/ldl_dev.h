@@ -52,6 +52,13 @@ __device__ __forceinline__ void set_add(uint32_t* stamp, uint32_t epoch, uint32_
   const uint32_t at = wave_reserve(count, claimed);
   if (claimed) list[at] = x;
 }
+// ------------------------------------------------------------------ record keys
+// A (row, col) record key is row << ks | col with ks >= the bits of a vertex id, so keys sort by
+// row, then column, over their low 2 ks bits.
+__device__ __forceinline__ uint64_t kpack(uint32_t r, uint32_t c, int ks) { return ((uint64_t)r << ks) | c; }
+__device__ __forceinline__ uint32_t krow(uint64_t k, int ks) { return (uint32_t)(k >> ks); }
+__device__ __forceinline__ uint32_t kcol(uint64_t k, int ks) { return (uint32_t)(k & ((1ull << ks) - 1ull)); }
+
 // ------------------------------------------------------------------ exact accumulation
 // Signed 128-bit accumulation into (lo, hi) words with two 64-bit atomics: the carry out of
 // the low word is detected from the value returned by the low-word atomic.

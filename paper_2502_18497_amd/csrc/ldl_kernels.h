@@ -132,31 +132,32 @@ void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t b
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
                        CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
                        int repair, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                       uint32_t* seed_stamp, uint32_t seed_ep, hipStream_t s);
+                       uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s);
 
 // ---------------------------------------------------------------- dynamic CSR
-// Records sorted by key = row << 32 | col with deltas; zero deltas are ignored.
+// Records sorted by key = row << ks | col (ks = bits of a vertex id) with deltas; zero deltas
+// are ignored.
 // row lookup of sorted records split over (segment, record chunk, row slice) items: slot of
 // every record (or -1).  Segments (first record of each row, ascending) come from
 // prim_select_heads.
 void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
                        uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
-                       size_t* tmp_bytes, hipStream_t s);
+                       size_t* tmp_bytes, int ks, hipStream_t s);
 // in-place row update (record types into rtype, hole scratch of k words; optional row delta
 // sums added to deg_arr); rows that outgrow their capacity are listed for launch_seg_move,
 // which takes new regions from the pool (bit 0 of *overflow when full: grow, launch again)
 void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                        const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
                        uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel, uint32_t* rowins, uint32_t* move_list,
-                       uint32_t* move_count, hipStream_t s);
+                       uint32_t* move_count, int ks, hipStream_t s);
 void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                      const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,
                      uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                     uint32_t* overflow, hipStream_t s);
+                     uint32_t* overflow, int ks, hipStream_t s);
 void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
                             const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                             int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
-                            hipStream_t s);
+                            int ks, hipStream_t s);
 // new_cap[u] = deg[u] + slack, for a pool rebuild
 void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, hipStream_t s);
 void launch_csr_move_rows(CsrRef from, CsrRef to, const uint64_t* new_off, const uint32_t* new_cap, uint32_t n,
@@ -167,21 +168,21 @@ void launch_csr_entries(CsrRef c, uint32_t n, uint64_t* out_keys, int64_t* out_w
 // kinds: 0 insert (u,v,w), 1 delete (u,v), 2 change (u,v,w)
 void launch_ingest_records(const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                            uint64_t nc, uint32_t n, int directed, uint64_t* keys, uint32_t* idx, uint32_t* err,
-                           hipStream_t s);
+                           int ks, hipStream_t s);
 void launch_ingest_entries(const uint64_t* keys, const int64_t* delta, uint64_t k, int directed, uint64_t* ekeys,
-                           int64_t* edelta, u64a* count, hipStream_t s);
+                           int64_t* edelta, u64a* count, int ks, hipStream_t s);
 // touched communities of the level-0 entries (old totals recorded), seeds at level 0
 void launch_ingest_mark(const uint64_t* ekeys, uint64_t k, const uint32_t* lab0, const int64_t* Kout,
-                        const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s);
+                        const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, int ks, hipStream_t s);
 void launch_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t k, const uint32_t* lab0,
-                          int64_t* Kout, int64_t* Kin_or_null, i64a* dein, hipStream_t s);
+                          int64_t* Kout, int64_t* Kin_or_null, i64a* dein, int ks, hipStream_t s);
 void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, const int64_t* Kout, const int64_t* Kin,
                  const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s);
 // cascade: (x,y) <- (par[x], par[y]); keys rebuilt; both endpoints seeded
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
-                        uint64_t* keys, int64_t* vals, SetRef seeds, hipStream_t s);
-void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, hipStream_t s);
-void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, hipStream_t s);
+                        uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s);
+void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks, hipStream_t s);
+void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, int ks, hipStream_t s);
 
 // ---------------------------------------------------------------- local move / refinement
 // candidate kernels of degree bins 0..3 over a device-resident bin list
@@ -285,8 +286,8 @@ int prim_exclusive_sum_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, ui
 // ids i < n with stamp[i] == ep, in increasing order, count written to *d_count
 int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* out,
                       uint32_t* d_count, hipStream_t s);
-// first index of every run of equal rows (key >> 32) in sorted keys, ascending; count to *d_count
-int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, uint64_t* out,
+// first index of every run of equal rows (key >> ks) in sorted keys, ascending; count to *d_count
+int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, int ks, uint64_t* out,
                       uint32_t* d_count, hipStream_t s);
 int prim_exclusive_sum_u64x3(void** tmp, size_t* tmp_bytes, const U64x3* in, U64x3* out, uint64_t n, hipStream_t s);
 int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,

@@ -30,8 +30,9 @@ struct StampIs {
 
 struct RowHead {
   const uint64_t* keys;
+  int ks;
   __host__ __device__ __forceinline__ bool operator()(const uint64_t& i) const {
-    return i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32);
+    return i == 0 || (keys[i] >> ks) != (keys[i - 1] >> ks);
   }
 };
 
@@ -123,11 +124,11 @@ int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint
   return hipcub::DeviceSelect::If(*tmp, have, ids, out, d_count, (int)n, pred, s) == hipSuccess ? 0 : -1;
 }
 
-int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, uint64_t* out,
+int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, int ks, uint64_t* out,
                       uint32_t* d_count, hipStream_t s) {
   if (k == 0) return 0;
   hipcub::CountingInputIterator<uint64_t> ids(0);
-  RowHead pred{keys};
+  RowHead pred{keys, ks};
   size_t need = 0;
   if (hipcub::DeviceSelect::If(nullptr, need, ids, out, d_count, (int)k, pred, s) != hipSuccess) return -1;
   if (ensure(tmp, tmp_bytes, need)) return -2;
