@@ -65,6 +65,10 @@ typedef struct ldl_pair {
  *   device              HIP device ordinal
  *   stream              hipStream_t to run on, or NULL for the handle's own stream
  *   profile             nonzero: time the local-move kernels with HIP events (see stats)
+ *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
+ *                       results unchanged: 1 = one decoupling round between host checks (second
+ *                       commit phase), 2 = minimal hub hash-table pool (overflow and redo of an
+ *                       iteration), 4 = no spare adjacency capacity (row moves, pool growth)
  */
 typedef struct ldl_config {
   int32_t directed;
@@ -75,6 +79,7 @@ typedef struct ldl_config {
   int32_t device;
   void* stream;
   int32_t profile;
+  int32_t test_flags;
 } ldl_config;
 
 /* Per-call statistics (all counts summed over the call). */

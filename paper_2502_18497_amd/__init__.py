@@ -30,7 +30,7 @@ class ldl_config(ctypes.Structure):
                 ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("alpha_num", ctypes.c_int32), ("alpha_den", ctypes.c_int32), ("beta_num", ctypes.c_int32),
                 ("beta_den", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
 
 
 class ldl_batch_stats(ctypes.Structure):
@@ -153,7 +153,7 @@ class Graph:
     edges; ``apply_batch`` runs one batch update (Algorithm 1)."""
 
     def __init__(self, n, edges, directed=False, gamma=(1, 1), N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100),
-                 device=0, stream=None, profile=False):
+                 device=0, stream=None, profile=False, test_flags=0):
         self.lib = load_library()
         c = ldl_default_config()
         c.directed, c.gamma_num, c.gamma_den = int(directed), gamma[0], gamma[1]
@@ -162,6 +162,7 @@ class Graph:
         c.device = device
         c.stream = stream
         c.profile = int(bool(profile))
+        c.test_flags = int(test_flags)
         self.n = int(n)
         self.directed = bool(directed)
         self.L = L

@@ -129,6 +129,7 @@ struct Engine {
   int64_t an = 1, ad = 1000, bn = 1, bd = 100;
   int device = 0;
   int profile = 0;
+  int test_flags = 0;   // see ldl_config
   hipStream_t st = nullptr;
   bool own_stream = false;
   uint32_t n = 0;
@@ -303,6 +304,7 @@ struct Engine {
     an = c.alpha_num; ad = c.alpha_den; bn = c.beta_num; bd = c.beta_den;
     device = c.device;
     profile = c.profile;
+    test_flags = c.test_flags;
     n = n_;
     id_bits = 1;
     while (id_bits < 32 && (1ull << id_bits) < (uint64_t)n) ++id_bits;
@@ -401,13 +403,13 @@ struct Engine {
     cand.count = &ds->ps.ncand;
     hub.top = &ds->ps.hub_need;
     hub.over_count = &ds->ps.hub_over;
-    hub_pool(4ull * n);
+    hub_pool((test_flags & 2) ? 0 : 4ull * n);
     hcheck(hipStreamSynchronize(st));
   }
 
   // (re)allocate the hub table pool with at least `slots` slots, empty, and its partials
   void hub_pool(uint64_t slots) {
-    uint64_t hc = 1ull << 16;
+    uint64_t hc = (test_flags & 2) ? 256 : 1ull << 16;
     while (hc < slots) hc <<= 1;
     release(hub.keys);
     release(hub.vals);
@@ -490,14 +492,15 @@ struct Engine {
     uint32_t* newcap = alloc<uint32_t>(n);
     uint64_t* newcap64 = alloc<uint64_t>(n);
     uint64_t* newoff = alloc<uint64_t>(n);
-    launch_csr_newcap(c.ref.deg, newcap, newcap64, n, st);
+    const int tight = (test_flags & 4) ? 1 : 0;
+    launch_csr_newcap(c.ref.deg, newcap, newcap64, n, tight, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, newcap64, newoff, n, st));
     uint64_t last_off = 0, last_cap = 0;
     hcheck(hipMemcpyAsync(&last_off, newoff + (n - 1), 8, hipMemcpyDeviceToHost, st));
     hcheck(hipMemcpyAsync(&last_cap, newcap64 + (n - 1), 8, hipMemcpyDeviceToHost, st));
     hcheck(hipStreamSynchronize(st));
     const uint64_t used = last_off + last_cap;
-    uint64_t cap = used + extra + (used + extra) / 2 + 1024;
+    uint64_t cap = tight ? used + extra : used + extra + (used + extra) / 2 + 1024;
     CsrRef to = c.ref;
     to.nbr = alloc<uint32_t>(cap);
     to.w = c.ref.wide ? (void*)alloc<int64_t>(cap) : (void*)alloc<uint32_t>(cap);
@@ -532,14 +535,14 @@ struct Engine {
     launch_seg_update(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, holebuf, deg_arr, rowdel,
                       rowins, movelist, &ds->nmove, id_bits, st);
     launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
-                    &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, id_bits, st);
+                    &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, (test_flags & 4) ? 1 : 0, id_bits, st);
     sync_read();
     for (int attempt = 0; hs->overflow; ++attempt) {
-      if (attempt > 3) throw NoMem{};
-      csr_grow(c, 2 * k + c.pool_cap / 4);
+      if (attempt > 6) throw NoMem{};
+      csr_grow(c, 2 * k + (c.pool_cap / 4 << attempt));   // the extra room doubles per failed attempt
       zero(&ds->overflow);
       launch_seg_move(c.ref, keys, delta, k, seg_lo, seg_hi, insflag, rowdel, rowins, movelist, &ds->nmove,
-                      &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, id_bits, st);
+                      &ds->pool_top[c.slot], c.pool_cap, &ds->overflow, (test_flags & 4) ? 1 : 0, id_bits, st);
       sync_read();
     }
   }
@@ -746,6 +749,7 @@ struct Engine {
   // ---- exact greedy filter over the candidates (Sec. III-E), count read on the device:
   // accepted candidate indices are appended to `acc`, their count in ds->nacc
   static constexpr int kLfRounds = 4;   // rounds launched before the host looks
+  int lf_rounds() const { return (test_flags & 1) ? 1 : kLfRounds; }
   void decouple_start() {
     if (++acc_epoch == 0) {
       launch_fill_u32(accE, 0, n, st);
@@ -756,7 +760,7 @@ struct Engine {
     lf_la = liveA;
     lf_lb = liveB;
     lf_ca = 0;
-    decouple_rounds(kLfRounds);
+    decouple_rounds(lf_rounds());
   }
   void decouple_rounds(int rounds) {
     for (int k = 0; k < rounds; ++k) {
@@ -773,7 +777,7 @@ struct Engine {
     const uint32_t na1 = hs->nacc;
     uint32_t known = hs->nlive[lf_ca];
     while (known) {
-      decouple_rounds(kLfRounds);
+      decouple_rounds(lf_rounds());
       sync_read();
       const uint32_t nl = hs->nlive[lf_ca];
       if (nl >= known) throw DeviceError{hipErrorUnknown};   // every round accepts a candidate

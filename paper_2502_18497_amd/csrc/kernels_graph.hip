@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* key
                                                    const uint64_t* seg_lo, const uint64_t* seg_hi, const uint8_t* rtype,
                                                    const uint32_t* rowdel, const uint32_t* rowins, uint32_t* move_list,
                                                    const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                                                   uint32_t* overflow, int ks) {
+                                                   uint32_t* overflow, int tight, int ks) {
   __shared__ uint32_t lds[kTpb / kWave];
   __shared__ uint64_t s_dst;
   const uint32_t nm = *move_count;
@@ -333,8 +333,8 @@ __global__ __launch_bounds__(kTpb) void k_seg_move(CsrRef c, const uint64_t* key
     const uint64_t src = c.off[row];
     const uint32_t deg = c.deg[row];
     const uint64_t ndeg = (uint64_t)deg - rowdel[row] + rowins[row];
-    uint64_t nc = ndeg + (ndeg >> 2);
-    if (nc < ndeg + 4) nc = ndeg + 4;
+    uint64_t nc = tight ? ndeg : ndeg + (ndeg >> 2);
+    if (!tight && nc < ndeg + 4) nc = ndeg + 4;
     if (nc > 0xFFFFFFFFull) nc = 0xFFFFFFFFull;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -437,11 +437,11 @@ __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key)
   return lo;
 }
 
-__global__ void k_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n) {
+__global__ void k_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, int tight) {
   for (uint64_t u = gtid(); u < n; u += gstride()) {
     uint64_t d = deg[u];
-    uint64_t nc = d + (d >> 2);
-    if (nc < d + 2) nc = d + 2;
+    uint64_t nc = tight ? d : d + (d >> 2);
+    if (!tight && nc < d + 2) nc = d + 2;
     if (nc > 0xFFFFFFFFull) nc = 0xFFFFFFFFull;
     newcap[u] = (uint32_t)nc;
     newcap64[u] = nc;
@@ -1034,14 +1034,14 @@ void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uin
 void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                      const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,
                      uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                     uint32_t* overflow, int ks, hipStream_t s) {
+                     uint32_t* overflow, int tight, int ks, hipStream_t s) {
   if (!k) return;
   const unsigned g = k < 1024 ? (unsigned)k : 1024u;
   k_seg_move<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, rtype, rowdel, rowins, move_list, move_count, pool_top,
-                                pool_cap, overflow, ks);
+                                pool_cap, overflow, tight, ks);
 }
-void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, hipStream_t s) {
-  if (n) k_csr_newcap<<<grid_for(n), kTpb, 0, s>>>(deg, newcap, newcap64, n);
+void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, int tight, hipStream_t s) {
+  if (n) k_csr_newcap<<<grid_for(n), kTpb, 0, s>>>(deg, newcap, newcap64, n, tight);
 }
 void launch_csr_move_rows(CsrRef from, CsrRef to, const uint64_t* new_off, const uint32_t* new_cap, uint32_t n,
                           hipStream_t s) {

@@ -153,13 +153,14 @@ void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uin
 void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                      const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,
                      uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
-                     uint32_t* overflow, int ks, hipStream_t s);
+                     uint32_t* overflow, int tight, int ks, hipStream_t s);
 void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
                             const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
                             int directed, int64_t* delta, uint32_t* err, uint32_t* first_bad, i64a* dm,
                             int ks, hipStream_t s);
 // new_cap[u] = deg[u] + slack, for a pool rebuild
-void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, hipStream_t s);
+// (tight: exactly deg[u], no slack)
+void launch_csr_newcap(const uint32_t* deg, uint32_t* newcap, uint64_t* newcap64, uint32_t n, int tight, hipStream_t s);
 void launch_csr_move_rows(CsrRef from, CsrRef to, const uint64_t* new_off, const uint32_t* new_cap, uint32_t n,
                           hipStream_t s);
 void launch_csr_entries(CsrRef c, uint32_t n, uint64_t* out_keys, int64_t* out_w, u64a* counter, hipStream_t s);

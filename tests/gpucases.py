@@ -17,13 +17,15 @@ def first_trace_divergence(tg: np.ndarray, to: np.ndarray):
     return None
 
 
-def run_parity(n, edges, batches, directed=False, full_state=True, check_invariants=True, **cfg):
+def run_parity(n, edges, batches, directed=False, full_state=True, check_invariants=True, gpu_flags=0,
+               stats_out=None, **cfg):
     """Create both sides, apply the same batches and compare after every step.  Returns the
-    GPU graph and the oracle for further checks."""
+    GPU graph and the oracle for further checks.  gpu_flags go to the GPU side only (they
+    select internal paths, not results); per-batch GPU statistics are appended to stats_out."""
     import paper_2502_18497_amd as ldl
 
     og = oracle.Oracle(n, edges, directed=directed, flags=oracle.FLAG_TRACE, **cfg)
-    g = ldl.Graph(n, edges, directed=directed, **cfg)
+    g = ldl.Graph(n, edges, directed=directed, test_flags=gpu_flags, **cfg)
     g.set_trace(True)
     # the trace is enabled after creation on the GPU side: compare creation by state only
     step = "create"
@@ -51,6 +53,8 @@ def run_parity(n, edges, batches, directed=False, full_state=True, check_invaria
         rco = og.apply_batch(b.ins, b.dels, b.chg)
         assert rco == 0, (step, rco)
         assert isinstance(rcg, dict), (step, rcg)
+        if stats_out is not None:
+            stats_out.append(rcg)
         msgs = compare()
         if msgs:
             div = first_trace_divergence(g.trace(), og.trace())

@@ -1,0 +1,50 @@
+"""Rarely taken internal paths of the GPU library, forced by ldl_config.test_flags, must leave
+every result bit-identical to the oracle:
+  1  one decoupling round between host checks: live candidates remain after the speculative
+     pass, so the filter is finished and its moves committed as a second phase
+  2  minimal hub hash-table pool: hub tables overflow, the iteration is undone and redone
+  4  no spare adjacency capacity: every insertion moves its row, pools grow under load
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpucases import run_parity
+
+pytestmark = pytest.mark.gpu
+
+ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR = 1, 2, 4
+
+
+def _batches(stream, sizes):
+    return [stream.batch(s) for s in sizes]
+
+
+@pytest.mark.parametrize("flags", [ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR])
+def test_rmat_undirected_rare_paths(flags):
+    s = synth.rmat_undirected(scale=11, seed_offset=400)
+    stats = []
+    run_parity(s.n, s.edges(), _batches(s, [800, 60, 800]), gpu_flags=flags, stats_out=stats)
+    if flags & ONE_ROUND:
+        # more filter rounds than iterations: some filters needed rounds after the first pass
+        assert any(st["lf_rounds"] > st["move_iters"] + st["refine_iters"] for st in stats), stats
+
+
+@pytest.mark.parametrize("flags", [ONE_ROUND | TIGHT_CSR, SMALL_HUB_POOL])
+def test_directed_rare_paths(flags):
+    s = synth.rmat_directed_lognormal(1 << 11, 12 * (1 << 11), seed_offset=410)
+    run_parity(s.n, s.edges(), _batches(s, [400, 40, 400]), directed=True, gpu_flags=flags)
+
+
+def test_hub_overflow_and_tight_rows_planted():
+    # a 5,200-neighbour hub on a planted graph with every rare path forced
+    s = synth.Stream(8000, False, synth.BASE_SEED + 420)
+    s.planted(100, 0.08, 0.0005, 1, 8)
+    e = s.edges()
+    rng = np.random.default_rng(9)
+    have = {(int(min(u, v)), int(max(u, v))) for u, v, _ in e}
+    hub = 23
+    extra = [(hub, int(v), int(rng.integers(1, 9))) for v in rng.permutation(8000)[:5200]
+             if int(v) != hub and (min(hub, int(v)), max(hub, int(v))) not in have]
+    e = np.concatenate([e, np.array(extra, dtype=np.uint32)])
+    run_parity(8000, e, _batches(s, [200, 200]), gpu_flags=ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR)
