@@ -176,6 +176,51 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def kernel_source_sha():
+    """Hash of the candidate-kernel source: counters taken on another version do not apply."""
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2502_18497_amd", "csrc", "kernels_move.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, avg_launch_us):
+    """HBM traffic of `kernel` from the committed rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE
+    per dispatch, each scaled by the factor the same counter reads on a plain copy of known
+    size), as GB/s over the kernel's average launch time; None when no summary for this kernel
+    and this kernel source exists."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("source_sha") != kernel_source_sha():
+        return None
+    k = doc.get("kernels", {}).get(kernel)
+    if not k or avg_launch_us <= 0:
+        return None
+    per_launch = 1024.0 * (k["fetch_kib"] * doc["copy_factor_fetch"] + k["write_kib"] * doc["copy_factor_write"])
+    return per_launch / (avg_launch_us * 1e-6) / 1e9
+
+
+def run_copy(args):
+    """Counter calibration: a plain device-to-device copy of a known size (torch's copy kernel),
+    repeated a few times; rocprofv3 FETCH_SIZE / WRITE_SIZE of these dispatches give the factor
+    between the counters and bytes moved."""
+    import torch
+
+    n = args.copy_mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n, "copies": 5}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,7 +232,8 @@ def main():
     ap.add_argument("--small-steps", type=int, default=20)
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["rmat", "mix", "serve"], default="rmat")
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy"], default="rmat")
+    ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--graphs", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--mix-max-exp", type=float, default=5.0)
@@ -207,6 +253,8 @@ def main():
         return run_mix(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "copy":
+        return run_copy(args)
 
     import numpy as np
     import torch
@@ -226,13 +274,17 @@ def main():
     s = synth.rmat_undirected(scale=args.scale)
     e = s.edges()
     log(f"generated n={s.n} edges={len(e)} in {time.perf_counter() - t0:.1f}s")
-    t0 = time.perf_counter()
-    g = ldl.Graph(s.n, e, profile=True)
-    create_s = time.perf_counter() - t0
-    log(f"create (static Leiden) {create_s:.2f}s Q={g.modularity():.6f}")
-
     def to_dev(b):
         return [torch.from_numpy(x.astype(np.int32)).cuda() if len(x) else None for x in (b.ins, b.dels, b.chg)]
+
+    # static Leiden as the first batch on an empty graph (the same computation as ldl_create): its
+    # first iterations scan the whole graph, so its kernel counters give the full-frontier scan rate
+    t0 = time.perf_counter()
+    g = ldl.Graph(s.n, np.zeros((0, 3), np.uint32), profile=True)
+    create_stats = g.apply_batch_device(torch.from_numpy(e.astype(np.int32)).cuda(), None, None)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    log(f"create (static Leiden) {create_s:.2f}s Q={g.modularity():.6f}")
 
     big = [to_dev(s.batch(args.batch)) for _ in range(args.warmup + args.steps)]
     small = [to_dev(s.batch(args.small_batch)) for _ in range(args.small_steps)]
@@ -254,8 +306,9 @@ def main():
 
     T, per, stats = timed(big[args.warmup:])
     log(f"timed {args.steps} batches of {args.batch}: {T:.3f}s")
-    Ts, per_s, _ = timed(small)
-    log(f"timed {args.small_steps} batches of {args.small_batch}: {Ts:.3f}s")
+    if small:
+        Ts, per_s, _ = timed(small)
+        log(f"timed {args.small_steps} batches of {args.small_batch}: {Ts:.3f}s")
 
     updates = sum(int(x.shape[0]) for b in big[args.warmup:] for x in b if x is not None)
     value = updates / T
@@ -268,6 +321,23 @@ def main():
     bm_ms = sum(st["bm_ms"] for st in stats)
     bm_bytes = sum(st["bm_bytes"] for st in stats)
     small_updates = sum(int(x.shape[0]) for b in small for x in b if x is not None)
+
+    cb_ms, cb_bytes = np.array(create_stats["bin_ms"]), np.array(create_stats["bin_bytes"])
+    cdom = int(np.argmax(cb_ms))
+    full_frontier = {
+        "workload": f"static Leiden on rmat{args.scale} (all {len(e)} edges as one batch)",
+        "scanned_entries": int(create_stats["scanned_entries"]),
+        "local_move_ms": float(create_stats["bm_ms"]),
+        "local_move_GBps_all_bins": float(create_stats["bm_bytes"] / (create_stats["bm_ms"] * 1e-3) / 1e9)
+        if create_stats["bm_ms"] > 0 else 0.0,
+        "dominant_kernel": ldl.candidate_kernel_name(cdom),
+        "dominant_GBps": float(cb_bytes[cdom] / (cb_ms[cdom] * 1e-3) / 1e9) if cb_ms[cdom] > 0 else 0.0,
+        "per_kernel_GBps": {ldl.candidate_kernel_name(k): round(float(cb_bytes[k] / (cb_ms[k] * 1e-3) / 1e9), 1)
+                            for k in range(ldl.NUM_CATS) if cb_ms[k] > 0},
+    }
+    dom_name = ldl.candidate_kernel_name(dom)
+    avg_us = float(1e3 * bin_ms[dom] / max(1, bin_launch[dom]))
+    traffic = measured_traffic(dom_name, avg_us)
 
     cpu_obj = None
     if th is not None:
@@ -302,9 +372,8 @@ def main():
                    "mix": "70/20/10 insert/delete/reweight", "gamma": 1, "N": 2, "L": 4, "M": 5,
                    "alpha": 0.001, "beta": 0.01},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ldl.candidate_kernel_name(dom), "launches": int(bin_launch[dom]),
-                     "avg_launch_us": float(1e3 * bin_ms[dom] / max(1, bin_launch[dom])),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom_name, "launches": int(bin_launch[dom]), "avg_launch_us": avg_us,
                      "bytes_per_launch": float(bin_bytes[dom] / max(1, bin_launch[dom]))},
         "cpu_baseline": cpu_obj,
         "latency_ms": {"p50": float(1e3 * np.percentile(per, 50)), "p99": float(1e3 * np.percentile(per, 99))},
@@ -312,10 +381,11 @@ def main():
         "local_move_GBps_all_bins": (bm_bytes / (bm_ms * 1e-3) / 1e9) if bm_ms > 0 else 0.0,
         "candidate_kernels": {ldl.candidate_kernel_name(k): {"ms": float(bin_ms[k]), "GBps": float(
             bin_bytes[k] / (bin_ms[k] * 1e-3) / 1e9) if bin_ms[k] > 0 else 0.0, "launches": int(bin_launch[k])}
-            for k in range(20) if bin_launch[k]},
+            for k in range(ldl.NUM_CATS) if bin_launch[k]},
         "small_batch": {"batch": args.small_batch, "edges_per_s": small_updates / Ts,
                         "p50_ms": float(1e3 * np.percentile(per_s, 50)),
-                        "p99_ms": float(1e3 * np.percentile(per_s, 99))},
+                        "p99_ms": float(1e3 * np.percentile(per_s, 99))} if small else None,
+        "full_frontier_scan": full_frontier,
         "create_s": create_s,
         "modularity": g.modularity(),
     }

@@ -100,15 +100,15 @@ typedef struct ldl_batch_stats {
   double bm_ms;               /* summed local-move kernel time in ms (profile != 0)       */
   double bm_bytes;            /* algorithmic bytes of those kernels (profile != 0)        */
   double total_ms;            /* wall time of the call measured with HIP events           */
-  /* per candidate kernel k = 10*refine + 5*wide + bin, where bin is the degree bin of the
-   * scanned vertices (entries per vertex in (0,8], (8,32], (32,128], (128,2048], above),
-   * wide = 1 for the int64 weights of aggregate levels and refine = 1 for BestRef:
+  /* per candidate kernel k = 12*refine + 6*wide + bin, where bin is the degree bin of the
+   * scanned vertices (entries per vertex in (0,8], (8,32], (32,128], (128,512], (512,2048],
+   * above), wide = 1 for the int64 weights of aggregate levels and refine = 1 for BestRef:
    * launches, kernel time (HIP events around each launch, profile != 0), algorithmic bytes
    * (profile != 0) and adjacency entries read */
-  uint64_t bin_launches[20];
-  double bin_ms[20];
-  double bin_bytes[20];
-  uint64_t bin_entries[20];
+  uint64_t bin_launches[24];
+  double bin_ms[24];
+  double bin_bytes[24];
+  uint64_t bin_entries[24];
   uint64_t lf_rounds;         /* decoupling rounds launched                               */
   uint64_t host_syncs;        /* stream synchronisations (host reads of device counters)  */
   uint64_t agg_records;       /* reduced records applied to levels above 0                */

@@ -33,13 +33,17 @@ class ldl_config(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
 
 
+NUM_BINS = 6                 # degree bins of the candidate kernels
+NUM_CATS = 4 * NUM_BINS      # x (move, refine) x (u32, i64 weights)
+
+
 class ldl_batch_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "updates", "levels_processed", "move_iters", "refine_iters", "scanned_vertices", "scanned_entries",
         "distinct_comms", "candidates", "accepted", "rollbacks", "refine_moves", "agg_tuples", "bm_launches")] + \
         [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")] + \
-        [("bin_launches", ctypes.c_uint64 * 20), ("bin_ms", ctypes.c_double * 20),
-         ("bin_bytes", ctypes.c_double * 20), ("bin_entries", ctypes.c_uint64 * 20)] + \
+        [("bin_launches", ctypes.c_uint64 * NUM_CATS), ("bin_ms", ctypes.c_double * NUM_CATS),
+         ("bin_bytes", ctypes.c_double * NUM_CATS), ("bin_entries", ctypes.c_uint64 * NUM_CATS)] + \
         [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")]
 
     def as_dict(self) -> dict:
@@ -350,19 +354,13 @@ class Server:
 
 
 def candidate_kernel_name(k: int, directed: bool = False) -> str:
-    """rocprofv3 name of candidate kernel k = 10*refine + 5*wide + bin (see ldl_batch_stats)."""
-    refine, wide, b = k // 10, (k // 5) % 2, k % 5
+    """rocprofv3 name of candidate kernel k = 12*refine + 6*wide + bin (see ldl_batch_stats)."""
+    refine, wide, b = k // (2 * NUM_BINS), (k // NUM_BINS) % 2, k % NUM_BINS
     wt = "long" if wide else "unsigned int"
     d, r = ("true" if directed else "false"), ("true" if refine else "false")
-    if b == 0:
-        return f"k_best_group<{wt}, 8, {d}, {r}>"
-    if b == 1:
-        return f"k_best_group<{wt}, 32, {d}, {r}>"
-    if b == 2:
-        return f"k_best_hash<{wt}, 64, 256, {d}, {r}>"
-    if b == 3:
-        return f"k_best_hash<{wt}, 256, 4096, {d}, {r}>"
-    return f"k_hub_insert<{wt}, {d}, {r}>"
+    return [f"k_best_group<{wt}, 8, {d}, {r}>", f"k_best_group<{wt}, 32, {d}, {r}>",
+            f"k_best_wave<{wt}, 256, {d}, {r}>", f"k_best_wave<{wt}, 1024, {d}, {r}>",
+            f"k_best_hash<{wt}, 256, 4096, {d}, {r}>", f"k_hub_insert<{wt}, {d}, {r}>"][b]
 
 
 def version() -> str:

@@ -427,7 +427,7 @@ struct Engine {
     }
   }
 
-  // upper bound on the number of hub vertices (more than kBinLimit[3] entries) of level r
+  // upper bound on the number of hub vertices (more than kBinLimit[kNumBins - 2] entries) of level r
   uint32_t hub_bound(int r) const {
     const Level& V = lv[r];
     const uint64_t ent = V.out.pool_cap + (directed ? V.in.pool_cap : 0);
@@ -680,7 +680,7 @@ struct Engine {
     MoveView mv = view(r, refine);
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
-    const int cat0 = 10 * refine + 5 * lv[r].out.ref.wide;
+    const int cat0 = 2 * kNumBins * refine + kNumBins * lv[r].out.ref.wide;
     launch_bin_count(mv, list, cnt, refine, bhist, (uint32_t*)&ds->ps, sizeof(PassScal) / 4, st);
     launch_bin_fill(mv, list, cnt, refine, bhist, binbuf, ds->bin_start, ds->bins, st);
     const uint32_t hb = hub_bound(r);
@@ -722,7 +722,7 @@ struct Engine {
     // the parent in refinement); per distinct community its totals; per candidate 28 bytes.
     // The hub insert kernel reads per vertex its id, offsets, degrees and label, and the entries.
     const int wide = lv[r].out.ref.wide;
-    const int cat0 = 10 * refine + 5 * wide;
+    const int cat0 = 2 * kNumBins * refine + kNumBins * wide;
     const double wb = wide ? 8.0 : 4.0;
     const double dirf = directed ? 2.0 : 1.0;
     const double per_v = 4 + 12 * dirf + 4 + 8 * dirf + (refine ? 0 : 8 * dirf);

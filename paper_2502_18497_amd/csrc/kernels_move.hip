@@ -65,7 +65,8 @@ template <bool REF>
 __device__ __forceinline__ uint32_t entry_key(const MoveView& mv, uint32_t v, uint32_t labv, uint32_t x) {
   if (x == v) return kEmpty;
   if (!REF) return mv.lab[x];
-  return mv.lab[x] == labv ? mv.par[x] : kEmpty;
+  const uint32_t lx = mv.lab[x], px = mv.par[x];   // two independent gathers
+  return lx == labv ? px : kEmpty;
 }
 
 struct VInfo {
@@ -73,24 +74,25 @@ struct VInfo {
   uint32_t lab;
 };
 
+// gain of moving to b given b's totals (Kob, Kib) and the weights towards b and the own community
 template <bool DIR, bool REF>
-__device__ __forceinline__ i128 gain(const MoveView& mv, const VInfo& vi, uint32_t b, int64_t accb, int64_t acca) {
+__device__ __forceinline__ i128 gain_t(const MoveView& mv, const VInfo& vi, int64_t Kob, int64_t Kib, int64_t accb,
+                                       int64_t acca) {
   if (!REF) {
-    const int64_t Kob = mv.Kout[b];
-    if (DIR) {
-      const int64_t Kib = mv.Kin[b];
+    if (DIR)
       return (i128)mv.qm * (accb - acca) -
              (i128)mv.p * ((i128)vi.ko * (Kib - vi.Kia + vi.ki) + (i128)vi.ki * (Kob - vi.Koa + vi.ko));
-    }
     return (i128)mv.qm * (accb - acca) - (i128)mv.p * ((i128)vi.ko * (Kob - vi.Koa + vi.ko));
   } else {
-    const int64_t Kob = mv.Kout[b];
-    if (DIR) {
-      const int64_t Kib = mv.Kin[b];
-      return (i128)mv.qm * accb - (i128)mv.p * ((i128)vi.ko * Kib + (i128)vi.ki * Kob);
-    }
+    if (DIR) return (i128)mv.qm * accb - (i128)mv.p * ((i128)vi.ko * Kib + (i128)vi.ki * Kob);
     return (i128)mv.qm * accb - (i128)mv.p * ((i128)vi.ko * Kob);
   }
+}
+template <bool DIR, bool REF>
+__device__ __forceinline__ i128 gain(const MoveView& mv, const VInfo& vi, uint32_t b, int64_t accb, int64_t acca) {
+  const int64_t Kob = mv.Kout[b];
+  const int64_t Kib = DIR ? mv.Kin[b] : 0;
+  return gain_t<DIR, REF>(mv, vi, Kob, Kib, accb, acca);
 }
 
 template <bool DIR, bool REF>
@@ -121,11 +123,10 @@ __device__ __forceinline__ int bin_of(const MoveView& mv, uint32_t v, int refine
   if (refine && !(mv.par[v] == v && mv.rsize[v] == 1)) return -1;   // only singletons move
   const uint64_t T = (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
   if (T == 0) return -1;
-  if (T <= kBinLimit[0]) return 0;
-  if (T <= kBinLimit[1]) return 1;
-  if (T <= kBinLimit[2]) return 2;
-  if (T <= kBinLimit[3]) return 3;
-  return 4;
+#pragma unroll
+  for (int b = 0; b < kNumBins - 1; ++b)
+    if (T <= kBinLimit[b]) return b;
+  return kNumBins - 1;
 }
 
 // block b owns list[b*chunk, (b+1)*chunk); hist[bin * gridDim + b] = its count per bin
@@ -310,9 +311,14 @@ __device__ __forceinline__ void stats_flush(LocalStats ls, const MoveStats& st, 
 }
 
 // ------------------------------------------------------------------ small degrees: lane groups
+// G lanes per vertex, one entry per lane; every lane group works on U vertices at once and
+// issues each phase's loads for all of them before using any (the kernel is bound by the
+// latency of its dependent gathers: vertex -> row -> neighbour -> label -> community totals).
 template <typename WT, int G, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
-  constexpr int VPB = kTpb / G;            // vertices per block iteration
+  constexpr int VPB = kTpb / G;            // vertices per block and set
+  constexpr int U = 2;                     // vertex sets per block iteration
+  static_assert(U * VPB <= 256, "stage capacity");
   __shared__ Stage<256> stage;
   __shared__ unsigned long long red[5 * (kTpb / kWave)];
   if (threadIdx.x == 0) stage.n = 0;
@@ -321,56 +327,94 @@ __global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, BinRef br, Can
   const uint32_t* list = br.base + *br.start;
   LocalStats ls;
   const int li = threadIdx.x & (G - 1);
-  for (uint64_t base = (uint64_t)blockIdx.x * VPB; base < count; base += (uint64_t)gridDim.x * VPB) {
-    const uint64_t gid = base + threadIdx.x / G;
-    const bool active = gid < count;        // every lane stays for the shuffles
-    uint32_t v = 0, key = kEmpty;
-    int64_t w = 0;
-    VInfo vi{};
-    uint32_t T = 0;
-    if (active) {
-      v = list[gid];
-      vi = vinfo<DIR, REF>(mv, v);
-      const uint32_t dout = mv.out.deg[v];
-      const uint32_t din = DIR ? mv.in.deg[v] : 0;
-      T = dout + din;
-      if ((uint32_t)li < T) {
-        uint32_t x;
-        entry_at<WT, DIR>(mv, mv.out.off[v], dout, DIR ? mv.in.off[v] : 0, (uint32_t)li, x, w);
-        key = entry_key<REF>(mv, v, vi.lab, x);
+  for (uint64_t base = (uint64_t)blockIdx.x * VPB * U; base < count; base += (uint64_t)gridDim.x * VPB * U) {
+    bool act[U];
+    uint32_t v[U], T[U], dout[U];
+    uint64_t oo[U], oi[U];
+    VInfo vi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t gid = base + (uint64_t)u * VPB + threadIdx.x / G;
+      act[u] = gid < count;                  // every lane stays for the shuffles
+      v[u] = act[u] ? list[gid] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      dout[u] = 0; T[u] = 0; oo[u] = 0; oi[u] = 0;
+      vi[u] = VInfo{};
+      if (act[u]) {
+        dout[u] = mv.out.deg[v[u]];
+        T[u] = dout[u] + (DIR ? mv.in.deg[v[u]] : 0);
+        oo[u] = mv.out.off[v[u]];
+        if (DIR) oi[u] = mv.in.off[v[u]];
+        vi[u].lab = mv.lab[v[u]];
+        vi[u].ko = mv.kout[v[u]];
+        vi[u].ki = DIR ? mv.kin[v[u]] : 0;
       }
     }
-    // weight towards the own community (move only)
-    int64_t own = (!REF && key != kEmpty && key == vi.lab) ? w : 0;
+    uint32_t x[U];
+    int64_t w[U];
 #pragma unroll
-    for (int o = G >> 1; o > 0; o >>= 1) own += __shfl_xor(own, o, G);
+    for (int u = 0; u < U; ++u) {
+      if (!DIR) vi[u].ki = vi[u].ko;
+      if (!REF && act[u]) {
+        vi[u].Koa = mv.Kout[vi[u].lab];
+        vi[u].Kia = DIR ? mv.Kin[vi[u].lab] : vi[u].Koa;
+      }
+      x[u] = v[u];                           // the vertex itself does not count
+      w[u] = 0;
+      if (act[u] && (uint32_t)li < T[u]) entry_at<WT, DIR>(mv, oo[u], dout[u], oi[u], (uint32_t)li, x[u], w[u]);
+    }
+    uint32_t key[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) key[u] = act[u] ? entry_key<REF>(mv, v[u], vi[u].lab, x[u]) : kEmpty;
     // sum equal keys across the group; the lowest lane of each key represents it
-    int64_t acc = 0;
-    bool rep = key != kEmpty && (REF || key != vi.lab);
+    int64_t acc[U], own[U];
+    bool rep[U];
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const uint32_t kj = (uint32_t)__shfl((int)key, j, G);
-      const int64_t wj = __shfl(w, j, G);
-      if (kj == key) {
-        acc += wj;
-        if (j < li) rep = false;
+    for (int u = 0; u < U; ++u) {
+      own[u] = (!REF && key[u] != kEmpty && key[u] == vi[u].lab) ? w[u] : 0;
+#pragma unroll
+      for (int o = G >> 1; o > 0; o >>= 1) own[u] += __shfl_xor(own[u], o, G);
+      acc[u] = 0;
+      rep[u] = key[u] != kEmpty && (REF || key[u] != vi[u].lab);
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const uint32_t kj = (uint32_t)__shfl((int)key[u], j, G);
+        const int64_t wj = __shfl(w[u], j, G);
+        if (kj == key[u]) {
+          acc[u] += wj;
+          if (j < li) rep[u] = false;
+        }
       }
     }
-    Best b;
-    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    if (active && rep) b = make_best(gain<DIR, REF>(mv, vi, key, acc, own), key);
-    ls.distinct += (active && rep) ? 1 : 0;
-    b = group_best(b, G);
-    if (active && li == 0) {
-      ls.entries += T;
-      ls.vertices += 1;
-      if (b.valid && best_gain(b) > 0) {
-        stage_push(stage, v, REF ? v : vi.lab, b);
-        note_cand(ls, b);
+    int64_t Kob[U], Kib[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      Kob[u] = 0; Kib[u] = 0;
+      if (act[u] && rep[u]) {
+        Kob[u] = mv.Kout[key[u]];
+        if (DIR) Kib[u] = mv.Kin[key[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      Best b;
+      b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
+      if (act[u] && rep[u]) b = make_best(gain_t<DIR, REF>(mv, vi[u], Kob[u], Kib[u], acc[u], own[u]), key[u]);
+      ls.distinct += (act[u] && rep[u]) ? 1 : 0;
+      b = group_best(b, G);
+      if (act[u] && li == 0) {
+        ls.entries += T[u];
+        ls.vertices += 1;
+        if (b.valid && best_gain(b) > 0) {
+          stage_push(stage, v[u], REF ? v[u] : vi[u].lab, b);
+          note_cand(ls, b);
+        }
       }
     }
     __syncthreads();
-    if (stage.n + VPB > 256) stage_flush(stage, cand);
+    if (stage.n + U * VPB > 256) stage_flush(stage, cand);
   }
   stage_flush(stage, cand);
   stats_flush(ls, st, red);
@@ -416,10 +460,149 @@ __device__ __forceinline__ void table_insert(uint32_t* keys, u64a* vals, uint32_
   }
 }
 
-// TEAM lanes per vertex with a private LDS table of SLOTS (>= 2 T) entries
+// ------------------------------------------------------------------ wavefront teams
+// Orders the LDS accesses of one wavefront (all its lanes) with respect to each other.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per vertex with a private LDS table of pow2 >= max(64, 2 T) slots (at most
+// SLOTS).  The wavefronts of a workgroup run independently: no workgroup barrier inside the
+// loop, candidates staged per wavefront.  A lane loads all of its entries (at most
+// SLOTS / 128), then all their labels, before inserting; slots are evaluated SB at a time.
+template <typename WT, int SLOTS, bool DIR, bool REF>
+__global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
+  constexpr int W = kTpb / kWave;
+  constexpr int EPL = SLOTS / 2 / kWave;   // entries per lane, T <= SLOTS / 2
+  constexpr int SB = 4;
+  constexpr uint32_t SCAP = 32;            // staged candidates per wavefront
+  __shared__ uint32_t skey[W][SLOTS];
+  __shared__ u64a sval[W][SLOTS];
+  __shared__ uint32_t cv[W][SCAP], ca[W][SCAP], cb[W][SCAP];
+  __shared__ uint64_t clo[W][SCAP];
+  __shared__ int64_t chi[W][SCAP];
+  __shared__ unsigned long long red_s[5 * W];
+  const int wv = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const uint32_t count = *br.count;
+  const uint32_t* list = br.base + *br.start;
+  uint32_t* keys = skey[wv];
+  u64a* vals = sval[wv];
+  LocalStats ls;
+  uint32_t ns = 0;   // staged candidates of this wavefront (same in every lane)
+  auto flush = [&]() {
+    wave_sync();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(cand.count, ns);
+    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+    if ((uint32_t)lane < ns) {
+      cand.v[base + lane] = cv[wv][lane];
+      cand.a[base + lane] = ca[wv][lane];
+      cand.b[base + lane] = cb[wv][lane];
+      cand.glo[base + lane] = clo[wv][lane];
+      cand.ghi[base + lane] = chi[wv][lane];
+    }
+    wave_sync();
+    ns = 0;
+  };
+  for (uint64_t i = (uint64_t)blockIdx.x * W + wv; i < count; i += (uint64_t)gridDim.x * W) {
+    const uint32_t v = list[i];
+    const uint32_t dout = mv.out.deg[v];
+    const uint32_t din = DIR ? mv.in.deg[v] : 0;
+    const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
+    const VInfo vi = vinfo<DIR, REF>(mv, v);
+    const uint32_t T = dout + din;
+    uint32_t size = 64;
+    while (size < 2 * T && size < (uint32_t)SLOTS) size <<= 1;
+    for (uint32_t s = lane; s < size; s += kWave) {
+      keys[s] = kEmpty;
+      vals[s] = 0;
+    }
+    uint32_t xs[EPL];
+    int64_t ws[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const uint32_t j = (uint32_t)lane + (uint32_t)q * kWave;
+      xs[q] = v;                              // the vertex itself does not count
+      ws[q] = 0;
+      if (j < T) entry_at<WT, DIR>(mv, oo, dout, oi, j, xs[q], ws[q]);
+    }
+    uint32_t ks[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) ks[q] = entry_key<REF>(mv, v, vi.lab, xs[q]);
+    wave_sync();                              // table cleared
+    int64_t own = 0;
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const uint32_t key = ks[q];
+      if (key == kEmpty) continue;
+      if (!REF && key == vi.lab) {
+        own += ws[q];
+        continue;
+      }
+      table_insert(keys, vals, size - 1, key, ws[q]);
+    }
+    wave_sync();
+    own = wave_sum_i64(own);
+    Best b;
+    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
+    for (uint32_t s0 = 0; s0 < size; s0 += SB * kWave) {
+      uint32_t kk[SB];
+      int64_t av[SB], Kb[SB], Kib[SB];
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        const uint32_t s = s0 + (uint32_t)lane + (uint32_t)q * kWave;
+        kk[q] = s < size ? keys[s] : kEmpty;
+        av[q] = s < size ? (int64_t)vals[s] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        Kb[q] = 0; Kib[q] = 0;
+        if (kk[q] != kEmpty) {
+          Kb[q] = mv.Kout[kk[q]];
+          if (DIR) Kib[q] = mv.Kin[kk[q]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        if (kk[q] == kEmpty) continue;
+        ls.distinct += 1;
+        const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), kk[q]);
+        if (better(c, b)) b = c;
+      }
+    }
+    b = group_best(b, kWave);                 // every lane holds the wavefront's best
+    wave_sync();                              // table reads done before the next vertex clears it
+    if (lane == 0) {
+      ls.entries += T;
+      ls.vertices += 1;
+    }
+    if (b.valid && best_gain(b) > 0) {
+      if (lane == 0) {
+        cv[wv][ns] = v;
+        ca[wv][ns] = REF ? v : vi.lab;
+        cb[wv][ns] = b.id;
+        clo[wv][ns] = b.lo;
+        chi[wv][ns] = b.hi;
+        note_cand(ls, b);
+      }
+      if (++ns == SCAP) flush();
+    }
+  }
+  if (ns) flush();
+  stats_flush(ls, st, red_s);
+}
+
+// TEAM lanes per vertex with a private LDS table of pow2 >= max(64, 2 T) slots (at most SLOTS).
+// A lane loads all of its entries (at most SLOTS / (2 TEAM)), then all their labels, before
+// inserting; table slots are evaluated SB at a time with their totals gathered together.
 template <typename WT, int TEAM, int SLOTS, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int TEAMS = kTpb / TEAM;
+  constexpr int EPL = SLOTS / 2 / TEAM;    // entries per lane, T <= SLOTS / 2
+  constexpr int SB = 4;                    // slots per lane per evaluation step
   __shared__ uint32_t skey[TEAMS][SLOTS];
   __shared__ u64a sval[TEAMS][SLOTS];
   __shared__ int64_t red_i[kTpb / kWave];
@@ -436,44 +619,77 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
     const uint64_t slot = base + t;
     const bool active = slot < count;
     const uint32_t v = active ? list[slot] : 0;
-    for (int s = li; s < SLOTS; s += TEAM) {
+    uint32_t dout = 0, din = 0;
+    uint64_t oo = 0, oi = 0;
+    VInfo vi{};
+    if (active) {
+      dout = mv.out.deg[v];
+      din = DIR ? mv.in.deg[v] : 0;
+      oo = mv.out.off[v];
+      if (DIR) oi = mv.in.off[v];
+      vi = vinfo<DIR, REF>(mv, v);
+    }
+    const uint32_t T = dout + din;
+    // the team's table: pow2 >= 2T slots (at least 64), cleared and scanned, not all SLOTS
+    uint32_t size = 64;
+    while (size < 2 * T && size < (uint32_t)SLOTS) size <<= 1;
+    for (uint32_t s = li; s < size; s += TEAM) {
       skey[t][s] = kEmpty;
       sval[t][s] = 0;
     }
-    __syncthreads();
-    VInfo vi{};
+    uint32_t xs[EPL];
+    int64_t ws[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const uint32_t j = (uint32_t)li + (uint32_t)q * TEAM;
+      xs[q] = v;                              // the vertex itself does not count
+      ws[q] = 0;
+      if (active && j < T) entry_at<WT, DIR>(mv, oo, dout, oi, j, xs[q], ws[q]);
+    }
+    uint32_t ks[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) ks[q] = active ? entry_key<REF>(mv, v, vi.lab, xs[q]) : kEmpty;
+    __syncthreads();                          // table cleared
     int64_t own = 0;
-    uint32_t T = 0;
-    if (active) {
-      vi = vinfo<DIR, REF>(mv, v);
-      const uint32_t dout = mv.out.deg[v];
-      const uint32_t din = DIR ? mv.in.deg[v] : 0;
-      const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-      T = dout + din;
-      for (uint32_t j = li; j < T; j += TEAM) {
-        uint32_t x;
-        int64_t w;
-        entry_at<WT, DIR>(mv, oo, dout, oi, j, x, w);
-        const uint32_t key = entry_key<REF>(mv, v, vi.lab, x);
-        if (key == kEmpty) continue;
-        if (!REF && key == vi.lab) {
-          own += w;
-          continue;
-        }
-        table_insert(skey[t], sval[t], SLOTS - 1, key, w);
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      const uint32_t key = ks[q];
+      if (key == kEmpty) continue;
+      if (!REF && key == vi.lab) {
+        own += ws[q];
+        continue;
       }
+      table_insert(skey[t], sval[t], size - 1, key, ws[q]);
     }
     __syncthreads();
     own = team_sum<TEAM>(own, red_i);
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
     if (active) {
-      for (int s = li; s < SLOTS; s += TEAM) {
-        const uint32_t key = skey[t][s];
-        if (key == kEmpty) continue;
-        ls.distinct += 1;
-        const Best c = make_best(gain<DIR, REF>(mv, vi, key, (int64_t)sval[t][s], own), key);
-        if (better(c, b)) b = c;
+      for (uint32_t s0 = 0; s0 < size; s0 += SB * TEAM) {
+        uint32_t kk[SB];
+        int64_t av[SB], Kb[SB], Kib[SB];
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          const uint32_t s = s0 + (uint32_t)li + (uint32_t)q * TEAM;
+          kk[q] = s < size ? skey[t][s] : kEmpty;
+          av[q] = s < size ? (int64_t)sval[t][s] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          Kb[q] = 0; Kib[q] = 0;
+          if (kk[q] != kEmpty) {
+            Kb[q] = mv.Kout[kk[q]];
+            if (DIR) Kib[q] = mv.Kin[kk[q]];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          if (kk[q] == kEmpty) continue;
+          ls.distinct += 1;
+          const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), kk[q]);
+          if (better(c, b)) b = c;
+        }
       }
     }
     b = team_best<TEAM>(b, red_b);
@@ -720,7 +936,10 @@ void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, C
       k_best_group<WT, 32, DIR, REF><<<persist_grid((c + 7) / 8), kTpb, 0, s>>>(mv, br, cand, st);
       break;
     case 2:
-      k_best_hash<WT, 64, 256, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_wave<WT, 256, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
+      break;
+    case 3:
+      k_best_wave<WT, 1024, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
       break;
     default:
       k_best_hash<WT, 256, 4096, DIR, REF><<<persist_grid(c), kTpb, 0, s>>>(mv, br, cand, st);

@@ -79,10 +79,12 @@ struct BinRef {
   const uint32_t* count;
 };
 
-constexpr int kNumBins = 5;
+constexpr int kNumBins = 6;
 constexpr uint32_t kHubScanSlots = 8192;   // table slots evaluated per hub scan workgroup
-// degree bins: total entries T in (0,8], (8,32], (32,128], (128,2048], (2048, inf)
-constexpr uint32_t kBinLimit[kNumBins - 1] = {8, 32, 128, 2048};
+// degree bins: total entries T in (0,8], (8,32], (32,128], (128,512], (512,2048], (2048, inf)
+constexpr uint32_t kBinLimit[kNumBins - 1] = {8, 32, 128, 512, 2048};
+// statistics category of a candidate kernel: 2 kNumBins refine + kNumBins wide + bin
+constexpr int kNumCats = 4 * kNumBins;
 
 // ---------------------------------------------------------------- sets and generic helpers
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -186,7 +188,7 @@ void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t*
 void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, int ks, hipStream_t s);
 
 // ---------------------------------------------------------------- local move / refinement
-// candidate kernels of degree bins 0..3 over a device-resident bin list
+// candidate kernels of degree bins 0..kNumBins-2 over a device-resident bin list
 void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int refine, CandBuf cand, MoveStats st,
                  hipStream_t s);
 // hub bin, device driven: per-hub table sizes, insert chunks and scan parts are prefix-summed
