@@ -188,20 +188,20 @@ def kernel_source_sha():
 def measured_traffic(kernel, avg_launch_us):
     """HBM traffic of `kernel` from the committed rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE
     per dispatch, each scaled by the factor the same counter reads on a plain copy of known
-    size), as GB/s over the kernel's average launch time; None when no summary for this kernel
-    and this kernel source exists."""
+    size): (GB/s over the kernel's average launch time, bytes per launch), or (None, None) when
+    no summary for this kernel and this kernel source exists."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         doc = json.load(f)
     if doc.get("source_sha") != kernel_source_sha():
-        return None
+        return None, None
     k = doc.get("kernels", {}).get(kernel)
     if not k or avg_launch_us <= 0:
-        return None
+        return None, None
     per_launch = 1024.0 * (k["fetch_kib"] * doc["copy_factor_fetch"] + k["write_kib"] * doc["copy_factor_write"])
-    return per_launch / (avg_launch_us * 1e-6) / 1e9
+    return per_launch / (avg_launch_us * 1e-6) / 1e9, per_launch
 
 
 def run_copy(args):
@@ -337,7 +337,7 @@ def main():
     }
     dom_name = ldl.candidate_kernel_name(dom)
     avg_us = float(1e3 * bin_ms[dom] / max(1, bin_launch[dom]))
-    traffic = measured_traffic(dom_name, avg_us)
+    traffic, traffic_bytes = measured_traffic(dom_name, avg_us)
 
     cpu_obj = None
     if th is not None:
@@ -372,7 +372,7 @@ def main():
                    "mix": "70/20/10 insert/delete/reweight", "gamma": 1, "N": 2, "L": 4, "M": 5,
                    "alpha": 0.001, "beta": 0.01},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": dom_name, "launches": int(bin_launch[dom]), "avg_launch_us": avg_us,
                      "bytes_per_launch": float(bin_bytes[dom] / max(1, bin_launch[dom]))},
         "cpu_baseline": cpu_obj,
