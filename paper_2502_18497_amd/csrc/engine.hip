@@ -154,6 +154,7 @@ struct Engine {
 
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
+  uint2* lpk = nullptr;   // (label, parent) of the level being refined, packed for one gather
   uint32_t *accE = nullptr, *accA = nullptr;
   LfFirst lfE{}, lfA{};
   uint32_t *lf_la = nullptr, *lf_lb = nullptr;
@@ -361,6 +362,7 @@ struct Engine {
     launch_fill_i64(Kout, 0, n, st);
     if (directed) launch_fill_i64(Kin, 0, n, st);
     oldlab = alloc<uint32_t>(n);
+    lpk = alloc<uint2>(n);
     oldpar = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
@@ -645,6 +647,7 @@ struct Engine {
     mv.in = directed ? V.in.ref : CsrRef{};
     mv.lab = V.lab;
     mv.par = V.par;
+    mv.lp = refine ? lpk : nullptr;
     mv.alive = V.alive;
     mv.kout = V.kout;
     mv.kin = V.kin;
@@ -821,7 +824,8 @@ struct Engine {
     Level* H = refine ? &lv[r + 1] : nullptr;
     int64_t* Krin = (refine && directed) ? H->kin : nullptr;
     auto commit = [&](const uint32_t* accp, const uint32_t* nap, int forward) {
-      if (refine) launch_ref_commit(accp, nap, n, cand, V.par, V.kout, V.kin, H->kout, Krin, V.rsize, forward, st);
+      if (refine)
+        launch_ref_commit(accp, nap, n, cand, V.par, lpk, V.kout, V.kin, H->kout, Krin, V.rsize, forward, st);
       else if (forward) commit_launch(r, accp, nap);
       else launch_commit_apply(accp, nap, n, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
     };
@@ -937,6 +941,7 @@ struct Engine {
     const uint32_t nR0 = count(S_RSET);
     launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st);
     launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 1, st);
+    launch_pack_lab_par(n, V.lab, V.par, lpk, st);   // refinement commits keep it current
     int cur = S_RSET;          // the set whose list this iteration scans
     bool rset_grew = false;    // SPExpand marked new members: rebuild the Rset list at the end
     CsrRef in = directed ? V.in.ref : V.out.ref;

@@ -1019,7 +1019,7 @@ void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_
   k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items, ks);
   prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
   k_fill_i64_dev<<<grid_for(k), kTpb, 0, s>>>(slot_out, -1, k);
-  const unsigned g = k < 8192 ? (unsigned)k : 8192u;
+  const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_lookup, 256));
   k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out, ks);
 }
 void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
@@ -1027,7 +1027,7 @@ void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uin
                        uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel, uint32_t* rowins, uint32_t* move_list,
                        uint32_t* move_count, int ks, hipStream_t s) {
   if (!k) return;
-  const unsigned g = k < 8192 ? (unsigned)k : 8192u;
+  const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_update, kTpb));
   k_seg_update<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel, rowins,
                                   move_list, move_count, ks);
 }
@@ -1036,7 +1036,7 @@ void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint6
                      uint32_t* move_list, const uint32_t* move_count, u64a* pool_top, uint64_t pool_cap,
                      uint32_t* overflow, int tight, int ks, hipStream_t s) {
   if (!k) return;
-  const unsigned g = k < 1024 ? (unsigned)k : 1024u;
+  const unsigned g = cap_blocks(k < 1024 ? k : 1024u, LDL_RESIDENT(k_seg_move, kTpb));
   k_seg_move<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, rtype, rowdel, rowins, move_list, move_count, pool_top,
                                 pool_cap, overflow, tight, ks);
 }

@@ -65,8 +65,8 @@ template <bool REF>
 __device__ __forceinline__ uint32_t entry_key(const MoveView& mv, uint32_t v, uint32_t labv, uint32_t x) {
   if (x == v) return kEmpty;
   if (!REF) return mv.lab[x];
-  const uint32_t lx = mv.lab[x], px = mv.par[x];   // two independent gathers
-  return lx == labv ? px : kEmpty;
+  const uint2 q = mv.lp[x];                        // label and parent in one gather
+  return q.x == labv ? q.y : kEmpty;
 }
 
 struct VInfo {
@@ -468,15 +468,33 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wavefront per vertex with a private LDS table of pow2 >= max(64, 2 T) slots (at most
-// SLOTS).  The wavefronts of a workgroup run independently: no workgroup barrier inside the
-// loop, candidates staged per wavefront.  A lane loads all of its entries (at most
-// SLOTS / 128), then all their labels, before inserting; slots are evaluated SB at a time.
+// Insert (key, w) into an LDS table that is empty between vertices.  Returns the slot when
+// this call created the key's entry (the calling lane then owns it), else kNoSlot.
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+__device__ __forceinline__ uint32_t table_insert_own(uint32_t* keys, u64a* vals, uint32_t mask, uint32_t key,
+                                                     int64_t w) {
+  uint32_t h = hash32(key) & mask;
+  for (;;) {
+    const uint32_t prev = atomicCAS(&keys[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd(&vals[h], (u64a)w);
+      return prev == kEmpty ? h : kNoSlot;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// One wavefront per vertex with a private LDS table of SLOTS slots (load factor <= 1/2), kept
+// empty between vertices: the lane that creates a key's slot owns it, evaluates that
+// community after the wavefront has inserted everything and empties the slot afterwards, so
+// no cycle is spent on empty slots.  A lane loads all of its entries (at most SLOTS / 128),
+// then all their keys, then inserts; the totals of all its owned communities are gathered
+// together.  The wavefronts of a workgroup run independently (no workgroup barrier inside the
+// loop); candidates are staged per wavefront.
 template <typename WT, int SLOTS, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int W = kTpb / kWave;
   constexpr int EPL = SLOTS / 2 / kWave;   // entries per lane, T <= SLOTS / 2
-  constexpr int SB = 4;
   constexpr uint32_t SCAP = 32;            // staged candidates per wavefront
   __shared__ uint32_t skey[W][SLOTS];
   __shared__ u64a sval[W][SLOTS];
@@ -507,6 +525,12 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     wave_sync();
     ns = 0;
   };
+  if ((uint64_t)blockIdx.x * W + wv < count) {
+    for (uint32_t s = lane; s < (uint32_t)SLOTS; s += kWave) {
+      keys[s] = kEmpty;
+      vals[s] = 0;
+    }
+  }
   for (uint64_t i = (uint64_t)blockIdx.x * W + wv; i < count; i += (uint64_t)gridDim.x * W) {
     const uint32_t v = list[i];
     const uint32_t dout = mv.out.deg[v];
@@ -514,12 +538,6 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
     const VInfo vi = vinfo<DIR, REF>(mv, v);
     const uint32_t T = dout + din;
-    uint32_t size = 64;
-    while (size < 2 * T && size < (uint32_t)SLOTS) size <<= 1;
-    for (uint32_t s = lane; s < size; s += kWave) {
-      keys[s] = kEmpty;
-      vals[s] = 0;
-    }
     uint32_t xs[EPL];
     int64_t ws[EPL];
 #pragma unroll
@@ -532,49 +550,51 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     uint32_t ks[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) ks[q] = entry_key<REF>(mv, v, vi.lab, xs[q]);
-    wave_sync();                              // table cleared
+    wave_sync();                              // the previous vertex's slots are empty
     int64_t own = 0;
+    uint32_t mine[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
       const uint32_t key = ks[q];
+      mine[q] = kNoSlot;
       if (key == kEmpty) continue;
       if (!REF && key == vi.lab) {
         own += ws[q];
         continue;
       }
-      table_insert(keys, vals, size - 1, key, ws[q]);
+      mine[q] = table_insert_own(keys, vals, (uint32_t)SLOTS - 1, key, ws[q]);
     }
-    wave_sync();
+    wave_sync();                              // every insert done
     own = wave_sum_i64(own);
+    int64_t av[EPL], Kb[EPL], Kib[EPL];
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      av[q] = 0; Kb[q] = 0; Kib[q] = 0;
+      if (mine[q] != kNoSlot) {
+        av[q] = (int64_t)vals[mine[q]];
+        Kb[q] = mv.Kout[ks[q]];
+        if (DIR) Kib[q] = mv.Kin[ks[q]];
+      }
+    }
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    for (uint32_t s0 = 0; s0 < size; s0 += SB * kWave) {
-      uint32_t kk[SB];
-      int64_t av[SB], Kb[SB], Kib[SB];
 #pragma unroll
-      for (int q = 0; q < SB; ++q) {
-        const uint32_t s = s0 + (uint32_t)lane + (uint32_t)q * kWave;
-        kk[q] = s < size ? keys[s] : kEmpty;
-        av[q] = s < size ? (int64_t)vals[s] : 0;
-      }
+    for (int q = 0; q < EPL; ++q) {
+      if (mine[q] == kNoSlot) continue;
+      ls.distinct += 1;
+      const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), ks[q]);
+      if (better(c, b)) b = c;
+    }
+    // each slot is read and emptied by its owner only; the barrier at the top of the next
+    // vertex orders the resets before any insert
 #pragma unroll
-      for (int q = 0; q < SB; ++q) {
-        Kb[q] = 0; Kib[q] = 0;
-        if (kk[q] != kEmpty) {
-          Kb[q] = mv.Kout[kk[q]];
-          if (DIR) Kib[q] = mv.Kin[kk[q]];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < SB; ++q) {
-        if (kk[q] == kEmpty) continue;
-        ls.distinct += 1;
-        const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), kk[q]);
-        if (better(c, b)) b = c;
+    for (int q = 0; q < EPL; ++q) {
+      if (mine[q] != kNoSlot) {
+        keys[mine[q]] = kEmpty;
+        vals[mine[q]] = 0;
       }
     }
     b = group_best(b, kWave);                 // every lane holds the wavefront's best
-    wave_sync();                              // table reads done before the next vertex clears it
     if (lane == 0) {
       ls.entries += T;
       ls.vertices += 1;
@@ -595,14 +615,14 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
   stats_flush(ls, st, red_s);
 }
 
-// TEAM lanes per vertex with a private LDS table of pow2 >= max(64, 2 T) slots (at most SLOTS).
-// A lane loads all of its entries (at most SLOTS / (2 TEAM)), then all their labels, before
-// inserting; table slots are evaluated SB at a time with their totals gathered together.
+// TEAM lanes per vertex with a private LDS table of SLOTS slots (load factor <= 1/2), empty
+// between vertices: as in k_best_wave, the lane that creates a key's slot evaluates that
+// community and empties the slot.  A lane loads all of its entries (at most SLOTS / (2 TEAM)),
+// then all their keys, then inserts; the totals of its owned communities are gathered together.
 template <typename WT, int TEAM, int SLOTS, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int TEAMS = kTpb / TEAM;
   constexpr int EPL = SLOTS / 2 / TEAM;    // entries per lane, T <= SLOTS / 2
-  constexpr int SB = 4;                    // slots per lane per evaluation step
   __shared__ uint32_t skey[TEAMS][SLOTS];
   __shared__ u64a sval[TEAMS][SLOTS];
   __shared__ int64_t red_i[kTpb / kWave];
@@ -615,6 +635,12 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
   const int t = threadIdx.x / TEAM;
   const int li = threadIdx.x % TEAM;
   LocalStats ls;
+  if ((uint64_t)blockIdx.x * TEAMS < count) {
+    for (uint32_t s = li; s < (uint32_t)SLOTS; s += TEAM) {
+      skey[t][s] = kEmpty;
+      sval[t][s] = 0;
+    }
+  }
   for (uint64_t base = (uint64_t)blockIdx.x * TEAMS; base < count; base += (uint64_t)gridDim.x * TEAMS) {
     const uint64_t slot = base + t;
     const bool active = slot < count;
@@ -630,13 +656,6 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
       vi = vinfo<DIR, REF>(mv, v);
     }
     const uint32_t T = dout + din;
-    // the team's table: pow2 >= 2T slots (at least 64), cleared and scanned, not all SLOTS
-    uint32_t size = 64;
-    while (size < 2 * T && size < (uint32_t)SLOTS) size <<= 1;
-    for (uint32_t s = li; s < size; s += TEAM) {
-      skey[t][s] = kEmpty;
-      sval[t][s] = 0;
-    }
     uint32_t xs[EPL];
     int64_t ws[EPL];
 #pragma unroll
@@ -649,50 +668,49 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
     uint32_t ks[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) ks[q] = active ? entry_key<REF>(mv, v, vi.lab, xs[q]) : kEmpty;
-    __syncthreads();                          // table cleared
+    __syncthreads();                          // the previous vertex's slots are empty
     int64_t own = 0;
+    uint32_t mine[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
       const uint32_t key = ks[q];
+      mine[q] = kNoSlot;
       if (key == kEmpty) continue;
       if (!REF && key == vi.lab) {
         own += ws[q];
         continue;
       }
-      table_insert(skey[t], sval[t], size - 1, key, ws[q]);
+      mine[q] = table_insert_own(skey[t], sval[t], (uint32_t)SLOTS - 1, key, ws[q]);
     }
-    __syncthreads();
+    __syncthreads();                          // every insert done
     own = team_sum<TEAM>(own, red_i);
-    Best b;
-    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    if (active) {
-      for (uint32_t s0 = 0; s0 < size; s0 += SB * TEAM) {
-        uint32_t kk[SB];
-        int64_t av[SB], Kb[SB], Kib[SB];
+    int64_t av[EPL], Kb[EPL], Kib[EPL];
 #pragma unroll
-        for (int q = 0; q < SB; ++q) {
-          const uint32_t s = s0 + (uint32_t)li + (uint32_t)q * TEAM;
-          kk[q] = s < size ? skey[t][s] : kEmpty;
-          av[q] = s < size ? (int64_t)sval[t][s] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < SB; ++q) {
-          Kb[q] = 0; Kib[q] = 0;
-          if (kk[q] != kEmpty) {
-            Kb[q] = mv.Kout[kk[q]];
-            if (DIR) Kib[q] = mv.Kin[kk[q]];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < SB; ++q) {
-          if (kk[q] == kEmpty) continue;
-          ls.distinct += 1;
-          const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), kk[q]);
-          if (better(c, b)) b = c;
-        }
+    for (int q = 0; q < EPL; ++q) {
+      av[q] = 0; Kb[q] = 0; Kib[q] = 0;
+      if (mine[q] != kNoSlot) {
+        av[q] = (int64_t)sval[t][mine[q]];
+        Kb[q] = mv.Kout[ks[q]];
+        if (DIR) Kib[q] = mv.Kin[ks[q]];
       }
     }
+    Best b;
+    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      if (mine[q] == kNoSlot) continue;
+      ls.distinct += 1;
+      const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), ks[q]);
+      if (better(c, b)) b = c;
+    }
     b = team_best<TEAM>(b, red_b);
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      if (mine[q] != kNoSlot) {
+        skey[t][mine[q]] = kEmpty;
+        sval[t][mine[q]] = 0;
+      }
+    }
     if (active && li == 0) {
       ls.entries += T;
       ls.vertices += 1;
@@ -908,21 +926,16 @@ int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, Hub
   const int rc = prim_exclusive_sum_u64x3(tmp, tmp_bytes, hw.cnt, hw.off, (uint64_t)bound + 1, s);
   if (rc) return rc;
   if (ev_a) (void)hipEventRecord(ev_a, s);
-  k_hub_insert<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.off, hub, hw.own, st);
+  k_hub_insert<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_insert<WT, DIR, REF>), kTpb)), kTpb,
+                               0, s>>>(mv, br, bound, hw.off, hub, hw.own, st);
   if (ev_b) (void)hipEventRecord(ev_b, s);
-  k_hub_scan<WT, DIR, REF><<<kPersistBlocks, kTpb, 0, s>>>(mv, br, bound, hw.off, hub, hw.own, hw.phi, hw.plo, hw.pid,
-                                                           hw.pvalid, st);
+  k_hub_scan<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_scan<WT, DIR, REF>), kTpb)), kTpb, 0,
+                             s>>>(mv, br, bound, hw.off, hub, hw.own, hw.phi, hw.plo, hw.pid, hw.pvalid, st);
   k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.off, hub.cap, mv.lab, hw.phi, hw.plo, hw.pid,
                                                       hw.pvalid, cand, st, hub.top, hub.over_count);
   return 0;
 }
 
-inline unsigned persist_grid(uint64_t items_per_block_units) {
-  uint64_t g = items_per_block_units;
-  if (g < 1) g = 1;
-  if (g > kPersistBlocks) g = kPersistBlocks;
-  return (unsigned)g;
-}
 
 template <typename WT, bool DIR, bool REF>
 void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, CandBuf cand, MoveStats st,
@@ -930,19 +943,29 @@ void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, C
   const uint64_t c = max_count;
   switch (bin) {
     case 0:
-      k_best_group<WT, 8, DIR, REF><<<persist_grid((c + 31) / 32), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_group<WT, 8, DIR, REF>
+          <<<cap_blocks((c + 31) / 32, LDL_RESIDENT((k_best_group<WT, 8, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
+                                                                                                      cand, st);
       break;
     case 1:
-      k_best_group<WT, 32, DIR, REF><<<persist_grid((c + 7) / 8), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_group<WT, 32, DIR, REF>
+          <<<cap_blocks((c + 7) / 8, LDL_RESIDENT((k_best_group<WT, 32, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
+                                                                                                      cand, st);
       break;
     case 2:
-      k_best_wave<WT, 256, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_wave<WT, 256, DIR, REF>
+          <<<cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 256, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
+                                                                                                      cand, st);
       break;
     case 3:
-      k_best_wave<WT, 1024, DIR, REF><<<persist_grid((c + 3) / 4), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_wave<WT, 1024, DIR, REF>
+          <<<cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 1024, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
+                                                                                                       cand, st);
       break;
     default:
-      k_best_hash<WT, 256, 4096, DIR, REF><<<persist_grid(c), kTpb, 0, s>>>(mv, br, cand, st);
+      k_best_hash<WT, 256, 4096, DIR, REF>
+          <<<cap_blocks(c, LDL_RESIDENT((k_best_hash<WT, 256, 4096, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br, cand,
+                                                                                                  st);
   }
 }
 
@@ -1145,7 +1168,7 @@ __global__ void k_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t*
 }
 
 // singleton u joins refined community y (forward) or returns to itself (undo)
-__global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* par,
+__global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* par, uint2* lp,
                              const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize,
                              int forward) {
   const uint32_t na = *nap;
@@ -1154,6 +1177,7 @@ __global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf c
     const uint32_t u = cand.v[i], y = cand.b[i];
     const int64_t sg = forward ? 1 : -1;
     par[u] = forward ? y : u;
+    lp[u].y = forward ? y : u;
     atomic_add_i64(&Krout[y], sg * kout[u]);
     atomic_add_i64(&Krout[u], -sg * kout[u]);
     if (Krin) {
@@ -1168,6 +1192,10 @@ __global__ void k_ref_commit(const uint32_t* acc, const uint32_t* nap, CandBuf c
       atomicAdd(&rsize[u], 1u);
     }
   }
+}
+
+__global__ void k_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* par, uint2* lp) {
+  for (uint64_t u = gtid(); u < n; u += gstride()) lp[u] = make_uint2(lab[u], par[u]);
 }
 
 }  // namespace
@@ -1269,11 +1297,14 @@ void launch_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t* na, u
   if (na_max) k_set_add_acc_v<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(set, acc, na, cand);
 }
 void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
-                       const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize,
-                       int forward, hipStream_t s) {
+                       uint2* lp, const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null,
+                       uint32_t* rsize, int forward, hipStream_t s) {
   if (na_max)
-    k_ref_commit<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, par, kout, kin, Krout, Krin_or_null, rsize,
-                                                             forward);
+    k_ref_commit<<<cap_grid(grid_for(na_max)), kTpb, 0, s>>>(acc, na, cand, par, lp, kout, kin, Krout, Krin_or_null,
+                                                             rsize, forward);
+}
+void launch_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* par, uint2* lp, hipStream_t s) {
+  if (n) k_pack_lab_par<<<grid_for(n), kTpb, 0, s>>>(n, lab, par, lp);
 }
 
 }  // namespace ldl

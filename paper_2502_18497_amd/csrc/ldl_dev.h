@@ -138,4 +138,33 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
+// ------------------------------------------------------------------ launch shapes (host)
+// Workgroups of `kernel` (launched with `threads` per workgroup) that are resident on the
+// current device at once.  Kernels whose work count is read on the device loop over it
+// grid-stride; a grid larger than this only adds workgroups that wait for a free slot and then
+// find nothing to do, which costs more than the work itself when the count is small.
+inline unsigned resident_blocks(const void* kernel, int threads) {
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) {
+    (void)hipGetLastError();
+    per_cu = 1;
+  }
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  return (unsigned)per_cu * (unsigned)cus;
+}
+// resident_blocks of one kernel, computed on its first launch (per template instantiation)
+#define LDL_RESIDENT(kern, threads)                                                     \
+  ([] {                                                                                 \
+    static const unsigned resident_ = ::ldl::resident_blocks((const void*)(kern), (threads)); \
+    return resident_;                                                                   \
+  }())
+inline unsigned cap_blocks(uint64_t want, unsigned resident) {
+  if (want < 1) want = 1;
+  return want < resident ? (unsigned)want : resident;
+}
+
 }  // namespace ldl

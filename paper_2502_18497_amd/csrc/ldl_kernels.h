@@ -34,6 +34,7 @@ struct MoveView {
   CsrRef out, in;            // in.off == nullptr for undirected graphs
   const uint32_t* lab;       // P^r
   const uint32_t* par;       // pi_r (refinement)
+  const uint2* lp;           // (P^r, pi_r) of every node packed in one word (refinement)
   const uint8_t* alive;
   const int64_t* kout;       // level-r degrees
   const int64_t* kin;
@@ -250,8 +251,10 @@ void launch_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* o
                       hipStream_t s);
 // forward: singletons join their targets; otherwise the same moves are undone
 void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
-                       const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize,
-                       int forward, hipStream_t s);
+                       uint2* lp, const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null,
+                       uint32_t* rsize, int forward, hipStream_t s);
+// lp[u] = (lab[u], par[u]) for u < n
+void launch_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* par, uint2* lp, hipStream_t s);
 // SPExpand over wavefront items of the movers (node i = movers[idx[i]], count on the device;
 // items from launch_items with the same list): plain-store marks into Rcur and Rset, oldpar of
 // new Rset members = themselves; the lists are built later by select
