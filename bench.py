@@ -232,6 +232,7 @@ def main():
     ap.add_argument("--small-steps", type=int, default=20)
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy"], default="rmat")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--graphs", type=int, default=64)
@@ -285,6 +286,13 @@ def main():
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     log(f"create (static Leiden) {create_s:.2f}s Q={g.modularity():.6f}")
+
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = g.autotune()
+        log(f"autotuned degree bins in {time.perf_counter() - t0:.2f}s: {tune['limits'].tolist()} "
+            f"cost {tune['ms_before']} -> {tune['ms_after']} ms")
 
     big = [to_dev(s.batch(args.batch)) for _ in range(args.warmup + args.steps)]
     small = [to_dev(s.batch(args.small_batch)) for _ in range(args.small_steps)]
@@ -386,6 +394,9 @@ def main():
                         "p50_ms": float(1e3 * np.percentile(per_s, 50)),
                         "p99_ms": float(1e3 * np.percentile(per_s, 99))} if small else None,
         "full_frontier_scan": full_frontier,
+        "degree_bins": {"limits": g.bins().tolist(), "autotuned": tune is not None,
+                        "tune_cost_ms_before": tune["ms_before"] if tune else None,
+                        "tune_cost_ms_after": tune["ms_after"] if tune else None},
         "create_s": create_s,
         "modularity": g.modularity(),
     }

@@ -219,6 +219,36 @@ int ldl_server_drain(ldl_server* s);
 /* Drain, stop the workers and free the server (handles stay valid). NULL is ignored. */
 void ldl_server_destroy(ldl_server* s);
 
+/*
+ * Degree bins of the candidate search (the per-vertex neighbour-community accumulation and argmax
+ * of Sec. III-D; the bins are an implementation choice, not part of the method).  A vertex with T
+ * adjacency entries (out + in) is evaluated by the kernel of the first bin b with T <= limit[b],
+ * or by the multi-workgroup hub path when T exceeds limit[4].  Bin b's kernel holds at most
+ * {8, 32, 128, 512, 2048}[b] entries, so a valid set has limit[b] <= that cap and
+ * limit[0] <= limit[1] <= ... <= limit[4]; equal neighbours leave a bin empty.  Row 0 applies to
+ * level 0 (32-bit weights), row 1 to the aggregate levels (64-bit weights).  Every valid set gives
+ * bit-identical results; only the speed differs.  Defaults: {8, 32, 128, 512, 2048} for both.
+ * ldl_set_bins returns LDL_EINVAL for an invalid set (limits unchanged).
+ */
+int ldl_get_bins(const ldl_handle* h, uint32_t limits[2][5]);
+int ldl_set_bins(ldl_handle* h, const uint32_t limits[2][5]);
+
+/*
+ * Autotuner of the degree bins: on the handle's current graph, times the move-phase candidate
+ * search over every alive node of level 0 (and of level 1 when it exists) plus a 1/64 stride
+ * sample of them (the small frontiers of batch updates), runs one round of coordinate descent over
+ * the five limits of each row and keeps the fastest set.  Read-only for the graph and partition.
+ * report (nullable) receives the chosen limits and the cost (full + sample, ms) before and after.
+ */
+typedef struct ldl_tune_report {
+  uint32_t limit[2][5];
+  double ms_before[2];
+  double ms_after[2];
+  uint32_t trials;
+} ldl_tune_report;
+
+int ldl_autotune(ldl_handle* h, ldl_tune_report* report);
+
 /* Human-readable name of an LDL_* code. */
 const char* ldl_strerror(int code);
 

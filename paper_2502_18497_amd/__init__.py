@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libldl.so")
 
 LDL_OK = 0
+LDL_EINVAL, LDL_EDUP, LDL_ENOEDGE, LDL_EOVERFLOW, LDL_ENOMEM, LDL_EDEVICE, LDL_EBROKEN = -1, -2, -3, -4, -5, -6, -7
 ERRORS = {0: "LDL_OK", -1: "LDL_EINVAL", -2: "LDL_EDUP", -3: "LDL_ENOEDGE", -4: "LDL_EOVERFLOW",
           -5: "LDL_ENOMEM", -6: "LDL_EDEVICE", -7: "LDL_EBROKEN"}
 
@@ -59,7 +60,16 @@ ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply
                "ldl_modularity", "ldl_modularity_exact", "ldl_destroy", "ldl_export_scalars", "ldl_export_totals",
                "ldl_export_level", "ldl_level_nnz", "ldl_export_entries", "ldl_set_trace", "ldl_trace_len",
                "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
-               "ldl_server_drain", "ldl_server_destroy", "ldl_strerror", "ldl_version")
+               "ldl_server_drain", "ldl_server_destroy", "ldl_get_bins", "ldl_set_bins", "ldl_autotune",
+               "ldl_strerror", "ldl_version")
+
+
+class ldl_tune_report(ctypes.Structure):
+    _fields_ = [("limit", (ctypes.c_uint32 * 5) * 2), ("ms_before", ctypes.c_double * 2),
+                ("ms_after", ctypes.c_double * 2), ("trials", ctypes.c_uint32)]
+
+
+BIN_CAPS = (8, 32, 128, 512, 2048)   # entries a bin's kernel holds (ldl_set_bins limits)
 
 
 class ldl_batch(ctypes.Structure):
@@ -116,6 +126,12 @@ def load_library():
     lib.ldl_trace_len.restype = u64
     lib.ldl_trace.argtypes = [vp, vp]
     lib.ldl_trace.restype = i32
+    lib.ldl_get_bins.argtypes = [vp, vp]
+    lib.ldl_get_bins.restype = i32
+    lib.ldl_set_bins.argtypes = [vp, vp]
+    lib.ldl_set_bins.restype = i32
+    lib.ldl_autotune.argtypes = [vp, P(ldl_tune_report)]
+    lib.ldl_autotune.restype = i32
     lib.ldl_strerror.argtypes = [i32]
     lib.ldl_strerror.restype = ctypes.c_char_p
     lib.ldl_version.argtypes = []
@@ -212,6 +228,30 @@ class Graph:
         if rc != LDL_OK and raise_on_error:
             raise LdlError(rc, "ldl_apply_batch_device")
         return (st.as_dict() if rc == LDL_OK else rc)
+
+    def bins(self) -> np.ndarray:
+        """Degree-bin limits, shape (2, 5): row 0 for level 0, row 1 for the aggregate levels."""
+        out = np.zeros((2, 5), dtype=np.uint32)
+        rc = self.lib.ldl_get_bins(self.h, out.ctypes.data)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_get_bins")
+        return out
+
+    def set_bins(self, limits, raise_on_error=True):
+        a = np.ascontiguousarray(np.asarray(limits, dtype=np.uint32).reshape(2, 5))
+        rc = self.lib.ldl_set_bins(self.h, a.ctypes.data)
+        if rc != LDL_OK and raise_on_error:
+            raise LdlError(rc, "ldl_set_bins")
+        return rc
+
+    def autotune(self) -> dict:
+        """Run the degree-bin autotuner on the current graph; returns its report."""
+        rep = ldl_tune_report()
+        rc = self.lib.ldl_autotune(self.h, ctypes.byref(rep))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_autotune")
+        return {"limits": np.array([[rep.limit[w][b] for b in range(5)] for w in range(2)], dtype=np.uint32),
+                "ms_before": list(rep.ms_before), "ms_after": list(rep.ms_after), "trials": rep.trials}
 
     def partition(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.uint32)

@@ -155,6 +155,7 @@ struct Engine {
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
   uint2* lpk = nullptr;   // (label, parent) of the level being refined, packed for one gather
+  uint32_t lim[2][kNumBins - 1];   // degree-bin limits for 32-bit (level 0) and 64-bit weights
   uint32_t *accE = nullptr, *accA = nullptr;
   LfFirst lfE{}, lfA{};
   uint32_t *lf_la = nullptr, *lf_lb = nullptr;
@@ -363,6 +364,8 @@ struct Engine {
     if (directed) launch_fill_i64(Kin, 0, n, st);
     oldlab = alloc<uint32_t>(n);
     lpk = alloc<uint2>(n);
+    for (int w = 0; w < 2; ++w)
+      for (int b = 0; b < kNumBins - 1; ++b) lim[w][b] = kBinLimit[b];
     oldpar = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
@@ -433,7 +436,7 @@ struct Engine {
   uint32_t hub_bound(int r) const {
     const Level& V = lv[r];
     const uint64_t ent = V.out.pool_cap + (directed ? V.in.pool_cap : 0);
-    const uint64_t b = ent / (kBinLimit[kNumBins - 2] + 1) + 1;
+    const uint64_t b = ent / ((uint64_t)lim[V.out.ref.wide][kNumBins - 2] + 1) + 1;
     return (uint32_t)std::min<uint64_t>(b, n);
   }
 
@@ -662,6 +665,7 @@ struct Engine {
     mv.qm = gq * m;
     mv.p = gp;
     mv.directed = directed;
+    for (int b = 0; b < kNumBins - 1; ++b) mv.lim[b] = lim[V.out.ref.wide][b];
     return mv;
   }
 
@@ -689,6 +693,7 @@ struct Engine {
     const uint32_t hb = hub_bound(r);
     for (int b = 0; b < kNumBins; ++b) {
       if (b == kNumBins - 1 && hb == 0) break;
+      if (b < kNumBins - 1 && mv.lim[b] == (b ? mv.lim[b - 1] : 0u)) continue;   // no entry count maps here
       MoveStats ms{&ds->ps.st_entries[b], &ds->ps.st_distinct[b], &ds->ps.st_vertices[b], &ds->ps.st_cands[b],
                    &ds->ps.maxhi};
       BinRef br{binbuf, &ds->bin_start[b], &ds->bins[b]};
@@ -1093,6 +1098,89 @@ struct Engine {
     return LDL_OK;
   }
 
+  // ------------------------------------------------------------------ degree-bin autotuner
+  // The bin limits decide which kernel evaluates a vertex, never what it computes, so any valid
+  // choice gives the same candidates.  The tuner times the move-phase candidate search over all
+  // alive nodes of a level and over a 1/64 stride sample of them (the small frontiers of batch
+  // updates), and runs one round of coordinate descent over the five limits.
+  static bool valid_limits(const uint32_t* l) {
+    for (int b = 0; b < kNumBins - 1; ++b)
+      if (l[b] > kBinCap[b] || (b && l[b] < l[b - 1])) return false;
+    return true;
+  }
+  // median time in ms of `reps` candidate searches (move mode) at level r over the list of set sid
+  double time_search(int r, int sid, int reps, hipEvent_t a, hipEvent_t b) {
+    std::vector<float> t;
+    for (int k = 0; k < reps; ++k) {
+      for (int attempt = 0;; ++attempt) {
+        hcheck(hipEventRecord(a, st));
+        best_launch(r, sid, 0);
+        hcheck(hipEventRecord(b, st));
+        sync_read();
+        uint32_t sc = 0, K = 0;
+        if (best_finish(r, sid, 0, pending.size(), sc, K)) break;
+        if (attempt > 2) throw NoMem{};
+      }
+      float ms = 0;
+      hcheck(hipEventElapsedTime(&ms, a, b));
+      t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+  }
+  void autotune(ldl_tune_report* rep) {
+    static const uint32_t opts[kNumBins - 1][4] = {{0, 4, 8, 8}, {16, 24, 32, 32}, {64, 96, 128, 128},
+                                                    {256, 384, 512, 512}, {1024, 2048, 2048, 2048}};
+    const int saved_profile = profile;
+    profile = 0;
+    hipEvent_t a = nullptr, b = nullptr;
+    hcheck(hipEventCreate(&a));
+    hcheck(hipEventCreate(&b));
+    ldl_tune_report out{};
+    for (int w = 0; w < 2; ++w) {
+      for (int k = 0; k < kNumBins - 1; ++k) out.limit[w][k] = lim[w][k];
+      const int r = w;   // level 0 holds the 32-bit weights, level 1 the 64-bit ones
+      if (r > top) continue;
+      begin(S_TMP);
+      launch_alive_list(n, lv[r].alive, ref(S_TMP), st);
+      sync_read();
+      const uint32_t na = count(S_TMP);
+      if (na == 0) continue;
+      launch_stride_sample(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], n, 64, sets[S_REV2].list,
+                           &ds->counts[sets[S_REV2].ci], st);
+      auto cost = [&]() { return time_search(r, S_TMP, 3, a, b) + time_search(r, S_REV2, 3, a, b); };
+      double best = cost();
+      out.ms_before[w] = best;
+      for (int k = 0; k < kNumBins - 1; ++k) {
+        const uint32_t keep = lim[w][k];
+        uint32_t best_v = keep;
+        for (int o = 0; o < 4; ++o) {
+          const uint32_t v = opts[k][o];
+          if (v == keep || (o && v == opts[k][o - 1])) continue;
+          lim[w][k] = v;
+          if (!valid_limits(lim[w])) continue;
+          const double c = cost();
+          out.trials++;
+          if (c < best) {
+            best = c;
+            best_v = v;
+          }
+        }
+        lim[w][k] = best_v;
+      }
+      out.ms_after[w] = best;
+      for (int k = 0; k < kNumBins - 1; ++k) out.limit[w][k] = lim[w][k];
+    }
+    begin(S_TMP);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    profile = saved_profile;
+    stats = ldl_batch_stats{};
+    pending.clear();
+    ev_used = 0;
+    if (rep) *rep = out;
+  }
+
   void finish_profile() {
     if (!profile) return;
     hcheck(hipStreamSynchronize(st));
@@ -1409,6 +1497,31 @@ int ldl_trace(const ldl_handle* h, int64_t* out) {
   if (!h || !out) return LDL_EINVAL;
   for (size_t i = 0; i < h->e->trace.size(); ++i) std::memcpy(out + 8 * i, h->e->trace[i].v, 64);
   return LDL_OK;
+}
+
+int ldl_get_bins(const ldl_handle* h, uint32_t limits[2][5]) {
+  if (!h || !limits) return LDL_EINVAL;
+  for (int w = 0; w < 2; ++w)
+    for (int b = 0; b < 5; ++b) limits[w][b] = h->e->lim[w][b];
+  return LDL_OK;
+}
+
+int ldl_set_bins(ldl_handle* h, const uint32_t limits[2][5]) {
+  if (!h || !limits) return LDL_EINVAL;
+  if (!ldl::Engine::valid_limits(limits[0]) || !ldl::Engine::valid_limits(limits[1])) return LDL_EINVAL;
+  for (int w = 0; w < 2; ++w)
+    for (int b = 0; b < 5; ++b) h->e->lim[w][b] = limits[w][b];
+  return LDL_OK;
+}
+
+int ldl_autotune(ldl_handle* h, ldl_tune_report* report) {
+  if (!h) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(h, [&]() -> int {
+    ldl::hcheck(hipSetDevice(h->e->device));
+    h->e->autotune(report);
+    return LDL_OK;
+  });
 }
 
 const char* ldl_strerror(int code) {

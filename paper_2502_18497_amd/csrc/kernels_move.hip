@@ -125,7 +125,7 @@ __device__ __forceinline__ int bin_of(const MoveView& mv, uint32_t v, int refine
   if (T == 0) return -1;
 #pragma unroll
   for (int b = 0; b < kNumBins - 1; ++b)
-    if (T <= kBinLimit[b]) return b;
+    if (T <= mv.lim[b]) return b;
   return kNumBins - 1;
 }
 
@@ -1198,6 +1198,15 @@ __global__ void k_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* 
   for (uint64_t u = gtid(); u < n; u += gstride()) lp[u] = make_uint2(lab[u], par[u]);
 }
 
+__global__ void k_stride_sample(const uint32_t* src, const uint32_t* countp, uint32_t bound, uint32_t stride,
+                                uint32_t* out, uint32_t* out_count) {
+  const uint32_t c0 = *countp;
+  const uint32_t c = c0 < bound ? c0 : bound;
+  const uint32_t k = (c + stride - 1) / stride;
+  if (gtid() == 0) *out_count = k;
+  for (uint64_t i = gtid(); i < k; i += gstride()) out[i] = src[i * (uint64_t)stride];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1305,6 +1314,11 @@ void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max,
 }
 void launch_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* par, uint2* lp, hipStream_t s) {
   if (n) k_pack_lab_par<<<grid_for(n), kTpb, 0, s>>>(n, lab, par, lp);
+}
+void launch_stride_sample(const uint32_t* src, const uint32_t* count, uint32_t bound, uint32_t stride, uint32_t* out,
+                          uint32_t* out_count, hipStream_t s) {
+  if (bound && stride) k_stride_sample<<<cap_grid(grid_for(bound)), kTpb, 0, s>>>(src, count, bound, stride, out,
+                                                                                   out_count);
 }
 
 }  // namespace ldl

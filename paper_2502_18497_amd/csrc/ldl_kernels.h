@@ -44,6 +44,7 @@ struct MoveView {
   int64_t qm;                // q * m
   int64_t p;                 // gamma numerator
   int directed;
+  uint32_t lim[5];           // degree-bin limits (entries per vertex), see kBinCap
 };
 
 struct CandBuf {
@@ -82,7 +83,11 @@ struct BinRef {
 
 constexpr int kNumBins = 6;
 constexpr uint32_t kHubScanSlots = 8192;   // table slots evaluated per hub scan workgroup
-// degree bins: total entries T in (0,8], (8,32], (32,128], (128,512], (512,2048], (2048, inf)
+// Degree bins: a vertex with T > 0 entries goes to the first bin b < kNumBins - 1 with
+// T <= lim[b], else to the hub path (bin kNumBins - 1).  Bin b's kernel accepts at most
+// kBinCap[b] entries, so 0 <= lim[0] <= ... <= lim[4] with lim[b] <= kBinCap[b]; the limits only
+// decide which kernel evaluates a vertex, never the result.  kBinLimit are the defaults.
+constexpr uint32_t kBinCap[kNumBins - 1] = {8, 32, 128, 512, 2048};
 constexpr uint32_t kBinLimit[kNumBins - 1] = {8, 32, 128, 512, 2048};
 // statistics category of a candidate kernel: 2 kNumBins refine + kNumBins wide + bin
 constexpr int kNumCats = 4 * kNumBins;
@@ -255,6 +260,9 @@ void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max,
                        uint32_t* rsize, int forward, hipStream_t s);
 // lp[u] = (lab[u], par[u]) for u < n
 void launch_pack_lab_par(uint32_t n, const uint32_t* lab, const uint32_t* par, uint2* lp, hipStream_t s);
+// out = src[0], src[stride], ... below *count (count on the device, at most bound); *out_count set
+void launch_stride_sample(const uint32_t* src, const uint32_t* count, uint32_t bound, uint32_t stride, uint32_t* out,
+                          uint32_t* out_count, hipStream_t s);
 // SPExpand over wavefront items of the movers (node i = movers[idx[i]], count on the device;
 // items from launch_items with the same list): plain-store marks into Rcur and Rset, oldpar of
 // new Rset members = themselves; the lists are built later by select

@@ -18,14 +18,21 @@ def first_trace_divergence(tg: np.ndarray, to: np.ndarray):
 
 
 def run_parity(n, edges, batches, directed=False, full_state=True, check_invariants=True, gpu_flags=0,
-               stats_out=None, **cfg):
+               stats_out=None, bins=None, **cfg):
     """Create both sides, apply the same batches and compare after every step.  Returns the
-    GPU graph and the oracle for further checks.  gpu_flags go to the GPU side only (they
-    select internal paths, not results); per-batch GPU statistics are appended to stats_out."""
+    GPU graph and the oracle for further checks.  gpu_flags and bins go to the GPU side only
+    (they select internal paths, not results); with bins the GPU graph is created empty, given
+    those degree-bin limits, and receives the initial edges as its first batch (static Leiden
+    either way).  Per-batch GPU statistics are appended to stats_out."""
     import paper_2502_18497_amd as ldl
 
     og = oracle.Oracle(n, edges, directed=directed, flags=oracle.FLAG_TRACE, **cfg)
-    g = ldl.Graph(n, edges, directed=directed, test_flags=gpu_flags, **cfg)
+    if bins is None:
+        g = ldl.Graph(n, edges, directed=directed, test_flags=gpu_flags, **cfg)
+    else:
+        g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=directed, test_flags=gpu_flags, **cfg)
+        g.set_bins(bins)
+        g.apply_batch(ins=edges)
     g.set_trace(True)
     # the trace is enabled after creation on the GPU side: compare creation by state only
     step = "create"
