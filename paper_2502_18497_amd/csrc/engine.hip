@@ -155,6 +155,14 @@ struct Engine {
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
   uint2* lpk = nullptr;   // (label, parent) of the level being refined, packed for one gather
+  // Deferred aggregate records per level (entry deltas not yet applied to that level's CSR; the
+  // level's degrees already include them).  See defer() and flush_to().
+  struct PendBuf {
+    uint64_t* keys = nullptr;
+    int64_t* vals = nullptr;
+    uint64_t count = 0, cap = 0;
+  };
+  std::vector<PendBuf> pend;
   uint32_t lim[2][kNumBins - 1];   // degree-bin limits for 32-bit (level 0) and 64-bit weights
   uint32_t *accE = nullptr, *accA = nullptr;
   LfFirst lfE{}, lfA{};
@@ -337,6 +345,7 @@ struct Engine {
       if (sets[i].stamp) begin(i);   // epoch 1: stamps start at 0, so every set starts empty
     hcheck(hipMemsetAsync(ds->counts, 0, sizeof(ds->counts), st));
     lv.resize(L + 1);
+    pend.resize(L + 1);
     for (int r = 0; r <= L; ++r) {
       Level& V = lv[r];
       V.alive = alloc<uint8_t>(n);
@@ -576,6 +585,64 @@ struct Engine {
     return hs->nruns;
   }
 
+  // ------------------------------------------------------------------ deferred aggregate records
+  // Entry deltas for an aggregate level s >= 1 (from the batch's level-0 changes and from the
+  // subtract-add tuples of aggregate repair) are appended to pend[s] and applied to the CSR of
+  // level s in one sort, reduce and row update right before level s is processed (and for every
+  // level before the call returns); the reduced deltas then cascade to level s+1 through pi_s
+  // the same way.  Integer sums commute, so the CSRs are exactly those of applying every delta at
+  // once.  Nothing reads the CSR of level s before that point, and pi_s does not change before it
+  // (only refinement of level s changes pi_s).  The degrees of level s, which refinement of level
+  // s-1 reads as refined-community totals, are updated when a delta is deferred.
+  void pend_reserve(int s, uint64_t extra) {
+    PendBuf& p = pend[s];
+    if (p.count + extra <= p.cap) return;
+    const uint64_t c = std::max<uint64_t>(p.count + extra, p.cap + p.cap / 2);
+    uint64_t* nk = alloc<uint64_t>(c);
+    int64_t* nv = alloc<int64_t>(c);
+    if (p.count) {
+      hcheck(hipMemcpyAsync(nk, p.keys, 8 * p.count, hipMemcpyDeviceToDevice, st));
+      hcheck(hipMemcpyAsync(nv, p.vals, 8 * p.count, hipMemcpyDeviceToDevice, st));
+    }
+    hcheck(hipStreamSynchronize(st));
+    release(p.keys);
+    release(p.vals);
+    p.keys = nk;
+    p.vals = nv;
+    p.cap = c;
+  }
+  void defer(int s, const uint64_t* keys, const int64_t* vals, uint64_t k, bool degrees) {
+    if (k == 0) return;
+    if (degrees) launch_record_degrees(keys, vals, k, lv[s].kout, directed ? lv[s].kin : nullptr, id_bits, st);
+    pend_reserve(s, k);
+    PendBuf& p = pend[s];
+    hcheck(hipMemcpyAsync(p.keys + p.count, keys, 8 * k, hipMemcpyDeviceToDevice, st));
+    hcheck(hipMemcpyAsync(p.vals + p.count, vals, 8 * k, hipMemcpyDeviceToDevice, st));
+    p.count += k;
+  }
+  // apply the deferred records of levels 1..s (in order: each cascades into the next)
+  void flush_to(int s) {
+    for (int t = 1; t <= s && t <= top; ++t) {
+      PendBuf& p = pend[t];
+      const uint64_t k = p.count;
+      if (!k) continue;
+      p.count = 0;
+      ensure_tuples(k + 16);
+      const uint64_t R = sort_reduce(p.keys, p.vals, k, tk2, tv2);
+      stats.agg_records += R;
+      if (R == 0) continue;
+      hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
+      hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
+      apply_records(t, tk0, tv0, R, false);   // degrees were updated when deferred
+      if (t + 1 <= top) {
+        launch_split_keys(tk0, R, tx, ty, id_bits, st);
+        SetRef none{};
+        launch_cascade_map(tx, ty, tv0, R, lv[t].par, tk2, tv2, none, id_bits, st);
+        defer(t + 1, tk2, tv2, R, true);
+      }
+    }
+  }
+
   // ------------------------------------------------------------------ batch ingest
   // Returns LDL_OK or a validation error (state untouched).
   int ingest(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg,
@@ -627,16 +694,13 @@ struct Engine {
     m += dm;
     Ein += hs->dein;
     SKK += ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
-    // cascade the entry deltas through pi to every existing level; ancestors are seeds
+    // the entry deltas go to level 1 (deferred; they reach higher levels when level 1 is
+    // flushed); their ancestors at every existing level are seeds
     if (top >= 1) {
       launch_split_keys(ekey1, E, ex, ey, id_bits, st);
       for (int s = 1; s <= top; ++s) {
         launch_cascade_map(ex, ey, edel1, E, lv[s - 1].par, tk0, tv0, ref(S_D0 + s), id_bits, st);
-        const uint64_t R = sort_reduce(tk0, tv0, E, tk2, tv2);
-        // tk2/tv2 are reused inside apply_records for directed graphs: keep a copy
-        hcheck(hipMemcpyAsync(ekey0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
-        hcheck(hipMemcpyAsync(edel0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
-        apply_records(s, ekey0, edel0, R, true);
+        if (s == 1) defer(1, tk0, tv0, E, true);
       }
     }
     return LDL_OK;
@@ -864,6 +928,7 @@ struct Engine {
   void process_level(int r) {
     Level& V = lv[r];
     stats.levels_processed++;
+    flush_to(r);   // level r's CSR receives its deferred records (and passes them upwards)
     sync_read();
     const uint32_t E0 = count(S_D0 + r);
     hcheck(hipMemcpyAsync(entry, sets[S_D0 + r].list, 4ull * E0, hipMemcpyDeviceToDevice, st));
@@ -989,10 +1054,14 @@ struct Engine {
     CsrRef in = directed ? V.in.ref : V.out.ref;
     const int Dn = S_D0 + r + 1;
     const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, sets[S_C].stamp, sets[S_C].epoch, 1);
+    // the tuples are written straight into the deferred records of level r+1
+    pend_reserve(r + 1, T);
+    PendBuf& pn = pend[r + 1];
     if (nC)
       launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, oldpar,
-                        sets[S_C].stamp, sets[S_C].epoch, 1, toffs, (u64a*)tcur, tk0, tv0, sets[Dn].stamp,
-                        sets[Dn].epoch, id_bits, st);
+                        sets[S_C].stamp, sets[S_C].epoch, 1, toffs, (u64a*)tcur, pn.keys + pn.count,
+                        pn.vals + pn.count, sets[Dn].stamp, sets[Dn].epoch, id_bits, st);
+    pn.count += T;
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
@@ -1024,26 +1093,9 @@ struct Engine {
       std::swap(died, died2);
       std::swap(rev, rev2);
     }
-    // subtract-add tuples: reduce, apply at r+1 (degrees already exact), cascade upwards
+    // the subtract-add tuples wait in pend[r+1] (level r+1's degrees are already exact: the
+    // refinement commits maintain them as refined-community totals)
     stats.agg_tuples += T;
-    uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
-    stats.agg_records += R;
-    if (R == 0) return;
-    hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
-    hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
-    apply_records(r + 1, tk0, tv0, R, false);
-    for (int s = r + 2; s <= top; ++s) {
-      launch_split_keys(tk0, R, tx, ty, id_bits, st);
-      SetRef none{};
-      launch_cascade_map(tx, ty, tv0, R, lv[s - 1].par, tk2, tv2, none, id_bits, st);
-      // tk2/tv2 hold the mapped records; reduce them into tk0/tv0
-      cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, tk2, tk1, tv2, tv1, R, 0, 2 * id_bits, st));
-      cub(prim_reduce_by_key(&cub_tmp, &cub_bytes, tk1, tk0, tv1, tv0, &ds->nruns, R, st));
-      sync_read();
-      R = hs->nruns;
-      if (R == 0) return;
-      apply_records(s, tk0, tv0, R, true);
-    }
   }
 
   // first visit of level r+1: Eq. 3 from scratch
@@ -1093,6 +1145,7 @@ struct Engine {
       if (!any || all_empty) break;
       if ((i128)ad * (qnum() - Qp) < (i128)an * Qp) break;  // Alg. 1 l.27
     }
+    flush_to(top);
     for (int r = 0; r <= L; ++r) begin(S_D0 + r);
     hcheck(hipStreamSynchronize(st));
     return LDL_OK;

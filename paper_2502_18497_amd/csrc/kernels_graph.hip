@@ -586,6 +586,59 @@ __global__ void k_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uin
   }
 }
 
+// Degree deltas of records (row, col, d): out-degree of the row, and in-degree of the column
+// when a separate in-degree array is given (directed graphs).  Deferred aggregate records often
+// concentrate on a few rows (large communities), so each workgroup first sums its chunk per
+// node in an LDS table and issues one global atomic per distinct node; a key that finds no free
+// slot within kDegProbe probes goes straight to the global atomic.
+constexpr uint32_t kDegSlots = 4096;
+constexpr uint32_t kDegChunk = 8192;
+constexpr int kDegProbe = 32;
+
+__device__ __forceinline__ void deg_local_add(uint32_t* tk, u64a* tv, uint32_t key, int64_t d, int64_t* glob) {
+  uint32_t h = hash32(key) & (kDegSlots - 1);
+  for (int p = 0; p < kDegProbe; ++p) {
+    const uint32_t prev = atomicCAS(&tk[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd(&tv[h], (u64a)d);
+      return;
+    }
+    h = (h + 1) & (kDegSlots - 1);
+  }
+  atomic_add_i64(&glob[key], d);
+}
+
+__global__ __launch_bounds__(kTpb) void k_record_degrees(const uint64_t* keys, const int64_t* vals, uint64_t k,
+                                                         int64_t* kout, int64_t* kin, int ks) {
+  __shared__ uint32_t rk[kDegSlots];
+  __shared__ u64a rv[kDegSlots];
+  __shared__ uint32_t ck[kDegSlots];
+  __shared__ u64a cv[kDegSlots];
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kDegChunk; c0 < k; c0 += (uint64_t)gridDim.x * kDegChunk) {
+    for (uint32_t t = threadIdx.x; t < kDegSlots; t += blockDim.x) {
+      rk[t] = kEmpty;
+      rv[t] = 0;
+      if (kin) {
+        ck[t] = kEmpty;
+        cv[t] = 0;
+      }
+    }
+    __syncthreads();
+    const uint64_t c1 = c0 + kDegChunk < k ? c0 + kDegChunk : k;
+    for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+      const int64_t d = vals[i];
+      if (d == 0) continue;
+      deg_local_add(rk, rv, krow(keys[i], ks), d, kout);
+      if (kin) deg_local_add(ck, cv, kcol(keys[i], ks), d, kin);
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < kDegSlots; t += blockDim.x) {
+      if (rk[t] != kEmpty && rv[t]) atomic_add_i64(&kout[rk[t]], (int64_t)rv[t]);
+      if (kin && ck[t] != kEmpty && cv[t]) atomic_add_i64(&kin[ck[t]], (int64_t)cv[t]);
+    }
+    __syncthreads();
+  }
+}
 __global__ void k_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     ex[i] = krow(keys[i], ks);
@@ -1077,6 +1130,12 @@ void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, c
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
                         uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s) {
   if (k) k_cascade_map<<<grid_for(k), kTpb, 0, s>>>(ex, ey, ed, k, par, keys, vals, seeds, ks);
+}
+void launch_record_degrees(const uint64_t* keys, const int64_t* vals, uint64_t k, int64_t* kout, int64_t* kin_or_null,
+                           int ks, hipStream_t s) {
+  if (k)
+    k_record_degrees<<<cap_blocks((k + kDegChunk - 1) / kDegChunk, LDL_RESIDENT(k_record_degrees, kTpb)), kTpb, 0,
+                       s>>>(keys, vals, k, kout, kin_or_null, ks);
 }
 void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks, hipStream_t s) {
   if (k) k_split_keys<<<grid_for(k), kTpb, 0, s>>>(keys, k, ex, ey, ks);
