@@ -68,7 +68,9 @@ typedef struct ldl_pair {
  *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
  *                       results unchanged: 1 = one decoupling round between host checks (second
  *                       commit phase), 2 = minimal hub hash-table pool (overflow and redo of an
- *                       iteration), 4 = no spare adjacency capacity (row moves, pool growth)
+ *                       iteration), 4 = no spare adjacency capacity (row moves, pool growth),
+ *                       8 = always queue the one-workgroup decoupling filter first (iterations
+ *                       with more candidates than it holds run the filter after the host check)
  */
 typedef struct ldl_config {
   int32_t directed;

@@ -375,6 +375,7 @@ struct Engine {
     lpk = alloc<uint2>(n);
     for (int w = 0; w < 2; ++w)
       for (int b = 0; b < kNumBins - 1; ++b) lim[w][b] = kBinLimit[b];
+    std::memset(lf_lastK, 0xFF, sizeof(lf_lastK));
     oldpar = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
@@ -822,6 +823,16 @@ struct Engine {
   // accepted candidate indices are appended to `acc`, their count in ds->nacc
   static constexpr int kLfRounds = 4;   // rounds launched before the host looks
   int lf_rounds() const { return (test_flags & 1) ? 1 : kLfRounds; }
+  // Which filter to queue before the candidate count is known: the rounds for the first
+  // iteration of a level's move or refinement phase, else the one-workgroup filter unless the
+  // previous iteration had far more candidates than it holds (candidate counts fall fast after
+  // the first iteration).  A wrong guess costs one more synchronisation, never a different result.
+  uint32_t lf_lastK[17][2];
+  bool lf_small_predicted(int r, int refine) const {
+    if (test_flags & 1) return false;
+    if (test_flags & 8) return true;
+    return lf_lastK[r][refine] <= 16 * kLfSmall;
+  }
   void decouple_start() {
     if (++acc_epoch == 0) {
       launch_fill_u32(accE, 0, n, st);
@@ -845,8 +856,9 @@ struct Engine {
   }
   // after a synchronisation: finish the filter when candidates are still live; returns the
   // index where the newly accepted candidates start (the total is then in hs->nacc)
-  uint32_t decouple_finish() {
-    const uint32_t na1 = hs->nacc;
+  // `committed` false: none of the accepted moves has been committed yet (returns 0)
+  uint32_t decouple_finish(bool committed = true) {
+    const uint32_t na1 = committed ? hs->nacc : 0;
     uint32_t known = hs->nlive[lf_ca];
     while (known) {
       decouple_rounds(lf_rounds());
@@ -898,19 +910,33 @@ struct Engine {
       else if (forward) commit_launch(r, accp, nap);
       else launch_commit_apply(accp, nap, n, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
     };
+    bool small = false;
     for (int attempt = 0;; ++attempt) {
       const size_t fp = pending.size();
       best_launch(r, sid, refine);
-      decouple_start();
+      small = lf_small_predicted(r, refine);
+      if (small) {
+        launch_lf_small(cand, acc, &ds->nacc, &ds->nlive[0], st);
+        lf_ca = 0;
+        stats.lf_rounds++;
+      } else {
+        decouple_start();
+      }
       commit(acc, &ds->nacc, 1);
       sync_read();
       if (best_finish(r, sid, refine, fp, scanned, K)) break;
       commit(acc, &ds->nacc, 0);   // undo: the candidate set was incomplete
       if (attempt > 2) throw NoMem{};
     }
+    lf_lastK[r][refine] = K;
     dein = refine ? 0 : hs->ps.cdein;
     dskk = refine ? 0 : read_dskk();
-    const uint32_t na1 = decouple_finish();
+    const bool missed = small && K > kLfSmall;   // the filter has not run, nothing is committed
+    if (missed) {
+      decouple_start();
+      sync_read();
+    }
+    const uint32_t na1 = decouple_finish(!missed);
     na = hs->nacc;
     if (na > na1) {
       hcheck(hipMemsetD32Async((hipDeviceptr_t)&ds->nacc2, (int)(na - na1), 1, st));
@@ -942,6 +968,7 @@ struct Engine {
     select_set(S_U);
     const i128 Q0 = qnum();
     begin(S_MOVED);
+    lf_lastK[r][0] = lf_lastK[r][1] = ~0u;   // the first iteration of each phase queues the rounds
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.move_iters++;

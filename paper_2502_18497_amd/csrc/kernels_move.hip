@@ -1070,6 +1070,125 @@ __global__ void k_lf_reject(const uint32_t* live, const uint32_t* nlp, uint32_t 
   }
 }
 
+// ---- the same filter in one workgroup for at most kLfSmall candidates.  The candidates are
+// ranked by a bitonic sort in LDS on (gain descending, vertex ascending); their source and target
+// communities get LDS slots from a hash table (at most 2 kLfSmall communities in kLfSlots slots);
+// then the rounds run on ranks: per community the first live candidate leaving it and the first
+// entering it by an LDS atomic min, acceptance of every live candidate that precedes both firsts
+// that concern it, and removal of the live candidates that conflict with an accepted one, with
+// workgroup barriers between the steps, until no candidate is live.  Each round accepts at least
+// the first live candidate.
+constexpr uint32_t kLfSlots = 4096;
+
+__device__ __forceinline__ bool lf_precedes(int64_t h1, uint64_t l1, uint32_t v1, int64_t h2, uint64_t l2,
+                                            uint32_t v2) {
+  if (h1 != h2) return h1 > h2;
+  if (l1 != l2) return l1 > l2;
+  return v1 < v2;
+}
+
+__device__ __forceinline__ uint32_t lf_slot(uint32_t* keys, uint32_t c) {
+  uint32_t h = hash32(c) & (kLfSlots - 1);
+  for (;;) {   // at most 2 kLfSmall keys in kLfSlots >= 4 kLfSmall slots: a free slot exists
+    const uint32_t prev = atomicCAS(&keys[h], kEmpty, c);
+    if (prev == kEmpty || prev == c) return h;
+    h = (h + 1) & (kLfSlots - 1);
+  }
+}
+
+__global__ __launch_bounds__(kLfSmall) void k_lf_small(CandBuf cand, uint32_t* acc, uint32_t* nacc, uint32_t* nlive) {
+  static_assert(kLfSlots >= 4 * kLfSmall, "load factor of the community table");
+  __shared__ int64_t shi[kLfSmall];
+  __shared__ uint64_t slo[kLfSmall];
+  __shared__ uint32_t sv[kLfSmall];
+  __shared__ uint16_t sid[kLfSmall];
+  __shared__ uint32_t rank[kLfSmall];
+  __shared__ uint32_t ckey[kLfSlots], emin[kLfSlots], amin[kLfSlots];
+  __shared__ uint8_t accE[kLfSlots], accA[kLfSlots];
+  __shared__ uint32_t s_nacc;
+  const uint32_t K = *cand.count;
+  const uint32_t t = threadIdx.x;
+  if (K > kLfSmall) {
+    if (t == 0) {
+      *nacc = 0;
+      *nlive = 0;
+    }
+    return;
+  }
+  // padding has gain 0 and sorts after every candidate (candidate gains are positive)
+  if (t < K) {
+    shi[t] = cand.ghi[t];
+    slo[t] = cand.glo[t];
+    sv[t] = cand.v[t];
+  } else {
+    shi[t] = 0;
+    slo[t] = 0;
+    sv[t] = kEmpty;
+  }
+  sid[t] = (uint16_t)t;
+  for (uint32_t q = t; q < kLfSlots; q += blockDim.x) {
+    ckey[q] = kEmpty;
+    emin[q] = kEmpty;
+    amin[q] = kEmpty;
+    accE[q] = 0;
+    accA[q] = 0;
+  }
+  if (t == 0) s_nacc = 0;
+  __syncthreads();
+  for (uint32_t k = 2; k <= kLfSmall; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t p = t ^ j;
+      if (p > t) {
+        const bool first_is_t = (t & k) == 0;   // this pair is ordered t before p
+        const bool sw = first_is_t ? lf_precedes(shi[p], slo[p], sv[p], shi[t], slo[t], sv[t])
+                                   : lf_precedes(shi[t], slo[t], sv[t], shi[p], slo[p], sv[p]);
+        if (sw) {
+          const int64_t h = shi[t]; shi[t] = shi[p]; shi[p] = h;
+          const uint64_t l = slo[t]; slo[t] = slo[p]; slo[p] = l;
+          const uint32_t v = sv[t]; sv[t] = sv[p]; sv[p] = v;
+          const uint16_t d = sid[t]; sid[t] = sid[p]; sid[p] = d;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  rank[sid[t]] = t;   // position t of the order holds candidate sid[t]
+  __syncthreads();
+  bool live = t < K;
+  uint32_t sa = 0, sb = 0, rk = 0;
+  if (live) {
+    sa = lf_slot(ckey, cand.a[t]);
+    sb = lf_slot(ckey, cand.b[t]);
+    rk = rank[t];
+  }
+  __syncthreads();
+  for (;;) {
+    if (live) {
+      atomicMin(&emin[sa], rk);   // first live candidate leaving the community
+      atomicMin(&amin[sb], rk);   // first live candidate entering it
+    }
+    __syncthreads();
+    const bool ok = live && rk < amin[sa] && rk < emin[sb];
+    __syncthreads();
+    if (ok) {
+      accE[sa] = 1;
+      accA[sb] = 1;
+      acc[atomicAdd(&s_nacc, 1u)] = t;
+    }
+    __syncthreads();
+    if (live) {
+      emin[sa] = kEmpty;
+      amin[sb] = kEmpty;
+    }
+    live = live && !ok && !(accA[sa] || accE[sb]);
+    if (!__syncthreads_or(live)) break;
+  }
+  if (t == 0) {
+    *nacc = s_nacc;
+    *nlive = 0;
+  }
+}
+
 // ------------------------------------------------------------------ commit / rollback
 __global__ void k_commit_mark(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* mov_stamp,
                               uint32_t mov_ep, uint32_t* oldlab, const int64_t* Kout, const int64_t* Kin,
@@ -1262,6 +1381,9 @@ int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPoo
 void launch_lf_init(const uint32_t* K, uint32_t bound, uint32_t* live, uint8_t* flag, uint32_t* nlive, uint32_t* nacc,
                     hipStream_t s) {
   k_lf_init<<<kLfBlocks, kTpb, 0, s>>>(K, bound, live, flag, nlive, nacc);
+}
+void launch_lf_small(CandBuf cand, uint32_t* acc, uint32_t* nacc, uint32_t* nlive, hipStream_t s) {
+  k_lf_small<<<1, kLfSmall, 0, s>>>(cand, acc, nacc, nlive);
 }
 void launch_lf_round(const uint32_t* live, const uint32_t* nl, uint32_t bound, CandBuf cand, LfFirst E, LfFirst A,
                      uint32_t* accE, uint32_t* accA, uint32_t ep, uint8_t* flag, uint32_t* acc_list,

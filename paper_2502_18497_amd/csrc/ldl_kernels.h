@@ -226,6 +226,11 @@ struct LfFirst {
   uint32_t* v;
 };
 constexpr unsigned kLfBlocks = 1024;
+// The whole filter in one workgroup when there are at most kLfSmall candidates (count read on the
+// device): accepted candidate indices in acc[0..*nacc), *nlive = 0.  With more candidates it does
+// nothing but set *nacc = *nlive = 0 (the caller then runs the rounds below).
+constexpr uint32_t kLfSmall = 1024;
+void launch_lf_small(CandBuf cand, uint32_t* acc, uint32_t* nacc, uint32_t* nlive, hipStream_t s);
 // live = 0..K-1 with K read on the device (at most bound), flags cleared, *nlive = K, *nacc = 0
 void launch_lf_init(const uint32_t* K, uint32_t bound, uint32_t* live, uint8_t* flag, uint32_t* nlive, uint32_t* nacc,
                     hipStream_t s);

@@ -4,6 +4,8 @@ every result bit-identical to the oracle:
      pass, so the filter is finished and its moves committed as a second phase
   2  minimal hub hash-table pool: hub tables overflow, the iteration is undone and redone
   4  no spare adjacency capacity: every insertion moves its row, pools grow under load
+  8  the one-workgroup decoupling filter is always queued first: iterations with more candidates
+     than it holds run the rounds after the host check and commit everything as a second phase
 """
 import numpy as np
 import pytest
@@ -13,14 +15,15 @@ from tests.gpucases import run_parity
 
 pytestmark = pytest.mark.gpu
 
-ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR = 1, 2, 4
+ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST = 1, 2, 4, 8
 
 
 def _batches(stream, sizes):
     return [stream.batch(s) for s in sizes]
 
 
-@pytest.mark.parametrize("flags", [ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR])
+@pytest.mark.parametrize("flags", [ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST,
+                                   ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR, SMALL_FILTER_FIRST | SMALL_HUB_POOL])
 def test_rmat_undirected_rare_paths(flags):
     s = synth.rmat_undirected(scale=11, seed_offset=400)
     stats = []
@@ -30,7 +33,7 @@ def test_rmat_undirected_rare_paths(flags):
         assert any(st["lf_rounds"] > st["move_iters"] + st["refine_iters"] for st in stats), stats
 
 
-@pytest.mark.parametrize("flags", [ONE_ROUND | TIGHT_CSR, SMALL_HUB_POOL])
+@pytest.mark.parametrize("flags", [ONE_ROUND | TIGHT_CSR, SMALL_HUB_POOL, SMALL_FILTER_FIRST])
 def test_directed_rare_paths(flags):
     s = synth.rmat_directed_lognormal(1 << 11, 12 * (1 << 11), seed_offset=410)
     run_parity(s.n, s.edges(), _batches(s, [400, 40, 400]), directed=True, gpu_flags=flags)
