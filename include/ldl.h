@@ -114,6 +114,9 @@ typedef struct ldl_batch_stats {
   uint64_t lf_rounds;         /* decoupling rounds launched                               */
   uint64_t host_syncs;        /* stream synchronisations (host reads of device counters)  */
   uint64_t agg_records;       /* reduced records applied to levels above 0                */
+  double search_ms;           /* summed time of whole candidate searches: binning, every bin's
+                                 kernel and the hub path's table scan and final reduction
+                                 (HIP events, profile != 0)                                  */
 } ldl_batch_stats;
 
 /* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */

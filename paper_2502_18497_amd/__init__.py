@@ -45,7 +45,8 @@ class ldl_batch_stats(ctypes.Structure):
         [(k, ctypes.c_double) for k in ("bm_ms", "bm_bytes", "total_ms")] + \
         [("bin_launches", ctypes.c_uint64 * NUM_CATS), ("bin_ms", ctypes.c_double * NUM_CATS),
          ("bin_bytes", ctypes.c_double * NUM_CATS), ("bin_entries", ctypes.c_uint64 * NUM_CATS)] + \
-        [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")]
+        [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")] + \
+        [("search_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {}

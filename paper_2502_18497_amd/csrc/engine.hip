@@ -753,6 +753,11 @@ struct Engine {
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
     const int cat0 = 2 * kNumBins * refine + kNumBins * lv[r].out.ref.wide;
+    std::pair<hipEvent_t, hipEvent_t> whole{};
+    if (profile) {
+      whole = next_events();
+      hcheck(hipEventRecord(whole.first, st));
+    }
     launch_bin_count(mv, list, cnt, refine, bhist, (uint32_t*)&ds->ps, sizeof(PassScal) / 4, st);
     launch_bin_fill(mv, list, cnt, refine, bhist, binbuf, ds->bin_start, ds->bins, st);
     const uint32_t hb = hub_bound(r);
@@ -774,6 +779,10 @@ struct Engine {
                        profile ? ev.second : nullptr));
       }
       if (profile) pending.push_back(Pending{cat0 + b, ev.first, ev.second, 0.0});
+    }
+    if (profile) {
+      hcheck(hipEventRecord(whole.second, st));
+      pending.push_back(Pending{-1, whole.first, whole.second, 0.0});
     }
   }
 
@@ -1267,6 +1276,10 @@ struct Engine {
     for (const Pending& p : pending) {
       float ms = 0;
       hcheck(hipEventElapsedTime(&ms, p.a, p.b));
+      if (p.bin < 0) {   // a whole candidate search
+        stats.search_ms += ms;
+        continue;
+      }
       stats.bin_ms[p.bin] += ms;
       stats.bin_bytes[p.bin] += p.bytes;
       stats.bin_launches[p.bin] += 1;

@@ -92,12 +92,14 @@ __global__ void k_set_add_mapped(SetRef set, const uint32_t* list, uint32_t coun
 // Row segments of sorted record keys: one entry (first record index) per distinct row.
 __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key);
 
-// ---- row lookup of sorted records.  The records of one row (a segment, up to 2048 at a
+// ---- row lookup of sorted records.  The records of one row (a segment, up to kSegChunk at a
 // time) go into an LDS hash table keyed by column and the row is streamed once, each entry
-// probing the table: O(degree + records) per row.  Work items are (segment, record chunk,
-// row slice) so a huge row is streamed by many workgroups.
-constexpr int kSegChunk = 2048;
-constexpr uint32_t kSlice = 16384;
+// probing the table: O(degree + records) per row.  Work items are (segment, record chunk, row
+// slice) and each wavefront takes items on its own, so a huge row is streamed by many
+// wavefronts and a small one costs one wavefront pass without workgroup barriers.
+constexpr uint32_t kSegChunk = 512;     // records per item
+constexpr uint32_t kSlice = 4096;       // row entries per item
+constexpr uint32_t kSegSlots = 2 * kSegChunk;
 
 __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo,
                             const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items, int ks) {
@@ -118,28 +120,39 @@ __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const ui
   }
 }
 
-__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t n, uint64_t key) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] <= key) lo = mid + 1;
-    else hi = mid;
+// largest s in [0, n] with off[s] <= it, for off non-decreasing with off[0] <= it < off[n]; a
+// 64-ary search by the whole wavefront (every lane returns the same value)
+__device__ __forceinline__ uint32_t wave_owner(const uint64_t* off, uint32_t n, uint64_t it) {
+  uint32_t lo = 0, hi = n;   // off[lo] <= it < off[hi]
+  const uint32_t lane = (uint32_t)lane_id();
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + kWave - 1) / kWave;
+    const uint32_t p = lo + lane * step;
+    const bool ok = p < hi && off[p] <= it;   // a prefix of the lanes, lane 0 always
+    const uint64_t m = __ballot(ok);
+    const uint32_t last = 63u - (uint32_t)__clzll((long long)m);
+    const uint32_t nlo = lo + last * step;
+    hi = nlo + step < hi ? nlo + step : hi;
+    lo = nlo;
   }
   return lo;
 }
 
-// workgroup per work item: LDS table of the item's record chunk, stream the item's row slice,
+// wavefront per work item: LDS table of the item's record chunk, stream the item's row slice,
 // write the slot of every record found (each record matches at most one entry)
 __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k,
                                                     const uint64_t* seg_lo, const uint64_t* seg_hi,
                                                     const uint32_t* nseg_ptr, const uint64_t* item_off,
                                                     int64_t* slot_out, int ks) {
-  __shared__ uint32_t tkey[2 * kSegChunk];
-  __shared__ uint32_t tval[2 * kSegChunk];
+  __shared__ uint32_t tkey_s[256 / kWave][kSegSlots];
+  __shared__ uint32_t tval_s[256 / kWave][kSegSlots];
+  const int lane = lane_id();
+  uint32_t* tkey = tkey_s[threadIdx.x / kWave];
+  uint32_t* tval = tval_s[threadIdx.x / kWave];
   const uint32_t nseg = *nseg_ptr;
   const uint64_t total = item_off[nseg];
-  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t sg = upper_bound_u64(item_off, nseg + 1, it) - 1;
+  for (uint64_t it = gwave(); it < total; it += gwstride()) {
+    const uint32_t sg = wave_owner(item_off, nseg, it);
     const uint64_t sub = it - item_off[sg];
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
     const uint32_t row = krow(keys[lo], ks);
@@ -151,9 +164,9 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
     uint32_t size = 64;
     while (size < 2 * kk) size <<= 1;
     const uint32_t mask = size - 1;
-    for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
+    for (uint32_t i = lane; i < size; i += kWave) tkey[i] = kEmpty;
+    wave_sync();
+    for (uint32_t i = lane; i < kk; i += kWave) {
       const uint32_t col = kcol(keys[clo + i], ks);
       uint32_t h = hash32(col) & mask;
       for (;;) {
@@ -165,11 +178,11 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
         h = (h + 1) & mask;
       }
     }
-    __syncthreads();
+    wave_sync();
     const uint64_t off = c.off[row];
     const uint64_t e0 = sl * kSlice;
     const uint64_t e1 = e0 + kSlice < deg ? e0 + kSlice : deg;
-    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
+    for (uint64_t j = e0 + lane; j < e1; j += kWave) {
       const uint32_t x = c.nbr[off + j];
       uint32_t h = hash32(x) & mask;
       for (;;) {
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
         h = (h + 1) & mask;
       }
     }
-    __syncthreads();
+    wave_sync();   // table reads done before the next item clears it
   }
 }
 
@@ -193,18 +206,29 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
 // move into the deletion holes below t0 (the two counts are equal), and insertions are
 // written from t0 on.  Entry order within a row carries no meaning.  Rows that outgrow their
 // capacity are listed for k_seg_move.
+constexpr uint64_t kSegWaveMax = 1024;   // segments updated by one wavefront
+constexpr int kSegTpb = 1024;            // threads of the workgroup that updates a larger segment
+
+// Orders the global-memory accesses of one wavefront's lanes with respect to each other (a
+// workgroup-scope fence waits for the wavefront's own stores; no other wavefront takes part).
+__device__ __forceinline__ void wave_sync_global() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 constexpr uint8_t kRecNone = 0, kRecUpd = 1, kRecDel = 2, kRecIns = 3;
 
-__global__ __launch_bounds__(kTpb) void k_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta,
+__global__ __launch_bounds__(kSegTpb) void k_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta,
                                                      const uint64_t* seg_lo, const uint64_t* seg_hi,
                                                      const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
                                                      uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel,
                                                      uint32_t* rowins, uint32_t* move_list, uint32_t* move_count, int ks) {
-  __shared__ int64_t red[3 * (kTpb / kWave)];
-  __shared__ uint32_t lds[kTpb / kWave];
+  __shared__ int64_t red[3 * (kSegTpb / kWave)];
+  __shared__ uint32_t lds[kSegTpb / kWave];
   const uint32_t nseg = *nseg_ptr;
   for (uint32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    if (hi - lo <= kSegWaveMax) continue;   // k_seg_update_wave's segment
     const uint32_t row = krow(keys[lo], ks);
     const uint64_t off = c.off[row];
     const uint32_t deg = c.deg[row];
@@ -311,6 +335,113 @@ __global__ __launch_bounds__(kTpb) void k_seg_update(CsrRef c, const uint64_t* k
     }
     if (threadIdx.x == 0) c.deg[row] = (uint32_t)ndeg;
     __syncthreads();
+  }
+}
+
+
+// The same update with one wavefront per segment, for segments of at most kSegWaveMax records
+// (the common case at aggregate levels): ranks come from ballots, no workgroup barrier.
+__global__ __launch_bounds__(kTpb) void k_seg_update_wave(CsrRef c, const uint64_t* keys, const int64_t* delta,
+                                                          const uint64_t* seg_lo, const uint64_t* seg_hi,
+                                                          const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
+                                                          uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel,
+                                                          uint32_t* rowins, uint32_t* move_list, uint32_t* move_count,
+                                                          int ks) {
+  const int lane = lane_id();
+  const uint32_t nseg = *nseg_ptr;
+  for (uint64_t sg = gwave(); sg < nseg; sg += gwstride()) {
+    const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    if (hi - lo > kSegWaveMax) continue;   // k_seg_update's segment
+    const uint32_t row = krow(keys[lo], ks);
+    const uint64_t off = c.off[row];
+    const uint32_t deg = c.deg[row];
+    const uint32_t cap = c.cap[row];
+    int64_t ndel = 0, nins = 0, dsum = 0;
+    for (uint64_t i = lo + lane; i < hi; i += kWave) {
+      const int64_t d = delta[i];
+      const int64_t sl = slot[i];
+      dsum += d;
+      uint8_t t = kRecNone;
+      if (d != 0) {
+        if (sl >= 0) {
+          const int64_t nw = wget(c, (uint64_t)sl) + d;
+          wset(c, (uint64_t)sl, nw);
+          t = nw == 0 ? kRecDel : kRecUpd;
+          if (nw == 0) ++ndel;
+        } else {
+          t = kRecIns;
+          ++nins;
+        }
+      }
+      rtype[i] = t;
+    }
+    ndel = wave_sum_i64(ndel);
+    nins = wave_sum_i64(nins);
+    dsum = wave_sum_i64(dsum);
+    wave_sync_global();                                  // weights and record types written above
+    if (lane == 0 && deg_arr && dsum) deg_arr[row] += dsum;
+    if (ndel + nins == 0) continue;                       // uniform over the wavefront
+    const uint64_t ndeg = (uint64_t)deg - (uint64_t)ndel + (uint64_t)nins;
+    if (ndeg > cap) {
+      if (lane == 0) {
+        rowdel[row] = (uint32_t)ndel;
+        rowins[row] = (uint32_t)nins;
+        move_list[atomicAdd(move_count, 1u)] = (uint32_t)sg;
+      }
+      continue;
+    }
+    const uint32_t t0 = deg - (uint32_t)ndel;
+    // holes below t0, in record order (at most ndel <= hi - lo of them)
+    uint32_t nh = 0;
+    for (uint64_t b = lo; b < hi; b += kWave) {
+      const uint64_t i = b + lane;
+      bool f = false;
+      uint64_t sl = 0;
+      if (i < hi && rtype[i] == kRecDel) {
+        sl = (uint64_t)slot[i];
+        f = sl - off < t0;
+      }
+      const uint64_t m = __ballot(f);
+      if (f) hole[lo + nh + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = sl;
+      nh += (uint32_t)__popcll(m);
+    }
+    wave_sync_global();
+    // survivors among the last ndel slots fill the holes
+    uint32_t ns = 0;
+    for (uint32_t b = t0; b < deg; b += kWave) {
+      const uint32_t p = b + (uint32_t)lane;
+      bool f = false;
+      uint32_t x = 0;
+      int64_t wv = 0;
+      if (p < deg) {
+        wv = wget(c, off + p);
+        f = wv != 0;
+        if (f) x = c.nbr[off + p];
+      }
+      const uint64_t m = __ballot(f);
+      const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (f && ns + r < nh) {
+        const uint64_t dst = hole[lo + ns + r];
+        c.nbr[dst] = x;
+        wset(c, dst, wv);
+      }
+      ns += (uint32_t)__popcll(m);
+    }
+    wave_sync_global();
+    // insertions from t0 on
+    uint32_t ni = 0;
+    for (uint64_t b = lo; b < hi; b += kWave) {
+      const uint64_t i = b + lane;
+      const bool f = i < hi && rtype[i] == kRecIns;
+      const uint64_t m = __ballot(f);
+      if (f) {
+        const uint64_t dst = off + t0 + ni + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        c.nbr[dst] = kcol(keys[i], ks);
+        wset(c, dst, delta[i]);
+      }
+      ni += (uint32_t)__popcll(m);
+    }
+    if (lane == 0) c.deg[row] = (uint32_t)ndeg;
   }
 }
 
@@ -1080,9 +1211,14 @@ void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uin
                        uint64_t* hole, int64_t* deg_arr, uint32_t* rowdel, uint32_t* rowins, uint32_t* move_list,
                        uint32_t* move_count, int ks, hipStream_t s) {
   if (!k) return;
-  const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_update, kTpb));
-  k_seg_update<<<g, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel, rowins,
-                                  move_list, move_count, ks);
+  const unsigned gw = cap_blocks((k + 3) / 4, LDL_RESIDENT(k_seg_update_wave, kTpb));
+  k_seg_update_wave<<<gw, kTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel,
+                                        rowins, move_list, move_count, ks);
+  if (k > kSegWaveMax) {   // a segment above the wavefront limit exists only then
+    const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_update, kSegTpb));
+    k_seg_update<<<g, kSegTpb, 0, s>>>(c, keys, delta, seg_lo, seg_hi, nseg_ptr, slot, rtype, hole, deg_arr, rowdel,
+                                    rowins, move_list, move_count, ks);
+  }
 }
 void launch_seg_move(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                      const uint64_t* seg_hi, const uint8_t* rtype, const uint32_t* rowdel, const uint32_t* rowins,

@@ -461,12 +461,6 @@ __device__ __forceinline__ void table_insert(uint32_t* keys, u64a* vals, uint32_
 }
 
 // ------------------------------------------------------------------ wavefront teams
-// Orders the LDS accesses of one wavefront (all its lanes) with respect to each other.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Insert (key, w) into an LDS table that is empty between vertices.  Returns the slot when
 // this call created the key's entry (the calling lane then owns it), else kNoSlot.

@@ -71,6 +71,13 @@ __device__ __forceinline__ void atomic_add_i128(u64a* lo, i64a* hi, i128 v) {
 }
 __device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) { atomicAdd((u64a*)p, (u64a)v); }
 
+// Orders the LDS accesses of one wavefront (all its lanes) with respect to each other.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ wave reductions
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
