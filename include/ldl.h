@@ -70,7 +70,9 @@ typedef struct ldl_pair {
  *                       commit phase), 2 = minimal hub hash-table pool (overflow and redo of an
  *                       iteration), 4 = no spare adjacency capacity (row moves, pool growth),
  *                       8 = always queue the one-workgroup decoupling filter first (iterations
- *                       with more candidates than it holds run the filter after the host check)
+ *                       with more candidates than it holds run the filter after the host check),
+ *                       16 = 64-slot LDS tables for the hub partitions (partition overflow, redo of
+ *                       the iteration with more partitions per hub)
  */
 typedef struct ldl_config {
   int32_t directed;

@@ -401,7 +401,7 @@ def candidate_kernel_name(k: int, directed: bool = False) -> str:
     d, r = ("true" if directed else "false"), ("true" if refine else "false")
     return [f"k_best_group<{wt}, 8, {d}, {r}>", f"k_best_group<{wt}, 32, {d}, {r}>",
             f"k_best_wave<{wt}, 256, {d}, {r}>", f"k_best_wave<{wt}, 1024, {d}, {r}>",
-            f"k_best_hash<{wt}, 256, 4096, {d}, {r}>", f"k_hub_insert<{wt}, {d}, {r}>"][b]
+            f"k_best_hash<{wt}, 256, 4096, {d}, {r}>", f"k_hub_keys<{wt}, {d}, {r}>"][b]
 
 
 def version() -> str:

@@ -418,26 +418,33 @@ struct Engine {
     cand.count = &ds->ps.ncand;
     hub.top = &ds->ps.hub_need;
     hub.over_count = &ds->ps.hub_over;
+    hw.pshift = 0;
+    hw.tslots = (test_flags & 16) ? 64u : kPartSlots;
     hub_pool((test_flags & 2) ? 0 : 4ull * n);
     hcheck(hipStreamSynchronize(st));
   }
 
-  // (re)allocate the hub table pool with at least `slots` slots, empty, and its partials
-  void hub_pool(uint64_t slots) {
+  // (re)allocate the hub bucket pool for at least `entries` entries and its partition arrays
+  // (partition counts and cursors start at zero; the hub kernels return them to zero)
+  void hub_pool(uint64_t entries) {
     uint64_t hc = (test_flags & 2) ? 256 : 1ull << 16;
-    while (hc < slots) hc <<= 1;
-    release(hub.keys);
-    release(hub.vals);
-    hub.keys = nullptr;
-    hub.vals = nullptr;
-    hub.keys = alloc<uint32_t>(hc);
-    hub.vals = alloc<u64a>(hc);
+    while (hc < entries) hc <<= 1;
+    release(hub.ekey);
+    release(hub.bkey);
+    release(hub.bw);
+    hub.ekey = nullptr;
+    hub.bkey = nullptr;
+    hub.bw = nullptr;
+    hub.ekey = alloc<uint32_t>(hc);
+    hub.bkey = alloc<uint32_t>(hc);
+    hub.bw = alloc<int64_t>(hc);
     hub.cap = hc;
-    hcheck(hipMemsetAsync(hub.keys, 0xFF, 4ull * hc, st));
-    hcheck(hipMemsetAsync(hub.vals, 0, 8ull * hc, st));
-    const uint64_t parts = hc / kHubScanSlots + (uint64_t)n + 2;
+    const uint64_t parts = hc / 16 + (uint64_t)n + 2;
     if (parts > part_cap) {
       regrow(hw.phi, parts); regrow(hw.plo, parts); regrow(hw.pid, parts); regrow(hw.pvalid, parts);
+      regrow(hw.pcount, parts); regrow(hw.pcur, parts); regrow(hw.poff, parts); regrow(hw.pcnt, parts);
+      hcheck(hipMemsetAsync(hw.pcount, 0, 4ull * parts, st));
+      hcheck(hipMemsetAsync(hw.pcur, 0, 4ull * parts, st));
       part_cap = parts;
     }
   }
@@ -797,6 +804,12 @@ struct Engine {
       pending.resize(first_pending);
       return false;
     }
+    if (ps.hub_over & 4u) {   // a hash partition outgrew its LDS table: more partitions per hub
+      if (hw.pshift >= kPartShiftMax) throw DeviceError{hipErrorUnknown};
+      hw.pshift++;
+      pending.resize(first_pending);
+      return false;
+    }
     scanned = hs->counts[sets[sid].ci];
     K = ps.ncand;
     // algorithmic bytes: per vertex its list id, offsets and degrees, label, degrees and the
@@ -935,7 +948,7 @@ struct Engine {
       sync_read();
       if (best_finish(r, sid, refine, fp, scanned, K)) break;
       commit(acc, &ds->nacc, 0);   // undo: the candidate set was incomplete
-      if (attempt > 2) throw NoMem{};
+      if (attempt > 2 + kPartShiftMax) throw NoMem{};
     }
     lf_lastK[r][refine] = K;
     dein = refine ? 0 : hs->ps.cdein;
@@ -1208,7 +1221,7 @@ struct Engine {
         sync_read();
         uint32_t sc = 0, K = 0;
         if (best_finish(r, sid, 0, pending.size(), sc, K)) break;
-        if (attempt > 2) throw NoMem{};
+        if (attempt > 2 + kPartShiftMax) throw NoMem{};
       }
       float ms = 0;
       hcheck(hipEventElapsedTime(&ms, a, b));

@@ -721,15 +721,20 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
 }
 
 // ---- hubs split over many workgroups, driven from device counts.  Hub i (of the bin's h
-// vertices) owns a table of pow2 >= max(64, 2 T_i) slots in the pool, has ceil(T_i / kHubChunk)
-// insert items (entry chunks pre-aggregated in LDS) and one scan item per kHubScan table
-// slots; one exclusive scan of the three counts places tables, items and partial bests.
-// Scan items evaluate the gains into partial bests and return their slots to empty; one
-// wavefront per hub reduces the partials.  Hubs whose table ends beyond the pool are
-// skipped and reported (bit 0 of *over, with the pool size needed in *need); more than
-// `bound` hubs is reported as bit 1.
+// vertices, T_i entries) has ceil(T_i / kHubChunk) chunk items and P_i hash partitions of its
+// neighbour communities (P_i = ceil(T_i 2^pshift / kPartEntries), at most ceil(T_i / 16)); one
+// exclusive scan of (entries, chunks, partitions) places the hub's slice of the bucket pool, its
+// items and its partitions.  The keys pass computes every entry's community key (the own
+// community's weight is summed apart) and counts the entries per partition; a per-hub scan turns
+// the counts into bucket offsets; the scatter pass writes (key, weight) into the buckets; one
+// workgroup per partition then sums its bucket by key in an LDS table and evaluates the gains
+// into a partial best; one wavefront per hub reduces its partials.  Every key of a hub lands in
+// exactly one partition, so the sums are complete without global atomics on them.  Hubs whose
+// entries end beyond the pool are skipped and reported (bit 0 of *over, with the entries needed
+// in *need); more than `bound` hubs is bit 1; a partition with more distinct keys than its LDS
+// table is bit 2 (the host then redoes the pass with more partitions).
 constexpr uint32_t kHubChunk = 2048;
-constexpr uint32_t kHubScan = kHubScanSlots;
+constexpr uint32_t kPartHist = 4096;   // partitions counted in LDS per chunk (more: global atomics)
 
 __device__ __forceinline__ uint32_t hub_count(const BinRef& br, uint32_t bound) {
   const uint32_t c = *br.count;
@@ -738,6 +743,12 @@ __device__ __forceinline__ uint32_t hub_count(const BinRef& br, uint32_t bound) 
 
 __device__ __forceinline__ uint64_t entries_of(const MoveView& mv, uint32_t v) {
   return (uint64_t)mv.out.deg[v] + (mv.directed ? (uint64_t)mv.in.deg[v] : 0ull);
+}
+
+// partition of a key among P: the high bits of a second hash (the LDS tables use the low bits
+// of hash32, so keys of one partition do not crowd one end of its table)
+__device__ __forceinline__ uint32_t part_of(uint32_t key, uint32_t P) {
+  return (uint32_t)(((uint64_t)hash32(key * 0x9E3779B1u + 0x7F4A7C15u) * P) >> 32);
 }
 
 // largest i in [0, h) with off[i].F <= it, for off non-decreasing in F with off[h].F > it
@@ -753,7 +764,8 @@ __device__ __forceinline__ uint32_t item_owner(const U64x3* off, uint32_t h, uin
   return lo;
 }
 
-__global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, U64x3* cnt, int64_t* own, uint32_t* over) {
+__global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, int pshift, U64x3* cnt, int64_t* own,
+                           uint32_t* over) {
   const uint32_t c = *br.count;
   const uint32_t h = c < bound ? c : bound;
   const uint32_t* list = br.base + *br.start;
@@ -762,23 +774,25 @@ __global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, U64x3* cnt, i
     U64x3 x{0, 0, 0};
     if (i < h) {
       const uint64_t T = entries_of(mv, list[i]);
-      uint64_t size = 64;
-      while (size < 2 * T) size <<= 1;
-      x.x = size;
+      uint64_t P = ((T << pshift) + kPartEntries - 1) / kPartEntries;
+      const uint64_t Pmax = (T + 15) / 16;
+      if (P > Pmax) P = Pmax;
+      if (P < 1) P = 1;
+      x.x = T;
       x.y = (T + kHubChunk - 1) / kHubChunk;
-      x.z = (size + kHubScan - 1) / kHubScan;
+      x.z = P;
       own[i] = 0;
     }
     cnt[i] = x;
   }
 }
 
+// chunk items: keys of the entries, own-community weight, entries per partition
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
-                                                     HubPool hub, int64_t* own, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_hub_keys(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
+                                                   HubPool hub, HubWork hw, MoveStats st) {
   __shared__ int64_t red[kTpb / kWave];
-  __shared__ uint32_t lkey[2 * kHubChunk];
-  __shared__ u64a lval[2 * kHubChunk];
+  __shared__ uint32_t lh[kPartHist];
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
   const uint64_t total = off[h].y;
@@ -786,91 +800,209 @@ __global__ __launch_bounds__(kTpb) void k_hub_insert(MoveView mv, BinRef br, uin
   for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const uint32_t i = item_owner<1>(off, h, it);
     const uint64_t base = off[i].x;
-    const uint64_t size = off[i + 1].x - base;
-    if (base + size > hub.cap) continue;       // table beyond the pool: reported by k_hub_final
+    if (off[i + 1].x > hub.cap) continue;      // beyond the pool: reported by k_hub_final
     const uint32_t v = list[i];
     const uint32_t dout = mv.out.deg[v];
-    const uint32_t din = DIR ? mv.in.deg[v] : 0;
-    const uint32_t T = dout + din;
+    const uint32_t T = dout + (DIR ? mv.in.deg[v] : 0);
+    const uint32_t P = (uint32_t)(off[i + 1].z - off[i].z);
+    const uint64_t pbase = off[i].z;
     const uint64_t e0 = (it - off[i].y) * kHubChunk;
     const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
-    const uint32_t mask = (uint32_t)(size - 1);
-    uint32_t* keys = hub.keys + base;
-    u64a* vals = hub.vals + base;
     const uint32_t labv = mv.lab[v];
     const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-    // aggregate the chunk in LDS first so hot communities cost one global update per chunk
-    for (uint32_t t = threadIdx.x; t < 2 * kHubChunk; t += blockDim.x) {
-      lkey[t] = kEmpty;
-      lval[t] = 0;
-    }
+    const bool local = P <= kPartHist;
+    if (local)
+      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) lh[t] = 0;
     __syncthreads();
     int64_t ow = 0;
     for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
       uint32_t x;
       int64_t w;
       entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
-      const uint32_t key = entry_key<REF>(mv, v, labv, x);
-      if (key == kEmpty) continue;
+      uint32_t key = entry_key<REF>(mv, v, labv, x);
       if (!REF && key == labv) {
         ow += w;
-        continue;
+        key = kEmpty;
       }
-      table_insert(lkey, lval, 2 * kHubChunk - 1, key, w);
+      hub.ekey[base + j] = key;
+      if (key == kEmpty) continue;
+      const uint32_t p = part_of(key, P);
+      if (local) atomicAdd(&lh[p], 1u);
+      else atomicAdd(&hw.pcount[pbase + p], 1u);
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < 2 * kHubChunk; t += blockDim.x) {
-      const uint32_t key = lkey[t];
-      if (key != kEmpty) table_insert(keys, vals, mask, key, (int64_t)lval[t]);
-    }
+    if (local)
+      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x)
+        if (lh[t]) atomicAdd(&hw.pcount[pbase + t], lh[t]);
     ow = team_sum<kTpb>(ow, red);
-    if (threadIdx.x == 0 && ow) atomic_add_i64(&own[i], ow);
+    if (threadIdx.x == 0 && ow) atomic_add_i64(&hw.own[i], ow);
     nent += e1 - e0;
     __syncthreads();
   }
   if (threadIdx.x == 0 && st.entries && nent) atomicAdd(st.entries, (u64a)nent);
 }
 
+// per hub: bucket offsets of its partitions (exclusive scan of the counts); counts return to 0
+__global__ __launch_bounds__(kTpb) void k_hub_poff(BinRef br, uint32_t bound, const U64x3* off, HubPool hub,
+                                                   HubWork hw) {
+  __shared__ uint64_t wsum[kTpb / kWave];
+  const uint32_t h = hub_count(br, bound);
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (uint32_t i = blockIdx.x; i < h; i += gridDim.x) {
+    if (off[i + 1].x > hub.cap) continue;
+    const uint64_t p0 = off[i].z, p1 = off[i + 1].z;
+    uint64_t carry = off[i].x;
+    for (uint64_t b = p0; b < p1; b += blockDim.x) {
+      const uint64_t q = b + threadIdx.x;
+      const uint64_t c = q < p1 ? hw.pcount[q] : 0;
+      uint64_t incl = c;   // inclusive scan within the wavefront
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const uint64_t t = (uint64_t)__shfl_up((long long)incl, o, kWave);
+        if (lane >= o) incl += t;
+      }
+      if (lane == kWave - 1) wsum[w] = incl;
+      __syncthreads();
+      uint64_t before = 0, all = 0;
+      for (int k = 0; k < kTpb / kWave; ++k) {
+        if (k < w) before += wsum[k];
+        all += wsum[k];
+      }
+      if (q < p1) {
+        hw.poff[q] = carry + before + incl - c;
+        hw.pcnt[q] = (uint32_t)c;
+        hw.pcount[q] = 0;
+      }
+      carry += all;
+      __syncthreads();
+    }
+  }
+}
+
+// chunk items: (key, weight) of every counted entry into its partition's bucket
 template <typename WT, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_hub_scan(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
-                                                   HubPool hub, const int64_t* own, int64_t* phi, uint64_t* plo,
-                                                   uint32_t* pid, int* pvalid, MoveStats st) {
+__global__ __launch_bounds__(kTpb) void k_hub_scatter(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
+                                                      HubPool hub, HubWork hw) {
+  __shared__ uint32_t lh[kPartHist];
+  __shared__ uint32_t lb[kPartHist];
+  const uint32_t h = hub_count(br, bound);
+  const uint32_t* list = br.base + *br.start;
+  const uint64_t total = off[h].y;
+  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t i = item_owner<1>(off, h, it);
+    const uint64_t base = off[i].x;
+    if (off[i + 1].x > hub.cap) continue;
+    const uint32_t v = list[i];
+    const uint32_t dout = mv.out.deg[v];
+    const uint32_t T = dout + (DIR ? mv.in.deg[v] : 0);
+    const uint32_t P = (uint32_t)(off[i + 1].z - off[i].z);
+    const uint64_t pbase = off[i].z;
+    const uint64_t e0 = (it - off[i].y) * kHubChunk;
+    const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
+    const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
+    const bool local = P <= kPartHist;
+    if (local) {
+      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) lh[t] = 0;
+      __syncthreads();
+      for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
+        const uint32_t key = hub.ekey[base + j];
+        if (key != kEmpty) atomicAdd(&lh[part_of(key, P)], 1u);
+      }
+      __syncthreads();
+      // one global reservation per partition of the chunk; lh becomes the chunk's local cursor
+      for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
+        if (lh[t]) lb[t] = atomicAdd(&hw.pcur[pbase + t], lh[t]);
+        lh[t] = 0;
+      }
+      __syncthreads();
+    }
+    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
+      const uint32_t key = hub.ekey[base + j];
+      if (key == kEmpty) continue;
+      uint32_t x;
+      int64_t w;
+      entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
+      const uint32_t p = part_of(key, P);
+      const uint32_t at = local ? lb[p] + atomicAdd(&lh[p], 1u) : atomicAdd(&hw.pcur[pbase + p], 1u);
+      const uint64_t pos = hw.poff[pbase + p] + at;
+      hub.bkey[pos] = key;
+      hub.bw[pos] = w;
+    }
+    __syncthreads();
+  }
+}
+
+// workgroup per partition: sum its bucket by key in LDS, evaluate every key's gain, keep the
+// partition's best; the scatter cursor returns to 0
+template <bool DIR, bool REF>
+__global__ __launch_bounds__(kTpb) void k_hub_part(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
+                                                   HubPool hub, HubWork hw, MoveStats st) {
+  __shared__ uint32_t tk[kPartSlots];
+  __shared__ u64a tv[kPartSlots];
   __shared__ Best red_b[kTpb / kWave];
   __shared__ int64_t red_i[kTpb / kWave];
+  __shared__ int s_over;
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
   const uint64_t total = off[h].z;
   uint64_t ndist = 0;
-  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const uint32_t i = item_owner<2>(off, h, it);
-    const uint64_t base = off[i].x;
-    const uint64_t size = off[i + 1].x - base;
-    if (base + size > hub.cap) continue;
-    const uint64_t s0 = (it - off[i].z) * kHubScan;
-    const uint64_t s1 = s0 + kHubScan < size ? s0 + kHubScan : size;
+  for (uint64_t q = blockIdx.x; q < total; q += gridDim.x) {
+    const uint32_t i = item_owner<2>(off, h, q);
+    if (off[i + 1].x > hub.cap) continue;
+    const uint64_t b0 = hw.poff[q], nb = hw.pcnt[q];
+    uint32_t size = 64;   // pow2 >= 2 nb slots (at most the table), cleared and scanned
+    while (size < 2 * nb && size < hw.tslots) size <<= 1;
+    if (size > hw.tslots) size = hw.tslots;
+    const uint32_t mask = size - 1;
+    for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
+      tk[t] = kEmpty;
+      tv[t] = 0;
+    }
+    if (threadIdx.x == 0) s_over = 0;
+    __syncthreads();
+    for (uint64_t j = threadIdx.x; j < nb; j += blockDim.x) {
+      const uint32_t key = hub.bkey[b0 + j];
+      uint32_t slot = hash32(key) & mask;
+      uint32_t probes = 0;
+      for (;;) {
+        const uint32_t prev = atomicCAS(&tk[slot], kEmpty, key);
+        if (prev == kEmpty || prev == key) {
+          atomicAdd(&tv[slot], (u64a)hub.bw[b0 + j]);
+          break;
+        }
+        slot = (slot + 1) & mask;
+        if (++probes == size) {   // table full: more distinct keys than slots
+          s_over = 1;
+          break;
+        }
+      }
+    }
+    __syncthreads();
     const uint32_t v = list[i];
     const VInfo vi = vinfo<DIR, REF>(mv, v);
-    const int64_t ow = own[i];
+    const int64_t ow = hw.own[i];
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
     int64_t nd = 0;
-    for (uint64_t sl = s0 + threadIdx.x; sl < s1; sl += blockDim.x) {
-      const uint32_t key = hub.keys[base + sl];
+    for (uint32_t t = threadIdx.x; t < size; t += blockDim.x) {
+      const uint32_t key = tk[t];
       if (key == kEmpty) continue;
       ++nd;
-      const int64_t a = (int64_t)hub.vals[base + sl];
-      hub.keys[base + sl] = kEmpty;    // the pool is left empty for the next launch
-      hub.vals[base + sl] = 0;
-      const Best c = make_best(gain<DIR, REF>(mv, vi, key, a, ow), key);
+      const Best c = make_best(gain<DIR, REF>(mv, vi, key, (int64_t)tv[t], ow), key);
       if (better(c, b)) b = c;
     }
     nd = team_sum<kTpb>(nd, red_i);
     b = team_best<kTpb>(b, red_b);
     if (threadIdx.x == 0) {
-      phi[it] = b.hi;
-      plo[it] = b.lo;
-      pid[it] = b.id;
-      pvalid[it] = b.valid;
+      if (s_over) {
+        atomicOr(hub.over_count, 4u);
+        b.valid = 0;
+      }
+      hw.phi[q] = b.hi;
+      hw.plo[q] = b.lo;
+      hw.pid[q] = b.id;
+      hw.pvalid[q] = b.valid;
+      hw.pcur[q] = 0;
       ndist += (uint64_t)nd;
     }
     __syncthreads();
@@ -891,7 +1023,7 @@ __global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_
     if (total > cap) atomicOr(over, 1u);
   }
   for (uint64_t i = gwave(); i < h; i += gwstride()) {
-    if (off[i + 1].x > cap) continue;          // skipped: table beyond the pool
+    if (off[i + 1].x > cap) continue;          // skipped: entries beyond the pool
     const uint64_t p0 = off[i].z, p1 = off[i + 1].z;
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
@@ -916,20 +1048,23 @@ __global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_
 template <typename WT, bool DIR, bool REF>
 int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, HubWork hw, CandBuf cand, MoveStats st,
                  void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-  k_hub_size<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(mv, br, bound, hw.cnt, hw.own, hub.over_count);
+  k_hub_size<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(mv, br, bound, hw.pshift, hw.cnt, hw.own,
+                                                            hub.over_count);
   const int rc = prim_exclusive_sum_u64x3(tmp, tmp_bytes, hw.cnt, hw.off, (uint64_t)bound + 1, s);
   if (rc) return rc;
   if (ev_a) (void)hipEventRecord(ev_a, s);
-  k_hub_insert<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_insert<WT, DIR, REF>), kTpb)), kTpb,
-                               0, s>>>(mv, br, bound, hw.off, hub, hw.own, st);
+  k_hub_keys<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_keys<WT, DIR, REF>), kTpb)), kTpb, 0,
+                             s>>>(mv, br, bound, hw.off, hub, hw, st);
   if (ev_b) (void)hipEventRecord(ev_b, s);
-  k_hub_scan<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_scan<WT, DIR, REF>), kTpb)), kTpb, 0,
-                             s>>>(mv, br, bound, hw.off, hub, hw.own, hw.phi, hw.plo, hw.pid, hw.pvalid, st);
+  k_hub_poff<<<cap_blocks(bound, LDL_RESIDENT(k_hub_poff, kTpb)), kTpb, 0, s>>>(br, bound, hw.off, hub, hw);
+  k_hub_scatter<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_scatter<WT, DIR, REF>), kTpb)), kTpb,
+                                0, s>>>(mv, br, bound, hw.off, hub, hw);
+  k_hub_part<DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_part<DIR, REF>), kTpb)), kTpb, 0, s>>>(
+      mv, br, bound, hw.off, hub, hw, st);
   k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.off, hub.cap, mv.lab, hw.phi, hw.plo, hw.pid,
                                                       hw.pvalid, cand, st, hub.top, hub.over_count);
   return 0;
 }
-
 
 template <typename WT, bool DIR, bool REF>
 void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, CandBuf cand, MoveStats st,

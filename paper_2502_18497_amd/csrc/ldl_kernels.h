@@ -56,14 +56,16 @@ struct CandBuf {
   uint32_t* count;
 };
 
-// Hash-table pool of the hub bin: keys kEmpty and values 0 between launches (the scan kernel
-// empties every slot it reads).
+// Bucket pool of the hub bin: the neighbour-community keys of every hub entry (ekey) and the
+// (key, weight) pairs scattered into per-hub hash partitions (bkey, bw), cap entries each.
 struct HubPool {
-  uint32_t* keys;
-  u64a* vals;
-  uint64_t cap;         // slots
-  u64a* top;            // device word: slots the last launch needed
-  uint32_t* over_count; // device flags: bit 0 pool too small, bit 1 more hubs than the bound
+  uint32_t* ekey;
+  uint32_t* bkey;
+  int64_t* bw;
+  uint64_t cap;         // entries
+  u64a* top;            // device word: entries the last launch needed
+  uint32_t* over_count; // device flags: bit 0 pool too small, bit 1 more hubs than the bound,
+                        // bit 2 a partition had more distinct keys than its LDS table holds
 };
 
 struct MoveStats {  // per-launch counters (null: not counted)
@@ -82,7 +84,6 @@ struct BinRef {
 };
 
 constexpr int kNumBins = 6;
-constexpr uint32_t kHubScanSlots = 8192;   // table slots evaluated per hub scan workgroup
 // Degree bins: a vertex with T > 0 entries goes to the first bin b < kNumBins - 1 with
 // T <= lim[b], else to the hub path (bin kNumBins - 1).  Bin b's kernel accepts at most
 // kBinCap[b] entries, so 0 <= lim[0] <= ... <= lim[4] with lim[b] <= kBinCap[b]; the limits only
@@ -200,21 +201,30 @@ void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, in
 // candidate kernels of degree bins 0..kNumBins-2 over a device-resident bin list
 void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int refine, CandBuf cand, MoveStats st,
                  hipStream_t s);
-// hub bin, device driven: per-hub table sizes, insert chunks and scan parts are prefix-summed
-// over `bound` + 1 entries (bound >= number of hubs); hubs whose tables do not fit the pool are
-// skipped and flagged.  Work arrays hold bound + 1 entries, partials cap / kHubScanSlots + bound.
+// hub bin, device driven: per-hub entry counts, chunk items and hash partitions are prefix-summed
+// over `bound` + 1 entries (bound >= number of hubs); hubs whose entries do not fit the pool are
+// skipped and flagged.  Work arrays hold bound + 1 entries, partition arrays cap / 16 + bound + 1.
 struct U64x3 {
   uint64_t x, y, z;
 };
 struct HubWork {
-  U64x3* cnt;     // per hub: table slots, insert items, scan items (bound + 1 entries)
-  U64x3* off;     // their exclusive prefix
-  int64_t* own;   // weight towards the own community, per hub
-  int64_t* phi;   // partial bests, one per scan item
+  U64x3* cnt;      // per hub: entries, chunk items, partitions (bound + 1 entries)
+  U64x3* off;      // their exclusive prefix
+  int64_t* own;    // weight towards the own community, per hub
+  uint32_t* pcount;   // per partition: entries counted (zero between launches)
+  uint32_t* pcur;     // per partition: scatter cursor (zero between launches)
+  uint64_t* poff;     // per partition: first bucket entry
+  uint32_t* pcnt;     // per partition: bucket entries
+  int64_t* phi;    // partial bests, one per partition
   uint64_t* plo;
   uint32_t* pid;
   int* pvalid;
+  int pshift;      // partitions per hub: ceil(T 2^pshift / kPartEntries), at most ceil(T / 16)
+  uint32_t tslots; // LDS table slots of a partition (power of two <= kPartSlots)
 };
+constexpr uint32_t kPartEntries = 1024;   // target entries per partition (pshift 0)
+constexpr uint32_t kPartSlots = 4096;     // LDS table slots of a partition
+constexpr int kPartShiftMax = 6;
 int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPool hub, HubWork hw, CandBuf cand,
                MoveStats st, void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b);
 

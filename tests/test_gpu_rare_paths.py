@@ -6,6 +6,8 @@ every result bit-identical to the oracle:
   4  no spare adjacency capacity: every insertion moves its row, pools grow under load
   8  the one-workgroup decoupling filter is always queued first: iterations with more candidates
      than it holds run the rounds after the host check and commit everything as a second phase
+ 16  tiny LDS tables for the hub hash partitions: partitions overflow, the iteration is redone with
+     more partitions per hub
 """
 import numpy as np
 import pytest
@@ -15,7 +17,7 @@ from tests.gpucases import run_parity
 
 pytestmark = pytest.mark.gpu
 
-ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST = 1, 2, 4, 8
+ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS = 1, 2, 4, 8, 16
 
 
 def _batches(stream, sizes):
@@ -51,3 +53,19 @@ def test_hub_overflow_and_tight_rows_planted():
              if int(v) != hub and (min(hub, int(v)), max(hub, int(v))) not in have]
     e = np.concatenate([e, np.array(extra, dtype=np.uint32)])
     run_parity(8000, e, _batches(s, [200, 200]), gpu_flags=ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR)
+
+
+@pytest.mark.parametrize("flags", [TINY_PARTITIONS, TINY_PARTITIONS | SMALL_HUB_POOL])
+def test_hub_partition_overflow(flags):
+    # a 5,200-neighbour hub whose hash partitions overflow 64-slot tables until the pass is redone
+    # with more partitions
+    s = synth.Stream(8000, False, synth.BASE_SEED + 430)
+    s.planted(100, 0.08, 0.0005, 1, 8)
+    e = s.edges()
+    rng = np.random.default_rng(11)
+    have = {(int(min(u, v)), int(max(u, v))) for u, v, _ in e}
+    hub = 31
+    extra = [(hub, int(v), int(rng.integers(1, 9))) for v in rng.permutation(8000)[:5200]
+             if int(v) != hub and (min(hub, int(v)), max(hub, int(v))) not in have]
+    e = np.concatenate([e, np.array(extra, dtype=np.uint32)])
+    run_parity(8000, e, _batches(s, [200, 200]), gpu_flags=flags)
