@@ -289,6 +289,92 @@ def run_scan(args):
     print(json.dumps(out), flush=True)
 
 
+def modularity_of(n, edges, labels):
+    """Eq. 1 (undirected, gamma = 1) of a labelling, from the edge list: the reference value of
+    the planted blocks."""
+    import numpy as np
+
+    u, v, w = edges[:, 0].astype(np.int64), edges[:, 1].astype(np.int64), edges[:, 2].astype(np.float64)
+    m2 = 2.0 * w.sum()
+    k = np.bincount(u, w, n) + np.bincount(v, w, n)
+    same = labels[u] == labels[v]
+    ein2 = 2.0 * w[same].sum()
+    K = np.bincount(labels, k)
+    return float(ein2 / m2 - np.sum((K / m2) ** 2))
+
+
+def run_quality(args):
+    """Quality of the batch updates against a full static rerun, on planted partitions with known
+    blocks (synthetic evidence of the kind the paper gives in Tab. IV and Fig. 5).  After every
+    batch: modularity of the incrementally maintained partition and of static Leiden run from
+    scratch on the same graph (a fresh handle of the same library), NMI and ARI of both against the
+    planted blocks, and the GPU time of the update and of the rerun.  Then the per-batch update
+    time over a sweep of average degrees and its log-log slope."""
+    import numpy as np
+    import torch  # noqa: F401
+    from sklearn.metrics import adjusted_rand_score, normalized_mutual_info_score
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    def planted(seed_off, n, d, mu, block=100):
+        s = synth.Stream(n, False, synth.BASE_SEED + seed_off)
+        s.planted(block, min(1.0, (1.0 - mu) * d / (block - 1)), mu * d / (n - block), 1, 8)
+        return s
+
+    n, mu = args.quality_n, args.quality_mu
+    truth = np.arange(n) // 100
+    s = planted(6, n, 16.0, mu)
+    g = ldl.Graph(n, s.edges())
+    rows = []
+    for j in range(args.quality_batches):
+        b = s.batch(args.quality_batch)
+        st = g.apply_batch(b.ins, b.dels, b.chg)
+        e = s.edges()
+        gs = ldl.Graph(n, np.zeros((0, 3), np.uint32))
+        ss = gs.apply_batch(ins=e)   # static Leiden from scratch on the current graph
+        pd, ps = g.partition(), gs.partition()
+        rows.append({"batch": j, "updates": int(b.size), "update_ms": st["total_ms"], "rerun_ms": ss["total_ms"],
+                     "Q_dynamic": g.modularity(), "Q_rerun": gs.modularity(),
+                     "Q_planted": modularity_of(n, e, truth),
+                     "NMI_dynamic": float(normalized_mutual_info_score(truth, pd)),
+                     "NMI_rerun": float(normalized_mutual_info_score(truth, ps)),
+                     "ARI_dynamic": float(adjusted_rand_score(truth, pd)),
+                     "ARI_rerun": float(adjusted_rand_score(truth, ps))})
+        gs.close()
+        log(f"batch {j}: Q {rows[-1]['Q_dynamic']:.4f} vs rerun {rows[-1]['Q_rerun']:.4f}, "
+            f"{rows[-1]['update_ms']:.1f} ms vs {rows[-1]['rerun_ms']:.1f} ms")
+    sweep = []
+    ns = args.quality_sweep_n
+    for d in args.quality_degrees:
+        sd = planted(7, ns, float(d), mu)
+        gd = ldl.Graph(ns, sd.edges())
+        ms = [gd.apply_batch(*(lambda b: (b.ins, b.dels, b.chg))(sd.batch(args.quality_sweep_batch)))["total_ms"]
+              for _ in range(args.quality_sweep_batches)]
+        sweep.append({"avg_degree": d, "edges": sd.num_edges(), "update_ms_median": float(np.median(ms))})
+        gd.close()
+        log(f"degree {d}: median update {sweep[-1]['update_ms_median']:.2f} ms")
+    x = np.log([r["avg_degree"] for r in sweep])
+    y = np.log([r["update_ms_median"] for r in sweep])
+    slope = float(np.polyfit(x, y, 1)[0]) if len(sweep) > 1 else None
+    ratio = [r["Q_dynamic"] / r["Q_rerun"] for r in rows]
+    out = {"metric": "modularity ratio, batch update vs static rerun", "value": float(np.mean(ratio)),
+           "unit": "ratio", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+           "ms_per_step": float(np.mean([r["update_ms"] for r in rows])), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"planted-{n}-blocks-of-100-mu{mu}-degree16-batch{args.quality_batch}",
+                      "n": n, "mixing": mu, "avg_degree": 16, "batch": args.quality_batch},
+           "Q_ratio_min": float(np.min(ratio)),
+           "speedup_vs_rerun": float(np.mean([r["rerun_ms"] / r["update_ms"] for r in rows])),
+           "NMI_dynamic_mean": float(np.mean([r["NMI_dynamic"] for r in rows])),
+           "NMI_rerun_mean": float(np.mean([r["NMI_rerun"] for r in rows])),
+           "ARI_dynamic_mean": float(np.mean([r["ARI_dynamic"] for r in rows])),
+           "ARI_rerun_mean": float(np.mean([r["ARI_rerun"] for r in rows])),
+           "degree_sweep": {"n": ns, "batch": args.quality_sweep_batch, "points": sweep},
+           "time_vs_degree_loglog_slope": slope, "batches": rows}
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of a known size (torch's copy kernel),
     repeated a few times; rocprofv3 FETCH_SIZE / WRITE_SIZE of these dispatches give the factor
@@ -318,7 +404,15 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
-    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan"], default="rmat")
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality"], default="rmat")
+    ap.add_argument("--quality-n", type=int, default=20000)
+    ap.add_argument("--quality-mu", type=float, default=0.3)
+    ap.add_argument("--quality-batch", type=int, default=500)
+    ap.add_argument("--quality-batches", type=int, default=20)
+    ap.add_argument("--quality-degrees", type=int, nargs="+", default=[4, 8, 16, 32, 64])
+    ap.add_argument("--quality-sweep-batches", type=int, default=10)
+    ap.add_argument("--quality-sweep-n", type=int, default=200000)
+    ap.add_argument("--quality-sweep-batch", type=int, default=5000)
     ap.add_argument("--avg-degree", type=int, default=16)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--graphs", type=int, default=64)
@@ -344,6 +438,8 @@ def main():
         return run_copy(args)
     if args.workload == "scan":
         return run_scan(args)
+    if args.workload == "quality":
+        return run_quality(args)
 
     import numpy as np
     import torch

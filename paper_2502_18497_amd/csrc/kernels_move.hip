@@ -1048,8 +1048,8 @@ __global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_
 template <typename WT, bool DIR, bool REF>
 int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, HubWork hw, CandBuf cand, MoveStats st,
                  void** tmp, size_t* tmp_bytes, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
-  k_hub_size<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(mv, br, bound, hw.pshift, hw.cnt, hw.own,
-                                                            hub.over_count);
+  k_hub_size<<<cap_blocks(grid_for((uint64_t)bound + 1), LDL_RESIDENT(k_hub_size, kTpb)), kTpb, 0, s>>>(
+      mv, br, bound, hw.pshift, hw.cnt, hw.own, hub.over_count);
   const int rc = prim_exclusive_sum_u64x3(tmp, tmp_bytes, hw.cnt, hw.off, (uint64_t)bound + 1, s);
   if (rc) return rc;
   if (ev_a) (void)hipEventRecord(ev_a, s);
@@ -1061,8 +1061,8 @@ int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, Hub
                                 0, s>>>(mv, br, bound, hw.off, hub, hw);
   k_hub_part<DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_part<DIR, REF>), kTpb)), kTpb, 0, s>>>(
       mv, br, bound, hw.off, hub, hw, st);
-  k_hub_final<REF><<<grid_waves(bound), kTpb, 0, s>>>(br, bound, hw.off, hub.cap, mv.lab, hw.phi, hw.plo, hw.pid,
-                                                      hw.pvalid, cand, st, hub.top, hub.over_count);
+  k_hub_final<REF><<<cap_blocks(grid_waves(bound), LDL_RESIDENT(k_hub_final<REF>, kTpb)), kTpb, 0, s>>>(
+      br, bound, hw.off, hub.cap, mv.lab, hw.phi, hw.plo, hw.pid, hw.pvalid, cand, st, hub.top, hub.over_count);
   return 0;
 }
 
