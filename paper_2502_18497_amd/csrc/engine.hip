@@ -193,7 +193,7 @@ struct Engine {
   uint64_t* holebuf = nullptr;
   uint32_t* movelist = nullptr;
   uint64_t* seg_lo = nullptr;
-  uint64_t *seg_hi = nullptr, *items = nullptr, *item_off = nullptr;
+  uint64_t *seg_hi = nullptr, *items = nullptr, *item_off = nullptr, *items_big = nullptr, *item_off_big = nullptr;
   int64_t* slotbuf = nullptr;
   int64_t* rslot = nullptr;
   uint64_t ins_cap = 0;
@@ -493,6 +493,8 @@ struct Engine {
     regrow(seg_hi, c);
     regrow(items, c + 1);
     regrow(item_off, c + 1);
+    regrow(items_big, c + 1);
+    regrow(item_off_big, c + 1);
     regrow(slotbuf, c);
     ins_cap = c;
   }
@@ -552,7 +554,8 @@ struct Engine {
     if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
     ensure_insflag(k);
     cub(prim_select_heads(&cub_tmp, &cub_bytes, keys, k, id_bits, seg_lo, &ds->nseg, st));
-    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, slotbuf, &cub_tmp, &cub_bytes, id_bits, st);
+    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big, slotbuf,
+                      &cub_tmp, &cub_bytes, id_bits, st);
     hcheck(hipMemsetAsync(&ds->nmove, 0, 2 * sizeof(uint32_t), st));   // nmove, overflow
     launch_seg_update(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, holebuf, deg_arr, rowdel,
                       rowins, movelist, &ds->nmove, id_bits, st);
@@ -671,7 +674,8 @@ struct Engine {
     if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
     ensure_insflag(K);
     cub(prim_select_heads(&cub_tmp, &cub_bytes, rkey1, K, id_bits, seg_lo, &ds->nseg, st));
-    launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, rslot, &cub_tmp, &cub_bytes,
+    launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big, rslot,
+                      &cub_tmp, &cub_bytes,
                       id_bits, st);
     launch_ingest_validate(V0.out.ref, rkey1, ridx1, rslot, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
                            &ds->first_bad, &ds->dm, id_bits, st);

@@ -92,21 +92,26 @@ __global__ void k_set_add_mapped(SetRef set, const uint32_t* list, uint32_t coun
 // Row segments of sorted record keys: one entry (first record index) per distinct row.
 __device__ uint64_t lower_bound_u64(const uint64_t* a, uint64_t n, uint64_t key);
 
-// ---- row lookup of sorted records.  The records of one row (a segment, up to kSegChunk at a
-// time) go into an LDS hash table keyed by column and the row is streamed once, each entry
-// probing the table: O(degree + records) per row.  Work items are (segment, record chunk, row
-// slice) and each wavefront takes items on its own, so a huge row is streamed by many
-// wavefronts and a small one costs one wavefront pass without workgroup barriers.
-constexpr uint32_t kSegChunk = 512;     // records per item
-constexpr uint32_t kSlice = 4096;       // row entries per item
+// ---- row lookup of sorted records.  The records of one row (a segment) go into an LDS hash
+// table keyed by column and the row is streamed once per table, each entry probing it.  A
+// segment of at most kSegChunk records is one table: its work items are (segment, row slice of
+// kSlice entries), each taken by a single wavefront without workgroup barriers.  A longer
+// segment is cut into tables of kBigChunk records, each streamed over the row by a 256-lane
+// workgroup in slices of kBigSlice entries: O(degree x records / kBigChunk + records) per row.
+constexpr uint32_t kSegChunk = 512;     // records of a wavefront table
+constexpr uint32_t kSlice = 4096;       // row entries per wavefront item
 constexpr uint32_t kSegSlots = 2 * kSegChunk;
+constexpr uint32_t kBigChunk = 4096;    // records of a workgroup table
+constexpr uint32_t kBigSlice = 16384;   // row entries per workgroup item
 
 __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo,
-                            const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items, int ks) {
+                            const uint32_t* nseg_ptr, uint64_t* seg_hi, uint64_t* items, uint64_t* items_big,
+                            int ks) {
   const uint32_t nseg = *nseg_ptr;
   for (uint64_t s = gtid(); s <= k; s += gstride()) {
     if (s >= nseg) {
       items[s] = 0;
+      items_big[s] = 0;
       continue;
     }
     const uint64_t lo = seg_lo[s];
@@ -114,9 +119,13 @@ __global__ void k_seg_items(CsrRef c, const uint64_t* keys, uint64_t k, const ui
     const uint64_t hi = s + 1 < nseg ? seg_lo[s + 1] : k;   // heads are selected in key order
     seg_hi[s] = hi;
     const uint64_t deg = c.deg[row];
-    const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
-    const uint64_t nrc = (hi - lo + kSegChunk - 1) / kSegChunk;
-    items[s] = nsl * nrc;
+    if (hi - lo <= kSegChunk) {
+      items[s] = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
+      items_big[s] = 0;
+    } else {
+      items[s] = 0;
+      items_big[s] = (deg == 0 ? 1 : (deg + kBigSlice - 1) / kBigSlice) * ((hi - lo + kBigChunk - 1) / kBigChunk);
+    }
   }
 }
 
@@ -153,14 +162,12 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
   const uint64_t total = item_off[nseg];
   for (uint64_t it = gwave(); it < total; it += gwstride()) {
     const uint32_t sg = wave_owner(item_off, nseg, it);
-    const uint64_t sub = it - item_off[sg];
+    const uint64_t sl = it - item_off[sg];
     const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
     const uint32_t row = krow(keys[lo], ks);
     const uint64_t deg = c.deg[row];
-    const uint64_t nsl = deg == 0 ? 1 : (deg + kSlice - 1) / kSlice;
-    const uint64_t rc = sub / nsl, sl = sub % nsl;
-    const uint64_t clo = lo + rc * kSegChunk;
-    const uint32_t kk = (uint32_t)((hi - clo) < (uint64_t)kSegChunk ? (hi - clo) : (uint64_t)kSegChunk);
+    const uint64_t clo = lo;
+    const uint32_t kk = (uint32_t)(hi - lo);   // at most kSegChunk (small segment)
     uint32_t size = 64;
     while (size < 2 * kk) size <<= 1;
     const uint32_t mask = size - 1;
@@ -196,6 +203,63 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
       }
     }
     wave_sync();   // table reads done before the next item clears it
+  }
+}
+
+// workgroup per big-segment item: LDS table of a kBigChunk-record chunk, stream one row slice
+__global__ __launch_bounds__(256) void k_seg_lookup_big(CsrRef c, const uint64_t* keys, uint64_t k,
+                                                        const uint64_t* seg_lo, const uint64_t* seg_hi,
+                                                        const uint32_t* nseg_ptr, const uint64_t* item_off,
+                                                        int64_t* slot_out, int ks) {
+  __shared__ uint32_t tkey[2 * kBigChunk];
+  __shared__ uint32_t tval[2 * kBigChunk];
+  const uint32_t nseg = *nseg_ptr;
+  const uint64_t total = item_off[nseg];
+  for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const uint32_t sg = wave_owner(item_off, nseg, it);   // every wavefront finds the same segment
+    const uint64_t sub = it - item_off[sg];
+    const uint64_t lo = seg_lo[sg], hi = seg_hi[sg];
+    const uint32_t row = krow(keys[lo], ks);
+    const uint64_t deg = c.deg[row];
+    const uint64_t nsl = deg == 0 ? 1 : (deg + kBigSlice - 1) / kBigSlice;
+    const uint64_t rc = sub / nsl, sl = sub % nsl;
+    const uint64_t clo = lo + rc * kBigChunk;
+    const uint32_t kk = (uint32_t)((hi - clo) < (uint64_t)kBigChunk ? (hi - clo) : (uint64_t)kBigChunk);
+    uint32_t size = 64;
+    while (size < 2 * kk) size <<= 1;
+    const uint32_t mask = size - 1;
+    for (uint32_t i = threadIdx.x; i < size; i += blockDim.x) tkey[i] = kEmpty;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kk; i += blockDim.x) {
+      const uint32_t col = kcol(keys[clo + i], ks);
+      uint32_t h = hash32(col) & mask;
+      for (;;) {
+        const uint32_t prev = atomicCAS(&tkey[h], kEmpty, col);
+        if (prev == kEmpty) {
+          tval[h] = i;
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+    }
+    __syncthreads();
+    const uint64_t off = c.off[row];
+    const uint64_t e0 = sl * kBigSlice;
+    const uint64_t e1 = e0 + kBigSlice < deg ? e0 + kBigSlice : deg;
+    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
+      const uint32_t x = c.nbr[off + j];
+      uint32_t h = hash32(x) & mask;
+      for (;;) {
+        const uint32_t kx = tkey[h];
+        if (kx == kEmpty) break;
+        if (kx == x) {
+          slot_out[clo + tval[h]] = (int64_t)(off + j);
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1197,14 +1261,20 @@ void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* i
                                                    err, first_bad, dm, ks);
 }
 void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
-                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
-                       size_t* tmp_bytes, int ks, hipStream_t s) {
+                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, uint64_t* items_big,
+                       uint64_t* item_off_big, int64_t* slot_out, void** tmp, size_t* tmp_bytes, int ks,
+                       hipStream_t s) {
   if (!k) return;
-  k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items, ks);
+  k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items, items_big, ks);
   prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
   k_fill_i64_dev<<<grid_for(k), kTpb, 0, s>>>(slot_out, -1, k);
   const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_lookup, 256));
   k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out, ks);
+  if (k > kSegChunk) {   // a segment above the wavefront limit exists only then
+    prim_exclusive_sum_u64(tmp, tmp_bytes, items_big, item_off_big, k + 1, s);
+    const unsigned gb = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_lookup_big, 256));
+    k_seg_lookup_big<<<gb, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off_big, slot_out, ks);
+  }
 }
 void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                        const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,

@@ -150,8 +150,9 @@ void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bou
 // every record (or -1).  Segments (first record of each row, ascending) come from
 // prim_select_heads.
 void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
-                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, int64_t* slot_out, void** tmp,
-                       size_t* tmp_bytes, int ks, hipStream_t s);
+                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, uint64_t* items_big,
+                       uint64_t* item_off_big, int64_t* slot_out, void** tmp, size_t* tmp_bytes, int ks,
+                       hipStream_t s);
 // in-place row update (record types into rtype, hole scratch of k words; optional row delta
 // sums added to deg_arr); rows that outgrow their capacity are listed for launch_seg_move,
 // which takes new regions from the pool (bit 0 of *overflow when full: grow, launch again)
