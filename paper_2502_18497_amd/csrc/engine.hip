@@ -283,10 +283,11 @@ struct Engine {
 
   i128 qnum() const { return (i128)gq * m * Ein - (i128)gp * SKK; }
 
-  // list of a marked set: ids with stamp == epoch, ascending, count into the set's counter
+  // list of a marked set: ids with stamp == epoch (list order carries no meaning), count into the
+  // set's counter
   void select_set(int id) {
     HSet& s = sets[id];
-    cub(prim_select_stamp(&cub_tmp, &cub_bytes, s.stamp, s.epoch, n, s.list, &ds->counts[s.ci], st));
+    launch_select_stamp(s.stamp, s.epoch, n, s.list, &ds->counts[s.ci], st);
   }
 
   // per-node tuple counts over the list of set `sid` (k nodes) and their exclusive prefix

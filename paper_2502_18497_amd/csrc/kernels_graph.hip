@@ -1187,7 +1187,72 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
 
 }  // namespace
 
+// ids x < n with stamp[x] == ep appended to list (ascending within each 4096-id chunk, chunks in
+// any order), one global atomic per chunk; *count must be 0 at launch
+constexpr uint32_t kSelChunk = 4096;
+__global__ __launch_bounds__(kTpb) void k_select_stamp(const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* list,
+                                                       uint32_t* count) {
+  constexpr uint32_t PER = kSelChunk / kTpb;
+  __shared__ uint32_t wsum[kTpb / kWave];
+  __shared__ uint32_t s_base;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (uint64_t c0 = (uint64_t)blockIdx.x * kSelChunk; c0 < n; c0 += (uint64_t)gridDim.x * kSelChunk) {
+    // thread t owns ids c0 + t*PER .. + PER (contiguous, so the chunk's output stays ascending)
+    const uint64_t b = c0 + (uint64_t)threadIdx.x * PER;
+    uint32_t sv[PER];
+    if (b + PER <= n) {   // 64 contiguous bytes per lane (b is a multiple of 16 ids)
+      const uint4* p4 = reinterpret_cast<const uint4*>(stamp + b);
+#pragma unroll
+      for (uint32_t k = 0; k < PER / 4; ++k) {
+        const uint4 v4 = p4[k];
+        sv[4 * k] = v4.x;
+        sv[4 * k + 1] = v4.y;
+        sv[4 * k + 2] = v4.z;
+        sv[4 * k + 3] = v4.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t q = 0; q < PER; ++q) sv[q] = b + q < n ? stamp[b + q] : ~ep;
+    }
+    uint32_t mine = 0;
+    uint32_t flags = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+      const bool f = sv[q] == ep;
+      flags |= (f ? 1u : 0u) << q;
+      mine += f ? 1u : 0u;
+    }
+    uint32_t incl = mine;   // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t t = (uint32_t)__shfl_up((int)incl, o, kWave);
+      if (lane >= o) incl += t;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int k = 0; k < kTpb / kWave; ++k) {
+      if (k < w) before += wsum[k];
+      total += wsum[k];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(count, total) : 0u;
+    __syncthreads();
+    uint32_t at = s_base + before + incl - mine;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q)
+      if (flags & (1u << q)) list[at++] = (uint32_t)(b + q);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ launchers
+void launch_select_stamp(const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* list, uint32_t* count,
+                         hipStream_t s) {
+  (void)hipMemsetAsync(count, 0, sizeof(uint32_t), s);
+  if (n)
+    k_select_stamp<<<cap_blocks((n + kSelChunk - 1) / kSelChunk, LDL_RESIDENT(k_select_stamp, kTpb)), kTpb, 0, s>>>(
+        stamp, ep, n, list, count);
+}
 
 void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t* alive, const uint32_t* key,
                          const uint32_t* mark, uint32_t mark_ep, hipStream_t s) {

@@ -192,6 +192,9 @@ void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, c
 // cascade: (x,y) <- (par[x], par[y]); keys rebuilt; both endpoints seeded
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
                         uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s);
+// list = ids x < n with stamp[x] == ep (ascending within 4096-id chunks), count into *count
+void launch_select_stamp(const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* list, uint32_t* count,
+                         hipStream_t s);
 void launch_split_keys(const uint64_t* keys, uint64_t k, uint32_t* ex, uint32_t* ey, int ks, hipStream_t s);
 // kout[row] += d for every record (row, col, d); kin[col] += d as well when kin_or_null is given
 void launch_record_degrees(const uint64_t* keys, const int64_t* vals, uint64_t k, int64_t* kout, int64_t* kin_or_null,
