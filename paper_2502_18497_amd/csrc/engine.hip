@@ -292,13 +292,12 @@ struct Engine {
 
   // per-node tuple counts over the list of set `sid` (k nodes) and their exclusive prefix
   // (toffs); returns the tuple total and grows the tuple buffers
-  uint64_t tuple_offsets(int sid, uint32_t k, CsrRef out, CsrRef in, const uint32_t* cstamp, uint32_t cep,
-                         int repair) {
+  uint64_t tuple_offsets(int sid, uint32_t k, CsrRef out, CsrRef in, const uint2* po, int repair) {
     if (k == 0) return 0;
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
     cub(launch_items(list, nullptr, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
-    launch_tuples_count(list, cnt, k, it_off, out, in, cstamp, cep, repair, (u64a*)tcounts, st);
+    launch_tuples_count(list, cnt, k, it_off, out, in, po, repair, (u64a*)tcounts, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
     uint64_t T = 0;
     hcheck(hipMemcpyAsync(&T, toffs + k, 8, hipMemcpyDeviceToHost, st));
@@ -1107,14 +1106,18 @@ struct Engine {
     const uint32_t nC = count(S_C);
     CsrRef in = directed ? V.in.ref : V.out.ref;
     const int Dn = S_D0 + r + 1;
-    const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, sets[S_C].stamp, sets[S_C].epoch, 1);
+    // both parents of every node in one word for the tuple kernels (lpk's storage is free here:
+    // refinement of this level has finished)
+    uint2* po = lpk;
+    launch_pack_parents(n, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, po, st);
+    const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, po, 1);
     // the tuples are written straight into the deferred records of level r+1
     pend_reserve(r + 1, T);
     PendBuf& pn = pend[r + 1];
     if (nC)
-      launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, oldpar,
-                        sets[S_C].stamp, sets[S_C].epoch, 1, toffs, (u64a*)tcur, pn.keys + pn.count,
-                        pn.vals + pn.count, sets[Dn].stamp, sets[Dn].epoch, id_bits, st);
+      launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, po, 1, toffs,
+                        (u64a*)tcur, pn.keys + pn.count, pn.vals + pn.count, sets[Dn].stamp, sets[Dn].epoch, id_bits,
+                        st);
     pn.count += T;
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
@@ -1161,10 +1164,10 @@ struct Engine {
     launch_alive_list(n, V.alive, ref(S_TMP), st);
     sync_read();
     const uint32_t na = count(S_TMP);
-    const uint64_t T = tuple_offsets(S_TMP, na, V.out.ref, CsrRef{}, nullptr, 0, 0);
+    const uint64_t T = tuple_offsets(S_TMP, na, V.out.ref, CsrRef{}, nullptr, 0);
     if (na)
-      launch_tuples_gen(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], na, it_off, V.out.ref, CsrRef{}, V.par,
-                        nullptr, nullptr, 0, 0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, id_bits, st);
+      launch_tuples_gen(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], na, it_off, V.out.ref, CsrRef{}, V.par, nullptr,
+                        0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, id_bits, st);
     const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
     hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
     hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));

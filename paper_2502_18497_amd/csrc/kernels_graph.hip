@@ -1066,9 +1066,19 @@ __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list,
 // keeps its parent); for an in entry (v, u) with v outside C, (par v, oldpar u) loses w and
 // (par v, par u) gains it (entries between two C nodes come from the out side).  Node i's
 // tuples start at toffs[i]: out tuples in entry order, then in tuples at a per-node cursor.
+// po[x] = (pi(x), old pi(x) if x changed parent else pi(x)): the neighbour's both parents in one
+// gather for the repair tuples (x changed iff the two differ)
+__global__ void k_pack_parents(uint32_t n, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp,
+                               uint32_t cep, uint2* po) {
+  for (uint64_t x = gtid(); x < n; x += gstride()) {
+    const uint32_t p = par[x];
+    po[x] = make_uint2(p, cstamp[x] == cep ? oldpar[x] : p);
+  }
+}
+
 template <bool REPAIR>
 __global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
-                               CsrRef out, CsrRef in, const uint32_t* cstamp, uint32_t cep, u64a* counts) {
+                               CsrRef out, CsrRef in, const uint2* po, u64a* counts) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
@@ -1079,8 +1089,12 @@ __global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uin
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
     int64_t c = 0;
     for (uint64_t j = j0 + lane; j < j1; j += kWave) {
-      if (j < dout) c += REPAIR ? 2 : 1;
-      else if (cstamp[in.nbr[in.off[u] + (j - dout)]] != cep) c += 2;
+      if (j < dout) {
+        c += REPAIR ? 2 : 1;
+      } else {
+        const uint2 q2 = po[in.nbr[in.off[u] + (j - dout)]];
+        if (q2.x == q2.y) c += 2;   // the neighbour keeps its parent
+      }
     }
     c = wave_sum_i64(c);
     if (lane == 0 && c) atomicAdd(&counts[i], (u64a)c);
@@ -1089,16 +1103,22 @@ __global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uin
 
 template <bool REPAIR>
 __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
-                             CsrRef out, CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp,
-                             uint32_t cep, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                             uint32_t* seed_stamp, uint32_t seed_ep, int ks) {
+                             CsrRef out, CsrRef in, const uint32_t* par, const uint2* po, const uint64_t* toffs,
+                             u64a* cur, uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep,
+                             int ks) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
   wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
     const uint32_t u = list[i];
-    const uint32_t pu = par[u];
-    const uint32_t ou = REPAIR ? oldpar[u] : pu;
+    uint32_t pu, ou;
+    if (REPAIR) {
+      const uint2 qu = po[u];
+      pu = qu.x;
+      ou = qu.y;
+    } else {
+      pu = ou = par[u];
+    }
     const uint32_t dout = out.deg[u];
     const uint64_t s = node_slots(out, in, u);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
@@ -1113,13 +1133,15 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
       uint32_t x = 0;
       int64_t w = 0;
       if (valid) node_entry(out, in, u, dout, j, x, w);
+      uint2 qx = make_uint2(0u, 0u);
+      if (REPAIR && valid) qx = po[x];
       if (valid && j < dout) {
-        const uint32_t px = par[x];
         if (!REPAIR) {
+          const uint32_t px = par[x];
           tkeys[base + j] = kpack(pu, px, ks);
           tvals[base + j] = w;
         } else {
-          const uint32_t ox = cstamp[x] == cep ? oldpar[x] : px;
+          const uint32_t px = qx.x, ox = qx.y;
           tkeys[base + 2 * j] = kpack(ou, ox, ks);
           tvals[base + 2 * j] = -w;
           tkeys[base + 2 * j + 1] = kpack(pu, px, ks);
@@ -1129,7 +1151,7 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
         }
       }
       if (REPAIR && jb + kWave > dout) {
-        const bool act = valid && j >= dout && cstamp[x] != cep;
+        const bool act = valid && j >= dout && qx.x == qx.y;   // neighbour keeps its parent
         const uint64_t m = __ballot(act);
         if (m) {
           const uint32_t tot = (uint32_t)__popcll(m);
@@ -1140,7 +1162,7 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
           const uint32_t bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
           b = ((u64a)bhi << 32) | blo;
           if (act) {
-            const uint32_t pv = par[x];
+            const uint32_t pv = qx.x;
             const uint64_t p2 = base + 2ull * dout + b + 2ull * r;
             tkeys[p2] = kpack(pv, ou, ks);
             tvals[p2] = -w;
@@ -1279,21 +1301,24 @@ void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const
                        const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s) {
   k_mark_items<<<kItemBlocks, kTpb, 0, s>>>(stamp, ep, list, count, bound, ioff, out, in);
 }
+void launch_pack_parents(uint32_t n, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
+                         uint2* po, hipStream_t s) {
+  if (n) k_pack_parents<<<grid_for(n), kTpb, 0, s>>>(n, par, oldpar, cstamp, cep, po);
+}
 void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
-                         CsrRef in, const uint32_t* cstamp, uint32_t cep, int repair, u64a* counts, hipStream_t s) {
-  if (repair) k_tuples_count<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, cstamp, cep, counts);
-  else k_tuples_count<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, cstamp, cep, counts);
+                         CsrRef in, const uint2* po, int repair, u64a* counts, hipStream_t s) {
+  if (repair) k_tuples_count<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, po, counts);
+  else k_tuples_count<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, po, counts);
 }
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
-                       CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
-                       int repair, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                       uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s) {
+                       CsrRef in, const uint32_t* par, const uint2* po, int repair, const uint64_t* toffs, u64a* cur,
+                       uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s) {
   if (repair)
-    k_tuples_gen<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
-                                                    cur, tkeys, tvals, seed_stamp, seed_ep, ks);
+    k_tuples_gen<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur, tkeys, tvals,
+                                                    seed_stamp, seed_ep, ks);
   else
-    k_tuples_gen<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, oldpar, cstamp, cep, toffs,
-                                                     cur, tkeys, tvals, seed_stamp, seed_ep, ks);
+    k_tuples_gen<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur, tkeys,
+                                                     tvals, seed_stamp, seed_ep, ks);
 }
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n) k_fill_u32<<<grid_for(n), kTpb, 0, s>>>(p, v, n);

@@ -136,12 +136,15 @@ void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const
 // subtract-add tuples over items: per-node counts (added into zeroed counts), then tuples at
 // toffs (the exclusive prefix of counts) with a zeroed per-node cursor; seeds marked by
 // plain stores (seed_stamp may be null when not repairing)
+// po[x] = (par[x], cstamp[x] == cep ? oldpar[x] : par[x]) for x < n
+void launch_pack_parents(uint32_t n, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
+                         uint2* po, hipStream_t s);
+// (repair: a neighbour x changed parent iff po[x].x != po[x].y; otherwise po is unused)
 void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
-                         CsrRef in, const uint32_t* cstamp, uint32_t cep, int repair, u64a* counts, hipStream_t s);
+                         CsrRef in, const uint2* po, int repair, u64a* counts, hipStream_t s);
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
-                       CsrRef in, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
-                       int repair, const uint64_t* toffs, u64a* cur, uint64_t* tkeys, int64_t* tvals,
-                       uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s);
+                       CsrRef in, const uint32_t* par, const uint2* po, int repair, const uint64_t* toffs, u64a* cur,
+                       uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s);
 
 // ---------------------------------------------------------------- dynamic CSR
 // Records sorted by key = row << ks | col (ks = bits of a vertex id) with deltas; zero deltas
