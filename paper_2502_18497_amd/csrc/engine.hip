@@ -781,11 +781,10 @@ struct Engine {
       std::pair<hipEvent_t, hipEvent_t> ev{};
       if (profile) ev = next_events();
       if (b < kNumBins - 1) {
-        if (profile) hcheck(hipEventRecord(ev.first, st));
-        launch_best(mv, b, br, n, refine, cand, ms, st);
-        if (profile) hcheck(hipEventRecord(ev.second, st));
+        // with profiling, the events are attached to the kernel's dispatch
+        launch_best(mv, b, br, n, refine, cand, ms, st, profile ? ev.first : nullptr, profile ? ev.second : nullptr);
       } else {
-        // hubs: the events bracket the table-insert kernel, which reads the entries
+        // hubs: the events time the keys pass, which reads the entries and their labels
         cub(launch_hub(mv, br, hb, refine, hub, hw, cand, ms, &cub_tmp, &cub_bytes, st, profile ? ev.first : nullptr,
                        profile ? ev.second : nullptr));
       }

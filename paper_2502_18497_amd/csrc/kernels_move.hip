@@ -14,6 +14,8 @@
 // Vertices are binned by their entry count T: groups of 8 or 32 lanes hold one entry per
 // lane and sum equal keys with lane shuffles; wavefront and workgroup teams accumulate in an
 // LDS hash table; hubs use a workgroup with a hash table in global memory.
+#include <hip/hip_ext.h>
+
 #include "ldl_dev.h"
 #include "ldl_kernels.h"
 
@@ -222,6 +224,15 @@ __global__ void k_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32
 // are kept in registers until the block exits, so global atomics on the shared counters are
 // a handful per workgroup rather than several per wavefront.
 constexpr unsigned kPersistBlocks = 2048;
+
+// Launch with the optional start / stop events attached to the kernel's own dispatch, so that
+// their elapsed time is the kernel's execution time and not the gaps around it.
+template <typename... KArgs, typename... Args>
+inline void launch_timed(void (*kern)(KArgs...), unsigned grid, hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b,
+                         Args... args) {
+  if (ev_a) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kTpb), 0, s, ev_a, ev_b, 0, args...);
+  else hipLaunchKernelGGL(kern, dim3(grid), dim3(kTpb), 0, s, args...);
+}
 
 template <int CAP>
 struct Stage {
@@ -1052,10 +1063,8 @@ int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, Hub
       mv, br, bound, hw.pshift, hw.cnt, hw.own, hub.over_count);
   const int rc = prim_exclusive_sum_u64x3(tmp, tmp_bytes, hw.cnt, hw.off, (uint64_t)bound + 1, s);
   if (rc) return rc;
-  if (ev_a) (void)hipEventRecord(ev_a, s);
-  k_hub_keys<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_keys<WT, DIR, REF>), kTpb)), kTpb, 0,
-                             s>>>(mv, br, bound, hw.off, hub, hw, st);
-  if (ev_b) (void)hipEventRecord(ev_b, s);
+  launch_timed(k_hub_keys<WT, DIR, REF>, cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_keys<WT, DIR, REF>), kTpb)), s,
+               ev_a, ev_b, mv, br, bound, (const U64x3*)hw.off, hub, hw, st);
   k_hub_poff<<<cap_blocks(bound, LDL_RESIDENT(k_hub_poff, kTpb)), kTpb, 0, s>>>(br, bound, hw.off, hub, hw);
   k_hub_scatter<WT, DIR, REF><<<cap_blocks(kPersistBlocks, LDL_RESIDENT((k_hub_scatter<WT, DIR, REF>), kTpb)), kTpb,
                                 0, s>>>(mv, br, bound, hw.off, hub, hw);
@@ -1068,33 +1077,33 @@ int hub_dispatch(const MoveView& mv, BinRef br, uint32_t bound, HubPool hub, Hub
 
 template <typename WT, bool DIR, bool REF>
 void best_dispatch(const MoveView& mv, int bin, BinRef br, uint32_t max_count, CandBuf cand, MoveStats st,
-                   hipStream_t s) {
+                   hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
   const uint64_t c = max_count;
   switch (bin) {
     case 0:
-      k_best_group<WT, 8, DIR, REF>
-          <<<cap_blocks((c + 31) / 32, LDL_RESIDENT((k_best_group<WT, 8, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
-                                                                                                      cand, st);
+      launch_timed(k_best_group<WT, 8, DIR, REF>,
+                   cap_blocks((c + 31) / 32, LDL_RESIDENT((k_best_group<WT, 8, DIR, REF>), kTpb)), s, ev_a, ev_b, mv,
+                   br, cand, st);
       break;
     case 1:
-      k_best_group<WT, 32, DIR, REF>
-          <<<cap_blocks((c + 7) / 8, LDL_RESIDENT((k_best_group<WT, 32, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
-                                                                                                      cand, st);
+      launch_timed(k_best_group<WT, 32, DIR, REF>,
+                   cap_blocks((c + 7) / 8, LDL_RESIDENT((k_best_group<WT, 32, DIR, REF>), kTpb)), s, ev_a, ev_b, mv,
+                   br, cand, st);
       break;
     case 2:
-      k_best_wave<WT, 256, DIR, REF>
-          <<<cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 256, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
-                                                                                                      cand, st);
+      launch_timed(k_best_wave<WT, 256, DIR, REF>,
+                   cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 256, DIR, REF>), kTpb)), s, ev_a, ev_b, mv,
+                   br, cand, st);
       break;
     case 3:
-      k_best_wave<WT, 1024, DIR, REF>
-          <<<cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 1024, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br,
-                                                                                                       cand, st);
+      launch_timed(k_best_wave<WT, 1024, DIR, REF>,
+                   cap_blocks((c + 3) / 4, LDL_RESIDENT((k_best_wave<WT, 1024, DIR, REF>), kTpb)), s, ev_a, ev_b, mv,
+                   br, cand, st);
       break;
     default:
-      k_best_hash<WT, 256, 4096, DIR, REF>
-          <<<cap_blocks(c, LDL_RESIDENT((k_best_hash<WT, 256, 4096, DIR, REF>), kTpb)), kTpb, 0, s>>>(mv, br, cand,
-                                                                                                  st);
+      launch_timed(k_best_hash<WT, 256, 4096, DIR, REF>,
+                   cap_blocks(c, LDL_RESIDENT((k_best_hash<WT, 256, 4096, DIR, REF>), kTpb)), s, ev_a, ev_b, mv, br,
+                   cand, st);
   }
 }
 
@@ -1489,9 +1498,9 @@ void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* ac
   } while (0)
 
 void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int refine, CandBuf cand, MoveStats st,
-                 hipStream_t s) {
+                 hipStream_t s, hipEvent_t ev_a, hipEvent_t ev_b) {
   if (!max_count) return;
-#define LDL_BEST(WT, D, R) best_dispatch<WT, D, R>(mv, bin, br, max_count, cand, st, s)
+#define LDL_BEST(WT, D, R) best_dispatch<WT, D, R>(mv, bin, br, max_count, cand, st, s, ev_a, ev_b)
   LDL_TYPED(LDL_BEST);
 #undef LDL_BEST
 }

@@ -207,7 +207,7 @@ void launch_transpose_keys(const uint64_t* keys, uint64_t* tkeys, uint64_t k, in
 // ---------------------------------------------------------------- local move / refinement
 // candidate kernels of degree bins 0..kNumBins-2 over a device-resident bin list
 void launch_best(const MoveView& mv, int bin, BinRef br, uint32_t max_count, int refine, CandBuf cand, MoveStats st,
-                 hipStream_t s);
+                 hipStream_t s, hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr);
 // hub bin, device driven: per-hub entry counts, chunk items and hash partitions are prefix-summed
 // over `bound` + 1 entries (bound >= number of hubs); hubs whose entries do not fit the pool are
 // skipped and flagged.  Work arrays hold bound + 1 entries, partition arrays cap / 16 + bound + 1.
