@@ -256,12 +256,17 @@ def run_scan(args):
     t0 = time.perf_counter()
     n, e = rmat_directed_device(args.scale, args.avg_degree << args.scale, synth.BASE_SEED + 3, "cuda")
     torch.cuda.synchronize()
-    log(f"generated directed R-MAT scale {args.scale}: n={n} edges={e.shape[0]} in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.empty_cache()   # the generator's temporaries go back to the device for the library
+    log(f"generated directed R-MAT scale {args.scale}: n={n} edges={e.shape[0]} in {time.perf_counter() - t0:.1f}s; "
+        f"device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
     g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=True, L=0, N=1, M=1, profile=True)
+    log(f"graph handle created; device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
     t0 = time.perf_counter()
     st = g.apply_batch_device(e, None, None)
     torch.cuda.synchronize()
-    log(f"ingest + one full-frontier iteration in {time.perf_counter() - t0:.2f}s (GPU {st['total_ms']:.1f} ms)")
+    free_after = torch.cuda.mem_get_info()[0]
+    log(f"ingest + one full-frontier iteration in {time.perf_counter() - t0:.2f}s (GPU {st['total_ms']:.1f} ms); "
+        f"device memory free {free_after / 2**30:.1f} GiB")
     ms, by = np.array(st["bin_ms"]), np.array(st["bin_bytes"])
     ent, lau = np.array(st["bin_entries"]), np.array(st["bin_launches"])
     dom = int(np.argmax(ms))
@@ -282,6 +287,7 @@ def run_scan(args):
                         "frac": achieved / HBM_PEAK_GBS, "kernel": ldl.candidate_kernel_name(dom, True),
                         "launches": int(lau[dom]), "avg_launch_us": float(1e3 * ms[dom] / max(1, lau[dom])),
                         "bytes_per_launch": float(by[dom] / max(1, lau[dom]))},
+           "load_and_iteration_ms": float(st["total_ms"]),
            "scanned_entries": int(st["scanned_entries"]),
            "frontier_entries_per_s": float(st["scanned_entries"] / (st["search_ms"] * 1e-3)),
            "bin_kernels_ms": float(st["bm_ms"]),

@@ -14,9 +14,13 @@
  * deterministic and independent of launch shapes.
  *
  * Conventions for every call:
- *   - Return value: LDL_OK (0) or a negative LDL_E* code.  Batches are atomic: on any error
- *     except LDL_EDEVICE the graph and partition are unchanged.  After LDL_EDEVICE the handle
- *     is poisoned and every later call returns LDL_EBROKEN.
+ *   - Return value: LDL_OK (0) or a negative LDL_E* code.  Batches are atomic: validation and
+ *     the allocations that depend on the batch size finish before the state changes, so on
+ *     LDL_EINVAL, LDL_EDUP, LDL_ENOEDGE, LDL_EOVERFLOW and on LDL_ENOMEM from those
+ *     allocations the graph and partition are unchanged.  After LDL_EDEVICE, or LDL_ENOMEM
+ *     once the update has started (a pool that cannot grow), the handle is poisoned and every
+ *     later call returns LDL_EBROKEN.
+ *   - A batch holds fewer than 2^31 updates (2^30 for undirected graphs), else LDL_EINVAL.
  *   - Vertices are 0..n-1 (n fixed at creation).  Undirected pairs are unordered.
  *   - Input arrays are owned by the caller and only read during the call; the handle owns
  *     all device memory it allocates.  A handle is not thread-safe; distinct handles may be
@@ -72,7 +76,9 @@ typedef struct ldl_pair {
  *                       8 = always queue the one-workgroup decoupling filter first (iterations
  *                       with more candidates than it holds run the filter after the host check),
  *                       16 = 64-slot LDS tables for the hub partitions (partition overflow, redo of
- *                       the iteration with more partitions per hub)
+ *                       the iteration with more partitions per hub), 32 = no bulk load (the first
+ *                       insert-only batch of a graph goes through the general lookup and row-update
+ *                       path instead of being laid out directly from its sorted records)
  */
 typedef struct ldl_config {
   int32_t directed;

@@ -135,6 +135,7 @@ struct Engine {
   uint32_t n = 0;
   int id_bits = 32;     // bits of a vertex id: keys row << 32 | col need 2 * id_bits bits
   bool broken = false;
+  bool mutating = false;   // the current call has passed validation and started changing state
 
   // exact scalars (host)
   int64_t m = 0, Ein = 0;
@@ -511,8 +512,9 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ dynamic CSR
-  // Rebuild the pool of c with per-row slack and room for `extra` more slots.
-  void csr_grow(Csr& c, uint64_t extra) {
+  // Rebuild the pool of c with per-row slack and room for `extra` more slots (plus a share of
+  // 2^-room_shift of the total for rows that move later).
+  void csr_grow(Csr& c, uint64_t extra, int room_shift = 1) {
     uint32_t* newcap = alloc<uint32_t>(n);
     uint64_t* newcap64 = alloc<uint64_t>(n);
     uint64_t* newoff = alloc<uint64_t>(n);
@@ -524,7 +526,7 @@ struct Engine {
     hcheck(hipMemcpyAsync(&last_cap, newcap64 + (n - 1), 8, hipMemcpyDeviceToHost, st));
     hcheck(hipStreamSynchronize(st));
     const uint64_t used = last_off + last_cap;
-    uint64_t cap = tight ? used + extra : used + extra + (used + extra) / 2 + 1024;
+    uint64_t cap = tight ? used + extra : used + extra + ((used + extra) >> room_shift) + 1024;
     CsrRef to = c.ref;
     to.nbr = alloc<uint32_t>(cap);
     to.w = c.ref.wide ? (void*)alloc<int64_t>(cap) : (void*)alloc<uint32_t>(cap);
@@ -554,8 +556,8 @@ struct Engine {
     if (!c.ref.nbr) csr_grow(c, k + 4ull * n);
     ensure_insflag(k);
     cub(prim_select_heads(&cub_tmp, &cub_bytes, keys, k, id_bits, seg_lo, &ds->nseg, st));
-    launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big, slotbuf,
-                      &cub_tmp, &cub_bytes, id_bits, st);
+    cub(launch_seg_lookup(c.ref, keys, k, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big,
+                          slotbuf, &cub_tmp, &cub_bytes, id_bits, st));
     hcheck(hipMemsetAsync(&ds->nmove, 0, 2 * sizeof(uint32_t), st));   // nmove, overflow
     launch_seg_update(c.ref, keys, delta, k, seg_lo, seg_hi, &ds->nseg, slotbuf, insflag, holebuf, deg_arr, rowdel,
                       rowins, movelist, &ds->nmove, id_bits, st);
@@ -654,12 +656,116 @@ struct Engine {
     }
   }
 
+  // ------------------------------------------------------------------ bulk load
+  // An insert-only batch into a graph without entries and without aggregate levels (the first
+  // batch: static Leiden at creation, Sec. IV-E) lays its rows out directly from the sorted
+  // records: two ping-pong sorts and a placement pass, with no lookup or row-update buffers, so
+  // a graph of k edges needs about 24 bytes per edge of transient memory (72 for undirected
+  // graphs, whose entries are mirrored) beside its adjacency.  The resulting matrix, degrees, totals and seeds are those of
+  // the general path; rows hold their entries in column order, with the same per-row slack.
+  bool bulk_eligible(uint64_t nd, uint64_t nc) const {
+    return nd == 0 && nc == 0 && top == 0 && m == 0 && !(test_flags & 32);   // m == 0: no entry at all
+  }
+  struct Transient {   // device buffers released when the bulk load returns or throws
+    Engine* e;
+    std::vector<void*> ps;
+    template <typename T>
+    T* get(uint64_t count) {
+      T* p = e->alloc<T>(count);
+      ps.push_back((void*)p);
+      return p;
+    }
+    ~Transient() {
+      for (void* p : ps) e->release(p);
+    }
+  };
+  // rows of c (level 0, no entry) from a sorted entry list
+  void bulk_rows(Csr& c, const uint64_t* keys, const uint32_t* wts, uint64_t E, const uint32_t* lab_or_null) {
+    if (c.ref.nbr) {   // a pool whose rows are all empty: laid out anew
+      hcheck(hipStreamSynchronize(st));
+      release(c.ref.nbr);
+      release(c.ref.w);
+      c.ref.nbr = nullptr;
+      c.ref.w = nullptr;
+      c.pool_cap = 0;
+    }
+    uint64_t* start = tcounts;   // n + 1 words each; no aggregation pass is running
+    uint64_t* end = toffs;
+    hcheck(hipMemsetAsync(start, 0, 8ull * n, st));
+    hcheck(hipMemsetAsync(end, 0, 8ull * n, st));
+    launch_bulk_rows(keys, E, start, end, n, c.ref.deg, id_bits, st);
+    csr_grow(c, 0, 3);
+    launch_bulk_place(keys, wts, E, start, c.ref, lab_or_null, &ds->dein, id_bits, st);
+    hcheck(hipMemsetAsync(tcounts, 0, 8ull * ((uint64_t)n + 1), st));   // kept zero between passes
+  }
+  int bulk_ingest(const uint32_t* dins, uint64_t K) {
+    Transient t{this, {}};
+    uint64_t* k0 = t.get<uint64_t>(K);
+    uint64_t* k1 = t.get<uint64_t>(K);
+    uint32_t* v0 = t.get<uint32_t>(K);
+    uint32_t* v1 = t.get<uint32_t>(K);
+    zero(&ds->err);
+    zero(&ds->dm);
+    zero(&ds->dein);
+    launch_ingest_records(dins, K, nullptr, 0, nullptr, 0, n, directed, k0, v0, &ds->err, id_bits, st);
+    int sel = 0;
+    cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, k0, k1, v0, v1, K, 0, 2 * id_bits, &sel, st));
+    uint64_t* keys = sel ? k1 : k0;   // sorted records
+    uint64_t* kfree = sel ? k0 : k1;
+    uint32_t* idx = sel ? v1 : v0;
+    uint32_t* wts = sel ? v0 : v1;    // their weights, in sorted order
+    launch_bulk_check(keys, idx, K, dins, directed, wts, &ds->err, (u64a*)&ds->dm, id_bits, st);
+    sync_read();
+    if (hs->err & 1u) return LDL_EINVAL;
+    if (hs->err & 2u) return LDL_EDUP;
+    const uint64_t dm = (uint64_t)hs->dm;   // unsigned sum of the batch's weights
+    if (dm >= ((uint64_t)1 << 40) || m + (int64_t)dm >= ((int64_t)1 << 40)) return LDL_EOVERFLOW;
+    mutating = true;
+    Level& V0 = lv[0];
+    if (directed) {
+      launch_bulk_transpose(keys, wts, K, kfree, idx, id_bits, st);   // in-adjacency records
+      bulk_rows(V0.out, keys, wts, K, V0.lab);
+      int sel2 = 0;
+      cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, kfree, keys, idx, wts, K, 0, 2 * id_bits, &sel2, st));
+      bulk_rows(V0.in, sel2 ? keys : kfree, sel2 ? wts : idx, K, nullptr);
+    } else {
+      uint64_t* e0 = t.get<uint64_t>(2 * K);
+      uint64_t* e1 = t.get<uint64_t>(2 * K);
+      uint32_t* w0 = t.get<uint32_t>(2 * K);
+      uint32_t* w1 = t.get<uint32_t>(2 * K);
+      zero(&ds->ecount);
+      launch_bulk_mirror(keys, wts, K, e0, w0, &ds->ecount, id_bits, st);
+      sync_read();
+      const uint64_t E = hs->ecount;
+      int sel2 = 0;
+      cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, e0, e1, w0, w1, E, 0, 2 * id_bits, &sel2, st));
+      bulk_rows(V0.out, sel2 ? e1 : e0, sel2 ? w1 : w0, E, V0.lab);
+    }
+    // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
+    const CsrRef in = directed ? V0.in.ref : CsrRef{};
+    begin(S_TOUCH);
+    launch_bulk_mark(n, V0.out.ref, in, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), st);
+    launch_bulk_totals(n, V0.out.ref, in, V0.lab, V0.kout, directed ? V0.kin : nullptr, Kout,
+                       directed ? Kin : nullptr, st);
+    zero(&ds->dskk_lo);
+    zero(&ds->dskk_hi);
+    launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], n, Kout, Kin, tko, tki, &ds->dskk_lo,
+                &ds->dskk_hi, st);
+    sync_read();
+    stats.updates = K;
+    m += (int64_t)dm;
+    Ein += hs->dein;
+    SKK += ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
+    return LDL_OK;
+  }
+
   // ------------------------------------------------------------------ batch ingest
   // Returns LDL_OK or a validation error (state untouched).
   int ingest(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg,
              uint64_t nc) {
     const uint64_t K = ni + nd + nc;
     if (K == 0) return LDL_OK;
+    if (bulk_eligible(nd, nc)) return bulk_ingest(dins, ni);
     ensure_records(K);
     ensure_entries(2 * K);
     ensure_tuples(2 * K);
@@ -674,15 +780,15 @@ struct Engine {
     if (!V0.out.ref.nbr) csr_grow(V0.out, 2 * K + 4ull * n);
     ensure_insflag(K);
     cub(prim_select_heads(&cub_tmp, &cub_bytes, rkey1, K, id_bits, seg_lo, &ds->nseg, st));
-    launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big, rslot,
-                      &cub_tmp, &cub_bytes,
-                      id_bits, st);
+    cub(launch_seg_lookup(V0.out.ref, rkey1, K, seg_lo, &ds->nseg, seg_hi, items, item_off, items_big, item_off_big,
+                          rslot, &cub_tmp, &cub_bytes, id_bits, st));
     launch_ingest_validate(V0.out.ref, rkey1, ridx1, rslot, K, dins, ni, ddel, nd, dchg, directed, rdelta, &ds->err,
                            &ds->first_bad, &ds->dm, id_bits, st);
     sync_read();
     if (hs->err & 2u) return LDL_EDUP;
     if (hs->err & 12u) return hs->first_bad < ni ? LDL_EOVERFLOW : LDL_ENOEDGE;
     if (m + hs->dm >= ((int64_t)1 << 40)) return LDL_EOVERFLOW;
+    mutating = true;
     const int64_t dm = hs->dm;
     // matrix entries of the net changes
     zero(&ds->ecount);
@@ -1204,6 +1310,7 @@ struct Engine {
     flush_to(top);
     for (int r = 0; r <= L; ++r) begin(S_D0 + r);
     hcheck(hipStreamSynchronize(st));
+    mutating = false;
     return LDL_OK;
   }
 
@@ -1351,8 +1458,10 @@ struct ldl_handle {
 
 namespace {
 
+// A device error poisons the handle; so does running out of memory once the batch has started
+// changing the state (the batch can then be neither finished nor undone).
 int guard_err(ldl_handle* h, int code) {
-  if (code == LDL_EDEVICE && h) h->e->broken = true;
+  if (h && (code == LDL_EDEVICE || (code == LDL_ENOMEM && h->e->mutating))) h->e->broken = true;
   return code;
 }
 
@@ -1361,11 +1470,11 @@ int run_guarded(ldl_handle* h, F&& f) {
   try {
     return f();
   } catch (const ldl::NoMem&) {
-    return LDL_ENOMEM;
+    return guard_err(h, LDL_ENOMEM);
   } catch (const ldl::DeviceError&) {
     return guard_err(h, LDL_EDEVICE);
   } catch (const std::bad_alloc&) {
-    return LDL_ENOMEM;
+    return guard_err(h, LDL_ENOMEM);
   }
 }
 
@@ -1381,7 +1490,8 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
   if (!h) return LDL_EINVAL;
   if (h->e->broken) return LDL_EBROKEN;
   if ((ni && !ins) || (nd && !del) || (nc && !chg)) return LDL_EINVAL;
-  if (ni + nd + nc >= (1ull << 31)) return LDL_EINVAL;
+  if (ni + nd + nc >= (1ull << (h->e->directed ? 31 : 30))) return LDL_EINVAL;
+  h->e->mutating = false;
   return run_guarded(h, [&]() -> int {
     ldl::Engine& e = *h->e;
     ldl::hcheck(hipSetDevice(e.device));

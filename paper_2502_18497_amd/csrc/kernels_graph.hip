@@ -1207,6 +1207,144 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
   });
 }
 
+// ------------------------------------------------------------------ bulk load
+// An insert-only batch into a level-0 graph that has never held an entry (the first batch of a
+// graph, Alg. 1 l.1-2 on the all-singleton state) builds its rows directly from the sorted
+// records: the slot of a record is its row's first slot plus its rank within the row.
+
+// Per sorted record: duplicate check, the record's weight in sorted order, and the batch's
+// matrix sum (each undirected pair u != v counts twice) into *dm as an unsigned sum.
+__global__ void k_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins,
+                             int directed, uint32_t* wts, uint32_t* err, u64a* dm, int ks) {
+  uint64_t sum = 0;
+  bool dup = false;
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint64_t key = keys[i];
+    if (i > 0 && keys[i - 1] == key) dup = true;
+    const uint32_t w = ins[3 * (uint64_t)idx[i] + 2];
+    wts[i] = w;
+    sum += (!directed && krow(key, ks) != kcol(key, ks)) ? 2ull * w : (uint64_t)w;
+  }
+  const bool any_dup = __ballot(dup) != 0;
+  sum = (uint64_t)wave_sum_i64((int64_t)sum);   // two's-complement sums are exact modulo 2^64
+  if (lane_id() == 0) {
+    if (any_dup) atomicOr(err, 2u);
+    if (sum) atomicAdd(dm, (u64a)sum);
+  }
+}
+
+// Mirror entries of sorted canonical undirected records (u <= v): (u, v) and, for u != v, (v, u).
+__global__ void k_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
+                              u64a* count, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint64_t key = keys[i];
+    const uint32_t u = krow(key, ks), v = kcol(key, ks);
+    const uint32_t w = wts[i];
+    const unsigned long long a = wave_reserve64(count, true, 1);
+    ekeys[a] = key;
+    ew[a] = w;
+    const unsigned long long b = wave_reserve64(count, u != v, 1);
+    if (u != v) {
+      ekeys[b] = kpack(v, u, ks);
+      ew[b] = w;
+    }
+  }
+}
+
+// (row, col, w) -> (col, row, w) for the in-adjacency of a directed graph
+__global__ void k_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys,
+                                 uint32_t* twts, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint64_t key = keys[i];
+    tkeys[i] = kpack(kcol(key, ks), krow(key, ks), ks);
+    twts[i] = wts[i];
+  }
+}
+
+// first and one-past-last position of every row in a sorted entry list (rows without entries
+// keep the zeros they were given)
+__global__ void k_bulk_bounds(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint32_t r = krow(keys[i], ks);
+    if (i == 0 || krow(keys[i - 1], ks) != r) start[r] = i;
+    if (i + 1 == k || krow(keys[i + 1], ks) != r) end[r] = i + 1;
+  }
+}
+
+__global__ void k_bulk_deg(const uint64_t* start, const uint64_t* end, uint32_t n, uint32_t* deg) {
+  for (uint64_t u = gtid(); u < n; u += gstride()) deg[u] = (uint32_t)(end[u] - start[u]);
+}
+
+// Entry i of the sorted list goes to slot off[row] + (i - start[row]) of a level-0 (uint32
+// weight) CSR whose rows have room for their degree.  With lab, the weight of entries whose
+// endpoints share a community is added to *dein.
+__global__ void k_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
+                             const uint32_t* lab, i64a* dein, int ks) {
+  int64_t in_sum = 0;
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    const uint64_t key = keys[i];
+    const uint32_t r = krow(key, ks), col = kcol(key, ks);
+    const uint64_t slot = c.off[r] + (i - start[r]);
+    const uint32_t w = wts[i];
+    c.nbr[slot] = col;
+    ((uint32_t*)c.w)[slot] = w;
+    if (lab && lab[r] == lab[col]) in_sum += w;
+  }
+  in_sum = wave_sum_i64(in_sum);
+  if (lane_id() == 0 && in_sum) atomicAdd((u64a*)dein, (u64a)in_sum);
+}
+
+// Seeds and touched communities of a bulk load: every vertex with an entry is an endpoint of
+// the batch; its community is touched (old totals recorded before any total changes).
+__global__ void k_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout,
+                            const int64_t* Kin, SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0) {
+  for (uint64_t x = gtid(); x < n; x += gstride()) {
+    const uint32_t u = (uint32_t)x;
+    const bool e = out.deg[u] != 0 || (in.deg && in.deg[u] != 0);
+    set_add(seeds0.stamp, seeds0.epoch, seeds0.list, seeds0.count, u, e);
+    const uint32_t c = e ? lab0[u] : 0u;
+    const bool claimed = e && set_claim(touched.stamp, touched.epoch, c);
+    const uint32_t at = wave_reserve(touched.count, claimed);
+    if (claimed) {
+      touched.list[at] = c;
+      tko[at] = Kout[c];
+      tki[at] = Kin[c];
+    }
+  }
+}
+
+// Degrees and community totals of a bulk load, one wavefront per vertex: the out-row sum is
+// added to kout and to Kout of the vertex's community; for directed graphs the in-row sum to
+// kin and Kin.
+__global__ void k_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout,
+                              int64_t* kin_or_null, int64_t* Kout, int64_t* Kin_or_null) {
+  const int lane = lane_id();
+  for (uint64_t x = gwave(); x < n; x += gwstride()) {
+    int64_t so = 0, si = 0;
+    const uint64_t oo = out.off[x];
+    const uint32_t od = out.deg[x];
+    for (uint32_t j = lane; j < od; j += kWave) so += ((const uint32_t*)out.w)[oo + j];
+    if (kin_or_null) {
+      const uint64_t io = in.off[x];
+      const uint32_t id = in.deg[x];
+      for (uint32_t j = lane; j < id; j += kWave) si += ((const uint32_t*)in.w)[io + j];
+    }
+    so = wave_sum_i64(so);
+    si = wave_sum_i64(si);
+    if (lane == 0) {
+      const uint32_t c = lab0[x];
+      if (so) {
+        kout[x] += so;
+        atomic_add_i64(&Kout[c], so);
+      }
+      if (kin_or_null && si) {
+        kin_or_null[x] += si;
+        atomic_add_i64(&Kin_or_null[c], si);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // ids x < n with stamp[x] == ep appended to list (ascending within each 4096-id chunk, chunks in
@@ -1350,21 +1488,24 @@ void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* i
     k_ingest_validate<<<grid_for(k), kTpb, 0, s>>>(out0, keys, idx, slot, k, ins, ni, del, nd, chg, directed, delta,
                                                    err, first_bad, dm, ks);
 }
-void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
-                       uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, uint64_t* items_big,
-                       uint64_t* item_off_big, int64_t* slot_out, void** tmp, size_t* tmp_bytes, int ks,
-                       hipStream_t s) {
-  if (!k) return;
+int launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
+                      uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, uint64_t* items_big,
+                      uint64_t* item_off_big, int64_t* slot_out, void** tmp, size_t* tmp_bytes, int ks,
+                      hipStream_t s) {
+  if (!k) return 0;
   k_seg_items<<<grid_for(k + 1), kTpb, 0, s>>>(c, keys, k, seg_lo, nseg_ptr, seg_hi, items, items_big, ks);
-  prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
+  int rc = prim_exclusive_sum_u64(tmp, tmp_bytes, items, item_off, k + 1, s);
+  if (rc) return rc;
   k_fill_i64_dev<<<grid_for(k), kTpb, 0, s>>>(slot_out, -1, k);
   const unsigned g = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_lookup, 256));
   k_seg_lookup<<<g, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off, slot_out, ks);
   if (k > kSegChunk) {   // a segment above the wavefront limit exists only then
-    prim_exclusive_sum_u64(tmp, tmp_bytes, items_big, item_off_big, k + 1, s);
+    rc = prim_exclusive_sum_u64(tmp, tmp_bytes, items_big, item_off_big, k + 1, s);
+    if (rc) return rc;
     const unsigned gb = cap_blocks(k < 8192 ? k : 8192u, LDL_RESIDENT(k_seg_lookup_big, 256));
     k_seg_lookup_big<<<gb, 256, 0, s>>>(c, keys, k, seg_lo, seg_hi, nseg_ptr, item_off_big, slot_out, ks);
   }
+  return 0;
 }
 void launch_seg_update(CsrRef c, const uint64_t* keys, const int64_t* delta, uint64_t k, const uint64_t* seg_lo,
                        const uint64_t* seg_hi, const uint32_t* nseg_ptr, const int64_t* slot, uint8_t* rtype,
@@ -1473,6 +1614,36 @@ void launch_materialise_nodes(uint32_t n, const uint32_t* rsize, uint8_t* alive_
 void launch_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t* par, const uint32_t* lab_up,
                           uint32_t* lab, SetRef seeds, hipStream_t s) {
   if (n) k_label_refresh<<<grid_for(n), kTpb, 0, s>>>(n, alive, par, lab_up, lab, seeds);
+}
+void launch_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins, int directed,
+                       uint32_t* wts, uint32_t* err, u64a* dm, int ks, hipStream_t s) {
+  if (k) k_bulk_check<<<grid_for(k), kTpb, 0, s>>>(keys, idx, k, ins, directed, wts, err, dm, ks);
+}
+void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
+                        u64a* count, int ks, hipStream_t s) {
+  if (k) k_bulk_mirror<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, ekeys, ew, count, ks);
+}
+void launch_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys, uint32_t* twts,
+                           int ks, hipStream_t s) {
+  if (k) k_bulk_transpose<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, tkeys, twts, ks);
+}
+void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, uint32_t n, uint32_t* deg,
+                      int ks, hipStream_t s) {
+  if (!n) return;
+  if (k) k_bulk_bounds<<<grid_for(k), kTpb, 0, s>>>(keys, k, start, end, ks);
+  k_bulk_deg<<<grid_for(n), kTpb, 0, s>>>(start, end, n, deg);
+}
+void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
+                       const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s) {
+  if (k) k_bulk_place<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, start, c, lab_or_null, dein, ks);
+}
+void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
+                      SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s) {
+  if (n) k_bulk_mark<<<grid_for(n), kTpb, 0, s>>>(n, out, in, lab0, Kout, Kin, touched, tko, tki, seeds0);
+}
+void launch_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout, int64_t* kin_or_null,
+                        int64_t* Kout, int64_t* Kin_or_null, hipStream_t s) {
+  if (n) k_bulk_totals<<<grid_waves(n), kTpb, 0, s>>>(n, out, in, lab0, kout, kin_or_null, Kout, Kin_or_null);
 }
 void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t s) {
   if (n) k_recount_degrees<<<grid_waves(n), kTpb, 0, s>>>(c, n, deg_out);

@@ -152,7 +152,7 @@ void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bou
 // row lookup of sorted records split over (segment, record chunk, row slice) items: slot of
 // every record (or -1).  Segments (first record of each row, ascending) come from
 // prim_select_heads.
-void launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
+int launch_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k, const uint64_t* seg_lo, const uint32_t* nseg_ptr,
                        uint64_t* seg_hi, uint64_t* items, uint64_t* item_off, uint64_t* items_big,
                        uint64_t* item_off_big, int64_t* slot_out, void** tmp, size_t* tmp_bytes, int ks,
                        hipStream_t s);
@@ -192,6 +192,25 @@ void launch_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t
                           int64_t* Kout, int64_t* Kin_or_null, i64a* dein, int ks, hipStream_t s);
 void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, const int64_t* Kout, const int64_t* Kin,
                  const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s);
+// ---- bulk load: an insert-only batch into a level-0 graph that has never held an entry
+// sorted records: duplicate flag (err bit 1), weights in sorted order, unsigned matrix sum into *dm
+void launch_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins, int directed,
+                       uint32_t* wts, uint32_t* err, u64a* dm, int ks, hipStream_t s);
+// undirected: (u, v, w) and (v, u, w) for u != v appended at *count (2k entries of room)
+void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
+                        u64a* count, int ks, hipStream_t s);
+void launch_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys, uint32_t* twts,
+                           int ks, hipStream_t s);
+// row bounds of a sorted entry list (start and end: n zeroed words each) and row degrees
+void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, uint32_t n, uint32_t* deg,
+                      int ks, hipStream_t s);
+// entries into their slots (rows laid out for their degrees); intra-community weight into *dein
+void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
+                       const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s);
+void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
+                      SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s);
+void launch_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout, int64_t* kin_or_null,
+                        int64_t* Kout, int64_t* Kin_or_null, hipStream_t s);
 // cascade: (x,y) <- (par[x], par[y]); keys rebuilt; both endpoints seeded
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
                         uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s);
@@ -314,6 +333,8 @@ void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t 
 
 // ---------------------------------------------------------------- library primitives (hipCUB)
 // temp storage is grown on demand through *tmp / *tmp_bytes (device memory owned by caller)
+int prim_sort_pairs_u64_u32_db(void** tmp, size_t* tmp_bytes, uint64_t* k0, uint64_t* k1, uint32_t* v0, uint32_t* v1,
+                               uint64_t n, int begin_bit, int end_bit, int* sel, hipStream_t s);
 int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                             uint32_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s);
 int prim_sort_pairs_u64_i64(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,

@@ -51,6 +51,7 @@ struct SumI64 {
 int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                             uint32_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) !=
       hipSuccess)
@@ -63,9 +64,30 @@ int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, 
              : -1;
 }
 
+// Ping-pong form: the sorted pairs end in buffers 0 or 1 (*sel), both of which are overwritten;
+// the temporary storage is independent of n's element size (no internal copy of the data).
+int prim_sort_pairs_u64_u32_db(void** tmp, size_t* tmp_bytes, uint64_t* k0, uint64_t* k1, uint32_t* v0, uint32_t* v1,
+                               uint64_t n, int begin_bit, int end_bit, int* sel, hipStream_t s) {
+  *sel = 0;
+  if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;
+  hipcub::DoubleBuffer<uint64_t> keys(k0, k1);
+  hipcub::DoubleBuffer<uint32_t> vals(v0, v1);
+  size_t need = 0;
+  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, vals, (int)n, begin_bit, end_bit, s) != hipSuccess)
+    return -1;
+  if (ensure(tmp, tmp_bytes, need)) return -2;
+  size_t have = *tmp_bytes;
+  if (hipcub::DeviceRadixSort::SortPairs(*tmp, have, keys, vals, (int)n, begin_bit, end_bit, s) != hipSuccess)
+    return -1;
+  *sel = keys.selector;
+  return 0;
+}
+
 int prim_sort_pairs_u64_i64(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,
                             int64_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, begin_bit, end_bit, s) !=
       hipSuccess)
@@ -81,6 +103,7 @@ int prim_sort_pairs_u64_i64(void** tmp, size_t* tmp_bytes, const uint64_t* kin, 
 int prim_reduce_by_key(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const int64_t* vin,
                        int64_t* vout, u64a* nruns, uint64_t n, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceReduce::ReduceByKey(nullptr, need, kin, kout, vin, vout, nruns, SumI64(), (int)n, s) !=
       hipSuccess)
@@ -96,6 +119,7 @@ int prim_reduce_by_key(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint6
 int prim_exclusive_sum_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, uint64_t* out, uint64_t n,
                            hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s) != hipSuccess) return -1;
   if (ensure(tmp, tmp_bytes, need)) return -2;
@@ -105,6 +129,7 @@ int prim_exclusive_sum_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, ui
 
 int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, uint64_t n, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceReduce::Max(nullptr, need, in, (uint64_t*)out, (int)n, s) != hipSuccess) return -1;
   if (ensure(tmp, tmp_bytes, need)) return -2;
@@ -115,6 +140,7 @@ int prim_max_u64(void** tmp, size_t* tmp_bytes, const uint64_t* in, u64a* out, u
 int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint32_t ep, uint32_t n, uint32_t* out,
                       uint32_t* d_count, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   hipcub::CountingInputIterator<uint32_t> ids(0);
   StampIs pred{stamp, ep};
   size_t need = 0;
@@ -127,6 +153,7 @@ int prim_select_stamp(void** tmp, size_t* tmp_bytes, const uint32_t* stamp, uint
 int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint64_t k, int ks, uint64_t* out,
                       uint32_t* d_count, hipStream_t s) {
   if (k == 0) return 0;
+  if (k > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   hipcub::CountingInputIterator<uint64_t> ids(0);
   RowHead pred{keys, ks};
   size_t need = 0;
@@ -138,6 +165,7 @@ int prim_select_heads(void** tmp, size_t* tmp_bytes, const uint64_t* keys, uint6
 
 int prim_exclusive_sum_u64x3(void** tmp, size_t* tmp_bytes, const U64x3* in, U64x3* out, uint64_t n, hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   const U64x3 zero{0, 0, 0};
   if (hipcub::DeviceScan::ExclusiveScan(nullptr, need, in, out, SumU64x3(), zero, (int)n, s) != hipSuccess) return -1;
@@ -149,6 +177,7 @@ int prim_exclusive_sum_u64x3(void** tmp, size_t* tmp_bytes, const U64x3* in, U64
 int prim_exclusive_sum_u32(void** tmp, size_t* tmp_bytes, const uint32_t* in, uint32_t* out, uint64_t n,
                            hipStream_t s) {
   if (n == 0) return 0;
+  if (n > (uint64_t)INT32_MAX) return -2;   // counts are int in the library
   size_t need = 0;
   if (hipcub::DeviceScan::ExclusiveSum(nullptr, need, in, out, (int)n, s) != hipSuccess) return -1;
   if (ensure(tmp, tmp_bytes, need)) return -2;

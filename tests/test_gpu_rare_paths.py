@@ -8,6 +8,7 @@ every result bit-identical to the oracle:
      than it holds run the rounds after the host check and commit everything as a second phase
  16  tiny LDS tables for the hub hash partitions: partitions overflow, the iteration is redone with
      more partitions per hub
+ 32  no bulk load: creation inserts through the general lookup and row-update path
 """
 import numpy as np
 import pytest
@@ -17,7 +18,7 @@ from tests.gpucases import run_parity
 
 pytestmark = pytest.mark.gpu
 
-ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS = 1, 2, 4, 8, 16
+ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS, NO_BULK = 1, 2, 4, 8, 16, 32
 
 
 def _batches(stream, sizes):
@@ -25,7 +26,8 @@ def _batches(stream, sizes):
 
 
 @pytest.mark.parametrize("flags", [ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST,
-                                   ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR, SMALL_FILTER_FIRST | SMALL_HUB_POOL])
+                                   ONE_ROUND | SMALL_HUB_POOL | TIGHT_CSR, SMALL_FILTER_FIRST | SMALL_HUB_POOL,
+                                   NO_BULK])
 def test_rmat_undirected_rare_paths(flags):
     s = synth.rmat_undirected(scale=11, seed_offset=400)
     stats = []
@@ -35,7 +37,8 @@ def test_rmat_undirected_rare_paths(flags):
         assert any(st["lf_rounds"] > st["move_iters"] + st["refine_iters"] for st in stats), stats
 
 
-@pytest.mark.parametrize("flags", [ONE_ROUND | TIGHT_CSR, SMALL_HUB_POOL, SMALL_FILTER_FIRST])
+@pytest.mark.parametrize("flags", [ONE_ROUND | TIGHT_CSR, SMALL_HUB_POOL, SMALL_FILTER_FIRST, NO_BULK,
+                                   NO_BULK | TIGHT_CSR])
 def test_directed_rare_paths(flags):
     s = synth.rmat_directed_lognormal(1 << 11, 12 * (1 << 11), seed_offset=410)
     run_parity(s.n, s.edges(), _batches(s, [400, 40, 400]), directed=True, gpu_flags=flags)
