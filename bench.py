@@ -210,20 +210,23 @@ def measured_traffic(kernel, avg_launch_us):
     return per_launch / (avg_launch_us * 1e-6) / 1e9, per_launch
 
 
-def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19):
+def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19, parts=8):
     """Directed R-MAT on the GPU (torch, seeded): 2^scale vertices, exactly n_edges distinct
-    non-loop pairs (oversampled, deduplicated, then a seeded random subset of that size), a
-    seeded vertex permutation, and lognormal(mu = 1, sigma = 1) weights rounded to >= 1.  Input
-    generation only: a stand-in of the paper's largest streamed graph at a size one run can
-    generate in seconds."""
+    non-loop pairs (oversampled in rounds of at most 2^28 samples, deduplicated within `parts`
+    hash buckets of the pair key so that no single sort exceeds the library's 2^31-element
+    limit, then a seeded random subset of that size), a seeded vertex permutation, and
+    lognormal(mu = 1, sigma = 1) weights rounded to >= 1.  Input generation only: a stand-in of
+    the paper's largest streamed graph at a size one run can generate in seconds."""
     import torch
 
     g = torch.Generator(device=device)
     g.manual_seed(seed)
     n = 1 << scale
-    keys = torch.empty(0, dtype=torch.int64, device=device)
-    while keys.numel() < n_edges:
-        need = int((n_edges - keys.numel()) * 1.15) + 4096
+    mult = 0x9E3779B97F4A7C15 - (1 << 64)   # odd 64-bit multiplier as a signed value
+    buckets = [torch.empty(0, dtype=torch.int64, device=device) for _ in range(parts)]
+    have = 0
+    while have < n_edges:
+        need = min(int((n_edges - have) * 1.15) + 4096, 1 << 28)
         src = torch.zeros(need, dtype=torch.int64, device=device)
         dst = torch.zeros(need, dtype=torch.int64, device=device)
         for _ in range(scale):
@@ -231,11 +234,23 @@ def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19):
             src = src * 2 + (u >= a + b).long()
             dst = dst * 2 + (((u >= a) & (u < a + b)) | (u >= a + b + c)).long()
         keep = src != dst
-        keys = torch.unique(torch.cat([keys, (src[keep] << 32) | dst[keep]]))
+        keys = (src[keep] << 32) | dst[keep]
         del src, dst, keep
-    keys = keys[torch.randperm(keys.numel(), generator=g, device=device)[:n_edges]]
+        h = ((keys * mult) >> 58) & (parts - 1)
+        for p in range(parts):
+            buckets[p] = torch.unique(torch.cat([buckets[p], keys[h == p]]))
+        del keys, h
+        have = sum(int(x.numel()) for x in buckets)
+    # exactly n_edges: a seeded random subset of every bucket, in proportion to its size
+    sizes = [int(x.numel()) for x in buckets]
+    take = [sz * n_edges // have for sz in sizes]
+    for p in range(n_edges - sum(take)):
+        take[p % parts] += 1
+    keys = torch.cat([x[torch.randperm(sz, generator=g, device=device)[:t]] for x, sz, t in zip(buckets, sizes, take)])
+    del buckets
     perm = torch.randperm(n, generator=g, device=device)
     src, dst = perm[keys >> 32], perm[keys & 0xFFFFFFFF]
+    del keys
     w = torch.clamp(torch.round(torch.exp(1.0 + torch.randn(n_edges, generator=g, device=device))), min=1)
     w = torch.clamp(w, max=2 ** 31 - 1).long()
     return n, torch.stack([src, dst, w], dim=1).int().contiguous()

@@ -72,7 +72,7 @@ struct PassScal {
   u64a cdskk_lo;
   i64a cdskk_hi;
   uint32_t ntouch;
-  uint32_t pad_;
+  uint32_t nbig;    // movers of the commit listed for the split Ein pass
 };
 static_assert(sizeof(PassScal) % 4 == 0, "PassScal is cleared as 32-bit words");
 struct Scal {
@@ -155,6 +155,7 @@ struct Engine {
 
   // scratch (size n unless noted)
   uint32_t *oldlab = nullptr, *oldpar = nullptr, *rowdel = nullptr, *rowins = nullptr;
+  uint32_t* bigmov = nullptr;   // movers with long rows, for the split Ein pass of a commit
   uint2* lpk = nullptr;   // (label, parent) of the level being refined, packed for one gather
   // Deferred aggregate records per level (entry deltas not yet applied to that level's CSR; the
   // level's degrees already include them).  See defer() and flush_to().
@@ -378,6 +379,7 @@ struct Engine {
       for (int b = 0; b < kNumBins - 1; ++b) lim[w][b] = kBinLimit[b];
     std::memset(lf_lastK, 0xFF, sizeof(lf_lastK));
     oldpar = alloc<uint32_t>(n);
+    bigmov = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
     rowins = alloc<uint32_t>(n);
     lfE = LfFirst{alloc<u64a>(n), alloc<u64a>(n), alloc<uint32_t>(n)};
@@ -680,7 +682,8 @@ struct Engine {
     }
   };
   // rows of c (level 0, no entry) from a sorted entry list
-  void bulk_rows(Csr& c, const uint64_t* keys, const uint32_t* wts, uint64_t E, const uint32_t* lab_or_null) {
+  void bulk_rows(Csr& c, const uint64_t* keys, const uint32_t* wts, uint64_t E, int64_t* rowsum,
+                 const uint32_t* lab_or_null) {
     if (c.ref.nbr) {   // a pool whose rows are all empty: laid out anew
       hcheck(hipStreamSynchronize(st));
       release(c.ref.nbr);
@@ -695,7 +698,7 @@ struct Engine {
     hcheck(hipMemsetAsync(end, 0, 8ull * n, st));
     launch_bulk_rows(keys, E, start, end, n, c.ref.deg, id_bits, st);
     csr_grow(c, 0, 3);
-    launch_bulk_place(keys, wts, E, start, c.ref, lab_or_null, &ds->dein, id_bits, st);
+    launch_bulk_place(keys, wts, E, start, c.ref, rowsum, lab_or_null, &ds->dein, id_bits, st);
     hcheck(hipMemsetAsync(tcounts, 0, 8ull * ((uint64_t)n + 1), st));   // kept zero between passes
   }
   int bulk_ingest(const uint32_t* dins, uint64_t K) {
@@ -707,14 +710,14 @@ struct Engine {
     zero(&ds->err);
     zero(&ds->dm);
     zero(&ds->dein);
-    launch_ingest_records(dins, K, nullptr, 0, nullptr, 0, n, directed, k0, v0, &ds->err, id_bits, st);
+    launch_bulk_records(dins, K, n, directed, k0, v0, &ds->err, id_bits, st);
     int sel = 0;
     cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, k0, k1, v0, v1, K, 0, 2 * id_bits, &sel, st));
-    uint64_t* keys = sel ? k1 : k0;   // sorted records
-    uint64_t* kfree = sel ? k0 : k1;
-    uint32_t* idx = sel ? v1 : v0;
-    uint32_t* wts = sel ? v0 : v1;    // their weights, in sorted order
-    launch_bulk_check(keys, idx, K, dins, directed, wts, &ds->err, (u64a*)&ds->dm, id_bits, st);
+    uint64_t* keys = sel ? k1 : k0;   // sorted records and their weights
+    uint32_t* wts = sel ? v1 : v0;
+    uint64_t* kfree = sel ? k0 : k1;  // the other halves of the ping-pong pairs
+    uint32_t* vfree = sel ? v0 : v1;
+    launch_bulk_check(keys, wts, K, directed, &ds->err, (u64a*)&ds->dm, id_bits, st);
     sync_read();
     if (hs->err & 1u) return LDL_EINVAL;
     if (hs->err & 2u) return LDL_EDUP;
@@ -723,11 +726,11 @@ struct Engine {
     mutating = true;
     Level& V0 = lv[0];
     if (directed) {
-      launch_bulk_transpose(keys, wts, K, kfree, idx, id_bits, st);   // in-adjacency records
-      bulk_rows(V0.out, keys, wts, K, V0.lab);
+      launch_bulk_transpose(keys, wts, K, kfree, vfree, id_bits, st);   // in-adjacency records
+      bulk_rows(V0.out, keys, wts, K, V0.kout, V0.lab);
       int sel2 = 0;
-      cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, kfree, keys, idx, wts, K, 0, 2 * id_bits, &sel2, st));
-      bulk_rows(V0.in, sel2 ? keys : kfree, sel2 ? wts : idx, K, nullptr);
+      cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, kfree, keys, vfree, wts, K, 0, 2 * id_bits, &sel2, st));
+      bulk_rows(V0.in, sel2 ? keys : kfree, sel2 ? wts : vfree, K, V0.kin, nullptr);
     } else {
       uint64_t* e0 = t.get<uint64_t>(2 * K);
       uint64_t* e1 = t.get<uint64_t>(2 * K);
@@ -739,14 +742,13 @@ struct Engine {
       const uint64_t E = hs->ecount;
       int sel2 = 0;
       cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, e0, e1, w0, w1, E, 0, 2 * id_bits, &sel2, st));
-      bulk_rows(V0.out, sel2 ? e1 : e0, sel2 ? w1 : w0, E, V0.lab);
+      bulk_rows(V0.out, sel2 ? e1 : e0, sel2 ? w1 : w0, E, V0.kout, V0.lab);
     }
     // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
     const CsrRef in = directed ? V0.in.ref : CsrRef{};
     begin(S_TOUCH);
     launch_bulk_mark(n, V0.out.ref, in, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), st);
-    launch_bulk_totals(n, V0.out.ref, in, V0.lab, V0.kout, directed ? V0.kin : nullptr, Kout,
-                       directed ? Kin : nullptr, st);
+    launch_bulk_totals(n, V0.lab, V0.kout, directed ? V0.kin : nullptr, Kout, directed ? Kin : nullptr, st);
     zero(&ds->dskk_lo);
     zero(&ds->dskk_hi);
     launch_dskk(sets[S_TOUCH].list, &ds->counts[sets[S_TOUCH].ci], n, Kout, Kin, tko, tki, &ds->dskk_lo,
@@ -1021,7 +1023,7 @@ struct Engine {
                        tki, st);
     launch_commit_apply(accp, nap, n, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 1, st);
     launch_commit_dein(accp, nap, n, cand, V.out.ref, directed ? V.in.ref : V.out.ref, directed, V.lab,
-                       sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, &ds->ps.cdein, st);
+                       sets[S_MOV].stamp, sets[S_MOV].epoch, oldlab, bigmov, &ds->ps.nbig, &ds->ps.cdein, st);
     launch_dskk(sets[S_TOUCH].list, &ds->ps.ntouch, n, Kout, Kin, tko, tki, &ds->ps.cdskk_lo, &ds->ps.cdskk_hi, st);
   }
   i128 read_dskk() const { return ((i128)hs->ps.cdskk_hi << 64) | (i128)hs->ps.cdskk_lo; }
@@ -1071,7 +1073,7 @@ struct Engine {
     na = hs->nacc;
     if (na > na1) {
       hcheck(hipMemsetD32Async((hipDeviceptr_t)&ds->nacc2, (int)(na - na1), 1, st));
-      hcheck(hipMemsetAsync(&ds->ps.cdein, 0, 32, st));   // cdein, cdskk_lo/hi, ntouch
+      hcheck(hipMemsetAsync(&ds->ps.cdein, 0, 32, st));   // cdein, cdskk_lo/hi, ntouch, nbig
       commit(acc + na1, &ds->nacc2, 1);
       sync_read();
       if (!refine) {

@@ -1045,6 +1045,10 @@ __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list,
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
+  if (c0 >= bound) {   // every id of [0, bound) is listed: the neighbours are listed nodes
+    for (uint64_t i = gtid(); i < cnt; i += gstride()) stamp[list[i]] = ep;
+    return;
+  }
   wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
     const uint32_t u = list[i];
     const uint32_t dout = out.deg[u];
@@ -1212,24 +1216,59 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
 // graph, Alg. 1 l.1-2 on the all-singleton state) builds its rows directly from the sorted
 // records: the slot of a record is its row's first slot plus its rank within the row.
 
-// Per sorted record: duplicate check, the record's weight in sorted order, and the batch's
-// matrix sum (each undirected pair u != v counts twice) into *dm as an unsigned sum.
-__global__ void k_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins,
-                             int directed, uint32_t* wts, uint32_t* err, u64a* dm, int ks) {
+// Insert records of a bulk load: key (canonical pair for undirected graphs) and weight; an id
+// >= n or a zero weight sets err bit 0
+__global__ void k_bulk_records(const uint32_t* ins, uint64_t k, uint32_t n, int directed, uint64_t* keys,
+                               uint32_t* wts, uint32_t* err, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) {
+    uint32_t u = ins[3 * i], v = ins[3 * i + 1];
+    const uint32_t w = ins[3 * i + 2];
+    if (u >= n || v >= n || w == 0) {
+      atomicOr(err, 1u);
+      u = 0;
+      v = 0;
+    }
+    if (!directed && u > v) {
+      const uint32_t t = u;
+      u = v;
+      v = t;
+    }
+    keys[i] = kpack(u, v, ks);
+    wts[i] = w;
+  }
+}
+
+// Sorted records: duplicate check (err bit 1) and the batch's matrix sum (each undirected pair
+// u != v counts twice) into *dm as an unsigned sum.
+__global__ void k_bulk_check(const uint64_t* keys, const uint32_t* wts, uint64_t k, int directed, uint32_t* err,
+                             u64a* dm, int ks) {
   uint64_t sum = 0;
   bool dup = false;
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const uint64_t key = keys[i];
     if (i > 0 && keys[i - 1] == key) dup = true;
-    const uint32_t w = ins[3 * (uint64_t)idx[i] + 2];
-    wts[i] = w;
+    const uint32_t w = wts[i];
     sum += (!directed && krow(key, ks) != kcol(key, ks)) ? 2ull * w : (uint64_t)w;
   }
+  // one atomic per workgroup (a launch of at most kItemBlocks workgroups)
+  __shared__ uint64_t part[kTpb / kWave];
+  __shared__ int pdup[kTpb / kWave];
   const bool any_dup = __ballot(dup) != 0;
   sum = (uint64_t)wave_sum_i64((int64_t)sum);   // two's-complement sums are exact modulo 2^64
   if (lane_id() == 0) {
-    if (any_dup) atomicOr(err, 2u);
-    if (sum) atomicAdd(dm, (u64a)sum);
+    part[threadIdx.x / kWave] = sum;
+    pdup[threadIdx.x / kWave] = any_dup;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    int d = 0;
+    for (int w = 0; w < kTpb / kWave; ++w) {
+      t += part[w];
+      d |= pdup[w];
+    }
+    if (d) atomicOr(err, 2u);
+    if (t) atomicAdd(dm, (u64a)t);
   }
 }
 
@@ -1276,22 +1315,42 @@ __global__ void k_bulk_deg(const uint64_t* start, const uint64_t* end, uint32_t 
 }
 
 // Entry i of the sorted list goes to slot off[row] + (i - start[row]) of a level-0 (uint32
-// weight) CSR whose rows have room for their degree.  With lab, the weight of entries whose
-// endpoints share a community is added to *dein.
+// weight) CSR whose rows have room for their degree.  Each row's weight sum is added to
+// rowsum[row] (one atomic per run of the row within a wavefront: the entries of a row are
+// contiguous, so a segmented scan over the wavefront's lanes forms the runs).  With lab, the
+// weight of entries whose endpoints share a community is added to *dein.
 __global__ void k_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
-                             const uint32_t* lab, i64a* dein, int ks) {
+                             int64_t* rowsum, const uint32_t* lab, i64a* dein, int ks) {
+  const int lane = lane_id();
   int64_t in_sum = 0;
-  for (uint64_t i = gtid(); i < k; i += gstride()) {
-    const uint64_t key = keys[i];
-    const uint32_t r = krow(key, ks), col = kcol(key, ks);
-    const uint64_t slot = c.off[r] + (i - start[r]);
-    const uint32_t w = wts[i];
-    c.nbr[slot] = col;
-    ((uint32_t*)c.w)[slot] = w;
-    if (lab && lab[r] == lab[col]) in_sum += w;
+  for (uint64_t base = gwave() * kWave; base < k; base += gwstride() * kWave) {
+    const uint64_t i = base + lane;
+    const bool valid = i < k;
+    uint32_t r = kEmpty;
+    int64_t w = 0;
+    if (valid) {
+      const uint64_t key = keys[i];
+      const uint32_t col = kcol(key, ks);
+      r = krow(key, ks);
+      w = wts[i];
+      const uint64_t slot = c.off[r] + (i - start[r]);
+      c.nbr[slot] = col;
+      ((uint32_t*)c.w)[slot] = (uint32_t)w;
+      if (lab && lab[r] == lab[col]) in_sum += w;
+    }
+    int64_t run = w;   // inclusive segmented scan by row (rows are non-decreasing over the lanes)
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t t = __shfl_up(run, o, kWave);
+      const uint32_t ro = (uint32_t)__shfl_up((int)r, o, kWave);
+      if (lane >= o && ro == r) run += t;
+    }
+    const uint32_t rn = (uint32_t)__shfl_down((int)r, 1, kWave);
+    const bool last = lane == kWave - 1 || rn != r;
+    if (valid && last && run) atomic_add_i64(&rowsum[r], run);
   }
   in_sum = wave_sum_i64(in_sum);
-  if (lane_id() == 0 && in_sum) atomicAdd((u64a*)dein, (u64a)in_sum);
+  if (lane == 0 && in_sum) atomicAdd((u64a*)dein, (u64a)in_sum);
 }
 
 // Seeds and touched communities of a bulk load: every vertex with an entry is an endpoint of
@@ -1313,35 +1372,14 @@ __global__ void k_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* l
   }
 }
 
-// Degrees and community totals of a bulk load, one wavefront per vertex: the out-row sum is
-// added to kout and to Kout of the vertex's community; for directed graphs the in-row sum to
-// kin and Kin.
-__global__ void k_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout,
-                              int64_t* kin_or_null, int64_t* Kout, int64_t* Kin_or_null) {
-  const int lane = lane_id();
-  for (uint64_t x = gwave(); x < n; x += gwstride()) {
-    int64_t so = 0, si = 0;
-    const uint64_t oo = out.off[x];
-    const uint32_t od = out.deg[x];
-    for (uint32_t j = lane; j < od; j += kWave) so += ((const uint32_t*)out.w)[oo + j];
-    if (kin_or_null) {
-      const uint64_t io = in.off[x];
-      const uint32_t id = in.deg[x];
-      for (uint32_t j = lane; j < id; j += kWave) si += ((const uint32_t*)in.w)[io + j];
-    }
-    so = wave_sum_i64(so);
-    si = wave_sum_i64(si);
-    if (lane == 0) {
-      const uint32_t c = lab0[x];
-      if (so) {
-        kout[x] += so;
-        atomic_add_i64(&Kout[c], so);
-      }
-      if (kin_or_null && si) {
-        kin_or_null[x] += si;
-        atomic_add_i64(&Kin_or_null[c], si);
-      }
-    }
+// Community totals of a bulk load: the degrees of the loaded rows (zero before the load) are
+// added to the totals of each vertex's community.
+__global__ void k_bulk_totals(uint32_t n, const uint32_t* lab0, const int64_t* kout, const int64_t* kin_or_null,
+                              int64_t* Kout, int64_t* Kin_or_null) {
+  for (uint64_t x = gtid(); x < n; x += gstride()) {
+    const uint32_t c = lab0[x];
+    if (kout[x]) atomic_add_i64(&Kout[c], kout[x]);
+    if (kin_or_null && kin_or_null[x]) atomic_add_i64(&Kin_or_null[c], kin_or_null[x]);
   }
 }
 
@@ -1615,9 +1653,16 @@ void launch_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t* par,
                           uint32_t* lab, SetRef seeds, hipStream_t s) {
   if (n) k_label_refresh<<<grid_for(n), kTpb, 0, s>>>(n, alive, par, lab_up, lab, seeds);
 }
-void launch_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins, int directed,
-                       uint32_t* wts, uint32_t* err, u64a* dm, int ks, hipStream_t s) {
-  if (k) k_bulk_check<<<grid_for(k), kTpb, 0, s>>>(keys, idx, k, ins, directed, wts, err, dm, ks);
+void launch_bulk_records(const uint32_t* ins, uint64_t k, uint32_t n, int directed, uint64_t* keys, uint32_t* wts,
+                         uint32_t* err, int ks, hipStream_t s) {
+  if (k) k_bulk_records<<<grid_for(k), kTpb, 0, s>>>(ins, k, n, directed, keys, wts, err, ks);
+}
+void launch_bulk_check(const uint64_t* keys, const uint32_t* wts, uint64_t k, int directed, uint32_t* err, u64a* dm,
+                       int ks, hipStream_t s) {
+  if (k) {
+    const unsigned g = grid_for(k) < kItemBlocks ? grid_for(k) : kItemBlocks;
+    k_bulk_check<<<g, kTpb, 0, s>>>(keys, wts, k, directed, err, dm, ks);
+  }
 }
 void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
                         u64a* count, int ks, hipStream_t s) {
@@ -1634,16 +1679,16 @@ void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_
   k_bulk_deg<<<grid_for(n), kTpb, 0, s>>>(start, end, n, deg);
 }
 void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
-                       const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s) {
-  if (k) k_bulk_place<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, start, c, lab_or_null, dein, ks);
+                       int64_t* rowsum, const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s) {
+  if (k) k_bulk_place<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, start, c, rowsum, lab_or_null, dein, ks);
 }
 void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
                       SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s) {
   if (n) k_bulk_mark<<<grid_for(n), kTpb, 0, s>>>(n, out, in, lab0, Kout, Kin, touched, tko, tki, seeds0);
 }
-void launch_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout, int64_t* kin_or_null,
-                        int64_t* Kout, int64_t* Kin_or_null, hipStream_t s) {
-  if (n) k_bulk_totals<<<grid_waves(n), kTpb, 0, s>>>(n, out, in, lab0, kout, kin_or_null, Kout, Kin_or_null);
+void launch_bulk_totals(uint32_t n, const uint32_t* lab0, const int64_t* kout, const int64_t* kin_or_null, int64_t* Kout,
+                        int64_t* Kin_or_null, hipStream_t s) {
+  if (n) k_bulk_totals<<<grid_for(n), kTpb, 0, s>>>(n, lab0, kout, kin_or_null, Kout, Kin_or_null);
 }
 void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t s) {
   if (n) k_recount_degrees<<<grid_waves(n), kTpb, 0, s>>>(c, n, deg_out);

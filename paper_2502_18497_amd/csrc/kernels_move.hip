@@ -1369,43 +1369,74 @@ __global__ void k_commit_apply(const uint32_t* acc, const uint32_t* nap, CandBuf
   }
 }
 
-// wave per mover: exact change of the same-label weight over matrix entries incident to
-// movers, each entry once (entries between two movers from the out side)
-__global__ void k_commit_dein(const uint32_t* acc, const uint32_t* nap, CandBuf cand, CsrRef out, CsrRef in,
-                              int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
-                              const uint32_t* oldlab, i64a* dein) {
+// Exact change of the same-label weight over the matrix entries incident to movers, each entry
+// once: mover v's out entries (with the neighbour's old label when the neighbour moved too),
+// then its in entries whose other end did not move (for undirected graphs the out entries
+// again, standing for the mirrored matrix entries).  One wavefront per mover; a mover with more
+// than kDeinBig entries is listed instead and taken by a whole workgroup in k_commit_dein_big.
+constexpr uint32_t kDeinBig = 4096;
+
+__device__ __forceinline__ int64_t dein_entry(const CsrRef& out, const CsrRef& second, uint32_t dout, uint64_t oo,
+                                              uint64_t os, uint64_t j, uint32_t lv_new, uint32_t lv_old,
+                                              const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
+                                              const uint32_t* oldlab) {
+  if (j < dout) {
+    const uint32_t u = out.nbr[oo + j];
+    const int64_t w = wget(out, oo + j);
+    const uint32_t lu_new = lab[u];
+    const uint32_t lu_old = mov_stamp[u] == mov_ep ? oldlab[u] : lu_new;
+    return w * ((int64_t)(lv_new == lu_new) - (int64_t)(lv_old == lu_old));
+  }
+  const uint64_t e = os + (j - dout);
+  const uint32_t u = second.nbr[e];
+  if (mov_stamp[u] == mov_ep) return 0;
+  const int64_t w = wget(second, e);
+  const uint32_t lu = lab[u];
+  return w * ((int64_t)(lv_new == lu) - (int64_t)(lv_old == lu));
+}
+
+__global__ void k_commit_dein(const uint32_t* acc, const uint32_t* nap, CandBuf cand, CsrRef out, CsrRef second,
+                              const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep, const uint32_t* oldlab,
+                              uint32_t* big, uint32_t* nbig, i64a* dein) {
   const int lane = lane_id();
   const uint32_t na = *nap;
+  int64_t s = 0;
   for (uint64_t t = gwave(); t < na; t += gwstride()) {
     const uint32_t v = cand.v[acc[t]];
+    const uint32_t dout = out.deg[v];
+    const uint64_t sl = (uint64_t)dout + second.deg[v];
+    if (sl > kDeinBig) {
+      if (lane == 0) big[atomicAdd(nbig, 1u)] = v;
+      continue;
+    }
     const uint32_t lv_new = lab[v], lv_old = oldlab[v];
-    int64_t s = 0;
-    {
-      const uint64_t o = out.off[v];
-      const uint32_t d = out.deg[v];
-      for (uint32_t j = lane; j < d; j += kWave) {
-        const uint32_t u = out.nbr[o + j];
-        const int64_t w = wget(out, o + j);
-        const uint32_t lu_new = lab[u];
-        const uint32_t lu_old = mov_stamp[u] == mov_ep ? oldlab[u] : lu_new;
-        s += w * ((int64_t)(lv_new == lu_new) - (int64_t)(lv_old == lu_old));
-      }
-    }
-    {
-      const CsrRef& c = directed ? in : out;
-      const uint64_t o = c.off[v];
-      const uint32_t d = c.deg[v];
-      for (uint32_t j = lane; j < d; j += kWave) {
-        const uint32_t u = c.nbr[o + j];
-        if (mov_stamp[u] == mov_ep) continue;
-        const int64_t w = wget(c, o + j);
-        const uint32_t lu = lab[u];
-        s += w * ((int64_t)(lv_new == lu) - (int64_t)(lv_old == lu));
-      }
-    }
-    s = wave_sum_i64(s);
-    if (lane == 0 && s != 0) atomicAdd((u64a*)dein, (u64a)s);
+    const uint64_t oo = out.off[v], os = second.off[v];
+    for (uint64_t j = lane; j < sl; j += kWave)
+      s += dein_entry(out, second, dout, oo, os, j, lv_new, lv_old, lab, mov_stamp, mov_ep, oldlab);
   }
+  s = wave_sum_i64(s);
+  if (lane == 0 && s != 0) atomicAdd((u64a*)dein, (u64a)s);
+}
+
+// the listed movers: one workgroup of kDeinTpb threads per mover
+constexpr int kDeinTpb = 1024;
+__global__ __launch_bounds__(kDeinTpb) void k_commit_dein_big(const uint32_t* big, const uint32_t* nbig, CsrRef out,
+                                                              CsrRef second, const uint32_t* lab,
+                                                              const uint32_t* mov_stamp, uint32_t mov_ep,
+                                                              const uint32_t* oldlab, i64a* dein) {
+  const uint32_t nb = *nbig;
+  int64_t s = 0;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t v = big[b];
+    const uint32_t dout = out.deg[v];
+    const uint64_t sl = (uint64_t)dout + second.deg[v];
+    const uint32_t lv_new = lab[v], lv_old = oldlab[v];
+    const uint64_t oo = out.off[v], os = second.off[v];
+    for (uint64_t j = threadIdx.x; j < sl; j += blockDim.x)
+      s += dein_entry(out, second, dout, oo, os, j, lv_new, lv_old, lab, mov_stamp, mov_ep, oldlab);
+  }
+  s = wave_sum_i64(s);
+  if (lane_id() == 0 && s != 0) atomicAdd((u64a*)dein, (u64a)s);
 }
 
 __global__ void k_mark_acc_comms(const uint32_t* acc, const uint32_t* nap, CandBuf cand, uint32_t* stamp,
@@ -1552,10 +1583,13 @@ void launch_commit_apply(const uint32_t* acc, const uint32_t* na, uint32_t na_ma
 }
 void launch_commit_dein(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
                         int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
-                        const uint32_t* oldlab, i64a* dein, hipStream_t s) {
-  if (na_max)
-    k_commit_dein<<<cap_grid(grid_waves(na_max)), kTpb, 0, s>>>(acc, na, cand, out, in, directed, lab, mov_stamp,
-                                                                mov_ep, oldlab, dein);
+                        const uint32_t* oldlab, uint32_t* big, uint32_t* nbig, i64a* dein, hipStream_t s) {
+  if (!na_max) return;
+  const CsrRef second = directed ? in : out;
+  k_commit_dein<<<cap_grid(grid_waves(na_max)), kTpb, 0, s>>>(acc, na, cand, out, second, lab, mov_stamp, mov_ep,
+                                                              oldlab, big, nbig, dein);
+  k_commit_dein_big<<<cap_blocks(kPersistBlocks, LDL_RESIDENT(k_commit_dein_big, kDeinTpb)), kDeinTpb, 0, s>>>(
+      big, nbig, out, second, lab, mov_stamp, mov_ep, oldlab, dein);
 }
 void launch_mark_acc_comms(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* stamp,
                            uint32_t ep, hipStream_t s) {

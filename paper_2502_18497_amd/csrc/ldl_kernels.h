@@ -193,9 +193,12 @@ void launch_ingest_totals(const uint64_t* ekeys, const int64_t* edelta, uint64_t
 void launch_dskk(const uint32_t* touched, const uint32_t* nt, uint32_t nt_max, const int64_t* Kout, const int64_t* Kin,
                  const int64_t* tko, const int64_t* tki, u64a* lo, i64a* hi, hipStream_t s);
 // ---- bulk load: an insert-only batch into a level-0 graph that has never held an entry
-// sorted records: duplicate flag (err bit 1), weights in sorted order, unsigned matrix sum into *dm
-void launch_bulk_check(const uint64_t* keys, const uint32_t* idx, uint64_t k, const uint32_t* ins, int directed,
-                       uint32_t* wts, uint32_t* err, u64a* dm, int ks, hipStream_t s);
+// insert records (key, weight); bad ids or zero weights set err bit 0
+void launch_bulk_records(const uint32_t* ins, uint64_t k, uint32_t n, int directed, uint64_t* keys, uint32_t* wts,
+                         uint32_t* err, int ks, hipStream_t s);
+// sorted records: duplicate flag (err bit 1), unsigned matrix sum into *dm
+void launch_bulk_check(const uint64_t* keys, const uint32_t* wts, uint64_t k, int directed, uint32_t* err, u64a* dm,
+                       int ks, hipStream_t s);
 // undirected: (u, v, w) and (v, u, w) for u != v appended at *count (2k entries of room)
 void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
                         u64a* count, int ks, hipStream_t s);
@@ -204,13 +207,15 @@ void launch_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k
 // row bounds of a sorted entry list (start and end: n zeroed words each) and row degrees
 void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, uint32_t n, uint32_t* deg,
                       int ks, hipStream_t s);
-// entries into their slots (rows laid out for their degrees); intra-community weight into *dein
+// entries into their slots (rows laid out for their degrees); row weight sums added to rowsum,
+// intra-community weight into *dein
 void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
-                       const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s);
+                       int64_t* rowsum, const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s);
 void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
                       SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s);
-void launch_bulk_totals(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, int64_t* kout, int64_t* kin_or_null,
-                        int64_t* Kout, int64_t* Kin_or_null, hipStream_t s);
+// Kout[lab0[x]] += kout[x] (and Kin with kin) for degrees that were zero before the load
+void launch_bulk_totals(uint32_t n, const uint32_t* lab0, const int64_t* kout, const int64_t* kin_or_null, int64_t* Kout,
+                        int64_t* Kin_or_null, hipStream_t s);
 // cascade: (x,y) <- (par[x], par[y]); keys rebuilt; both endpoints seeded
 void launch_cascade_map(uint32_t* ex, uint32_t* ey, const int64_t* ed, uint64_t k, const uint32_t* par,
                         uint64_t* keys, int64_t* vals, SetRef seeds, int ks, hipStream_t s);
@@ -284,9 +289,11 @@ void launch_commit_mark(const uint32_t* acc, const uint32_t* na, uint32_t na_max
 void launch_commit_apply(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* lab,
                          const int64_t* kout, const int64_t* kin, int64_t* Kout, int64_t* Kin_or_null, int forward,
                          hipStream_t s);
+// big: room for na_max mover ids, *nbig zero at launch (movers with long rows are listed there
+// and split over the grid)
 void launch_commit_dein(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in,
                         int directed, const uint32_t* lab, const uint32_t* mov_stamp, uint32_t mov_ep,
-                        const uint32_t* oldlab, i64a* dein, hipStream_t s);
+                        const uint32_t* oldlab, uint32_t* big, uint32_t* nbig, i64a* dein, hipStream_t s);
 void launch_mark_acc_comms(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* stamp,
                            uint32_t ep, hipStream_t s);
 void launch_set_add_acc_v(SetRef set, const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand,
