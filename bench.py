@@ -183,12 +183,15 @@ def run_serve(args):
 
 
 def kernel_source_sha():
-    """Hash of the candidate-kernel source: counters taken on another version do not apply."""
+    """Hash of the candidate kernels' source and of the header with their launch parameters and
+    default degree bins: counters taken on another version do not apply."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2502_18497_amd", "csrc", "kernels_move.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("kernels_move.hip", "ldl_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2502_18497_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, avg_launch_us):

@@ -240,7 +240,8 @@ void ldl_server_destroy(ldl_server* s);
  * {8, 32, 128, 512, 2048}[b] entries, so a valid set has limit[b] <= that cap and
  * limit[0] <= limit[1] <= ... <= limit[4]; equal neighbours leave a bin empty.  Row 0 applies to
  * level 0 (32-bit weights), row 1 to the aggregate levels (64-bit weights).  Every valid set gives
- * bit-identical results; only the speed differs.  Defaults: {8, 32, 128, 512, 2048} for both.
+ * bit-identical results; only the speed differs.  Defaults: {8, 32, 128, 128, 2048} for both (bin 3
+ * empty: vertices with 129..2048 entries go to the 256-lane workgroup kernel).
  * ldl_set_bins returns LDL_EINVAL for an invalid set (limits unchanged).
  */
 int ldl_get_bins(const ldl_handle* h, uint32_t limits[2][5]);

@@ -1348,7 +1348,7 @@ struct Engine {
   }
   void autotune(ldl_tune_report* rep) {
     static const uint32_t opts[kNumBins - 1][4] = {{0, 4, 8, 8}, {16, 24, 32, 32}, {64, 96, 128, 128},
-                                                    {256, 384, 512, 512}, {1024, 2048, 2048, 2048}};
+                                                    {128, 256, 384, 512}, {1024, 2048, 2048, 2048}};
     const int saved_profile = profile;
     profile = 0;
     hipEvent_t a = nullptr, b = nullptr;
