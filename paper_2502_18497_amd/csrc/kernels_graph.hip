@@ -1039,22 +1039,20 @@ __device__ __forceinline__ void wave_items(const uint64_t* ioff, uint32_t cnt, F
   }
 }
 
-// stamp[x] = ep for every listed node and each of its entries' neighbours
+// stamp[x] = ep for every listed node (with or without entries) and each of its entries'
+// neighbours
 __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* countp, uint32_t bound,
                              const uint64_t* ioff, CsrRef out, CsrRef in) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
-  if (c0 >= bound) {   // every id of [0, bound) is listed: the neighbours are listed nodes
-    for (uint64_t i = gtid(); i < cnt; i += gstride()) stamp[list[i]] = ep;
-    return;
-  }
+  for (uint64_t i = gtid(); i < cnt; i += gstride()) stamp[list[i]] = ep;
+  if (c0 >= bound) return;   // every id of [0, bound) is listed: the neighbours are listed nodes
   wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
     const uint32_t u = list[i];
     const uint32_t dout = out.deg[u];
     const uint64_t s = node_slots(out, in, u);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
-    if (q == 0 && lane == 0) stamp[u] = ep;
     for (uint64_t j = j0 + lane; j < j1; j += kWave) {
       uint32_t x;
       int64_t w;

@@ -56,6 +56,22 @@ def test_rmat_directed_lognormal():
     run_parity(s.n, e, _batches(s, [500, 50, 500]), directed=True)
 
 
+def test_rmat18_directed_lognormal_batches_of_1e5():
+    # the directed lognormal R-MAT stream at 2^18 vertices and 4,194,304 edges (the largest size the
+    # oracle follows within a test): bit-exact state after creation and after batches of 10^5 and
+    # 10^3 updates
+    s = synth.rmat_directed_lognormal(1 << 18, 16 << 18, seed_offset=130)
+    e = s.edges()
+    run_parity(s.n, e, _batches(s, [100000, 1000]), directed=True)
+
+
+def test_rmat18_directed_lognormal_scan_configuration():
+    # the configuration of the full-frontier scan measurement (L = 0, N = 1, M = 1): one local-move
+    # iteration over every vertex of a bulk-loaded directed graph, bit-exact
+    s = synth.rmat_directed_lognormal(1 << 18, 16 << 18, seed_offset=131)
+    run_parity(s.n, s.edges(), [], directed=True, L=0, N=1, M=1)
+
+
 def _with_hub(n, base_edges, hub, k, seed):
     rng = np.random.default_rng(seed)
     have = {(int(min(u, v)), int(max(u, v))) for u, v, _ in base_edges}
@@ -240,6 +256,32 @@ def test_bulk_load_equals_general_path(directed):
         g2.apply_batch(b.ins, b.dels, b.chg)
         msgs = diff_states(g1.state(), g2.state())
         assert not msgs, msgs
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_isolated_vertices_in_scan_sets(directed):
+    # 3,000 of 4,000 vertices have no edge: at the aggregate levels they are alive supernodes
+    # without entries, members of the frontier and so of the scan set (which the moved-fraction stop
+    # of Alg. 1 l.14 divides by); every iteration's record (scan-set size, candidates, accepted
+    # moves, exact gain) must match the oracle's
+    import paper_2502_18497_amd as ldl
+    from tests.gpucases import first_trace_divergence
+    from tests.statecheck import diff_states
+
+    s = synth.Stream(1000, directed, synth.BASE_SEED + 207)
+    s.planted(50, 0.12, 0.004, 1, 8)
+    e = s.edges()
+    n = 4000
+    og = oracle.Oracle(n, np.zeros((0, 3), np.uint32), directed=directed, flags=oracle.FLAG_TRACE)
+    g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=directed)
+    g.set_trace(True)
+    assert og.apply_batch(ins=e) == 0
+    g.apply_batch(ins=e)
+    tg, to = g.trace(), og.trace()
+    assert np.array_equal(tg, to), first_trace_divergence(tg, to)
+    assert any(r[1] >= 1 and r[4] > 1000 for r in to.tolist())   # scan sets above level 0 hold isolated nodes
+    msgs = diff_states(g.state(), oracle_state(og))
+    assert not msgs, msgs
 
 
 def test_device_inputs_equal_host_inputs():
