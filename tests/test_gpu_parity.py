@@ -50,6 +50,13 @@ def test_rmat_undirected(scale):
     run_parity(s.n, e, _batches(s, [1000, 100, 1000]))
 
 
+def test_rmat17_undirected_batches_of_1e4():
+    # the benchmark's stream (undirected R-MAT, weights 1..16, 70/20/10 updates) at 2^17 vertices and
+    # 1,048,576 edges, with the benchmark's batch size: bit-exact after creation and every batch
+    s = synth.rmat_undirected(scale=17, seed_offset=157)
+    run_parity(s.n, s.edges(), _batches(s, [10000, 10000, 1000]))
+
+
 def test_rmat_directed_lognormal():
     s = synth.rmat_directed_lognormal(1 << 12, 16 * (1 << 12), seed_offset=120)
     e = s.edges()
