@@ -213,18 +213,19 @@ def measured_traffic(kernel, avg_launch_us):
     return per_launch / (avg_launch_us * 1e-6) / 1e9, per_launch
 
 
-def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19, parts=8):
-    """Directed R-MAT on the GPU (torch, seeded): 2^scale vertices, exactly n_edges distinct
-    non-loop pairs (oversampled in rounds of at most 2^28 samples, deduplicated within `parts`
-    hash buckets of the pair key so that no single sort exceeds the library's 2^31-element
-    limit, then a seeded random subset of that size), a seeded vertex permutation, and
-    lognormal(mu = 1, sigma = 1) weights rounded to >= 1.  Input generation only: a stand-in of
-    the paper's largest streamed graph at a size one run can generate in seconds."""
+def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19, parts=8, n=None):
+    """Directed R-MAT on the GPU (torch, seeded): ids drawn at 2^scale, pairs with an id >= n
+    rejected (n = 2^scale by default), exactly n_edges distinct non-loop pairs (oversampled in
+    rounds of at most 2^28 samples, deduplicated within `parts` hash buckets of the pair key so
+    that no single torch sort exceeds 2^31 elements, then a seeded random subset of that size), a
+    seeded vertex permutation, and lognormal(mu = 1, sigma = 1) weights rounded to >= 1, as an
+    (n_edges, 3) int32 tensor.  Input generation only: a stand-in of the paper's largest streamed
+    graph that one run can generate in seconds."""
     import torch
 
     g = torch.Generator(device=device)
     g.manual_seed(seed)
-    n = 1 << scale
+    n = (1 << scale) if n is None else n
     mult = 0x9E3779B97F4A7C15 - (1 << 64)   # odd 64-bit multiplier as a signed value
     buckets = [torch.empty(0, dtype=torch.int64, device=device) for _ in range(parts)]
     have = 0
@@ -236,7 +237,7 @@ def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19, p
             u = torch.rand(need, generator=g, device=device)
             src = src * 2 + (u >= a + b).long()
             dst = dst * 2 + (((u >= a) & (u < a + b)) | (u >= a + b + c)).long()
-        keep = src != dst
+        keep = (src != dst) & (src < n) & (dst < n)
         keys = (src[keep] << 32) | dst[keep]
         del src, dst, keep
         h = ((keys * mult) >> 58) & (parts - 1)
@@ -249,14 +250,24 @@ def rmat_directed_device(scale, n_edges, seed, device, a=0.57, b=0.19, c=0.19, p
     take = [sz * n_edges // have for sz in sizes]
     for p in range(n_edges - sum(take)):
         take[p % parts] += 1
-    keys = torch.cat([x[torch.randperm(sz, generator=g, device=device)[:t]] for x, sz, t in zip(buckets, sizes, take)])
-    del buckets
+    for p in range(parts):
+        buckets[p] = buckets[p][torch.randperm(sizes[p], generator=g, device=device)[:take[p]]]
     perm = torch.randperm(n, generator=g, device=device)
-    src, dst = perm[keys >> 32], perm[keys & 0xFFFFFFFF]
-    del keys
-    w = torch.clamp(torch.round(torch.exp(1.0 + torch.randn(n_edges, generator=g, device=device))), min=1)
-    w = torch.clamp(w, max=2 ** 31 - 1).long()
-    return n, torch.stack([src, dst, w], dim=1).int().contiguous()
+    out = torch.empty((n_edges, 3), dtype=torch.int32, device=device)
+    at = 0
+    for p in range(parts):   # written bucket by bucket, in chunks, to bound the temporaries
+        x = buckets[p]
+        buckets[p] = None
+        for c0 in range(0, x.numel(), 1 << 28):
+            k = x[c0:c0 + (1 << 28)]
+            m = k.numel()
+            out[at:at + m, 0] = perm[k >> 32].int()
+            out[at:at + m, 1] = perm[k & 0xFFFFFFFF].int()
+            w = torch.clamp(torch.round(torch.exp(1.0 + torch.randn(m, generator=g, device=device))), min=1)
+            out[at:at + m, 2] = torch.clamp(w, max=2 ** 31 - 1).int()
+            at += m
+        del x
+    return n, out
 
 
 def run_scan(args):
@@ -272,7 +283,9 @@ def run_scan(args):
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    n, e = rmat_directed_device(args.scale, args.avg_degree << args.scale, synth.BASE_SEED + 3, "cuda")
+    n_req = args.vertices or (1 << args.scale)
+    n_edges = args.edges or args.avg_degree * n_req
+    n, e = rmat_directed_device(args.scale, n_edges, synth.BASE_SEED + 3, "cuda", n=n_req)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()   # the generator's temporaries go back to the device for the library
     log(f"generated directed R-MAT scale {args.scale}: n={n} edges={e.shape[0]} in {time.perf_counter() - t0:.1f}s; "
@@ -300,6 +313,7 @@ def run_scan(args):
            "vs_baseline": None,
            "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"rmat{args.scale}-directed-lognormal-full-frontier-scan", "n": n,
+                      "rmat_scale": args.scale,
                       "edges": int(e.shape[0]), "rmat": [0.57, 0.19, 0.19, 0.05], "weights": "lognormal(1,1) >= 1"},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "kernel": ldl.candidate_kernel_name(dom, True),
@@ -438,6 +452,8 @@ def main():
     ap.add_argument("--quality-sweep-n", type=int, default=200000)
     ap.add_argument("--quality-sweep-batch", type=int, default=5000)
     ap.add_argument("--avg-degree", type=int, default=16)
+    ap.add_argument("--vertices", type=int, default=0, help="scan: vertex count below 2^scale (ids >= it rejected)")
+    ap.add_argument("--edges", type=int, default=0, help="scan: edge count (default avg-degree x vertices)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--graphs", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)

@@ -20,7 +20,9 @@
  *     allocations the graph and partition are unchanged.  After LDL_EDEVICE, or LDL_ENOMEM
  *     once the update has started (a pool that cannot grow), the handle is poisoned and every
  *     later call returns LDL_EBROKEN.
- *   - A batch holds fewer than 2^31 updates (2^30 for undirected graphs), else LDL_EINVAL.
+ *   - A batch holds fewer than 2^31 updates (2^30 for undirected graphs), else LDL_EINVAL; an
+ *     insert-only batch into a graph without entries and without aggregate levels (the first
+ *     batch, as at creation) may hold up to 2^32 - 1.
  *   - Vertices are 0..n-1 (n fixed at creation).  Undirected pairs are unordered.
  *   - Input arrays are owned by the caller and only read during the call; the handle owns
  *     all device memory it allocates.  A handle is not thread-safe; distinct handles may be

@@ -180,6 +180,7 @@ struct Engine {
   uint64_t *tcounts = nullptr, *toffs = nullptr, *tcur = nullptr, *it_cnt = nullptr, *it_off = nullptr;
   HubWork hw{};
   uint64_t part_cap = 0;
+  uint64_t hw_cap = 0;   // entries of hw.cnt / hw.off / hw.own
   CandBuf cand{};
   HubPool hub{};
   // growable record buffers
@@ -410,9 +411,6 @@ struct Engine {
     tcur = alloc<uint64_t>((uint64_t)n + 1);
     it_cnt = alloc<uint64_t>((uint64_t)n + 1);
     it_off = alloc<uint64_t>((uint64_t)n + 1);
-    hw.cnt = alloc<U64x3>((uint64_t)n + 1);
-    hw.off = alloc<U64x3>((uint64_t)n + 1);
-    hw.own = alloc<int64_t>((uint64_t)n + 1);
     cand.v = alloc<uint32_t>(n);
     cand.a = alloc<uint32_t>(n);
     cand.b = alloc<uint32_t>(n);
@@ -423,7 +421,7 @@ struct Engine {
     hub.over_count = &ds->ps.hub_over;
     hw.pshift = 0;
     hw.tslots = (test_flags & 16) ? 64u : kPartSlots;
-    hub_pool((test_flags & 2) ? 0 : 4ull * n);
+    hub_pool((test_flags & 2) ? 0 : std::min<uint64_t>(4ull * n, 1ull << 26));
     hcheck(hipStreamSynchronize(st));
   }
 
@@ -431,7 +429,7 @@ struct Engine {
   // (partition counts and cursors start at zero; the hub kernels return them to zero)
   void hub_pool(uint64_t entries) {
     uint64_t hc = (test_flags & 2) ? 256 : 1ull << 16;
-    while (hc < entries) hc <<= 1;
+    if (hc < entries) hc = (entries + entries / 8 + 0xFFFF) & ~0xFFFFull;
     release(hub.ekey);
     release(hub.bkey);
     release(hub.bw);
@@ -442,7 +440,20 @@ struct Engine {
     hub.bkey = alloc<uint32_t>(hc);
     hub.bw = alloc<int64_t>(hc);
     hub.cap = hc;
-    const uint64_t parts = hc / 16 + (uint64_t)n + 2;
+  }
+  // per-hub work arrays for at most `bound` hubs and partition arrays for the pool's entries (a
+  // hub of T entries has ceil(T 2^pshift / kPartEntries) partitions, at most one per 16 entries);
+  // partition counts and cursors start at zero and the hub kernels return them to zero
+  void hub_work(uint32_t bound) {
+    const uint64_t per = std::min<uint64_t>((hub.cap << hw.pshift) / kPartEntries, hub.cap / 16);
+    const uint64_t parts = per + (uint64_t)bound + 2;
+    if ((uint64_t)bound + 1 <= hw_cap && parts <= part_cap) return;
+    hcheck(hipStreamSynchronize(st));   // queued hub passes may still use the arrays
+    if ((uint64_t)bound + 1 > hw_cap) {
+      const uint64_t c = std::min<uint64_t>((uint64_t)n + 1, (uint64_t)bound + 1 + bound / 4);
+      regrow(hw.cnt, c); regrow(hw.off, c); regrow(hw.own, c);
+      hw_cap = c;
+    }
     if (parts > part_cap) {
       regrow(hw.phi, parts); regrow(hw.plo, parts); regrow(hw.pid, parts); regrow(hw.pvalid, parts);
       regrow(hw.pcount, parts); regrow(hw.pcur, parts); regrow(hw.poff, parts); regrow(hw.pcnt, parts);
@@ -661,9 +672,10 @@ struct Engine {
   // ------------------------------------------------------------------ bulk load
   // An insert-only batch into a graph without entries and without aggregate levels (the first
   // batch: static Leiden at creation, Sec. IV-E) lays its rows out directly from the sorted
-  // records: two ping-pong sorts and a placement pass, with no lookup or row-update buffers, so
-  // a graph of k edges needs about 24 bytes per edge of transient memory (72 for undirected
-  // graphs, whose entries are mirrored) beside its adjacency.  The resulting matrix, degrees, totals and seeds are those of
+  // records: a ping-pong sort and a placement pass, with no lookup or row-update buffers; the
+  // in-rows of a directed graph are filled by scattering the same records.  A graph of k edges
+  // needs 24 bytes per edge of transient memory during the sort and 12 afterwards (undirected
+  // graphs: 12 per mirrored entry more) beside its adjacency.  The resulting matrix, degrees, totals and seeds are those of
   // the general path; rows hold their entries in column order, with the same per-row slack.
   bool bulk_eligible(uint64_t nd, uint64_t nc) const {
     return nd == 0 && nc == 0 && top == 0 && m == 0 && !(test_flags & 32);   // m == 0: no entry at all
@@ -677,21 +689,27 @@ struct Engine {
       ps.push_back((void*)p);
       return p;
     }
+    void drop(void* p) {   // release early (after the stream has drained)
+      hcheck(hipStreamSynchronize(e->st));
+      e->release(p);
+      ps.erase(std::find(ps.begin(), ps.end(), p));
+    }
     ~Transient() {
       for (void* p : ps) e->release(p);
     }
   };
+  void bulk_drop_pool(Csr& c) {   // a pool whose rows are all empty: laid out anew
+    hcheck(hipStreamSynchronize(st));
+    release(c.ref.nbr);
+    release(c.ref.w);
+    c.ref.nbr = nullptr;
+    c.ref.w = nullptr;
+    c.pool_cap = 0;
+  }
   // rows of c (level 0, no entry) from a sorted entry list
   void bulk_rows(Csr& c, const uint64_t* keys, const uint32_t* wts, uint64_t E, int64_t* rowsum,
                  const uint32_t* lab_or_null) {
-    if (c.ref.nbr) {   // a pool whose rows are all empty: laid out anew
-      hcheck(hipStreamSynchronize(st));
-      release(c.ref.nbr);
-      release(c.ref.w);
-      c.ref.nbr = nullptr;
-      c.ref.w = nullptr;
-      c.pool_cap = 0;
-    }
+    if (c.ref.nbr) bulk_drop_pool(c);
     uint64_t* start = tcounts;   // n + 1 words each; no aggregation pass is running
     uint64_t* end = toffs;
     hcheck(hipMemsetAsync(start, 0, 8ull * n, st));
@@ -725,21 +743,29 @@ struct Engine {
     if (dm >= ((uint64_t)1 << 40) || m + (int64_t)dm >= ((int64_t)1 << 40)) return LDL_EOVERFLOW;
     mutating = true;
     Level& V0 = lv[0];
+    t.drop(kfree);   // the ping-pong halves are not needed any more
+    t.drop(vfree);
     if (directed) {
-      launch_bulk_transpose(keys, wts, K, kfree, vfree, id_bits, st);   // in-adjacency records
       bulk_rows(V0.out, keys, wts, K, V0.kout, V0.lab);
-      int sel2 = 0;
-      cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, kfree, keys, vfree, wts, K, 0, 2 * id_bits, &sel2, st));
-      bulk_rows(V0.in, sel2 ? keys : kfree, sel2 ? wts : vfree, K, V0.kin, nullptr);
+      // in-rows: column counts, the layout, then every record scattered to its column's row
+      // (entry order inside a row carries no meaning)
+      launch_bulk_count_cols(keys, K, V0.in.ref.deg, id_bits, st);
+      if (V0.in.ref.nbr) bulk_drop_pool(V0.in);
+      csr_grow(V0.in, 0, 3);
+      uint32_t* cursor = t.get<uint32_t>(n);
+      hcheck(hipMemsetAsync(cursor, 0, 4ull * n, st));
+      launch_bulk_scatter_in(keys, wts, K, V0.in.ref, cursor, V0.kin, id_bits, st);
     } else {
-      uint64_t* e0 = t.get<uint64_t>(2 * K);
-      uint64_t* e1 = t.get<uint64_t>(2 * K);
-      uint32_t* w0 = t.get<uint32_t>(2 * K);
-      uint32_t* w1 = t.get<uint32_t>(2 * K);
       zero(&ds->ecount);
+      uint64_t* e0 = t.get<uint64_t>(2 * K);
+      uint32_t* w0 = t.get<uint32_t>(2 * K);
       launch_bulk_mirror(keys, wts, K, e0, w0, &ds->ecount, id_bits, st);
       sync_read();
       const uint64_t E = hs->ecount;
+      t.drop(keys);
+      t.drop(wts);
+      uint64_t* e1 = t.get<uint64_t>(E);
+      uint32_t* w1 = t.get<uint32_t>(E);
       int sel2 = 0;
       cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, e0, e1, w0, w1, E, 0, 2 * id_bits, &sel2, st));
       bulk_rows(V0.out, sel2 ? e1 : e0, sel2 ? w1 : w0, E, V0.kout, V0.lab);
@@ -872,6 +898,8 @@ struct Engine {
     const uint32_t* list = sets[sid].list;
     const uint32_t* cnt = &ds->counts[sets[sid].ci];
     const int cat0 = 2 * kNumBins * refine + kNumBins * lv[r].out.ref.wide;
+    const uint32_t hb = hub_bound(r);
+    if (hb) hub_work(hb);   // grows (rarely) before the search is queued, outside its timing
     std::pair<hipEvent_t, hipEvent_t> whole{};
     if (profile) {
       whole = next_events();
@@ -879,7 +907,6 @@ struct Engine {
     }
     launch_bin_count(mv, list, cnt, refine, bhist, (uint32_t*)&ds->ps, sizeof(PassScal) / 4, st);
     launch_bin_fill(mv, list, cnt, refine, bhist, binbuf, ds->bin_start, ds->bins, st);
-    const uint32_t hb = hub_bound(r);
     for (int b = 0; b < kNumBins; ++b) {
       if (b == kNumBins - 1 && hb == 0) break;
       if (b < kNumBins - 1 && mv.lim[b] == (b ? mv.lim[b - 1] : 0u)) continue;   // no entry count maps here
@@ -1492,7 +1519,8 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
   if (!h) return LDL_EINVAL;
   if (h->e->broken) return LDL_EBROKEN;
   if ((ni && !ins) || (nd && !del) || (nc && !chg)) return LDL_EINVAL;
-  if (ni + nd + nc >= (1ull << (h->e->directed ? 31 : 30))) return LDL_EINVAL;
+  const bool bulk = h->e->bulk_eligible(nd, nc);   // laid out from 64-bit-count sorts
+  if (ni + nd + nc >= (1ull << (bulk ? 32 : (h->e->directed ? 31 : 30)))) return LDL_EINVAL;
   h->e->mutating = false;
   return run_guarded(h, [&]() -> int {
     ldl::Engine& e = *h->e;

@@ -1288,13 +1288,23 @@ __global__ void k_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_
   }
 }
 
-// (row, col, w) -> (col, row, w) for the in-adjacency of a directed graph
-__global__ void k_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys,
-                                 uint32_t* twts, int ks) {
+// in-degree of every column of a directed bulk load (deg zero at launch)
+__global__ void k_bulk_count_cols(const uint64_t* keys, uint64_t k, uint32_t* deg, int ks) {
+  for (uint64_t i = gtid(); i < k; i += gstride()) atomicAdd(&deg[kcol(keys[i], ks)], 1u);
+}
+
+// every record (u, v, w) into the in-row of v at the row's next free slot (cursor zero at launch;
+// exactly deg[v] records have column v), its weight added to kin[v]
+__global__ void k_bulk_scatter_in(const uint64_t* keys, const uint32_t* wts, uint64_t k, CsrRef in, uint32_t* cursor,
+                                  int64_t* kin, int ks) {
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const uint64_t key = keys[i];
-    tkeys[i] = kpack(kcol(key, ks), krow(key, ks), ks);
-    twts[i] = wts[i];
+    const uint32_t u = krow(key, ks), v = kcol(key, ks);
+    const uint32_t w = wts[i];
+    const uint64_t slot = in.off[v] + atomicAdd(&cursor[v], 1u);
+    in.nbr[slot] = u;
+    ((uint32_t*)in.w)[slot] = w;
+    atomic_add_i64(&kin[v], (int64_t)w);
   }
 }
 
@@ -1666,9 +1676,12 @@ void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, u
                         u64a* count, int ks, hipStream_t s) {
   if (k) k_bulk_mirror<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, ekeys, ew, count, ks);
 }
-void launch_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys, uint32_t* twts,
-                           int ks, hipStream_t s) {
-  if (k) k_bulk_transpose<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, tkeys, twts, ks);
+void launch_bulk_count_cols(const uint64_t* keys, uint64_t k, uint32_t* deg, int ks, hipStream_t s) {
+  if (k) k_bulk_count_cols<<<grid_for(k), kTpb, 0, s>>>(keys, k, deg, ks);
+}
+void launch_bulk_scatter_in(const uint64_t* keys, const uint32_t* wts, uint64_t k, CsrRef in, uint32_t* cursor,
+                            int64_t* kin, int ks, hipStream_t s) {
+  if (k) k_bulk_scatter_in<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, in, cursor, kin, ks);
 }
 void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, uint32_t n, uint32_t* deg,
                       int ks, hipStream_t s) {

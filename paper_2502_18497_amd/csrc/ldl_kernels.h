@@ -204,8 +204,11 @@ void launch_bulk_check(const uint64_t* keys, const uint32_t* wts, uint64_t k, in
 // undirected: (u, v, w) and (v, u, w) for u != v appended at *count (2k entries of room)
 void launch_bulk_mirror(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* ekeys, uint32_t* ew,
                         u64a* count, int ks, hipStream_t s);
-void launch_bulk_transpose(const uint64_t* keys, const uint32_t* wts, uint64_t k, uint64_t* tkeys, uint32_t* twts,
-                           int ks, hipStream_t s);
+// directed in-rows: column counts into deg (zero at launch), then every record scattered to its
+// column's row (cursor: n zeroed words) with its weight added to kin
+void launch_bulk_count_cols(const uint64_t* keys, uint64_t k, uint32_t* deg, int ks, hipStream_t s);
+void launch_bulk_scatter_in(const uint64_t* keys, const uint32_t* wts, uint64_t k, CsrRef in, uint32_t* cursor,
+                            int64_t* kin, int ks, hipStream_t s);
 // row bounds of a sorted entry list (start and end: n zeroed words each) and row degrees
 void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_t* end, uint32_t n, uint32_t* deg,
                       int ks, hipStream_t s);

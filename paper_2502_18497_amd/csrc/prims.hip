@@ -1,6 +1,7 @@
-// Library primitives (radix sort, reduce-by-key, scan, max) from hipCUB, with temporary
+// Library primitives (radix sort, reduce-by-key, scan, max) from hipCUB and rocPRIM, with temporary
 // storage grown on demand.
 #include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "ldl_kernels.h"
 
@@ -64,23 +65,25 @@ int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, 
              : -1;
 }
 
-// Ping-pong form: the sorted pairs end in buffers 0 or 1 (*sel), both of which are overwritten;
-// the temporary storage is independent of n's element size (no internal copy of the data).
+// Ping-pong form with a 64-bit count (rocPRIM sorts in batches of 2^30 items): the sorted pairs
+// end in buffers 0 or 1 (*sel), both of which are overwritten; the temporary storage does not hold
+// a copy of the data.
 int prim_sort_pairs_u64_u32_db(void** tmp, size_t* tmp_bytes, uint64_t* k0, uint64_t* k1, uint32_t* v0, uint32_t* v1,
                                uint64_t n, int begin_bit, int end_bit, int* sel, hipStream_t s) {
   *sel = 0;
   if (n == 0) return 0;
-  if (n > (uint64_t)INT32_MAX) return -2;
-  hipcub::DoubleBuffer<uint64_t> keys(k0, k1);
-  hipcub::DoubleBuffer<uint32_t> vals(v0, v1);
+  rocprim::double_buffer<uint64_t> keys(k0, k1);
+  rocprim::double_buffer<uint32_t> vals(v0, v1);
+  const size_t count = (size_t)n;
   size_t need = 0;
-  if (hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, vals, (int)n, begin_bit, end_bit, s) != hipSuccess)
+  if (rocprim::radix_sort_pairs(nullptr, need, keys, vals, count, (unsigned)begin_bit, (unsigned)end_bit, s) !=
+      hipSuccess)
     return -1;
   if (ensure(tmp, tmp_bytes, need)) return -2;
   size_t have = *tmp_bytes;
-  if (hipcub::DeviceRadixSort::SortPairs(*tmp, have, keys, vals, (int)n, begin_bit, end_bit, s) != hipSuccess)
+  if (rocprim::radix_sort_pairs(*tmp, have, keys, vals, count, (unsigned)begin_bit, (unsigned)end_bit, s) != hipSuccess)
     return -1;
-  *sel = keys.selector;
+  *sel = keys.current() == k0 ? 0 : 1;
   return 0;
 }
 
