@@ -57,6 +57,21 @@ def test_rmat17_undirected_batches_of_1e4():
     run_parity(s.n, s.edges(), _batches(s, [10000, 10000, 1000]))
 
 
+def test_rmat18_undirected_batch_of_1e5():
+    # undirected R-MAT at 2^18 vertices (2,097,152 edges) with a batch of 10^5 updates, bit-exact
+    s = synth.rmat_undirected(scale=18, seed_offset=503)
+    run_parity(s.n, s.edges(), _batches(s, [100000, 10000]))
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_planted_1e5_batches_of_1e4(directed):
+    # planted partition with 100,000 vertices in blocks of 100, average degree 16, mixing 0.4 (the
+    # shape of the batched form's larger graphs), batches of 10^4, bit-exact
+    s = synth.Stream(100000, directed, synth.BASE_SEED + (502 if directed else 501))
+    s.planted(100, 0.6 * 16 / 99, 0.4 * 16 / (100000 - 100), 1, 8)
+    run_parity(s.n, s.edges(), _batches(s, [10000, 1000]), directed=directed)
+
+
 def test_rmat_directed_lognormal():
     s = synth.rmat_directed_lognormal(1 << 12, 16 * (1 << 12), seed_offset=120)
     e = s.edges()
