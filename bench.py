@@ -413,6 +413,74 @@ def run_quality(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sweep(args):
+    """Batch regimes and a parameter sweep on a planted partition (synthetic versions of the kind of
+    evidence in the paper's Tab. VI and its parameter study).  Regimes: the graph's edges, in a
+    seeded shuffled order, streamed as 1, 10, 100 and 1000 insert-only batches into an empty handle;
+    total GPU time of the batches, final modularity and NMI against the planted blocks, and the
+    GPU time of static Leiden run from scratch after every batch (measured at up to 10 evenly
+    spaced batches, their mean times the number of batches).  Parameters: N, L, M, alpha and beta
+    varied one at a time around the defaults; static Leiden on the graph, then the same 20 batches
+    of 10^3 updates (70/20/10) for every setting; mean update time and final modularity and NMI."""
+    import numpy as np
+    import torch  # noqa: F401
+    from sklearn.metrics import normalized_mutual_info_score
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    n, mu, d = args.sweep_n, args.quality_mu, 16.0
+    truth = np.arange(n) // 100
+    s = synth.Stream(n, False, synth.BASE_SEED + 8)
+    s.planted(100, min(1.0, (1.0 - mu) * d / 99), mu * d / (n - 100), 1, 8)
+    e = s.edges()
+    e = e[np.random.default_rng(8).permutation(len(e))]
+    ldl.Graph(n, e).close()   # warm-up: first-use costs of the process stay out of the timings
+    regimes = []
+    for B in args.sweep_regimes:
+        g = ldl.Graph(n, np.zeros((0, 3), np.uint32))
+        chunks = np.array_split(e, B)
+        probe = set(np.linspace(0, B - 1, min(B, 10)).round().astype(int).tolist())
+        total_ms, rerun_ms = 0.0, []
+        for i, c in enumerate(chunks):
+            total_ms += g.apply_batch(ins=c)["total_ms"]
+            if i in probe:
+                gs = ldl.Graph(n, np.zeros((0, 3), np.uint32))
+                rerun_ms.append(gs.apply_batch(ins=e[: sum(len(x) for x in chunks[: i + 1])])["total_ms"])
+                gs.close()
+        regimes.append({"batches": B, "edges_per_batch": int(len(e) // B), "total_ms": total_ms,
+                        "rerun_total_ms_est": float(np.mean(rerun_ms) * B),
+                        "Q": g.modularity(), "NMI": float(normalized_mutual_info_score(truth, g.partition()))})
+        g.close()
+        log(f"{B} batches: {total_ms:.1f} ms in all, reruns ~{regimes[-1]['rerun_total_ms_est']:.0f} ms, "
+            f"Q {regimes[-1]['Q']:.4f}")
+    base = dict(N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100))
+    variants = [("default", {})] + [(f"N={v}", {"N": v}) for v in (1, 3)] + [(f"L={v}", {"L": v}) for v in (1, 2, 8)] + \
+               [(f"M={v}", {"M": v}) for v in (1, 3, 10)] + [("alpha=0", {"alpha": (0, 1)}), ("alpha=1/100", {"alpha": (1, 100)})] + \
+               [("beta=0", {"beta": (0, 1)}), ("beta=1/10", {"beta": (1, 10)})]
+    s2 = synth.Stream(n, False, synth.BASE_SEED + 9)
+    s2.planted(100, min(1.0, (1.0 - mu) * d / 99), mu * d / (n - 100), 1, 8)
+    e2 = s2.edges()
+    stream = [s2.batch(args.sweep_batch) for _ in range(args.sweep_batches)]
+    params = []
+    for name, over in variants:
+        cfg = dict(base, **over)
+        g = ldl.Graph(n, e2, **cfg)
+        ms = [g.apply_batch(b.ins, b.dels, b.chg)["total_ms"] for b in stream]
+        params.append({"setting": name, "update_ms_mean": float(np.mean(ms)), "Q": g.modularity(),
+                       "NMI": float(normalized_mutual_info_score(truth, g.partition()))})
+        g.close()
+        log(f"{name}: {params[-1]['update_ms_mean']:.2f} ms per batch, Q {params[-1]['Q']:.4f}")
+    out = {"metric": "batch regimes and parameter sweep (time, modularity)", "value": regimes[-1]["total_ms"],
+           "unit": "ms", "n_gpus": 1, "steps": len(regimes) + len(params), "warmup": 0,
+           "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"planted-{n}-blocks-of-100-mu{mu}-degree16", "n": n, "edges": int(len(e)),
+                      "sweep_batch": args.sweep_batch, "sweep_batches": args.sweep_batches},
+           "regimes": regimes, "parameters": params}
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of a known size (torch's copy kernel),
     repeated a few times; rocprofv3 FETCH_SIZE / WRITE_SIZE of these dispatches give the factor
@@ -442,7 +510,7 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
-    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality"], default="rmat")
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep"], default="rmat")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
     ap.add_argument("--quality-batch", type=int, default=500)
@@ -452,6 +520,10 @@ def main():
     ap.add_argument("--quality-sweep-n", type=int, default=200000)
     ap.add_argument("--quality-sweep-batch", type=int, default=5000)
     ap.add_argument("--avg-degree", type=int, default=16)
+    ap.add_argument("--sweep-n", type=int, default=100000)
+    ap.add_argument("--sweep-regimes", type=int, nargs="+", default=[1, 10, 100, 1000])
+    ap.add_argument("--sweep-batch", type=int, default=1000)
+    ap.add_argument("--sweep-batches", type=int, default=20)
     ap.add_argument("--vertices", type=int, default=0, help="scan: vertex count below 2^scale (ids >= it rejected)")
     ap.add_argument("--edges", type=int, default=0, help="scan: edge count (default avg-degree x vertices)")
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -480,6 +552,8 @@ def main():
         return run_scan(args)
     if args.workload == "quality":
         return run_quality(args)
+    if args.workload == "sweep":
+        return run_sweep(args)
 
     import numpy as np
     import torch
