@@ -327,6 +327,93 @@ def run_scan(args):
     print(json.dumps(out), flush=True)
 
 
+def run_bigstream(args):
+    """Batch updates on a large directed R-MAT graph (the scan workload's generator and sizes): static
+    Leiden at creation through the bulk load, then batches of updates generated on the device -- 70 %
+    insertions of uniform random pairs, 20 % deletions and 10 % weight changes (w -> w + 1) of
+    distinct original edges never touched before -- each applied with ldl_apply_batch_device.
+    Reports updates/s over the timed batches, per-batch latency and the candidate-search figures."""
+    import numpy as np
+    import torch
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    torch.cuda.set_device(0)
+    n_req = args.vertices or (1 << args.scale)
+    n_edges = args.edges or args.avg_degree * n_req
+    t0 = time.perf_counter()
+    n, e = rmat_directed_device(args.scale, n_edges, synth.BASE_SEED + 3, "cuda", n=n_req)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"generated directed R-MAT: n={n} edges={e.shape[0]} in {time.perf_counter() - t0:.1f}s")
+    g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=True, L=args.big_L, N=args.big_N, M=args.big_M,
+                  profile=True)
+    t0 = time.perf_counter()
+    st0 = g.apply_batch_device(e, None, None)
+    torch.cuda.synchronize()
+    log(f"static Leiden (L={args.big_L}, N={args.big_N}, M={args.big_M}) by bulk load in {time.perf_counter() - t0:.2f}s; "
+        f"device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.BASE_SEED + 11)
+    E = e.shape[0]
+    used = torch.zeros(E, dtype=torch.bool, device="cuda")
+
+    def batch(size):
+        nd, nc = size // 5, size // 10
+        ni = size - nd - nc
+        idx = torch.empty(0, dtype=torch.int64, device="cuda")
+        while idx.numel() < nd + nc:   # distinct original edges never deleted or changed before
+            cand = torch.unique(torch.randint(0, E, (2 * (nd + nc),), generator=gen, device="cuda"))
+            cand = cand[~used[cand]]
+            idx = torch.unique(torch.cat([idx, cand]))
+        idx = idx[torch.randperm(idx.numel(), generator=gen, device="cuda")[: nd + nc]]
+        used[idx] = True
+        dels = e[idx[:nd], :2].contiguous()
+        chg = e[idx[nd:]].clone()
+        chg[:, 2] += 1
+        taken = (e[idx, 0].long() << 32) | e[idx, 1].long()
+        ins = torch.empty((0, 2), dtype=torch.int64, device="cuda")
+        while ins.shape[0] < ni:       # distinct random pairs, none of them deleted or changed here
+            p = torch.randint(0, n, (2 * ni, 2), generator=gen, device="cuda")
+            p = p[p[:, 0] != p[:, 1]]
+            k = torch.unique(torch.cat([(ins[:, 0] << 32) | ins[:, 1], (p[:, 0] << 32) | p[:, 1]]))
+            k = k[~torch.isin(k, taken)]
+            ins = torch.stack([k >> 32, k & 0xFFFFFFFF], dim=1)
+        ins = ins[torch.randperm(ins.shape[0], generator=gen, device="cuda")[:ni]]
+        w = torch.randint(1, 17, (ni, 1), generator=gen, device="cuda")
+        return torch.cat([ins, w], dim=1).int().contiguous(), dels, chg
+
+    batches = [batch(args.batch) for _ in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+    for b in batches[: args.warmup]:
+        g.apply_batch_device(*b)
+    torch.cuda.synchronize()
+    lat, stats = [], []
+    t0 = time.perf_counter()
+    for b in batches[args.warmup:]:
+        t1 = time.perf_counter()
+        stats.append(g.apply_batch_device(*b))
+        lat.append(time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    upd = args.batch * args.steps
+    log(f"timed {args.steps} batches of {args.batch}: {T:.2f}s")
+    out = {"metric": "batch edges/s (large directed graph)", "value": upd / T, "unit": "edges/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"rmat{args.scale}-directed-lognormal-batch{args.batch}", "n": n, "edges": int(E),
+                      "batch": args.batch, "mix": "70/20/10 insert/delete/reweight", "L": args.big_L, "N": args.big_N,
+                      "M": args.big_M},
+           "latency_ms": {"p50": float(1e3 * np.percentile(lat, 50)), "p99": float(1e3 * np.percentile(lat, 99))},
+           "static_ms": float(st0["total_ms"]),
+           "candidate_search_ms_per_step": float(np.mean([x["search_ms"] for x in stats])),
+           "scanned_entries_per_step": float(np.mean([x["scanned_entries"] for x in stats])),
+           "move_iters_per_step": float(np.mean([x["move_iters"] for x in stats])),
+           "host_syncs_per_step": float(np.mean([x["host_syncs"] for x in stats]))}
+    print(json.dumps(out), flush=True)
+
+
 def modularity_of(n, edges, labels):
     """Eq. 1 (undirected, gamma = 1) of a labelling, from the edge list: the reference value of
     the planted blocks."""
@@ -510,7 +597,8 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
-    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep"], default="rmat")
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream"],
+                    default="rmat")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
     ap.add_argument("--quality-batch", type=int, default=500)
@@ -520,6 +608,9 @@ def main():
     ap.add_argument("--quality-sweep-n", type=int, default=200000)
     ap.add_argument("--quality-sweep-batch", type=int, default=5000)
     ap.add_argument("--avg-degree", type=int, default=16)
+    ap.add_argument("--big-L", type=int, default=0, help="bigstream: hierarchy levels of the handle")
+    ap.add_argument("--big-N", type=int, default=2)
+    ap.add_argument("--big-M", type=int, default=5)
     ap.add_argument("--sweep-n", type=int, default=100000)
     ap.add_argument("--sweep-regimes", type=int, nargs="+", default=[1, 10, 100, 1000])
     ap.add_argument("--sweep-batch", type=int, default=1000)
@@ -554,6 +645,8 @@ def main():
         return run_quality(args)
     if args.workload == "sweep":
         return run_sweep(args)
+    if args.workload == "bigstream":
+        return run_bigstream(args)
 
     import numpy as np
     import torch
