@@ -73,7 +73,7 @@ typedef struct ldl_pair {
  *   profile             nonzero: time the local-move kernels with HIP events (see stats)
  *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
  *                       results unchanged: 1 = one decoupling round between host checks (second
- *                       commit phase), 2 = minimal hub hash-table pool (overflow and redo of an
+ *                       commit phase), 2 = minimal hub bucket pool (overflow and redo of an
  *                       iteration), 4 = no spare adjacency capacity (row moves, pool growth),
  *                       8 = always queue the one-workgroup decoupling filter first (iterations
  *                       with more candidates than it holds run the filter after the host check),
@@ -125,7 +125,7 @@ typedef struct ldl_batch_stats {
   uint64_t host_syncs;        /* stream synchronisations (host reads of device counters)  */
   uint64_t agg_records;       /* reduced records applied to levels above 0                */
   double search_ms;           /* summed time of whole candidate searches: binning, every bin's
-                                 kernel and the hub path's table scan and final reduction
+                                 kernel and the hub path's passes and final reduction
                                  (HIP events, profile != 0)                                  */
 } ldl_batch_stats;
 

@@ -106,8 +106,8 @@ def _with_hub(n, base_edges, hub, k, seed):
     return np.concatenate([base_edges, np.array(extra, dtype=np.uint32)])
 
 
-def test_hub_vertex_global_table():
-    # one vertex adjacent to ~5,000 others exercises the global-memory hash bin
+def test_hub_vertex_partitioned_path():
+    # one vertex adjacent to ~5,000 others takes the multi-workgroup hub path (hash partitions)
     s = synth.Stream(8000, False, synth.BASE_SEED + 130)
     s.planted(100, 0.08, 0.0005, 1, 8)
     e = _with_hub(8000, s.edges(), 17, 5200, 7)

@@ -2,7 +2,7 @@
 every result bit-identical to the oracle:
   1  one decoupling round between host checks: live candidates remain after the speculative
      pass, so the filter is finished and its moves committed as a second phase
-  2  minimal hub hash-table pool: hub tables overflow, the iteration is undone and redone
+  2  minimal hub bucket pool: the hub buckets overflow, the iteration is undone and redone
   4  no spare adjacency capacity: every insertion moves its row, pools grow under load
   8  the one-workgroup decoupling filter is always queued first: iterations with more candidates
      than it holds run the rounds after the host check and commit everything as a second phase
