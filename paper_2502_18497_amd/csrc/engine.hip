@@ -64,7 +64,7 @@ static T* dalloc(uint64_t count) {
 struct PassScal {
   u64a st_entries[kNumBins], st_distinct[kNumBins], st_vertices[kNumBins], st_cands[kNumBins];
   u64a maxhi;       // max high word of the candidates' gains
-  u64a hub_need;    // pool slots the hub tables needed
+  u64a hub_need;    // bucket-pool entries the hub passes needed
   uint32_t ncand;
   uint32_t hub_over;
   // commit of the iteration: exact changes of Ein and sum Kout*Kin, touched communities
