@@ -793,7 +793,19 @@ struct Engine {
              uint64_t nc) {
     const uint64_t K = ni + nd + nc;
     if (K == 0) return LDL_OK;
-    if (bulk_eligible(nd, nc)) return bulk_ingest(dins, ni);
+    if (bulk_eligible(nd, nc)) {
+      const int rc = bulk_ingest(dins, ni);
+      if (rc == LDL_OK && !(test_flags & 2)) {
+        // the first search scans every vertex: size the hub bucket pool for level 0's hubs now
+        // (after the load's transient buffers are gone) instead of growing it in a redo
+        zero(&ds->tneed);
+        launch_hub_entries(lv[0].out.ref.deg, directed ? lv[0].in.ref.deg : nullptr, n, lim[0][kNumBins - 2],
+                           &ds->tneed, st);
+        sync_read();
+        if (hs->tneed > hub.cap) hub_pool(hs->tneed);
+      }
+      return rc;
+    }
     ensure_records(K);
     ensure_entries(2 * K);
     ensure_tuples(2 * K);

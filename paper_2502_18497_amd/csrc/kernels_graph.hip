@@ -1361,6 +1361,25 @@ __global__ void k_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t
   if (lane == 0 && in_sum) atomicAdd((u64a*)dein, (u64a)in_sum);
 }
 
+// entries of the vertices with more than `lim` entries (out + in): the hub entries of a full scan
+__global__ void k_hub_entries(const uint32_t* dout, const uint32_t* din_or_null, uint32_t n, uint32_t lim,
+                              u64a* total) {
+  __shared__ uint64_t part[kTpb / kWave];
+  uint64_t sum = 0;
+  for (uint64_t x = gtid(); x < n; x += gstride()) {
+    const uint64_t t = (uint64_t)dout[x] + (din_or_null ? din_or_null[x] : 0u);
+    if (t > lim) sum += t;
+  }
+  sum = (uint64_t)wave_sum_i64((int64_t)sum);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < kTpb / kWave; ++w) t += part[w];
+    if (t) atomicAdd(total, (u64a)t);
+  }
+}
+
 // Seeds and touched communities of a bulk load: every vertex with an entry is an endpoint of
 // the batch; its community is touched (old totals recorded before any total changes).
 __global__ void k_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout,
@@ -1692,6 +1711,13 @@ void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_
 void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
                        int64_t* rowsum, const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s) {
   if (k) k_bulk_place<<<grid_for(k), kTpb, 0, s>>>(keys, wts, k, start, c, rowsum, lab_or_null, dein, ks);
+}
+void launch_hub_entries(const uint32_t* dout, const uint32_t* din_or_null, uint32_t n, uint32_t lim, u64a* total,
+                        hipStream_t s) {
+  if (n) {
+    const unsigned g = grid_for(n) < kItemBlocks ? grid_for(n) : kItemBlocks;
+    k_hub_entries<<<g, kTpb, 0, s>>>(dout, din_or_null, n, lim, total);
+  }
 }
 void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
                       SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s) {

@@ -216,6 +216,9 @@ void launch_bulk_rows(const uint64_t* keys, uint64_t k, uint64_t* start, uint64_
 // intra-community weight into *dein
 void launch_bulk_place(const uint64_t* keys, const uint32_t* wts, uint64_t k, const uint64_t* start, CsrRef c,
                        int64_t* rowsum, const uint32_t* lab_or_null, i64a* dein, int ks, hipStream_t s);
+// *total += entries (out + in) of the vertices with more than lim entries (*total zero at launch)
+void launch_hub_entries(const uint32_t* dout, const uint32_t* din_or_null, uint32_t n, uint32_t lim, u64a* total,
+                        hipStream_t s);
 void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, const int64_t* Kout, const int64_t* Kin,
                       SetRef touched, int64_t* tko, int64_t* tki, SetRef seeds0, hipStream_t s);
 // Kout[lab0[x]] += kout[x] (and Kin with kin) for degrees that were zero before the load
