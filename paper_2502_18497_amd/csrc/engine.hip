@@ -1197,19 +1197,18 @@ struct Engine {
     Level& H = lv[r + 1];
     int64_t* Krin = directed ? H.kin : nullptr;
     if (r == top) launch_ref_init_top(n, V.alive, V.kout, V.kin, H.kout, Krin, V.rsize, st);
-    sync_read();
-    const uint32_t nMoved = count(S_MOVED);
+    // the list lengths below stay on the device (no host synchronisation before the iterations)
+    const uint32_t* nMoved = &ds->counts[sets[S_MOVED].ci];
     begin(S_REFM);
     launch_set_add_mapped(ref(S_REFM), entry, E0, V.par, nullptr, st);
-    launch_set_add_mapped(ref(S_REFM), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
+    launch_set_add_mapped(ref(S_REFM), sets[S_MOVED].list, n, V.par, nullptr, st, nMoved);
     begin(S_RSET);
     launch_mark_members(sets[S_RSET].stamp, sets[S_RSET].epoch, n, V.alive, V.par, sets[S_REFM].stamp,
                         sets[S_REFM].epoch, st);
     select_set(S_RSET);
-    sync_read();
-    const uint32_t nR0 = count(S_RSET);
-    launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st);
-    launch_ref_reset(sets[S_RSET].list, nR0, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 1, st);
+    const uint32_t* nR0 = &ds->counts[sets[S_RSET].ci];
+    launch_ref_reset(sets[S_RSET].list, n, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 0, st, nR0);
+    launch_ref_reset(sets[S_RSET].list, n, V.par, oldpar, V.kout, V.kin, H.kout, Krin, V.rsize, 1, st, nR0);
     launch_pack_lab_par(n, V.lab, V.par, lpk, st);   // refinement commits keep it current
     int cur = S_RSET;          // the set whose list this iteration scans
     bool rset_grew = false;    // SPExpand marked new members: rebuild the Rset list at the end
@@ -1243,13 +1242,12 @@ struct Engine {
   void aggregate(int r, uint32_t E0) {
     Level& V = lv[r];
     Level& H = lv[r + 1];
-    sync_read();
-    const uint32_t nRset = count(S_RSET), nMoved = count(S_MOVED);
     begin(S_C);
-    launch_mark_changed(sets[S_C].stamp, sets[S_C].epoch, sets[S_RSET].list, nRset, V.par, oldpar, st);
+    launch_mark_changed(sets[S_C].stamp, sets[S_C].epoch, sets[S_RSET].list, n, V.par, oldpar, st,
+                        &ds->counts[sets[S_RSET].ci]);
     select_set(S_C);
     sync_read();
-    const uint32_t nC = count(S_C);
+    const uint32_t nC = count(S_C), nRset = count(S_RSET), nMoved = count(S_MOVED);
     CsrRef in = directed ? V.in.ref : V.out.ref;
     const int Dn = S_D0 + r + 1;
     // both parents of every node in one word for the tuple kernels (lpk's storage is free here:
@@ -1275,11 +1273,10 @@ struct Engine {
     begin(S_LVC);
     launch_set_add_mapped(ref(S_LVC), sets[S_RSET].list, nRset, oldpar, nullptr, st);
     launch_set_add_mapped(ref(S_LVC), sets[S_RSET].list, nRset, V.par, nullptr, st);
-    sync_read();
     begin(S_DIED);
     begin(S_REV);
-    launch_live_update(sets[S_LVC].list, count(S_LVC), V.rsize, H.alive, r + 1 < L ? H.par : nullptr, H.lab, V.lab,
-                       ref(S_DIED), ref(S_REV), st);
+    launch_live_update(sets[S_LVC].list, n, V.rsize, H.alive, r + 1 < L ? H.par : nullptr, H.lab, V.lab,
+                       ref(S_DIED), ref(S_REV), st, &ds->counts[sets[S_LVC].ci]);
     launch_label_up(sets[S_RSET].list, nRset, V.par, H.alive, V.lab, H.lab, st);
     int died = S_DIED, rev = S_REV, died2 = S_DIED2, rev2 = S_REV2;
     for (int s = r + 2; s <= top; ++s) {
@@ -1288,11 +1285,10 @@ struct Engine {
       if (nd + nrv == 0) break;
       begin(S_LVC);
       launch_live_prop(sets[died].list, nd, sets[rev].list, nrv, lv[s - 1].par, lv[s - 1].rsize, ref(S_LVC), st);
-      sync_read();
       begin(died2);
       begin(rev2);
-      launch_live_update(sets[S_LVC].list, count(S_LVC), lv[s - 1].rsize, lv[s].alive, s < L ? lv[s].par : nullptr,
-                         lv[s].lab, lv[s - 1].lab, ref(died2), ref(rev2), st);
+      launch_live_update(sets[S_LVC].list, n, lv[s - 1].rsize, lv[s].alive, s < L ? lv[s].par : nullptr, lv[s].lab,
+                         lv[s - 1].lab, ref(died2), ref(rev2), st, &ds->counts[sets[S_LVC].ci]);
       std::swap(died, died2);
       std::swap(rev, rev2);
     }

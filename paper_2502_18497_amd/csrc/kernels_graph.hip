@@ -23,6 +23,17 @@ __device__ __forceinline__ uint64_t gstride() { return (uint64_t)gridDim.x * blo
 __device__ __forceinline__ uint64_t gwave() { return ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; }
 __device__ __forceinline__ uint64_t gwstride() { return (uint64_t)gridDim.x * blockDim.x / kWave; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+// a list length given on the host (bound) or, when countp is set, read on the device and capped
+__device__ __forceinline__ uint32_t list_len(const uint32_t* countp, uint32_t bound) {
+  if (!countp) return bound;
+  const uint32_t c = *countp;
+  return c < bound ? c : bound;
+}
+// grid of a launch whose length may be read on the device (grid-stride loops)
+inline unsigned list_grid(uint32_t bound, const uint32_t* countp) {
+  const unsigned g = grid_for(bound);
+  return countp && g > 1024u ? 1024u : g;
+}
 
 __device__ __forceinline__ int64_t wget(const CsrRef& c, uint64_t i) {
   return c.wide ? ((const int64_t*)c.w)[i] : (int64_t)((const uint32_t*)c.w)[i];
@@ -79,8 +90,9 @@ __global__ void k_copy_i64(int64_t* d, const int64_t* s, uint64_t n) {
 __global__ void k_set_add_list(SetRef set, const uint32_t* list, uint32_t count) {
   for (uint64_t i = gtid(); i < count; i += gstride()) set_add(set.stamp, set.epoch, set.list, set.count, list[i]);
 }
-__global__ void k_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, const uint32_t* key,
-                                 const uint8_t* alive) {
+__global__ void k_set_add_mapped(SetRef set, const uint32_t* list, uint32_t bound, const uint32_t* countp,
+                                 const uint32_t* key, const uint8_t* alive) {
+  const uint32_t count = list_len(countp, bound);
   for (uint64_t i = gtid(); i < count; i += gstride()) {
     uint32_t x = list[i];
     if (alive && !alive[x]) continue;
@@ -858,8 +870,10 @@ __global__ void k_ref_init_top(uint32_t n, const uint8_t* alive, const int64_t* 
 }
 
 // phase 0: record the old parent and take the node out of it; phase 1: make it a singleton
-__global__ void k_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* oldpar, const int64_t* kout,
-                            const int64_t* kin, int64_t* Krout, int64_t* Krin, uint32_t* rsize, int phase) {
+__global__ void k_ref_reset(const uint32_t* R, uint32_t bound, const uint32_t* countp, uint32_t* par,
+                            uint32_t* oldpar, const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin,
+                            uint32_t* rsize, int phase) {
+  const uint32_t nr = list_len(countp, bound);
   for (uint64_t i = gtid(); i < nr; i += gstride()) {
     const uint32_t u = R[i];
     if (phase == 0) {
@@ -879,9 +893,10 @@ __global__ void k_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint3
 
 // liveness of level-(r+1) candidates from child counts; revivals get an identity parent
 // (when the level has one) and their child's label
-__global__ void k_live_update(const uint32_t* cand, uint32_t k, const uint32_t* rsize_below, uint8_t* alive,
-                              uint32_t* par, uint32_t* lab, const uint32_t* lab_below, SetRef died,
+__global__ void k_live_update(const uint32_t* cand, uint32_t bound, const uint32_t* countp, const uint32_t* rsize_below,
+                              uint8_t* alive, uint32_t* par, uint32_t* lab, const uint32_t* lab_below, SetRef died,
                               SetRef revived) {
+  const uint32_t k = list_len(countp, bound);
   for (uint64_t i = gtid(); i < k; i += gstride()) {
     const uint32_t x = cand[i];
     const uint8_t a = rsize_below[x] > 0 ? 1 : 0;
@@ -966,8 +981,9 @@ __global__ void k_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const u
 }
 
 // wave per listed vertex; plain stores (every writer stores the same epoch)
-__global__ void k_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
-                               const uint32_t* oldpar) {
+__global__ void k_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t bound,
+                               const uint32_t* countp, const uint32_t* par, const uint32_t* oldpar) {
+  const uint32_t nr = list_len(countp, bound);
   for (uint64_t i = gtid(); i < nr; i += gstride()) {
     const uint32_t u = rset[i];
     if (par[u] != oldpar[u]) stamp[u] = ep;
@@ -1484,8 +1500,8 @@ void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t
   if (n) k_mark_members<<<grid_for(n), kTpb, 0, s>>>(stamp, ep, n, alive, key, mark, mark_ep);
 }
 void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
-                         const uint32_t* oldpar, hipStream_t s) {
-  if (nr) k_mark_changed<<<grid_for(nr), kTpb, 0, s>>>(stamp, ep, rset, nr, par, oldpar);
+                         const uint32_t* oldpar, hipStream_t s, const uint32_t* countp) {
+  if (nr) k_mark_changed<<<list_grid(nr, countp), kTpb, 0, s>>>(stamp, ep, rset, nr, countp, par, oldpar);
 }
 int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
                  CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
@@ -1542,8 +1558,9 @@ void launch_set_add_list(SetRef set, const uint32_t* list, uint32_t count, hipSt
   if (count) k_set_add_list<<<grid_for(count), kTpb, 0, s>>>(set, list, count);
 }
 void launch_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, const uint32_t* key,
-                           const uint8_t* alive_or_null, hipStream_t s) {
-  if (count) k_set_add_mapped<<<grid_for(count), kTpb, 0, s>>>(set, list, count, key, alive_or_null);
+                           const uint8_t* alive_or_null, hipStream_t s, const uint32_t* countp) {
+  if (count)
+    k_set_add_mapped<<<list_grid(count, countp), kTpb, 0, s>>>(set, list, count, countp, key, alive_or_null);
 }
 void launch_ingest_validate(CsrRef out0, const uint64_t* keys, const uint32_t* idx, const int64_t* slot, uint64_t k,
                             const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
@@ -1651,15 +1668,17 @@ void launch_ref_init_top(uint32_t n, const uint8_t* alive, const int64_t* kout, 
 }
 void launch_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* oldpar, const int64_t* kout,
                       const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize, int phase,
-                      hipStream_t s) {
-  if (nr) k_ref_reset<<<grid_for(nr), kTpb, 0, s>>>(R, nr, par, oldpar, kout, kin, Krout, Krin_or_null, rsize, phase);
+                      hipStream_t s, const uint32_t* countp) {
+  if (nr)
+    k_ref_reset<<<list_grid(nr, countp), kTpb, 0, s>>>(R, nr, countp, par, oldpar, kout, kin, Krout, Krin_or_null,
+                                                        rsize, phase);
 }
 void launch_live_update(const uint32_t* cand, uint32_t k, const uint32_t* rsize_below, uint8_t* alive,
                         uint32_t* par_or_null, uint32_t* lab, const uint32_t* lab_below, SetRef died,
-                        SetRef revived, hipStream_t s) {
+                        SetRef revived, hipStream_t s, const uint32_t* countp) {
   if (k)
-    k_live_update<<<grid_for(k), kTpb, 0, s>>>(cand, k, rsize_below, alive, par_or_null, lab, lab_below, died,
-                                               revived);
+    k_live_update<<<list_grid(k, countp), kTpb, 0, s>>>(cand, k, countp, rsize_below, alive, par_or_null, lab,
+                                                         lab_below, died, revived);
 }
 void launch_live_prop(const uint32_t* died, uint32_t nd, const uint32_t* revived, uint32_t nr, const uint32_t* par,
                       uint32_t* rsize, SetRef cand, hipStream_t s) {

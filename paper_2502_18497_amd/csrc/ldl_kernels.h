@@ -103,9 +103,10 @@ void launch_iota(uint32_t* p, uint64_t n, hipStream_t s);
 void launch_copy_i64(int64_t* dst, const int64_t* src, uint64_t n, hipStream_t s);
 // set.add(x) for every x in list[0..count)
 void launch_set_add_list(SetRef set, const uint32_t* list, uint32_t count, hipStream_t s);
-// set.add(key[x]) for every x in list[0..count) (optionally only alive x)
+// set.add(key[x]) for every x in list[0..count) (optionally only alive x).  The list launchers
+// below take an optional countp: the length is then read on the device (count is its bound).
 void launch_set_add_mapped(SetRef set, const uint32_t* list, uint32_t count, const uint32_t* key,
-                           const uint8_t* alive_or_null, hipStream_t s);
+                           const uint8_t* alive_or_null, hipStream_t s, const uint32_t* countp = nullptr);
 // set.add(u) for every alive u < n with mark[key[u]] == mark_epoch
 // plain-store marking (stamp[x] = ep, no list): members of marked keys, listed vertices and
 // their neighbours, accepted movers and their neighbours; a later select builds the list
@@ -114,7 +115,7 @@ void launch_mark_members(uint32_t* stamp, uint32_t ep, uint32_t n, const uint8_t
 void launch_mark_neighbours_acc(uint32_t* stamp, uint32_t ep, const uint32_t* acc, const uint32_t* na,
                                 uint32_t na_max, CandBuf cand, CsrRef out, CsrRef in, int directed, hipStream_t s);
 void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uint32_t nr, const uint32_t* par,
-                         const uint32_t* oldpar, hipStream_t s);
+                         const uint32_t* oldpar, hipStream_t s, const uint32_t* countp = nullptr);
 // degree binning without global atomics: per-block histograms, then a fill whose blocks
 // derive their output positions from the histograms
 constexpr unsigned kBinBlocks = 256;
@@ -312,7 +313,7 @@ void launch_ref_init_top(uint32_t n, const uint8_t* alive, const int64_t* kout, 
                          int64_t* Krin_or_null, uint32_t* rsize, hipStream_t s);
 void launch_ref_reset(const uint32_t* R, uint32_t nr, uint32_t* par, uint32_t* oldpar, const int64_t* kout,
                       const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null, uint32_t* rsize, int phase,
-                      hipStream_t s);
+                      hipStream_t s, const uint32_t* countp = nullptr);
 // forward: singletons join their targets; otherwise the same moves are undone
 void launch_ref_commit(const uint32_t* acc, const uint32_t* na, uint32_t na_max, CandBuf cand, uint32_t* par,
                        uint2* lp, const int64_t* kout, const int64_t* kin, int64_t* Krout, int64_t* Krin_or_null,
@@ -334,7 +335,7 @@ void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t
 // materialise: every entry of every alive node (list = alive nodes); repair: entries of C
 void launch_live_update(const uint32_t* cand, uint32_t k, const uint32_t* rsize_below, uint8_t* alive,
                         uint32_t* par_or_null, uint32_t* lab, const uint32_t* lab_below, SetRef died,
-                        SetRef revived, hipStream_t s);
+                        SetRef revived, hipStream_t s, const uint32_t* countp = nullptr);
 void launch_live_prop(const uint32_t* died, uint32_t nd, const uint32_t* revived, uint32_t nr,
                       const uint32_t* par, uint32_t* rsize, SetRef cand, hipStream_t s);
 void launch_label_up(const uint32_t* rset, uint32_t nr, const uint32_t* par, const uint8_t* alive_up,
