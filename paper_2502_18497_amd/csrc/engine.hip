@@ -1126,9 +1126,9 @@ struct Engine {
   void process_level(int r) {
     Level& V = lv[r];
     stats.levels_processed++;
-    flush_to(r);   // level r's CSR receives its deferred records (and passes them upwards)
-    sync_read();
+    // the seed count was read by the caller's synchronisation; flushing does not change the seeds
     const uint32_t E0 = count(S_D0 + r);
+    flush_to(r);   // level r's CSR receives its deferred records (and passes them upwards)
     hcheck(hipMemcpyAsync(entry, sets[S_D0 + r].list, 4ull * E0, hipMemcpyDeviceToDevice, st));
     begin(S_D0 + r);
     // frontier: alive seeds and all members of their communities
