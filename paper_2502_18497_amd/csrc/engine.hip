@@ -1186,8 +1186,10 @@ struct Engine {
       }
       std::swap(sets[S_U], sets[S_U2]);
     }
+    // the movers' count is final after the move phase: the synchronisations of refinement and
+    // aggregation have read it; without refinement (r == L) one is needed here
     if (r < L) refine(r, E0);
-    sync_read();
+    else sync_read();
     if (r >= 1 && count(S_MOVED) > 0) label_refresh(r);
   }
 
