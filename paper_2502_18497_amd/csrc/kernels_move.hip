@@ -489,13 +489,64 @@ __device__ __forceinline__ uint32_t table_insert_own(uint32_t* keys, u64a* vals,
   }
 }
 
+// Row of one vertex for the LDS-table kernels: degrees, row offsets and the vertex's own label,
+// degrees and (move) community totals.
+struct HashRow {
+  uint32_t v, dout, din;
+  uint64_t oo, oi;
+  VInfo vi;
+  bool active;
+};
+
+// first dependent level: everything read at the vertex's own index
+template <bool DIR>
+__device__ __forceinline__ HashRow hash_row_head(const MoveView& mv, bool active, uint32_t v) {
+  HashRow r;
+  r.active = active;
+  r.v = v;
+  r.dout = r.din = 0;
+  r.oo = r.oi = 0;
+  r.vi.lab = 0;
+  r.vi.ko = r.vi.ki = r.vi.Koa = r.vi.Kia = 0;
+  if (active) {
+    r.dout = mv.out.deg[v];
+    r.oo = mv.out.off[v];
+    if (DIR) {
+      r.din = mv.in.deg[v];
+      r.oi = mv.in.off[v];
+    }
+    r.vi.lab = mv.lab[v];
+    r.vi.ko = mv.kout[v];
+    r.vi.ki = DIR ? mv.kin[v] : r.vi.ko;
+  }
+  return r;
+}
+
+// second dependent level: the entries of lane li (j = li + q TEAM) and the own community's totals
+template <typename WT, int TEAM, int EPL, bool DIR, bool REF>
+__device__ __forceinline__ void hash_row_entries(const MoveView& mv, HashRow& r, int li, uint32_t* xs, int64_t* ws) {
+  const uint32_t T = r.dout + r.din;
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) {
+    const uint32_t j = (uint32_t)li + (uint32_t)q * TEAM;
+    xs[q] = r.v;                              // the vertex itself does not count
+    ws[q] = 0;
+    if (r.active && j < T) entry_at<WT, DIR>(mv, r.oo, r.dout, r.oi, j, xs[q], ws[q]);
+  }
+  if (!REF && r.active) {
+    r.vi.Koa = mv.Kout[r.vi.lab];
+    r.vi.Kia = DIR ? mv.Kin[r.vi.lab] : r.vi.Koa;
+  }
+}
+
 // One wavefront per vertex with a private LDS table of SLOTS slots (load factor <= 1/2), kept
 // empty between vertices: the lane that creates a key's slot owns it, evaluates that
 // community after the wavefront has inserted everything and empties the slot afterwards, so
 // no cycle is spent on empty slots.  A lane loads all of its entries (at most SLOTS / 128),
 // then all their keys, then inserts; the totals of all its owned communities are gathered
 // together.  The wavefronts of a workgroup run independently (no workgroup barrier inside the
-// loop); candidates are staged per wavefront.
+// loop); candidates are staged per wavefront.  The loop over the wavefront's vertices is
+// software-pipelined as in k_best_hash below.
 template <typename WT, int SLOTS, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int W = kTpb / kWave;
@@ -530,31 +581,27 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     wave_sync();
     ns = 0;
   };
-  if ((uint64_t)blockIdx.x * W + wv < count) {
+  uint64_t i = (uint64_t)blockIdx.x * W + wv;
+  const uint64_t step = (uint64_t)gridDim.x * W;
+  if (i < count) {
     for (uint32_t s = lane; s < (uint32_t)SLOTS; s += kWave) {
       keys[s] = kEmpty;
       vals[s] = 0;
     }
   }
-  for (uint64_t i = (uint64_t)blockIdx.x * W + wv; i < count; i += (uint64_t)gridDim.x * W) {
-    const uint32_t v = list[i];
-    const uint32_t dout = mv.out.deg[v];
-    const uint32_t din = DIR ? mv.in.deg[v] : 0;
-    const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-    const VInfo vi = vinfo<DIR, REF>(mv, v);
-    const uint32_t T = dout + din;
-    uint32_t xs[EPL];
-    int64_t ws[EPL];
-#pragma unroll
-    for (int q = 0; q < EPL; ++q) {
-      const uint32_t j = (uint32_t)lane + (uint32_t)q * kWave;
-      xs[q] = v;                              // the vertex itself does not count
-      ws[q] = 0;
-      if (j < T) entry_at<WT, DIR>(mv, oo, dout, oi, j, xs[q], ws[q]);
-    }
+  // pipeline state: the current vertex's row and entries, the next vertex's id
+  HashRow cur = hash_row_head<DIR>(mv, i < count, i < count ? list[i] : 0);
+  uint32_t xs[EPL];
+  int64_t ws[EPL];
+  hash_row_entries<WT, kWave, EPL, DIR, REF>(mv, cur, lane, xs, ws);
+  uint32_t vnext = i + step < count ? list[i + step] : 0;
+  for (; i < count; i += step) {
+    const uint32_t v = cur.v;
     uint32_t ks[EPL];
 #pragma unroll
-    for (int q = 0; q < EPL; ++q) ks[q] = entry_key<REF>(mv, v, vi.lab, xs[q]);
+    for (int q = 0; q < EPL; ++q) ks[q] = entry_key<REF>(mv, v, cur.vi.lab, xs[q]);
+    HashRow nxt = hash_row_head<DIR>(mv, i + step < count, vnext);
+    const uint32_t vnext2 = i + 2 * step < count ? list[i + 2 * step] : 0;
     wave_sync();                              // the previous vertex's slots are empty
     int64_t own = 0;
     uint32_t mine[EPL];
@@ -563,7 +610,7 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
       const uint32_t key = ks[q];
       mine[q] = kNoSlot;
       if (key == kEmpty) continue;
-      if (!REF && key == vi.lab) {
+      if (!REF && key == cur.vi.lab) {
         own += ws[q];
         continue;
       }
@@ -571,23 +618,26 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     }
     wave_sync();                              // every insert done
     own = wave_sum_i64(own);
-    int64_t av[EPL], Kb[EPL], Kib[EPL];
+    int64_t Kb[EPL], Kib[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
-      av[q] = 0; Kb[q] = 0; Kib[q] = 0;
+      Kb[q] = 0; Kib[q] = 0;
       if (mine[q] != kNoSlot) {
-        av[q] = (int64_t)vals[mine[q]];
         Kb[q] = mv.Kout[ks[q]];
         if (DIR) Kib[q] = mv.Kin[ks[q]];
       }
     }
+    uint32_t xn[EPL];
+    int64_t wn[EPL];
+    hash_row_entries<WT, kWave, EPL, DIR, REF>(mv, nxt, lane, xn, wn);
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
       if (mine[q] == kNoSlot) continue;
       ls.distinct += 1;
-      const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), ks[q]);
+      const int64_t av = (int64_t)vals[mine[q]];
+      const Best c = make_best(gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
       if (better(c, b)) b = c;
     }
     // each slot is read and emptied by its owner only; the barrier at the top of the next
@@ -601,13 +651,13 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
     }
     b = group_best(b, kWave);                 // every lane holds the wavefront's best
     if (lane == 0) {
-      ls.entries += T;
+      ls.entries += cur.dout + cur.din;
       ls.vertices += 1;
     }
     if (b.valid && best_gain(b) > 0) {
       if (lane == 0) {
         cv[wv][ns] = v;
-        ca[wv][ns] = REF ? v : vi.lab;
+        ca[wv][ns] = REF ? v : cur.vi.lab;
         cb[wv][ns] = b.id;
         clo[wv][ns] = b.lo;
         chi[wv][ns] = b.hi;
@@ -615,6 +665,13 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
       }
       if (++ns == SCAP) flush();
     }
+    cur = nxt;
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      xs[q] = xn[q];
+      ws[q] = wn[q];
+    }
+    vnext = vnext2;
   }
   if (ns) flush();
   stats_flush(ls, st, red_s);
@@ -624,8 +681,13 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
 // between vertices: as in k_best_wave, the lane that creates a key's slot evaluates that
 // community and empties the slot.  A lane loads all of its entries (at most SLOTS / (2 TEAM)),
 // then all their keys, then inserts; the totals of its owned communities are gathered together.
+// The loop is software-pipelined over the team's vertices: the next vertex's header is read
+// while the current one's keys are, and its entries while the current one's community totals
+// are, so each vertex waits on two dependent gathers instead of five (list, header, entries,
+// keys, totals).
 template <typename WT, int TEAM, int SLOTS, bool DIR, bool REF>
-__global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
+__global__ __launch_bounds__(kTpb) __attribute__((amdgpu_waves_per_eu(3)))   // LDS holds 3 workgroups per CU
+void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
   constexpr int TEAMS = kTpb / TEAM;
   constexpr int EPL = SLOTS / 2 / TEAM;    // entries per lane, T <= SLOTS / 2
   __shared__ uint32_t skey[TEAMS][SLOTS];
@@ -639,40 +701,33 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
   const uint32_t* list = br.base + *br.start;
   const int t = threadIdx.x / TEAM;
   const int li = threadIdx.x % TEAM;
+  const uint64_t step = (uint64_t)gridDim.x * TEAMS;
   LocalStats ls;
-  if ((uint64_t)blockIdx.x * TEAMS < count) {
+  uint64_t base = (uint64_t)blockIdx.x * TEAMS;
+  if (base < count) {
     for (uint32_t s = li; s < (uint32_t)SLOTS; s += TEAM) {
       skey[t][s] = kEmpty;
       sval[t][s] = 0;
     }
   }
-  for (uint64_t base = (uint64_t)blockIdx.x * TEAMS; base < count; base += (uint64_t)gridDim.x * TEAMS) {
-    const uint64_t slot = base + t;
-    const bool active = slot < count;
-    const uint32_t v = active ? list[slot] : 0;
-    uint32_t dout = 0, din = 0;
-    uint64_t oo = 0, oi = 0;
-    VInfo vi{};
-    if (active) {
-      dout = mv.out.deg[v];
-      din = DIR ? mv.in.deg[v] : 0;
-      oo = mv.out.off[v];
-      if (DIR) oi = mv.in.off[v];
-      vi = vinfo<DIR, REF>(mv, v);
-    }
-    const uint32_t T = dout + din;
-    uint32_t xs[EPL];
-    int64_t ws[EPL];
-#pragma unroll
-    for (int q = 0; q < EPL; ++q) {
-      const uint32_t j = (uint32_t)li + (uint32_t)q * TEAM;
-      xs[q] = v;                              // the vertex itself does not count
-      ws[q] = 0;
-      if (active && j < T) entry_at<WT, DIR>(mv, oo, dout, oi, j, xs[q], ws[q]);
-    }
+  // pipeline state: the current vertex's row and entries, the next vertex's id
+  HashRow cur;
+  uint32_t xs[EPL];
+  int64_t ws[EPL];
+  uint32_t vnext = 0;
+  {
+    const uint64_t s0 = base + t, s1 = base + step + t;
+    cur = hash_row_head<DIR>(mv, s0 < count, s0 < count ? list[s0] : 0);
+    hash_row_entries<WT, TEAM, EPL, DIR, REF>(mv, cur, li, xs, ws);
+    if (s1 < count) vnext = list[s1];
+  }
+  for (; base < count; base += step) {
+    const uint64_t s1 = base + step + t, s2 = base + 2 * step + t;
     uint32_t ks[EPL];
 #pragma unroll
-    for (int q = 0; q < EPL; ++q) ks[q] = active ? entry_key<REF>(mv, v, vi.lab, xs[q]) : kEmpty;
+    for (int q = 0; q < EPL; ++q) ks[q] = cur.active ? entry_key<REF>(mv, cur.v, cur.vi.lab, xs[q]) : kEmpty;
+    HashRow nxt = hash_row_head<DIR>(mv, s1 < count, vnext);
+    const uint32_t vnext2 = s2 < count ? list[s2] : 0;
     __syncthreads();                          // the previous vertex's slots are empty
     int64_t own = 0;
     uint32_t mine[EPL];
@@ -681,7 +736,7 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
       const uint32_t key = ks[q];
       mine[q] = kNoSlot;
       if (key == kEmpty) continue;
-      if (!REF && key == vi.lab) {
+      if (!REF && key == cur.vi.lab) {
         own += ws[q];
         continue;
       }
@@ -689,23 +744,26 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
     }
     __syncthreads();                          // every insert done
     own = team_sum<TEAM>(own, red_i);
-    int64_t av[EPL], Kb[EPL], Kib[EPL];
+    int64_t Kb[EPL], Kib[EPL];
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
-      av[q] = 0; Kb[q] = 0; Kib[q] = 0;
+      Kb[q] = 0; Kib[q] = 0;
       if (mine[q] != kNoSlot) {
-        av[q] = (int64_t)sval[t][mine[q]];
         Kb[q] = mv.Kout[ks[q]];
         if (DIR) Kib[q] = mv.Kin[ks[q]];
       }
     }
+    uint32_t xn[EPL];
+    int64_t wn[EPL];
+    hash_row_entries<WT, TEAM, EPL, DIR, REF>(mv, nxt, li, xn, wn);
     Best b;
     b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
 #pragma unroll
     for (int q = 0; q < EPL; ++q) {
       if (mine[q] == kNoSlot) continue;
       ls.distinct += 1;
-      const Best c = make_best(gain_t<DIR, REF>(mv, vi, Kb[q], Kib[q], av[q], own), ks[q]);
+      const int64_t av = (int64_t)sval[t][mine[q]];
+      const Best c = make_best(gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
       if (better(c, b)) b = c;
     }
     b = team_best<TEAM>(b, red_b);
@@ -716,16 +774,23 @@ __global__ __launch_bounds__(kTpb) void k_best_hash(MoveView mv, BinRef br, Cand
         sval[t][mine[q]] = 0;
       }
     }
-    if (active && li == 0) {
-      ls.entries += T;
+    if (cur.active && li == 0) {
+      ls.entries += cur.dout + cur.din;
       ls.vertices += 1;
       if (b.valid && best_gain(b) > 0) {
-        stage_push(stage, v, REF ? v : vi.lab, b);
+        stage_push(stage, cur.v, REF ? cur.v : cur.vi.lab, b);
         note_cand(ls, b);
       }
     }
     __syncthreads();
     if (stage.n + TEAMS > 64) stage_flush(stage, cand);
+    cur = nxt;
+#pragma unroll
+    for (int q = 0; q < EPL; ++q) {
+      xs[q] = xn[q];
+      ws[q] = wn[q];
+    }
+    vnext = vnext2;
   }
   stage_flush(stage, cand);
   stats_flush(ls, st, red_s);
