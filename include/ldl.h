@@ -80,7 +80,9 @@ typedef struct ldl_pair {
  *                       16 = 64-slot LDS tables for the hub partitions (partition overflow, redo of
  *                       the iteration with more partitions per hub), 32 = no bulk load (the first
  *                       insert-only batch of a graph goes through the general lookup and row-update
- *                       path instead of being laid out directly from its sorted records)
+ *                       path instead of being laid out directly from its sorted records), 64 = every
+ *                       candidate kernel of the degree bins runs as one workgroup (each workgroup
+ *                       and wavefront walks many vertices through its software pipeline)
  */
 typedef struct ldl_config {
   int32_t directed;

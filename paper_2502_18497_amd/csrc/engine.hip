@@ -929,7 +929,9 @@ struct Engine {
       if (profile) ev = next_events();
       if (b < kNumBins - 1) {
         // with profiling, the events are attached to the kernel's dispatch
-        launch_best(mv, b, br, n, refine, cand, ms, st, profile ? ev.first : nullptr, profile ? ev.second : nullptr);
+        // the grid is sized for n vertices (test flag 64: for one, i.e. a single workgroup)
+        launch_best(mv, b, br, (test_flags & 64) ? 1u : n, refine, cand, ms, st, profile ? ev.first : nullptr,
+                    profile ? ev.second : nullptr);
       } else {
         // hubs: the events time the keys pass, which reads the entries and their labels
         cub(launch_hub(mv, br, hb, refine, hub, hw, cand, ms, &cub_tmp, &cub_bytes, st, profile ? ev.first : nullptr,

@@ -9,6 +9,8 @@ every result bit-identical to the oracle:
  16  tiny LDS tables for the hub hash partitions: partitions overflow, the iteration is redone with
      more partitions per hub
  32  no bulk load: creation inserts through the general lookup and row-update path
+ 64  one workgroup per candidate kernel of the degree bins: every workgroup and wavefront walks
+     many vertices, through every stage of the kernels' software pipelines
 """
 import numpy as np
 import pytest
@@ -18,7 +20,7 @@ from tests.gpucases import run_parity
 
 pytestmark = pytest.mark.gpu
 
-ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS, NO_BULK = 1, 2, 4, 8, 16, 32
+ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS, NO_BULK, ONE_GROUP = 1, 2, 4, 8, 16, 32, 64
 
 
 def _batches(stream, sizes):
@@ -72,3 +74,26 @@ def test_hub_partition_overflow(flags):
              if int(v) != hub and (min(hub, int(v)), max(hub, int(v))) not in have]
     e = np.concatenate([e, np.array(extra, dtype=np.uint32)])
     run_parity(8000, e, _batches(s, [200, 200]), gpu_flags=flags)
+
+
+def _bin_entries(stats, b):
+    # candidate kernel k = 12 * refine + 6 * wide + bin
+    return sum(st["bin_entries"][12 * r + 6 * w + b] for st in stats for r in (0, 1) for w in (0, 1))
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("bins", [None, [[8, 32, 128, 512, 2048], [8, 32, 128, 512, 2048]]])
+def test_one_workgroup_candidate_kernels(directed, bins):
+    # a single workgroup per candidate kernel: the vertex loops of the lane-group, wavefront and
+    # workgroup kernels run many times per workgroup and wavefront, with the next vertex's row read
+    # while the current one is evaluated; with the second bin set the 1,024-slot wavefront kernel
+    # takes the vertices with 129-512 entries
+    if directed:
+        s = synth.rmat_directed_lognormal(1 << 11, 24 * (1 << 11), seed_offset=440)
+    else:
+        s = synth.rmat_undirected(scale=11, seed_offset=440)
+    stats = []
+    run_parity(s.n, s.edges(), _batches(s, [800, 60, 800]), directed=directed, gpu_flags=ONE_GROUP,
+               stats_out=stats, bins=bins)
+    assert _bin_entries(stats, 2) > 0
+    assert _bin_entries(stats, 3 if bins else 4) > 0
