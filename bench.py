@@ -18,7 +18,6 @@ import argparse
 import json
 import os
 import sys
-import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -656,11 +655,6 @@ def main():
 
     torch.cuda.set_device(0)
     cpu = {}
-    th = None
-    if not args.no_cpu_baseline:
-        th = threading.Thread(target=cpu_baseline_worker, args=(args.scale, args.batch, args.cpu_batches, cpu),
-                              daemon=True)
-        th.start()
 
     t0 = time.perf_counter()
     s = synth.rmat_undirected(scale=args.scale)
@@ -740,8 +734,9 @@ def main():
     traffic, traffic_bytes = measured_traffic(dom_name, avg_us)
 
     cpu_obj = None
-    if th is not None:
-        th.join()
+    if not args.no_cpu_baseline:
+        # after the GPU timing, so the oracle shares no host time with the thread driving the GPU
+        cpu_baseline_worker(args.scale, args.batch, args.cpu_batches, cpu)
         o = cpu["oracle"]
         n_cpu = 0
         t0 = time.perf_counter()
