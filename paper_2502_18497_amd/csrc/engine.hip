@@ -893,11 +893,9 @@ struct Engine {
 
   std::pair<hipEvent_t, hipEvent_t> next_events() {
     if (ev_used == ev_pool.size()) {
-      // timing-only events: no system-scope fence (cache write-back and invalidation) at each
-      // record; they are read only after the stream has been synchronised
       hipEvent_t a, b;
-      hcheck(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
-      hcheck(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
+      hcheck(hipEventCreate(&a));
+      hcheck(hipEventCreate(&b));
       ev_pool.push_back(std::make_pair(a, b));
     }
     return ev_pool[ev_used++];
