@@ -159,6 +159,38 @@ __device__ __forceinline__ uint32_t wave_owner(const uint64_t* off, uint32_t n, 
   return lo;
 }
 
+// Row entries jb, jb + stride, ... (U of them, those below e1) probed against an LDS table of
+// record columns: all U neighbour loads are issued before the first probe, so each lane keeps U
+// loads in flight.  A found entry's slot goes to the record that holds its column.
+constexpr int kStreamU = 4;
+template <int U>
+__device__ __forceinline__ void probe_entries(const uint32_t* nbr, uint64_t off, uint64_t jb, uint64_t stride,
+                                              uint64_t e1, const uint32_t* tkey, const uint32_t* tval,
+                                              uint32_t mask, int64_t* slot_out) {
+  uint32_t xs[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t j = jb + (uint64_t)u * stride;
+    xs[u] = j < e1 ? nbr[off + j] : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t j = jb + (uint64_t)u * stride;
+    if (j >= e1) continue;
+    const uint32_t x = xs[u];
+    uint32_t h = hash32(x) & mask;
+    for (;;) {
+      const uint32_t kx = tkey[h];
+      if (kx == kEmpty) break;
+      if (kx == x) {
+        slot_out[tval[h]] = (int64_t)(off + j);
+        break;
+      }
+      h = (h + 1) & mask;
+    }
+  }
+}
+
 // wavefront per work item: LDS table of the item's record chunk, stream the item's row slice,
 // write the slot of every record found (each record matches at most one entry)
 __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* keys, uint64_t k,
@@ -201,19 +233,8 @@ __global__ __launch_bounds__(256) void k_seg_lookup(CsrRef c, const uint64_t* ke
     const uint64_t off = c.off[row];
     const uint64_t e0 = sl * kSlice;
     const uint64_t e1 = e0 + kSlice < deg ? e0 + kSlice : deg;
-    for (uint64_t j = e0 + lane; j < e1; j += kWave) {
-      const uint32_t x = c.nbr[off + j];
-      uint32_t h = hash32(x) & mask;
-      for (;;) {
-        const uint32_t kx = tkey[h];
-        if (kx == kEmpty) break;
-        if (kx == x) {
-          slot_out[clo + tval[h]] = (int64_t)(off + j);
-          break;
-        }
-        h = (h + 1) & mask;
-      }
-    }
+    for (uint64_t jb = e0 + lane; jb < e1; jb += kStreamU * kWave)
+      probe_entries<kStreamU>(c.nbr, off, jb, kWave, e1, tkey, tval, mask, slot_out + clo);
     wave_sync();   // table reads done before the next item clears it
   }
 }
@@ -258,19 +279,8 @@ __global__ __launch_bounds__(256) void k_seg_lookup_big(CsrRef c, const uint64_t
     const uint64_t off = c.off[row];
     const uint64_t e0 = sl * kBigSlice;
     const uint64_t e1 = e0 + kBigSlice < deg ? e0 + kBigSlice : deg;
-    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
-      const uint32_t x = c.nbr[off + j];
-      uint32_t h = hash32(x) & mask;
-      for (;;) {
-        const uint32_t kx = tkey[h];
-        if (kx == kEmpty) break;
-        if (kx == x) {
-          slot_out[clo + tval[h]] = (int64_t)(off + j);
-          break;
-        }
-        h = (h + 1) & mask;
-      }
-    }
+    for (uint64_t jb = e0 + threadIdx.x; jb < e1; jb += kStreamU * (uint64_t)blockDim.x)
+      probe_entries<kStreamU>(c.nbr, off, jb, blockDim.x, e1, tkey, tval, mask, slot_out + clo);
     __syncthreads();
   }
 }
@@ -1069,11 +1079,18 @@ __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list,
     const uint32_t dout = out.deg[u];
     const uint64_t s = node_slots(out, in, u);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
-    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
-      uint32_t x;
-      int64_t w;
-      node_entry(out, in, u, dout, j, x, w);
-      stamp[x] = ep;
+    // four neighbour loads in flight per lane before their stamps are written
+    for (uint64_t jb = j0 + lane; jb < j1; jb += 4 * kWave) {
+      uint32_t xs[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * kWave;
+        xs[k] = 0;
+        if (j < j1) xs[k] = j < dout ? out.nbr[out.off[u] + j] : in.nbr[in.off[u] + (j - dout)];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (jb + (uint64_t)k * kWave < j1) stamp[xs[k]] = ep;
     }
   });
 }
@@ -1211,15 +1228,35 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
     const uint32_t dout = out.deg[v];
     const uint64_t s = node_slots(out, in, v);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
-    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
-      uint32_t x;
-      int64_t w;
-      node_entry(out, in, v, dout, j, x, w);
-      if (x == v || lab[x] != lv || par[x] != x || rsize[x] != 1) continue;
-      rcur_stamp[x] = rcur_ep;
-      if (rset_stamp[x] != rset_ep) {
-        oldpar[x] = x;
-        rset_stamp[x] = rset_ep;
+    // four entries per lane at a time: their neighbour loads, then their label gathers, then the
+    // parent and size gathers of those in v's community, each group issued before any is used
+    for (uint64_t jb = j0 + lane; jb < j1; jb += 4 * kWave) {
+      uint32_t xs[4];
+      bool ok[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * kWave;
+        ok[k] = j < j1;
+        xs[k] = v;
+        if (ok[k]) xs[k] = j < dout ? out.nbr[out.off[v] + j] : in.nbr[in.off[v] + (j - dout)];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ok[k] = ok[k] && xs[k] != v && lab[xs[k]] == lv;
+      uint32_t px[4], rx[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        px[k] = ok[k] ? par[xs[k]] : 0u;
+        rx[k] = ok[k] ? rsize[xs[k]] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t x = xs[k];
+        if (!ok[k] || px[k] != x || rx[k] != 1) continue;
+        rcur_stamp[x] = rcur_ep;
+        if (rset_stamp[x] != rset_ep) {
+          oldpar[x] = x;
+          rset_stamp[x] = rset_ep;
+        }
       }
     }
   });
