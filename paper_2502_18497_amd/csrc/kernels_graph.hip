@@ -842,11 +842,26 @@ __global__ __launch_bounds__(kTpb) void k_record_degrees(const uint64_t* keys, c
     }
     __syncthreads();
     const uint64_t c1 = c0 + kDegChunk < k ? c0 + kDegChunk : k;
-    for (uint64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
-      const int64_t d = vals[i];
-      if (d == 0) continue;
-      deg_local_add(rk, rv, krow(keys[i], ks), d, kout);
-      if (kin) deg_local_add(ck, cv, kcol(keys[i], ks), d, kin);
+    // four records per thread at a time, all loaded before the first is added
+    for (uint64_t ib = c0 + threadIdx.x; ib < c1; ib += 4 * (uint64_t)blockDim.x) {
+      int64_t ds[4];
+      uint64_t kk[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t i = ib + (uint64_t)q * blockDim.x;
+        ds[q] = 0;
+        kk[q] = 0;
+        if (i < c1) {
+          ds[q] = vals[i];
+          kk[q] = keys[i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (ds[q] == 0) continue;
+        deg_local_add(rk, rv, krow(kk[q], ks), ds[q], kout);
+        if (kin) deg_local_add(ck, cv, kcol(kk[q], ks), ds[q], kin);
+      }
     }
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < kDegSlots; t += blockDim.x) {
