@@ -320,23 +320,42 @@ __global__ __launch_bounds__(kSegTpb) void k_seg_update(CsrRef c, const uint64_t
     const uint32_t deg = c.deg[row];
     const uint32_t cap = c.cap[row];
     int64_t ndel = 0, nins = 0, dsum = 0;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-      const int64_t d = delta[i];
-      const int64_t sl = slot[i];
-      dsum += d;
-      uint8_t t = kRecNone;
-      if (d != 0) {
-        if (sl >= 0) {
-          const int64_t nw = wget(c, (uint64_t)sl) + d;
-          wset(c, (uint64_t)sl, nw);
-          t = nw == 0 ? kRecDel : kRecUpd;
-          if (nw == 0) ++ndel;
-        } else {
-          t = kRecIns;
-          ++nins;
+    // four records per thread at a time: their deltas and slots, then the old weights at the slots
+    // (the records of a segment have distinct columns, hence distinct slots)
+    for (uint64_t ib = lo + threadIdx.x; ib < hi; ib += 4 * (uint64_t)blockDim.x) {
+      int64_t dd[4], sl[4], ow[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t i = ib + (uint64_t)q * blockDim.x;
+        dd[q] = 0;
+        sl[q] = -1;
+        if (i < hi) {
+          dd[q] = delta[i];
+          sl[q] = slot[i];
         }
       }
-      rtype[i] = t;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ow[q] = (dd[q] != 0 && sl[q] >= 0) ? wget(c, (uint64_t)sl[q]) : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t i = ib + (uint64_t)q * blockDim.x;
+        if (i >= hi) continue;
+        const int64_t d = dd[q];
+        dsum += d;
+        uint8_t t = kRecNone;
+        if (d != 0) {
+          if (sl[q] >= 0) {
+            const int64_t nw = ow[q] + d;
+            wset(c, (uint64_t)sl[q], nw);
+            t = nw == 0 ? kRecDel : kRecUpd;
+            if (nw == 0) ++ndel;
+          } else {
+            t = kRecIns;
+            ++nins;
+          }
+        }
+        rtype[i] = t;
+      }
     }
     ndel = wave_sum_i64(ndel);
     nins = wave_sum_i64(nins);
@@ -1138,12 +1157,23 @@ __global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uin
     const uint64_t s = node_slots(out, in, u);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
     int64_t c = 0;
-    for (uint64_t j = j0 + lane; j < j1; j += kWave) {
-      if (j < dout) {
-        c += REPAIR ? 2 : 1;
-      } else {
-        const uint2 q2 = po[in.nbr[in.off[u] + (j - dout)]];
-        if (q2.x == q2.y) c += 2;   // the neighbour keeps its parent
+    // four entries per lane at a time: the in-entries' neighbour loads, then their parent gathers
+    for (uint64_t jb = j0 + lane; jb < j1; jb += 4 * kWave) {
+      uint32_t xs[4];
+      int kind[4];   // 0: past the item, 1: out entry, 2: in entry
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * kWave;
+        kind[k] = j >= j1 ? 0 : (j < dout ? 1 : 2);
+        xs[k] = kind[k] == 2 ? in.nbr[in.off[u] + (j - dout)] : 0u;
+      }
+      uint2 qs[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qs[k] = kind[k] == 2 ? po[xs[k]] : make_uint2(0u, 0u);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (kind[k] == 1) c += REPAIR ? 2 : 1;
+        else if (kind[k] == 2 && qs[k].x == qs[k].y) c += 2;   // the neighbour keeps its parent
       }
     }
     c = wave_sum_i64(c);
