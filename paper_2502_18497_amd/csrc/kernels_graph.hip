@@ -997,9 +997,12 @@ __global__ void k_materialise_nodes(uint32_t n, const uint32_t* rsize, uint8_t* 
 __global__ void k_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t* par, const uint32_t* lab_up,
                                 uint32_t* lab, SetRef seeds) {
   for (uint64_t u = gtid(); u < n; u += gstride()) {
-    if (!alive[u]) continue;
-    const uint32_t nl = lab_up[par[u]];
-    if (nl != lab[u]) {
+    // the node's own words are read together; only the label gather depends on them
+    const uint8_t al = alive[u];
+    const uint32_t pu = par[u], lu = lab[u];
+    if (!al) continue;
+    const uint32_t nl = lab_up[pu];
+    if (nl != lu) {
       lab[u] = nl;
       set_add(seeds.stamp, seeds.epoch, seeds.list, seeds.count, (uint32_t)u);
     }
