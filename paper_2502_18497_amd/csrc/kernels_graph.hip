@@ -1125,9 +1125,14 @@ __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list,
         xs[k] = 0;
         if (j < j1) xs[k] = j < dout ? out.nbr[out.off[u] + j] : in.nbr[in.off[u] + (j - dout)];
       }
+      // neighbours shared by many listed nodes are stamped once: a stamp already set is not
+      // written again, so its cache line stays clean
+      uint32_t cur[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cur[k] = jb + (uint64_t)k * kWave < j1 ? stamp[xs[k]] : ep;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (jb + (uint64_t)k * kWave < j1) stamp[xs[k]] = ep;
+        if (cur[k] != ep) stamp[xs[k]] = ep;
     }
   });
 }
