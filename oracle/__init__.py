@@ -63,6 +63,7 @@ def _load():
         lib.orc_trace_clear.argtypes = [vp]
         lib.orc_eval_modularity.restype = i32
         lib.orc_eval_modularity.argtypes = [i32, i32, i32, u32, vp, u64, vp, vp, vp, vp]
+        lib.orc_check_counts.argtypes = [vp, vp]
         lib.orc_decouple.restype = i32
         lib.orc_decouple.argtypes = [u64, vp, vp, vp, vp]
         _lib = lib
@@ -172,6 +173,14 @@ class Oracle:
         buf = ctypes.create_string_buffer(256)
         rc = self.lib.orc_check(self.h, buf, 256)
         return "" if rc == 0 else buf.value.decode()
+
+    def check_counts(self) -> dict:
+        """Recount checks done under FLAG_CHECK_MOVES: move and refinement commits, and the
+        single-move commits whose predicted gain was compared with the recount."""
+        out = np.zeros(4, dtype=np.uint64)
+        self.lib.orc_check_counts(self.h, out.ctypes.data)
+        return {"move": int(out[0]), "refine": int(out[1]), "move_single": int(out[2]),
+                "refine_single": int(out[3])}
 
     def trace(self) -> np.ndarray:
         k = int(self.lib.orc_trace_len(self.h))

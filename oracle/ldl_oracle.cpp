@@ -142,7 +142,9 @@ struct Oracle {
   int pass_idx = 0;
   // debugging / checking modes
   int single_move = 0;            // accept only the best candidate per move iteration
-  int check_moves = 0;            // recount Q from scratch around every move commit
+  int check_moves = 0;            // recount Q from scratch around every move and refinement commit
+  uint64_t checks[4] = {0, 0, 0, 0};   // recount checks done: moves, refinements, and of those
+                                       // the single-move ones that compared a predicted gain
   std::string err;
   std::vector<TraceRec> trace;
   int tracing = 0;
@@ -224,6 +226,26 @@ struct Oracle {
     i64 mm = 0, ein = 0;
     std::vector<uint32_t> g(n);
     for (uint32_t u = 0; u < n; ++u) g[u] = lv[r].lab[anc(u, r)];
+    for (uint32_t u = 0; u < n; ++u)
+      for (auto& e : L0.out[u]) {
+        mm += e.second;
+        ko[g[u]] += e.second;
+        ki[g[e.first]] += e.second;
+        if (g[u] == g[e.first]) ein += e.second;
+      }
+    i128 skk = 0;
+    for (uint32_t c = 0; c < n; ++c) skk += (i128)ko[c] * ki[c];
+    return (i128)cfg.gq * mm * ein - (i128)cfg.gp * skk;
+  }
+
+  // Exact numerator of Eq. 1 for the refined partition of level r: ground node u belongs to
+  // the refined community pi_r(anc_r(u)).  Refinement moves change this partition only.
+  i128 recount_qnum_refined(int r) const {
+    const Level& L0 = lv[0];
+    std::vector<i64> ko(n, 0), ki(n, 0);
+    i64 mm = 0, ein = 0;
+    std::vector<uint32_t> g(n);
+    for (uint32_t u = 0; u < n; ++u) g[u] = lv[r].par[anc(u, r)];
     for (uint32_t u = 0; u < n; ++u)
       for (auto& e : L0.out[u]) {
         mm += e.second;
@@ -407,8 +429,10 @@ struct Oracle {
         if (single_move && B.size() == 1) {
           i128 expect = cfg.directed ? B[0].G : 2 * B[0].G;
           if (dq != expect && err.empty()) err = "single-move gain differs from predicted gain";
+          checks[2]++;
         }
         if (qnum() != after && err.empty()) err = "maintained Q numerator differs from recount";
+        checks[0]++;
       }
       record(r, 0, j, S.size(), cands.size(), B.size(), dq);
       if (dq < 0) {  // Alg. 1 l.11: roll the whole mini-batch back and stop moving
@@ -458,11 +482,30 @@ struct Oracle {
         if (!(L.par[u] == u && rsize[u] == 1)) continue;   // only singletons move
         Cand c; if (best_ref(r, u, Krout, Krin, c)) cands.push_back(c);
       }
-      std::vector<Cand> B = decouple(cands, false);
+      std::vector<Cand> B = decouple(cands, single_move != 0);
+      i128 before = 0;
+      if (check_moves) before = recount_qnum_refined(r);
       for (auto& c : B) {
         L.par[c.v] = c.b;
         Krout[c.b] += L.kout[c.v]; Krin[c.b] += L.kin[c.v]; rsize[c.b]++;
         Krout[c.v] -= L.kout[c.v]; Krin[c.v] -= L.kin[c.v]; rsize[c.v]--;
+      }
+      if (check_moves) {
+        // A singleton {u} joining refined community y changes the refined partition's numerator
+        // by exactly the predicted gain (directed; twice it for the symmetric matrix of an
+        // undirected graph), and the maintained refined totals equal their recount.
+        const i128 dq_ref = recount_qnum_refined(r) - before;
+        if (single_move && B.size() == 1) {
+          const i128 expect = cfg.directed ? B[0].G : 2 * B[0].G;
+          if (dq_ref != expect && err.empty()) err = "single-move refinement gain differs from recount";
+          checks[3]++;
+        }
+        std::vector<i64> ro(n, 0), ri(n, 0);
+        std::vector<uint32_t> rs(n, 0);
+        for (uint32_t u = 0; u < n; ++u)
+          if (L.alive[u]) { ro[L.par[u]] += L.kout[u]; ri[L.par[u]] += L.kin[u]; rs[L.par[u]]++; }
+        if ((ro != Krout || ri != Krin || rs != rsize) && err.empty()) err = "refined totals differ from recount";
+        checks[1]++;
       }
       record(r, 1, j, R.size(), cands.size(), B.size(), 0);
       if ((i128)cfg.bd * B.size() < (i128)cfg.bn * R.size()) break;
@@ -841,6 +884,13 @@ int orc_check(void* h, char* msg, int cap) {
   if (s.empty() && !o->err.empty()) s = o->err;
   if (msg && cap > 0) { std::strncpy(msg, s.c_str(), cap - 1); msg[cap - 1] = 0; }
   return s.empty() ? OK : ECHECK_;
+}
+
+// Recount checks done so far (FLAG_CHECK_MOVES): [0] move commits, [1] refinement commits,
+// [2] single-move move commits compared with their predicted gain, [3] likewise for refinement.
+void orc_check_counts(void* h, uint64_t* out4) {
+  Oracle* o = (Oracle*)h;
+  for (int i = 0; i < 4; ++i) out4[i] = o->checks[i];
 }
 
 uint64_t orc_trace_len(void* h) { return ((Oracle*)h)->trace.size(); }

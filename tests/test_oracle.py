@@ -201,6 +201,39 @@ def test_every_move_matches_recount(directed, gamma, single):
     assert o.check() == ""
 
 
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("gamma", [(1, 1), (3, 2), (2, 5)])
+def test_every_refinement_move_matches_recount(directed, gamma):
+    """BestRef (Alg. 1 l.18): in single-move mode every refinement commit moves one singleton
+    {u} into an adjacent refined community y, and Eq. 1 recounted from scratch on the refined
+    partition (ground node -> pi_r of its level-r ancestor) changes by exactly the predicted gain
+    q m acc[y] - p (kout_u Krin_y + kin_u Krout_y) (twice that for the symmetric matrix of an
+    undirected graph).  The maintained refined totals must equal their recount after every
+    commit.  A swapped Krin/Krout in the directed gain, or a dropped acc term, fails here."""
+    rng = np.random.default_rng(31 + directed + 5 * gamma[0])
+    total = {"refine_single": 0, "refine": 0}
+    for trial in range(3):
+        n = 60 + 20 * trial
+        s = synth.Stream(n, directed, synth.BASE_SEED + 700 + 10 * trial + directed)
+        s.planted(10, 0.35, 0.04, 1, 8)
+        flags = oracle.FLAG_CHECK_MOVES | oracle.FLAG_SINGLE_MOVE
+        o = oracle.Oracle(n, s.edges(), directed=directed, flags=flags, gamma=gamma, L=2)
+        assert o.last_rc == 0, o.check()
+        # self-loops (not drawn by the generator): they move with their node and cancel
+        loops = [(int(x), int(x), int(rng.integers(1, 9))) for x in rng.choice(n, 4, replace=False)]
+        assert o.apply_batch(ins=np.array(loops, np.uint32)) == 0, o.check()
+        for _ in range(3):
+            b = s.batch(12)
+            assert o.apply_batch(b.ins, b.dels, b.chg) == 0, o.check()
+        assert o.check() == ""
+        c = o.check_counts()
+        for k in total:
+            total[k] += c[k]
+    # the pin really ran: refinement commits were recounted, many against their predicted gain
+    assert total["refine_single"] >= 20, total
+    assert total["refine"] >= total["refine_single"]
+
+
 def test_eq2_differs_by_target_independent_terms():
     """Eq. 2 as printed (K_a and w(v,a) include v) equals the recounted change of Q minus
     2 w_vv / m plus 2 gamma kout_v kin_v / m^2, for arbitrary moves."""
