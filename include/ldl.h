@@ -82,7 +82,9 @@ typedef struct ldl_pair {
  *                       insert-only batch of a graph goes through the general lookup and row-update
  *                       path instead of being laid out directly from its sorted records), 64 = every
  *                       candidate kernel of the degree bins runs as one workgroup (each workgroup
- *                       and wavefront walks many vertices through its software pipeline)
+ *                       and wavefront walks many vertices through its software pipeline),
+ *                       128 = aggregation tuples sorted in chunks of 4,096, and every repair of
+ *                       more than 4,096 tuples done as a rebuild of the level above from scratch
  */
 typedef struct ldl_config {
   int32_t directed;
@@ -129,6 +131,10 @@ typedef struct ldl_batch_stats {
   double search_ms;           /* summed time of whole candidate searches: binning, every bin's
                                  kernel and the hub path's passes and final reduction
                                  (HIP events, profile != 0)                                  */
+  uint64_t max_gain_hi;       /* largest high 64-bit word of any candidate's exact 128-bit gain
+                                 (nonzero once a gain reaches 2^64)                          */
+  uint64_t agg_rebuilds;      /* aggregate levels rebuilt from scratch by Eq. 3 instead of
+                                 repaired by subtract-add tuples (same matrix, lower cost)    */
 } ldl_batch_stats;
 
 /* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */
@@ -188,6 +194,60 @@ int ldl_export_level(const ldl_handle* h, int32_t r, uint8_t* alive, uint32_t* l
 uint64_t ldl_level_nnz(const ldl_handle* h, int32_t r);
 int ldl_export_entries(const ldl_handle* h, int32_t r, uint32_t* rows, uint32_t* cols, int64_t* w);
 
+/* Copy the level-0 partition (as ldl_get_partition) into device memory of the handle's device
+ * (d_labels: n u32 words, caller-owned).  The copy has completed when the call returns. */
+int ldl_get_partition_device(const ldl_handle* h, uint32_t* d_labels, uint64_t n);
+
+/*
+ * Checkpoint of the whole state (paper Sec. III-A: the hierarchy H = (G^0..G^L) with its parent
+ * maps, level labels and cached community totals, plus the exact m, Ein and sum Kout*Kin of
+ * Eq. 1) as an opaque, versioned blob in host memory.  ldl_export_state writes the blob size to
+ * *size; with blob == NULL it only reports the size, with capacity < size it returns LDL_EINVAL
+ * and writes nothing.  Equal states give equal blobs.  ldl_import_state creates a new handle from
+ * a blob (cfg supplies device, stream, profile and test flags, or NULL for the defaults; the
+ * method parameters come from the blob); a handle continued from the import behaves exactly like
+ * the exported one.  A blob that is truncated, of another version, or holds an id >= n, a zero or
+ * negative weight, or a level with 2^31 or more entries is LDL_EINVAL (the blob is only checked
+ * for consistency of its layout; ldl_check_invariants recounts the method's invariants).
+ */
+int ldl_export_state(const ldl_handle* h, void* blob, uint64_t capacity, uint64_t* size);
+int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl_handle** out);
+
+/*
+ * Device-side recount of the state's invariants, reading every stored entry once per
+ * orientation and every node once per level:
+ *   LDL_INV_DEGREES    kout/kin are the row/column sums of each level's matrix (positive weights,
+ *                      entries only between alive nodes, dead nodes have zero degrees)
+ *   LDL_INV_TRANSPOSE  the in-rows of a directed level hold the transpose of its out-rows; an
+ *                      undirected level's matrix is symmetric
+ *   LDL_INV_AGGREGATE  Eq. 3 (Sec. III-F): W_{r+1}(x,y) = sum of W_r(u,v) over pi_r(u) = x,
+ *                      pi_r(v) = y, and a level-(r+1) node is alive iff it has an alive child
+ *   LDL_INV_LABELS     labels nest: P^r(u) = P^{r+1}(pi_r(u)) (Sec. III-A)
+ *   LDL_INV_ROOTS      an alive refined community x contains its root node x at level r
+ *   LDL_INV_TOTALS     m, Ein and the community totals Kout/Kin recounted from the level-0 matrix
+ *                      and P^0, and sum Kout*Kin exactly (the terms of Eq. 1)
+ *   LDL_INV_RANGE      a neighbour id or label outside [0, n)
+ * Degrees, labels, roots, liveness, m, Ein and sum Kout*Kin are compared exactly; the matrix
+ * comparisons (aggregation, transpose) and the per-community totals compare weighted 64-bit
+ * fingerprints (sums of w * h(key) for two fixed odd hash functions), which always differ when a
+ * single entry differs.  report->failed is the mask of failed checks (0: all hold), report->level
+ * the lowest level where one failed (-1: none), report->entries the matrix entries read.  The
+ * call allocates its small block of recount sums on the device and frees it before returning.
+ */
+#define LDL_INV_DEGREES 1u
+#define LDL_INV_TRANSPOSE 2u
+#define LDL_INV_AGGREGATE 4u
+#define LDL_INV_LABELS 8u
+#define LDL_INV_ROOTS 16u
+#define LDL_INV_TOTALS 32u
+#define LDL_INV_RANGE 64u
+typedef struct ldl_invariant_report {
+  uint32_t failed;
+  int32_t level;
+  uint64_t entries;
+} ldl_invariant_report;
+int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report);
+
 /* Per-iteration trace (8 int64 per record: pass, level, phase 0 move / 1 refine, iteration,
  * scanned vertices, candidates, accepted, low 64 bits of the exact batch gain). */
 int ldl_set_trace(ldl_handle* h, int32_t on);
@@ -222,7 +282,8 @@ int ldl_apply_batches(ldl_handle* const* hs, const ldl_batch* bs, uint32_t count
  * different handles overlap on the device.  A request is admitted only while the estimated
  * device-memory footprint of all running requests stays within `mem_budget_bytes` (a request
  * larger than the budget runs alone).  ldl_server_wait blocks until the ticket completes and
- * returns its code, statistics and latency (submission to completion, milliseconds).  A handle
+ * returns its code, statistics and latency (submission to completion, milliseconds); a ticket can
+ * be waited on once (a second or concurrent wait on it returns LDL_EINVAL).  A handle
  * must not be used outside the server while it has queued requests.
  */
 typedef struct ldl_server ldl_server;

@@ -46,7 +46,7 @@ class ldl_batch_stats(ctypes.Structure):
         [("bin_launches", ctypes.c_uint64 * NUM_CATS), ("bin_ms", ctypes.c_double * NUM_CATS),
          ("bin_bytes", ctypes.c_double * NUM_CATS), ("bin_entries", ctypes.c_uint64 * NUM_CATS)] + \
         [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")] + \
-        [("search_ms", ctypes.c_double)]
+        [("search_ms", ctypes.c_double), ("max_gain_hi", ctypes.c_uint64), ("agg_rebuilds", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -62,7 +62,14 @@ ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply
                "ldl_export_level", "ldl_level_nnz", "ldl_export_entries", "ldl_set_trace", "ldl_trace_len",
                "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
                "ldl_server_drain", "ldl_server_destroy", "ldl_get_bins", "ldl_set_bins", "ldl_autotune",
-               "ldl_strerror", "ldl_version")
+               "ldl_strerror", "ldl_version", "ldl_get_partition_device", "ldl_export_state", "ldl_import_state",
+               "ldl_check_invariants")
+
+INV_BITS = {1: "degrees", 2: "transpose", 4: "aggregate", 8: "labels", 16: "roots", 32: "totals", 64: "range"}
+
+
+class ldl_invariant_report(ctypes.Structure):
+    _fields_ = [("failed", ctypes.c_uint32), ("level", ctypes.c_int32), ("entries", ctypes.c_uint64)]
 
 
 class ldl_tune_report(ctypes.Structure):
@@ -149,6 +156,14 @@ def load_library():
     lib.ldl_server_drain.restype = i32
     lib.ldl_server_destroy.argtypes = [vp]
     lib.ldl_server_destroy.restype = None
+    lib.ldl_get_partition_device.argtypes = [vp, vp, u64]
+    lib.ldl_get_partition_device.restype = i32
+    lib.ldl_export_state.argtypes = [vp, vp, u64, P(u64)]
+    lib.ldl_export_state.restype = i32
+    lib.ldl_import_state.argtypes = [P(ldl_config), vp, u64, P(vp)]
+    lib.ldl_import_state.restype = i32
+    lib.ldl_check_invariants.argtypes = [vp, P(ldl_invariant_report)]
+    lib.ldl_check_invariants.restype = i32
     _lib = lib
     return lib
 
@@ -193,6 +208,56 @@ class Graph:
         if rc != LDL_OK:
             raise LdlError(rc, "ldl_create")
         self.h = h.value
+
+    @classmethod
+    def from_state(cls, blob: bytes, device=0, stream=None, profile=False, test_flags=0) -> "Graph":
+        """A new handle restored from an ``export_state`` blob (ldl_import_state)."""
+        lib = load_library()
+        c = ldl_default_config()
+        c.device, c.stream, c.profile, c.test_flags = device, stream, int(bool(profile)), int(test_flags)
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = ctypes.c_void_p()
+        rc = lib.ldl_import_state(ctypes.byref(c), buf, len(blob), ctypes.byref(h))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_import_state")
+        g = cls.__new__(cls)
+        g.lib = lib
+        g.h = h.value
+        hdr = np.frombuffer(bytes(blob[:80]), dtype=np.uint8)
+        cfg = hdr[16:56].view(np.int32)
+        g.n = int(hdr[56:60].view(np.uint32)[0])
+        g.directed = bool(cfg[0])
+        g.L = int(cfg[4])
+        return g
+
+    def export_state(self) -> bytes:
+        """The whole state as an opaque blob (ldl_export_state)."""
+        size = ctypes.c_uint64()
+        rc = self.lib.ldl_export_state(self.h, None, 0, ctypes.byref(size))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_state")
+        buf = ctypes.create_string_buffer(size.value)
+        rc = self.lib.ldl_export_state(self.h, buf, size.value, ctypes.byref(size))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_export_state")
+        return buf.raw
+
+    def check_invariants(self) -> dict:
+        """Device-side recount of the invariants (ldl_check_invariants)."""
+        rep = ldl_invariant_report()
+        rc = self.lib.ldl_check_invariants(self.h, ctypes.byref(rep))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_check_invariants")
+        return {"failed": rep.failed, "level": rep.level, "entries": rep.entries,
+                "names": [v for k, v in INV_BITS.items() if rep.failed & k]}
+
+    def partition_device(self, out_tensor):
+        """Copy the partition into a caller-owned device tensor of n int32/uint32 words."""
+        assert out_tensor.numel() == self.n and out_tensor.element_size() == 4 and out_tensor.is_contiguous()
+        rc = self.lib.ldl_get_partition_device(self.h, ctypes.c_void_p(out_tensor.data_ptr()), self.n)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_get_partition_device")
+        return out_tensor
 
     def close(self):
         if getattr(self, "h", None):

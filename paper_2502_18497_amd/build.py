@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libldl.so")
-SOURCES = ["kernels_graph.hip", "kernels_move.hip", "prims.hip", "engine.hip", "server.cpp"]
+SOURCES = ["kernels_graph.hip", "kernels_move.hip", "kernels_check.hip", "prims.hip", "engine.hip", "server.cpp"]
 ARCH = os.environ.get("LDL_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

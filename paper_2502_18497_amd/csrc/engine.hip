@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "ldl.h"
+#include "ldl_check.h"
 #include "ldl_kernels.h"
 
 namespace ldl {
@@ -84,7 +85,7 @@ struct Scal {
   i64a dm, dein;
   u64a dskk_lo;
   i64a dskk_hi;
-  u64a tcount, tneed, nruns, ecount;
+  u64a tcount, tneed, nruns, ecount, nnz;
   PassScal ps;
 };
 
@@ -165,6 +166,15 @@ struct Engine {
     uint64_t count = 0, cap = 0;
   };
   std::vector<PendBuf> pend;
+  // rebuild_flag[s]: level s's matrix is rebuilt from level s-1 by Eq. 3 before it is next read,
+  // instead of applying its deferred records (set when a repair would sort more tuples than a
+  // rebuild, or more than one chunk); its degrees stay exact meanwhile
+  std::vector<uint8_t> rebuild_flag;
+  // Tuples are sorted in chunks of at most this many (radix-sort and tuple buffers are sized by
+  // it); test flag 128 makes the chunks tiny so that every path through them is exercised.
+  static constexpr uint64_t kTupleChunk = 1ull << 28;
+  uint64_t tuple_chunk() const { return (test_flags & 128) ? 4096 : kTupleChunk; }
+  static constexpr int kChunkSlot = 60;   // ds->counts word holding a chunk's list length
   uint32_t lim[2][kNumBins - 1];   // degree-bin limits for 32-bit (level 0) and 64-bit weights
   uint32_t *accE = nullptr, *accA = nullptr;
   LfFirst lfE{}, lfA{};
@@ -295,17 +305,21 @@ struct Engine {
 
   // per-node tuple counts over the list of set `sid` (k nodes) and their exclusive prefix
   // (toffs); returns the tuple total and grows the tuple buffers
-  uint64_t tuple_offsets(int sid, uint32_t k, CsrRef out, CsrRef in, const uint2* po, int repair) {
+  uint64_t tuple_offsets(int sid, uint32_t k, CsrRef out, CsrRef in, const uint2* po, int repair, bool grow = true) {
+    return tuple_offsets_at(sets[sid].list, &ds->counts[sets[sid].ci], k, out, in, po, repair, grow);
+  }
+  // the same over list[0..k) with its length in the device word cnt; grow = false leaves the
+  // tuple buffers as they are (the caller decides how the tuples are produced)
+  uint64_t tuple_offsets_at(const uint32_t* list, const uint32_t* cnt, uint32_t k, CsrRef out, CsrRef in,
+                            const uint2* po, int repair, bool grow) {
     if (k == 0) return 0;
-    const uint32_t* list = sets[sid].list;
-    const uint32_t* cnt = &ds->counts[sets[sid].ci];
     cub(launch_items(list, nullptr, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
     launch_tuples_count(list, cnt, k, it_off, out, in, po, repair, (u64a*)tcounts, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
     uint64_t T = 0;
     hcheck(hipMemcpyAsync(&T, toffs + k, 8, hipMemcpyDeviceToHost, st));
     hcheck(hipStreamSynchronize(st));
-    ensure_tuples(T + 16);
+    if (grow) ensure_tuples(T + 16);
     return T;
   }
 
@@ -349,6 +363,7 @@ struct Engine {
     hcheck(hipMemsetAsync(ds->counts, 0, sizeof(ds->counts), st));
     lv.resize(L + 1);
     pend.resize(L + 1);
+    rebuild_flag.assign(L + 2, 0);
     for (int r = 0; r <= L; ++r) {
       Level& V = lv[r];
       V.alive = alloc<uint8_t>(n);
@@ -640,6 +655,11 @@ struct Engine {
   void defer(int s, const uint64_t* keys, const int64_t* vals, uint64_t k, bool degrees) {
     if (k == 0) return;
     if (degrees) launch_record_degrees(keys, vals, k, lv[s].kout, directed ? lv[s].kin : nullptr, id_bits, st);
+    if (!rebuild_flag[s] && pend[s].count + k > tuple_chunk()) rebuild_flag[s] = 1;
+    if (rebuild_flag[s]) {   // the rebuild supersedes the records (the degrees are exact already)
+      pend[s].count = 0;
+      return;
+    }
     pend_reserve(s, k);
     PendBuf& p = pend[s];
     hcheck(hipMemcpyAsync(p.keys + p.count, keys, 8 * k, hipMemcpyDeviceToDevice, st));
@@ -650,6 +670,22 @@ struct Engine {
   void flush_to(int s) {
     for (int t = 1; t <= s && t <= top; ++t) {
       PendBuf& p = pend[t];
+      if (rebuild_flag[t]) {
+        p.count = 0;
+        rebuild_flag[t] = 0;
+        build_level(t - 1);
+        stats.agg_rebuilds++;
+        if (t + 1 <= top) {
+          // the change of W_t reaches the level above through a rebuild as well; its degrees
+          // (row sums, read as refined-community totals) are recounted from this level's now
+          Level& U = lv[t + 1];
+          launch_fill_i64(U.kout, 0, n, st);
+          if (directed) launch_fill_i64(U.kin, 0, n, st);
+          launch_degrees_up(n, lv[t].alive, lv[t].par, lv[t].kout, lv[t].kin, U.kout, directed ? U.kin : nullptr, st);
+          rebuild_flag[t + 1] = 1;
+        }
+        continue;
+      }
       const uint64_t k = p.count;
       if (!k) continue;
       p.count = 0;
@@ -964,6 +1000,7 @@ struct Engine {
     }
     scanned = hs->counts[sets[sid].ci];
     K = ps.ncand;
+    if (ps.maxhi > stats.max_gain_hi) stats.max_gain_hi = ps.maxhi;
     // algorithmic bytes: per vertex its list id, offsets and degrees, label, degrees and the
     // totals of its own community; per entry neighbour id, weight and neighbour label (plus
     // the parent in refinement); per distinct community its totals; per candidate 28 bytes.
@@ -1258,15 +1295,30 @@ struct Engine {
     // refinement of this level has finished)
     uint2* po = lpk;
     launch_pack_parents(n, V.par, oldpar, sets[S_C].stamp, sets[S_C].epoch, po, st);
-    const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, po, 1);
-    // the tuples are written straight into the deferred records of level r+1
-    pend_reserve(r + 1, T);
-    PendBuf& pn = pend[r + 1];
-    if (nC)
-      launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, po, 1, toffs,
-                        (u64a*)tcur, pn.keys + pn.count, pn.vals + pn.count, sets[Dn].stamp, sets[Dn].epoch, id_bits,
-                        st);
-    pn.count += T;
+    const uint64_t T = tuple_offsets(S_C, nC, V.out.ref, in, po, 1, false);
+    // Repair by subtract-add tuples, or -- when they would outnumber the tuples of building level
+    // r+1 from scratch (Eq. 3 over every out-entry of level r), or exceed a chunk -- rebuild level
+    // r+1 before it is next read; both give the same matrix (Eq. 3), so only the cost differs.
+    // The rebuild still marks every seed the tuples' endpoints would.
+    bool rebuild_up = rebuild_flag[r + 1] != 0;
+    if (!rebuild_up && T > tuple_chunk()) rebuild_up = true;
+    if (!rebuild_up && T > (1u << 16)) rebuild_up = T > level_out_entries(r);
+    if (rebuild_up) {
+      if (nC)
+        launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, po, 1, toffs,
+                          (u64a*)tcur, nullptr, nullptr, sets[Dn].stamp, sets[Dn].epoch, id_bits, st);
+      rebuild_flag[r + 1] = 1;
+      pend[r + 1].count = 0;
+    } else {
+      // the tuples are written straight into the deferred records of level r+1
+      pend_reserve(r + 1, T);
+      PendBuf& pn = pend[r + 1];
+      if (nC)
+        launch_tuples_gen(sets[S_C].list, &ds->counts[sets[S_C].ci], nC, it_off, V.out.ref, in, V.par, po, 1, toffs,
+                          (u64a*)tcur, pn.keys + pn.count, pn.vals + pn.count, sets[Dn].stamp, sets[Dn].epoch,
+                          id_bits, st);
+      pn.count += T;
+    }
     // NextFrontier: parents of seeds, movers and refined nodes; old parents of changed nodes
     launch_set_add_mapped(ref(Dn), entry, E0, V.par, nullptr, st);
     launch_set_add_mapped(ref(Dn), sets[S_MOVED].list, nMoved, V.par, nullptr, st);
@@ -1306,20 +1358,85 @@ struct Engine {
     Level& V = lv[r];
     Level& H = lv[r + 1];
     launch_materialise_nodes(n, V.rsize, H.alive, V.lab, H.lab, r + 1 < L ? H.par : nullptr, st);
+    build_level(r);
+    top = r + 1;
+    launch_alive_list(n, H.alive, ref(S_D0 + r + 1), st);
+  }
+
+  // out-entries of level r (the tuples of building level r+1 from scratch)
+  uint64_t level_out_entries(int r) {
+    zero(&ds->nnz);
+    launch_sum_u32(lv[r].out.ref.deg, n, &ds->nnz, st);
+    uint64_t k = 0;
+    hcheck(hipMemcpyAsync(&k, &ds->nnz, 8, hipMemcpyDeviceToHost, st));
+    hcheck(hipStreamSynchronize(st));
+    stats.host_syncs++;
+    return k;
+  }
+
+  // every row of c empty and its pool released (the next row update lays the pool out anew)
+  void drop_csr(Csr& c) {
+    hcheck(hipStreamSynchronize(st));
+    release(c.ref.nbr);
+    release(c.ref.w);
+    c.ref.nbr = nullptr;
+    c.ref.w = nullptr;
+    c.pool_cap = 0;
+    hcheck(hipMemsetAsync(c.ref.off, 0, 8ull * n, st));
+    hcheck(hipMemsetAsync(c.ref.deg, 0, 4ull * n, st));
+    hcheck(hipMemsetAsync(c.ref.cap, 0, 4ull * n, st));
+  }
+
+  // W_{r+1} = Eq. 3 of (W_r, pi_r) from scratch into level r+1's emptied rows: the (pi(u), pi(v),
+  // w) tuples of every out-entry of an alive level-r node, in chunks of whole nodes with at most
+  // tuple_chunk() tuples each (one node with more forms its own chunk), each chunk sorted,
+  // reduced and added to the rows (sums over chunks commute).  Level r+1's degrees are exact
+  // already and are not touched.
+  void build_level(int r) {
+    Level& V = lv[r];
+    Level& H = lv[r + 1];
+    drop_csr(H.out);
+    if (directed) drop_csr(H.in);
     begin(S_TMP);
     launch_alive_list(n, V.alive, ref(S_TMP), st);
     sync_read();
     const uint32_t na = count(S_TMP);
-    const uint64_t T = tuple_offsets(S_TMP, na, V.out.ref, CsrRef{}, nullptr, 0);
-    if (na)
-      launch_tuples_gen(sets[S_TMP].list, &ds->counts[sets[S_TMP].ci], na, it_off, V.out.ref, CsrRef{}, V.par, nullptr,
-                        0, toffs, (u64a*)tcur, tk0, tv0, nullptr, 0, id_bits, st);
-    const uint64_t R = sort_reduce(tk0, tv0, T, tk2, tv2);
-    hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
-    hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
-    apply_records(r + 1, tk0, tv0, R, false);
-    top = r + 1;
-    launch_alive_list(n, H.alive, ref(S_D0 + r + 1), st);
+    if (na == 0) return;
+    const uint32_t* list = sets[S_TMP].list;
+    const uint64_t C = tuple_chunk();
+    const uint64_t T = tuple_offsets_at(list, &ds->counts[sets[S_TMP].ci], na, V.out.ref, CsrRef{}, nullptr, 0, false);
+    std::vector<uint64_t> offs;
+    if (T > C) {
+      offs.resize((size_t)na + 1);
+      hcheck(hipMemcpyAsync(offs.data(), toffs, 8ull * ((uint64_t)na + 1), hipMemcpyDeviceToHost, st));
+      hcheck(hipStreamSynchronize(st));
+    }
+    uint32_t* cntp = &ds->counts[kChunkSlot];
+    for (uint32_t i0 = 0; i0 < na;) {
+      uint32_t i1 = na;
+      uint64_t Tc = T;
+      const uint32_t* sub = list + i0;
+      const uint32_t* subcnt = &ds->counts[sets[S_TMP].ci];
+      if (T > C) {
+        // the longest run of nodes from i0 whose tuples fit a chunk (at least one node)
+        const uint64_t limit = offs[i0] + C;
+        i1 = (uint32_t)(std::upper_bound(offs.begin() + i0 + 1, offs.end(), limit) - offs.begin()) - 1;
+        if (i1 <= i0) i1 = i0 + 1;
+        hcheck(hipMemsetD32Async((hipDeviceptr_t)cntp, (int)(i1 - i0), 1, st));
+        subcnt = cntp;
+        Tc = tuple_offsets_at(sub, subcnt, i1 - i0, V.out.ref, CsrRef{}, nullptr, 0, false);
+      }
+      ensure_tuples(Tc + 16);
+      if (Tc) {
+        launch_tuples_gen(sub, subcnt, i1 - i0, it_off, V.out.ref, CsrRef{}, V.par, nullptr, 0, toffs, (u64a*)tcur,
+                          tk0, tv0, nullptr, 0, id_bits, st);
+        const uint64_t R = sort_reduce(tk0, tv0, Tc, tk2, tv2);
+        hcheck(hipMemcpyAsync(tk0, tk2, 8 * R, hipMemcpyDeviceToDevice, st));
+        hcheck(hipMemcpyAsync(tv0, tv2, 8 * R, hipMemcpyDeviceToDevice, st));
+        apply_records(r + 1, tk0, tv0, R, false);
+      }
+      i0 = i1;
+    }
   }
 
   void label_refresh(int r) {
@@ -1459,6 +1576,62 @@ struct Engine {
     pending.clear();
   }
 
+  // ------------------------------------------------------------------ invariant recount
+  // Device recount of the invariants (I1-I3, I5, I6 and the transpose / symmetry of the stored
+  // matrices) with the scratch words at sc: one row pass per CSR and one node pass per level,
+  // then a comparison of the sums on the host.
+  void check_invariants(InvScratch* sc, ldl_invariant_report* rep) {
+    ldl_invariant_report out{};
+    out.level = -1;
+    auto fail = [&](uint32_t bits, int r) {
+      if (!bits) return;
+      out.failed |= bits;
+      if (out.level < 0) out.level = r;
+    };
+    uint64_t prev_w = 0, prev_a1 = 0, prev_a2 = 0;   // parent-mapped sums of the level below
+    for (int r = 0; r <= top; ++r) {
+      Level& V = lv[r];
+      const bool up = r < top;
+      launch_inv_clear(sc, st);
+      launch_inv_rows(V.out.ref, n, V.alive, V.kout, up ? V.par : nullptr, r == 0 ? V.lab : nullptr, 0, sc, st);
+      if (directed) launch_inv_rows(V.in.ref, n, V.alive, V.kin, nullptr, nullptr, 1, sc, st);
+      launch_inv_nodes(n, V.alive, V.lab, up ? V.par : nullptr, up ? V.rsize : nullptr, V.kout, V.kin,
+                       up ? lv[r + 1].alive : nullptr, up ? lv[r + 1].lab : nullptr, r == 0 ? Kout : nullptr,
+                       r == 0 ? Kin : nullptr, sc, st);
+      InvScratch h;
+      hcheck(hipMemcpyAsync(&h, sc, sizeof(InvScratch), hipMemcpyDeviceToHost, st));
+      hcheck(hipStreamSynchronize(st));
+      uint32_t bits = 0;
+      if (h.flags & kInvDegrees) bits |= LDL_INV_DEGREES;
+      if (h.flags & kInvAggregate) bits |= LDL_INV_AGGREGATE;
+      if (h.flags & kInvLabels) bits |= LDL_INV_LABELS;
+      if (h.flags & kInvRoots) bits |= LDL_INV_ROOTS;
+      if (h.flags & kInvRange) bits |= LDL_INV_RANGE;
+      // the in-rows hold the transpose of the out-rows (directed); an undirected matrix is symmetric
+      const bool tr_ok = directed ? (h.out[0] == h.in[0] && h.out[1] == h.in[1] && h.out[2] == h.in[2] &&
+                                     h.out[3] == h.in[3])
+                                  : (h.out[2] == h.out[4] && h.out[3] == h.out[5]);
+      if (!tr_ok) bits |= LDL_INV_TRANSPOSE;
+      // Eq. 3: this level's matrix is the grouped sum of the level below under its parents
+      if (r >= 1 && !(h.out[1] == prev_w && h.out[2] == prev_a1 && h.out[3] == prev_a2)) bits |= LDL_INV_AGGREGATE;
+      if (up) {
+        prev_w = h.out[1];
+        prev_a1 = h.out[6];
+        prev_a2 = h.out[7];
+        if (h.node[0] != h.node[1]) bits |= LDL_INV_AGGREGATE;   // refined sizes count the children
+      }
+      if (r == 0) {
+        const i128 skk = ((i128)(int64_t)h.skk_hi << 64) | (i128)h.node[kInvNodeWords];
+        const bool tot_ok = (int64_t)h.out[1] == m && (int64_t)h.out[8] == Ein && h.node[2] == h.node[4] &&
+                            h.node[3] == h.node[5] && (int64_t)h.node[6] == m && (int64_t)h.node[7] == m && skk == SKK;
+        if (!tot_ok) bits |= LDL_INV_TOTALS;
+      }
+      fail(bits, r);
+      out.entries += h.out[0] + (directed ? h.in[0] : 0);
+    }
+    if (rep) *rep = out;
+  }
+
   // ------------------------------------------------------------------ export
   void export_entries(int r, std::vector<uint64_t>& keys, std::vector<int64_t>& w) {
     Level& V = lv[r];
@@ -1479,6 +1652,199 @@ struct Engine {
     std::sort(kv.begin(), kv.end());
     for (uint64_t i = 0; i < nnz; ++i) { keys[i] = kv[i].first; w[i] = kv[i].second; }
   }
+  // ------------------------------------------------------------------ state blob
+  // Layout (little-endian): StateHeader, community totals Kout[n] (and Kin[n] when directed),
+  // then per level r = 0..top: alive u8[n], lab u32[n], (r < L) par u32[n] and rsize u32[n],
+  // kout i64[n], (directed) kin i64[n], deg u32[n] (out-rows), nnz u64, then the row-major
+  // entries: columns u32[nnz] (ascending within a row) and weights (u32 at level 0, i64 above).
+  struct StateHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int32_t cfg[10];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den
+    uint32_t n;
+    int32_t top;
+    int64_t m, ein, skk_hi;
+    uint64_t skk_lo;
+    uint32_t lim[2][5];
+    uint64_t total_bytes;
+  };
+  static constexpr uint32_t kStateVersion = 1;
+  uint64_t level_node_bytes(int r) const {
+    return (uint64_t)n * (1 + 4 + (r < L ? 8 : 0) + 8 + (directed ? 8 : 0) + 4) + 8;
+  }
+  uint64_t state_bytes(std::vector<uint64_t>& nnz) {
+    nnz.assign(top + 1, 0);
+    uint64_t b = sizeof(StateHeader) + 8ull * n * (directed ? 2 : 1);
+    for (int r = 0; r <= top; ++r) {
+      nnz[r] = nnz_of(r);
+      b += level_node_bytes(r) + nnz[r] * (4 + (r == 0 ? 4 : 8));
+    }
+    return b;
+  }
+  void export_state(uint8_t* out, uint64_t bytes) {
+    uint8_t* p = out;
+    auto put = [&](const void* src, uint64_t k) {
+      std::memcpy(p, src, k);
+      p += k;
+    };
+    auto put_dev = [&](const void* dsrc, uint64_t k) {
+      hcheck(hipMemcpyAsync(p, dsrc, k, hipMemcpyDeviceToHost, st));
+      hcheck(hipStreamSynchronize(st));
+      p += k;
+    };
+    StateHeader hd{};
+    std::memcpy(hd.magic, "LDLSTATE", 8);
+    hd.version = kStateVersion;
+    hd.header_bytes = sizeof(StateHeader);
+    const int32_t c10[10] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
+                             (int32_t)bd};
+    std::memcpy(hd.cfg, c10, sizeof(c10));
+    hd.n = n;
+    hd.top = top;
+    hd.m = m;
+    hd.ein = Ein;
+    hd.skk_hi = (int64_t)(SKK >> 64);
+    hd.skk_lo = (uint64_t)SKK;
+    std::memcpy(hd.lim, lim, sizeof(hd.lim));
+    hd.total_bytes = bytes;
+    put(&hd, sizeof hd);
+    put_dev(Kout, 8ull * n);
+    if (directed) put_dev(Kin, 8ull * n);
+    for (int r = 0; r <= top; ++r) {
+      Level& V = lv[r];
+      put_dev(V.alive, n);
+      put_dev(V.lab, 4ull * n);
+      if (r < L) {
+        put_dev(V.par, 4ull * n);
+        put_dev(V.rsize, 4ull * n);
+      }
+      put_dev(V.kout, 8ull * n);
+      if (directed) put_dev(V.kin, 8ull * n);
+      std::vector<uint64_t> keys;
+      std::vector<int64_t> w;
+      export_entries(r, keys, w);   // sorted by (row, column)
+      std::vector<uint32_t> deg(n, 0);
+      for (uint64_t k : keys) deg[k >> 32]++;
+      put(deg.data(), 4ull * n);
+      const uint64_t nnz = keys.size();
+      put(&nnz, 8);
+      for (uint64_t k : keys) {
+        const uint32_t c = (uint32_t)k;
+        put(&c, 4);
+      }
+      if (r == 0) {
+        for (int64_t x : w) {
+          const uint32_t v = (uint32_t)x;
+          put(&v, 4);
+        }
+      } else {
+        put(w.data(), 8 * nnz);
+      }
+    }
+    if ((uint64_t)(p - out) != bytes) throw DeviceError{hipErrorUnknown};
+  }
+  // Restore a state written by export_state into this freshly initialised engine (same n and
+  // parameters).  The caller has checked the header and the blob's size.
+  int import_state(const uint8_t* blob, uint64_t bytes) {
+    const StateHeader& hd = *(const StateHeader*)blob;
+    const uint8_t* p = blob + sizeof(StateHeader);
+    const uint8_t* end = blob + bytes;
+    auto take = [&](uint64_t k) -> const uint8_t* {
+      if ((uint64_t)(end - p) < k) return nullptr;
+      const uint8_t* q = p;
+      p += k;
+      return q;
+    };
+    if (hd.top < 0 || hd.top > L) return LDL_EINVAL;
+    if (hd.m < 0 || hd.m >= ((int64_t)1 << 40)) return LDL_EINVAL;
+    for (int w = 0; w < 2; ++w)
+      if (!valid_limits(hd.lim[w])) return LDL_EINVAL;
+    // validate the whole blob on the host before any device state is written
+    struct LevelPtrs {
+      const uint8_t *alive, *lab, *par, *rsize, *kout, *kin, *deg, *cols, *w;
+      uint64_t nnz;
+    };
+    const uint8_t* kout_t = take(8ull * n);
+    const uint8_t* kin_t = directed ? take(8ull * n) : kout_t;
+    if (!kout_t || !kin_t) return LDL_EINVAL;
+    std::vector<LevelPtrs> lp(hd.top + 1);
+    for (int r = 0; r <= hd.top; ++r) {
+      LevelPtrs& q = lp[r];
+      q.alive = take(n);
+      q.lab = take(4ull * n);
+      q.par = r < L ? take(4ull * n) : nullptr;
+      q.rsize = r < L ? take(4ull * n) : nullptr;
+      q.kout = take(8ull * n);
+      q.kin = directed ? take(8ull * n) : q.kout;
+      q.deg = take(4ull * n);
+      const uint8_t* nz = take(8);
+      if (!q.alive || !q.lab || (r < L && (!q.par || !q.rsize)) || !q.kout || !q.kin || !q.deg || !nz)
+        return LDL_EINVAL;
+      std::memcpy(&q.nnz, nz, 8);
+      if (q.nnz >= (1ull << 31)) return LDL_EINVAL;   // restored through the row-update path
+      q.cols = take(4 * q.nnz);
+      q.w = take((r == 0 ? 4 : 8) * q.nnz);
+      if (!q.cols || !q.w) return LDL_EINVAL;
+      const uint32_t* lab = (const uint32_t*)q.lab;
+      const uint32_t* deg = (const uint32_t*)q.deg;
+      const uint32_t* cols = (const uint32_t*)q.cols;
+      uint64_t sum = 0;
+      for (uint32_t u = 0; u < n; ++u) {
+        if (lab[u] >= n || (q.par && ((const uint32_t*)q.par)[u] >= n)) return LDL_EINVAL;
+        sum += deg[u];
+      }
+      if (sum != q.nnz) return LDL_EINVAL;
+      uint64_t k = 0;
+      for (uint32_t u = 0; u < n; ++u)
+        for (uint32_t i = 0; i < deg[u]; ++i, ++k) {
+          if (cols[k] >= n || (i && cols[k] <= cols[k - 1])) return LDL_EINVAL;   // ascending, distinct
+          const int64_t w = r == 0 ? (int64_t)((const uint32_t*)q.w)[k] : ((const int64_t*)q.w)[k];
+          if (w <= 0) return LDL_EINVAL;
+        }
+    }
+    if (p != end) return LDL_EINVAL;
+    mutating = true;
+    hcheck(hipMemcpyAsync(Kout, kout_t, 8ull * n, hipMemcpyHostToDevice, st));
+    if (directed) hcheck(hipMemcpyAsync(Kin, kin_t, 8ull * n, hipMemcpyHostToDevice, st));
+    top = hd.top;
+    for (int r = 0; r <= top; ++r) {
+      const LevelPtrs& q = lp[r];
+      Level& V = lv[r];
+      hcheck(hipMemcpyAsync(V.alive, q.alive, n, hipMemcpyHostToDevice, st));
+      hcheck(hipMemcpyAsync(V.lab, q.lab, 4ull * n, hipMemcpyHostToDevice, st));
+      if (r < L) {
+        hcheck(hipMemcpyAsync(V.par, q.par, 4ull * n, hipMemcpyHostToDevice, st));
+        hcheck(hipMemcpyAsync(V.rsize, q.rsize, 4ull * n, hipMemcpyHostToDevice, st));
+      }
+      if (q.nnz) {   // rows through the general row-update path (the degrees are restored below)
+        std::vector<uint64_t> keys(q.nnz);
+        std::vector<int64_t> w(q.nnz);
+        const uint32_t* deg = (const uint32_t*)q.deg;
+        const uint32_t* cols = (const uint32_t*)q.cols;
+        uint64_t k = 0;
+        for (uint32_t u = 0; u < n; ++u)
+          for (uint32_t i = 0; i < deg[u]; ++i, ++k) {
+            keys[k] = ((uint64_t)u << id_bits) | cols[k];
+            w[k] = r == 0 ? (int64_t)((const uint32_t*)q.w)[k] : ((const int64_t*)q.w)[k];
+          }
+        ensure_tuples(q.nnz + 16);
+        hcheck(hipMemcpyAsync(tk0, keys.data(), 8 * q.nnz, hipMemcpyHostToDevice, st));
+        hcheck(hipMemcpyAsync(tv0, w.data(), 8 * q.nnz, hipMemcpyHostToDevice, st));
+        apply_records(r, tk0, tv0, q.nnz, false);
+        hcheck(hipStreamSynchronize(st));
+      }
+      hcheck(hipMemcpyAsync(V.kout, q.kout, 8ull * n, hipMemcpyHostToDevice, st));
+      if (directed) hcheck(hipMemcpyAsync(V.kin, q.kin, 8ull * n, hipMemcpyHostToDevice, st));
+      hcheck(hipStreamSynchronize(st));
+    }
+    m = hd.m;
+    Ein = hd.ein;
+    SKK = ((i128)hd.skk_hi << 64) | (i128)hd.skk_lo;
+    std::memcpy(lim, hd.lim, sizeof(lim));
+    mutating = false;
+    return LDL_OK;
+  }
+
   uint64_t nnz_of(int r) {
     std::vector<uint32_t> deg(n);
     hcheck(hipMemcpyAsync(deg.data(), lv[r].out.ref.deg, 4ull * n, hipMemcpyDeviceToHost, st));
@@ -1745,6 +2111,91 @@ int ldl_export_entries(const ldl_handle* h, int32_t r, uint32_t* rows, uint32_t*
       cols[i] = (uint32_t)keys[i];
       w[i] = ws[i];
     }
+    return LDL_OK;
+  });
+}
+
+int ldl_get_partition_device(const ldl_handle* h, uint32_t* d_labels, uint64_t n) {
+  if (!h || !d_labels || n != h->e->n) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    ldl::hcheck(hipMemcpyAsync(d_labels, e.lv[0].lab, 4ull * e.n, hipMemcpyDeviceToDevice, e.st));
+    ldl::hcheck(hipStreamSynchronize(e.st));
+    return LDL_OK;
+  });
+}
+
+int ldl_export_state(const ldl_handle* h, void* blob, uint64_t capacity, uint64_t* size) {
+  if (!h || !size) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    std::vector<uint64_t> nnz;
+    const uint64_t bytes = e.state_bytes(nnz);
+    *size = bytes;
+    if (!blob) return LDL_OK;
+    if (capacity < bytes) return LDL_EINVAL;
+    e.export_state((uint8_t*)blob, bytes);
+    return LDL_OK;
+  });
+}
+
+int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl_handle** out) {
+  if (!out) return LDL_EINVAL;
+  *out = nullptr;
+  using Hd = ldl::Engine::StateHeader;
+  if (!blob || size < sizeof(Hd)) return LDL_EINVAL;
+  Hd hd;
+  std::memcpy(&hd, blob, sizeof(Hd));
+  if (std::memcmp(hd.magic, "LDLSTATE", 8) != 0 || hd.version != ldl::Engine::kStateVersion ||
+      hd.header_bytes != sizeof(Hd) || hd.total_bytes != size || hd.n == 0)
+    return LDL_EINVAL;
+  ldl_config c;
+  ldl_default_config(&c);
+  if (cfg) c = *cfg;   // device, stream, profile and test flags from the caller
+  c.directed = hd.cfg[0];
+  c.gamma_num = hd.cfg[1]; c.gamma_den = hd.cfg[2];
+  c.N = hd.cfg[3]; c.L = hd.cfg[4]; c.M = hd.cfg[5];
+  c.alpha_num = hd.cfg[6]; c.alpha_den = hd.cfg[7];
+  c.beta_num = hd.cfg[8]; c.beta_den = hd.cfg[9];
+  if (!cfg_ok(c)) return LDL_EINVAL;
+  ldl_handle* h = new (std::nothrow) ldl_handle;
+  if (!h) return LDL_ENOMEM;
+  h->e = new (std::nothrow) ldl::Engine();
+  if (!h->e) {
+    delete h;
+    return LDL_ENOMEM;
+  }
+  int rc = run_guarded(h, [&]() -> int {
+    h->e->init(c, hd.n);
+    return h->e->import_state((const uint8_t*)blob, size);
+  });
+  if (rc != LDL_OK) {
+    delete h->e;
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return LDL_OK;
+}
+
+int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report) {
+  if (!h || !report) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    ldl::InvScratch* sc = ldl::dalloc<ldl::InvScratch>(1);   // the recount's sums, freed on return
+    try {
+      e.check_invariants(sc, report);
+    } catch (...) {
+      (void)hipFree(sc);
+      throw;
+    }
+    (void)hipFree(sc);
     return LDL_OK;
   });
 }

@@ -1009,6 +1009,26 @@ __global__ void k_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t
   }
 }
 
+// *total += sum of a[0..n) (one atomic per wavefront)
+__global__ void k_sum_u32(const uint32_t* a, uint32_t n, u64a* total) {
+  uint64_t t = 0;
+  for (uint64_t i = gtid(); i < n; i += gstride()) t += a[i];
+  t = (uint64_t)wave_sum_i64((int64_t)t);
+  if (lane_id() == 0 && t) atomicAdd(total, (u64a)t);
+}
+
+// kout_up[par[u]] += kout[u] (and kin) over the alive nodes u < n: degrees of the level above as
+// sums over its children (zeroed beforehand)
+__global__ void k_degrees_up(uint32_t n, const uint8_t* alive, const uint32_t* par, const int64_t* kout,
+                             const int64_t* kin, int64_t* kout_up, int64_t* kin_up) {
+  for (uint64_t u = gtid(); u < n; u += gstride()) {
+    if (!alive[u]) continue;
+    const uint32_t x = par[u];
+    if (kout[u]) atomic_add_i64(&kout_up[x], kout[u]);
+    if (kin_up && kin[u]) atomic_add_i64(&kin_up[x], kin[u]);
+  }
+}
+
 __global__ void k_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out) {
   const int lane = lane_id();
   for (uint64_t u = gwave(); u < n; u += gwstride()) {
@@ -1189,7 +1209,9 @@ __global__ void k_tuples_count(const uint32_t* list, const uint32_t* countp, uin
   });
 }
 
-template <bool REPAIR>
+// WRITE = false (repair only): no tuples are written, only the seeds their endpoints would mark
+// (used when the level above is rebuilt from scratch instead of repaired).
+template <bool REPAIR, bool WRITE>
 __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint32_t bound, const uint64_t* ioff,
                              CsrRef out, CsrRef in, const uint32_t* par, const uint2* po, const uint64_t* toffs,
                              u64a* cur, uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep,
@@ -1230,15 +1252,19 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
           tvals[base + j] = w;
         } else {
           const uint32_t px = qx.x, ox = qx.y;
-          tkeys[base + 2 * j] = kpack(ou, ox, ks);
-          tvals[base + 2 * j] = -w;
-          tkeys[base + 2 * j + 1] = kpack(pu, px, ks);
-          tvals[base + 2 * j + 1] = w;
+          if (WRITE) {
+            tkeys[base + 2 * j] = kpack(ou, ox, ks);
+            tvals[base + 2 * j] = -w;
+            tkeys[base + 2 * j + 1] = kpack(pu, px, ks);
+            tvals[base + 2 * j + 1] = w;
+          }
           seed_stamp[ox] = seed_ep;
           seed_stamp[px] = seed_ep;
         }
       }
-      if (REPAIR && jb + kWave > dout) {
+      if (REPAIR && !WRITE && jb + kWave > dout) {
+        if (valid && j >= dout && qx.x == qx.y) seed_stamp[qx.x] = seed_ep;
+      } else if (REPAIR && jb + kWave > dout) {
         const bool act = valid && j >= dout && qx.x == qx.y;   // neighbour keeps its parent
         const uint64_t m = __ballot(act);
         if (m) {
@@ -1622,12 +1648,15 @@ void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t b
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
                        CsrRef in, const uint32_t* par, const uint2* po, int repair, const uint64_t* toffs, u64a* cur,
                        uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s) {
-  if (repair)
-    k_tuples_gen<true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur, tkeys, tvals,
-                                                    seed_stamp, seed_ep, ks);
+  if (repair && !tkeys)
+    k_tuples_gen<true, false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur,
+                                                           tkeys, tvals, seed_stamp, seed_ep, ks);
+  else if (repair)
+    k_tuples_gen<true, true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur,
+                                                          tkeys, tvals, seed_stamp, seed_ep, ks);
   else
-    k_tuples_gen<false><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur, tkeys,
-                                                     tvals, seed_stamp, seed_ep, ks);
+    k_tuples_gen<false, true><<<kItemBlocks, kTpb, 0, s>>>(list, count, bound, ioff, out, in, par, po, toffs, cur,
+                                                           tkeys, tvals, seed_stamp, seed_ep, ks);
 }
 void launch_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n) k_fill_u32<<<grid_for(n), kTpb, 0, s>>>(p, v, n);
@@ -1835,6 +1864,13 @@ void launch_bulk_mark(uint32_t n, CsrRef out, CsrRef in, const uint32_t* lab0, c
 void launch_bulk_totals(uint32_t n, const uint32_t* lab0, const int64_t* kout, const int64_t* kin_or_null, int64_t* Kout,
                         int64_t* Kin_or_null, hipStream_t s) {
   if (n) k_bulk_totals<<<grid_for(n), kTpb, 0, s>>>(n, lab0, kout, kin_or_null, Kout, Kin_or_null);
+}
+void launch_degrees_up(uint32_t n, const uint8_t* alive, const uint32_t* par, const int64_t* kout, const int64_t* kin,
+                       int64_t* kout_up, int64_t* kin_up_or_null, hipStream_t s) {
+  if (n) k_degrees_up<<<grid_for(n), kTpb, 0, s>>>(n, alive, par, kout, kin, kout_up, kin_up_or_null);
+}
+void launch_sum_u32(const uint32_t* a, uint32_t n, u64a* total, hipStream_t s) {
+  if (n) k_sum_u32<<<grid_for(n) < 1024u ? grid_for(n) : 1024u, kTpb, 0, s>>>(a, n, total);
 }
 void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t s) {
   if (n) k_recount_degrees<<<grid_waves(n), kTpb, 0, s>>>(c, n, deg_out);

@@ -145,6 +145,7 @@ void launch_pack_parents(uint32_t n, const uint32_t* par, const uint32_t* oldpar
 // (repair: a neighbour x changed parent iff po[x].x != po[x].y; otherwise po is unused)
 void launch_tuples_count(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
                          CsrRef in, const uint2* po, int repair, u64a* counts, hipStream_t s);
+// (repair with tkeys == nullptr: only the seeds are marked, no tuple is written)
 void launch_tuples_gen(const uint32_t* list, const uint32_t* count, uint32_t bound, const uint64_t* ioff, CsrRef out,
                        CsrRef in, const uint32_t* par, const uint2* po, int repair, const uint64_t* toffs, u64a* cur,
                        uint64_t* tkeys, int64_t* tvals, uint32_t* seed_stamp, uint32_t seed_ep, int ks, hipStream_t s);
@@ -346,6 +347,11 @@ void launch_materialise_nodes(uint32_t n, const uint32_t* rsize, uint8_t* alive_
 void launch_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t* par, const uint32_t* lab_up,
                           uint32_t* lab, SetRef seeds, hipStream_t s);
 void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t s);
+// *total += sum of a[0..n)
+void launch_sum_u32(const uint32_t* a, uint32_t n, u64a* total, hipStream_t s);
+// kout_up[par[u]] += kout[u] (kin likewise when kin_up_or_null is set) over alive u < n
+void launch_degrees_up(uint32_t n, const uint8_t* alive, const uint32_t* par, const int64_t* kout, const int64_t* kin,
+                       int64_t* kout_up, int64_t* kin_up_or_null, hipStream_t s);
 
 // ---------------------------------------------------------------- library primitives (hipCUB)
 // temp storage is grown on demand through *tmp / *tmp_bytes (device memory owned by caller)

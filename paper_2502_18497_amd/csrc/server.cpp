@@ -35,6 +35,7 @@ struct ldl_server {
     uint64_t fp;
     Clock::time_point submit;
     bool done = false;
+    bool claimed = false;   // a waiter owns the result (a second wait on the ticket is refused)
     int rc = LDL_OK;
     ldl_batch_stats stats{};
     double latency_ms = 0;
@@ -149,6 +150,8 @@ int ldl_server_wait(ldl_server* s, uint64_t ticket, int* status, ldl_batch_stats
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return LDL_EINVAL;
   ldl_server::Request* r = it->second;
+  if (r->claimed) return LDL_EINVAL;   // another thread waits on this ticket and will free it
+  r->claimed = true;
   s->cv_done.wait(lk, [&] { return r->done; });
   if (status) *status = r->rc;
   if (stats) *stats = r->stats;

@@ -144,3 +144,49 @@ def diff_states(a: dict, b: dict) -> list[str]:
         if not (np.array_equal(ka[oa], kb[ob]) and np.array_equal(A["w"][oa], B["w"][ob])):
             d.append(f"level {r}: matrix entries differ")
     return d
+
+
+def state_digest(st: dict) -> dict:
+    """SHA-256 digests of an exported state, field by field, in the comparison of diff_states
+    (node arrays on alive nodes, parents below the top level, matrix entries in key order), plus
+    a few plain values for reading a mismatch."""
+    import hashlib
+
+    def h(*arrs):
+        d = hashlib.sha256()
+        for a in arrs:
+            d.update(np.ascontiguousarray(a).tobytes())
+        return d.hexdigest()[:32]
+
+    out = {"top": int(st["top"]), "m": int(st["m"]), "Ein": int(st["Ein"]), "SKK": str(int(st["SKK"])),
+           "Kout": h(st["Kout"].astype("<i8")), "Kin": h(st["Kin"].astype("<i8")), "levels": []}
+    for r, L in enumerate(st["levels"]):
+        al = L["alive"].astype(bool)
+        k = _keys(L["rows"], L["cols"])
+        w = L["w"].astype("<i8")
+        if len(k) > 1 and not bool(np.all(k[1:] > k[:-1])):
+            o = np.argsort(k, kind="stable")
+            k, w = k[o], w[o]
+        lv = {"alive": h(L["alive"].astype(np.uint8)), "n_alive": int(al.sum()), "lab": h(L["lab"][al].astype("<u4")),
+              "kout": h(L["kout"][al].astype("<i8")), "kin": h(L["kin"][al].astype("<i8")), "nnz": int(len(k)),
+              "entries": h(k.astype("<u8"), w)}
+        if r < st["top"]:
+            lv["par"] = h(L["par"][al].astype("<u4"))
+        out["levels"].append(lv)
+    lab0 = st["levels"][0]["lab"]
+    out["communities"] = int(len(np.unique(lab0)))
+    out["labels_head"] = [int(x) for x in lab0[:8]]
+    return out
+
+
+def digest_diff(a: dict, b: dict) -> list[str]:
+    """Fields in which two state digests differ."""
+    d = []
+    for k in ("top", "m", "Ein", "SKK", "Kout", "Kin", "communities", "labels_head"):
+        if a.get(k) != b.get(k):
+            d.append(f"{k}: {a.get(k)} != {b.get(k)}")
+    for r, (x, y) in enumerate(zip(a["levels"], b["levels"])):
+        for k in sorted(set(x) | set(y)):
+            if x.get(k) != y.get(k):
+                d.append(f"level {r} {k}: {x.get(k)} != {y.get(k)}")
+    return d

@@ -1,0 +1,100 @@
+"""GPU (HIP, gfx950) versus the CPU oracle on the cases that stress exactness rather than size:
+gains whose exact 128-bit value needs the high word, the rollback branch of Alg. 1 l.11, and the
+parameter settings of the batch-regime and parameter sweep.  Full state bit-identical after every
+step (partition, Q numerator, totals, every level's nodes and matrix)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpucases import run_parity
+from tests.statecheck import check_state, diff_states, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("gamma", [(1, 1), (1, 65535), (3, 2)])
+def test_gains_beyond_64_bits(directed, gamma):
+    """Weights in [2^31, 2^32 - 1] with m just below 2^40 (about 8.6e11): q m acc[b] exceeds 2^64,
+    so every candidate gain, the decoupling filter's ordering, the sum of Kout*Kin and the Q
+    numerator work in the high 64-bit word.  The GPU must report a nonzero high word and agree
+    with the oracle bit for bit after the load and every batch."""
+    import paper_2502_18497_amd as ldl
+
+    s = synth.Stream(64, directed, synth.BASE_SEED + 800 + directed)
+    s.planted(8, 0.35, 0.03, 2 ** 31, 2 ** 32 - 1)
+    e = s.edges()
+    og = oracle.Oracle(64, np.zeros((0, 3), np.uint32), directed=directed, gamma=gamma)
+    g = ldl.Graph(64, np.zeros((0, 3), np.uint32), directed=directed, gamma=gamma)
+    assert og.apply_batch(ins=e) == 0
+    st = g.apply_batch(ins=e)
+    sc = og.scalars()
+    assert 2 ** 39 < sc["m"] < 2 ** 40
+    maxhi = st["max_gain_hi"]
+    msgs = diff_states(g.state(), oracle_state(og))
+    assert not msgs, ("load", msgs)
+    assert g.qnum() == og.qnum()
+    for i in range(4):
+        b = s.batch(10, 0.3, 0.4)   # more deletions than insertions keeps m below 2^40
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+        st = g.apply_batch(b.ins, b.dels, b.chg)
+        maxhi = max(maxhi, st["max_gain_hi"])
+        msgs = diff_states(g.state(), oracle_state(og))
+        assert not msgs, (f"batch {i}", msgs)
+        assert g.qnum() == og.qnum()
+    assert maxhi > 0, "no candidate gain reached 2^64"
+    assert abs(og.scalars()["SKK"]) >= 2 ** 64   # the sum of Kout*Kin needs the high word too
+    assert not check_state(g.state(), directed)
+
+
+@pytest.mark.parametrize("trial", [16, 156, 196])
+def test_rollback_branch_taken(trial):
+    """Seeded undirected planted partitions (300 vertices in blocks of 30) with a move iteration
+    at an aggregate level whose exact batch gain is negative, so Alg. 1 l.11 rolls the whole
+    iteration back: in the static run (trials 16, 196) or in the third batch (trial 156), as the
+    oracle's trace shows.  The GPU must take the same branch at the same iteration (its
+    statistics count each rollback) and stay bit-identical."""
+    import paper_2502_18497_amd as ldl
+    from tests.gpucases import first_trace_divergence
+
+    s = synth.Stream(300, False, synth.BASE_SEED + 5000 + trial)
+    s.planted(30, 0.25, 0.02, 1, 8)
+    e = s.edges()
+    og = oracle.Oracle(300, np.zeros((0, 3), np.uint32), flags=oracle.FLAG_TRACE)
+    g = ldl.Graph(300, np.zeros((0, 3), np.uint32))
+    total = 0
+    for step in range(4):
+        if step == 0:   # static Leiden as the first batch (equal to creation)
+            ins, dels, chg = e, None, None
+        else:
+            b = s.batch(40)
+            ins, dels, chg = b.ins, b.dels, b.chg
+        og.trace_clear()
+        g.set_trace(True)
+        assert og.apply_batch(ins, dels, chg) == 0
+        st = g.apply_batch(ins, dels, chg)
+        to, tg = og.trace(), g.trace()
+        assert np.array_equal(tg, to), (step, first_trace_divergence(tg, to))
+        rolled = sum(1 for r in to.tolist() if r[2] == 0 and r[7] < 0)
+        assert st["rollbacks"] == rolled, (step, st["rollbacks"], rolled)
+        total += rolled
+        msgs = diff_states(g.state(), oracle_state(og))
+        assert not msgs, (step, msgs)
+    assert total > 0, "no rollback happened"
+
+
+@pytest.mark.parametrize("cfg", [dict(L=2), dict(L=8), dict(M=3), dict(M=10), dict(alpha=(1, 100)),
+                                 dict(beta=(1, 10)), dict(N=1, L=8, M=10)])
+def test_sweep_parameter_settings(cfg):
+    """The N, L, M, alpha, beta settings the parameter sweep times, bit-exact on a planted
+    partition of 3,000 vertices with batches of 100."""
+    s = synth.planted_small(seed_offset=145, n=3000, blocks=30, p_in=0.05, p_out=0.002)
+    run_parity(s.n, s.edges(), [s.batch(100) for _ in range(3)], **cfg)
+
+
+@pytest.mark.parametrize("cfg", [dict(L=8), dict(M=10, beta=(1, 10))])
+def test_sweep_parameter_settings_directed(cfg):
+    s = synth.Stream(2000, True, synth.BASE_SEED + 146)
+    s.planted(100, 0.04, 0.002, 1, 8)
+    run_parity(s.n, s.edges(), [s.batch(80) for _ in range(3)], directed=True, **cfg)

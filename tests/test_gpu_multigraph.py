@@ -10,15 +10,29 @@ from tests.statecheck import diff_states, oracle_state
 pytestmark = pytest.mark.gpu
 
 SIZES = [400, 900, 2500, 6000, 700, 12000]
+DIRECTED = [False, True, False, True, False, False]   # the mix holds directed graphs too
 
 
 def _graphs(seed0):
     out = []
     for i, n in enumerate(SIZES):
-        s = synth.Stream(n, False, synth.BASE_SEED + seed0 + 1000 * i)
+        s = synth.Stream(n, DIRECTED[i], synth.BASE_SEED + seed0 + 1000 * i)
         s.planted(100, 0.12, 0.6 * 12 / max(1, n - 100), 1, 8)
         out.append(s)
     return out
+
+
+def _graph(s, e):
+    import paper_2502_18497_amd as ldl
+
+    return ldl.Graph(s.n, e, directed=s.directed)
+
+
+def _oracle_matches(g, s, e, batches):
+    o = oracle.Oracle(s.n, e, directed=s.directed)
+    for b in batches:
+        assert o.apply_batch(b.ins, b.dels, b.chg) == 0
+    return diff_states(g.state(), oracle_state(o))
 
 
 def _stream_batches(streams, per_graph, rng):
@@ -34,8 +48,8 @@ def test_apply_batches_equals_alone():
     streams = _graphs(300)
     edges = [s.edges() for s in streams]
     batches = _stream_batches(streams, 4, rng)
-    mixed = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
-    alone = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+    mixed = [_graph(s, e) for s, e in zip(streams, edges)]
+    alone = [_graph(s, e) for s, e in zip(streams, edges)]
     # interleave: step j holds batch j of every graph, in a shuffled graph order
     for j in range(4):
         order = rng.permutation(len(streams))
@@ -48,12 +62,10 @@ def test_apply_batches_equals_alone():
             gr.apply_batch(b.ins, b.dels, b.chg)
     for g in range(len(streams)):
         assert not diff_states(mixed[g].state(), alone[g].state()), g
-    # and against the oracle for two graphs
+    # and against the oracle for an undirected and a directed graph
     for g in (0, 3):
-        o = oracle.Oracle(streams[g].n, edges[g])
-        for b in batches[g]:
-            assert o.apply_batch(b.ins, b.dels, b.chg) == 0
-        assert not diff_states(mixed[g].state(), oracle_state(o)), g
+        msgs = _oracle_matches(mixed[g], streams[g], edges[g], batches[g])
+        assert not msgs, (g, msgs)
 
 
 def test_apply_batches_same_graph_in_order():
@@ -87,8 +99,8 @@ def test_server_mix_equals_alone(budget):
     streams = _graphs(400)
     edges = [s.edges() for s in streams]
     batches = _stream_batches(streams, 5, rng)
-    served = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
-    alone = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
+    served = [_graph(s, e) for s, e in zip(streams, edges)]
+    alone = [_graph(s, e) for s, e in zip(streams, edges)]
     srv = ldl.Server(workers=4, mem_budget_bytes=budget)
     # arrival order: a random interleaving that keeps each graph's own order
     pending = [0] * len(streams)
@@ -110,3 +122,22 @@ def test_server_mix_equals_alone(budget):
             gr.apply_batch(b.ins, b.dels, b.chg)
     for g in range(len(streams)):
         assert not diff_states(served[g].state(), alone[g].state()), g
+    # served results against the oracle: an undirected and a directed graph
+    for g in (2, 3):
+        msgs = _oracle_matches(served[g], streams[g], edges[g], batches[g])
+        assert not msgs, (g, msgs)
+
+
+def test_server_second_wait_on_a_ticket_is_refused():
+    import paper_2502_18497_amd as ldl
+
+    s = synth.planted_small(seed_offset=330, n=400, blocks=4, p_in=0.1, p_out=0.01)
+    g = ldl.Graph(s.n, s.edges())
+    srv = ldl.Server(workers=2)
+    b = s.batch(20)
+    t = srv.submit(g, b.ins, b.dels, b.chg)
+    rc, _, _ = srv.wait(t)
+    assert rc == 0
+    with pytest.raises(ldl.LdlError):
+        srv.wait(t)
+    srv.close()

@@ -11,6 +11,8 @@ every result bit-identical to the oracle:
  32  no bulk load: creation inserts through the general lookup and row-update path
  64  one workgroup per candidate kernel of the degree bins: every workgroup and wavefront walks
      many vertices, through every stage of the kernels' software pipelines
+128  aggregation in chunks of 4,096 tuples, and every repair of more than 4,096 tuples done as a
+     rebuild of the level above from scratch (Eq. 3) instead of subtract-add tuples
 """
 import numpy as np
 import pytest
@@ -21,6 +23,7 @@ from tests.gpucases import run_parity
 pytestmark = pytest.mark.gpu
 
 ONE_ROUND, SMALL_HUB_POOL, TIGHT_CSR, SMALL_FILTER_FIRST, TINY_PARTITIONS, NO_BULK, ONE_GROUP = 1, 2, 4, 8, 16, 32, 64
+CHUNKED = 128
 
 
 def _batches(stream, sizes):
@@ -97,3 +100,27 @@ def test_one_workgroup_candidate_kernels(directed, bins):
                stats_out=stats, bins=bins)
     assert _bin_entries(stats, 2) > 0
     assert _bin_entries(stats, 3 if bins else 4) > 0
+
+
+@pytest.mark.parametrize("directed", [False, True])
+@pytest.mark.parametrize("extra", [0, TIGHT_CSR])
+def test_chunked_aggregation_and_rebuilds(directed, extra):
+    # materialisation in many chunks and aggregate levels rebuilt from scratch instead of repaired
+    # by tuples (through the row-update path, also with no spare row capacity): same state
+    if directed:
+        s = synth.rmat_directed_lognormal(1 << 12, 12 * (1 << 12), seed_offset=430)
+    else:
+        s = synth.rmat_undirected(scale=12, seed_offset=431)
+    stats = []
+    run_parity(s.n, s.edges(), _batches(s, [600, 40, 2000]), directed=directed, gpu_flags=CHUNKED | extra,
+               stats_out=stats)
+    assert sum(st["agg_rebuilds"] for st in stats) > 0, stats
+
+
+def test_rebuilds_under_default_thresholds():
+    # large batches on a small graph: repairs that would sort more tuples than the level has
+    # out-entries are done as rebuilds with the default thresholds too
+    s = synth.rmat_undirected(scale=12, seed_offset=432)
+    stats = []
+    run_parity(s.n, s.edges(), _batches(s, [8000, 8000]), stats_out=stats)
+    assert sum(st["agg_rebuilds"] for st in stats) > 0, [st["agg_tuples"] for st in stats]

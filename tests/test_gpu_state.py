@@ -1,0 +1,193 @@
+"""Checkpoint (state export / import), device partition copy and the device-side invariant
+recount, through the C ABI on the GPU.  A handle restored from a blob continues bit-exactly like
+the handle it was exported from and like the oracle; the recount passes on every valid state and
+flags each kind of planted corruption."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.statecheck import diff_states, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+HEADER_BYTES = 144
+
+
+def blob_layout(blob: bytes, L: int):
+    """Byte offsets of the sections of a state blob (the layout documented with
+    ldl_export_state)."""
+    hdr = np.frombuffer(blob[:HEADER_BYTES], dtype=np.uint8)
+    cfg = hdr[16:56].view(np.int32)
+    directed = bool(cfg[0])
+    n = int(hdr[56:60].view(np.uint32)[0])
+    top = int(hdr[60:64].view(np.int32)[0])
+    off = {"Kout": HEADER_BYTES}
+    p = HEADER_BYTES + 8 * n
+    if directed:
+        off["Kin"] = p
+        p += 8 * n
+    levels = []
+    for r in range(top + 1):
+        lv = {"alive": p}
+        p += n
+        lv["lab"] = p
+        p += 4 * n
+        if r < L:
+            lv["par"] = p
+            p += 4 * n
+            lv["rsize"] = p
+            p += 4 * n
+        lv["kout"] = p
+        p += 8 * n
+        if directed:
+            lv["kin"] = p
+            p += 8 * n
+        lv["deg"] = p
+        p += 4 * n
+        nnz = int(np.frombuffer(blob[p:p + 8], dtype=np.uint64)[0])
+        p += 8
+        lv["cols"] = p
+        p += 4 * nnz
+        lv["w"] = p
+        p += (4 if r == 0 else 8) * nnz
+        lv["nnz"] = nnz
+        levels.append(lv)
+    assert p == len(blob)
+    return n, top, off, levels
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_export_import_continues_bit_exact(directed):
+    import paper_2502_18497_amd as ldl
+
+    s = synth.Stream(3000, directed, synth.BASE_SEED + 600 + directed)
+    s.planted(100, 0.06, 0.002, 1, 8)
+    e = s.edges()
+    g = ldl.Graph(s.n, e, directed=directed)
+    og = oracle.Oracle(s.n, e, directed=directed)
+    for _ in range(2):
+        b = s.batch(150)
+        g.apply_batch(b.ins, b.dels, b.chg)
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+    blob = g.export_state()
+    assert blob == g.export_state()   # equal states, equal blobs
+    before = g.state()
+    g2 = ldl.Graph.from_state(blob)
+    assert not diff_states(g2.state(), before)
+    assert g2.export_state() == blob
+    g2_blob = g2.export_state()
+    g.close()   # the restored handle outlives the exported one
+    g3 = ldl.Graph.from_state(g2_blob)   # a second, uninterrupted reference from the same blob
+    for _ in range(3):
+        b = s.batch(150)
+        g2.apply_batch(b.ins, b.dels, b.chg)
+        g3.apply_batch(b.ins, b.dels, b.chg)
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+        msgs = diff_states(g2.state(), oracle_state(og))
+        assert not msgs, msgs
+        assert g2.qnum() == og.qnum()
+    assert g2.export_state() == g3.export_state()
+    assert g2.check_invariants()["failed"] == 0
+
+
+def test_import_rejects_bad_blobs():
+    import paper_2502_18497_amd as ldl
+
+    s = synth.planted_small(seed_offset=610, n=500, blocks=5, p_in=0.1, p_out=0.01)
+    g = ldl.Graph(s.n, s.edges())
+    blob = g.export_state()
+    n, top, off, levels = blob_layout(blob, 4)
+    bad = [blob[:-1], b"XXXXXXXX" + blob[8:]]
+    b2 = bytearray(blob)   # a neighbour id >= n
+    b2[levels[0]["cols"]:levels[0]["cols"] + 4] = np.array([n + 3], np.uint32).tobytes()
+    bad.append(bytes(b2))
+    b3 = bytearray(blob)   # a zero weight
+    b3[levels[0]["w"]:levels[0]["w"] + 4] = np.array([0], np.uint32).tobytes()
+    bad.append(bytes(b3))
+    for b in bad:
+        with pytest.raises(ldl.LdlError) as ei:
+            ldl.Graph.from_state(b)
+        assert ei.value.code == ldl.LDL_EINVAL
+
+
+def test_partition_device_equals_host_copy():
+    import torch
+
+    import paper_2502_18497_amd as ldl
+
+    s = synth.planted_small(seed_offset=620, n=2000)
+    g = ldl.Graph(s.n, s.edges())
+    t = torch.full((s.n,), -1, dtype=torch.int32, device="cuda")
+    g.partition_device(t)
+    assert np.array_equal(t.cpu().numpy().view(np.uint32), g.partition())
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_invariant_recount_passes_on_valid_states(directed):
+    import paper_2502_18497_amd as ldl
+
+    if directed:
+        s = synth.rmat_directed_lognormal(1 << 14, 16 << 14, seed_offset=630)
+    else:
+        s = synth.rmat_undirected(scale=14, seed_offset=631)
+    g = ldl.Graph(s.n, s.edges(), directed=directed)
+    rep = g.check_invariants()
+    assert rep["failed"] == 0 and rep["level"] == -1, rep
+    st = g.state()
+    assert rep["entries"] == sum(len(L["w"]) for L in st["levels"]) * (2 if directed else 1)
+    for _ in range(2):
+        b = s.batch(2000)
+        g.apply_batch(b.ins, b.dels, b.chg)
+        rep = g.check_invariants()
+        assert rep["failed"] == 0, rep
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_invariant_recount_flags_planted_corruption(directed):
+    """Corruptions planted in an exported blob and restored: each must be flagged by the check
+    that covers it (the import only checks the blob's layout)."""
+    import paper_2502_18497_amd as ldl
+
+    s = synth.Stream(2000, directed, synth.BASE_SEED + 640 + directed)
+    s.planted(100, 0.08, 0.003, 1, 8)
+    g = ldl.Graph(s.n, s.edges(), directed=directed)
+    blob = g.export_state()
+    assert g.check_invariants()["failed"] == 0
+    n, top, off, levels = blob_layout(blob, 4)
+    assert top >= 2
+    L0, L1 = levels[0], levels[1]
+    lab0 = np.frombuffer(blob[L0["lab"]:L0["lab"] + 4 * n], np.uint32)
+    par0 = np.frombuffer(blob[L0["par"]:L0["par"] + 4 * n], np.uint32)
+
+    def planted(edit):
+        b = bytearray(blob)
+        edit(b)
+        return ldl.Graph.from_state(bytes(b)).check_invariants()
+
+    def put(b, at, arr):
+        raw = arr.tobytes()
+        b[at:at + len(raw)] = raw
+
+    # a level-0 weight: degrees, totals and the aggregate above it
+    rep = planted(lambda b: put(b, L0["w"], np.array([7 + int(np.frombuffer(blob[L0["w"]:L0["w"] + 4],
+                                                                             np.uint32)[0])], np.uint32)))
+    assert rep["failed"] & 1 and rep["level"] == 0, rep
+    # a level-1 weight: that level's degrees and Eq. 3
+    w1 = int(np.frombuffer(blob[L1["w"]:L1["w"] + 8], np.int64)[0])
+    rep = planted(lambda b: put(b, L1["w"], np.array([w1 + 1], np.int64)))
+    assert rep["failed"] & 1 and rep["failed"] & 4, rep
+    # a community total
+    k0 = int(np.frombuffer(blob[off["Kout"]:off["Kout"] + 8], np.int64)[0])
+    rep = planted(lambda b: put(b, off["Kout"], np.array([k0 + 5], np.int64)))
+    assert rep["failed"] == 32 and rep["level"] == 0, rep
+    # a level-0 label moved to another community: totals and nesting
+    u = 5
+    other = int(lab0[(u + 1000) % n])
+    assert other != lab0[u]
+    rep = planted(lambda b: put(b, L0["lab"] + 4 * u, np.array([other], np.uint32)))
+    assert rep["failed"] & 32 and rep["failed"] & 8, rep
+    # a node given a parent that is not its refined community's root: aggregation
+    v = int(np.nonzero(par0 != np.arange(n))[0][0])
+    rep = planted(lambda b: put(b, L0["par"] + 4 * v, np.array([v], np.uint32)))
+    assert rep["failed"] & 4, rep
