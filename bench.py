@@ -352,7 +352,9 @@ def run_bigstream(args):
     st0 = g.apply_batch_device(e, None, None)
     torch.cuda.synchronize()
     log(f"static Leiden (L={args.big_L}, N={args.big_N}, M={args.big_M}) by bulk load in {time.perf_counter() - t0:.2f}s; "
-        f"device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
+        f"device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB; rebuilds {st0['agg_rebuilds']}")
+    level_nnz = [int(g.lib.ldl_level_nnz(g.h, r)) for r in range(g.scalars()["top"] + 1)]
+    log(f"stored entries per level (out-rows): {level_nnz}")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(synth.BASE_SEED + 11)
     E = e.shape[0]
@@ -406,6 +408,10 @@ def run_bigstream(args):
                       "M": args.big_M},
            "latency_ms": {"p50": float(1e3 * np.percentile(lat, 50)), "p99": float(1e3 * np.percentile(lat, 99))},
            "static_ms": float(st0["total_ms"]),
+           "level_entries_after_static": level_nnz,
+           "rebuilds_per_step": float(np.mean([x["agg_rebuilds"] for x in stats])),
+           "agg_tuples_per_step": float(np.mean([x["agg_tuples"] for x in stats])),
+           "device_free_gib_after": torch.cuda.mem_get_info()[0] / 2 ** 30,
            "candidate_search_ms_per_step": float(np.mean([x["search_ms"] for x in stats])),
            "scanned_entries_per_step": float(np.mean([x["scanned_entries"] for x in stats])),
            "move_iters_per_step": float(np.mean([x["move_iters"] for x in stats])),
@@ -567,6 +573,71 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_latency(args):
+    """Latency of small batches: the 2,000-vertex planted partition (20 blocks, p_in = 0.05,
+    p_out = 0.002, weights 1..8), static Leiden at creation, then 10 batches of 50 updates
+    (70/20/10), repeated from a fresh handle `--latency-runs` times with the same stream.  Every
+    ldl_apply_batch_device call is timed on the host around the call (the batch is already in
+    device memory); p50 / p99 over all timed batches, updates/s over their sum.  The first run
+    is a warm-up and is not timed.  The oracle runs the same stream once for the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    torch.cuda.set_device(0)
+    s = synth.planted_small()
+    e = s.edges()
+    batches = [s.batch(50) for _ in range(10)]
+    dev = [[torch.from_numpy(x.astype(np.int32)).cuda() if len(x) else None for x in (b.ins, b.dels, b.chg)]
+           for b in batches]
+    torch.cuda.synchronize()
+    lat, create_ms, qs = [], [], set()
+    for run in range(args.latency_runs + 1):
+        t0 = time.perf_counter()
+        g = ldl.Graph(s.n, e)
+        c_ms = 1e3 * (time.perf_counter() - t0)
+        per = []
+        for b in dev:
+            t = time.perf_counter()
+            g.apply_batch_device(*b)
+            per.append(1e3 * (time.perf_counter() - t))
+        qs.add(g.qnum())
+        g.close()
+        if run:   # run 0 warms the library and the device up
+            lat += per
+            create_ms.append(c_ms)
+    updates = sum(b.size for b in batches) * args.latency_runs
+    total_s = sum(lat) / 1e3
+    cpu_obj = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        o = oracle.Oracle(s.n, e)
+        t0 = time.perf_counter()
+        for b in batches:
+            assert o.apply_batch(b.ins, b.dels, b.chg) == 0
+        tc = time.perf_counter() - t0
+        cpu_obj = {"value": sum(b.size for b in batches) / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                   "sample": f"the same 10 batches of 50 updates after an untimed static Leiden; "
+                             f"single-threaded C++ oracle, {tc * 1e3:.1f} ms"}
+        assert o.qnum() in qs
+    out = {"metric": "p99 latency of small batch updates", "value": float(np.percentile(lat, 99)), "unit": "ms",
+           "n_gpus": 1, "steps": len(lat), "warmup": 10, "ms_per_step": float(np.mean(lat)),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "planted2000-batch50-latency", "n": s.n, "edges": int(len(e)), "blocks": 20,
+                      "p_in": 0.05, "p_out": 0.002, "weights": "uniform 1..8", "batch": 50, "batches_per_run": 10,
+                      "runs": args.latency_runs, "mix": "70/20/10 insert/delete/reweight"},
+           "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                          "max": float(np.max(lat))},
+           "edges_per_s": updates / total_s,
+           "create_ms": {"p50": float(np.percentile(create_ms, 50)), "max": float(np.max(create_ms))},
+           "identical_runs": len(qs) == 1,
+           "cpu_baseline": cpu_obj}
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of a known size (torch's copy kernel),
     repeated a few times; rocprofv3 FETCH_SIZE / WRITE_SIZE of these dispatches give the factor
@@ -596,7 +667,8 @@ def main():
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
-    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream"],
+    ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream",
+                                           "latency"],
                     default="rmat")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
@@ -617,6 +689,7 @@ def main():
     ap.add_argument("--vertices", type=int, default=0, help="scan: vertex count below 2^scale (ids >= it rejected)")
     ap.add_argument("--edges", type=int, default=0, help="scan: edge count (default avg-degree x vertices)")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--latency-runs", type=int, default=20)
     ap.add_argument("--graphs", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--mix-max-exp", type=float, default=5.0)
@@ -646,6 +719,8 @@ def main():
         return run_sweep(args)
     if args.workload == "bigstream":
         return run_bigstream(args)
+    if args.workload == "latency":
+        return run_latency(args)
 
     import numpy as np
     import torch
