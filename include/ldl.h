@@ -248,6 +248,18 @@ typedef struct ldl_invariant_report {
 } ldl_invariant_report;
 int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report);
 
+/*
+ * ldl_check_invariants for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same recount and the same
+ * report, with its sums in a 512-byte block of static device memory that each device holds for
+ * the life of the process (its address is looked up once per device when a handle is created on
+ * it).  It calls no allocating routine.  There is no size limit (the kernels loop over any n and
+ * any number of entries with a fixed grid).  Every call on one device shares that device's block
+ * and clears it first: calls that overlap on one device (different handles on different host
+ * threads or streams) race and may report wrong results.
+ */
+int ldl_check_invariants_noalloc(const ldl_handle* h, ldl_invariant_report* report);
+
 /* Per-iteration trace (8 int64 per record: pass, level, phase 0 move / 1 refine, iteration,
  * scanned vertices, candidates, accepted, low 64 bits of the exact batch gain). */
 int ldl_set_trace(ldl_handle* h, int32_t on);

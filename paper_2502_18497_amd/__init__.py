@@ -63,7 +63,7 @@ ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply
                "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
                "ldl_server_drain", "ldl_server_destroy", "ldl_get_bins", "ldl_set_bins", "ldl_autotune",
                "ldl_strerror", "ldl_version", "ldl_get_partition_device", "ldl_export_state", "ldl_import_state",
-               "ldl_check_invariants")
+               "ldl_check_invariants", "ldl_check_invariants_noalloc")
 
 INV_BITS = {1: "degrees", 2: "transpose", 4: "aggregate", 8: "labels", 16: "roots", 32: "totals", 64: "range"}
 
@@ -162,8 +162,9 @@ def load_library():
     lib.ldl_export_state.restype = i32
     lib.ldl_import_state.argtypes = [P(ldl_config), vp, u64, P(vp)]
     lib.ldl_import_state.restype = i32
-    lib.ldl_check_invariants.argtypes = [vp, P(ldl_invariant_report)]
-    lib.ldl_check_invariants.restype = i32
+    for name in ("ldl_check_invariants", "ldl_check_invariants_noalloc"):
+        getattr(lib, name).argtypes = [vp, P(ldl_invariant_report)]
+        getattr(lib, name).restype = i32
     _lib = lib
     return lib
 
@@ -242,12 +243,14 @@ class Graph:
             raise LdlError(rc, "ldl_export_state")
         return buf.raw
 
-    def check_invariants(self) -> dict:
-        """Device-side recount of the invariants (ldl_check_invariants)."""
+    def check_invariants(self, noalloc=False) -> dict:
+        """Device-side recount of the invariants (ldl_check_invariants, or its allocation-free
+        variant ldl_check_invariants_noalloc)."""
         rep = ldl_invariant_report()
-        rc = self.lib.ldl_check_invariants(self.h, ctypes.byref(rep))
+        name = "ldl_check_invariants_noalloc" if noalloc else "ldl_check_invariants"
+        rc = getattr(self.lib, name)(self.h, ctypes.byref(rep))
         if rc != LDL_OK:
-            raise LdlError(rc, "ldl_check_invariants")
+            raise LdlError(rc, name)
         return {"failed": rep.failed, "level": rep.level, "entries": rep.entries,
                 "names": [v for k, v in INV_BITS.items() if rep.failed & k]}
 

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -38,6 +39,7 @@ namespace ldl {
 
 typedef __int128 i128;
 
+
 struct DeviceError {
   hipError_t e;
 };
@@ -45,6 +47,30 @@ struct NoMem {};
 
 static void hcheck(hipError_t e) {
   if (e != hipSuccess) throw DeviceError{e};
+}
+
+// Recount sums of ldl_check_invariants_noalloc, for callers that cannot allocate device memory:
+// 512 bytes that every device the library runs on holds until the process ends.  Host code never
+// uses this name as an address: each device's copy is reached through the address that
+// hipGetSymbolAddress returned for it (noalloc_scratch below).
+constexpr int kNoAllocWords = 64;
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
+static_assert(sizeof(InvScratch) <= kNoAllocWords * sizeof(unsigned long long), "recount sums fit the scratch");
+
+// Device address of `scratch` on the current device, looked up once per device (with that
+// device current) and kept.
+static void* noalloc_scratch(int device) {
+  static std::mutex mu;
+  static void* addr[256] = {};
+  if (device < 0 || device >= 256) throw DeviceError{hipErrorInvalidDevice};
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) throw DeviceError{e == hipSuccess ? hipErrorUnknown : e};
+    addr[device] = p;
+  }
+  return addr[device];
 }
 
 template <typename T>
@@ -133,6 +159,7 @@ struct Engine {
   int test_flags = 0;   // see ldl_config
   hipStream_t st = nullptr;
   bool own_stream = false;
+  InvScratch* static_sums = nullptr;   // this device's copy of `scratch` (allocation-free recount)
   uint32_t n = 0;
   int id_bits = 32;     // bits of a vertex id: keys row << 32 | col need 2 * id_bits bits
   bool broken = false;
@@ -336,6 +363,7 @@ struct Engine {
     id_bits = 1;
     while (id_bits < 32 && (1ull << id_bits) < (uint64_t)n) ++id_bits;
     hcheck(hipSetDevice(device));
+    static_sums = (InvScratch*)noalloc_scratch(device);
     if (c.stream) {
       st = (hipStream_t)c.stream;
     } else {
@@ -2196,6 +2224,17 @@ int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report) {
       throw;
     }
     (void)hipFree(sc);
+    return LDL_OK;
+  });
+}
+
+int ldl_check_invariants_noalloc(const ldl_handle* h, ldl_invariant_report* report) {
+  if (!h || !report) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
+    ldl::Engine& e = *h->e;
+    ldl::hcheck(hipSetDevice(e.device));
+    e.check_invariants(e.static_sums, report);   // the device's static sums; no allocation
     return LDL_OK;
   });
 }
