@@ -64,6 +64,8 @@ def _load():
         lib.orc_eval_modularity.restype = i32
         lib.orc_eval_modularity.argtypes = [i32, i32, i32, u32, vp, u64, vp, vp, vp, vp]
         lib.orc_check_counts.argtypes = [vp, vp]
+        lib.orc_set_refresh.restype = u64
+        lib.orc_set_refresh.argtypes = [vp, i32, i32]
         lib.orc_decouple.restype = i32
         lib.orc_decouple.argtypes = [u64, vp, vp, vp, vp]
         _lib = lib
@@ -95,7 +97,7 @@ class Oracle:
     """Plain LD-Leiden state.  ``create`` runs static Leiden (the batch update applied to the
     empty singleton state)."""
 
-    def __init__(self, n, edges, directed=False, flags=0, **cfg):
+    def __init__(self, n, edges, directed=False, flags=0, refresh=(0, 1), **cfg):
         self.lib = _load()
         self.n = int(n)
         self.directed = bool(directed)
@@ -107,6 +109,11 @@ class Oracle:
         self.last_rc = rc
         if rc not in (0, -100):
             raise OracleError(rc)
+        self.lib.orc_set_refresh(self.h, int(refresh[0]), int(refresh[1]))
+
+    def refreshes(self) -> int:
+        """Batches so far that switched to full reoptimisation (adaptive refresh)."""
+        return int(self.lib.orc_set_refresh(self.h, -1, 0))
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -45,6 +45,7 @@ struct Cfg {
   int N, L, M;     // outer passes, top level index, move/refine iterations
   int an, ad;      // alpha = an / ad
   int bn, bd;      // beta = bn / bd
+  int rn = 0, rd = 1;   // adaptive refresh threshold rho = rn / rd (0: never)
 };
 
 typedef std::vector<std::pair<uint32_t, i64>> Row;  // sorted by column
@@ -140,6 +141,7 @@ struct Oracle {
   i128 SKK = 0;                   // sum_c Kout[c] * Kin[c]
   std::vector<NodeSet> D;         // pending seeds per level
   int pass_idx = 0;
+  uint64_t refreshes = 0;         // batches that switched to full reoptimisation
   // debugging / checking modes
   int single_move = 0;            // accept only the best candidate per move iteration
   int check_moves = 0;            // recount Q from scratch around every move and refinement commit
@@ -682,6 +684,21 @@ struct Oracle {
       }
       apply_reduced(s, reduce_tuples(agg), true);
     }
+    // ---- adaptive refresh (a variant, off unless rho > 0): when the level-0 frontier A^0
+    // (InitFrontier: alive seeds and every alive member of their communities) reaches rho n, the
+    // update no longer has locality (Sec. IV-F, Sec. V), so the batch reoptimises from scratch:
+    // the hierarchy and partition are discarded and static Leiden runs on the current graph.
+    if (cfg.rn > 0) {
+      const Level& L0 = lv[0];
+      std::vector<uint8_t> cm(n, 0);
+      for (uint32_t x : D[0].list) if (L0.alive[x]) cm[L0.lab[x]] = 1;
+      uint64_t a0 = 0;
+      for (uint32_t u = 0; u < n; ++u) if (L0.alive[u] && cm[L0.lab[u]]) ++a0;
+      if ((i128)cfg.rd * a0 >= (i128)cfg.rn * n) {
+        record(0, 2, 0, a0, 0, 0, 0);
+        refresh();
+      }
+    }
     // ---- l.4-28: outer passes over levels
     for (int i = 1; i <= cfg.N; ++i) {
       pass_idx = i;
@@ -699,6 +716,28 @@ struct Oracle {
     }
     for (int r = 0; r <= cfg.L; ++r) D[r].clear();
     return err.empty() ? OK : ECHECK_;
+  }
+
+  // Full reoptimisation of the current graph: the state static Leiden starts from (singleton
+  // labels and parents at level 0, no aggregate level, totals equal to the degrees), seeded with
+  // every vertex that has an entry -- the state ldl_create reaches before its passes.
+  void refresh() {
+    Level& L0 = lv[0];
+    for (uint32_t u = 0; u < n; ++u) { L0.lab[u] = u; L0.par[u] = u; }
+    for (int r = 1; r <= top; ++r) lv[r] = Level();
+    top = 0;
+    Ein = 0;
+    SKK = 0;
+    for (uint32_t u = 0; u < n; ++u) {
+      Kout[u] = L0.kout[u];
+      Kin[u] = L0.kin[u];
+      SKK += (i128)Kout[u] * Kin[u];
+      Ein += row_get(L0.out[u], u);
+    }
+    for (auto& d : D) d.clear();
+    for (uint32_t u = 0; u < n; ++u)
+      if (!L0.out[u].empty() || (cfg.directed && !L0.in[u].empty())) D[0].add(u);
+    refreshes++;
   }
 
   // ---------------------------------------------------------------- invariants (recount)
@@ -810,6 +849,14 @@ int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t
 }
 
 void orc_destroy(void* h) { delete (Oracle*)h; }
+
+// Adaptive refresh threshold rho = num / den for the following batches (num = 0: never);
+// returns the number of batches so far that switched to full reoptimisation.
+uint64_t orc_set_refresh(void* h, int32_t num, int32_t den) {
+  Oracle* o = (Oracle*)h;
+  if (num >= 0 && den >= 1) { o->cfg.rn = num; o->cfg.rd = den; }
+  return o->refreshes;
+}
 
 int orc_apply_batch(void* h, const uint32_t* ins, uint64_t n_ins, const uint32_t* del, uint64_t n_del,
                     const uint32_t* chg, uint64_t n_chg) {

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 import synth
-from tests.statecheck import check_state, oracle_state
+from tests.statecheck import check_state, diff_states, oracle_state
 
 
 def ring_of_cliques(r, s, wc=1, wr=1):
@@ -445,3 +445,55 @@ def test_planted_partition_recovery_sanity():
     truth = np.arange(s.n) // 100
     purity = sum(np.bincount(lab[truth == b]).max() for b in range(20)) / s.n
     assert purity == 1.0 and len(set(lab.tolist())) == 20
+
+
+def _current_edges(o, directed):
+    """The current edge list of an oracle's level-0 matrix (undirected: one entry per pair)."""
+    L0 = o.level(0)
+    r, c, w = L0["rows"], L0["cols"], L0["w"]
+    keep = np.ones(len(r), bool) if directed else r <= c
+    return np.stack([r[keep], c[keep], w[keep]], axis=1).astype(np.uint32)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_adaptive_refresh_equals_static_rerun(directed):
+    """Adaptive refresh (Sec. IV-F, Sec. V: switch to full reoptimisation when locality no longer
+    holds): a batch whose level-0 frontier reaches rho n leaves exactly the state of static Leiden
+    run from scratch on the current graph -- here the state of a second oracle created on the
+    current edge list (creation runs static Leiden as a batch on the empty singleton state, a
+    different path).  Below the threshold, or with rho = 0, the update stays local."""
+    s = synth.Stream(800, directed, synth.BASE_SEED + 720 + directed)
+    s.planted(40, 0.12, 0.006, 1, 8)
+    o = oracle.Oracle(800, s.edges(), directed=directed, refresh=(1, 2), flags=oracle.FLAG_TRACE)
+    plain = oracle.Oracle(800, s.edges(), directed=directed)
+    big, small = s.batch(300), s.batch(5)
+    o.trace_clear()
+    assert o.apply_batch(big.ins, big.dels, big.chg) == 0
+    assert plain.apply_batch(big.ins, big.dels, big.chg) == 0
+    assert o.refreshes() == 1
+    tr = o.trace()
+    assert tr[0][2] == 2 and 2 * tr[0][4] >= 800          # the refresh record: |A^0| >= n / 2
+    fresh = oracle.Oracle(800, _current_edges(o, directed), directed=directed)
+    assert not diff_states(oracle_state(o), oracle_state(fresh))
+    assert diff_states(oracle_state(o), oracle_state(plain))   # the local update differs
+    assert o.check() == ""
+    # a small batch under rho = 99/100 stays local
+    o.lib.orc_set_refresh(o.h, 99, 100)
+    o.trace_clear()
+    assert o.apply_batch(small.ins, small.dels, small.chg) == 0
+    assert o.refreshes() == 1 and all(r[2] != 2 for r in o.trace())
+    assert o.check() == ""
+
+
+def test_adaptive_refresh_threshold_is_exact():
+    s = synth.planted_small(seed_offset=730, n=400, blocks=4, p_in=0.1, p_out=0.01)
+    o0 = oracle.Oracle(400, s.edges(), refresh=(1, 1), flags=oracle.FLAG_TRACE)   # rho = 1: all of n
+    o0.trace_clear()
+    b = s.batch(3)
+    o0.apply_batch(b.ins, b.dels, b.chg)
+    a0 = None
+    for r in o0.trace():
+        if r[2] == 2:
+            a0 = r[4]
+    # rho = 1 refreshes only when the closure is all 400 vertices
+    assert (a0 == 400) == (o0.refreshes() == 1)
