@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Batch-update throughput of the gfx950 LD-Leiden library on one GPU.
 
-Workload: undirected R-MAT, scale 20 (1,048,576 vertices, 8,388,608 unique edges,
-a/b/c/d = 0.57/0.19/0.19/0.05, weights uniform 1..16, gamma = 1), static Leiden at creation
-(untimed set-up), then a stream of update batches of 10^4 updates (70% inserts of random
-non-edges, 20% deletions, 10% reweights).  One step = one ldl_apply_batch_device call (the
-whole batch update of Algorithm 1) on a batch already resident in HBM.  A second timed phase
-runs batches of 10^3 updates for the batch-size comparison.
+Default line (no --workload): the full method (Algorithm 1 with L = 4, N = 2, M = 5) on a
+directed weighted R-MAT graph shaped like the paper's largest streams (a/b/c/d =
+0.57/0.19/0.19/0.05, average out-degree 15.42, lognormal(1, 1) integer weights, gamma = 1) at the
+largest size whose hierarchy fits one GPU's HBM (2^25 vertices, 517,409,341 edges), static Leiden
+at creation (untimed set-up), then batches of 10^5 updates (70% inserts of random pairs, 20%
+deletions, 10% weight changes).  One step = one ldl_apply_batch_device call (the whole batch
+update) on a batch already resident in HBM; value = updates / wall time of the timed steps.
+Sub-objects: the 214,000,000-vertex, 3,300,000,000-edge graph itself with L = 0 (its full-frontier
+scan and batches of 10^5), the undirected R-MAT scale-20 stream (batches of 10^4 and 10^3), and
+the small-batch latency workload (2,000-vertex planted partition, batches of 50).
 
-The JSON line carries the roofline of the dominant local-move kernel (HIP events around each
-of its launches during the timed steps, algorithmic bytes counted by the kernels) and the CPU
-oracle's throughput on a bounded sample of the same stream.
+The JSON line carries the roofline of the dominant local-move kernel (HIP events around each of
+its launches during the timed steps, algorithmic bytes counted by the kernels) and the CPU
+oracle's throughput on a bounded sample of the same workload shape.  --workload selects one of
+the other measurements instead (each prints its own line).
 """
 from __future__ import annotations
 
@@ -326,12 +331,13 @@ def run_scan(args):
     print(json.dumps(out), flush=True)
 
 
-def run_bigstream(args):
-    """Batch updates on a large directed R-MAT graph (the scan workload's generator and sizes): static
-    Leiden at creation through the bulk load, then batches of updates generated on the device -- 70 %
-    insertions of uniform random pairs, 20 % deletions and 10 % weight changes (w -> w + 1) of
-    distinct original edges never touched before -- each applied with ldl_apply_batch_device.
-    Reports updates/s over the timed batches, per-batch latency and the candidate-search figures."""
+def directed_stream(scale, n_req, n_edges, L, N, M, batch, steps, warmup, label):
+    """Batch updates on a large directed R-MAT graph with lognormal weights (the generator and
+    sizes of the scan workload): static Leiden at creation through the bulk load, then batches of
+    updates generated on the device -- 70 % insertions of uniform random pairs, 20 % deletions and
+    10 % weight changes (w -> w + 1) of distinct original edges never touched before -- each
+    applied with ldl_apply_batch_device on a batch already in device memory.  Returns the figures
+    of the timed batches (with HIP-event timings of the candidate kernels) and of the static run."""
     import numpy as np
     import torch
 
@@ -339,28 +345,28 @@ def run_bigstream(args):
     import synth
 
     torch.cuda.set_device(0)
-    n_req = args.vertices or (1 << args.scale)
-    n_edges = args.edges or args.avg_degree * n_req
     t0 = time.perf_counter()
-    n, e = rmat_directed_device(args.scale, n_edges, synth.BASE_SEED + 3, "cuda", n=n_req)
+    n, e = rmat_directed_device(scale, n_edges, synth.BASE_SEED + 3, "cuda", n=n_req)
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    log(f"generated directed R-MAT: n={n} edges={e.shape[0]} in {time.perf_counter() - t0:.1f}s")
-    g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=True, L=args.big_L, N=args.big_N, M=args.big_M,
-                  profile=True)
+    gen_s = time.perf_counter() - t0
+    log(f"[{label}] generated directed R-MAT: n={n} edges={e.shape[0]} in {gen_s:.1f}s")
+    g = ldl.Graph(n, np.zeros((0, 3), np.uint32), directed=True, L=L, N=N, M=M, profile=True)
     t0 = time.perf_counter()
     st0 = g.apply_batch_device(e, None, None)
     torch.cuda.synchronize()
-    log(f"static Leiden (L={args.big_L}, N={args.big_N}, M={args.big_M}) by bulk load in {time.perf_counter() - t0:.2f}s; "
-        f"device memory free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB; rebuilds {st0['agg_rebuilds']}")
-    level_nnz = [int(g.lib.ldl_level_nnz(g.h, r)) for r in range(g.scalars()["top"] + 1)]
-    log(f"stored entries per level (out-rows): {level_nnz}")
+    static_s = time.perf_counter() - t0
+    free_gib = torch.cuda.mem_get_info()[0] / 2 ** 30
+    top = g.scalars()["top"]
+    level_nnz = [int(g.lib.ldl_level_nnz(g.h, r)) for r in range(top + 1)]
+    log(f"[{label}] static Leiden (L={L}, N={N}, M={M}) by bulk load in {static_s:.2f}s; device memory free "
+        f"{free_gib:.1f} GiB; rebuilds {st0['agg_rebuilds']}; stored out-entries per level {level_nnz}")
     gen = torch.Generator(device="cuda")
     gen.manual_seed(synth.BASE_SEED + 11)
     E = e.shape[0]
     used = torch.zeros(E, dtype=torch.bool, device="cuda")
 
-    def batch(size):
+    def make_batch(size):
         nd, nc = size // 5, size // 10
         ni = size - nd - nc
         idx = torch.empty(0, dtype=torch.int64, device="cuda")
@@ -385,37 +391,94 @@ def run_bigstream(args):
         w = torch.randint(1, 17, (ni, 1), generator=gen, device="cuda")
         return torch.cat([ins, w], dim=1).int().contiguous(), dels, chg
 
-    batches = [batch(args.batch) for _ in range(args.warmup + args.steps)]
+    batches = [make_batch(batch) for _ in range(warmup + steps)]
     torch.cuda.synchronize()
-    for b in batches[: args.warmup]:
+    for b in batches[:warmup]:
         g.apply_batch_device(*b)
     torch.cuda.synchronize()
     lat, stats = [], []
     t0 = time.perf_counter()
-    for b in batches[args.warmup:]:
+    for b in batches[warmup:]:
         t1 = time.perf_counter()
         stats.append(g.apply_batch_device(*b))
         lat.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    upd = args.batch * args.steps
-    log(f"timed {args.steps} batches of {args.batch}: {T:.2f}s")
-    out = {"metric": "batch edges/s (large directed graph)", "value": upd / T, "unit": "edges/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * T / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-           "config": {"workload": f"rmat{args.scale}-directed-lognormal-batch{args.batch}", "n": n, "edges": int(E),
-                      "batch": args.batch, "mix": "70/20/10 insert/delete/reweight", "L": args.big_L, "N": args.big_N,
-                      "M": args.big_M},
-           "latency_ms": {"p50": float(1e3 * np.percentile(lat, 50)), "p99": float(1e3 * np.percentile(lat, 99))},
-           "static_ms": float(st0["total_ms"]),
-           "level_entries_after_static": level_nnz,
-           "rebuilds_per_step": float(np.mean([x["agg_rebuilds"] for x in stats])),
-           "agg_tuples_per_step": float(np.mean([x["agg_tuples"] for x in stats])),
-           "device_free_gib_after": torch.cuda.mem_get_info()[0] / 2 ** 30,
-           "candidate_search_ms_per_step": float(np.mean([x["search_ms"] for x in stats])),
-           "scanned_entries_per_step": float(np.mean([x["scanned_entries"] for x in stats])),
-           "move_iters_per_step": float(np.mean([x["move_iters"] for x in stats])),
-           "host_syncs_per_step": float(np.mean([x["host_syncs"] for x in stats]))}
+    log(f"[{label}] timed {steps} batches of {batch}: {T:.2f}s")
+    rep = g.check_invariants()
+    free_after = torch.cuda.mem_get_info()[0] / 2 ** 30
+    g.close()
+    del e, used, batches
+    torch.cuda.empty_cache()
+    return {"n": n, "edges": int(E), "L": L, "N": N, "M": M, "batch": batch, "steps": steps, "warmup": warmup,
+            "T": T, "lat": lat, "stats": stats, "static": st0, "gen_s": gen_s, "static_s": static_s,
+            "level_entries_after_static": level_nnz, "device_free_gib_after_static": free_gib,
+            "device_free_gib_after_batches": free_after, "invariants_after": rep}
+
+
+def kernel_roofline(stats_list, directed):
+    """Roofline of the candidate kernel with the most time over the given per-call statistics:
+    algorithmic bytes counted by the kernels over their HIP-event times (profile on)."""
+    import numpy as np
+
+    import paper_2502_18497_amd as ldl
+
+    ms = np.sum([st["bin_ms"] for st in stats_list], axis=0)
+    by = np.sum([st["bin_bytes"] for st in stats_list], axis=0)
+    la = np.sum([st["bin_launches"] for st in stats_list], axis=0)
+    dom = int(np.argmax(ms))
+    achieved = float(by[dom] / (ms[dom] * 1e-3) / 1e9) if ms[dom] > 0 else 0.0
+    name = ldl.candidate_kernel_name(dom, directed)
+    avg_us = float(1e3 * ms[dom] / max(1, la[dom]))
+    traffic, traffic_bytes = measured_traffic(name, avg_us)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
+            "kernel": name, "launches": int(la[dom]), "avg_launch_us": avg_us,
+            "bytes_per_launch": float(by[dom] / max(1, la[dom]))}
+
+
+def stream_summary(r):
+    import numpy as np
+
+    stats = r["stats"]
+    upd = r["batch"] * r["steps"]
+    st0 = r["static"]
+    return {"n": r["n"], "edges": r["edges"], "L": r["L"], "N": r["N"], "M": r["M"], "batch": r["batch"],
+            "edges_per_s": upd / r["T"], "ms_per_step": 1e3 * r["T"] / r["steps"],
+            "latency_ms": {"p50": float(1e3 * np.percentile(r["lat"], 50)),
+                           "p99": float(1e3 * np.percentile(r["lat"], 99))},
+            "static_s": r["static_s"], "generate_s": r["gen_s"],
+            "level_entries_after_static": r["level_entries_after_static"],
+            "device_free_gib_after_static": r["device_free_gib_after_static"],
+            "candidate_search_ms_per_step": float(np.mean([x["search_ms"] for x in stats])),
+            "scanned_entries_per_step": float(np.mean([x["scanned_entries"] for x in stats])),
+            "frontier_entries_per_s": float(sum(x["scanned_entries"] for x in stats) / r["T"]),
+            "agg_tuples_per_step": float(np.mean([x["agg_tuples"] for x in stats])),
+            "rebuilds_per_step": float(np.mean([x["agg_rebuilds"] for x in stats])),
+            "move_iters_per_step": float(np.mean([x["move_iters"] for x in stats])),
+            "host_syncs_per_step": float(np.mean([x["host_syncs"] for x in stats])),
+            "static_full_frontier_scan": {
+                "scanned_entries": int(st0["scanned_entries"]), "search_ms": float(st0["search_ms"]),
+                "GBps_algorithmic": float(st0["bm_bytes"] / (st0["search_ms"] * 1e-3) / 1e9)
+                if st0["search_ms"] > 0 else 0.0},
+            "invariants_after": r["invariants_after"]}
+
+
+def run_bigstream(args):
+    """One directed large-graph stream (see directed_stream) as its own JSON line."""
+    n_req = args.vertices or (1 << args.scale)
+    n_edges = args.edges or args.avg_degree * n_req
+    r = directed_stream(args.scale, n_req, n_edges, args.big_L, args.big_N, args.big_M, args.batch, args.steps,
+                        args.warmup, "bigstream")
+    summ = stream_summary(r)
+    out = {"metric": "batch edges/s (large directed graph)", "value": summ["edges_per_s"], "unit": "edges/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": summ["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"rmat{args.scale}-directed-lognormal-batch{args.batch}", "n": r["n"],
+                      "edges": r["edges"], "batch": args.batch, "mix": "70/20/10 insert/delete/reweight",
+                      "L": args.big_L, "N": args.big_N, "M": args.big_M},
+           "roofline": kernel_roofline(r["stats"], True)}
+    out.update({k: v for k, v in summ.items() if k not in out})
     print(json.dumps(out), flush=True)
 
 
@@ -574,6 +637,10 @@ def run_sweep(args):
 
 
 def run_latency(args):
+    print(json.dumps(measure_latency(args)), flush=True)
+
+
+def measure_latency(args):
     """Latency of small batches: the 2,000-vertex planted partition (20 blocks, p_in = 0.05,
     p_out = 0.002, weights 1..8), static Leiden at creation, then 10 batches of 50 updates
     (70/20/10), repeated from a fresh handle `--latency-runs` times with the same stream.  Every
@@ -635,7 +702,7 @@ def run_latency(args):
            "create_ms": {"p50": float(np.percentile(create_ms, 50)), "max": float(np.max(create_ms))},
            "identical_runs": len(qs) == 1,
            "cpu_baseline": cpu_obj}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_copy(args):
@@ -658,8 +725,13 @@ def run_copy(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--head-scale", type=int, default=25, help="headline: R-MAT scale of the full-method graph")
+    ap.add_argument("--big-batch", type=int, default=100000, help="headline: updates per batch")
+    ap.add_argument("--skip-paper-scale", action="store_true", help="headline: leave the 3.3B-edge graph out")
+    ap.add_argument("--cpu-scale", type=int, default=19, help="headline: scale of the oracle's sample graph")
+    ap.add_argument("--cpu-batch", type=int, default=5000, help="headline: updates in the oracle's sample batch")
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--batch", type=int, default=10000)
     ap.add_argument("--small-batch", type=int, default=1000)
@@ -668,8 +740,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
     ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream",
-                                           "latency"],
-                    default="rmat")
+                                           "latency", "headline"],
+                    default="headline")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
     ap.add_argument("--quality-batch", type=int, default=500)
@@ -722,6 +794,97 @@ def main():
     if args.workload == "latency":
         return run_latency(args)
 
+    if args.workload == "rmat":
+        print(json.dumps(measure_rmat(args)), flush=True)
+        return
+    return run_headline(args)
+
+
+CFG3_OUT_DEGREE = 15.42   # 3.3e9 edges / 2.14e8 vertices: the paper-scale directed stream's average out-degree
+
+
+def cpu_baseline_directed(scale, batch):
+    """The oracle on a bounded sample of the headline workload's shape: a directed R-MAT of
+    2^scale vertices with the same average out-degree and lognormal(1, 1) weights (the host
+    generator), the full method (L = 4, N = 2, M = 5), static Leiden untimed, then one batch of
+    `batch` updates (70/20/10) timed, single-threaded."""
+    import oracle
+    import synth
+
+    n = 1 << scale
+    s = synth.rmat_directed_lognormal(n, round(CFG3_OUT_DEGREE * n), seed_offset=3)
+    e = s.edges()
+    t0 = time.perf_counter()
+    o = oracle.Oracle(n, e, directed=True)
+    create_s = time.perf_counter() - t0
+    b = s.batch(batch)
+    t0 = time.perf_counter()
+    assert o.apply_batch(b.ins, b.dels, b.chg) == 0
+    tc = time.perf_counter() - t0
+    return {"value": b.size / tc, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"directed lognormal R-MAT with 2^{scale} vertices and {len(e)} edges (average out-degree "
+                      f"{CFG3_OUT_DEGREE}), L = 4, N = 2, M = 5: one batch of {b.size} updates (70/20/10) after an "
+                      f"untimed static Leiden ({create_s:.1f}s); single-threaded C++ oracle, {tc:.1f}s"}
+
+
+def run_headline(args):
+    """The default line.  value: batch edges/s of the full method (L = 4, N = 2, M = 5) on the
+    largest directed lognormal R-MAT of the paper-scale stream's shape (average out-degree 15.42)
+    whose hierarchy fits one GPU's HBM (2^25 vertices, 517M edges; the 214M-vertex, 3.3B-edge
+    graph needs more than 288 GB with its aggregate levels), batches of 10^5 updates.
+    Sub-objects: that paper-scale graph itself with L = 0 (static local moving, its full-frontier
+    scan and batches of 10^5), the undirected R-MAT scale-20 stream (batches of 10^4 and 10^3)
+    and the small-batch latency workload."""
+    import copy
+
+    import numpy as np
+
+    scale = args.head_scale
+    n = 1 << scale
+    a = directed_stream(scale, n, round(CFG3_OUT_DEGREE * n), 4, 2, 5, args.big_batch, args.steps, args.warmup,
+                        "full method")
+    summ = stream_summary(a)
+    roof = kernel_roofline(a["stats"], True)
+    upd = a["batch"] * a["steps"]
+    out = {"metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
+           "value": upd / a["T"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * a["T"] / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"rmat{scale}-directed-lognormal-L4-batch{args.big_batch}", "n": a["n"],
+                      "edges": a["edges"], "avg_out_degree": CFG3_OUT_DEGREE, "rmat": [0.57, 0.19, 0.19, 0.05],
+                      "weights": "lognormal(1,1) >= 1", "batch": args.big_batch,
+                      "mix": "70/20/10 insert/delete/reweight", "gamma": 1, "N": 2, "L": 4, "M": 5,
+                      "alpha": 0.001, "beta": 0.01},
+           "roofline": roof,
+           "cpu_baseline": None,
+           "latency_ms": summ["latency_ms"]}
+    out["full_method"] = summ
+    if not args.skip_paper_scale:
+        b = directed_stream(28, 214_000_000, 3_300_000_000, 0, 2, 5, args.big_batch, 3, 1, "paper scale, L = 0")
+        sb = stream_summary(b)
+        sb["roofline_static_scan"] = kernel_roofline([b["static"]], True)
+        sb["why_L0"] = ("with its aggregate levels (L = 4) this graph needs more device memory than one GPU has: "
+                        "the levels above 0 keep most of level 0's entries on these graphs")
+        out["paper_scale_graph"] = sb
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.scale, sub.batch = 10, 2, 20, 10000
+    sub.small_steps, sub.no_cpu_baseline = 10, True
+    r = measure_rmat(sub)
+    out["rmat20_undirected"] = {k: r[k] for k in ("value", "unit", "ms_per_step", "latency_ms", "roofline",
+                                                  "small_batch", "candidate_search_ms_per_step", "config")}
+    lat_args = copy.copy(args)
+    lat_args.no_cpu_baseline = True
+    lt = measure_latency(lat_args)
+    out["planted2000_latency"] = {k: lt[k] for k in ("latency_ms", "edges_per_s", "config", "identical_runs")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_directed(args.cpu_scale, args.cpu_batch)
+    print(json.dumps(out), flush=True)
+
+
+def measure_rmat(args):
+    """The undirected R-MAT stream: static Leiden at creation (untimed set-up), then batches of
+    `--batch` updates (timed, with the roofline of the dominant candidate kernel) and of
+    `--small-batch` updates, and the oracle on one batch of the same stream."""
     import numpy as np
     import torch
 
@@ -863,7 +1026,7 @@ def main():
         "create_s": create_s,
         "modularity": g.modularity(),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

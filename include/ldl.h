@@ -71,6 +71,15 @@ typedef struct ldl_pair {
  *   device              HIP device ordinal
  *   stream              hipStream_t to run on, or NULL for the handle's own stream
  *   profile             nonzero: time the local-move kernels with HIP events (see stats)
+ *   refresh_num/den     adaptive refresh threshold rho (a variant, off by default: 0/1).  When a
+ *                       batch's level-0 frontier (InitFrontier: its alive seeds and every alive
+ *                       member of their communities) holds at least rho n vertices, locality no
+ *                       longer holds (Sec. IV-F, Sec. V) and the batch reoptimises from scratch:
+ *                       hierarchy and partition are discarded and static Leiden runs on the
+ *                       current graph (the state ldl_create would reach for the current edges).
+ *                       num in [0, 65535], den in [1, 65535]
+ *   alloc/free/alloc_ctx device allocator hook (see ldl_alloc_fn); NULL for hipMalloc / hipFree.
+ *                       One of the two set without the other is LDL_EINVAL.
  *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
  *                       results unchanged: 1 = one decoupling round between host checks (second
  *                       commit phase), 2 = minimal hub bucket pool (overflow and redo of an
@@ -86,6 +95,13 @@ typedef struct ldl_pair {
  *                       128 = aggregation tuples sorted in chunks of 4,096, and every repair of
  *                       more than 4,096 tuples done as a rebuild of the level above from scratch
  */
+/* Device-memory allocator hook (for example a caching allocator such as PyTorch's): alloc returns
+ * `bytes` of device memory on `device` for use on `stream` (the handle's stream), or NULL when it
+ * cannot; free releases a pointer alloc returned, with the same size, device and stream.  ctx is
+ * passed through.  Both are called only from the thread that calls into the handle. */
+typedef void* (*ldl_alloc_fn)(void* ctx, uint64_t bytes, int32_t device, void* stream);
+typedef void (*ldl_free_fn)(void* ctx, void* ptr, uint64_t bytes, int32_t device, void* stream);
+
 typedef struct ldl_config {
   int32_t directed;
   int32_t gamma_num, gamma_den;
@@ -96,6 +112,10 @@ typedef struct ldl_config {
   void* stream;
   int32_t profile;
   int32_t test_flags;
+  int32_t refresh_num, refresh_den;
+  ldl_alloc_fn alloc;   /* both set: every device allocation of the handle goes through them; */
+  ldl_free_fn free;     /* both NULL: hipMalloc / hipFree                                      */
+  void* alloc_ctx;
 } ldl_config;
 
 /* Per-call statistics (all counts summed over the call). */
@@ -135,6 +155,9 @@ typedef struct ldl_batch_stats {
                                  (nonzero once a gain reaches 2^64)                          */
   uint64_t agg_rebuilds;      /* aggregate levels rebuilt from scratch by Eq. 3 instead of
                                  repaired by subtract-add tuples (same matrix, lower cost)    */
+  uint64_t refreshes;         /* 1 when the batch switched to full reoptimisation (refresh)   */
+  uint64_t frontier0;         /* level-0 frontier size checked against the refresh threshold
+                                 (0 when refresh is off)                                      */
 } ldl_batch_stats;
 
 /* Fill *cfg with the defaults listed above (undirected, device 0, own stream). */
@@ -260,6 +283,12 @@ int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report);
  */
 int ldl_check_invariants_noalloc(const ldl_handle* h, ldl_invariant_report* report);
 
+/* Device memory of the handle: *held_bytes it holds now (state and the scratch it keeps between
+ * calls), *recent_growth_bytes the largest amount one of its last 8 batch calls allocated beyond
+ * what it held when the call began (creation not counted).  Read by the serving loop's
+ * admission; a handle must not be in use by another thread during the call. */
+int ldl_memory(const ldl_handle* h, uint64_t* held_bytes, uint64_t* recent_growth_bytes);
+
 /* Per-iteration trace (8 int64 per record: pass, level, phase 0 move / 1 refine, iteration,
  * scanned vertices, candidates, accepted, low 64 bits of the exact batch gain). */
 int ldl_set_trace(ldl_handle* h, int32_t on);
@@ -293,7 +322,9 @@ int ldl_apply_batches(ldl_handle* const* hs, const ldl_batch* bs, uint32_t count
  * run in submission order, back to back on the worker that holds the handle; requests of
  * different handles overlap on the device.  A request is admitted only while the estimated
  * device-memory footprint of all running requests stays within `mem_budget_bytes` (a request
- * larger than the budget runs alone).  ldl_server_wait blocks until the ticket completes and
+ * larger than the budget runs alone); a request's footprint is the larger of a linear estimate in
+ * its update count (1 MiB + 256 B per update) and the most its handle's recent batch calls have
+ * allocated (ldl_memory), taken when it is admitted.  ldl_server_wait blocks until the ticket completes and
  * returns its code, statistics and latency (submission to completion, milliseconds); a ticket can
  * be waited on once (a second or concurrent wait on it returns LDL_EINVAL).  A handle
  * must not be used outside the server while it has queued requests.

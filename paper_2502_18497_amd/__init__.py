@@ -31,7 +31,49 @@ class ldl_config(ctypes.Structure):
                 ("N", ctypes.c_int32), ("L", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("alpha_num", ctypes.c_int32), ("alpha_den", ctypes.c_int32), ("beta_num", ctypes.c_int32),
                 ("beta_den", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32), ("refresh_num", ctypes.c_int32),
+                ("refresh_den", ctypes.c_int32), ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p),
+                ("alloc_ctx", ctypes.c_void_p)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Allocator hook (ldl_config.alloc/free) that takes the handle's device memory from PyTorch's
+    caching allocator, on the handle's stream.  Keeps the live blocks and call counts."""
+
+    def __init__(self):
+        import torch
+
+        self._torch = torch
+        self.live = {}
+        self.allocs = 0
+        self.frees = 0
+        self.peak = 0
+        self._alloc = ALLOC_FN(self._on_alloc)
+        self._free = FREE_FN(self._on_free)
+
+    def _on_alloc(self, ctx, nbytes, device, stream):
+        try:
+            p = self._torch.cuda.caching_allocator_alloc(int(nbytes), int(device), int(stream or 0))
+        except Exception:
+            return None
+        self.live[int(p)] = int(nbytes)
+        self.allocs += 1
+        self.peak = max(self.peak, sum(self.live.values()))
+        return int(p)
+
+    def _on_free(self, ctx, ptr, nbytes, device, stream):
+        self.live.pop(int(ptr), None)
+        self.frees += 1
+        self._torch.cuda.caching_allocator_delete(int(ptr))
+
+    def install(self, cfg):
+        cfg.alloc = ctypes.cast(self._alloc, ctypes.c_void_p)
+        cfg.free = ctypes.cast(self._free, ctypes.c_void_p)
+        cfg.alloc_ctx = None
 
 
 NUM_BINS = 6                 # degree bins of the candidate kernels
@@ -46,7 +88,8 @@ class ldl_batch_stats(ctypes.Structure):
         [("bin_launches", ctypes.c_uint64 * NUM_CATS), ("bin_ms", ctypes.c_double * NUM_CATS),
          ("bin_bytes", ctypes.c_double * NUM_CATS), ("bin_entries", ctypes.c_uint64 * NUM_CATS)] + \
         [(k, ctypes.c_uint64) for k in ("lf_rounds", "host_syncs", "agg_records")] + \
-        [("search_ms", ctypes.c_double), ("max_gain_hi", ctypes.c_uint64), ("agg_rebuilds", ctypes.c_uint64)]
+        [("search_ms", ctypes.c_double)] + \
+        [(k, ctypes.c_uint64) for k in ("max_gain_hi", "agg_rebuilds", "refreshes", "frontier0")]
 
     def as_dict(self) -> dict:
         d = {}
@@ -63,7 +106,7 @@ ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply
                "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
                "ldl_server_drain", "ldl_server_destroy", "ldl_get_bins", "ldl_set_bins", "ldl_autotune",
                "ldl_strerror", "ldl_version", "ldl_get_partition_device", "ldl_export_state", "ldl_import_state",
-               "ldl_check_invariants", "ldl_check_invariants_noalloc")
+               "ldl_check_invariants", "ldl_check_invariants_noalloc", "ldl_memory")
 
 INV_BITS = {1: "degrees", 2: "transpose", 4: "aggregate", 8: "labels", 16: "roots", 32: "totals", 64: "range"}
 
@@ -158,6 +201,8 @@ def load_library():
     lib.ldl_server_destroy.restype = None
     lib.ldl_get_partition_device.argtypes = [vp, vp, u64]
     lib.ldl_get_partition_device.restype = i32
+    lib.ldl_memory.argtypes = [vp, P(u64), P(u64)]
+    lib.ldl_memory.restype = i32
     lib.ldl_export_state.argtypes = [vp, vp, u64, P(u64)]
     lib.ldl_export_state.restype = i32
     lib.ldl_import_state.argtypes = [P(ldl_config), vp, u64, P(vp)]
@@ -190,7 +235,7 @@ class Graph:
     edges; ``apply_batch`` runs one batch update (Algorithm 1)."""
 
     def __init__(self, n, edges, directed=False, gamma=(1, 1), N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100),
-                 device=0, stream=None, profile=False, test_flags=0):
+                 device=0, stream=None, profile=False, test_flags=0, refresh=(0, 1), allocator=None):
         self.lib = load_library()
         c = ldl_default_config()
         c.directed, c.gamma_num, c.gamma_den = int(directed), gamma[0], gamma[1]
@@ -200,6 +245,10 @@ class Graph:
         c.stream = stream
         c.profile = int(bool(profile))
         c.test_flags = int(test_flags)
+        c.refresh_num, c.refresh_den = int(refresh[0]), int(refresh[1])
+        self.allocator = allocator   # kept alive as long as the handle (its callbacks are called)
+        if allocator is not None:
+            allocator.install(c)
         self.n = int(n)
         self.directed = bool(directed)
         self.L = L
@@ -225,11 +274,19 @@ class Graph:
         g.lib = lib
         g.h = h.value
         hdr = np.frombuffer(bytes(blob[:80]), dtype=np.uint8)
-        cfg = hdr[16:56].view(np.int32)
-        g.n = int(hdr[56:60].view(np.uint32)[0])
+        cfg = hdr[16:64].view(np.int32)
+        g.n = int(hdr[64:68].view(np.uint32)[0])
         g.directed = bool(cfg[0])
         g.L = int(cfg[4])
         return g
+
+    def memory(self) -> dict:
+        """Device bytes held by the handle and the largest growth of its recent batch calls."""
+        held, growth = ctypes.c_uint64(), ctypes.c_uint64()
+        rc = self.lib.ldl_memory(self.h, ctypes.byref(held), ctypes.byref(growth))
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_memory")
+        return {"held": held.value, "recent_growth": growth.value}
 
     def export_state(self) -> bytes:
         """The whole state as an opaque blob (ldl_export_state)."""

@@ -73,18 +73,6 @@ static void* noalloc_scratch(int device) {
   return addr[device];
 }
 
-template <typename T>
-static T* dalloc(uint64_t count) {
-  void* p = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&p, count * sizeof(T));
-  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
-    (void)hipGetLastError();
-    throw NoMem{};
-  }
-  hcheck(e);
-  return (T*)p;
-}
 
 // Device-side counters and accumulators, mirrored into pinned host memory on demand.
 // Counters written by one candidate pass (cleared together before it).
@@ -154,6 +142,7 @@ struct Engine {
   int64_t gp = 1, gq = 1;
   int N = 2, L = 4, M = 5;
   int64_t an = 1, ad = 1000, bn = 1, bd = 100;
+  int64_t rn = 0, rd = 1;   // adaptive refresh threshold (0: never)
   int device = 0;
   int profile = 0;
   int test_flags = 0;   // see ldl_config
@@ -243,7 +232,27 @@ struct Engine {
   uint32_t *tx = nullptr, *ty = nullptr;
   void* cub_tmp = nullptr;
   size_t cub_bytes = 0;
-  std::vector<void*> owned;
+  // device memory: hipMalloc / hipFree, or the caller's allocator hook (ldl_config.alloc/free)
+  ldl_alloc_fn halloc = nullptr;
+  ldl_free_fn hfree = nullptr;
+  void* hctx = nullptr;
+  PrimAlloc palloc{};   // the same source for the library primitives' temporary storage
+  std::vector<std::pair<void*, uint64_t>> owned;
+  // device bytes held now, at the start of the current call and at its peak; the growth of the
+  // last batch calls (the serving loop's admission reads it through ldl_memory)
+  uint64_t held = 0, call_start = 0, call_peak = 0;
+  uint64_t growth_hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  uint32_t growth_next = 0, calls_done = 0;
+  void call_begin() { call_start = call_peak = held; }
+  void call_end() {
+    if (calls_done++ == 0) return;   // creation's own allocations are the state, not scratch growth
+    growth_hist[growth_next++ % 8] = call_peak - call_start;
+  }
+  uint64_t recent_growth() const {
+    uint64_t g = 0;
+    for (uint64_t x : growth_hist) g = std::max(g, x);
+    return g;
+  }
 
   // statistics / trace
   ldl_batch_stats stats{};
@@ -259,17 +268,52 @@ struct Engine {
   std::vector<Pending> pending;
 
   // ------------------------------------------------------------------ memory helpers
+  void* raw_alloc(uint64_t bytes) {
+    if (bytes == 0) bytes = 1;
+    void* p = nullptr;
+    if (halloc) {
+      p = halloc(hctx, bytes, device, (void*)st);
+      if (!p) throw NoMem{};
+    } else {
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        (void)hipGetLastError();
+        throw NoMem{};
+      }
+      hcheck(e);
+    }
+    held += bytes;
+    call_peak = std::max(call_peak, held);
+    return p;
+  }
+  void raw_free(void* p, uint64_t bytes) {
+    if (!p) return;
+    held -= std::min(held, bytes);
+    if (hfree) hfree(hctx, p, bytes, device, (void*)st);
+    else (void)hipFree(p);
+  }
+  static void* prim_alloc_cb(void* ctx, size_t bytes) {
+    try {
+      return ((Engine*)ctx)->raw_alloc(bytes);
+    } catch (...) {
+      return nullptr;
+    }
+  }
+  static void prim_free_cb(void* ctx, void* p, size_t bytes) { ((Engine*)ctx)->raw_free(p, bytes); }
   template <typename T>
   T* alloc(uint64_t count) {
-    T* p = dalloc<T>(count);
-    owned.push_back((void*)p);
+    const uint64_t bytes = (count ? count : 1) * sizeof(T);
+    T* p = (T*)raw_alloc(bytes);
+    owned.push_back(std::make_pair((void*)p, bytes));
     return p;
   }
   void release(void* p) {
     if (!p) return;
-    auto it = std::find(owned.begin(), owned.end(), p);
-    if (it != owned.end()) owned.erase(it);
-    (void)hipFree(p);
+    auto it = std::find_if(owned.begin(), owned.end(), [&](const std::pair<void*, uint64_t>& o) { return o.first == p; });
+    if (it == owned.end()) return;
+    const uint64_t bytes = it->second;
+    owned.erase(it);
+    raw_free(p, bytes);
   }
   template <typename T>
   void regrow(T*& p, uint64_t count) {
@@ -278,9 +322,10 @@ struct Engine {
   }
 
   ~Engine() {
-    for (void* p : owned) (void)hipFree(p);
+    if (st) (void)hipStreamSynchronize(st);
+    for (auto& o : owned) raw_free(o.first, o.second);
     if (hs) (void)hipHostFree(hs);
-    if (cub_tmp) (void)hipFree(cub_tmp);
+    raw_free(cub_tmp, cub_bytes);   // allocated through the same source (palloc)
     for (auto& e : ev_pool) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -356,6 +401,14 @@ struct Engine {
     gp = c.gamma_num; gq = c.gamma_den;
     N = c.N; L = c.L; M = c.M;
     an = c.alpha_num; ad = c.alpha_den; bn = c.beta_num; bd = c.beta_den;
+    rn = c.refresh_num; rd = c.refresh_den;
+    halloc = c.alloc;
+    hfree = c.free;
+    hctx = c.alloc_ctx;
+    if (halloc) {
+      palloc = PrimAlloc{&Engine::prim_alloc_cb, &Engine::prim_free_cb, this};
+      prim_set_allocator(&palloc);   // for the rest of this call (the entry point resets it)
+    }
     device = c.device;
     profile = c.profile;
     test_flags = c.test_flags;
@@ -1473,9 +1526,68 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ Algorithm 1
+  // Adaptive refresh (a variant, off unless rn > 0): the size of the level-0 frontier A^0 (alive
+  // seeds and every alive member of their communities); when it reaches rn/rd of n, locality no
+  // longer holds (Sec. IV-F, Sec. V) and the batch reoptimises from scratch.
+  void maybe_refresh() {
+    if (rn <= 0) return;
+    Level& V0 = lv[0];
+    begin(S_COMM);
+    launch_set_add_mapped(ref(S_COMM), sets[S_D0].list, n, V0.lab, V0.alive, st, &ds->counts[sets[S_D0].ci]);
+    zero(&ds->tcount);
+    launch_count_members(n, V0.alive, V0.lab, sets[S_COMM].stamp, sets[S_COMM].epoch, &ds->tcount, st);
+    sync_read();
+    const uint64_t a0 = hs->tcount;
+    stats.frontier0 = a0;
+    if ((i128)rd * a0 < (i128)rn * n) return;
+    record(0, 2, 0, a0, 0, 0, 0);
+    stats.refreshes = 1;
+    refresh_state();
+  }
+  // The state static Leiden starts from on the current graph: singleton labels and parents at
+  // level 0, no aggregate level, totals equal to the degrees, Ein the self-loops, and every node
+  // with an entry a seed (the state ldl_create reaches before its passes).
+  void refresh_state() {
+    Level& V0 = lv[0];
+    launch_iota(V0.lab, n, st);
+    if (L > 0) {
+      launch_iota(V0.par, n, st);
+      launch_fill_u32(V0.rsize, 0, n, st);
+    }
+    for (int r = 1; r <= top; ++r) {
+      Level& V = lv[r];
+      launch_fill_u8(V.alive, 0, n, st);
+      launch_iota(V.lab, n, st);
+      launch_fill_i64(V.kout, 0, n, st);
+      if (directed) launch_fill_i64(V.kin, 0, n, st);
+      if (r < L) {
+        launch_iota(V.par, n, st);
+        launch_fill_u32(V.rsize, 0, n, st);
+      }
+      drop_csr(V.out);
+      if (directed) drop_csr(V.in);
+      pend[r].count = 0;
+      rebuild_flag[r] = 0;
+    }
+    for (int r = 0; r <= L; ++r) begin(S_D0 + r);
+    top = 0;
+    launch_copy_i64(Kout, V0.kout, n, st);
+    if (directed) launch_copy_i64(Kin, V0.kin, n, st);
+    zero(&ds->dein);
+    zero(&ds->dskk_lo);
+    zero(&ds->dskk_hi);
+    launch_refresh_scalars(V0.out.ref, directed ? V0.in.ref : CsrRef{}, n, V0.kout, V0.kin, ref(S_D0), &ds->dein,
+                           &ds->dskk_lo, &ds->dskk_hi, st);
+    select_set(S_D0);
+    sync_read();
+    Ein = hs->dein;
+    SKK = ((i128)hs->dskk_hi << 64) | (i128)hs->dskk_lo;
+  }
+
   int apply(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg, uint64_t nc) {
     const int rc = ingest(dins, ni, ddel, nd, dchg, nc);
     if (rc != LDL_OK) return rc;
+    maybe_refresh();
     for (int i = 1; i <= N; ++i) {
       pass_idx = i;
       const i128 Qp = qnum();
@@ -1688,7 +1800,7 @@ struct Engine {
   struct StateHeader {
     char magic[8];
     uint32_t version, header_bytes;
-    int32_t cfg[10];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den
+    int32_t cfg[12];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den, refresh num, den
     uint32_t n;
     int32_t top;
     int64_t m, ein, skk_hi;
@@ -1696,7 +1808,7 @@ struct Engine {
     uint32_t lim[2][5];
     uint64_t total_bytes;
   };
-  static constexpr uint32_t kStateVersion = 1;
+  static constexpr uint32_t kStateVersion = 2;
   uint64_t level_node_bytes(int r) const {
     return (uint64_t)n * (1 + 4 + (r < L ? 8 : 0) + 8 + (directed ? 8 : 0) + 4) + 8;
   }
@@ -1724,9 +1836,9 @@ struct Engine {
     std::memcpy(hd.magic, "LDLSTATE", 8);
     hd.version = kStateVersion;
     hd.header_bytes = sizeof(StateHeader);
-    const int32_t c10[10] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
-                             (int32_t)bd};
-    std::memcpy(hd.cfg, c10, sizeof(c10));
+    const int32_t c12[12] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
+                             (int32_t)bd, (int32_t)rn, (int32_t)rd};
+    std::memcpy(hd.cfg, c12, sizeof(c12));
     hd.n = n;
     hd.top = top;
     hd.m = m;
@@ -1900,8 +2012,15 @@ int guard_err(ldl_handle* h, int code) {
   return code;
 }
 
+// the handle's allocator serves the library primitives' temporary storage during the call
+struct PrimAllocScope {
+  explicit PrimAllocScope(ldl_handle* h) { ldl::prim_set_allocator(h && h->e->halloc ? &h->e->palloc : nullptr); }
+  ~PrimAllocScope() { ldl::prim_set_allocator(nullptr); }
+};
+
 template <typename F>
 int run_guarded(ldl_handle* h, F&& f) {
+  PrimAllocScope scope(h);
   try {
     return f();
   } catch (const ldl::NoMem&) {
@@ -1917,7 +2036,8 @@ bool cfg_ok(const ldl_config& c) {
   auto in16 = [](int32_t x, int32_t lo) { return x >= lo && x < 65536; };
   return in16(c.gamma_num, 1) && in16(c.gamma_den, 1) && c.N >= 1 && c.M >= 1 && c.L >= 0 && c.L <= 16 &&
          in16(c.alpha_num, 0) && in16(c.alpha_den, 1) && in16(c.beta_num, 0) && in16(c.beta_den, 1) &&
-         (c.directed == 0 || c.directed == 1);
+         in16(c.refresh_num, 0) && in16(c.refresh_den, 1) && (c.directed == 0 || c.directed == 1) &&
+         ((c.alloc == nullptr) == (c.free == nullptr));
 }
 
 int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair* del, uint64_t nd,
@@ -1932,6 +2052,7 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     ldl::Engine& e = *h->e;
     ldl::hcheck(hipSetDevice(e.device));
     e.stats = ldl_batch_stats{};
+    e.call_begin();
     hipEvent_t t0, t1;
     ldl::hcheck(hipEventCreate(&t0));
     ldl::hcheck(hipEventCreate(&t1));
@@ -1940,7 +2061,7 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     uint32_t* tmp = nullptr;
     if (!on_device) {
       const uint64_t words = 3 * ni + 2 * nd + 3 * nc;
-      tmp = ldl::dalloc<uint32_t>(words ? words : 1);
+      tmp = e.alloc<uint32_t>(words ? words : 1);
       if (ni) ldl::hcheck(hipMemcpyAsync(tmp, ins, 12 * ni, hipMemcpyHostToDevice, e.st));
       if (nd) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni, del, 8 * nd, hipMemcpyHostToDevice, e.st));
       if (nc) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni + 2 * nd, chg, 12 * nc, hipMemcpyHostToDevice, e.st));
@@ -1952,7 +2073,7 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     try {
       rc = e.apply(di, ni, dd, nd, dc, nc);
     } catch (...) {
-      if (tmp) (void)hipFree(tmp);
+      e.release(tmp);
       (void)hipEventDestroy(t0);
       (void)hipEventDestroy(t1);
       throw;
@@ -1963,8 +2084,10 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     ldl::hcheck(hipEventElapsedTime(&ms, t0, t1));
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    if (tmp) (void)hipFree(tmp);
+    ldl::hcheck(hipStreamSynchronize(e.st));
+    e.release(tmp);
     e.finish_profile();
+    e.call_end();
     e.stats.total_ms = ms;
     if (stats) *stats = e.stats;
     return rc;
@@ -1986,6 +2109,11 @@ void ldl_default_config(ldl_config* c) {
   c->device = 0;
   c->stream = nullptr;
   c->profile = 0;
+  c->refresh_num = 0;
+  c->refresh_den = 1;
+  c->alloc = nullptr;
+  c->free = nullptr;
+  c->alloc_ctx = nullptr;
 }
 
 int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_t n_edges, ldl_handle** out) {
@@ -2189,6 +2317,7 @@ int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl
   c.N = hd.cfg[3]; c.L = hd.cfg[4]; c.M = hd.cfg[5];
   c.alpha_num = hd.cfg[6]; c.alpha_den = hd.cfg[7];
   c.beta_num = hd.cfg[8]; c.beta_den = hd.cfg[9];
+  c.refresh_num = hd.cfg[10]; c.refresh_den = hd.cfg[11];
   if (!cfg_ok(c)) return LDL_EINVAL;
   ldl_handle* h = new (std::nothrow) ldl_handle;
   if (!h) return LDL_ENOMEM;
@@ -2216,14 +2345,14 @@ int ldl_check_invariants(const ldl_handle* h, ldl_invariant_report* report) {
   return run_guarded(const_cast<ldl_handle*>(h), [&]() -> int {
     ldl::Engine& e = *h->e;
     ldl::hcheck(hipSetDevice(e.device));
-    ldl::InvScratch* sc = ldl::dalloc<ldl::InvScratch>(1);   // the recount's sums, freed on return
+    ldl::InvScratch* sc = e.alloc<ldl::InvScratch>(1);   // the recount's sums, freed on return
     try {
       e.check_invariants(sc, report);
     } catch (...) {
-      (void)hipFree(sc);
+      e.release(sc);
       throw;
     }
-    (void)hipFree(sc);
+    e.release(sc);
     return LDL_OK;
   });
 }
@@ -2237,6 +2366,13 @@ int ldl_check_invariants_noalloc(const ldl_handle* h, ldl_invariant_report* repo
     e.check_invariants(e.static_sums, report);   // the device's static sums; no allocation
     return LDL_OK;
   });
+}
+
+int ldl_memory(const ldl_handle* h, uint64_t* held_bytes, uint64_t* recent_growth_bytes) {
+  if (!h || !held_bytes || !recent_growth_bytes) return LDL_EINVAL;
+  *held_bytes = h->e->held + h->e->cub_bytes;
+  *recent_growth_bytes = h->e->recent_growth();
+  return LDL_OK;
 }
 
 int ldl_set_trace(ldl_handle* h, int32_t on) {

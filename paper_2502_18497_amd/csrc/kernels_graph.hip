@@ -984,6 +984,38 @@ __global__ void k_alive_list(uint32_t n, const uint8_t* alive, SetRef set) {
     if (alive[x]) set_add(set.stamp, set.epoch, set.list, set.count, (uint32_t)x);
 }
 
+// *count += alive nodes u < n whose key is marked (stamp[key[u]] == ep): the size of a frontier
+// closure without listing it
+__global__ void k_count_members(uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* stamp,
+                                uint32_t ep, u64a* count) {
+  uint64_t c = 0;
+  for (uint64_t u = gtid(); u < n; u += gstride())
+    if (alive[u] && stamp[key[u]] == ep) ++c;
+  c = (uint64_t)wave_sum_i64((int64_t)c);
+  if (lane_id() == 0 && c) atomicAdd(count, (u64a)c);
+}
+
+// Refresh: seeds = nodes with an entry; the intra-community weight of the singleton partition
+// (the self-loops) and sum kout kin (exact), one wavefront per node
+__global__ void k_refresh_scalars(CsrRef out, CsrRef in, uint32_t n, const int64_t* kout, const int64_t* kin,
+                                  SetRef seeds, i64a* ein, u64a* skk_lo, i64a* skk_hi) {
+  const int lane = lane_id();
+  for (uint64_t u = gwave(); u < n; u += gwstride()) {
+    const uint32_t d = out.deg[u];
+    const uint64_t o = out.off[u];
+    int64_t self = 0;
+    for (uint32_t i = lane; i < d; i += kWave)
+      if (out.nbr[o + i] == (uint32_t)u) self += wget(out, o + i);
+    self = wave_sum_i64(self);
+    if (lane == 0) {
+      if (self) atomicAdd((u64a*)ein, (u64a)self);
+      const i128 p = (i128)kout[u] * (i128)kin[u];
+      if (p) atomic_add_i128(skk_lo, skk_hi, p);
+      if (d || (in.off && in.deg[u])) seeds.stamp[u] = seeds.epoch;
+    }
+  }
+}
+
 __global__ void k_materialise_nodes(uint32_t n, const uint32_t* rsize, uint8_t* alive_up, const uint32_t* lab,
                                     uint32_t* lab_up, uint32_t* par_up) {
   for (uint64_t x = gtid(); x < n; x += gstride()) {
@@ -1868,6 +1900,15 @@ void launch_bulk_totals(uint32_t n, const uint32_t* lab0, const int64_t* kout, c
 void launch_degrees_up(uint32_t n, const uint8_t* alive, const uint32_t* par, const int64_t* kout, const int64_t* kin,
                        int64_t* kout_up, int64_t* kin_up_or_null, hipStream_t s) {
   if (n) k_degrees_up<<<grid_for(n), kTpb, 0, s>>>(n, alive, par, kout, kin, kout_up, kin_up_or_null);
+}
+void launch_count_members(uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* stamp, uint32_t ep,
+                          u64a* count, hipStream_t s) {
+  if (n) k_count_members<<<grid_for(n) < 2048u ? grid_for(n) : 2048u, kTpb, 0, s>>>(n, alive, key, stamp, ep, count);
+}
+void launch_refresh_scalars(CsrRef out, CsrRef in, uint32_t n, const int64_t* kout, const int64_t* kin, SetRef seeds,
+                            i64a* ein, u64a* skk_lo, i64a* skk_hi, hipStream_t s) {
+  if (n) k_refresh_scalars<<<grid_waves(n) < 4096u ? grid_waves(n) : 4096u, kTpb, 0, s>>>(out, in, n, kout, kin, seeds,
+                                                                                           ein, skk_lo, skk_hi);
 }
 void launch_sum_u32(const uint32_t* a, uint32_t n, u64a* total, hipStream_t s) {
   if (n) k_sum_u32<<<grid_for(n) < 1024u ? grid_for(n) : 1024u, kTpb, 0, s>>>(a, n, total);

@@ -349,11 +349,27 @@ void launch_label_refresh(uint32_t n, const uint8_t* alive, const uint32_t* par,
 void launch_recount_degrees(CsrRef c, uint32_t n, int64_t* deg_out, hipStream_t s);
 // *total += sum of a[0..n)
 void launch_sum_u32(const uint32_t* a, uint32_t n, u64a* total, hipStream_t s);
+// *count += alive nodes u < n with stamp[key[u]] == ep
+void launch_count_members(uint32_t n, const uint8_t* alive, const uint32_t* key, const uint32_t* stamp, uint32_t ep,
+                          u64a* count, hipStream_t s);
+// seeds (stamps only) = nodes with an out- or in-entry; *ein += self-loop weights; sum kout kin
+// added exactly into (skk_lo, skk_hi)
+void launch_refresh_scalars(CsrRef out, CsrRef in, uint32_t n, const int64_t* kout, const int64_t* kin, SetRef seeds,
+                            i64a* ein, u64a* skk_lo, i64a* skk_hi, hipStream_t s);
 // kout_up[par[u]] += kout[u] (kin likewise when kin_up_or_null is set) over alive u < n
 void launch_degrees_up(uint32_t n, const uint8_t* alive, const uint32_t* par, const int64_t* kout, const int64_t* kin,
                        int64_t* kout_up, int64_t* kin_up_or_null, hipStream_t s);
 
 // ---------------------------------------------------------------- library primitives (hipCUB)
+// Temporary storage of the primitives comes from this allocator when one is set for the calling
+// thread (null: hipMalloc / hipFree); prim_free_tmp releases it the same way.
+struct PrimAlloc {
+  void* (*alloc)(void* ctx, size_t bytes);
+  void (*free)(void* ctx, void* p, size_t bytes);
+  void* ctx;
+};
+void prim_set_allocator(const PrimAlloc* a);
+void prim_free_tmp(void* tmp, size_t bytes);
 // temp storage is grown on demand through *tmp / *tmp_bytes (device memory owned by caller)
 int prim_sort_pairs_u64_u32_db(void** tmp, size_t* tmp_bytes, uint64_t* k0, uint64_t* k1, uint32_t* v0, uint32_t* v1,
                                uint64_t n, int begin_bit, int end_bit, int* sel, hipStream_t s);

@@ -9,16 +9,29 @@ namespace ldl {
 
 namespace {
 
+thread_local const PrimAlloc* t_alloc = nullptr;   // set by the handle that calls in
+
+void tmp_free(void* p, size_t bytes) {
+  if (!p) return;
+  if (t_alloc && t_alloc->free) t_alloc->free(t_alloc->ctx, p, bytes);
+  else (void)hipFree(p);
+}
+
 int ensure(void** tmp, size_t* bytes, size_t need) {
   if (need <= *bytes && *tmp) return 0;
-  if (*tmp) (void)hipFree(*tmp);
+  tmp_free(*tmp, *bytes);
   *tmp = nullptr;
   size_t n = need + (need >> 2) + 256;
-  if (hipMalloc(tmp, n) != hipSuccess) {
+  void* p = nullptr;
+  if (t_alloc && t_alloc->alloc) p = t_alloc->alloc(t_alloc->ctx, n);
+  else if (hipMalloc(&p, n) != hipSuccess) p = nullptr;
+  if (!p) {
+    (void)hipGetLastError();
     *tmp = nullptr;
     *bytes = 0;
     return -1;
   }
+  *tmp = p;
   *bytes = n;
   return 0;
 }
@@ -48,6 +61,9 @@ struct SumI64 {
 };
 
 }  // namespace
+
+void prim_set_allocator(const PrimAlloc* a) { t_alloc = a; }
+void prim_free_tmp(void* tmp, size_t bytes) { tmp_free(tmp, bytes); }
 
 int prim_sort_pairs_u64_u32(void** tmp, size_t* tmp_bytes, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                             uint32_t* vout, uint64_t n, int begin_bit, int end_bit, hipStream_t s) {

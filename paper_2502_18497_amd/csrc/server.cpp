@@ -19,9 +19,15 @@ namespace {
 
 typedef std::chrono::steady_clock Clock;
 
-// device bytes a batch occupies while it runs: records, sorted copies, entries and the
-// aggregation tuples it can cascade (a conservative linear estimate) plus fixed scratch
-uint64_t footprint(uint64_t updates) { return ((uint64_t)1 << 20) + updates * 256ull; }
+// device bytes a batch may allocate while it runs: the larger of a linear estimate in its
+// updates (records, sorted copies, entries) and the most the handle's recent batch calls have
+// allocated beyond what they held (tuple buffers, hub pools, row growth), measured by the handle
+uint64_t footprint(ldl_handle* h, uint64_t updates) {
+  const uint64_t linear = ((uint64_t)1 << 20) + updates * 256ull;
+  uint64_t held = 0, growth = 0;
+  if (ldl_memory(h, &held, &growth) != LDL_OK) growth = 0;
+  return linear > growth ? linear : growth;
+}
 
 }  // namespace
 
@@ -61,6 +67,7 @@ struct ldl_server {
       if (blocked.count(r->h)) continue;
       blocked.insert(r->h);                   // later requests of this handle wait for it
       if (busy.count(r->h)) continue;
+      r->fp = footprint(r->h, r->ins.size() + r->del.size() + r->chg.size());
       const bool fits = in_use + r->fp <= budget || running == 0;
       if (!fits) continue;
       if (r->h == prefer) {
@@ -127,7 +134,7 @@ int ldl_server_submit(ldl_server* s, ldl_handle* h, const ldl_edge* ins, uint64_
   r->ins.assign(ins, ins + n_ins);
   r->del.assign(del, del + n_del);
   r->chg.assign(chg, chg + n_chg);
-  r->fp = footprint(n_ins + n_del + n_chg);
+  r->fp = 0;   // measured when the request is considered for admission (its handle idle then)
   r->submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);

@@ -98,3 +98,27 @@ def test_sweep_parameter_settings_directed(cfg):
     s = synth.Stream(2000, True, synth.BASE_SEED + 146)
     s.planted(100, 0.04, 0.002, 1, 8)
     run_parity(s.n, s.edges(), [s.batch(80) for _ in range(3)], directed=True, **cfg)
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_adaptive_refresh(directed):
+    """Adaptive refresh (rho = 1/2): batches whose level-0 frontier reaches half of the vertices
+    reoptimise from scratch.  Bit-identical to the oracle (which takes the same decision on the
+    same frontier size), the refreshed state equal to a fresh handle created on the current
+    edges, and the per-batch refresh statistics equal to the oracle's count."""
+    import paper_2502_18497_amd as ldl
+
+    s = synth.Stream(800, directed, synth.BASE_SEED + 720 + directed)
+    s.planted(40, 0.12, 0.006, 1, 8)
+    stats = []
+    g, og = run_parity(800, s.edges(), [s.batch(300), s.batch(5), s.batch(300)], directed=directed,
+                       stats_out=stats, refresh=(1, 2))
+    assert sum(st["refreshes"] for st in stats) == og.refreshes() > 0
+    assert all(st["frontier0"] > 0 for st in stats)
+    L0 = g.level(0)
+    keep = np.ones(len(L0["rows"]), bool) if directed else L0["rows"] <= L0["cols"]
+    cur = np.stack([L0["rows"][keep], L0["cols"][keep], L0["w"][keep]], axis=1).astype(np.uint32)
+    if stats[-1]["refreshes"]:
+        fresh = ldl.Graph(800, cur, directed=directed)
+        msgs = diff_states(g.state(), fresh.state())
+        assert not msgs, msgs

@@ -11,17 +11,17 @@ from tests.statecheck import diff_states, oracle_state
 
 pytestmark = pytest.mark.gpu
 
-HEADER_BYTES = 144
+HEADER_BYTES = 152
 
 
 def blob_layout(blob: bytes, L: int):
     """Byte offsets of the sections of a state blob (the layout documented with
     ldl_export_state)."""
     hdr = np.frombuffer(blob[:HEADER_BYTES], dtype=np.uint8)
-    cfg = hdr[16:56].view(np.int32)
+    cfg = hdr[16:64].view(np.int32)
     directed = bool(cfg[0])
-    n = int(hdr[56:60].view(np.uint32)[0])
-    top = int(hdr[60:64].view(np.int32)[0])
+    n = int(hdr[64:68].view(np.uint32)[0])
+    top = int(hdr[68:72].view(np.int32)[0])
     off = {"Kout": HEADER_BYTES}
     p = HEADER_BYTES + 8 * n
     if directed:
@@ -191,3 +191,55 @@ def test_invariant_recount_flags_planted_corruption(directed):
     v = int(np.nonzero(par0 != np.arange(n))[0][0])
     rep = planted(lambda b: put(b, L0["par"] + 4 * v, np.array([v], np.uint32)))
     assert rep["failed"] & 4, rep
+
+
+def test_allocator_hook_serves_every_device_allocation():
+    """With ldl_config.alloc/free set (here PyTorch's caching allocator on the handle's stream),
+    every device allocation of the handle -- state, scratch and the primitives' temporary storage
+    -- goes through the hook and is returned through it by ldl_destroy; results are unchanged."""
+    import torch
+
+    import paper_2502_18497_amd as ldl
+
+    s = synth.rmat_directed_lognormal(1 << 13, 12 << 13, seed_offset=660)
+    e = s.edges()
+    a = ldl.TorchAllocator()
+    base = torch.cuda.memory_allocated()
+    g = ldl.Graph(s.n, e, directed=True, allocator=a)
+    g0 = ldl.Graph(s.n, e, directed=True)
+    assert a.allocs > 0 and torch.cuda.memory_allocated() > base
+    for _ in range(3):
+        b = s.batch(500)
+        g.apply_batch(b.ins, b.dels, b.chg)
+        g0.apply_batch(b.ins, b.dels, b.chg)
+    assert not diff_states(g.state(), g0.state())
+    assert g.check_invariants()["failed"] == 0
+    g.close()
+    assert not a.live and a.frees == a.allocs, (len(a.live), a.allocs, a.frees)
+
+
+def test_half_an_allocator_hook_is_refused():
+    import ctypes
+
+    import paper_2502_18497_amd as ldl
+
+    lib = ldl.load_library()
+    c = ldl.ldl_default_config()
+    a = ldl.TorchAllocator()
+    c.alloc = ctypes.cast(a._alloc, ctypes.c_void_p)   # free left NULL
+    h = ctypes.c_void_p()
+    e = np.array([[0, 1, 1]], np.uint32)
+    assert lib.ldl_create(ctypes.byref(c), 4, e.ctypes.data, 1, ctypes.byref(h)) == ldl.LDL_EINVAL
+
+
+def test_memory_report_tracks_held_bytes_and_growth():
+    import paper_2502_18497_amd as ldl
+
+    s = synth.rmat_undirected(scale=13, seed_offset=670)
+    g = ldl.Graph(s.n, s.edges())
+    m0 = g.memory()
+    assert m0["held"] > 0 and m0["recent_growth"] == 0   # creation is the state, not growth
+    b = s.batch(20000)   # a batch far larger than any before: its buffers grow
+    g.apply_batch(b.ins, b.dels, b.chg)
+    m1 = g.memory()
+    assert m1["recent_growth"] > 0 and m1["held"] >= m0["held"]
