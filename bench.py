@@ -393,8 +393,7 @@ def directed_stream(scale, n_req, n_edges, L, N, M, batch, steps, warmup, label)
 
     batches = [make_batch(batch) for _ in range(warmup + steps)]
     torch.cuda.synchronize()
-    for b in batches[:warmup]:
-        g.apply_batch_device(*b)
+    wstats = [g.apply_batch_device(*b) for b in batches[:warmup]]
     torch.cuda.synchronize()
     lat, stats = [], []
     t0 = time.perf_counter()
@@ -411,14 +410,17 @@ def directed_stream(scale, n_req, n_edges, L, N, M, batch, steps, warmup, label)
     del e, used, batches
     torch.cuda.empty_cache()
     return {"n": n, "edges": int(E), "L": L, "N": N, "M": M, "batch": batch, "steps": steps, "warmup": warmup,
-            "T": T, "lat": lat, "stats": stats, "static": st0, "gen_s": gen_s, "static_s": static_s,
+            "T": T, "lat": lat, "stats": stats, "before": [st0] + wstats, "static": st0, "gen_s": gen_s,
+            "static_s": static_s,
             "level_entries_after_static": level_nnz, "device_free_gib_after_static": free_gib,
             "device_free_gib_after_batches": free_after, "invariants_after": rep}
 
 
-def kernel_roofline(stats_list, directed):
+def kernel_roofline(stats_list, directed, before=None):
     """Roofline of the candidate kernel with the most time over the given per-call statistics:
-    algorithmic bytes counted by the kernels over their HIP-event times (profile on)."""
+    algorithmic bytes counted by the kernels over their HIP-event times (profile on).  `before`: the
+    statistics of the calls before these (their launches of the kernel are counted, so that counter
+    runs can pick this kernel's dispatches of the timed calls out of the whole process)."""
     import numpy as np
 
     import paper_2502_18497_amd as ldl
@@ -427,14 +429,58 @@ def kernel_roofline(stats_list, directed):
     by = np.sum([st["bin_bytes"] for st in stats_list], axis=0)
     la = np.sum([st["bin_launches"] for st in stats_list], axis=0)
     dom = int(np.argmax(ms))
+    skip = int(sum(st["bin_launches"][dom] for st in before)) if before else 0
     achieved = float(by[dom] / (ms[dom] * 1e-3) / 1e9) if ms[dom] > 0 else 0.0
     name = ldl.candidate_kernel_name(dom, directed)
     avg_us = float(1e3 * ms[dom] / max(1, la[dom]))
     traffic, traffic_bytes = measured_traffic(name, avg_us)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
-            "kernel": name, "launches": int(la[dom]), "avg_launch_us": avg_us,
+            "kernel": name, "launches": int(la[dom]), "launches_before": skip, "avg_launch_us": avg_us,
             "bytes_per_launch": float(by[dom] / max(1, la[dom]))}
+
+
+def pmc_summary(args):
+    """Per-dispatch HBM traffic of one kernel from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
+    csv output), scaled by what the same counters read for a plain copy of known size (the `copy`
+    workload), averaged over the dispatches of the timed calls (the first `--pmc-skip` dispatches of
+    the kernel in the process are those of earlier calls); merged into profiles/pmc_traffic.json
+    under the current kernel-source hash."""
+    import csv
+
+    def per_dispatch(path, counter, name_sub):
+        vals = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter or name_sub not in row.get("Kernel_Name", ""):
+                    continue
+                d = int(row["Dispatch_Id"])
+                vals[d] = vals.get(d, 0.0) + float(row["Counter_Value"])
+        return [vals[d] for d in sorted(vals)]
+
+    f_copy = per_dispatch(args.pmc_copy_fetch, "FETCH_SIZE", "copyBuffer")
+    w_copy = per_dispatch(args.pmc_copy_write, "WRITE_SIZE", "copyBuffer")
+    copy_bytes = args.copy_mib << 20
+    cf = copy_bytes / (1024.0 * (sum(f_copy) / len(f_copy)))
+    cw = copy_bytes / (1024.0 * (sum(w_copy) / len(w_copy)))
+    fk = per_dispatch(args.pmc_fetch, "FETCH_SIZE", args.pmc_kernel)[args.pmc_skip:]
+    wk = per_dispatch(args.pmc_write, "WRITE_SIZE", args.pmc_kernel)[args.pmc_skip:]
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    doc = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            doc = json.load(f)
+    if doc.get("source_sha") != kernel_source_sha():
+        doc = {"source_sha": kernel_source_sha(), "kernels": {}}
+    doc.update({"copy_factor_fetch": cf, "copy_factor_write": cw,
+                "copy_fetch_kib_per_GiB": (sum(f_copy) / len(f_copy)) * (1 << 30) / copy_bytes,
+                "copy_write_kib_per_GiB": (sum(w_copy) / len(w_copy)) * (1 << 30) / copy_bytes})
+    doc["kernels"][args.pmc_kernel] = {"dispatches": len(fk), "fetch_kib": sum(fk) / max(1, len(fk)),
+                                       "write_kib": sum(wk) / max(1, len(wk))}
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    print(json.dumps({"kernel": args.pmc_kernel, **doc["kernels"][args.pmc_kernel], "copy_factor_fetch": cf,
+                      "copy_factor_write": cw}), flush=True)
 
 
 def stream_summary(r):
@@ -477,7 +523,7 @@ def run_bigstream(args):
            "config": {"workload": f"rmat{args.scale}-directed-lognormal-batch{args.batch}", "n": r["n"],
                       "edges": r["edges"], "batch": args.batch, "mix": "70/20/10 insert/delete/reweight",
                       "L": args.big_L, "N": args.big_N, "M": args.big_M},
-           "roofline": kernel_roofline(r["stats"], True)}
+           "roofline": kernel_roofline(r["stats"], True, r["before"])}
     out.update({k: v for k, v in summ.items() if k not in out})
     print(json.dumps(out), flush=True)
 
@@ -740,7 +786,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
     ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream",
-                                           "latency", "headline"],
+                                           "latency", "headline", "pmc-summary"],
                     default="headline")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
@@ -762,6 +808,12 @@ def main():
     ap.add_argument("--edges", type=int, default=0, help="scan: edge count (default avg-degree x vertices)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--latency-runs", type=int, default=20)
+    ap.add_argument("--pmc-kernel", default="", help="pmc-summary: kernel name as in the roofline object")
+    ap.add_argument("--pmc-skip", type=int, default=0, help="pmc-summary: the kernel's dispatches before the timed calls")
+    ap.add_argument("--pmc-fetch", default="", help="pmc-summary: counter csv of the FETCH_SIZE run")
+    ap.add_argument("--pmc-write", default="", help="pmc-summary: counter csv of the WRITE_SIZE run")
+    ap.add_argument("--pmc-copy-fetch", default="", help="pmc-summary: FETCH_SIZE csv of the copy workload")
+    ap.add_argument("--pmc-copy-write", default="", help="pmc-summary: WRITE_SIZE csv of the copy workload")
     ap.add_argument("--graphs", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--mix-max-exp", type=float, default=5.0)
@@ -793,6 +845,8 @@ def main():
         return run_bigstream(args)
     if args.workload == "latency":
         return run_latency(args)
+    if args.workload == "pmc-summary":
+        return pmc_summary(args)
 
     if args.workload == "rmat":
         print(json.dumps(measure_rmat(args)), flush=True)
@@ -844,7 +898,7 @@ def run_headline(args):
     a = directed_stream(scale, n, round(CFG3_OUT_DEGREE * n), 4, 2, 5, args.big_batch, args.steps, args.warmup,
                         "full method")
     summ = stream_summary(a)
-    roof = kernel_roofline(a["stats"], True)
+    roof = kernel_roofline(a["stats"], True, a["before"])
     upd = a["batch"] * a["steps"]
     out = {"metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
            "value": upd / a["T"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -1270,7 +1270,7 @@ struct Engine {
       cub(launch_items(sets[S_U].list, nullptr, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off, nullptr,
                        nullptr, &cub_tmp, &cub_bytes, st));
       launch_mark_items(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, &ds->counts[sets[S_U].ci], n, it_off,
-                        V.out.ref, in_or_none, st);
+                        V.out.ref, in_or_none, st, sets[S_U].stamp, sets[S_U].epoch, V.alive);
       select_set(S_S);
       uint32_t nS = 0, K = 0, na = 0;
       int64_t dein = 0;

@@ -1157,9 +1157,10 @@ __device__ __forceinline__ void wave_items(const uint64_t* ioff, uint32_t cnt, F
 // stamp[x] = ep for every listed node (with or without entries) and each of its entries'
 // neighbours
 __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* countp, uint32_t bound,
-                             const uint64_t* ioff, CsrRef out, CsrRef in) {
+                             const uint64_t* ioff, CsrRef out, CsrRef in, uint32_t pull_from) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
+  if (c0 >= pull_from) return;   // a dense list: k_mark_pull builds the set instead
   const uint32_t cnt = c0 < bound ? c0 : bound;
   for (uint64_t i = gtid(); i < cnt; i += gstride()) stamp[list[i]] = ep;
   if (c0 >= bound) return;   // every id of [0, bound) is listed: the neighbours are listed nodes
@@ -1187,6 +1188,36 @@ __global__ void k_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list,
         if (cur[k] != ep) stamp[xs[k]] = ep;
     }
   });
+}
+
+// The same set pulled instead of pushed, for a dense list (at least pull_from nodes; the list is
+// the nodes whose ustamp equals uep): an alive node x joins when it is listed or when one of its
+// out- or in-neighbours is (the in-rows hold the transpose, so x is a neighbour of a listed u iff
+// u is a neighbour of x).  Each node stops reading its rows at the first listed neighbour, so a
+// dense list costs about one gather per node instead of a write per entry of every listed node.
+__global__ void k_mark_pull(uint32_t* stamp, uint32_t ep, const uint32_t* ustamp, uint32_t uep,
+                            const uint32_t* countp, uint32_t pull_from, uint32_t n, const uint8_t* alive, CsrRef out,
+                            CsrRef in) {
+  if (*countp < pull_from) return;
+  const int lane = lane_id();
+  // one wavefront per node: 64 entries per step, a ballot ends the walk at the first listed one
+  // (a long row of a node with few listed neighbours is read by the whole wavefront, not one lane)
+  for (uint64_t x = gwave(); x < n; x += gwstride()) {
+    if (!alive[x]) continue;
+    bool hit = ustamp[x] == uep;
+    const uint32_t dout = out.deg[x];
+    const uint64_t s = node_slots(out, in, (uint32_t)x);
+    for (uint64_t jb = 0; jb < s && !hit; jb += kWave) {
+      const uint64_t j = jb + lane;
+      bool h = false;
+      if (j < s) {
+        const uint32_t y = j < dout ? out.nbr[out.off[x] + j] : in.nbr[in.off[x] + (j - dout)];
+        h = ustamp[y] == uep;
+      }
+      hit = __ballot(h) != 0;
+    }
+    if (hit && lane == 0) stamp[x] = ep;
+  }
 }
 
 // Subtract-add tuples of Eq. 3.  Materialise (REPAIR false): (P(u), P(x), w) for every out entry.
@@ -1665,8 +1696,14 @@ void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t
                                                 rcur_ep, rset_stamp, rset_ep, oldpar);
 }
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
-                       const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s) {
-  k_mark_items<<<kItemBlocks, kTpb, 0, s>>>(stamp, ep, list, count, bound, ioff, out, in);
+                       const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s, const uint32_t* ustamp,
+                       uint32_t uep, const uint8_t* alive) {
+  // dense lists (a quarter of the nodes or more) are pulled when the list's stamps are given
+  const uint32_t pull_from = ustamp ? (uint32_t)(((uint64_t)bound + 3) / 4) : 0xFFFFFFFFu;
+  k_mark_items<<<kItemBlocks, kTpb, 0, s>>>(stamp, ep, list, count, bound, ioff, out, in, pull_from);
+  if (ustamp)
+    k_mark_pull<<<grid_waves(bound) < 8192u ? grid_waves(bound) : 8192u, kTpb, 0, s>>>(stamp, ep, ustamp, uep, count,
+                                                                                     pull_from, bound, alive, out, in);
 }
 void launch_pack_parents(uint32_t n, const uint32_t* par, const uint32_t* oldpar, const uint32_t* cstamp, uint32_t cep,
                          uint2* po, hipStream_t s) {

@@ -134,8 +134,11 @@ int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* coun
                  CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
                  size_t* tmp_bytes, hipStream_t s);
 // stamp[x] = ep for every listed node and every neighbour over its items
+// (with ustamp / uep, the stamps of the listed set, and bound = n: a list of at least n/4 nodes
+// is pulled instead -- alive nodes that are listed or have a listed neighbour -- same set)
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
-                       const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s);
+                       const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s, const uint32_t* ustamp = nullptr,
+                       uint32_t uep = 0, const uint8_t* alive = nullptr);
 // subtract-add tuples over items: per-node counts (added into zeroed counts), then tuples at
 // toffs (the exclusive prefix of counts) with a zeroed per-node cursor; seeds marked by
 // plain stores (seed_stamp may be null when not repairing)
@@ -263,7 +266,7 @@ struct HubWork {
   int pshift;      // partitions per hub: ceil(T 2^pshift / kPartEntries), at most ceil(T / 16)
   uint32_t tslots; // LDS table slots of a partition (power of two <= kPartSlots)
 };
-constexpr uint32_t kPartEntries = 1024;   // target entries per partition (pshift 0)
+constexpr uint32_t kPartEntries = 2048;   // target entries per partition (pshift 0)
 constexpr uint32_t kPartSlots = 4096;     // LDS table slots of a partition
 constexpr int kPartShiftMax = 6;
 int launch_hub(const MoveView& mv, BinRef br, uint32_t bound, int refine, HubPool hub, HubWork hw, CandBuf cand,
