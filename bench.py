@@ -49,6 +49,32 @@ def cpu_baseline_worker(scale, batch, nbatches, out):
     out["oracle"] = o
 
 
+class _Drawn:
+    def __init__(self, n):
+        self.n = n
+
+
+class _Batch:
+    def __init__(self, ins, dels, chg):
+        self.ins, self.dels, self.chg = ins, dels, chg
+        self.size = len(ins) + len(dels) + len(chg)
+
+
+def _mix_graph_inputs(job):
+    """One graph of the uneven mix and its first `steps` batches (sizes log-uniform in [10, 10^5],
+    clipped to half its edges and to `max_batch`), drawn in a worker process."""
+    import synth
+
+    g, max_exp, steps, max_batch = job
+    s, bs = synth.planted_mix_graph(g, nmin_exp=3.0, nmax_exp=max_exp)
+    e = s.edges()
+    out = []
+    for b in bs[:steps]:
+        x = s.batch(min(b, max(1, s.num_edges() // 2), max_batch))
+        out.append((x.ins, x.dels, x.chg))
+    return s.n, e, out
+
+
 def run_mix(args):
     """Uneven multi-graph mix: graphs of log-uniform size with their own batch streams of
     log-uniform batch size; plain = each graph's batches applied one call at a time, graph
@@ -60,14 +86,18 @@ def run_mix(args):
     import paper_2502_18497_amd as ldl
     import synth
 
-    rng = np.random.default_rng(synth.BASE_SEED + 4)
-    streams, sizes = [], []
-    for g in range(args.graphs):
-        s, bs = synth.planted_mix_graph(g, nmin_exp=3.0, nmax_exp=args.mix_max_exp)
-        streams.append(s)
-        sizes.append([min(b, max(1, s.num_edges() // 2), args.mix_max_batch) for b in bs[:args.steps]])
-    edges = [s.edges() for s in streams]
-    batches = [[st.batch(b) for b in sz] for st, sz in zip(streams, sizes)]
+    t0 = time.perf_counter()
+    # every graph and its batches are drawn in worker processes (the host generator is serial per
+    # graph); the seeds are per graph, so the inputs do not depend on the number of workers
+    from concurrent.futures import ProcessPoolExecutor
+
+    jobs = [(g, args.mix_max_exp, args.steps, args.mix_max_batch) for g in range(args.graphs)]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        drawn = list(ex.map(_mix_graph_inputs, jobs))
+    streams = [_Drawn(n) for n, _, _ in drawn]
+    edges = [e for _, e, _ in drawn]
+    batches = [[_Batch(*b) for b in bl] for _, _, bl in drawn]
+    log(f"drew {len(drawn)} graphs ({sum(len(e) for e in edges)} edges) in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     plain = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
     batched = [ldl.Graph(s.n, e) for s, e in zip(streams, edges)]
@@ -183,6 +213,127 @@ def run_serve(args):
                       "batch": "lognormal median 1e3 sigma 1.5", "updates": updates},
            "plain_fifo_edges_per_s": updates / t_plain, "served_vs_plain": best["edges_per_s"] / (updates / t_plain),
            "identical_to_plain": bool(final_same), "sweep": results}
+    print(json.dumps(out), flush=True)
+
+
+def _serve_graph_inputs(job):
+    """One resident graph of the serving mix and its requests' batches, drawn in a worker process:
+    kind 0 an undirected R-MAT of 2^scale vertices with average degree 16 and weights 1..16, kind 1
+    a directed planted partition of n vertices (blocks of 100, average degree 12, mixing 0.3,
+    weights 1..16); sizes are the update counts of its requests in arrival order."""
+    import synth
+
+    g, kind, size_param, sizes = job
+    if kind == 0:
+        s = synth.rmat_undirected(scale=size_param, seed_offset=6 + 1000 * g)
+    else:
+        n = size_param
+        s = synth.Stream(n, True, synth.BASE_SEED + 6 + 1000 * g)
+        s.planted(100, 0.7 * 12 / 99, 0.3 * 12 / (n - 100), 1, 16)
+    e = s.edges()
+    out = []
+    for k in sizes:
+        b = s.batch(min(k, max(1, s.num_edges() // 4)))
+        out.append((b.ins, b.dels, b.chg))
+    return s.n, bool(kind), e, out
+
+
+def run_serve_mix(args):
+    """The serving form at a reduced size of its stated shape: 32 resident graphs, 16 undirected
+    R-MAT graphs of scales drawn from [--serve-scale-lo, --serve-scale-hi] and 16 directed planted
+    partitions with n log-uniform in [--serve-planted-lo, --serve-planted-hi], requests arriving as
+    a Poisson stream over uniformly chosen graphs, batch sizes lognormal (median 10^3, sigma 1.5,
+    clipped to [1, 10^6] and to a quarter of the graph's edges), 70/20/10 updates.  Plain = one
+    thread applying the requests in arrival order; served = ldl_server_* at several offered rates
+    (multiples of the plain path's saturation rate); latency = arrival to completion.  Every
+    graph's final state must equal its plain state."""
+    import math
+
+    import numpy as np
+    import torch  # noqa: F401
+
+    import paper_2502_18497_amd as ldl
+    import synth
+
+    from concurrent.futures import ProcessPoolExecutor
+
+    rng = np.random.default_rng(synth.BASE_SEED + 5)
+    kinds, params = [], []
+    for g in range(32):
+        if g % 2 == 0:
+            kinds.append(0)
+            params.append(int(rng.integers(args.serve_scale_lo, args.serve_scale_hi + 1)))
+        else:
+            kinds.append(1)
+            params.append(100 * round(10 ** rng.uniform(math.log10(args.serve_planted_lo),
+                                                         math.log10(args.serve_planted_hi)) / 100))
+    nreq = args.requests
+    req_graph = [int(rng.integers(0, 32)) for _ in range(nreq)]
+    req_size = [synth.lognormal_int(rng, 1000.0, 1.5, 1, 1_000_000) for _ in range(nreq)]
+    per_graph = [[req_size[i] for i in range(nreq) if req_graph[i] == g] for g in range(32)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        drawn = list(ex.map(_serve_graph_inputs, [(g, kinds[g], params[g], per_graph[g]) for g in range(32)]))
+    total_edges = sum(len(d[2]) for d in drawn)
+    log(f"drew 32 graphs ({sum(d[0] for d in drawn)} vertices, {total_edges} edges) in {time.perf_counter() - t0:.1f}s")
+    cursor = [0] * 32
+    reqs = []
+    for g in req_graph:
+        reqs.append((g, _Batch(*drawn[g][3][cursor[g]])))
+        cursor[g] += 1
+    updates = sum(b.size for _, b in reqs)
+
+    def make_graphs():
+        return [ldl.Graph(d[0], d[2], directed=d[1]) for d in drawn]
+
+    plain = make_graphs()
+    t0 = time.perf_counter()
+    for g, b in reqs:
+        plain[g].apply_batch(b.ins, b.dels, b.chg)
+    t_plain = time.perf_counter() - t0
+    final = [(p.partition(), p.qnum()) for p in plain]
+    for p in plain:
+        p.close()
+    sat = nreq / t_plain
+    results, same = [], True
+    for frac in args.rates:
+        served = make_graphs()
+        srv = ldl.Server(workers=args.workers, mem_budget_bytes=args.mem_budget)
+        arrivals = np.cumsum(rng.exponential(1.0 / (frac * sat), nreq))
+        t0 = time.perf_counter()
+        tickets = []
+        for (g, b), at in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if at > now:
+                time.sleep(at - now)
+            tickets.append(srv.submit(served[g], b.ins, b.dels, b.chg))
+        lat = []
+        for t in tickets:
+            rc, _, ms = srv.wait(t)
+            assert rc == 0
+            lat.append(ms)
+        t_all = time.perf_counter() - t0
+        srv.close()
+        same &= all(np.array_equal(f[0], x.partition()) and f[1] == x.qnum() for f, x in zip(final, served))
+        for x in served:
+            x.close()
+        results.append({"offered_x_plain_saturation": frac, "requests_per_s": nreq / t_all,
+                        "edges_per_s": updates / t_all, "p50_ms": float(np.percentile(lat, 50)),
+                        "p99_ms": float(np.percentile(lat, 99))})
+        log(f"rate {frac:.2f}x: {results[-1]}")
+    best = max(results, key=lambda r: r["edges_per_s"])
+    out = {"metric": "batch edges/s, frontier GB/s vs HBM peak; batched vs plain; p99 latency",
+           "value": best["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": nreq, "warmup": 0,
+           "ms_per_step": 1e3 / best["requests_per_s"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"serve-32-graphs-{total_edges}-edges",
+                      "rmat_undirected_scales": [p for k, p in zip(kinds, params) if k == 0],
+                      "planted_directed_n": [p for k, p in zip(kinds, params) if k == 1],
+                      "vertices": sum(d[0] for d in drawn), "edges": total_edges, "requests": nreq,
+                      "workers": args.workers, "mem_budget": args.mem_budget,
+                      "batch": "lognormal median 1e3 sigma 1.5, clipped to [1, 1e6]", "updates": updates},
+           "plain_fifo_edges_per_s": updates / t_plain, "served_vs_plain": best["edges_per_s"] / (updates / t_plain),
+           "identical_to_plain": bool(same), "sweep": results}
     print(json.dumps(out), flush=True)
 
 
@@ -786,7 +937,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the degree bins before the timed batches")
     ap.add_argument("--workload", choices=["rmat", "mix", "serve", "copy", "scan", "quality", "sweep", "bigstream",
-                                           "latency", "headline", "pmc-summary"],
+                                           "latency", "headline", "pmc-summary", "serve-mix"],
                     default="headline")
     ap.add_argument("--quality-n", type=int, default=20000)
     ap.add_argument("--quality-mu", type=float, default=0.3)
@@ -808,6 +959,10 @@ def main():
     ap.add_argument("--edges", type=int, default=0, help="scan: edge count (default avg-degree x vertices)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--latency-runs", type=int, default=20)
+    ap.add_argument("--serve-scale-lo", type=int, default=20)
+    ap.add_argument("--serve-scale-hi", type=int, default=23)
+    ap.add_argument("--serve-planted-lo", type=int, default=250000)
+    ap.add_argument("--serve-planted-hi", type=int, default=2500000)
     ap.add_argument("--pmc-kernel", default="", help="pmc-summary: kernel name as in the roofline object")
     ap.add_argument("--pmc-skip", type=int, default=0, help="pmc-summary: the kernel's dispatches before the timed calls")
     ap.add_argument("--pmc-fetch", default="", help="pmc-summary: counter csv of the FETCH_SIZE run")
@@ -847,6 +1002,8 @@ def main():
         return run_latency(args)
     if args.workload == "pmc-summary":
         return pmc_summary(args)
+    if args.workload == "serve-mix":
+        return run_serve_mix(args)
 
     if args.workload == "rmat":
         print(json.dumps(measure_rmat(args)), flush=True)

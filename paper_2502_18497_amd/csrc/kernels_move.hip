@@ -891,20 +891,35 @@ __global__ __launch_bounds__(kTpb) void k_hub_keys(MoveView mv, BinRef br, uint3
       for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) lh[t] = 0;
     __syncthreads();
     int64_t ow = 0;
-    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
-      uint32_t x;
-      int64_t w;
-      entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
-      uint32_t key = entry_key<REF>(mv, v, labv, x);
-      if (!REF && key == labv) {
-        ow += w;
-        key = kEmpty;
+    // four entries per thread at a time: their loads, then their key gathers, then the writes
+    // and counts, so four gathers are in flight before any is used
+    for (uint64_t jb = e0 + threadIdx.x; jb < e1; jb += 4 * (uint64_t)blockDim.x) {
+      uint32_t xs[4], ks[4];
+      int64_t wv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * blockDim.x;
+        xs[k] = v;   // a key of kEmpty for slots past the chunk
+        wv[k] = 0;
+        if (j < e1) entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, xs[k], wv[k]);
       }
-      hub.ekey[base + j] = key;
-      if (key == kEmpty) continue;
-      const uint32_t p = part_of(key, P);
-      if (local) atomicAdd(&lh[p], 1u);
-      else atomicAdd(&hw.pcount[pbase + p], 1u);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ks[k] = entry_key<REF>(mv, v, labv, xs[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * blockDim.x;
+        if (j >= e1) continue;
+        uint32_t key = ks[k];
+        if (!REF && key == labv) {
+          ow += wv[k];
+          key = kEmpty;
+        }
+        hub.ekey[base + j] = key;
+        if (key == kEmpty) continue;
+        const uint32_t p = part_of(key, P);
+        if (local) atomicAdd(&lh[p], 1u);
+        else atomicAdd(&hw.pcount[pbase + p], 1u);
+      }
     }
     __syncthreads();
     if (local)
@@ -992,17 +1007,31 @@ __global__ __launch_bounds__(kTpb) void k_hub_scatter(MoveView mv, BinRef br, ui
       }
       __syncthreads();
     }
-    for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
-      const uint32_t key = hub.ekey[base + j];
-      if (key == kEmpty) continue;
-      uint32_t x;
-      int64_t w;
-      entry_at<WT, DIR>(mv, oo, dout, oi, (uint32_t)j, x, w);
-      const uint32_t p = part_of(key, P);
-      const uint32_t at = local ? lb[p] + atomicAdd(&lh[p], 1u) : atomicAdd(&hw.pcur[pbase + p], 1u);
-      const uint64_t pos = hw.poff[pbase + p] + at;
-      hub.bkey[pos] = key;
-      hub.bw[pos] = w;
+    // four entries per thread at a time: keys and weights loaded together, then placed
+    for (uint64_t jb = e0 + threadIdx.x; jb < e1; jb += 4 * (uint64_t)blockDim.x) {
+      uint32_t ks[4];
+      int64_t wv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * blockDim.x;
+        ks[k] = kEmpty;
+        wv[k] = 0;
+        if (j < e1) {
+          ks[k] = hub.ekey[base + j];
+          const bool in_out = !DIR || j < dout;
+          wv[k] = in_out ? wload<WT>(mv.out, oo + j) : wload<WT>(mv.in, oi + (j - dout));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t key = ks[k];
+        if (key == kEmpty) continue;
+        const uint32_t p = part_of(key, P);
+        const uint32_t at = local ? lb[p] + atomicAdd(&lh[p], 1u) : atomicAdd(&hw.pcur[pbase + p], 1u);
+        const uint64_t pos = hw.poff[pbase + p] + at;
+        hub.bkey[pos] = key;
+        hub.bw[pos] = wv[k];
+      }
     }
     __syncthreads();
   }
@@ -1036,20 +1065,37 @@ __global__ __launch_bounds__(kTpb) void k_hub_part(MoveView mv, BinRef br, uint3
     }
     if (threadIdx.x == 0) s_over = 0;
     __syncthreads();
-    for (uint64_t j = threadIdx.x; j < nb; j += blockDim.x) {
-      const uint32_t key = hub.bkey[b0 + j];
-      uint32_t slot = hash32(key) & mask;
-      uint32_t probes = 0;
-      for (;;) {
-        const uint32_t prev = atomicCAS(&tk[slot], kEmpty, key);
-        if (prev == kEmpty || prev == key) {
-          atomicAdd(&tv[slot], (u64a)hub.bw[b0 + j]);
-          break;
+    // four bucket entries per thread at a time: keys and weights loaded together, then inserted
+    for (uint64_t jb = threadIdx.x; jb < nb; jb += 4 * (uint64_t)blockDim.x) {
+      uint32_t ks[4];
+      int64_t wv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t j = jb + (uint64_t)k * blockDim.x;
+        ks[k] = kEmpty;
+        wv[k] = 0;
+        if (j < nb) {
+          ks[k] = hub.bkey[b0 + j];
+          wv[k] = hub.bw[b0 + j];
         }
-        slot = (slot + 1) & mask;
-        if (++probes == size) {   // table full: more distinct keys than slots
-          s_over = 1;
-          break;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t key = ks[k];
+        if (key == kEmpty) continue;
+        uint32_t slot = hash32(key) & mask;
+        uint32_t probes = 0;
+        for (;;) {
+          const uint32_t prev = atomicCAS(&tk[slot], kEmpty, key);
+          if (prev == kEmpty || prev == key) {
+            atomicAdd(&tv[slot], (u64a)wv[k]);
+            break;
+          }
+          slot = (slot + 1) & mask;
+          if (++probes == size) {   // table full: more distinct keys than slots
+            s_over = 1;
+            break;
+          }
         }
       }
     }
