@@ -19,6 +19,7 @@ _SRC = os.path.join(_HERE, "ldl_oracle.cpp")
 FLAG_SINGLE_MOVE = 1
 FLAG_CHECK_MOVES = 2
 FLAG_TRACE = 4
+FLAG_EMPTY_TARGET = 8   # variant: BestMove may move a vertex to the empty community labelled by its id
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOEDGE", -4: "EOVERFLOW", -100: "ECHECK"}
 
@@ -97,8 +98,10 @@ class Oracle:
     """Plain LD-Leiden state.  ``create`` runs static Leiden (the batch update applied to the
     empty singleton state)."""
 
-    def __init__(self, n, edges, directed=False, flags=0, refresh=(0, 1), **cfg):
+    def __init__(self, n, edges, directed=False, flags=0, refresh=(0, 1), empty_target=False, **cfg):
         self.lib = _load()
+        if empty_target:
+            flags |= FLAG_EMPTY_TARGET
         self.n = int(n)
         self.directed = bool(directed)
         self.cfg = cfg_array(directed, **cfg)
@@ -183,11 +186,13 @@ class Oracle:
 
     def check_counts(self) -> dict:
         """Recount checks done under FLAG_CHECK_MOVES: move and refinement commits, and the
-        single-move commits whose predicted gain was compared with the recount."""
-        out = np.zeros(4, dtype=np.uint64)
+        single-move commits whose predicted gain was compared with the recount; empty-target
+        moves accepted (FLAG_EMPTY_TARGET, counted with or without checks) and the single-move
+        commits among them that were compared with the recount."""
+        out = np.zeros(6, dtype=np.uint64)
         self.lib.orc_check_counts(self.h, out.ctypes.data)
         return {"move": int(out[0]), "refine": int(out[1]), "move_single": int(out[2]),
-                "refine_single": int(out[3])}
+                "refine_single": int(out[3]), "empty_moves": int(out[4]), "empty_single": int(out[5])}
 
     def trace(self) -> np.ndarray:
         k = int(self.lib.orc_trace_len(self.h))

@@ -74,6 +74,7 @@ struct NodeSet {
 struct Cand {
   uint32_t v, a, b;
   i128 G;
+  bool empty = false;   // b is the empty community labelled v (variant, see best_move)
 };
 
 struct TraceRec {
@@ -145,8 +146,11 @@ struct Oracle {
   // debugging / checking modes
   int single_move = 0;            // accept only the best candidate per move iteration
   int check_moves = 0;            // recount Q from scratch around every move and refinement commit
-  uint64_t checks[4] = {0, 0, 0, 0};   // recount checks done: moves, refinements, and of those
-                                       // the single-move ones that compared a predicted gain
+  int empty_target = 0;           // variant: BestMove may also move v to an empty community
+  uint64_t checks[6] = {0, 0, 0, 0, 0, 0};   // recount checks done: moves, refinements, and of those
+                                             // the single-move ones that compared a predicted gain;
+                                             // empty-target moves accepted, and of those the
+                                             // single-move ones compared with a recount
   std::string err;
   std::vector<TraceRec> trace;
   int tracing = 0;
@@ -263,6 +267,13 @@ struct Oracle {
   // ------------------------------------------------------------------- candidates
   // BestMove_r (Sec. III-D): best adjacent community by the exact gain, ties to the lowest
   // community id, kept only if the gain is strictly positive.
+  //
+  // Variant (empty_target; the paper considers adjacent communities only, Sec. III-C): v may
+  // also move to an empty community, as in the Louvain and Leiden move phases.  The empty
+  // community offered to v is the one labelled v itself, when v does not carry label v and the
+  // totals of community v are zero (every member, if any, has no incident weight, so the move's
+  // gain is that of moving to an empty community: no weight towards it and zero totals).  It is
+  // one more candidate with its own id in the comparison above.
   bool best_move(int r, uint32_t v, Cand& out) {
     const Level& L = lv[r];
     const uint32_t a = L.lab[v];
@@ -292,8 +303,18 @@ struct Oracle {
       if (!found || G > bestG || (G == bestG && b < bestb)) { found = true; bestG = G; bestb = b; }
     }
     for (uint32_t b : acc_touched) acc_flag[b] = 0;
+    bool empty = false;
+    if (empty_target && a != v && Kout[v] == 0 && Kin[v] == 0) {
+      // the gain above with acc[b] = 0 and Kout[b] = Kin[b] = 0
+      i128 G;
+      if (cfg.directed)
+        G = -qm * acc_a - (i128)cfg.gp * ((i128)L.kout[v] * (L.kin[v] - Kin[a]) + (i128)L.kin[v] * (L.kout[v] - Kout[a]));
+      else
+        G = -qm * acc_a - (i128)cfg.gp * ((i128)L.kout[v] * (L.kout[v] - Kout[a]));
+      if (!found || G > bestG || (G == bestG && v < bestb)) { found = true; bestG = G; bestb = v; empty = true; }
+    }
     if (!found || bestG <= 0) return false;
-    out.v = v; out.a = a; out.b = bestb; out.G = bestG;
+    out.v = v; out.a = a; out.b = bestb; out.G = bestG; out.empty = empty;
     return true;
   }
 
@@ -422,6 +443,7 @@ struct Oracle {
       std::vector<Cand> cands;
       for (uint32_t v : S.list) { Cand c; if (best_move(r, v, c)) cands.push_back(c); }
       std::vector<Cand> B = decouple(cands, single_move != 0);
+      for (auto& c : B) checks[4] += c.empty ? 1 : 0;
       i128 before = 0;
       if (check_moves) before = recount_qnum(r);
       i128 dq = commit_moves(r, B);
@@ -432,6 +454,7 @@ struct Oracle {
           i128 expect = cfg.directed ? B[0].G : 2 * B[0].G;
           if (dq != expect && err.empty()) err = "single-move gain differs from predicted gain";
           checks[2]++;
+          checks[5] += B[0].empty ? 1 : 0;
         }
         if (qnum() != after && err.empty()) err = "maintained Q numerator differs from recount";
         checks[0]++;
@@ -834,6 +857,7 @@ int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t
   o->single_move = (flags & 1) != 0;
   o->check_moves = (flags & 2) != 0;
   o->tracing = (flags & 4) != 0;
+  o->empty_target = (flags & 8) != 0;
   o->lv.resize(c.L + 1);
   o->alloc_level(0);
   for (uint32_t u = 0; u < n; ++u) o->lv[0].alive[u] = 1;
@@ -935,9 +959,9 @@ int orc_check(void* h, char* msg, int cap) {
 
 // Recount checks done so far (FLAG_CHECK_MOVES): [0] move commits, [1] refinement commits,
 // [2] single-move move commits compared with their predicted gain, [3] likewise for refinement.
-void orc_check_counts(void* h, uint64_t* out4) {
+void orc_check_counts(void* h, uint64_t* out6) {
   Oracle* o = (Oracle*)h;
-  for (int i = 0; i < 4; ++i) out4[i] = o->checks[i];
+  for (int i = 0; i < 6; ++i) out6[i] = o->checks[i];
 }
 
 uint64_t orc_trace_len(void* h) { return ((Oracle*)h)->trace.size(); }

@@ -497,3 +497,65 @@ def test_adaptive_refresh_threshold_is_exact():
             a0 = r[4]
     # rho = 1 refreshes only when the closure is all 400 vertices
     assert (a0 == 400) == (o0.refreshes() == 1)
+
+
+def _loop_batches(stream, rng, n, steps, loops_per_step=6, size=16):
+    """Batches of the stream's own updates plus heavy self-loops on distinct vertices (never
+    drawn by the generator): a heavy loop raises a vertex's degree until staying in its
+    community costs more than it gains, which is when an empty community becomes its best
+    target."""
+    picks = rng.choice(n, steps * loops_per_step, replace=False)
+    out = []
+    for k in range(steps):
+        b = stream.batch(size, f_ins=0.4, f_del=0.5)
+        loops = np.array([(int(x), int(x), int(rng.integers(20, 200)))
+                          for x in picks[k * loops_per_step:(k + 1) * loops_per_step]], np.uint32)
+        out.append((np.concatenate([b.ins, loops]) if len(b.ins) else loops, b.dels, b.chg))
+    return out
+
+
+@pytest.mark.parametrize("gamma", [(1, 1), (3, 2), (2, 1)], ids=["g1", "g3/2", "g2"])
+@pytest.mark.parametrize("directed", [False, True])
+def test_every_empty_target_move_matches_recount(directed, gamma):
+    """Empty-community target (a variant of BestMove): in single-move mode every commit of a
+    move to the empty community labelled v changes Eq. 1, recounted from scratch, by exactly the
+    predicted gain -q m acc_a - p (kout_v (kin_v - Kin_a) + kin_v (kout_v - Kout_a)) (undirected:
+    twice -q m acc_a - p k_v (k_v - K_a)).  A target that is not really empty (nonzero totals), a
+    dropped own-community term or a sign slip fails the recount; the counts show that such moves
+    were taken and checked."""
+    rng = np.random.default_rng(41 + directed + 7 * gamma[0])
+    total = {"empty_moves": 0, "empty_single": 0}
+    for trial in range(3):
+        n = 60 + 20 * trial
+        s = synth.Stream(n, directed, synth.BASE_SEED + 900 + 10 * trial + directed)
+        s.planted(10, 0.35, 0.04, 1, 8)
+        flags = oracle.FLAG_CHECK_MOVES | oracle.FLAG_SINGLE_MOVE
+        o = oracle.Oracle(n, s.edges(), directed=directed, flags=flags, gamma=gamma, L=2, empty_target=True)
+        assert o.last_rc == 0, o.check()
+        for ins, dels, chg in _loop_batches(s, rng, n, 4):
+            assert o.apply_batch(ins, dels, chg) == 0, o.check()
+        assert o.check() == ""
+        c = o.check_counts()
+        for k in total:
+            total[k] += c[k]
+    assert total["empty_single"] >= 10, total
+    assert total["empty_moves"] == total["empty_single"]
+
+
+def test_empty_target_off_is_the_paper_method():
+    """Without the variant no move goes to an empty community, and the same stream gives a
+    different (but valid) state once the variant takes such a move."""
+    n = 80
+    results = []
+    for empty in (False, True):
+        s = synth.Stream(n, False, synth.BASE_SEED + 920)
+        s.planted(10, 0.35, 0.04, 1, 8)
+        o = oracle.Oracle(n, s.edges(), L=2, empty_target=empty)
+        r = np.random.default_rng(43)
+        for ins, dels, chg in _loop_batches(s, r, n, 4):
+            assert o.apply_batch(ins, dels, chg) == 0
+        assert o.check() == ""
+        results.append((o.partition(), o.check_counts()["empty_moves"]))
+    assert results[0][1] == 0
+    assert results[1][1] > 0
+    assert not np.array_equal(results[0][0], results[1][0])
