@@ -80,6 +80,14 @@ typedef struct ldl_pair {
  *                       num in [0, 65535], den in [1, 65535]
  *   alloc/free/alloc_ctx device allocator hook (see ldl_alloc_fn); NULL for hipMalloc / hipFree.
  *                       One of the two set without the other is LDL_EINVAL.
+ *   empty_target        0 or 1 (a variant, off by default).  The paper's BestMove considers the
+ *                       communities adjacent to v only (Sec. III-C).  With 1 it also considers an
+ *                       empty community, as the Louvain and Leiden move phases do: the community
+ *                       labelled v itself, offered when v does not carry label v and that
+ *                       community's totals Kout, Kin are zero (so no weight leads to it and the
+ *                       gain of Eq. 2 is that of an empty target).  It is one more candidate in the
+ *                       comparison (larger exact gain, equal gains to the lower id); refinement
+ *                       is unchanged.
  *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
  *                       results unchanged: 1 = one decoupling round between host checks (second
  *                       commit phase), 2 = minimal hub bucket pool (overflow and redo of an
@@ -116,6 +124,7 @@ typedef struct ldl_config {
   ldl_alloc_fn alloc;   /* both set: every device allocation of the handle goes through them; */
   ldl_free_fn free;     /* both NULL: hipMalloc / hipFree                                      */
   void* alloc_ctx;
+  int32_t empty_target;
 } ldl_config;
 
 /* Per-call statistics (all counts summed over the call). */
@@ -197,6 +206,14 @@ int ldl_modularity(const ldl_handle* h, double* q);
  * denominator q*m^2 likewise; Q = num / den. */
 int ldl_modularity_exact(const ldl_handle* h, int64_t* num_hi, uint64_t* num_lo, int64_t* den_hi,
                          uint64_t* den_lo);
+
+/* Free the handle's growable scratch: aggregation tuples, reduced records, sorted entries,
+ * row-update buffers and the sort and scan primitives' temporary storage, all of which a batch
+ * call grows to its own size and keeps for the next call.  The next call that needs them
+ * allocates them again; the state and every later result are unchanged.  ldl_create and
+ * ldl_import_state end with it (static Leiden's scratch is sized for the whole graph), so a
+ * resident handle holds its state plus what its batches use.  LDL_EINVAL for NULL. */
+int ldl_release_scratch(ldl_handle* h);
 
 /* Release every device resource of the handle.  NULL is ignored. */
 void ldl_destroy(ldl_handle* h);

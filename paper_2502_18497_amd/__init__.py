@@ -33,7 +33,7 @@ class ldl_config(ctypes.Structure):
                 ("beta_den", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32), ("refresh_num", ctypes.c_int32),
                 ("refresh_den", ctypes.c_int32), ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p),
-                ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc_ctx", ctypes.c_void_p), ("empty_target", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p)
@@ -105,6 +105,7 @@ ABI_SYMBOLS = ("ldl_default_config", "ldl_create", "ldl_apply_batch", "ldl_apply
                "ldl_export_level", "ldl_level_nnz", "ldl_export_entries", "ldl_set_trace", "ldl_trace_len",
                "ldl_trace", "ldl_apply_batches", "ldl_server_create", "ldl_server_submit", "ldl_server_wait",
                "ldl_server_drain", "ldl_server_destroy", "ldl_get_bins", "ldl_set_bins", "ldl_autotune",
+               "ldl_release_scratch",
                "ldl_strerror", "ldl_version", "ldl_get_partition_device", "ldl_export_state", "ldl_import_state",
                "ldl_check_invariants", "ldl_check_invariants_noalloc", "ldl_memory")
 
@@ -203,6 +204,8 @@ def load_library():
     lib.ldl_get_partition_device.restype = i32
     lib.ldl_memory.argtypes = [vp, P(u64), P(u64)]
     lib.ldl_memory.restype = i32
+    lib.ldl_release_scratch.argtypes = [vp]
+    lib.ldl_release_scratch.restype = i32
     lib.ldl_export_state.argtypes = [vp, vp, u64, P(u64)]
     lib.ldl_export_state.restype = i32
     lib.ldl_import_state.argtypes = [P(ldl_config), vp, u64, P(vp)]
@@ -235,7 +238,8 @@ class Graph:
     edges; ``apply_batch`` runs one batch update (Algorithm 1)."""
 
     def __init__(self, n, edges, directed=False, gamma=(1, 1), N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100),
-                 device=0, stream=None, profile=False, test_flags=0, refresh=(0, 1), allocator=None):
+                 device=0, stream=None, profile=False, test_flags=0, refresh=(0, 1), allocator=None,
+                 empty_target=False):
         self.lib = load_library()
         c = ldl_default_config()
         c.directed, c.gamma_num, c.gamma_den = int(directed), gamma[0], gamma[1]
@@ -246,6 +250,7 @@ class Graph:
         c.profile = int(bool(profile))
         c.test_flags = int(test_flags)
         c.refresh_num, c.refresh_den = int(refresh[0]), int(refresh[1])
+        c.empty_target = int(bool(empty_target))
         self.allocator = allocator   # kept alive as long as the handle (its callbacks are called)
         if allocator is not None:
             allocator.install(c)
@@ -274,8 +279,8 @@ class Graph:
         g.lib = lib
         g.h = h.value
         hdr = np.frombuffer(bytes(blob[:80]), dtype=np.uint8)
-        cfg = hdr[16:64].view(np.int32)
-        g.n = int(hdr[64:68].view(np.uint32)[0])
+        cfg = hdr[16:72].view(np.int32)
+        g.n = int(hdr[72:76].view(np.uint32)[0])
         g.directed = bool(cfg[0])
         g.L = int(cfg[4])
         return g
@@ -287,6 +292,12 @@ class Graph:
         if rc != LDL_OK:
             raise LdlError(rc, "ldl_memory")
         return {"held": held.value, "recent_growth": growth.value}
+
+    def release_scratch(self):
+        """Free the handle's growable scratch buffers (ldl_release_scratch); results unchanged."""
+        rc = self.lib.ldl_release_scratch(self.h)
+        if rc != LDL_OK:
+            raise LdlError(rc, "ldl_release_scratch")
 
     def export_state(self) -> bytes:
         """The whole state as an opaque blob (ldl_export_state)."""

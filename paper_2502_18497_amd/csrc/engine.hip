@@ -143,6 +143,7 @@ struct Engine {
   int N = 2, L = 4, M = 5;
   int64_t an = 1, ad = 1000, bn = 1, bd = 100;
   int64_t rn = 0, rd = 1;   // adaptive refresh threshold (0: never)
+  int empty_target = 0;     // BestMove may also target the empty community labelled by the vertex
   int device = 0;
   int profile = 0;
   int test_flags = 0;   // see ldl_config
@@ -402,6 +403,7 @@ struct Engine {
     N = c.N; L = c.L; M = c.M;
     an = c.alpha_num; ad = c.alpha_den; bn = c.beta_num; bd = c.beta_den;
     rn = c.refresh_num; rd = c.refresh_den;
+    empty_target = c.empty_target;
     halloc = c.alloc;
     hfree = c.free;
     hctx = c.alloc_ctx;
@@ -614,6 +616,25 @@ struct Engine {
     regrow(tk0, c); regrow(tk1, c); regrow(tk2, c); regrow(tv0, c); regrow(tv1, c); regrow(tv2, c);
     regrow(tx, c); regrow(ty, c);
     tup_cap = c;
+  }
+  // Free the growable scratch (aggregation tuples, reduced records, sorted entries, row-update
+  // buffers, the library primitives' temporary storage); the next call that needs them allocates
+  // them again at its own size.  The state is untouched.
+  void release_scratch() {
+    hcheck(hipStreamSynchronize(st));
+    for (void** p : {(void**)&tk0, (void**)&tk1, (void**)&tk2, (void**)&tv0, (void**)&tv1, (void**)&tv2,
+                     (void**)&tx, (void**)&ty, (void**)&rkey0, (void**)&rkey1, (void**)&ridx0, (void**)&ridx1,
+                     (void**)&rdelta, (void**)&rslot, (void**)&ekey0, (void**)&ekey1, (void**)&edel0,
+                     (void**)&edel1, (void**)&ex, (void**)&ey, (void**)&insflag, (void**)&holebuf,
+                     (void**)&movelist, (void**)&seg_lo, (void**)&seg_hi, (void**)&items, (void**)&item_off,
+                     (void**)&items_big, (void**)&item_off_big, (void**)&slotbuf}) {
+      release(*p);
+      *p = nullptr;
+    }
+    tup_cap = rec_cap = ent_cap = ins_cap = 0;
+    prim_free_tmp(cub_tmp, cub_bytes);
+    cub_tmp = nullptr;
+    cub_bytes = 0;
   }
   void cub(int rc) {
     if (rc == -2) throw NoMem{};
@@ -1004,6 +1025,7 @@ struct Engine {
     mv.qm = gq * m;
     mv.p = gp;
     mv.directed = directed;
+    mv.empty_target = refine ? 0 : empty_target;
     for (int b = 0; b < kNumBins - 1; ++b) mv.lim[b] = lim[V.out.ref.wide][b];
     return mv;
   }
@@ -1800,7 +1822,8 @@ struct Engine {
   struct StateHeader {
     char magic[8];
     uint32_t version, header_bytes;
-    int32_t cfg[12];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den, refresh num, den
+    int32_t cfg[14];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den, refresh num, den,
+                       // empty target, 0
     uint32_t n;
     int32_t top;
     int64_t m, ein, skk_hi;
@@ -1808,7 +1831,7 @@ struct Engine {
     uint32_t lim[2][5];
     uint64_t total_bytes;
   };
-  static constexpr uint32_t kStateVersion = 2;
+  static constexpr uint32_t kStateVersion = 3;
   uint64_t level_node_bytes(int r) const {
     return (uint64_t)n * (1 + 4 + (r < L ? 8 : 0) + 8 + (directed ? 8 : 0) + 4) + 8;
   }
@@ -1836,9 +1859,9 @@ struct Engine {
     std::memcpy(hd.magic, "LDLSTATE", 8);
     hd.version = kStateVersion;
     hd.header_bytes = sizeof(StateHeader);
-    const int32_t c12[12] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
-                             (int32_t)bd, (int32_t)rn, (int32_t)rd};
-    std::memcpy(hd.cfg, c12, sizeof(c12));
+    const int32_t c14[14] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
+                             (int32_t)bd, (int32_t)rn, (int32_t)rd, empty_target, 0};
+    std::memcpy(hd.cfg, c14, sizeof(c14));
     hd.n = n;
     hd.top = top;
     hd.m = m;
@@ -2037,6 +2060,7 @@ bool cfg_ok(const ldl_config& c) {
   return in16(c.gamma_num, 1) && in16(c.gamma_den, 1) && c.N >= 1 && c.M >= 1 && c.L >= 0 && c.L <= 16 &&
          in16(c.alpha_num, 0) && in16(c.alpha_den, 1) && in16(c.beta_num, 0) && in16(c.beta_den, 1) &&
          in16(c.refresh_num, 0) && in16(c.refresh_den, 1) && (c.directed == 0 || c.directed == 1) &&
+         (c.empty_target == 0 || c.empty_target == 1) &&
          ((c.alloc == nullptr) == (c.free == nullptr));
 }
 
@@ -2114,6 +2138,7 @@ void ldl_default_config(ldl_config* c) {
   c->alloc = nullptr;
   c->free = nullptr;
   c->alloc_ctx = nullptr;
+  c->empty_target = 0;
 }
 
 int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_t n_edges, ldl_handle** out) {
@@ -2135,6 +2160,8 @@ int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_
     return LDL_OK;
   });
   if (rc == LDL_OK) rc = apply_common(h, edges, n_edges, nullptr, 0, nullptr, 0, nullptr, false);
+  // static Leiden's scratch is sized for the whole graph; batches regrow what they need
+  if (rc == LDL_OK) rc = ldl_release_scratch(h);
   if (rc != LDL_OK) {
     delete h->e;
     delete h;
@@ -2142,6 +2169,16 @@ int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_
   }
   *out = h;
   return LDL_OK;
+}
+
+int ldl_release_scratch(ldl_handle* h) {
+  if (!h) return LDL_EINVAL;
+  if (h->e->broken) return LDL_EBROKEN;
+  return run_guarded(h, [&]() -> int {
+    ldl::hcheck(hipSetDevice(h->e->device));
+    h->e->release_scratch();
+    return LDL_OK;
+  });
 }
 
 int ldl_apply_batch(ldl_handle* h, const ldl_edge* ins, uint64_t n_ins, const ldl_pair* del, uint64_t n_del,
@@ -2318,7 +2355,8 @@ int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl
   c.alpha_num = hd.cfg[6]; c.alpha_den = hd.cfg[7];
   c.beta_num = hd.cfg[8]; c.beta_den = hd.cfg[9];
   c.refresh_num = hd.cfg[10]; c.refresh_den = hd.cfg[11];
-  if (!cfg_ok(c)) return LDL_EINVAL;
+  c.empty_target = hd.cfg[12];
+  if (!cfg_ok(c) || hd.cfg[13] != 0) return LDL_EINVAL;
   ldl_handle* h = new (std::nothrow) ldl_handle;
   if (!h) return LDL_ENOMEM;
   h->e = new (std::nothrow) ldl::Engine();
@@ -2328,7 +2366,9 @@ int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl
   }
   int rc = run_guarded(h, [&]() -> int {
     h->e->init(c, hd.n);
-    return h->e->import_state((const uint8_t*)blob, size);
+    const int r = h->e->import_state((const uint8_t*)blob, size);
+    if (r == LDL_OK) h->e->release_scratch();
+    return r;
   });
   if (rc != LDL_OK) {
     delete h->e;
@@ -2370,7 +2410,7 @@ int ldl_check_invariants_noalloc(const ldl_handle* h, ldl_invariant_report* repo
 
 int ldl_memory(const ldl_handle* h, uint64_t* held_bytes, uint64_t* recent_growth_bytes) {
   if (!h || !held_bytes || !recent_growth_bytes) return LDL_EINVAL;
-  *held_bytes = h->e->held + h->e->cub_bytes;
+  *held_bytes = h->e->held + (h->e->halloc ? 0 : h->e->cub_bytes);   // with the hook, held counts it
   *recent_growth_bytes = h->e->recent_growth();
   return LDL_OK;
 }

@@ -112,6 +112,17 @@ __device__ __forceinline__ VInfo vinfo(const MoveView& mv, uint32_t v) {
   return vi;
 }
 
+// Variant (mv.empty_target, moves only): the empty community labelled v is one more target when v
+// does not carry label v and that community's totals are zero; its gain is gain_t with no weight
+// towards it and zero totals.  Every lane that calls this with the same arguments gets the same b.
+template <bool DIR, bool REF>
+__device__ __forceinline__ Best with_empty(const MoveView& mv, const VInfo& vi, uint32_t v, int64_t own, Best b) {
+  if (REF || !mv.empty_target || vi.lab == v) return b;
+  if (mv.Kout[v] != 0 || (DIR && mv.Kin[v] != 0)) return b;
+  const Best e = make_best(gain_t<DIR, REF>(mv, vi, 0, 0, 0, own), v);
+  return better(e, b) ? e : b;
+}
+
 __device__ __forceinline__ void emit_cand_at(const CandBuf& cb, uint32_t at, uint32_t v, uint32_t a, const Best& b) {
   cb.v[at] = v;
   cb.a[at] = a;
@@ -418,6 +429,7 @@ __global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, BinRef br, Can
       if (act[u] && li == 0) {
         ls.entries += T[u];
         ls.vertices += 1;
+        b = with_empty<DIR, REF>(mv, vi[u], v[u], own[u], b);
         if (b.valid && best_gain(b) > 0) {
           stage_push(stage, v[u], REF ? v[u] : vi[u].lab, b);
           note_cand(ls, b);
@@ -650,6 +662,7 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
       }
     }
     b = group_best(b, kWave);                 // every lane holds the wavefront's best
+    b = with_empty<DIR, REF>(mv, cur.vi, v, own, b);
     if (lane == 0) {
       ls.entries += cur.dout + cur.din;
       ls.vertices += 1;
@@ -777,6 +790,7 @@ void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
     if (cur.active && li == 0) {
       ls.entries += cur.dout + cur.din;
       ls.vertices += 1;
+      b = with_empty<DIR, REF>(mv, cur.vi, cur.v, own, b);
       if (b.valid && best_gain(b) > 0) {
         stage_push(stage, cur.v, REF ? cur.v : cur.vi.lab, b);
         note_cand(ls, b);
@@ -1116,6 +1130,7 @@ __global__ __launch_bounds__(kTpb) void k_hub_part(MoveView mv, BinRef br, uint3
     nd = team_sum<kTpb>(nd, red_i);
     b = team_best<kTpb>(b, red_b);
     if (threadIdx.x == 0) {
+      if (q == off[i].z) b = with_empty<DIR, REF>(mv, vi, v, ow, b);   // once per hub
       if (s_over) {
         atomicOr(hub.over_count, 4u);
         b.valid = 0;

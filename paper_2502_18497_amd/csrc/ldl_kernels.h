@@ -44,6 +44,7 @@ struct MoveView {
   int64_t qm;                // q * m
   int64_t p;                 // gamma numerator
   int directed;
+  int empty_target;          // move: also offer the empty community labelled v (variant)
   uint32_t lim[5];           // degree-bin limits (entries per vertex), see kBinCap
 };
 

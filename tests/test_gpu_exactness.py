@@ -122,3 +122,34 @@ def test_adaptive_refresh(directed):
         fresh = ldl.Graph(800, cur, directed=directed)
         msgs = diff_states(g.state(), fresh.state())
         assert not msgs, msgs
+
+
+class _Batch:
+    def __init__(self, ins, dels, chg):
+        self.ins, self.dels, self.chg = ins, dels, chg
+
+
+# degree-bin limits that send every vertex to one candidate-kernel family
+_ONLY = {"wave": [[0, 0, 128, 128, 128]] * 2, "hash": [[0, 0, 0, 512, 512]] * 2,
+         "workgroup": [[0, 0, 0, 0, 2048]] * 2, "hub": [[0] * 5] * 2}
+
+
+@pytest.mark.parametrize("kernels", [None, "wave", "hash", "workgroup", "hub"])
+@pytest.mark.parametrize("directed", [False, True])
+def test_empty_target_variant(directed, kernels):
+    """BestMove with the empty-community target (a variant; the oracle's form is pinned by its
+    Eq. 1 recount): a planted partition whose batches add heavy self-loops, so that vertices
+    leave their communities for empty ones.  Bit-identical to the oracle after the load and every
+    batch, with the default bins and with every vertex sent to one kernel family in turn (lane
+    groups and the default mix, wavefronts, LDS hash teams, workgroups, the hub partitions)."""
+    from tests.test_oracle import _loop_batches
+
+    rng = np.random.default_rng(47 + directed)
+    n = 400
+    s = synth.Stream(n, directed, synth.BASE_SEED + 940 + directed)
+    s.planted(20, 0.3, 0.01, 1, 8)
+    e = s.edges()   # before the batches are drawn (drawing advances the stream)
+    batches = [_Batch(*b) for b in _loop_batches(s, rng, n, 5, 24, 60)]
+    bins = None if kernels is None else _ONLY[kernels]
+    g, og = run_parity(n, e, batches, directed=directed, bins=bins, empty_target=True, gamma=(2, 1))
+    assert og.check_counts()["empty_moves"] >= 10

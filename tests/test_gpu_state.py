@@ -11,17 +11,17 @@ from tests.statecheck import diff_states, oracle_state
 
 pytestmark = pytest.mark.gpu
 
-HEADER_BYTES = 152
+HEADER_BYTES = 160
 
 
 def blob_layout(blob: bytes, L: int):
     """Byte offsets of the sections of a state blob (the layout documented with
     ldl_export_state)."""
     hdr = np.frombuffer(blob[:HEADER_BYTES], dtype=np.uint8)
-    cfg = hdr[16:64].view(np.int32)
+    cfg = hdr[16:72].view(np.int32)
     directed = bool(cfg[0])
-    n = int(hdr[64:68].view(np.uint32)[0])
-    top = int(hdr[68:72].view(np.int32)[0])
+    n = int(hdr[72:76].view(np.uint32)[0])
+    top = int(hdr[76:80].view(np.int32)[0])
     off = {"Kout": HEADER_BYTES}
     p = HEADER_BYTES + 8 * n
     if directed:
@@ -243,3 +243,24 @@ def test_memory_report_tracks_held_bytes_and_growth():
     g.apply_batch(b.ins, b.dels, b.chg)
     m1 = g.memory()
     assert m1["recent_growth"] > 0 and m1["held"] >= m0["held"]
+
+
+def test_release_scratch_frees_memory_and_keeps_results():
+    """ldl_release_scratch frees the scratch a batch grew and changes no result: a handle that
+    releases after every batch stays bit-identical to one that keeps its buffers, and a created
+    handle holds no more than its state (creation releases static Leiden's scratch)."""
+    import paper_2502_18497_amd as ldl
+
+    s = synth.rmat_undirected(scale=13, seed_offset=680)
+    e = s.edges()
+    keep, rel = ldl.Graph(s.n, e), ldl.Graph(s.n, e)
+    assert keep.memory()["held"] == rel.memory()["held"]
+    for size in (20000, 300, 5000):
+        b = s.batch(size)
+        keep.apply_batch(b.ins, b.dels, b.chg)
+        rel.apply_batch(b.ins, b.dels, b.chg)
+        grown = rel.memory()["held"]
+        rel.release_scratch()
+        assert rel.memory()["held"] < grown
+        assert not diff_states(keep.state(), rel.state())
+    assert rel.memory()["held"] <= keep.memory()["held"]
