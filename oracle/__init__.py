@@ -20,6 +20,7 @@ FLAG_SINGLE_MOVE = 1
 FLAG_CHECK_MOVES = 2
 FLAG_TRACE = 4
 FLAG_EMPTY_TARGET = 8   # variant: BestMove may move a vertex to the empty community labelled by its id
+FLAG_RANDOM_REFINE = 16   # variant: BestRef draws its target among the improving ones (seeded)
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "EDUP", -3: "ENOEDGE", -4: "EOVERFLOW", -100: "ECHECK"}
 
@@ -44,6 +45,12 @@ def _load():
         vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
         lib.orc_create.restype = i32
         lib.orc_create.argtypes = [vp, u32, vp, u64, i32, ctypes.POINTER(vp)]
+        lib.orc_create_ex.restype = i32
+        lib.orc_create_ex.argtypes = [vp, u32, vp, u64, i32, u64, ctypes.POINTER(vp)]
+        lib.orc_splitmix_mix.restype = u64
+        lib.orc_splitmix_mix.argtypes = [u64]
+        lib.orc_choose_ref.restype = i32
+        lib.orc_choose_ref.argtypes = [i32, u64, u32, u64, vp, vp, vp]
         lib.orc_destroy.argtypes = [vp]
         lib.orc_apply_batch.restype = i32
         lib.orc_apply_batch.argtypes = [vp, vp, u64, vp, u64, vp, u64]
@@ -98,16 +105,20 @@ class Oracle:
     """Plain LD-Leiden state.  ``create`` runs static Leiden (the batch update applied to the
     empty singleton state)."""
 
-    def __init__(self, n, edges, directed=False, flags=0, refresh=(0, 1), empty_target=False, **cfg):
+    def __init__(self, n, edges, directed=False, flags=0, refresh=(0, 1), empty_target=False,
+                 refine_random=False, refine_seed=0, **cfg):
         self.lib = _load()
         if empty_target:
             flags |= FLAG_EMPTY_TARGET
+        if refine_random:
+            flags |= FLAG_RANDOM_REFINE
         self.n = int(n)
         self.directed = bool(directed)
         self.cfg = cfg_array(directed, **cfg)
         e = _arr(edges, np.uint32, 3)
         h = ctypes.c_void_p()
-        rc = self.lib.orc_create(self.cfg.ctypes.data, self.n, e.ctypes.data, len(e), flags, ctypes.byref(h))
+        rc = self.lib.orc_create_ex(self.cfg.ctypes.data, self.n, e.ctypes.data, len(e), flags, int(refine_seed),
+                                    ctypes.byref(h))
         self.h = h.value
         self.last_rc = rc
         if rc not in (0, -100):
@@ -203,6 +214,21 @@ class Oracle:
 
     def trace_clear(self):
         self.lib.orc_trace_clear(self.h)
+
+
+def splitmix_mix(z: int) -> int:
+    """SplitMix64's output function of a 64-bit state (the oracle's counter-based hash)."""
+    return int(_load().orc_splitmix_mix(z & 0xFFFFFFFFFFFFFFFF))
+
+
+def choose_ref(random: bool, key: int, u: int, ys, gains) -> int:
+    """The oracle's BestRef choice among targets ys with exact gains: index or -1."""
+    ys = np.ascontiguousarray(ys, dtype=np.uint32)
+    g = [int(x) for x in gains]
+    hi = np.array([x >> 64 for x in g], dtype=np.int64)
+    lo = np.array([x & 0xFFFFFFFFFFFFFFFF for x in g], dtype=np.uint64)
+    return int(_load().orc_choose_ref(int(random), key & 0xFFFFFFFFFFFFFFFF, u, len(ys), ys.ctypes.data,
+                                      hi.ctypes.data, lo.ctypes.data))
 
 
 def eval_modularity(n, edges, labels, directed=False, gamma=(1, 1)):

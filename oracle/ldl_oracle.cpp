@@ -48,6 +48,15 @@ struct Cfg {
   int rn = 0, rd = 1;   // adaptive refresh threshold rho = rn / rd (0: never)
 };
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", 2014):
+// the output function applied to a 64-bit state.  Its first output for seed s is
+// splitmix_mix(s + 0x9E3779B97F4A7C15).
+uint64_t splitmix_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 typedef std::vector<std::pair<uint32_t, i64>> Row;  // sorted by column
 
 struct Level {
@@ -147,6 +156,11 @@ struct Oracle {
   int single_move = 0;            // accept only the best candidate per move iteration
   int check_moves = 0;            // recount Q from scratch around every move and refinement commit
   int empty_target = 0;           // variant: BestMove may also move v to an empty community
+  int random_refine = 0;          // variant: BestRef picks a random target among improving ones
+  uint64_t seed = 0;              // seed of that choice
+  uint64_t batches = 0;           // batches accepted so far (creation's is batch 0)
+  uint64_t cur_batch = 0;         // index of the batch being applied
+  uint64_t rkey = 0;              // key of the current refinement iteration (random_refine)
   uint64_t checks[6] = {0, 0, 0, 0, 0, 0};   // recount checks done: moves, refinements, and of those
                                              // the single-move ones that compared a predicted gain;
                                              // empty-target moves accepted, and of those the
@@ -321,6 +335,40 @@ struct Oracle {
   // BestRef_r: a singleton refined community {u} joins an adjacent refined community y whose
   // members carry u's move label.  Gain on refined totals Kr (from a singleton there is no
   // acc[a] term): q m acc[y] - p (kout_u Krin_y + kin_u Krout_y); undirected q m acc[y] - p k_u Kr_y.
+  //
+  // Variant (random_refine): as in the Leiden refinement of Traag et al., the target is drawn at
+  // random among the refined communities whose gain is strictly positive, here uniformly (the
+  // limit of their exp(gain / theta) weights for large theta, which keeps the choice exact): each
+  // such y gets the priority prio(u, y) of a counter-based hash (SplitMix64's output function
+  // chained over seed, batch, pass, level, iteration, u and y) and the highest priority wins;
+  // equal priorities go to the larger gain, then to the lower id.
+  uint32_t prio(uint32_t u, uint32_t y) const { return ref_prio(rkey, u, y); }
+  static uint32_t ref_prio(uint64_t key, uint32_t u, uint32_t y) {
+    return (uint32_t)(splitmix_mix(splitmix_mix(key ^ u) ^ y) >> 32) | 1u;
+  }
+  // The choice among the evaluated targets ys with gains Gs: the largest gain (equal gains: the
+  // lower id), or with random_refine the highest priority among strictly positive gains.
+  // Returns the index of the chosen target, -1 when there is none.
+  static int choose_ref(bool random, uint64_t key, uint32_t u, const std::vector<uint32_t>& ys,
+                        const std::vector<i128>& Gs) {
+    int best = -1;
+    uint32_t bestP = 0;
+    for (size_t i = 0; i < ys.size(); ++i) {
+      const i128 G = Gs[i];
+      const uint32_t y = ys[i];
+      if (random) {
+        if (G <= 0) continue;
+        const uint32_t p = ref_prio(key, u, y);
+        if (best < 0 || p > bestP || (p == bestP && (G > Gs[best] || (G == Gs[best] && y < ys[best])))) {
+          best = (int)i;
+          bestP = p;
+        }
+      } else if (best < 0 || G > Gs[best] || (G == Gs[best] && y < ys[best])) {
+        best = (int)i;
+      }
+    }
+    return best;
+  }
   bool best_ref(int r, uint32_t u, const std::vector<i64>& Krout, const std::vector<i64>& Krin, Cand& out) {
     const Level& L = lv[r];
     const uint32_t lu = L.lab[u];
@@ -333,20 +381,18 @@ struct Oracle {
     };
     for (auto& e : L.out[u]) visit(e.first, e.second);
     if (cfg.directed) for (auto& e : L.in[u]) visit(e.first, e.second);
-    bool found = false;
-    i128 bestG = 0; uint32_t besty = 0;
+    std::vector<i128> Gs;
     const i128 qm = (i128)cfg.gq * m;
     for (uint32_t y : acc_touched) {
-      i128 G;
       if (cfg.directed)
-        G = qm * acc[y] - (i128)cfg.gp * ((i128)L.kout[u] * Krin[y] + (i128)L.kin[u] * Krout[y]);
+        Gs.push_back(qm * acc[y] - (i128)cfg.gp * ((i128)L.kout[u] * Krin[y] + (i128)L.kin[u] * Krout[y]));
       else
-        G = qm * acc[y] - (i128)cfg.gp * ((i128)L.kout[u] * Krout[y]);
-      if (!found || G > bestG || (G == bestG && y < besty)) { found = true; bestG = G; besty = y; }
+        Gs.push_back(qm * acc[y] - (i128)cfg.gp * ((i128)L.kout[u] * Krout[y]));
     }
     for (uint32_t y : acc_touched) acc_flag[y] = 0;
-    if (!found || bestG <= 0) return false;
-    out.v = u; out.a = u; out.b = besty; out.G = bestG;
+    const int k = choose_ref(random_refine != 0, rkey, u, acc_touched, Gs);
+    if (k < 0 || Gs[k] <= 0) return false;
+    out.v = u; out.a = u; out.b = acc_touched[k]; out.G = Gs[k];
     return true;
   }
 
@@ -502,6 +548,11 @@ struct Oracle {
     for (uint32_t u = 0; u < n; ++u)
       if (L.alive[u]) { Krout[L.par[u]] += L.kout[u]; Krin[L.par[u]] += L.kin[u]; rsize[L.par[u]]++; }
     for (int j = 1; j <= cfg.M; ++j) {
+      // key of this refinement iteration: SplitMix64's first output of the seed, chained with
+      // the batch index, the pass, then level and iteration in one word
+      rkey = splitmix_mix(splitmix_mix(splitmix_mix(splitmix_mix(seed + 0x9E3779B97F4A7C15ull) ^ cur_batch) ^
+                                       (uint64_t)pass_idx) ^
+                          (((uint64_t)r << 32) | (uint64_t)j)) | 1ull;
       std::vector<Cand> cands;
       for (uint32_t u : R) {
         if (!(L.par[u] == u && rsize[u] == 1)) continue;   // only singletons move
@@ -675,6 +726,7 @@ struct Oracle {
       dm += (!cfg.directed && x.u != x.v) ? 2 * d : d;
     }
     if (m + dm >= ((i64)1 << 40)) return EOVERFLOW_;
+    cur_batch = batches++;   // the batch is accepted
 
     // ---- Alg. 1 l.1-2: apply to G^0 as matrix entries, repair m, degrees, totals, Ein, SKK
     std::vector<std::pair<std::pair<uint32_t, uint32_t>, i64>> ent;
@@ -840,8 +892,8 @@ extern "C" {
 
 // cfg10 = {directed, gamma_num, gamma_den, N, L, M, alpha_num, alpha_den, beta_num, beta_den};
 // null -> defaults (N=2, L=4, M=5, alpha=1/1000, beta=1/100, gamma=1) for an undirected graph.
-int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t n_edges, int flags,
-               void** out) {
+int orc_create_ex(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t n_edges, int flags,
+                  uint64_t seed, void** out) {
   *out = nullptr;
   Cfg c = default_cfg(0);
   if (cfg10) {
@@ -858,6 +910,8 @@ int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t
   o->check_moves = (flags & 2) != 0;
   o->tracing = (flags & 4) != 0;
   o->empty_target = (flags & 8) != 0;
+  o->random_refine = (flags & 16) != 0;
+  o->seed = seed;
   o->lv.resize(c.L + 1);
   o->alloc_level(0);
   for (uint32_t u = 0; u < n; ++u) o->lv[0].alive[u] = 1;
@@ -872,7 +926,23 @@ int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t
   return rc;
 }
 
+int orc_create(const int32_t* cfg10, uint32_t n, const uint32_t* edges, uint64_t n_edges, int flags,
+               void** out) {
+  return orc_create_ex(cfg10, n, edges, n_edges, flags, 0, out);
+}
+
 void orc_destroy(void* h) { delete (Oracle*)h; }
+
+uint64_t orc_splitmix_mix(uint64_t z) { return splitmix_mix(z); }
+
+// The refinement target choice on given candidates (gains as hi/lo words): index or -1.
+int orc_choose_ref(int random, uint64_t key, uint32_t u, uint64_t k, const uint32_t* ys, const int64_t* ghi,
+                   const uint64_t* glo) {
+  std::vector<uint32_t> y(ys, ys + k);
+  std::vector<i128> g(k);
+  for (uint64_t i = 0; i < k; ++i) g[i] = ((i128)ghi[i] << 64) | (i128)glo[i];
+  return Oracle::choose_ref(random != 0, key, u, y, g);
+}
 
 // Adaptive refresh threshold rho = num / den for the following batches (num = 0: never);
 // returns the number of batches so far that switched to full reoptimisation.

@@ -559,3 +559,84 @@ def test_empty_target_off_is_the_paper_method():
     assert results[0][1] == 0
     assert results[1][1] > 0
     assert not np.array_equal(results[0][0], results[1][0])
+
+
+# ------------------------------------------------ randomised refinement (a variant)
+
+def test_splitmix64_published_outputs():
+    """The counter-based hash of the randomised refinement is SplitMix64's output function: with
+    the generator's state increment it reproduces the generator's published first outputs."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "splitmix64_vectors.json")) as f:
+        fx = json.load(f)
+    inc = int(fx["increment"], 16)
+    for v in fx["vectors"]:
+        want = v.get("outputs") or [int(x, 16) for x in v["outputs_hex"]]
+        state, got = v["seed"], []
+        for _ in want:
+            state = (state + inc) & 0xFFFFFFFFFFFFFFFF
+            got.append(oracle.splitmix_mix(state))
+        assert got == want
+
+
+def test_random_refinement_choice_is_uniform_among_improving_targets():
+    """The randomised choice picks each target of strictly positive gain equally often over
+    keys (here 4 such targets among 7, 4,000 keys: each share within 0.25 +- 0.035, about 5
+    standard deviations), never one of gain <= 0, and with no improving target nothing; the
+    deterministic choice is the largest gain, equal gains to the lower id."""
+    ys = [40, 12, 7, 33, 25, 8, 90]
+    gains = [5, -3, 2 ** 70, 0, 17, 5, -(2 ** 65)]
+    improving = {0, 2, 4, 5}
+    counts = dict.fromkeys(range(len(ys)), 0)
+    keys = 4000
+    for k in range(keys):
+        key = oracle.splitmix_mix(0x1234 + k) | 1
+        counts[oracle.choose_ref(True, key, 77, ys, gains)] += 1
+    assert set(i for i, c in counts.items() if c) == improving
+    for i in improving:
+        assert abs(counts[i] / keys - 0.25) < 0.035, counts
+    assert oracle.choose_ref(True, 99, 77, ys[1:2] + ys[3:4], [gains[1], gains[3]]) == -1
+    assert oracle.choose_ref(False, 99, 77, ys, gains) == 2
+    assert oracle.choose_ref(False, 99, 77, [9, 4, 6], [3, 3, 1]) == 1
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_random_refinement_moves_match_recount(directed):
+    """With the randomised refinement every single-move refinement commit still changes the
+    refined partition's Eq. 1, recounted from scratch, by exactly the chosen target's predicted
+    gain, and the refined totals equal their recount."""
+    total = 0
+    for trial in range(3):
+        n = 60 + 20 * trial
+        s = synth.Stream(n, directed, synth.BASE_SEED + 960 + 10 * trial + directed)
+        s.planted(10, 0.35, 0.04, 1, 8)
+        flags = oracle.FLAG_CHECK_MOVES | oracle.FLAG_SINGLE_MOVE
+        o = oracle.Oracle(n, s.edges(), directed=directed, flags=flags, L=2, refine_random=True,
+                          refine_seed=11 + trial)
+        assert o.last_rc == 0, o.check()
+        for _ in range(3):
+            b = s.batch(12)
+            assert o.apply_batch(b.ins, b.dels, b.chg) == 0, o.check()
+        assert o.check() == ""
+        total += o.check_counts()["refine_single"]
+    assert total >= 20
+
+
+def test_random_refinement_depends_on_seed_only():
+    """Equal seeds give equal states; other seeds give other refinements (the variant really
+    draws), and every state satisfies the hierarchy invariants."""
+    parts = []
+    for seed in (5, 5, 6, 7):
+        s = synth.Stream(600, False, synth.BASE_SEED + 980)
+        s.planted(30, 0.2, 0.01, 1, 8)
+        o = oracle.Oracle(600, s.edges(), refine_random=True, refine_seed=seed)
+        for _ in range(2):
+            b = s.batch(100)
+            assert o.apply_batch(b.ins, b.dels, b.chg) == 0
+        assert o.check() == ""
+        assert not check_state(oracle_state(o), False)
+        parts.append(oracle_state(o))
+    assert not diff_states(parts[0], parts[1])
+    assert diff_states(parts[0], parts[2]) or diff_states(parts[0], parts[3])
