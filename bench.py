@@ -294,7 +294,12 @@ def run_serve_mix(args):
     updates = sum(b.size for _, b in reqs)
 
     def make_graphs():
-        return [ldl.Graph(d[0], d[2], directed=d[1]) for d in drawn]
+        # each handle keeps at most 1 GiB of batch scratch between calls (an occasional batch
+        # whose frontier spans most of an R-MAT graph grows it to gigabytes)
+        gs = [ldl.Graph(d[0], d[2], directed=d[1], scratch_limit=1 << 30) for d in drawn]
+        log(f"created 32 graphs: device memory held {sum(x.memory()['held'] for x in gs) / 2**30:.1f} GiB, "
+            f"free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
+        return gs
 
     plain = make_graphs()
     t0 = time.perf_counter()
@@ -659,6 +664,8 @@ def stream_summary(r):
             "device_free_gib_after_static": r["device_free_gib_after_static"],
             "candidate_search_ms_per_step": float(np.mean([x["search_ms"] for x in stats])),
             "scanned_entries_per_step": float(np.mean([x["scanned_entries"] for x in stats])),
+            "distinct_comms_per_step": float(np.mean([x["distinct_comms"] for x in stats])),
+            "hub_entries_per_step": float(np.mean([sum(x["bin_entries"][k] for k in range(5, 24, 6)) for x in stats])),
             "frontier_entries_per_s": float(sum(x["scanned_entries"] for x in stats) / r["T"]),
             "agg_tuples_per_step": float(np.mean([x["agg_tuples"] for x in stats])),
             "rebuilds_per_step": float(np.mean([x["agg_rebuilds"] for x in stats])),

@@ -88,6 +88,22 @@ typedef struct ldl_pair {
  *                       gain of Eq. 2 is that of an empty target).  It is one more candidate in the
  *                       comparison (larger exact gain, equal gains to the lower id); refinement
  *                       is unchanged.
+ *   refine_random       0 or 1 (a variant, off by default).  The paper's BestRef, like BestMove,
+ *   refine_seed         takes the target of largest gain (Alg. 1 l.18).  With 1 the target is
+ *                       drawn at random among the refined communities of strictly positive gain,
+ *                       as the Leiden refinement of Traag et al. draws among improving ones; here
+ *                       uniformly (the large-temperature limit of its exp(gain / theta) weights,
+ *                       which keeps the choice exact).  Every such target y of node u gets the
+ *                       priority high32(mix(mix(key ^ u) ^ y)) | 1, where mix is SplitMix64's
+ *                       output function and key = mix(mix(mix(mix(seed + 0x9E3779B97F4A7C15) ^
+ *                       batch) ^ pass) ^ (level << 32 | iteration)) | 1, with batch the number of
+ *                       batches the handle accepted before this one (creation's is 0); the highest
+ *                       priority wins (equal priorities: the larger gain, then the lower id).
+ *                       The seed and the batch count travel in ldl_export_state's blob.
+ *   scratch_limit       bytes of growable scratch (see ldl_release_scratch) a handle may keep
+ *                       between calls: a call that leaves more frees it before returning (0, the
+ *                       default: keep it for the next call).  For many resident graphs whose
+ *                       occasional large batches would otherwise each keep their peak scratch.
  *   test_flags          0 in production.  Bits that drive rarely taken internal paths, with
  *                       results unchanged: 1 = one decoupling round between host checks (second
  *                       commit phase), 2 = minimal hub bucket pool (overflow and redo of an
@@ -125,6 +141,9 @@ typedef struct ldl_config {
   ldl_free_fn free;     /* both NULL: hipMalloc / hipFree                                      */
   void* alloc_ctx;
   int32_t empty_target;
+  uint64_t scratch_limit;
+  int32_t refine_random;
+  uint32_t refine_seed;
 } ldl_config;
 
 /* Per-call statistics (all counts summed over the call). */

@@ -33,7 +33,8 @@ class ldl_config(ctypes.Structure):
                 ("beta_den", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("profile", ctypes.c_int32), ("test_flags", ctypes.c_int32), ("refresh_num", ctypes.c_int32),
                 ("refresh_den", ctypes.c_int32), ("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p),
-                ("alloc_ctx", ctypes.c_void_p), ("empty_target", ctypes.c_int32)]
+                ("alloc_ctx", ctypes.c_void_p), ("empty_target", ctypes.c_int32), ("scratch_limit", ctypes.c_uint64),
+                ("refine_random", ctypes.c_int32), ("refine_seed", ctypes.c_uint32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p)
@@ -239,7 +240,7 @@ class Graph:
 
     def __init__(self, n, edges, directed=False, gamma=(1, 1), N=2, L=4, M=5, alpha=(1, 1000), beta=(1, 100),
                  device=0, stream=None, profile=False, test_flags=0, refresh=(0, 1), allocator=None,
-                 empty_target=False):
+                 empty_target=False, scratch_limit=0, refine_random=False, refine_seed=0):
         self.lib = load_library()
         c = ldl_default_config()
         c.directed, c.gamma_num, c.gamma_den = int(directed), gamma[0], gamma[1]
@@ -251,6 +252,9 @@ class Graph:
         c.test_flags = int(test_flags)
         c.refresh_num, c.refresh_den = int(refresh[0]), int(refresh[1])
         c.empty_target = int(bool(empty_target))
+        c.scratch_limit = int(scratch_limit)
+        c.refine_random = int(bool(refine_random))
+        c.refine_seed = int(refine_seed) & 0xFFFFFFFF
         self.allocator = allocator   # kept alive as long as the handle (its callbacks are called)
         if allocator is not None:
             allocator.install(c)

@@ -144,6 +144,12 @@ struct Engine {
   int64_t an = 1, ad = 1000, bn = 1, bd = 100;
   int64_t rn = 0, rd = 1;   // adaptive refresh threshold (0: never)
   int empty_target = 0;     // BestMove may also target the empty community labelled by the vertex
+  uint64_t scratch_limit = 0;   // free the growable scratch after a call that leaves more (0: keep)
+  int refine_random = 0;        // BestRef draws among improving targets (seeded)
+  uint64_t refine_seed = 0;
+  uint64_t batches = 0;         // batches accepted so far (creation's is batch 0)
+  uint64_t cur_batch = 0;       // index of the batch being applied
+  uint64_t cur_rkey = 0;        // key of the current refinement iteration's draw (0: none)
   int device = 0;
   int profile = 0;
   int test_flags = 0;   // see ldl_config
@@ -404,6 +410,9 @@ struct Engine {
     an = c.alpha_num; ad = c.alpha_den; bn = c.beta_num; bd = c.beta_den;
     rn = c.refresh_num; rd = c.refresh_den;
     empty_target = c.empty_target;
+    scratch_limit = c.scratch_limit;
+    refine_random = c.refine_random;
+    refine_seed = c.refine_seed;
     halloc = c.alloc;
     hfree = c.free;
     hctx = c.alloc_ctx;
@@ -620,6 +629,9 @@ struct Engine {
   // Free the growable scratch (aggregation tuples, reduced records, sorted entries, row-update
   // buffers, the library primitives' temporary storage); the next call that needs them allocates
   // them again at its own size.  The state is untouched.
+  uint64_t scratch_bytes() const {
+    return tup_cap * 56 + rec_cap * 40 + ent_cap * 40 + ins_cap * 69 + cub_bytes;
+  }
   void release_scratch() {
     hcheck(hipStreamSynchronize(st));
     for (void** p : {(void**)&tk0, (void**)&tk1, (void**)&tk2, (void**)&tv0, (void**)&tv1, (void**)&tv2,
@@ -1026,6 +1038,7 @@ struct Engine {
     mv.p = gp;
     mv.directed = directed;
     mv.empty_target = refine ? 0 : empty_target;
+    mv.rkey = refine ? cur_rkey : 0;
     for (int b = 0; b < kNumBins - 1; ++b) mv.lim[b] = lim[V.out.ref.wide][b];
     return mv;
   }
@@ -1359,6 +1372,15 @@ struct Engine {
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.refine_iters++;
+      // the draw's key: SplitMix64's first output of the seed chained with the batch, the pass,
+      // then level and iteration in one word
+      cur_rkey = refine_random
+                     ? splitmix64_out(splitmix64_out(splitmix64_out(splitmix64_out(refine_seed + 0x9E3779B97F4A7C15ull) ^
+                                                                    cur_batch) ^
+                                                     (uint64_t)pass_idx) ^
+                                      (((uint64_t)r << 32) | (uint64_t)j)) |
+                           1ull
+                     : 0;
       uint32_t Rc = 0, K = 0, na = 0;
       int64_t dein_unused = 0;
       i128 dskk_unused = 0;
@@ -1609,6 +1631,7 @@ struct Engine {
   int apply(const uint32_t* dins, uint64_t ni, const uint32_t* ddel, uint64_t nd, const uint32_t* dchg, uint64_t nc) {
     const int rc = ingest(dins, ni, ddel, nd, dchg, nc);
     if (rc != LDL_OK) return rc;
+    cur_batch = batches++;   // the batch is accepted
     maybe_refresh();
     for (int i = 1; i <= N; ++i) {
       pass_idx = i;
@@ -1823,11 +1846,12 @@ struct Engine {
     char magic[8];
     uint32_t version, header_bytes;
     int32_t cfg[14];   // directed, gamma p, q, N, L, M, alpha num, den, beta num, den, refresh num, den,
-                       // empty target, 0
+                       // variants (1 empty target, 2 randomised refinement), refinement seed
     uint32_t n;
     int32_t top;
     int64_t m, ein, skk_hi;
     uint64_t skk_lo;
+    uint64_t batches;   // batches accepted so far (the randomised refinement's counter)
     uint32_t lim[2][5];
     uint64_t total_bytes;
   };
@@ -1860,8 +1884,10 @@ struct Engine {
     hd.version = kStateVersion;
     hd.header_bytes = sizeof(StateHeader);
     const int32_t c14[14] = {directed, (int32_t)gp, (int32_t)gq, N, L, M, (int32_t)an, (int32_t)ad, (int32_t)bn,
-                             (int32_t)bd, (int32_t)rn, (int32_t)rd, empty_target, 0};
+                             (int32_t)bd, (int32_t)rn, (int32_t)rd, empty_target | (refine_random << 1),
+                             (int32_t)(uint32_t)refine_seed};
     std::memcpy(hd.cfg, c14, sizeof(c14));
+    hd.batches = batches;
     hd.n = n;
     hd.top = top;
     hd.m = m;
@@ -2003,6 +2029,7 @@ struct Engine {
     m = hd.m;
     Ein = hd.ein;
     SKK = ((i128)hd.skk_hi << 64) | (i128)hd.skk_lo;
+    batches = hd.batches;
     std::memcpy(lim, hd.lim, sizeof(lim));
     mutating = false;
     return LDL_OK;
@@ -2060,7 +2087,7 @@ bool cfg_ok(const ldl_config& c) {
   return in16(c.gamma_num, 1) && in16(c.gamma_den, 1) && c.N >= 1 && c.M >= 1 && c.L >= 0 && c.L <= 16 &&
          in16(c.alpha_num, 0) && in16(c.alpha_den, 1) && in16(c.beta_num, 0) && in16(c.beta_den, 1) &&
          in16(c.refresh_num, 0) && in16(c.refresh_den, 1) && (c.directed == 0 || c.directed == 1) &&
-         (c.empty_target == 0 || c.empty_target == 1) &&
+         (c.empty_target == 0 || c.empty_target == 1) && (c.refine_random == 0 || c.refine_random == 1) &&
          ((c.alloc == nullptr) == (c.free == nullptr));
 }
 
@@ -2112,6 +2139,7 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     e.release(tmp);
     e.finish_profile();
     e.call_end();
+    if (e.scratch_limit && e.scratch_bytes() > e.scratch_limit) e.release_scratch();
     e.stats.total_ms = ms;
     if (stats) *stats = e.stats;
     return rc;
@@ -2139,6 +2167,9 @@ void ldl_default_config(ldl_config* c) {
   c->free = nullptr;
   c->alloc_ctx = nullptr;
   c->empty_target = 0;
+  c->scratch_limit = 0;
+  c->refine_random = 0;
+  c->refine_seed = 0;
 }
 
 int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_t n_edges, ldl_handle** out) {
@@ -2355,8 +2386,11 @@ int ldl_import_state(const ldl_config* cfg, const void* blob, uint64_t size, ldl
   c.alpha_num = hd.cfg[6]; c.alpha_den = hd.cfg[7];
   c.beta_num = hd.cfg[8]; c.beta_den = hd.cfg[9];
   c.refresh_num = hd.cfg[10]; c.refresh_den = hd.cfg[11];
-  c.empty_target = hd.cfg[12];
-  if (!cfg_ok(c) || hd.cfg[13] != 0) return LDL_EINVAL;
+  if (hd.cfg[12] & ~3) return LDL_EINVAL;
+  c.empty_target = hd.cfg[12] & 1;
+  c.refine_random = (hd.cfg[12] >> 1) & 1;
+  c.refine_seed = (uint32_t)hd.cfg[13];
+  if (!cfg_ok(c)) return LDL_EINVAL;
   ldl_handle* h = new (std::nothrow) ldl_handle;
   if (!h) return LDL_ENOMEM;
   h->e = new (std::nothrow) ldl::Engine();

@@ -123,6 +123,15 @@ __device__ __forceinline__ Best with_empty(const MoveView& mv, const VInfo& vi, 
   return better(e, b) ? e : b;
 }
 
+// A target's entry in the reductions: its exact gain and id; with the randomised refinement
+// (mv.rkey != 0) only strictly positive gains count, ranked by their draw priority.
+template <bool REF>
+__device__ __forceinline__ Best cand_best(const MoveView& mv, uint32_t v, i128 g, uint32_t id) {
+  Best b = make_best(g, id);
+  if (REF && mv.rkey) b.valid = g > 0 ? (int)draw_priority(mv.rkey, v, id) : 0;
+  return b;
+}
+
 __device__ __forceinline__ void emit_cand_at(const CandBuf& cb, uint32_t at, uint32_t v, uint32_t a, const Best& b) {
   cb.v[at] = v;
   cb.a[at] = a;
@@ -423,7 +432,7 @@ __global__ __launch_bounds__(kTpb) void k_best_group(MoveView mv, BinRef br, Can
     for (int u = 0; u < U; ++u) {
       Best b;
       b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-      if (act[u] && rep[u]) b = make_best(gain_t<DIR, REF>(mv, vi[u], Kob[u], Kib[u], acc[u], own[u]), key[u]);
+      if (act[u] && rep[u]) b = cand_best<REF>(mv, v[u], gain_t<DIR, REF>(mv, vi[u], Kob[u], Kib[u], acc[u], own[u]), key[u]);
       ls.distinct += (act[u] && rep[u]) ? 1 : 0;
       b = group_best(b, G);
       if (act[u] && li == 0) {
@@ -649,7 +658,7 @@ __global__ __launch_bounds__(kTpb) void k_best_wave(MoveView mv, BinRef br, Cand
       if (mine[q] == kNoSlot) continue;
       ls.distinct += 1;
       const int64_t av = (int64_t)vals[mine[q]];
-      const Best c = make_best(gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
+      const Best c = cand_best<REF>(mv, v, gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
       if (better(c, b)) b = c;
     }
     // each slot is read and emptied by its owner only; the barrier at the top of the next
@@ -776,7 +785,7 @@ void k_best_hash(MoveView mv, BinRef br, CandBuf cand, MoveStats st) {
       if (mine[q] == kNoSlot) continue;
       ls.distinct += 1;
       const int64_t av = (int64_t)sval[t][mine[q]];
-      const Best c = make_best(gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
+      const Best c = cand_best<REF>(mv, cur.v, gain_t<DIR, REF>(mv, cur.vi, Kb[q], Kib[q], av, own), ks[q]);
       if (better(c, b)) b = c;
     }
     b = team_best<TEAM>(b, red_b);
@@ -1124,7 +1133,7 @@ __global__ __launch_bounds__(kTpb) void k_hub_part(MoveView mv, BinRef br, uint3
       const uint32_t key = tk[t];
       if (key == kEmpty) continue;
       ++nd;
-      const Best c = make_best(gain<DIR, REF>(mv, vi, key, (int64_t)tv[t], ow), key);
+      const Best c = cand_best<REF>(mv, v, gain<DIR, REF>(mv, vi, key, (int64_t)tv[t], ow), key);
       if (better(c, b)) b = c;
     }
     nd = team_sum<kTpb>(nd, red_i);

@@ -95,8 +95,9 @@ __device__ __forceinline__ i128 wave_sum_i128(i128 v) {
   return v;
 }
 
-// Best (gain, id): larger gain wins, equal gains go to the lower id.  valid == false is
-// worse than anything.
+// Best (gain, id): larger gain wins, equal gains go to the lower id.  valid == 0 is worse than
+// anything.  A valid entry's `valid` is 1, or, for the randomised refinement, the target's draw
+// priority (odd, compared as unsigned before the gain).
 struct Best {
   int64_t hi;
   uint64_t lo;
@@ -107,6 +108,7 @@ __device__ __forceinline__ i128 best_gain(const Best& b) { return ((i128)b.hi <<
 __device__ __forceinline__ bool better(const Best& x, const Best& y) {
   if (!x.valid) return false;
   if (!y.valid) return true;
+  if (x.valid != y.valid) return (uint32_t)x.valid > (uint32_t)y.valid;
   if (x.hi != y.hi) return x.hi > y.hi;
   if (x.lo != y.lo) return x.lo > y.lo;
   return x.id < y.id;

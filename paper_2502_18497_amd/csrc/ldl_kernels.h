@@ -9,6 +9,18 @@ namespace ldl {
 typedef unsigned long long u64a;
 typedef long long i64a;
 
+// SplitMix64's output function (Steele, Lea and Flood, 2014) of a 64-bit state: the
+// counter-based hash of the randomised refinement (keys on the host, priorities on the device).
+__host__ __device__ __forceinline__ uint64_t splitmix64_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// draw priority of target y for vertex u under an iteration key (odd, so never 0)
+__device__ __forceinline__ uint32_t draw_priority(uint64_t key, uint32_t u, uint32_t y) {
+  return (uint32_t)(splitmix64_out(splitmix64_out(key ^ u) ^ y) >> 32) | 1u;
+}
+
 // A stamped set over ids [0, n): x is a member iff stamp[x] == epoch; members are appended to
 // `list` and counted in *count.
 struct SetRef {
@@ -45,6 +57,7 @@ struct MoveView {
   int64_t p;                 // gamma numerator
   int directed;
   int empty_target;          // move: also offer the empty community labelled v (variant)
+  uint64_t rkey;             // refinement: key of the iteration's random draw (0: best gain)
   uint32_t lim[5];           // degree-bin limits (entries per vertex), see kBinCap
 };
 

@@ -153,3 +153,44 @@ def test_empty_target_variant(directed, kernels):
     bins = None if kernels is None else _ONLY[kernels]
     g, og = run_parity(n, e, batches, directed=directed, bins=bins, empty_target=True, gamma=(2, 1))
     assert og.check_counts()["empty_moves"] >= 10
+
+
+def _random_refine_parity(n, edges, batches, directed, seed, bins=None, export_at=None):
+    """Both sides created empty (creation is batch 0 of the draws' counter, the edges arrive as
+    batch 1, so the GPU side can take degree bins first) and compared after every batch."""
+    import paper_2502_18497_amd as ldl
+
+    empty = np.zeros((0, 3), np.uint32)
+    og = oracle.Oracle(n, empty, directed=directed, refine_random=True, refine_seed=seed)
+    g = ldl.Graph(n, empty, directed=directed, refine_random=True, refine_seed=seed)
+    if bins is not None:
+        g.set_bins(bins)
+    for k, b in enumerate([_Batch(edges, None, None)] + batches):
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+        g.apply_batch(b.ins, b.dels, b.chg)
+        if export_at == k:   # continue from a checkpoint: seed and batch counter travel with it
+            g = ldl.Graph.from_state(g.export_state())
+        msgs = diff_states(g.state(), oracle_state(og))
+        assert not msgs, (k, msgs)
+        assert np.array_equal(g.partition(), og.partition()) and g.qnum() == og.qnum()
+    return g, og
+
+
+@pytest.mark.parametrize("kernels", [None, "wave", "hash", "workgroup", "hub"])
+@pytest.mark.parametrize("directed", [False, True])
+def test_random_refinement_variant(directed, kernels):
+    """Randomised refinement (a variant; its draw is pinned on the CPU): planted partitions with
+    batch updates, bit-identical to the oracle drawing with the same seed, with the default bins
+    and with every vertex sent to one kernel family in turn; a checkpoint taken mid-stream
+    continues the same draws.  Another seed gives another state (the draws matter)."""
+    n = 1500
+    s = synth.Stream(n, directed, synth.BASE_SEED + 990 + directed)
+    s.planted(30, 0.2, 0.01, 1, 8)
+    e = s.edges()
+    batches = [_Batch(*(lambda b: (b.ins, b.dels, b.chg))(s.batch(sz))) for sz in (200, 30, 200)]
+    bins = None if kernels is None else _ONLY[kernels]
+    g, og = _random_refine_parity(n, e, batches, directed, 1234, bins=bins, export_at=2)
+    other = oracle.Oracle(n, np.zeros((0, 3), np.uint32), directed=directed, refine_random=True, refine_seed=4321)
+    for b in [_Batch(e, None, None)] + batches:
+        assert other.apply_batch(b.ins, b.dels, b.chg) == 0
+    assert diff_states(oracle_state(other), oracle_state(og))

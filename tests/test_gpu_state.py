@@ -11,7 +11,7 @@ from tests.statecheck import diff_states, oracle_state
 
 pytestmark = pytest.mark.gpu
 
-HEADER_BYTES = 160
+HEADER_BYTES = 168
 
 
 def blob_layout(blob: bytes, L: int):
@@ -264,3 +264,22 @@ def test_release_scratch_frees_memory_and_keeps_results():
         assert rel.memory()["held"] < grown
         assert not diff_states(keep.state(), rel.state())
     assert rel.memory()["held"] <= keep.memory()["held"]
+
+
+def test_scratch_limit_caps_what_a_handle_keeps():
+    """With scratch_limit set, a call that leaves more growable scratch than the limit frees it
+    before returning: the handle holds no more than right after creation between calls, and
+    its results equal those of a handle that keeps its scratch."""
+    import paper_2502_18497_amd as ldl
+
+    s = synth.rmat_undirected(scale=13, seed_offset=690)
+    e = s.edges()
+    keep, capped = ldl.Graph(s.n, e), ldl.Graph(s.n, e, scratch_limit=1)
+    created = capped.memory()["held"]
+    for size in (20000, 300, 5000):
+        b = s.batch(size)
+        keep.apply_batch(b.ins, b.dels, b.chg)
+        capped.apply_batch(b.ins, b.dels, b.chg)
+        assert capped.memory()["held"] <= max(created, keep.memory()["held"])
+        assert not diff_states(keep.state(), capped.state())
+    assert capped.memory()["held"] < keep.memory()["held"]

@@ -40,8 +40,8 @@ def test_noalloc_recount_equals_allocating_recount(directed):
         assert a == na and a[0] == 0 and a[2] > 0, (a, na)
         # a planted corruption: a community total off by one in a restored state
         blob = bytearray(g.export_state())
-        k = int(np.frombuffer(bytes(blob[160:168]), np.int64)[0])   # Kout of community 0, after the header
-        blob[160:168] = np.array([k + 1], np.int64).tobytes()
+        k = int(np.frombuffer(bytes(blob[168:176]), np.int64)[0])   # Kout of community 0, after the header
+        blob[168:176] = np.array([k + 1], np.int64).tobytes()
         bad = ldl.Graph.from_state(bytes(blob))
         a, na = _reports(bad)
         assert a == na and a[0] == 32, (a, na)
