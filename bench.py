@@ -993,7 +993,12 @@ def main():
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--rates", type=float, nargs="+", default=[0.5, 1.0, 2.0, 4.0])
     ap.add_argument("--mem-budget", type=int, default=16 << 30)
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="mix / serve: hardware queues per process (GPU_MAX_HW_QUEUES, at most 32; 0 = HIP's default)")
     args = ap.parse_args()
+    if args.hw_queues:
+        # read by the HIP runtime when it initialises, so it must be set before the first device call
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, args.hw_queues))
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -538,12 +538,15 @@ struct Engine {
     uint64_t hc = (test_flags & 2) ? 256 : 1ull << 16;
     if (hc < entries) hc = (entries + entries / 8 + 0xFFFF) & ~0xFFFFull;
     release(hub.ekey);
+    release(hub.ew);
     release(hub.bkey);
     release(hub.bw);
     hub.ekey = nullptr;
+    hub.ew = nullptr;
     hub.bkey = nullptr;
     hub.bw = nullptr;
     hub.ekey = alloc<uint32_t>(hc);
+    hub.ew = alloc<int64_t>(hc);
     hub.bkey = alloc<uint32_t>(hc);
     hub.bw = alloc<int64_t>(hc);
     hub.cap = hc;
@@ -564,6 +567,7 @@ struct Engine {
     if (parts > part_cap) {
       regrow(hw.phi, parts); regrow(hw.plo, parts); regrow(hw.pid, parts); regrow(hw.pvalid, parts);
       regrow(hw.pcount, parts); regrow(hw.pcur, parts); regrow(hw.poff, parts); regrow(hw.pcnt, parts);
+      regrow(hw.icnt, parts);   // chunk items: at most one per kPartEntries entries, so fewer than partitions
       hcheck(hipMemsetAsync(hw.pcount, 0, 4ull * parts, st));
       hcheck(hipMemsetAsync(hw.pcur, 0, 4ull * parts, st));
       part_cap = parts;
@@ -1393,7 +1397,7 @@ struct Engine {
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
       cub(launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, nullptr, nullptr, &cub_tmp,
                        &cub_bytes, st));
-      launch_spexpand(cand.v, acc, nap, na, it_off, V.out.ref, in_or_none, V.lab, V.par, V.rsize, sets[S_RCUR].stamp,
+      launch_spexpand(cand.v, acc, nap, na, it_off, V.out.ref, in_or_none, lpk, V.rsize, sets[S_RCUR].stamp,
                       sets[S_RCUR].epoch, sets[S_RSET].stamp, sets[S_RSET].epoch, oldpar, st);
       select_set(S_RCUR);
       rset_grew = rset_grew || na > 0;

@@ -1356,17 +1356,17 @@ __global__ void k_tuples_gen(const uint32_t* list, const uint32_t* countp, uint3
 // SPExpand over wavefront items of the refinement movers: their singleton neighbours with the
 // mover's label join Rcur; those new to Rset join it too, with their old parent (themselves)
 // recorded.  Plain-store marks (every writer of a word stores the same value); the lists
-// come from a select.
+// come from a select.  Label and parent come from one packed (label, parent) gather.
 __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, const uint32_t* countp, uint32_t bound,
-                                 const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
-                                 const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
-                                 uint32_t rset_ep, uint32_t* oldpar) {
+                                 const uint64_t* ioff, CsrRef out, CsrRef in, const uint2* lp, const uint32_t* rsize,
+                                 uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep,
+                                 uint32_t* oldpar) {
   const int lane = lane_id();
   const uint32_t c0 = *countp;
   const uint32_t cnt = c0 < bound ? c0 : bound;
   wave_items(ioff, cnt, [&](uint32_t i, uint64_t q) {
     const uint32_t v = list_node(movers, idx, i);
-    const uint32_t lv = lab[v];
+    const uint32_t lv = lp[v].x;
     const uint32_t dout = out.deg[v];
     const uint64_t s = node_slots(out, in, v);
     const uint64_t j0 = q * kItem, j1 = j0 + kItem < s ? j0 + kItem : s;
@@ -1382,14 +1382,15 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
         xs[k] = v;
         if (ok[k]) xs[k] = j < dout ? out.nbr[out.off[v] + j] : in.nbr[in.off[v] + (j - dout)];
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) ok[k] = ok[k] && xs[k] != v && lab[xs[k]] == lv;
       uint32_t px[4], rx[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        px[k] = ok[k] ? par[xs[k]] : 0u;
-        rx[k] = ok[k] ? rsize[xs[k]] : 0u;
+        const uint2 e = ok[k] && xs[k] != v ? lp[xs[k]] : make_uint2(~lv, 0u);
+        ok[k] = e.x == lv;
+        px[k] = e.y;
       }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rx[k] = ok[k] && px[k] == xs[k] ? rsize[xs[k]] : 0u;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const uint32_t x = xs[k];
@@ -1689,10 +1690,10 @@ int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* coun
   return prim_exclusive_sum_u64(tmp, tmp_bytes, icnt, ioff, (uint64_t)bound + 1, s);
 }
 void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t* count, uint32_t bound,
-                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
-                     const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
-                     uint32_t rset_ep, uint32_t* oldpar, hipStream_t s) {
-  k_spexpand_items<<<kItemBlocks, kTpb, 0, s>>>(movers, idx, count, bound, ioff, out, in, lab, par, rsize, rcur_stamp,
+                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint2* lp, const uint32_t* rsize,
+                     uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep, uint32_t* oldpar,
+                     hipStream_t s) {
+  k_spexpand_items<<<kItemBlocks, kTpb, 0, s>>>(movers, idx, count, bound, ioff, out, in, lp, rsize, rcur_stamp,
                                                 rcur_ep, rset_stamp, rset_ep, oldpar);
 }
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,

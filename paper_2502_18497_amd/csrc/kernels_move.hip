@@ -886,15 +886,30 @@ __global__ void k_hub_size(MoveView mv, BinRef br, uint32_t bound, int pshift, U
   }
 }
 
-// chunk items: keys of the entries, own-community weight, entries per partition
+// chunk items: the chunk's entries summed by key in LDS (each chunk of kHubChunk entries leaves
+// its distinct (key, weight) pairs at the start of its own stretch of the pool), the weight
+// towards the own community, and the pairs per partition.  The scatter and partition passes then
+// handle distinct pairs only: a hub's neighbours crowd into few communities.
+constexpr uint32_t kChunkSlots = 2 * kHubChunk;   // load factor <= 1/2
+constexpr uint32_t kKeysHist = 1024;              // partitions counted in LDS (more: global atomics)
 template <typename WT, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_hub_keys(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
                                                    HubPool hub, HubWork hw, MoveStats st) {
   __shared__ int64_t red[kTpb / kWave];
-  __shared__ uint32_t lh[kPartHist];
+  __shared__ uint32_t lh[kKeysHist];
+  __shared__ uint32_t tk[kChunkSlots];
+  __shared__ u64a tv[kChunkSlots];
+  __shared__ uint32_t s_nd;
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
   const uint64_t total = off[h].y;
+  // the table starts empty and every chunk leaves it empty (each slot is reset by its reader)
+  for (uint32_t t = threadIdx.x; t < kChunkSlots; t += blockDim.x) {
+    tk[t] = kEmpty;
+    tv[t] = 0;
+  }
+  if (threadIdx.x == 0) s_nd = 0;
+  __syncthreads();
   uint64_t nent = 0;
   for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const uint32_t i = item_owner<1>(off, h, it);
@@ -909,13 +924,12 @@ __global__ __launch_bounds__(kTpb) void k_hub_keys(MoveView mv, BinRef br, uint3
     const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
     const uint32_t labv = mv.lab[v];
     const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
-    const bool local = P <= kPartHist;
+    const bool local = P <= kKeysHist;
     if (local)
       for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) lh[t] = 0;
-    __syncthreads();
     int64_t ow = 0;
-    // four entries per thread at a time: their loads, then their key gathers, then the writes
-    // and counts, so four gathers are in flight before any is used
+    // four entries per thread at a time: their loads, then their key gathers, then the inserts,
+    // so four gathers are in flight before any is used
     for (uint64_t jb = e0 + threadIdx.x; jb < e1; jb += 4 * (uint64_t)blockDim.x) {
       uint32_t xs[4], ks[4];
       int64_t wv[4];
@@ -930,25 +944,38 @@ __global__ __launch_bounds__(kTpb) void k_hub_keys(MoveView mv, BinRef br, uint3
       for (int k = 0; k < 4; ++k) ks[k] = entry_key<REF>(mv, v, labv, xs[k]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const uint64_t j = jb + (uint64_t)k * blockDim.x;
-        if (j >= e1) continue;
-        uint32_t key = ks[k];
+        const uint32_t key = ks[k];
+        if (key == kEmpty) continue;
         if (!REF && key == labv) {
           ow += wv[k];
-          key = kEmpty;
+          continue;
         }
-        hub.ekey[base + j] = key;
-        if (key == kEmpty) continue;
-        const uint32_t p = part_of(key, P);
-        if (local) atomicAdd(&lh[p], 1u);
-        else atomicAdd(&hw.pcount[pbase + p], 1u);
+        table_insert(tk, tv, kChunkSlots - 1, key, wv[k]);
       }
+    }
+    __syncthreads();   // every insert done (and lh cleared)
+    // the chunk's distinct pairs to the start of its stretch of the pool, counted per partition
+    for (uint32_t t = threadIdx.x; t < kChunkSlots; t += blockDim.x) {
+      const uint32_t key = tk[t];
+      if (key == kEmpty) continue;
+      const uint32_t at = atomicAdd(&s_nd, 1u);
+      hub.ekey[base + e0 + at] = key;
+      hub.ew[base + e0 + at] = (int64_t)tv[t];
+      tk[t] = kEmpty;
+      tv[t] = 0;
+      const uint32_t p = part_of(key, P);
+      if (local) atomicAdd(&lh[p], 1u);
+      else atomicAdd(&hw.pcount[pbase + p], 1u);
     }
     __syncthreads();
     if (local)
       for (uint32_t t = threadIdx.x; t < P; t += blockDim.x)
         if (lh[t]) atomicAdd(&hw.pcount[pbase + t], lh[t]);
-    ow = team_sum<kTpb>(ow, red);
+    if (threadIdx.x == 0) {
+      hw.icnt[it] = s_nd;
+      s_nd = 0;
+    }
+    ow = team_sum<kTpb>(ow, red);   // its barriers also order the lh reads and s_nd before reuse
     if (threadIdx.x == 0 && ow) atomic_add_i64(&hw.own[i], ow);
     nent += e1 - e0;
     __syncthreads();
@@ -993,35 +1020,26 @@ __global__ __launch_bounds__(kTpb) void k_hub_poff(BinRef br, uint32_t bound, co
   }
 }
 
-// chunk items: (key, weight) of every counted entry into its partition's bucket
+// chunk items: each distinct (key, weight) pair the keys pass left into its partition's bucket
 template <typename WT, bool DIR, bool REF>
 __global__ __launch_bounds__(kTpb) void k_hub_scatter(MoveView mv, BinRef br, uint32_t bound, const U64x3* off,
                                                       HubPool hub, HubWork hw) {
   __shared__ uint32_t lh[kPartHist];
   __shared__ uint32_t lb[kPartHist];
   const uint32_t h = hub_count(br, bound);
-  const uint32_t* list = br.base + *br.start;
   const uint64_t total = off[h].y;
   for (uint64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const uint32_t i = item_owner<1>(off, h, it);
-    const uint64_t base = off[i].x;
     if (off[i + 1].x > hub.cap) continue;
-    const uint32_t v = list[i];
-    const uint32_t dout = mv.out.deg[v];
-    const uint32_t T = dout + (DIR ? mv.in.deg[v] : 0);
     const uint32_t P = (uint32_t)(off[i + 1].z - off[i].z);
     const uint64_t pbase = off[i].z;
-    const uint64_t e0 = (it - off[i].y) * kHubChunk;
-    const uint64_t e1 = e0 + kHubChunk < T ? e0 + kHubChunk : T;
-    const uint64_t oo = mv.out.off[v], oi = DIR ? mv.in.off[v] : 0;
+    const uint64_t p0 = off[i].x + (it - off[i].y) * kHubChunk;   // the chunk's pairs
+    const uint32_t nd = hw.icnt[it];
     const bool local = P <= kPartHist;
     if (local) {
       for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) lh[t] = 0;
       __syncthreads();
-      for (uint64_t j = e0 + threadIdx.x; j < e1; j += blockDim.x) {
-        const uint32_t key = hub.ekey[base + j];
-        if (key != kEmpty) atomicAdd(&lh[part_of(key, P)], 1u);
-      }
+      for (uint32_t j = threadIdx.x; j < nd; j += blockDim.x) atomicAdd(&lh[part_of(hub.ekey[p0 + j], P)], 1u);
       __syncthreads();
       // one global reservation per partition of the chunk; lh becomes the chunk's local cursor
       for (uint32_t t = threadIdx.x; t < P; t += blockDim.x) {
@@ -1030,31 +1048,14 @@ __global__ __launch_bounds__(kTpb) void k_hub_scatter(MoveView mv, BinRef br, ui
       }
       __syncthreads();
     }
-    // four entries per thread at a time: keys and weights loaded together, then placed
-    for (uint64_t jb = e0 + threadIdx.x; jb < e1; jb += 4 * (uint64_t)blockDim.x) {
-      uint32_t ks[4];
-      int64_t wv[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint64_t j = jb + (uint64_t)k * blockDim.x;
-        ks[k] = kEmpty;
-        wv[k] = 0;
-        if (j < e1) {
-          ks[k] = hub.ekey[base + j];
-          const bool in_out = !DIR || j < dout;
-          wv[k] = in_out ? wload<WT>(mv.out, oo + j) : wload<WT>(mv.in, oi + (j - dout));
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t key = ks[k];
-        if (key == kEmpty) continue;
-        const uint32_t p = part_of(key, P);
-        const uint32_t at = local ? lb[p] + atomicAdd(&lh[p], 1u) : atomicAdd(&hw.pcur[pbase + p], 1u);
-        const uint64_t pos = hw.poff[pbase + p] + at;
-        hub.bkey[pos] = key;
-        hub.bw[pos] = wv[k];
-      }
+    for (uint32_t j = threadIdx.x; j < nd; j += blockDim.x) {
+      const uint32_t key = hub.ekey[p0 + j];
+      const int64_t w = hub.ew[p0 + j];
+      const uint32_t p = part_of(key, P);
+      const uint32_t at = local ? lb[p] + atomicAdd(&lh[p], 1u) : atomicAdd(&hw.pcur[pbase + p], 1u);
+      const uint64_t pos = hw.poff[pbase + p] + at;
+      hub.bkey[pos] = key;
+      hub.bw[pos] = w;
     }
     __syncthreads();
   }

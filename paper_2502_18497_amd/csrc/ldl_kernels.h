@@ -70,10 +70,12 @@ struct CandBuf {
   uint32_t* count;
 };
 
-// Bucket pool of the hub bin: the neighbour-community keys of every hub entry (ekey) and the
-// (key, weight) pairs scattered into per-hub hash partitions (bkey, bw), cap entries each.
+// Bucket pool of the hub bin, cap entries each: the distinct (key, weight) pairs of every chunk
+// of a hub's entries, at the start of the chunk's own stretch (ekey, ew), and the same pairs
+// scattered into per-hub hash partitions (bkey, bw).
 struct HubPool {
   uint32_t* ekey;
+  int64_t* ew;
   uint32_t* bkey;
   int64_t* bw;
   uint64_t cap;         // entries
@@ -269,6 +271,7 @@ struct HubWork {
   U64x3* cnt;      // per hub: entries, chunk items, partitions (bound + 1 entries)
   U64x3* off;      // their exclusive prefix
   int64_t* own;    // weight towards the own community, per hub
+  uint32_t* icnt;     // per chunk item: distinct pairs it left in the pool
   uint32_t* pcount;   // per partition: entries counted (zero between launches)
   uint32_t* pcur;     // per partition: scatter cursor (zero between launches)
   uint64_t* poff;     // per partition: first bucket entry
@@ -345,9 +348,9 @@ void launch_stride_sample(const uint32_t* src, const uint32_t* count, uint32_t b
 // items from launch_items with the same list): plain-store marks into Rcur and Rset, oldpar of
 // new Rset members = themselves; the lists are built later by select
 void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t* count, uint32_t bound,
-                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint32_t* lab, const uint32_t* par,
-                     const uint32_t* rsize, uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp,
-                     uint32_t rset_ep, uint32_t* oldpar, hipStream_t s);
+                     const uint64_t* ioff, CsrRef out, CsrRef in, const uint2* lp, const uint32_t* rsize,
+                     uint32_t* rcur_stamp, uint32_t rcur_ep, uint32_t* rset_stamp, uint32_t rset_ep, uint32_t* oldpar,
+                     hipStream_t s);
 
 // ---------------------------------------------------------------- aggregate repair
 // materialise: every entry of every alive node (list = alive nodes); repair: entries of C
