@@ -254,7 +254,9 @@ def test_release_scratch_frees_memory_and_keeps_results():
     s = synth.rmat_undirected(scale=13, seed_offset=680)
     e = s.edges()
     keep, rel = ldl.Graph(s.n, e), ldl.Graph(s.n, e)
-    assert keep.memory()["held"] == rel.memory()["held"]
+    # (equal states may hold pools of slightly different sizes: a row update that overflows its
+    # pool grows it by what the rows that moved before the overflow left, which depends on timing)
+    assert not diff_states(keep.state(), rel.state())
     for size in (20000, 300, 5000):
         b = s.batch(size)
         keep.apply_batch(b.ins, b.dels, b.chg)
