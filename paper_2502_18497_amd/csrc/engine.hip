@@ -239,6 +239,13 @@ struct Engine {
   uint32_t *tx = nullptr, *ty = nullptr;
   void* cub_tmp = nullptr;
   size_t cub_bytes = 0;
+  // a host batch's staging: pinned host words and device words, grown on demand and kept, so a
+  // call allocates (and frees) nothing in the steady state
+  uint32_t* stage_h = nullptr;
+  uint32_t* stage_d = nullptr;
+  uint64_t stage_hcap = 0, stage_dcap = 0;
+  hipEvent_t call_t0 = nullptr, call_t1 = nullptr;   // brackets of a call (its total_ms)
+  static constexpr uint64_t kPinnedStageMax = 1ull << 26;   // words staged through pinned memory
   // device memory: hipMalloc / hipFree, or the caller's allocator hook (ldl_config.alloc/free)
   ldl_alloc_fn halloc = nullptr;
   ldl_free_fn hfree = nullptr;
@@ -332,6 +339,9 @@ struct Engine {
     if (st) (void)hipStreamSynchronize(st);
     for (auto& o : owned) raw_free(o.first, o.second);
     if (hs) (void)hipHostFree(hs);
+    if (stage_h) (void)hipHostFree(stage_h);
+    if (call_t0) (void)hipEventDestroy(call_t0);
+    if (call_t1) (void)hipEventDestroy(call_t1);
     raw_free(cub_tmp, cub_bytes);   // allocated through the same source (palloc)
     for (auto& e : ev_pool) {
       (void)hipEventDestroy(e.first);
@@ -634,7 +644,45 @@ struct Engine {
   // buffers, the library primitives' temporary storage); the next call that needs them allocates
   // them again at its own size.  The state is untouched.
   uint64_t scratch_bytes() const {
-    return tup_cap * 56 + rec_cap * 40 + ent_cap * 40 + ins_cap * 69 + cub_bytes;
+    return tup_cap * 56 + rec_cap * 40 + ent_cap * 40 + ins_cap * 69 + cub_bytes + 4 * stage_dcap;
+  }
+  // device words holding a host batch of `words` words (copied through pinned host memory)
+  uint32_t* stage_batch(const uint32_t* ins, uint64_t ni, const uint32_t* del, uint64_t nd, const uint32_t* chg,
+                        uint64_t nc) {
+    const uint64_t words = 3 * ni + 2 * nd + 3 * nc;
+    if (words == 0) return nullptr;
+    if (words > stage_dcap) {
+      release(stage_d);
+      stage_d = nullptr;
+      stage_dcap = 0;
+      const uint64_t c = std::max<uint64_t>(words, 1ull << 16);
+      stage_d = alloc<uint32_t>(c);
+      stage_dcap = c;
+    }
+    if (words > kPinnedStageMax) {   // a large batch (a graph's first) is copied from its own pages
+      if (ni) hcheck(hipMemcpyAsync(stage_d, ins, 12 * ni, hipMemcpyHostToDevice, st));
+      if (nd) hcheck(hipMemcpyAsync(stage_d + 3 * ni, del, 8 * nd, hipMemcpyHostToDevice, st));
+      if (nc) hcheck(hipMemcpyAsync(stage_d + 3 * ni + 2 * nd, chg, 12 * nc, hipMemcpyHostToDevice, st));
+      return stage_d;
+    }
+    if (words > stage_hcap) {
+      if (stage_h) hcheck(hipHostFree(stage_h));
+      stage_h = nullptr;
+      stage_hcap = 0;
+      const uint64_t c = std::max<uint64_t>(words, 1ull << 16);
+      if (hipHostMalloc((void**)&stage_h, 4 * c, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        stage_h = nullptr;
+        throw NoMem{};
+      }
+      stage_hcap = c;
+    }
+    // the previous call's copy out of stage_h ended with that call (its stream was synchronised)
+    if (ni) std::memcpy(stage_h, ins, 12 * ni);
+    if (nd) std::memcpy(stage_h + 3 * ni, del, 8 * nd);
+    if (nc) std::memcpy(stage_h + 3 * ni + 2 * nd, chg, 12 * nc);
+    hcheck(hipMemcpyAsync(stage_d, stage_h, 4 * words, hipMemcpyHostToDevice, st));
+    return stage_d;
   }
   void release_scratch() {
     hcheck(hipStreamSynchronize(st));
@@ -648,6 +696,12 @@ struct Engine {
       *p = nullptr;
     }
     tup_cap = rec_cap = ent_cap = ins_cap = 0;
+    release(stage_d);
+    stage_d = nullptr;
+    stage_dcap = 0;
+    if (stage_h) hcheck(hipHostFree(stage_h));
+    stage_h = nullptr;
+    stage_hcap = 0;
     prim_free_tmp(cub_tmp, cub_bytes);
     cub_tmp = nullptr;
     cub_bytes = 0;
@@ -2108,39 +2162,28 @@ int apply_common(ldl_handle* h, const ldl_edge* ins, uint64_t ni, const ldl_pair
     ldl::hcheck(hipSetDevice(e.device));
     e.stats = ldl_batch_stats{};
     e.call_begin();
-    hipEvent_t t0, t1;
-    ldl::hcheck(hipEventCreate(&t0));
-    ldl::hcheck(hipEventCreate(&t1));
-    ldl::hcheck(hipEventRecord(t0, e.st));
+    if (!e.call_t0) ldl::hcheck(hipEventCreate(&e.call_t0));
+    if (!e.call_t1) ldl::hcheck(hipEventCreate(&e.call_t1));
+    ldl::hcheck(hipEventRecord(e.call_t0, e.st));
     const uint32_t *di = (const uint32_t*)ins, *dd = (const uint32_t*)del, *dc = (const uint32_t*)chg;
-    uint32_t* tmp = nullptr;
     if (!on_device) {
-      const uint64_t words = 3 * ni + 2 * nd + 3 * nc;
-      tmp = e.alloc<uint32_t>(words ? words : 1);
-      if (ni) ldl::hcheck(hipMemcpyAsync(tmp, ins, 12 * ni, hipMemcpyHostToDevice, e.st));
-      if (nd) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni, del, 8 * nd, hipMemcpyHostToDevice, e.st));
-      if (nc) ldl::hcheck(hipMemcpyAsync(tmp + 3 * ni + 2 * nd, chg, 12 * nc, hipMemcpyHostToDevice, e.st));
-      di = tmp;
-      dd = tmp + 3 * ni;
-      dc = tmp + 3 * ni + 2 * nd;
+      const uint32_t* staged = e.stage_batch(di, ni, dd, nd, dc, nc);
+      di = staged;
+      dd = staged ? staged + 3 * ni : nullptr;
+      dc = staged ? staged + 3 * ni + 2 * nd : nullptr;
     }
     int rc;
     try {
       rc = e.apply(di, ni, dd, nd, dc, nc);
     } catch (...) {
-      e.release(tmp);
-      (void)hipEventDestroy(t0);
-      (void)hipEventDestroy(t1);
+      (void)hipStreamSynchronize(e.st);   // the staged copy may still be reading stage_h
       throw;
     }
-    ldl::hcheck(hipEventRecord(t1, e.st));
-    ldl::hcheck(hipEventSynchronize(t1));
+    ldl::hcheck(hipEventRecord(e.call_t1, e.st));
+    ldl::hcheck(hipEventSynchronize(e.call_t1));
     float ms = 0;
-    ldl::hcheck(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
+    ldl::hcheck(hipEventElapsedTime(&ms, e.call_t0, e.call_t1));
     ldl::hcheck(hipStreamSynchronize(e.st));
-    e.release(tmp);
     e.finish_profile();
     e.call_end();
     if (e.scratch_limit && e.scratch_bytes() > e.scratch_limit) e.release_scratch();
