@@ -227,8 +227,9 @@ int ldl_modularity_exact(const ldl_handle* h, int64_t* num_hi, uint64_t* num_lo,
                          uint64_t* den_lo);
 
 /* Free the handle's growable scratch: aggregation tuples, reduced records, sorted entries,
- * row-update buffers and the sort and scan primitives' temporary storage, all of which a batch
- * call grows to its own size and keeps for the next call.  The next call that needs them
+ * row-update buffers, the sort and scan primitives' temporary storage and the staging buffers of
+ * host batches (pinned host and device memory), all of which a batch call grows to its own size
+ * and keeps for the next call.  The next call that needs them
  * allocates them again; the state and every later result are unchanged.  ldl_create and
  * ldl_import_state end with it (static Leiden's scratch is sized for the whole graph), so a
  * resident handle holds its state plus what its batches use.  LDL_EINVAL for NULL. */
