@@ -1157,11 +1157,19 @@ __global__ __launch_bounds__(kTpb) void k_hub_part(MoveView mv, BinRef br, uint3
   if (threadIdx.x == 0 && st.entries && ndist) atomicAdd(st.distinct, (u64a)ndist);
 }
 
+// wavefront per hub: the best of its partitions' bests is its candidate.  Candidates and counts
+// are gathered per workgroup (one global atomic per 64 candidates): the hubs of a full-frontier
+// scan number in the millions.
 template <bool REF>
-__global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_t cap, const uint32_t* lab,
-                            const int64_t* phi, const uint64_t* plo, const uint32_t* pid, const int* pvalid,
-                            CandBuf cand, MoveStats st, u64a* need, uint32_t* over) {
+__global__ __launch_bounds__(kTpb) void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_t cap,
+                                                    const uint32_t* lab, const int64_t* phi, const uint64_t* plo,
+                                                    const uint32_t* pid, const int* pvalid, CandBuf cand, MoveStats st,
+                                                    u64a* need, uint32_t* over) {
+  constexpr int W = kTpb / kWave;
+  __shared__ Stage<64> stage;
+  __shared__ unsigned long long red_s[5 * W];
   const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
   const uint32_t h = hub_count(br, bound);
   const uint32_t* list = br.base + *br.start;
   if (gtid() == 0) {
@@ -1169,27 +1177,36 @@ __global__ void k_hub_final(BinRef br, uint32_t bound, const U64x3* off, uint64_
     *need = total;
     if (total > cap) atomicOr(over, 1u);
   }
-  for (uint64_t i = gwave(); i < h; i += gwstride()) {
-    if (off[i + 1].x > cap) continue;          // skipped: entries beyond the pool
-    const uint64_t p0 = off[i].z, p1 = off[i + 1].z;
-    Best b;
-    b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
-    for (uint64_t p = p0 + lane; p < p1; p += kWave) {
-      Best c;
-      c.hi = phi[p]; c.lo = plo[p]; c.id = pid[p]; c.valid = pvalid[p];
-      if (better(c, b)) b = c;
-    }
-    b = group_best(b, kWave);
-    if (lane == 0) {
-      const uint32_t v = list[i];
-      if (st.entries) atomicAdd(st.vertices, 1ull);
-      if (b.valid && best_gain(b) > 0) {
-        emit_cand_at(cand, atomicAdd(cand.count, 1u), v, REF ? v : lab[v], b);
-        if (st.entries) atomicAdd(st.cands, 1ull);
-        atomicMax(st.maxhi, (u64a)b.hi);
+  if (threadIdx.x == 0) stage.n = 0;
+  __syncthreads();
+  LocalStats ls;
+  // every wavefront of a workgroup takes one hub per round, so all of them reach its barriers
+  for (uint64_t base = (uint64_t)blockIdx.x * W; base < h; base += (uint64_t)gridDim.x * W) {
+    const uint64_t i = base + wv;
+    if (i < h && off[i + 1].x <= cap) {       // else skipped: entries beyond the pool
+      const uint64_t p0 = off[i].z, p1 = off[i + 1].z;
+      Best b;
+      b.valid = 0; b.hi = 0; b.lo = 0; b.id = 0;
+      for (uint64_t p = p0 + lane; p < p1; p += kWave) {
+        Best c;
+        c.hi = phi[p]; c.lo = plo[p]; c.id = pid[p]; c.valid = pvalid[p];
+        if (better(c, b)) b = c;
+      }
+      b = group_best(b, kWave);
+      if (lane == 0) {
+        const uint32_t v = list[i];
+        ls.vertices += 1;
+        if (b.valid && best_gain(b) > 0) {
+          stage_push(stage, v, REF ? v : lab[v], b);
+          note_cand(ls, b);
+        }
       }
     }
+    __syncthreads();
+    if (stage.n + W > 64) stage_flush(stage, cand);
   }
+  stage_flush(stage, cand);
+  stats_flush(ls, st, red_s);
 }
 
 template <typename WT, bool DIR, bool REF>
