@@ -1699,8 +1699,9 @@ void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t
 void launch_mark_items(uint32_t* stamp, uint32_t ep, const uint32_t* list, const uint32_t* count, uint32_t bound,
                        const uint64_t* ioff, CsrRef out, CsrRef in, hipStream_t s, const uint32_t* ustamp,
                        uint32_t uep, const uint8_t* alive) {
-  // dense lists (a quarter of the nodes or more) are pulled when the list's stamps are given
-  const uint32_t pull_from = ustamp ? (uint32_t)(((uint64_t)bound + 3) / 4) : 0xFFFFFFFFu;
+  // dense lists (1/64 of the nodes or more) are pulled when the list's stamps are given: on the
+  // full-method batches a pull already wins there (measured against 1/4, 1/16 and 1/256)
+  const uint32_t pull_from = ustamp ? (uint32_t)(((uint64_t)bound + 63) / 64) : 0xFFFFFFFFu;
   k_mark_items<<<kItemBlocks, kTpb, 0, s>>>(stamp, ep, list, count, bound, ioff, out, in, pull_from);
   if (ustamp)
     k_mark_pull<<<grid_waves(bound) < 8192u ? grid_waves(bound) : 8192u, kTpb, 0, s>>>(stamp, ep, ustamp, uep, count,
