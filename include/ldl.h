@@ -210,7 +210,9 @@ int ldl_create(const ldl_config* cfg, uint32_t n, const ldl_edge* edges, uint64_
 int ldl_apply_batch(ldl_handle* h, const ldl_edge* ins, uint64_t n_ins, const ldl_pair* del,
                     uint64_t n_del, const ldl_edge* chg, uint64_t n_chg, ldl_batch_stats* stats);
 
-/* As ldl_apply_batch, with the three arrays in device memory of the handle's device. */
+/* As ldl_apply_batch, with the three arrays in device memory of the handle's device.  They are read
+ * on the handle's stream (ldl_config.stream, or its own), which waits for no other stream: work that
+ * writes them on another stream must have completed before the call. */
 int ldl_apply_batch_device(ldl_handle* h, const ldl_edge* d_ins, uint64_t n_ins, const ldl_pair* d_del,
                            uint64_t n_del, const ldl_edge* d_chg, uint64_t n_chg, ldl_batch_stats* stats);
 

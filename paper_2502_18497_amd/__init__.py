@@ -355,8 +355,15 @@ class Graph:
         return (st.as_dict() if rc == LDL_OK else rc)
 
     def apply_batch_device(self, ins_t, dels_t, chg_t, raise_on_error=True):
-        """Device-resident batch: uint32/int32 torch tensors of shape (k,3), (k,2), (k,3)."""
+        """Device-resident batch: uint32/int32 torch tensors of shape (k,3), (k,2), (k,3).  The library
+        reads them on the handle's stream, so the stream that produced them is synchronised first."""
         st = ldl_batch_stats()
+        for t in (ins_t, dels_t, chg_t):
+            if t is not None and t.numel() and t.is_cuda:
+                import torch
+
+                torch.cuda.current_stream(t.device).synchronize()
+                break
 
         def ptr(t):
             return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)

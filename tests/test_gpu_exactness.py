@@ -194,3 +194,34 @@ def test_random_refinement_variant(directed, kernels):
     for b in [_Batch(e, None, None)] + batches:
         assert other.apply_batch(b.ins, b.dels, b.chg) == 0
     assert diff_states(oracle_state(other), oracle_state(og))
+
+
+@pytest.mark.parametrize("flags", [0, 1 | 2 | 4 | 128], ids=["default-paths", "rare-paths"])
+@pytest.mark.parametrize("directed", [False, True])
+def test_variants_together(directed, flags):
+    """All three variants at once (adaptive refresh at rho = 2/3, empty-community target,
+    randomised refinement), with the default internal paths and with the rarely taken ones forced
+    (one filter round per host check, a minimal hub pool, no spare row capacity, chunked
+    aggregation with rebuilds): bit-identical to the oracle after every batch, and the refresh and
+    empty-target branches are taken."""
+    from tests.test_oracle import _loop_batches
+    import paper_2502_18497_amd as ldl
+
+    rng = np.random.default_rng(59 + directed)
+    n = 600
+    s = synth.Stream(n, directed, synth.BASE_SEED + 1020 + directed)
+    s.planted(30, 0.2, 0.01, 1, 8)
+    e = s.edges()
+    batches = [_Batch(*b) for b in _loop_batches(s, rng, n, 8, 3, 10)]
+    cfg = dict(refresh=(2, 3), empty_target=True, refine_random=True, refine_seed=4242, gamma=(2, 1))
+    empty = np.zeros((0, 3), np.uint32)
+    og = oracle.Oracle(n, empty, directed=directed, **cfg)
+    g = ldl.Graph(n, empty, directed=directed, test_flags=flags, **cfg)
+    for k, b in enumerate([_Batch(e, None, None)] + batches):
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+        g.apply_batch(b.ins, b.dels, b.chg)
+        msgs = diff_states(g.state(), oracle_state(og))
+        assert not msgs, (k, msgs)
+    assert og.check_counts()["empty_moves"] > 0
+    assert og.refreshes() >= 3   # creation (every vertex a seed) and some of the batches, not all
+    assert og.refreshes() < 1 + len(batches)

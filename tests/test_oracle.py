@@ -640,3 +640,23 @@ def test_random_refinement_depends_on_seed_only():
         parts.append(oracle_state(o))
     assert not diff_states(parts[0], parts[1])
     assert diff_states(parts[0], parts[2]) or diff_states(parts[0], parts[3])
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_variants_together_keep_the_invariants(directed):
+    """The three variants at once (adaptive refresh, empty-community target, randomised
+    refinement): every move and refinement commit still matches its Eq. 1 recount, and the
+    hierarchy invariants hold after every batch."""
+    rng = np.random.default_rng(53 + directed)
+    n = 120
+    s = synth.Stream(n, directed, synth.BASE_SEED + 1010 + directed)
+    s.planted(12, 0.3, 0.03, 1, 8)
+    o = oracle.Oracle(n, s.edges(), directed=directed, flags=oracle.FLAG_CHECK_MOVES, L=3, refresh=(3, 4),
+                      empty_target=True, refine_random=True, refine_seed=77)
+    assert o.last_rc == 0, o.check()
+    for ins, dels, chg in _loop_batches(s, rng, n, 4, 10, 30):
+        assert o.apply_batch(ins, dels, chg) == 0, o.check()
+        assert o.check() == ""
+        assert not check_state(oracle_state(o), directed)
+    c = o.check_counts()
+    assert c["move"] > 0 and c["refine"] > 0
