@@ -66,8 +66,8 @@ typedef struct ldl_pair {
  *   N                   outer passes (>= 1); default 2
  *   L                   top hierarchy level index, levels 0..L (0..16); default 4
  *   M                   move / refinement iterations per level (>= 1); default 5
- *   alpha_num/den       gain threshold alpha (Alg. 1 l.13, l.27); default 1/1000
- *   beta_num/den        moved-frontier threshold beta (l.14, l.20); default 1/100
+ *   alpha_num/den       gain threshold alpha (Algorithm 1's move and pass stops); default 1/1000
+ *   beta_num/den        moved-fraction threshold beta (move and refinement stops); default 1/100
  *   device              HIP device ordinal
  *   stream              hipStream_t to run on, or NULL for the handle's own stream
  *   profile             nonzero: time the local-move kernels with HIP events (see stats)
@@ -89,7 +89,7 @@ typedef struct ldl_pair {
  *                       comparison (larger exact gain, equal gains to the lower id); refinement
  *                       is unchanged.
  *   refine_random       0 or 1 (a variant, off by default).  The paper's BestRef, like BestMove,
- *   refine_seed         takes the target of largest gain (Alg. 1 l.18).  With 1 the target is
+ *   refine_seed         takes the target of largest gain (Algorithm 1).  With 1 the target is
  *                       drawn at random among the refined communities of strictly positive gain,
  *                       as the Leiden refinement of Traag et al. draws among improving ones; here
  *                       uniformly (the large-temperature limit of its exp(gain / theta) weights,
@@ -157,7 +157,7 @@ typedef struct ldl_batch_stats {
   uint64_t distinct_comms;    /* (vertex, neighbour community) pairs evaluated            */
   uint64_t candidates;        /* candidates with positive gain                            */
   uint64_t accepted;          /* moves accepted by the decoupling filter                  */
-  uint64_t rollbacks;         /* move mini-batches rolled back (Alg. 1 l.11)              */
+  uint64_t rollbacks;         /* move mini-batches rolled back (negative batch gain)      */
   uint64_t refine_moves;      /* accepted refinement moves                                */
   uint64_t agg_tuples;        /* aggregate-repair tuples emitted                          */
   uint64_t bm_launches;       /* local-move kernel launches (profile != 0)                */

@@ -506,7 +506,7 @@ struct Oracle {
         checks[0]++;
       }
       record(r, 0, j, S.size(), cands.size(), B.size(), dq);
-      if (dq < 0) {  // Alg. 1 l.11: roll the whole mini-batch back and stop moving
+      if (dq < 0) {  // negative batch gain (Algorithm 1): roll the whole mini-batch back and stop moving
         rollback_moves(r, B, dq);
         break;
       }
@@ -521,7 +521,7 @@ struct Oracle {
       }
       if (!B.empty())
         for (uint32_t u = 0; u < n; ++u) if (L.alive[u] && cm[L.lab[u]]) U.add(u);
-      // Alg. 1 l.13-14 as exact rational comparisons
+      // the alpha and beta stops of the move loop as exact rational comparisons
       if ((i128)cfg.ad * dq < (i128)cfg.an * Q0) break;
       if ((i128)cfg.bd * B.size() < (i128)cfg.bn * S.size()) break;
     }
@@ -529,7 +529,7 @@ struct Oracle {
     if (r >= 1 && Moved.size() > 0) label_refresh(r);
   }
 
-  // Refinement (Alg. 1 l.16-22) and aggregate repair (l.23-24) at level r < L.
+  // Refinement (Algorithm 1, BestRef) and aggregate repair (Eq. 3) at level r < L.
   void refine_and_aggregate(int r, const std::vector<uint32_t>& entry, NodeSet& Moved) {
     Level& L = lv[r];
     // TouchedRefined: refined communities of this level's seeds and movers
@@ -728,7 +728,7 @@ struct Oracle {
     if (m + dm >= ((i64)1 << 40)) return EOVERFLOW_;
     cur_batch = batches++;   // the batch is accepted
 
-    // ---- Alg. 1 l.1-2: apply to G^0 as matrix entries, repair m, degrees, totals, Ein, SKK
+    // ---- batch ingest: apply to G^0 as matrix entries, repair m, degrees, totals, Ein, SKK
     std::vector<std::pair<std::pair<uint32_t, uint32_t>, i64>> ent;
     for (auto& kv : net) {
       ent.push_back(kv);
@@ -748,7 +748,7 @@ struct Oracle {
       add_total(lv[0].lab[y], 0, d);
       if (lv[0].lab[x] == lv[0].lab[y]) Ein += d;
     }
-    // ---- l.3 seeds; cascade of the entry deltas through pi to every existing level
+    // ---- seeds; cascade of the entry deltas through pi to every existing level
     for (auto& e : ent) { D[0].add(e.first.first); D[0].add(e.first.second); }
     for (int s = 1; s <= top; ++s) {
       std::vector<Tup> agg;
@@ -774,7 +774,7 @@ struct Oracle {
         refresh();
       }
     }
-    // ---- l.4-28: outer passes over levels
+    // ---- outer passes over levels
     for (int i = 1; i <= cfg.N; ++i) {
       pass_idx = i;
       const i128 Qp = qnum();

@@ -978,7 +978,7 @@ struct Engine {
       cub(prim_sort_pairs_u64_u32_db(&cub_tmp, &cub_bytes, e0, e1, w0, w1, E, 0, 2 * id_bits, &sel2, st));
       bulk_rows(V0.out, sel2 ? e1 : e0, sel2 ? w1 : w0, E, V0.kout, V0.lab);
     }
-    // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
+    // statistic repair and level-0 seeds (Algorithm 1, batch ingest)
     const CsrRef in = directed ? V0.in.ref : CsrRef{};
     begin(S_TOUCH);
     launch_bulk_mark(n, V0.out.ref, in, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), st);
@@ -1046,7 +1046,7 @@ struct Engine {
     if (E == 0) return LDL_OK;
     cub(prim_sort_pairs_u64_i64(&cub_tmp, &cub_bytes, ekey0, ekey1, edel0, edel1, E, 0, 2 * id_bits, st));
     stats.updates = K;
-    // statistic repair (Alg. 1 l.2) and level-0 seeds (l.3)
+    // statistic repair and level-0 seeds (Algorithm 1, batch ingest)
     begin(S_TOUCH);
     launch_ingest_mark(ekey1, E, V0.lab, Kout, Kin, ref(S_TOUCH), tko, tki, ref(S_D0), id_bits, st);
     zero(&ds->dein);
@@ -1372,7 +1372,7 @@ struct Engine {
       const i128 dq = (i128)gq * m * dein - (i128)gp * dskk;
       record(r, 0, j, nS, K, na, dq);
       const uint32_t* nap = &ds->nacc;
-      if (dq < 0) {  // Alg. 1 l.11: undo every accepted move of the iteration
+      if (dq < 0) {  // negative batch gain: undo every accepted move of the iteration
         launch_commit_apply(acc, nap, na, cand, V.lab, V.kout, V.kin, Kout, directed ? Kin : nullptr, 0, st);
         stats.rollbacks++;
         break;
@@ -1381,8 +1381,8 @@ struct Engine {
       SKK += dskk;
       stats.accepted += na;
       launch_set_add_acc_v(ref(S_MOVED), acc, nap, na, cand, st);
-      if ((i128)ad * dq < (i128)an * Q0) break;            // Alg. 1 l.13
-      if ((i128)bd * na < (i128)bn * nS) break;           // Alg. 1 l.14
+      if ((i128)ad * dq < (i128)an * Q0) break;            // alpha stop of the move loop
+      if ((i128)bd * na < (i128)bn * nS) break;           // beta stop of the move loop
       if (j == M) break;                                  // the next frontier would not be used
       // Expand_r: movers, their neighbours, members of the touched communities
       begin(S_U2);
@@ -1446,7 +1446,7 @@ struct Engine {
       const uint32_t* nap = &ds->nacc;
       stats.refine_moves += na;
       record(r, 1, j, Rc, K, na, 0);
-      if ((i128)bd * na < (i128)bn * Rc) break;            // Alg. 1 l.20
+      if ((i128)bd * na < (i128)bn * Rc) break;            // beta stop of the refinement loop
       begin(S_RCUR);
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
       cub(launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, nullptr, nullptr, &cub_tmp,
@@ -1706,7 +1706,7 @@ struct Engine {
       for (int r = 0; r <= L; ++r)
         if (count(S_D0 + r)) all_empty = false;
       if (!any || all_empty) break;
-      if ((i128)ad * (qnum() - Qp) < (i128)an * Qp) break;  // Alg. 1 l.27
+      if ((i128)ad * (qnum() - Qp) < (i128)an * Qp) break;  // alpha stop of the passes
     }
     flush_to(top);
     for (int r = 0; r <= L; ++r) begin(S_D0 + r);

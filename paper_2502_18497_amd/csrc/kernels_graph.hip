@@ -1,6 +1,6 @@
 // Graph-maintenance kernels: stamped sets, dynamic CSR edits, batch ingest and statistic
-// repair (Alg. 1 l.1-3), aggregate-repair tuples and hierarchy liveness (Alg. 1 l.23-24,
-// Eq. 3), label refresh.
+// repair (Algorithm 1), aggregate-repair tuples and hierarchy liveness (Eq. 3), label
+// refresh.
 #include "ldl_dev.h"
 #include "ldl_kernels.h"
 
@@ -1407,7 +1407,7 @@ __global__ void k_spexpand_items(const uint32_t* movers, const uint32_t* idx, co
 
 // ------------------------------------------------------------------ bulk load
 // An insert-only batch into a level-0 graph that has never held an entry (the first batch of a
-// graph, Alg. 1 l.1-2 on the all-singleton state) builds its rows directly from the sorted
+// graph, batch ingest on the all-singleton state) builds its rows directly from the sorted
 // records: the slot of a record is its row's first slot plus its rank within the row.
 
 // Insert records of a bulk load: key (canonical pair for undirected graphs) and weight; an id

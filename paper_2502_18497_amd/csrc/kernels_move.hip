@@ -1,4 +1,4 @@
-// Local-move and refinement kernels (Alg. 1 l.8-12 and l.16-21; gain of Sec. III-D), the
+// Local-move and refinement kernels (Algorithm 1; gain of Sec. III-D), the
 // exact decoupling filter of Sec. III-E as parallel rounds, and the commit / rollback /
 // expansion kernels.
 //

@@ -1,5 +1,5 @@
 """GPU (HIP, gfx950) versus the CPU oracle on the cases that stress exactness rather than size:
-gains whose exact 128-bit value needs the high word, the rollback branch of Alg. 1 l.11, and the
+gains whose exact 128-bit value needs the high word, the rollback branch of Algorithm 1, and the
 parameter settings of the batch-regime and parameter sweep.  Full state bit-identical after every
 step (partition, Q numerator, totals, every level's nodes and matrix)."""
 import numpy as np
@@ -51,7 +51,7 @@ def test_gains_beyond_64_bits(directed, gamma):
 @pytest.mark.parametrize("trial", [16, 156, 196])
 def test_rollback_branch_taken(trial):
     """Seeded undirected planted partitions (300 vertices in blocks of 30) with a move iteration
-    at an aggregate level whose exact batch gain is negative, so Alg. 1 l.11 rolls the whole
+    at an aggregate level whose exact batch gain is negative, so Algorithm 1 rolls the whole
     iteration back: in the static run (trials 16, 196) or in the third batch (trial 156), as the
     oracle's trace shows.  The GPU must take the same branch at the same iteration (its
     statistics count each rollback) and stay bit-identical."""

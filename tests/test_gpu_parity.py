@@ -284,7 +284,7 @@ def test_bulk_load_equals_general_path(directed):
 def test_isolated_vertices_in_scan_sets(directed):
     # 3,000 of 4,000 vertices have no edge: at the aggregate levels they are alive supernodes
     # without entries, members of the frontier and so of the scan set (which the moved-fraction stop
-    # of Alg. 1 l.14 divides by); every iteration's record (scan-set size, candidates, accepted
+    # of the move loop divides by); every iteration's record (scan-set size, candidates, accepted
     # moves, exact gain) must match the oracle's
     import paper_2502_18497_amd as ldl
     from tests.gpucases import first_trace_divergence

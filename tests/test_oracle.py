@@ -204,7 +204,7 @@ def test_every_move_matches_recount(directed, gamma, single):
 @pytest.mark.parametrize("directed", [False, True])
 @pytest.mark.parametrize("gamma", [(1, 1), (3, 2), (2, 5)])
 def test_every_refinement_move_matches_recount(directed, gamma):
-    """BestRef (Alg. 1 l.18): in single-move mode every refinement commit moves one singleton
+    """BestRef (Algorithm 1): in single-move mode every refinement commit moves one singleton
     {u} into an adjacent refined community y, and Eq. 1 recounted from scratch on the refined
     partition (ground node -> pi_r of its level-r ancestor) changes by exactly the predicted gain
     q m acc[y] - p (kout_u Krin_y + kin_u Krout_y) (twice that for the symmetric matrix of an
