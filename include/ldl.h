@@ -150,8 +150,8 @@ typedef struct ldl_config {
 typedef struct ldl_batch_stats {
   uint64_t updates;           /* input updates that changed a weight                      */
   uint64_t levels_processed;  /* process-level invocations over all passes                */
-  uint64_t move_iters;        /* move iterations                                          */
-  uint64_t refine_iters;      /* refinement iterations                                    */
+  uint64_t move_iters;        /* move iterations launched (not those over an empty set)   */
+  uint64_t refine_iters;      /* refinement iterations launched (idem)                    */
   uint64_t scanned_vertices;  /* vertices evaluated by the local-move kernels             */
   uint64_t scanned_entries;   /* adjacency entries read by the local-move kernels         */
   uint64_t distinct_comms;    /* (vertex, neighbour community) pairs evaluated            */

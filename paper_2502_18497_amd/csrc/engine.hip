@@ -1255,6 +1255,13 @@ struct Engine {
     return na1;
   }
 
+  // the iterations after `iter` of a phase whose next set is empty: each would scan nothing,
+  // accept nothing and pass no stop, so they are recorded (as the paper's loop runs them) but
+  // not launched
+  void record_empty(int r, int phase, int iter) {
+    for (int j = iter + 1; j <= M; ++j) record(r, phase, j, 0, 0, 0, 0);
+  }
+  static constexpr uint32_t kProbeEmpty = 2048;
   void record(int r, int phase, int iter, uint64_t nscan, uint64_t ncand, uint64_t nacc, i128 dq) {
     if (!tracing) return;
     TraceRec t;
@@ -1384,6 +1391,10 @@ struct Engine {
       if ((i128)ad * dq < (i128)an * Q0) break;            // alpha stop of the move loop
       if ((i128)bd * na < (i128)bn * nS) break;           // beta stop of the move loop
       if (j == M) break;                                  // the next frontier would not be used
+      if (nS == 0) {   // empty scan set: every later iteration is empty too and changes nothing
+        record_empty(r, 0, j);
+        break;
+      }
       // Expand_r: movers, their neighbours, members of the touched communities
       begin(S_U2);
       if (na) {
@@ -1447,6 +1458,10 @@ struct Engine {
       stats.refine_moves += na;
       record(r, 1, j, Rc, K, na, 0);
       if ((i128)bd * na < (i128)bn * Rc) break;            // beta stop of the refinement loop
+      if (Rc == 0) {   // an empty set stays empty: the later iterations change nothing
+        record_empty(r, 1, j);
+        break;
+      }
       begin(S_RCUR);
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
       cub(launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, nullptr, nullptr, &cub_tmp,
@@ -1456,6 +1471,13 @@ struct Engine {
       select_set(S_RCUR);
       rset_grew = rset_grew || na > 0;
       cur = S_RCUR;
+      if (j < M && na <= kProbeEmpty) {   // few movers often leave the next set empty: look first
+        sync_read();
+        if (count(S_RCUR) == 0) {
+          record_empty(r, 1, j);
+          break;
+        }
+      }
     }
     if (rset_grew) select_set(S_RSET);
     if (r == top) materialise(r);
