@@ -211,6 +211,7 @@ struct Engine {
   uint32_t* binbuf = nullptr;
   uint32_t* bhist = nullptr;
   uint64_t *tcounts = nullptr, *toffs = nullptr, *tcur = nullptr, *it_cnt = nullptr, *it_off = nullptr;
+  uint64_t* it_csum = nullptr;   // chunk sums of the item scan
   HubWork hw{};
   uint64_t part_cap = 0;
   uint64_t hw_cap = 0;   // entries of hw.cnt / hw.off / hw.own
@@ -402,7 +403,7 @@ struct Engine {
   uint64_t tuple_offsets_at(const uint32_t* list, const uint32_t* cnt, uint32_t k, CsrRef out, CsrRef in,
                             const uint2* po, int repair, bool grow) {
     if (k == 0) return 0;
-    cub(launch_items(list, nullptr, cnt, k, out, in, it_cnt, it_off, tcounts, tcur, &cub_tmp, &cub_bytes, st));
+    launch_items(list, nullptr, cnt, k, out, in, it_cnt, it_off, it_csum, tcounts, tcur, st);
     launch_tuples_count(list, cnt, k, it_off, out, in, po, repair, (u64a*)tcounts, st);
     cub(prim_exclusive_sum_u64(&cub_tmp, &cub_bytes, tcounts, toffs, (uint64_t)k + 1, st));
     uint64_t T = 0;
@@ -528,6 +529,7 @@ struct Engine {
     tcur = alloc<uint64_t>((uint64_t)n + 1);
     it_cnt = alloc<uint64_t>((uint64_t)n + 1);
     it_off = alloc<uint64_t>((uint64_t)n + 1);
+    it_csum = alloc<uint64_t>(kItemScanBlocks);
     cand.v = alloc<uint32_t>(n);
     cand.a = alloc<uint32_t>(n);
     cand.b = alloc<uint32_t>(n);
@@ -1367,8 +1369,8 @@ struct Engine {
       // scan set: the frontier and its neighbours (counts stay on the device)
       begin(S_S);
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
-      cub(launch_items(sets[S_U].list, nullptr, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off, nullptr,
-                       nullptr, &cub_tmp, &cub_bytes, st));
+      launch_items(sets[S_U].list, nullptr, &ds->counts[sets[S_U].ci], n, V.out.ref, in_or_none, it_cnt, it_off,
+                   it_csum, nullptr, nullptr, st);
       launch_mark_items(sets[S_S].stamp, sets[S_S].epoch, sets[S_U].list, &ds->counts[sets[S_U].ci], n, it_off,
                         V.out.ref, in_or_none, st, sets[S_U].stamp, sets[S_U].epoch, V.alive);
       select_set(S_S);
@@ -1464,8 +1466,7 @@ struct Engine {
       }
       begin(S_RCUR);
       const CsrRef in_or_none = directed ? V.in.ref : CsrRef{};
-      cub(launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, nullptr, nullptr, &cub_tmp,
-                       &cub_bytes, st));
+      launch_items(cand.v, acc, nap, na, V.out.ref, in_or_none, it_cnt, it_off, it_csum, nullptr, nullptr, st);
       launch_spexpand(cand.v, acc, nap, na, it_off, V.out.ref, in_or_none, lpk, V.rsize, sets[S_RCUR].stamp,
                       sets[S_RCUR].epoch, sets[S_RSET].stamp, sets[S_RSET].epoch, oldpar, st);
       select_set(S_RCUR);

@@ -1119,16 +1119,105 @@ __device__ __forceinline__ uint32_t list_node(const uint32_t* list, const uint32
   return idx ? list[idx[i]] : list[i];
 }
 
-__global__ void k_item_counts(const uint32_t* list, const uint32_t* idx, const uint32_t* countp, uint32_t bound,
-                              CsrRef out, CsrRef in, uint64_t* icnt, uint64_t* zero_a, uint64_t* zero_b) {
-  const uint32_t c0 = *countp;
-  const uint32_t cnt = c0 < bound ? c0 : bound;
-  for (uint64_t i = gtid(); i <= bound; i += gstride()) {
+// ---- item counts and their exclusive prefix over positions [0, cnt] of a list (cnt read on the
+// device): a fixed grid of kScanBlocks workgroups, each owning one contiguous chunk of at least
+// kScanMinChunk positions, writes the counts and its chunk's sum, then a second launch scans each
+// chunk offset by the sums of the chunks before it.  The work follows the device count, not the
+// host bound.
+constexpr unsigned kScanBlocks = kItemScanBlocks;
+constexpr uint64_t kScanMinChunk = 1024;
+constexpr int kScanPer = 4;   // consecutive positions per thread in one scan tile
+
+__device__ __forceinline__ void scan_chunk(uint32_t cnt, uint64_t& b0, uint64_t& b1) {
+  const uint64_t total = (uint64_t)cnt + 1;
+  uint64_t per = (total + kScanBlocks - 1) / kScanBlocks;
+  if (per < kScanMinChunk) per = kScanMinChunk;
+  b0 = (uint64_t)blockIdx.x * per;
+  b1 = b0 + per < total ? b0 + per : total;
+  if (b0 > b1) b0 = b1;
+}
+
+// sum over the workgroup; every thread calls it and gets the sum (lds: one word per wavefront)
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
+  v = (uint64_t)wave_sum_i64((int64_t)v);
+  __syncthreads();
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint64_t t = 0;
+  for (unsigned w = 0; w < blockDim.x / kWave; ++w) t += lds[w];
+  return t;
+}
+
+// inclusive prefix over the workgroup in thread order, and the workgroup total; every thread calls it
+__device__ __forceinline__ uint64_t block_incl_scan_u64(uint64_t v, uint64_t* lds, uint64_t& total) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint64_t t = (uint64_t)__shfl_up((long long)v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  const unsigned me = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == kWave - 1) lds[me] = v;
+  __syncthreads();
+  uint64_t before = 0;
+  total = 0;
+  for (unsigned w = 0; w < blockDim.x / kWave; ++w) {
+    if (w < me) before += lds[w];
+    total += lds[w];
+  }
+  return v + before;
+}
+
+__global__ __launch_bounds__(kTpb) void k_item_counts(const uint32_t* list, const uint32_t* idx,
+                                                      const uint32_t* countp, uint32_t bound, CsrRef out, CsrRef in,
+                                                      uint64_t* icnt, uint64_t* zero_a, uint64_t* zero_b,
+                                                      uint64_t* csum) {
+  __shared__ uint64_t lds[kTpb / kWave];
+  const uint32_t cnt = list_len(countp, bound);
+  uint64_t b0, b1;
+  scan_chunk(cnt, b0, b1);
+  uint64_t sum = 0;
+  for (uint64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
     uint64_t c = 0;
     if (i < cnt) c = (node_slots(out, in, list_node(list, idx, i)) + kItem - 1) / kItem;
     icnt[i] = c;
+    sum += c;
     if (zero_a) zero_a[i] = 0;
     if (zero_b) zero_b[i] = 0;
+  }
+  sum = block_sum_u64(sum, lds);
+  if (threadIdx.x == 0) csum[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kTpb) void k_item_offsets(const uint32_t* countp, uint32_t bound, const uint64_t* icnt,
+                                                       const uint64_t* csum, uint64_t* ioff) {
+  __shared__ uint64_t lds[kTpb / kWave];
+  const uint32_t cnt = list_len(countp, bound);
+  uint64_t b0, b1;
+  scan_chunk(cnt, b0, b1);
+  if (b0 >= b1) return;   // the whole workgroup: its chunk is empty (so are those after it)
+  uint64_t pre = 0;
+  for (unsigned j = threadIdx.x; j < blockIdx.x; j += blockDim.x) pre += csum[j];
+  pre = block_sum_u64(pre, lds);
+  const uint64_t tile = (uint64_t)blockDim.x * kScanPer;
+  for (uint64_t base = b0; base < b1; base += tile) {
+    const uint64_t i0 = base + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t v[kScanPer];
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      v[k] = i0 + k < b1 ? icnt[i0 + k] : 0;
+      mine += v[k];
+    }
+    uint64_t total = 0;
+    uint64_t run = pre + block_incl_scan_u64(mine, lds, total) - mine;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < b1) ioff[i0 + k] = run;
+      run += v[k];
+    }
+    pre += total;
   }
 }
 
@@ -1683,11 +1772,13 @@ void launch_mark_changed(uint32_t* stamp, uint32_t ep, const uint32_t* rset, uin
                          const uint32_t* oldpar, hipStream_t s, const uint32_t* countp) {
   if (nr) k_mark_changed<<<list_grid(nr, countp), kTpb, 0, s>>>(stamp, ep, rset, nr, countp, par, oldpar);
 }
-int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
-                 CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
-                 size_t* tmp_bytes, hipStream_t s) {
-  k_item_counts<<<grid_for((uint64_t)bound + 1), kTpb, 0, s>>>(list, idx, count, bound, out, in, icnt, zero_a, zero_b);
-  return prim_exclusive_sum_u64(tmp, tmp_bytes, icnt, ioff, (uint64_t)bound + 1, s);
+void launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
+                  CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* csum, uint64_t* zero_a, uint64_t* zero_b,
+                  hipStream_t s) {
+  const uint64_t need = ((uint64_t)bound + kScanMinChunk) / kScanMinChunk;   // chunks of bound + 1 positions
+  const unsigned g = need < kScanBlocks ? (unsigned)need : kScanBlocks;
+  k_item_counts<<<g, kTpb, 0, s>>>(list, idx, count, bound, out, in, icnt, zero_a, zero_b, csum);
+  k_item_offsets<<<g, kTpb, 0, s>>>(count, bound, icnt, csum, ioff);
 }
 void launch_spexpand(const uint32_t* movers, const uint32_t* idx, const uint32_t* count, uint32_t bound,
                      const uint64_t* ioff, CsrRef out, CsrRef in, const uint2* lp, const uint32_t* rsize,

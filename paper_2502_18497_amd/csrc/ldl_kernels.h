@@ -142,13 +142,16 @@ void launch_bin_fill(const MoveView& mv, const uint32_t* list, const uint32_t* c
                      uint32_t* out, uint32_t* bin_start, uint32_t* bin_count, hipStream_t s);
 // wavefront items over a node list (count on the device, at most `bound` nodes): node i has
 // out.deg + in.deg entries (in only when in.off is set), split into items of kItem entries;
-// icnt/ioff hold bound + 1 words; zero_a / zero_b (optional, bound + 1 words) are cleared
+// icnt/ioff hold bound + 1 words, of which words 0..count are written (ioff[count] is the item
+// total); zero_a / zero_b (optional, bound + 1 words) are cleared at 0..count; csum holds
+// kItemScanBlocks words of chunk sums
 constexpr uint32_t kItem = 512;
 constexpr unsigned kItemBlocks = 2048;
+constexpr unsigned kItemScanBlocks = 1024;
 // (node i = list[idx[i]] when idx is given)
-int launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
-                 CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* zero_a, uint64_t* zero_b, void** tmp,
-                 size_t* tmp_bytes, hipStream_t s);
+void launch_items(const uint32_t* list, const uint32_t* idx, const uint32_t* count, uint32_t bound, CsrRef out,
+                  CsrRef in, uint64_t* icnt, uint64_t* ioff, uint64_t* csum, uint64_t* zero_a, uint64_t* zero_b,
+                  hipStream_t s);
 // stamp[x] = ep for every listed node and every neighbour over its items
 // (with ustamp / uep, the stamps of the listed set, and bound = n: a list of at least n/4 nodes
 // is pulled instead -- alive nodes that are listed or have a listed neighbour -- same set)
