@@ -979,9 +979,21 @@ __global__ void k_label_up(const uint32_t* rset, uint32_t nr, const uint32_t* pa
   }
 }
 
-__global__ void k_alive_list(uint32_t n, const uint8_t* alive, SetRef set) {
-  for (uint64_t x = gtid(); x < n; x += gstride())
-    if (alive[x]) set_add(set.stamp, set.epoch, set.list, set.count, (uint32_t)x);
+// alive nodes not yet in the set join it; every id is read by one thread only, so its stamp is
+// tested and set without atomics, and each workgroup reserves its list slots with one atomic
+__global__ __launch_bounds__(kTpb) void k_alive_list(uint32_t n, const uint8_t* alive, SetRef set) {
+  __shared__ uint32_t lds[kTpb / kWave];
+  __shared__ uint32_t s_base;
+  for (uint64_t x0 = (uint64_t)blockIdx.x * kTpb; x0 < n; x0 += (uint64_t)gridDim.x * kTpb) {
+    const uint64_t x = x0 + threadIdx.x;
+    const bool add = x < n && alive[x] && set.stamp[x] != set.epoch;
+    if (add) set.stamp[x] = set.epoch;
+    uint32_t total = 0;
+    const uint32_t r = block_rank(add, lds, total);
+    if (threadIdx.x == 0 && total) s_base = atomicAdd(set.count, total);
+    __syncthreads();
+    if (add) set.list[s_base + r] = (uint32_t)x;
+  }
 }
 
 // *count += alive nodes u < n whose key is marked (stamp[key[u]] == ep): the size of a frontier
@@ -1970,7 +1982,7 @@ void launch_label_up(const uint32_t* rset, uint32_t nr, const uint32_t* par, con
   if (nr) k_label_up<<<grid_for(nr), kTpb, 0, s>>>(rset, nr, par, alive_up, lab, lab_up);
 }
 void launch_alive_list(uint32_t n, const uint8_t* alive, SetRef set, hipStream_t s) {
-  if (n) k_alive_list<<<grid_for(n), kTpb, 0, s>>>(n, alive, set);
+  if (n) k_alive_list<<<grid_for(n) < 2048u ? grid_for(n) : 2048u, kTpb, 0, s>>>(n, alive, set);
 }
 void launch_materialise_nodes(uint32_t n, const uint32_t* rsize, uint8_t* alive_up, const uint32_t* lab,
                               uint32_t* lab_up, uint32_t* par_up_or_null, hipStream_t s) {
