@@ -306,6 +306,38 @@ def test_isolated_vertices_in_scan_sets(directed):
     assert not msgs, msgs
 
 
+@pytest.mark.parametrize("directed", [False, True])
+def test_empty_iterations_recorded_not_launched(directed):
+    # refinement sets run empty after a few iterations on R-MAT streams; the GPU records the rest
+    # of such a phase (each iteration would scan, propose and accept nothing) without launching
+    # it, so its per-iteration trace must still equal the oracle's, which runs every iteration
+    import paper_2502_18497_amd as ldl
+    from tests.gpucases import first_trace_divergence
+
+    if directed:
+        s = synth.rmat_directed_lognormal(1 << 13, 1 << 17, seed_offset=311)
+    else:
+        s = synth.rmat_undirected(scale=13, seed_offset=312)
+    n, e = s.n, s.edges()
+    og = oracle.Oracle(n, e, directed=directed, flags=oracle.FLAG_TRACE)
+    g = ldl.Graph(n, e, directed=directed)
+    g.set_trace(True)
+    og.trace_clear()
+    launched = recorded = 0
+    for _ in range(3):
+        b = s.batch(500)
+        st = g.apply_batch(b.ins, b.dels, b.chg)
+        assert og.apply_batch(b.ins, b.dels, b.chg) == 0
+        tg, to = g.trace(), og.trace()
+        assert np.array_equal(tg, to), first_trace_divergence(tg, to)
+        launched += st["refine_iters"]
+        recorded += int(np.count_nonzero(to[:, 2] == 1))
+        g.set_trace(True)
+        og.trace_clear()
+    assert np.array_equal(g.partition(), og.partition())
+    assert recorded > launched, (recorded, launched)   # some empty iterations were not launched
+
+
 def test_device_inputs_equal_host_inputs():
     import torch
 
