@@ -497,6 +497,7 @@ struct Engine {
     for (int w = 0; w < 2; ++w)
       for (int b = 0; b < kNumBins - 1; ++b) lim[w][b] = kBinLimit[b];
     std::memset(lf_lastK, 0xFF, sizeof(lf_lastK));
+    std::memset(lf_first, 0xFF, sizeof(lf_first));
     oldpar = alloc<uint32_t>(n);
     bigmov = alloc<uint32_t>(n);
     rowdel = alloc<uint32_t>(n);
@@ -1210,14 +1211,19 @@ struct Engine {
   // accepted candidate indices are appended to `acc`, their count in ds->nacc
   static constexpr int kLfRounds = 4;   // rounds launched before the host looks
   int lf_rounds() const { return (test_flags & 1) ? 1 : kLfRounds; }
-  // Which filter to queue before the candidate count is known: the rounds for the first
-  // iteration of a level's move or refinement phase, else the one-workgroup filter unless the
-  // previous iteration had far more candidates than it holds (candidate counts fall fast after
-  // the first iteration).  A wrong guess costs one more synchronisation, never a different result.
-  uint32_t lf_lastK[17][2];
-  bool lf_small_predicted(int r, int refine) const {
+  // Which filter to queue before the candidate count is known.  For the first iteration of a
+  // level's move or refinement phase: the one-workgroup filter if the same pass, level and phase
+  // of the previous batch started with at most half of what it holds, else the rounds.  For a
+  // later iteration: the one-workgroup filter unless the previous iteration had far more
+  // candidates than it holds (candidate counts fall fast after the first iteration).  A wrong
+  // guess costs one more synchronisation, never a different result.
+  uint32_t lf_lastK[17][2];       // ~0u: the phase's first iteration is next
+  uint32_t lf_first[4][17][2];    // first iteration's count per pass (the last slot: later passes)
+  uint32_t& lf_first_of(int r, int refine) { return lf_first[pass_idx < 4 ? pass_idx : 3][r][refine]; }
+  bool lf_small_predicted(int r, int refine) {
     if (test_flags & 1) return false;
     if (test_flags & 8) return true;
+    if (lf_lastK[r][refine] == ~0u) return lf_first_of(r, refine) <= kLfSmall / 2;
     return lf_lastK[r][refine] <= 16 * kLfSmall;
   }
   void decouple_start() {
@@ -1322,6 +1328,7 @@ struct Engine {
       commit(acc, &ds->nacc, 0);   // undo: the candidate set was incomplete
       if (attempt > 2 + kPartShiftMax) throw NoMem{};
     }
+    if (lf_lastK[r][refine] == ~0u) lf_first_of(r, refine) = K;
     lf_lastK[r][refine] = K;
     dein = refine ? 0 : hs->ps.cdein;
     dskk = refine ? 0 : read_dskk();
@@ -1362,7 +1369,7 @@ struct Engine {
     select_set(S_U);
     const i128 Q0 = qnum();
     begin(S_MOVED);
-    lf_lastK[r][0] = lf_lastK[r][1] = ~0u;   // the first iteration of each phase queues the rounds
+    lf_lastK[r][0] = lf_lastK[r][1] = ~0u;   // each phase's first iteration: predicted from the last batch
     CsrRef in = directed ? V.in.ref : V.out.ref;
     for (int j = 1; j <= M; ++j) {
       stats.move_iters++;
