@@ -45,7 +45,7 @@ __device__ __forceinline__ int64_t wget(const CsrRef& c, uint64_t i) {
 
 template <typename WT>
 __device__ __forceinline__ int64_t wload(const CsrRef& c, uint64_t i) {
-  return (int64_t)((const WT*)c.w)[i];
+  return (int64_t)__builtin_nontemporal_load(&((const WT*)c.w)[i]);
 }
 
 // Entry j of vertex v's combined out/in list: (neighbour, weight).
@@ -53,10 +53,10 @@ template <typename WT, bool DIR>
 __device__ __forceinline__ void entry_at(const MoveView& mv, uint64_t oo, uint32_t dout, uint64_t oi, uint32_t j,
                                          uint32_t& x, int64_t& w) {
   if (!DIR || j < dout) {
-    x = mv.out.nbr[oo + j];
+    x = __builtin_nontemporal_load(&mv.out.nbr[oo + j]);
     w = wload<WT>(mv.out, oo + j);
   } else {
-    x = mv.in.nbr[oi + (j - dout)];
+    x = __builtin_nontemporal_load(&mv.in.nbr[oi + (j - dout)]);
     w = wload<WT>(mv.in, oi + (j - dout));
   }
 }
