@@ -48,7 +48,8 @@ __device__ __forceinline__ int64_t wload(const CsrRef& c, uint64_t i) {
   return (int64_t)__builtin_nontemporal_load(&((const WT*)c.w)[i]);
 }
 
-// Entry j of vertex v's combined out/in list: (neighbour, weight).
+// Entry j of vertex v's combined out/in list: (neighbour, weight).  The adjacency is read once per
+// search, so it is loaded nontemporally: the caches are left to the label and total gathers.
 template <typename WT, bool DIR>
 __device__ __forceinline__ void entry_at(const MoveView& mv, uint64_t oo, uint32_t dout, uint64_t oi, uint32_t j,
                                          uint32_t& x, int64_t& w) {
